@@ -1,0 +1,434 @@
+/*
+ * fk_oracle.c -- TEST INFRASTRUCTURE, not part of the product.
+ *
+ * Plain, slow, FP64 CPU oracle of the Monte-Carlo evaluation of the
+ * Feynman-Kac representation of the relaxed Winslow mesh equations
+ * (Bihlo & Haynes, "A stochastic domain decomposition method for time
+ * dependent mesh generation", Sect. 3, eqs. (5)-(7); Sect. 4).
+ *
+ * Only the test-suite, the smoke check and the benchmark's CPU-baseline leg
+ * load this file's library.  It shares no source with the GPU path: the
+ * counter-based generator, the normal transform, the densities, the
+ * Euler-Maruyama step, the exit test, the scoring and the statistics are all
+ * written out here a second time, in FP64, one path at a time.
+ *
+ * What is computed, for an interface node P and component c in {xi, eta}:
+ *
+ *   U_c(P) = mean over paths of  g_c(t - s_kappa, X_kappa)  if the path left
+ *            the closed unit square at step kappa <= K, else u0_c(X_K),
+ *
+ * where X_0 = P and X_{k+1} = X_k + b(tau_k, X_k) D_k + sqrt(2 D_k) z_k is the
+ * Euler-Maruyama chain of dX = -(grad w / w) ds + sqrt(2) dW (eq. (7a);
+ * Sect. 4 integrates it with the Euler-Maruyama scheme and Brownian
+ * increments sqrt(D) times a standard normal).  The drift is the
+ * Winslow choice a = I, b = -grad w / w (eq. (6)).  The estimator is the
+ * arithmetic mean of eq. (7b) (Sect. 4), with a sample standard error.
+ *
+ * Readings where the paper is silent (each one is also listed in the design
+ * notes):
+ *  - time argument of w along a path: BACKWARD uses the PDE time
+ *    t_init + t - s reached by running the path backward from the evaluation
+ *    time; FROZEN holds w at t_freeze over the whole solve (Sect. 4 freezes w
+ *    over one mesh step).
+ *  - the exit test runs after every step, the last included; points on the
+ *    boundary count as inside (eq. (5) uses strict inequalities).
+ *  - a path that exits scores the boundary data at its first outside point,
+ *    unclamped, with the data extended off the square (identity data extends
+ *    as xi = x, eta = y); a PROJECT mode clamps the point first.
+ *  - the normal generator: Philox4x32-10 (Salmon, Moraes, Dror & Shaw,
+ *    SC'11), key = (seed low word, seed high word), counter = (k/2, path,
+ *    node, (level << 4) | stream); one call serves two steps (words 0,1 for
+ *    even steps, 2,3 for odd); Box-Muller on 24-bit uniforms
+ *    u1 = ((r >> 8) + 1) 2^-24 in (0,1], u2 = (r >> 8) 2^-24 in [0,1).
+ *  - step sizes: K = ceil(t/dt), every step dt except the last, which is
+ *    t - (K-1) dt.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define OR_PI 3.14159265358979323846
+
+/* ---------------------------------------------------------------------------
+ * Philox4x32-10, written from its published definition (Salmon et al. 2011):
+ * a 4-word counter goes through 10 rounds; each round multiplies words 0 and 2
+ * by two fixed odd constants into 64-bit products, and the new state is
+ *   (hi(M1*x2) ^ x1 ^ k0,  lo(M1*x2),  hi(M0*x0) ^ x3 ^ k1,  lo(M0*x0)).
+ * Between rounds the 2-word key is advanced by the Weyl constants
+ * (golden ratio and sqrt(3)-1 in 32-bit fixed point).
+ * ------------------------------------------------------------------------- */
+static const uint32_t PHILOX_MULT_A = 0xD2511F53u;
+static const uint32_t PHILOX_MULT_B = 0xCD9E8D57u;
+static const uint32_t PHILOX_WEYL_A = 0x9E3779B9u;
+static const uint32_t PHILOX_WEYL_B = 0xBB67AE85u;
+
+void or_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
+    uint32_t k0 = key[0], k1 = key[1];
+    for (int round = 0; round < 10; ++round) {
+        if (round > 0) {
+            k0 += PHILOX_WEYL_A;
+            k1 += PHILOX_WEYL_B;
+        }
+        uint64_t pa = (uint64_t)PHILOX_MULT_A * (uint64_t)x0;
+        uint64_t pb = (uint64_t)PHILOX_MULT_B * (uint64_t)x2;
+        uint32_t n0 = (uint32_t)(pb >> 32) ^ x1 ^ k0;
+        uint32_t n1 = (uint32_t)pb;
+        uint32_t n2 = (uint32_t)(pa >> 32) ^ x3 ^ k1;
+        uint32_t n3 = (uint32_t)pa;
+        x0 = n0; x1 = n1; x2 = n2; x3 = n3;
+    }
+    out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
+}
+
+void or_philox_batch(const uint32_t *ctr, const uint32_t *key, int64_t n, uint32_t *out)
+{
+    for (int64_t i = 0; i < n; ++i)
+        or_philox4x32_10(ctr + 4 * i, key + 2 * i, out + 4 * i);
+}
+
+/* Box-Muller on the two 24-bit uniforms taken from a pair of Philox words. */
+static void box_muller(uint32_t ra, uint32_t rb, double *z0, double *z1)
+{
+    double u1 = ((double)(ra >> 8) + 1.0) * (1.0 / 16777216.0);   /* (0, 1] */
+    double u2 = (double)(rb >> 8) * (1.0 / 16777216.0);           /* [0, 1) */
+    double r = sqrt(-2.0 * log(u1));
+    *z0 = r * cos(2.0 * OR_PI * u2);
+    *z1 = r * sin(2.0 * OR_PI * u2);
+}
+
+void or_normals_batch(const uint32_t *ra, const uint32_t *rb, int64_t n, double *z)
+{
+    for (int64_t i = 0; i < n; ++i)
+        box_muller(ra[i], rb[i], &z[2 * i], &z[2 * i + 1]);
+}
+
+/* ---------------------------------------------------------------------------
+ * Densities w(tau, x, y) and the Winslow drift b = -grad w / w (eq. (6)).
+ * par = {amp, width2, cx, cy, orbit_r, omega, t_freeze}.
+ * ------------------------------------------------------------------------- */
+enum { K_CONST = 0, K_BUMP = 1, K_MOVING = 2, K_TWO = 3, K_RING = 4, K_RIDGE = 5 };
+
+/* w and its gradient, analytically. */
+static void density(int kind, const double *par, double tau, double x, double y,
+                    double *w, double *wx, double *wy)
+{
+    const double A = par[0], s2 = par[1], cx = par[2], cy = par[3];
+    const double R = par[4], om = par[5];
+    switch (kind) {
+    case K_BUMP: {
+        double dx = x - cx, dy = y - cy;
+        double e = exp(-(dx * dx + dy * dy) / s2);
+        *w = 1.0 + A * e;
+        *wx = A * e * (-2.0 * dx / s2);
+        *wy = A * e * (-2.0 * dy / s2);
+        return;
+    }
+    case K_MOVING: {
+        double ccx = cx + R * cos(om * tau), ccy = cy + R * sin(om * tau);
+        double dx = x - ccx, dy = y - ccy;
+        double e = exp(-(dx * dx + dy * dy) / s2);
+        *w = 1.0 + A * e;
+        *wx = A * e * (-2.0 * dx / s2);
+        *wy = A * e * (-2.0 * dy / s2);
+        return;
+    }
+    case K_TWO: {
+        double c = R * cos(om * tau), s = R * sin(om * tau);
+        double d1x = x - (cx + c), d1y = y - (cy + s);
+        double d2x = x - (cx - c), d2y = y - (cy + s);
+        double e1 = exp(-(d1x * d1x + d1y * d1y) / s2);
+        double e2 = exp(-(d2x * d2x + d2y * d2y) / s2);
+        *w = 1.0 + A * (e1 + e2);
+        *wx = A * (e1 * (-2.0 * d1x / s2) + e2 * (-2.0 * d2x / s2));
+        *wy = A * (e1 * (-2.0 * d1y / s2) + e2 * (-2.0 * d2y / s2));
+        return;
+    }
+    case K_RING: {
+        /* w = 1/rho, rho = 1 + alpha exp(beta |r^2 - 1/100|)  (Sect. 5);
+           amp = alpha, width2 = beta. */
+        double ccx = cx + R * cos(om * tau), ccy = cy + R * sin(om * tau);
+        double dx = x - ccx, dy = y - ccy;
+        double q = dx * dx + dy * dy - 0.01;
+        double e = exp(s2 * fabs(q));
+        double rho = 1.0 + A * e;
+        double sg = (q > 0.0) ? 1.0 : ((q < 0.0) ? -1.0 : 0.0);
+        double rx = A * e * s2 * sg * 2.0 * dx, ry = A * e * s2 * sg * 2.0 * dy;
+        *w = 1.0 / rho;
+        *wx = -rx / (rho * rho);
+        *wy = -ry / (rho * rho);
+        return;
+    }
+    case K_RIDGE: {
+        double dx = x - cx;
+        double e = exp(-dx * dx / s2);
+        *w = 1.0 + A * e;
+        *wx = A * e * (-2.0 * dx / s2);
+        *wy = 0.0;
+        return;
+    }
+    default:
+        *w = 1.0; *wx = 0.0; *wy = 0.0;
+        return;
+    }
+}
+
+static void drift(int kind, const double *par, double tau, double x, double y,
+                  double *bx, double *by)
+{
+    double w, wx, wy;
+    density(kind, par, tau, x, y, &w, &wx, &wy);
+    *bx = -wx / w;
+    *by = -wy / w;
+}
+
+void or_density_batch(int kind, const double *par, double tau, const double *pts, int64_t n,
+                      double *w, double *b)
+{
+    for (int64_t i = 0; i < n; ++i) {
+        double ww, wx, wy;
+        density(kind, par, tau, pts[2 * i], pts[2 * i + 1], &ww, &wx, &wy);
+        w[i] = ww;
+        b[2 * i] = -wx / ww;
+        b[2 * i + 1] = -wy / ww;
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * Initial data u0 and boundary data g (Sect. 3: xi0 = x, eta0 = y; boundary
+ * data of the uniform mesh).  Test modes: the decaying sine mode and zero.
+ * ------------------------------------------------------------------------- */
+enum { D_IDENTITY = 0, D_SIN = 1, D_ZERO = 2, D_GRID = 3 };
+
+static double sin_mode(double x, double y) { return sin(OR_PI * x) * sin(OR_PI * y); }
+
+static double bilinear(const double *g, int n, double x, double y)
+{
+    double fx = x * n, fy = y * n;
+    int i = (int)floor(fx), j = (int)floor(fy);
+    if (i < 0) i = 0;
+    if (i > n - 1) i = n - 1;
+    if (j < 0) j = 0;
+    if (j > n - 1) j = n - 1;
+    double ax = fx - i, ay = fy - j;
+    const double *r0 = g + (int64_t)j * (n + 1), *r1 = r0 + (n + 1);
+    return (1 - ay) * ((1 - ax) * r0[i] + ax * r0[i + 1]) + ay * ((1 - ax) * r1[i] + ax * r1[i + 1]);
+}
+
+typedef struct {
+    int init_kind, bdry_kind, score_mode;
+    const double *grid_xi, *grid_eta;
+    int grid_n;
+} or_data;
+
+static void initial_value(const or_data *d, double x, double y, double *xi, double *eta)
+{
+    switch (d->init_kind) {
+    case D_IDENTITY: *xi = x; *eta = y; return;
+    case D_SIN: *xi = *eta = sin_mode(x, y); return;
+    case D_GRID:
+        *xi = bilinear(d->grid_xi, d->grid_n, x, y);
+        *eta = bilinear(d->grid_eta, d->grid_n, x, y);
+        return;
+    default: *xi = *eta = 0.0; return;
+    }
+}
+
+/* Boundary data at elapsed time since the initial data, at an exit point. */
+static void boundary_value(const or_data *d, double elapsed, double x, double y,
+                           double *xi, double *eta)
+{
+    if (d->score_mode == 1) {
+        x = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
+        y = y < 0.0 ? 0.0 : (y > 1.0 ? 1.0 : y);
+    }
+    switch (d->bdry_kind) {
+    case D_IDENTITY: *xi = x; *eta = y; return;
+    case D_SIN: *xi = *eta = exp(-2.0 * OR_PI * OR_PI * elapsed) * sin_mode(x, y); return;
+    default: *xi = *eta = 0.0; return;
+    }
+}
+
+/* ---------------------------------------------------------------------------
+ * One Euler-Maruyama path from P; returns its exit step (k+1) or -1.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    int kind, time_mode;
+    const double *par;
+    or_data data;
+    double t_init, t, dt;
+    int64_t K;
+    uint32_t key[2];
+    uint32_t ctr3;
+} or_problem;
+
+static int64_t run_path(const or_problem *pb, double px, double py, uint32_t path, uint32_t node,
+                        double *score_xi, double *score_eta)
+{
+    double x = px, y = py, s = 0.0;
+    uint32_t r[4] = {0, 0, 0, 0};
+    for (int64_t k = 0; k < pb->K; ++k) {
+        if ((k & 1) == 0) {
+            uint32_t ctr[4] = {(uint32_t)(k >> 1), path, node, pb->ctr3};
+            or_philox4x32_10(ctr, pb->key, r);
+        }
+        double z0, z1;
+        if ((k & 1) == 0) box_muller(r[0], r[1], &z0, &z1);
+        else box_muller(r[2], r[3], &z0, &z1);
+        double D = (k == pb->K - 1) ? pb->t - (double)(pb->K - 1) * pb->dt : pb->dt;
+        double tau = (pb->time_mode == 0) ? pb->t_init + pb->t - s : pb->par[6];
+        double bx, by;
+        drift(pb->kind, pb->par, tau, x, y, &bx, &by);
+        double sd = sqrt(2.0 * D);
+        x = x + bx * D + sd * z0;
+        y = y + by * D + sd * z1;
+        s = s + D;
+        if (x < 0.0 || x > 1.0 || y < 0.0 || y > 1.0) {
+            boundary_value(&pb->data, pb->t - s, x, y, score_xi, score_eta);
+            return k + 1;
+        }
+    }
+    initial_value(&pb->data, x, y, score_xi, score_eta);
+    return -1;
+}
+
+static int64_t n_steps(double t, double dt)
+{
+    if (t <= 0.0) return 0;
+    return (int64_t)ceil(t / dt - 1e-9);
+}
+
+int64_t or_n_steps(double t, double dt) { return n_steps(t, dt); }
+
+/*
+ * Plain Monte-Carlo solve at n_nodes points.
+ *   pts        [n_nodes][2]           node coordinates
+ *   node_ids   [n_nodes] or NULL      counter word 2 (NULL: the index)
+ *   mean, se   [n_nodes][2]           (xi, eta) estimate and standard error
+ *   exit_step  [n_nodes][n_paths] or NULL
+ *   scores     [n_nodes][n_paths][2] or NULL
+ *   steps      [n_nodes] or NULL      Euler-Maruyama steps taken in total
+ * Returns 0, or -1 on bad arguments.
+ */
+int or_fk_solve(int kind, int time_mode, const double *par,
+                int init_kind, int bdry_kind, int score_mode, double t_init,
+                const double *grid_xi, const double *grid_eta, int grid_n,
+                const double *pts, const int64_t *node_ids, int64_t n_nodes,
+                double t, double dt, int64_t n_paths, uint64_t seed, uint32_t level_id,
+                uint32_t stream, int n_threads,
+                double *mean, double *se, int32_t *exit_step, double *scores, int64_t *steps)
+{
+    if (n_nodes < 0 || n_paths < 2 || !(dt > 0.0) || !(t >= 0.0)) return -1;
+    or_problem pb;
+    pb.kind = kind;
+    pb.time_mode = time_mode;
+    pb.par = par;
+    pb.data.init_kind = init_kind;
+    pb.data.bdry_kind = bdry_kind;
+    pb.data.score_mode = score_mode;
+    pb.data.grid_xi = grid_xi;
+    pb.data.grid_eta = grid_eta;
+    pb.data.grid_n = grid_n;
+    pb.t_init = t_init;
+    pb.t = t;
+    pb.dt = dt;
+    pb.K = n_steps(t, dt);
+    pb.key[0] = (uint32_t)seed;
+    pb.key[1] = (uint32_t)(seed >> 32);
+    pb.ctr3 = (level_id << 4) | (stream & 15u);
+
+    double *sc = scores;
+    if (!sc) {
+        sc = (double *)malloc(sizeof(double) * 2 * (size_t)(n_nodes * n_paths));
+        if (!sc) return -1;
+    }
+    int64_t *st = (int64_t *)calloc((size_t)(n_nodes * n_paths > 0 ? n_nodes * n_paths : 1), sizeof(int64_t));
+    const int64_t total = n_nodes * n_paths;
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 64)
+#endif
+    for (int64_t g = 0; g < total; ++g) {
+        int64_t i = g / n_paths, p = g % n_paths;
+        uint32_t nid = (uint32_t)(node_ids ? node_ids[i] : i);
+        double a, b;
+        int64_t e = run_path(&pb, pts[2 * i], pts[2 * i + 1], (uint32_t)p, nid, &a, &b);
+        sc[2 * g] = a;
+        sc[2 * g + 1] = b;
+        st[g] = (e < 0) ? pb.K : e;
+        if (exit_step) exit_step[g] = (int32_t)e;
+    }
+    /* Two-pass sample mean and variance per node and component. */
+    for (int64_t i = 0; i < n_nodes; ++i) {
+        for (int c = 0; c < 2; ++c) {
+            double sum = 0.0;
+            for (int64_t p = 0; p < n_paths; ++p) sum += sc[2 * (i * n_paths + p) + c];
+            double m = sum / (double)n_paths;
+            double ss = 0.0;
+            for (int64_t p = 0; p < n_paths; ++p) {
+                double d = sc[2 * (i * n_paths + p) + c] - m;
+                ss += d * d;
+            }
+            double var = ss / (double)(n_paths - 1);
+            mean[2 * i + c] = m;
+            se[2 * i + c] = sqrt(var / (double)n_paths);
+        }
+        if (steps) {
+            int64_t tot = 0;
+            for (int64_t p = 0; p < n_paths; ++p) tot += st[i * n_paths + p];
+            steps[i] = tot;
+        }
+    }
+    free(st);
+    if (!scores) free(sc);
+    return 0;
+}
+
+/*
+ * Individual paths, for sampled checks at sizes where a full oracle solve is
+ * out of reach: path path_ids[j] of the node at pts[j] with counter word 2
+ * node_ids[j].  Outputs the scores [m][2] and exit steps [m] (-1 = survived).
+ */
+int or_fk_paths(int kind, int time_mode, const double *par,
+                int init_kind, int bdry_kind, int score_mode, double t_init,
+                const double *grid_xi, const double *grid_eta, int grid_n,
+                const double *pts, const int64_t *node_ids, const int64_t *path_ids, int64_t m,
+                double t, double dt, uint64_t seed, uint32_t level_id, uint32_t stream, int n_threads,
+                double *scores, int32_t *exit_step)
+{
+    if (m < 0 || !(dt > 0.0) || !(t >= 0.0)) return -1;
+    or_problem pb;
+    pb.kind = kind;
+    pb.time_mode = time_mode;
+    pb.par = par;
+    pb.data.init_kind = init_kind;
+    pb.data.bdry_kind = bdry_kind;
+    pb.data.score_mode = score_mode;
+    pb.data.grid_xi = grid_xi;
+    pb.data.grid_eta = grid_eta;
+    pb.data.grid_n = grid_n;
+    pb.t_init = t_init;
+    pb.t = t;
+    pb.dt = dt;
+    pb.K = n_steps(t, dt);
+    pb.key[0] = (uint32_t)seed;
+    pb.key[1] = (uint32_t)(seed >> 32);
+    pb.ctr3 = (level_id << 4) | (stream & 15u);
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 4)
+#endif
+    for (int64_t j = 0; j < m; ++j) {
+        double a, b;
+        int64_t e = run_path(&pb, pts[2 * j], pts[2 * j + 1], (uint32_t)path_ids[j], (uint32_t)node_ids[j], &a, &b);
+        scores[2 * j] = a;
+        scores[2 * j + 1] = b;
+        exit_step[j] = (int32_t)e;
+    }
+    return 0;
+}
