@@ -1,0 +1,162 @@
+/*
+ * fk.h -- C ABI of the MI355X stochastic interface solver (libfk.so).
+ *
+ * The library evaluates, at interface nodes of a sub-domain decomposition of
+ * the unit square, the Feynman-Kac (probabilistic) representation of the
+ * relaxed Winslow mesh equations
+ *
+ *     xi_t  = -(1/w) grad w . grad xi  + Laplacian xi,
+ *     eta_t = -(1/w) grad w . grad eta + Laplacian eta        (Sect. 2, eq. (3))
+ *
+ * by Monte-Carlo: each node launches n_paths Euler-Maruyama paths of
+ * dX = -(grad w / w) ds + sqrt(2) dW (eq. (7a)); a path scores the boundary
+ * data where it first leaves the square, or the initial data where it is at
+ * the end of the time horizon (eqs. (5), (7b); Sect. 4).  One path set serves
+ * xi and eta, which share the drift.  Sub-domain meshes are then obtained by
+ * implicit finite-difference solves with the interface values as Dirichlet
+ * data (Sect. 4, deterministic single-domain solver).
+ *
+ * Conventions, for every call:
+ *  - Arrays marked "device" are caller-owned device memory; arrays marked
+ *    "host" are caller-owned host memory read before the call returns.  The
+ *    library keeps no pointer after a call returns, except inside the opaque
+ *    handles documented below.
+ *  - Calls are asynchronous and ordered on the given HIP stream, unless
+ *    stated otherwise.  Outputs are valid once the stream is synchronised.
+ *  - Every call returns an int status.  Arguments are validated before any
+ *    work is queued; on error nothing is queued, outputs are unspecified and
+ *    fk_last_error() describes the failure.  No C++ exception crosses the ABI.
+ *  - Errors of work already queued (device faults) surface as FK_E_DEVICE at
+ *    the next call that synchronises (fk_sync).
+ */
+#ifndef FK_H
+#define FK_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define FK_OK 0
+#define FK_E_INVAL (-1)        /* bad shape, t < 0, dt <= 0, n_paths < 2, node outside the square, NaN */
+#define FK_E_NODEVICE (-2)     /* no usable GPU */
+#define FK_E_NOMEM (-3)        /* workspace too small / allocation failed */
+#define FK_E_DEVICE (-4)       /* HIP runtime error (launch failure, fault) */
+#define FK_E_UNSUPPORTED (-5)  /* valid request this build does not implement */
+
+/* Density kinds: w(tau, x, y) of the mesh equations (Sect. 2; Sect. 5). */
+#define FK_DENSITY_CONST 0        /* w = 1 */
+#define FK_DENSITY_BUMP 1         /* w = 1 + amp exp(-|X - (cx,cy)|^2 / width2) */
+#define FK_DENSITY_MOVING_BUMP 2  /* centre (cx + orbit_r cos(omega tau), cy + orbit_r sin(omega tau)) */
+#define FK_DENSITY_TWO_BUMPS 3    /* w = 1 + amp (e1 + e2); e2 centred at (cx - orbit_r cos, cy + orbit_r sin) */
+#define FK_DENSITY_RIDGE 5        /* w = 1 + amp exp(-(x - cx)^2 / width2) */
+
+/* Time argument of w along a path. */
+#define FK_TIME_BACKWARD 0  /* w(t_init + t - s): the time reversal of the Feynman-Kac formula (eq. (5)) */
+#define FK_TIME_FROZEN 1    /* w(t_freeze): held fixed over one mesh time step (Sect. 4) */
+
+/* Initial / boundary data kinds (Sect. 3). */
+#define FK_DATA_IDENTITY 0  /* xi = x, eta = y: the initial uniform mesh and its boundary data */
+#define FK_DATA_SIN 1       /* test mode: phi = sin(pi x) sin(pi y) for both components; boundary
+                               data exp(-2 pi^2 (t - s)) phi(X) extended off the square */
+#define FK_DATA_ZERO 2      /* boundary data 0 */
+#define FK_DATA_GRID 3      /* initial data only: bilinear in (grid_n+1)^2 nodal FP64 grids */
+
+#define FK_SCORE_UNCLAMPED 0  /* boundary data at the first point outside the square */
+#define FK_SCORE_PROJECT 1    /* ... after clamping that point onto the square */
+
+/* Density parameters (plain values). */
+typedef struct fk_density {
+    int32_t kind;       /* FK_DENSITY_* */
+    int32_t time_mode;  /* FK_TIME_* */
+    double amp, width2, cx, cy, orbit_r, omega, t_freeze;
+} fk_density;
+
+/* Initial and boundary data. */
+typedef struct fk_data {
+    int32_t init_kind;   /* FK_DATA_* */
+    int32_t bdry_kind;   /* FK_DATA_IDENTITY, FK_DATA_SIN or FK_DATA_ZERO */
+    int32_t score_mode;  /* FK_SCORE_* */
+    int32_t grid_n;      /* FK_DATA_GRID: grid cells per side, else 0 */
+    double t_init;       /* PDE time at which the initial data hold */
+    const double *grid_xi;   /* device, [(grid_n+1)^2] row-major [j][i], x = i/grid_n; or NULL */
+    const double *grid_eta;  /* device, same layout; or NULL */
+} fk_data;
+
+/* Launch plan of the path kernel (see fk_plan_autotune). Zero fields take defaults. */
+typedef struct fk_plan {
+    int32_t block;          /* threads per workgroup (multiple of 64, <= 1024) */
+    int32_t blocks_per_cu;  /* resident workgroups per compute unit for the persistent grid */
+    int32_t chunk;          /* paths handed to a wavefront per queue grab (>= 1) */
+    int32_t reserved;
+} fk_plan;
+
+/*
+ * Bytes of device workspace fk_interface_solve needs for n_nodes x n_paths
+ * (per-path score records, queue counters and node tables).  Returns 0 for
+ * invalid sizes.
+ */
+size_t fk_interface_workspace_bytes(int64_t n_nodes, int64_t n_paths);
+
+/*
+ * Monte-Carlo interface solve (eqs. (5)-(7); Sect. 4).
+ *
+ * For node i (0 <= i < n_nodes) at pts[2i], pts[2i+1] (host, FP64, strictly
+ * inside the closed unit square) the library runs n_paths Euler-Maruyama
+ * paths over the horizon t with step dt (K = ceil(t/dt) steps, the last one
+ * t - (K-1) dt), drawing normals from Philox4x32-10 with key = seed and
+ * counter (step/2, path, i, (level_id << 4) | 0), two normals per step from
+ * one Box-Muller transform.  Path arithmetic is FP32; the estimator is
+ * accumulated in FP64.
+ *
+ *   xi, eta        device [n_nodes] FP64  sample means
+ *   se_xi, se_eta  device [n_nodes] FP64  standard errors sqrt(var/n_paths)
+ *   exit_step      device [n_nodes][n_paths] int32 or NULL: step after which
+ *                  the path left the square (1..K), -1 if it never did
+ *   scores         device [n_nodes][n_paths][2] FP32 or NULL: per-path score
+ *                  minus the node's shift (the FP32 rounding of the node
+ *                  coordinates when initial and boundary data are both the
+ *                  identity, 0 otherwise)
+ *   steps          device [n_nodes] int64 or NULL: Euler-Maruyama steps taken
+ *                  per node (needs exit_step != NULL)
+ *   total_steps    device [1] uint64 or NULL: steps taken over all nodes
+ *   plan           launch plan or NULL for the default
+ *   workspace      device, at least fk_interface_workspace_bytes() bytes,
+ *                  256-byte aligned; owned by the caller, must not be used by
+ *                  other work until the stream passes this call
+ */
+int fk_interface_solve(const fk_density *w, const fk_data *d,
+                       const double *pts, int64_t n_nodes,
+                       double t, double dt, int64_t n_paths, uint64_t seed, uint32_t level_id,
+                       double *xi, double *eta, double *se_xi, double *se_eta,
+                       int32_t *exit_step, float *scores, int64_t *steps, uint64_t *total_steps,
+                       const fk_plan *plan, void *workspace, size_t workspace_bytes,
+                       hipStream_t stream);
+
+/*
+ * Kernel timing.  While enabled (per calling thread), fk_interface_solve
+ * records HIP events on its stream around the path kernel and around the
+ * reduction kernel; fk_timing_last waits for the last recorded events and
+ * returns their durations in milliseconds.  Disabled by default (no events
+ * are recorded).  fk_timing_last returns FK_E_INVAL if nothing was recorded.
+ */
+int fk_timing_enable(int enable);
+int fk_timing_last(double *path_kernel_ms, double *reduce_kernel_ms);
+
+/* Wait for the stream; report queued device errors as FK_E_DEVICE. */
+int fk_sync(hipStream_t stream);
+
+/* Description of the last error on the calling thread ("" if none). */
+const char *fk_last_error(void);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int fk_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FK_H */

@@ -1,0 +1,195 @@
+"""MI355X stochastic domain-decomposition interface solver (Python binding).
+
+A thin ctypes binding of ``libfk.so`` (C ABI declared in ``include/fk.h``):
+the functions here only marshal arguments -- every step of the solve runs in
+the library's HIP kernels.  PyTorch supplies device memory and the stream.
+
+The library must be built first (``python paper_1402_0266_amd/build.py`` or
+``__graft_entry__.build()``); importing this package without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libfk.so")
+HEADER_PATH = os.path.join(os.path.dirname(_HERE), "include", "fk.h")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is not built; run paper_1402_0266_amd/build.py")
+
+# torch ships its own HIP runtime (soname libamdhip64.so.7).  Loading torch
+# first makes libfk.so bind to that same runtime instead of a second copy
+# from /opt/rocm, so both see the same device, memory and streams.
+import torch  # noqa: E402,F401
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+FK_OK = 0
+FK_E_INVAL = -1
+FK_E_NODEVICE = -2
+FK_E_NOMEM = -3
+FK_E_DEVICE = -4
+FK_E_UNSUPPORTED = -5
+
+
+class FkError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"fk error {code}: {msg}")
+        self.code = code
+
+
+class fk_density(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("time_mode", ctypes.c_int32),
+                ("amp", ctypes.c_double), ("width2", ctypes.c_double), ("cx", ctypes.c_double),
+                ("cy", ctypes.c_double), ("orbit_r", ctypes.c_double), ("omega", ctypes.c_double),
+                ("t_freeze", ctypes.c_double)]
+
+
+class fk_data(ctypes.Structure):
+    _fields_ = [("init_kind", ctypes.c_int32), ("bdry_kind", ctypes.c_int32),
+                ("score_mode", ctypes.c_int32), ("grid_n", ctypes.c_int32),
+                ("t_init", ctypes.c_double), ("grid_xi", ctypes.c_void_p), ("grid_eta", ctypes.c_void_p)]
+
+
+class fk_plan(ctypes.Structure):
+    _fields_ = [("block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_lib.fk_version.restype = ctypes.c_int
+_lib.fk_last_error.restype = ctypes.c_char_p
+_lib.fk_interface_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64]
+_lib.fk_interface_workspace_bytes.restype = ctypes.c_size_t
+_lib.fk_sync.argtypes = [_P]
+_lib.fk_sync.restype = ctypes.c_int
+_lib.fk_interface_solve.argtypes = [
+    ctypes.POINTER(fk_density), ctypes.POINTER(fk_data), _P, ctypes.c_int64,
+    ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
+    _P, _P, _P, _P, _P, _P, _P, _P,
+    ctypes.POINTER(fk_plan), _P, ctypes.c_size_t, _P]
+_lib.fk_interface_solve.restype = ctypes.c_int
+_lib.fk_timing_enable.argtypes = [ctypes.c_int]
+_lib.fk_timing_enable.restype = ctypes.c_int
+_lib.fk_timing_last.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+_lib.fk_timing_last.restype = ctypes.c_int
+
+
+def library():
+    """The loaded ctypes library handle."""
+    return _lib
+
+
+def declared_functions() -> list[str]:
+    """Names of the functions ``include/fk.h`` declares."""
+    src = open(HEADER_PATH).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*(fk_[a-z0-9_]+|subdomain_[a-z0-9_]+)\s*\(",
+                                 src, flags=re.M)))
+
+
+def _check(rc: int):
+    if rc != FK_OK:
+        raise FkError(rc, _lib.fk_last_error().decode())
+
+
+def fk_version() -> int:
+    return _lib.fk_version()
+
+
+def fk_last_error() -> str:
+    return _lib.fk_last_error().decode()
+
+
+def _density(d) -> fk_density:
+    return fk_density(int(d.kind), int(d.time_mode), float(d.amp), float(d.width2), float(d.cx),
+                      float(d.cy), float(d.orbit_r), float(d.omega), float(d.t_freeze))
+
+
+def _data(d, grids=None) -> fk_data:
+    gx = gy = None
+    n = 0
+    if grids is not None:
+        gx, gy = grids
+        n = int(round(gx.numel() ** 0.5)) - 1
+    return fk_data(int(d.init_kind), int(d.bdry_kind), int(d.score_mode), n, float(d.t_init),
+                   None if gx is None else gx.data_ptr(), None if gy is None else gy.data_ptr())
+
+
+def _stream(torch, device):
+    return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
+
+
+def fk_interface_workspace_bytes(n_nodes: int, n_paths: int) -> int:
+    return int(_lib.fk_interface_workspace_bytes(n_nodes, n_paths))
+
+
+def fk_timing_enable(enable: bool = True):
+    _check(_lib.fk_timing_enable(1 if enable else 0))
+
+
+def fk_timing_last():
+    """(path_kernel_ms, reduce_kernel_ms) of the last solve timed on this thread."""
+    a, b = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.fk_timing_last(ctypes.byref(a), ctypes.byref(b)))
+    return a.value, b.value
+
+
+def fk_sync(stream=None):
+    import torch
+    s = stream if stream is not None else _stream(torch, None)
+    _check(_lib.fk_sync(s))
+
+
+def fk_interface_solve(density, data, pts, t, dt, n_paths, seed=0, level_id=0, *,
+                       exit_step=False, scores=False, steps=False, plan=None,
+                       device="cuda", workspace=None, grids=None, out=None):
+    """Monte-Carlo interface solve (C: ``fk_interface_solve``).
+
+    ``density`` / ``data`` are objects with the fields of ``fk_density`` /
+    ``fk_data`` (e.g. ``workloads.Density`` / ``workloads.Data``); ``pts`` is
+    an [n, 2] array of node coordinates (host).  ``grids`` = (xi, eta) device
+    FP64 tensors for grid initial data.  Returns a dict of device tensors:
+    ``xi, eta, se_xi, se_eta`` (FP64 [n]), ``total_steps`` (uint64 [1] as
+    int64), and on request ``exit_step`` (int32 [n, N]), ``scores`` (FP32
+    [n, N, 2]) and ``steps`` (int64 [n]).  Runs asynchronously on torch's
+    current stream.
+    """
+    import torch
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 2)
+    n = pts.shape[0]
+    dev = torch.device(device)
+    if out is None:
+        out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("xi", "eta", "se_xi", "se_eta")}
+        out["total_steps"] = torch.zeros(1, dtype=torch.int64, device=dev)
+        if exit_step or steps:
+            out["exit_step"] = torch.empty((n, n_paths), dtype=torch.int32, device=dev)
+        if scores:
+            out["scores"] = torch.empty((n, n_paths, 2), dtype=torch.float32, device=dev)
+        if steps:
+            out["steps"] = torch.empty(n, dtype=torch.int64, device=dev)
+    need = _lib.fk_interface_workspace_bytes(n, n_paths)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    pl = None
+    if plan is not None:
+        pl = fk_plan(int(plan.get("block", 0)), int(plan.get("blocks_per_cu", 0)), int(plan.get("chunk", 0)), 0)
+
+    def ptr(k):
+        v = out.get(k)
+        return None if v is None else v.data_ptr()
+
+    rc = _lib.fk_interface_solve(
+        ctypes.byref(_density(density)), ctypes.byref(_data(data, grids)),
+        pts.ctypes.data_as(ctypes.c_void_p), n, float(t), float(dt), int(n_paths), int(seed), int(level_id),
+        ptr("xi"), ptr("eta"), ptr("se_xi"), ptr("se_eta"), ptr("exit_step"), ptr("scores"), ptr("steps"),
+        ptr("total_steps"), None if pl is None else ctypes.byref(pl),
+        workspace.data_ptr(), workspace.numel(), _stream(torch, dev))
+    _check(rc)
+    out["_workspace"] = workspace
+    return out

@@ -1,0 +1,342 @@
+// fk_api.hip -- C ABI of libfk.so: argument validation, host-side planning
+// (cost-ordered node tables, level constants, launch shape) and the launches
+// of the Monte-Carlo interface solve.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "fk.h"
+#include "fk_internal.hpp"
+
+namespace fk {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(FK_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+static size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+
+// Workspace layout of one interface solve.
+struct WsLayout {
+    size_t counters, levels, nodes, outs, scores, total;
+};
+
+static WsLayout ws_layout(int64_t n_levels, int64_t n_nodes, int64_t n_paths, bool own_scores) {
+    WsLayout L{};
+    size_t off = 0;
+    L.counters = off;
+    off += 256;
+    L.levels = off;
+    off += align256(sizeof(LevelDev) * (size_t)n_levels);
+    L.nodes = off;
+    off += align256(sizeof(NodeDev) * (size_t)n_nodes);
+    L.outs = off;
+    off += align256(sizeof(OutDev) * (size_t)n_nodes);
+    L.scores = off;
+    if (own_scores) off += align256(sizeof(float2) * (size_t)n_nodes * (size_t)n_paths);
+    L.total = off;
+    return L;
+}
+
+static int64_t step_count(double t, double dt) {
+    if (t <= 0.0) return 0;
+    return (int64_t)std::ceil(t / dt - 1e-9);
+}
+
+static bool kind_supported(int32_t kind) {
+    return kind == FK_DENSITY_CONST || kind == FK_DENSITY_BUMP || kind == FK_DENSITY_MOVING_BUMP ||
+           kind == FK_DENSITY_TWO_BUMPS || kind == FK_DENSITY_RIDGE;
+}
+
+int validate_density(const fk_density *w) {
+    if (!w) return fail(FK_E_INVAL, "density is NULL");
+    if (w->kind == 4) return fail(FK_E_UNSUPPORTED, "density kind 4 (ring) is not implemented on the GPU");
+    if (!kind_supported(w->kind)) return fail(FK_E_INVAL, "unknown density kind %d", w->kind);
+    if (w->time_mode != FK_TIME_BACKWARD && w->time_mode != FK_TIME_FROZEN)
+        return fail(FK_E_INVAL, "unknown time mode %d", w->time_mode);
+    const double v[] = {w->amp, w->width2, w->cx, w->cy, w->orbit_r, w->omega, w->t_freeze};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(FK_E_INVAL, "density parameter is not finite");
+    if (w->kind != FK_DENSITY_CONST) {
+        if (!(w->width2 > 0.0)) return fail(FK_E_INVAL, "density width2 must be > 0");
+        if (!(w->amp > -1.0)) return fail(FK_E_INVAL, "density amplitude must be > -1 (w > 0)");
+    }
+    return FK_OK;
+}
+
+int validate_data(const fk_data *d) {
+    if (!d) return fail(FK_E_INVAL, "data is NULL");
+    if (d->init_kind < 0 || d->init_kind > FK_DATA_GRID) return fail(FK_E_INVAL, "unknown init kind %d", d->init_kind);
+    if (d->bdry_kind < 0 || d->bdry_kind > FK_DATA_ZERO) return fail(FK_E_INVAL, "unknown boundary kind %d", d->bdry_kind);
+    if (d->score_mode != FK_SCORE_UNCLAMPED && d->score_mode != FK_SCORE_PROJECT)
+        return fail(FK_E_INVAL, "unknown score mode %d", d->score_mode);
+    if (!std::isfinite(d->t_init)) return fail(FK_E_INVAL, "t_init is not finite");
+    if (d->init_kind == FK_DATA_GRID) {
+        if (d->grid_n < 1 || !d->grid_xi || !d->grid_eta) return fail(FK_E_INVAL, "grid initial data needs grid_n >= 1 and both grids");
+    }
+    return FK_OK;
+}
+
+// Level constants in the FP32 form the path kernel uses.
+LevelDev make_level(const fk_density *w, const fk_data *d, double t, double dt, uint32_t level_id,
+                    uint32_t stream) {
+    LevelDev L{};
+    const int64_t K = step_count(t, dt);
+    const double dl = K > 0 ? t - (double)(K - 1) * dt : dt;
+    const double ln2 = 0.69314718055994530942;
+    L.tend = (float)(d->t_init + t);
+    L.horizon = (float)t;
+    L.dt = (float)dt;
+    L.dt_last = (float)dl;
+    L.cbm = (float)(-4.0 * ln2 * dt);
+    L.cbm_last = (float)(-4.0 * ln2 * dl);
+    L.K = (int32_t)K;
+    L.ctr3 = (level_id << 4) | (stream & 15u);
+    const double log2e = 1.44269504088896340736;
+    L.amp = (float)w->amp;
+    L.nscale = w->kind == FK_DENSITY_CONST ? 0.f : (float)(-log2e / w->width2);
+    L.a2s = w->kind == FK_DENSITY_CONST ? 0.f : (float)(2.0 * w->amp / w->width2);
+    L.cx = (float)w->cx;
+    L.cy = (float)w->cy;
+    L.orbit_r = (float)w->orbit_r;
+    L.omega_rev = (float)(w->omega / (2.0 * 3.14159265358979323846));
+    L.t_freeze = (float)w->t_freeze;
+    return L;
+}
+
+// Expected relative cost of a node: a proxy of its mean exit time, capped by
+// the horizon.  Only the order matters.
+double node_cost(double x, double y, double t) {
+    const double ax = x * (1.0 - x), ay = y * (1.0 - y);
+    if (ax <= 0.0 || ay <= 0.0) return 0.0;
+    const double tau = 1.0 / (2.0 / ax + 2.0 / ay);
+    return std::min(t, tau);
+}
+
+// Optional per-kernel event timing of the calling thread.
+struct Timing {
+    bool enabled = false;
+    bool recorded = false;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+};
+thread_local Timing g_timing;
+
+static hipError_t timing_mark(int i, hipStream_t s) {
+    if (!g_timing.enabled) return hipSuccess;
+    return hipEventRecord(g_timing.ev[i], s);
+}
+
+int device_cus(int *n_cu) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(FK_E_NODEVICE, "no HIP device: %s", hipGetErrorString(e));
+    e = hipDeviceGetAttribute(n_cu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    return FK_OK;
+}
+
+}  // namespace fk
+
+using namespace fk;
+
+extern "C" {
+
+int fk_version(void) { return 100; }
+
+const char *fk_last_error(void) { return g_last_error.c_str(); }
+
+size_t fk_interface_workspace_bytes(int64_t n_nodes, int64_t n_paths) {
+    if (n_nodes < 0 || n_paths < 2) return 0;
+    return ws_layout(1, n_nodes, n_paths, true).total;
+}
+
+int fk_timing_enable(int enable) {
+    g_last_error.clear();
+    if (enable && !g_timing.ev[0]) {
+        for (hipEvent_t &e : g_timing.ev) {
+            hipError_t r = hipEventCreate(&e);
+            if (r != hipSuccess) return hip_fail(r, "hipEventCreate");
+        }
+    }
+    g_timing.enabled = enable != 0;
+    g_timing.recorded = false;
+    return FK_OK;
+}
+
+int fk_timing_last(double *path_kernel_ms, double *reduce_kernel_ms) {
+    g_last_error.clear();
+    if (!g_timing.recorded) return fail(FK_E_INVAL, "no timed solve recorded");
+    hipError_t e = hipEventSynchronize(g_timing.ev[2]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float a = 0.f, b = 0.f;
+    if ((e = hipEventElapsedTime(&a, g_timing.ev[0], g_timing.ev[1])) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    if ((e = hipEventElapsedTime(&b, g_timing.ev[1], g_timing.ev[2])) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    if (path_kernel_ms) *path_kernel_ms = a;
+    if (reduce_kernel_ms) *reduce_kernel_ms = b;
+    return FK_OK;
+}
+
+int fk_sync(hipStream_t stream) {
+    hipError_t e = hipStreamSynchronize(stream);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "queued work");
+    return FK_OK;
+}
+
+int fk_interface_solve(const fk_density *w, const fk_data *d, const double *pts, int64_t n_nodes, double t,
+                       double dt, int64_t n_paths, uint64_t seed, uint32_t level_id, double *xi, double *eta,
+                       double *se_xi, double *se_eta, int32_t *exit_step, float *scores, int64_t *steps,
+                       uint64_t *total_steps, const fk_plan *plan, void *workspace, size_t workspace_bytes,
+                       hipStream_t stream) {
+    g_last_error.clear();
+    int rc;
+    if ((rc = validate_density(w)) != FK_OK) return rc;
+    if ((rc = validate_data(d)) != FK_OK) return rc;
+    if (n_nodes < 0) return fail(FK_E_INVAL, "n_nodes < 0");
+    if (n_paths < 2 || n_paths > 0x7fffffff) return fail(FK_E_INVAL, "n_paths must be in [2, 2^31)");
+    if (!std::isfinite(t) || t < 0.0) return fail(FK_E_INVAL, "t must be finite and >= 0");
+    if (!std::isfinite(dt) || !(dt > 0.0)) return fail(FK_E_INVAL, "dt must be finite and > 0");
+    if (level_id >= (1u << 28)) return fail(FK_E_INVAL, "level_id must be < 2^28");
+    const int64_t K = step_count(t, dt);
+    if (K > 0x7ffffffe) return fail(FK_E_INVAL, "t/dt too large");
+    if (n_nodes > 0 && !pts) return fail(FK_E_INVAL, "pts is NULL");
+    for (int64_t i = 0; i < n_nodes; ++i) {
+        const double x = pts[2 * i], y = pts[2 * i + 1];
+        if (!(x >= 0.0 && x <= 1.0 && y >= 0.0 && y <= 1.0))
+            return fail(FK_E_INVAL, "node %lld (%g, %g) is not in the closed unit square", (long long)i, x, y);
+    }
+    if (n_nodes > 0 && (!xi || !eta || !se_xi || !se_eta)) return fail(FK_E_INVAL, "an output pointer is NULL");
+    if (steps && !exit_step) return fail(FK_E_INVAL, "per-node steps need exit_step");
+    fk_plan pl{256, 0, 128, 0};
+    if (plan) {
+        if (plan->block) pl.block = plan->block;
+        if (plan->blocks_per_cu) pl.blocks_per_cu = plan->blocks_per_cu;
+        if (plan->chunk) pl.chunk = plan->chunk;
+    }
+    if (pl.block < 64 || pl.block > 256 || pl.block % 64) return fail(FK_E_INVAL, "plan block must be 64, 128, 192 or 256");
+    if (pl.chunk < 1 || pl.chunk > (1 << 20)) return fail(FK_E_INVAL, "plan chunk out of range");
+    if (pl.blocks_per_cu < 0 || pl.blocks_per_cu > 64) return fail(FK_E_INVAL, "plan blocks_per_cu out of range");
+    const int64_t cpn = (n_paths + pl.chunk - 1) / pl.chunk;
+    if (n_nodes * cpn >= 0xffffffffLL) return fail(FK_E_INVAL, "too many work chunks; raise plan chunk");
+    const WsLayout lay = ws_layout(1, n_nodes, n_paths, scores == nullptr);
+    if (!workspace || workspace_bytes < lay.total)
+        return fail(FK_E_NOMEM, "workspace too small: need %zu bytes", lay.total);
+    if (((uintptr_t)workspace & 255u) != 0) return fail(FK_E_INVAL, "workspace must be 256-byte aligned");
+    if (n_nodes == 0) return FK_OK;
+
+    int n_cu = 0;
+    if ((rc = device_cus(&n_cu)) != FK_OK) return rc;
+
+    // ---- host tables --------------------------------------------------------
+    const LevelDev lev = make_level(w, d, t, dt, level_id, 0u);
+    std::vector<int64_t> order((size_t)n_nodes);
+    std::iota(order.begin(), order.end(), 0);
+    std::vector<double> cost((size_t)n_nodes);
+    for (int64_t i = 0; i < n_nodes; ++i) cost[(size_t)i] = node_cost(pts[2 * i], pts[2 * i + 1], t);
+    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[(size_t)a] > cost[(size_t)b]; });
+    std::vector<NodeDev> nodes((size_t)n_nodes);
+    std::vector<OutDev> outs((size_t)n_nodes);
+    const bool shift = (d->init_kind == FK_DATA_IDENTITY && d->bdry_kind == FK_DATA_IDENTITY);
+    for (int64_t s = 0; s < n_nodes; ++s) {
+        const int64_t i = order[(size_t)s];
+        NodeDev &nd = nodes[(size_t)s];
+        // Start point as an FP32 (hi, lo) pair holding the FP64 node exactly
+        // to ~2^-48.
+        nd.x = (float)pts[2 * i];
+        nd.y = (float)pts[2 * i + 1];
+        nd.xlo = (float)(pts[2 * i] - (double)nd.x);
+        nd.ylo = (float)(pts[2 * i + 1] - (double)nd.y);
+        nd.nid = (uint32_t)i;
+        nd.level = 0;
+        nd.out = (uint64_t)i;
+        OutDev &od = outs[(size_t)i];
+        // The kernel stores scores minus the hi part of the start point; the
+        // shift adds that same value back.
+        od.shift_x = shift ? (double)nd.x : 0.0;
+        od.shift_y = shift ? (double)nd.y : 0.0;
+        od.K = K;
+    }
+
+    char *ws = (char *)workspace;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(ws + lay.levels, &lev, sizeof lev, hipMemcpyHostToDevice, stream)) != hipSuccess)
+        return hip_fail(e, "upload level table");
+    if ((e = hipMemcpyAsync(ws + lay.nodes, nodes.data(), sizeof(NodeDev) * nodes.size(), hipMemcpyHostToDevice, stream)) != hipSuccess)
+        return hip_fail(e, "upload node table");
+    if ((e = hipMemcpyAsync(ws + lay.outs, outs.data(), sizeof(OutDev) * outs.size(), hipMemcpyHostToDevice, stream)) != hipSuccess)
+        return hip_fail(e, "upload output table");
+    uint32_t *counters = (uint32_t *)(ws + lay.counters);
+    if ((e = launch_zero_u32(counters, 64, stream)) != hipSuccess) return hip_fail(e, "zero counters");
+
+    PathArgs a{};
+    a.levels = (const LevelDev *)(ws + lay.levels);
+    a.nodes = (const NodeDev *)(ws + lay.nodes);
+    a.scores = scores ? (float2 *)scores : (float2 *)(ws + lay.scores);
+    a.exit_step = exit_step;
+    a.queue = counters;
+    a.total_steps = total_steps ? (unsigned long long *)total_steps : (unsigned long long *)(counters + 2);
+    if (total_steps) {
+        if ((e = launch_zero_u32((uint32_t *)total_steps, 2, stream)) != hipSuccess) return hip_fail(e, "zero total_steps");
+    }
+    a.grid_xi = d->grid_xi;
+    a.grid_eta = d->grid_eta;
+    a.grid_n = d->grid_n;
+    a.init_kind = d->init_kind;
+    a.bdry_kind = d->bdry_kind;
+    a.score_mode = d->score_mode;
+    a.shift = shift ? 1 : 0;
+    a.key0 = (uint32_t)seed;
+    a.key1 = (uint32_t)(seed >> 32);
+    a.n_paths = (uint32_t)n_paths;
+    a.chunk = (uint32_t)pl.chunk;
+    a.cpn = (uint32_t)cpn;
+    a.total_chunks = (uint32_t)(n_nodes * cpn);
+
+    int bpc = pl.blocks_per_cu;
+    const int occ = path_kernel_max_blocks_per_cu(w->kind, w->time_mode, pl.block);
+    if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
+    const int grid = n_cu * bpc;
+    if ((e = timing_mark(0, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if ((e = launch_paths(w->kind, w->time_mode, a, grid, pl.block, stream)) != hipSuccess)
+        return hip_fail(e, "path kernel launch");
+    if ((e = timing_mark(1, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+
+    ReduceArgs r{};
+    r.scores = a.scores;
+    r.exit_step = exit_step;
+    r.outs = (const OutDev *)(ws + lay.outs);
+    r.n_out = n_nodes;
+    r.n_paths = n_paths;
+    r.xi = xi;
+    r.eta = eta;
+    r.se_xi = se_xi;
+    r.se_eta = se_eta;
+    r.steps = steps;
+    if ((e = launch_reduce(r, stream)) != hipSuccess) return hip_fail(e, "reduce kernel launch");
+    if ((e = timing_mark(2, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if (g_timing.enabled) g_timing.recorded = true;
+    return FK_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,119 @@
+// fk_device.hpp -- per-lane device math of the path kernels: counter-based
+// normals, the Winslow drift of the analytic densities, and the data
+// functions.  Everything here runs in registers in FP32 (integer for the
+// generator); nothing touches memory.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fk {
+
+// ---------------------------------------------------------------------------
+// Philox4x32-10 (Salmon, Moraes, Dror & Shaw, SC'11).  Ten rounds of two
+// 32x32->64-bit products (one v_mad_u64_u32 each on CDNA) and XORs; the key
+// schedule is wave-uniform and lives in scalar registers.
+// ---------------------------------------------------------------------------
+struct PhiloxOut {
+    uint32_t r0, r1, r2, r3;
+};
+
+__device__ __forceinline__ PhiloxOut philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                                   uint32_t k0, uint32_t k1) {
+#pragma unroll
+    for (int r = 0; r < 10; ++r) {
+        const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return PhiloxOut{c0, c1, c2, c3};
+}
+
+// Hardware transcendentals.  v_sin/v_cos take their argument in revolutions
+// (sin(2 pi x)), v_log is log2 and v_exp is exp2.
+__device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ float hw_exp2(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float hw_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float hw_sin_rev(float x) { return __builtin_amdgcn_sinf(x); }
+__device__ __forceinline__ float hw_cos_rev(float x) { return __builtin_amdgcn_cosf(x); }
+
+// Box-Muller increments: with u1 = ((ra >> 8) + 1) 2^-24 in (0,1] and
+// u2 = (rb >> 8) 2^-24 in [0,1), returns sqrt(2 D) (z0, z1) where
+// z0 = sqrt(-2 ln u1) cos(2 pi u2), z1 = sqrt(-2 ln u1) sin(2 pi u2).
+// cbm = -4 ln2 D folds sqrt(2 D) and the change of logarithm base.
+__device__ __forceinline__ void brownian_increment(uint32_t ra, uint32_t rb, float cbm,
+                                                   float &dwx, float &dwy) {
+    const float u1 = (float)((ra >> 8) + 1u) * 0x1p-24f;
+    const float u2 = (float)(rb >> 8) * 0x1p-24f;
+    const float rad = hw_sqrt(cbm * hw_log2(u1));
+    dwx = rad * hw_cos_rev(u2);
+    dwy = rad * hw_sin_rev(u2);
+}
+
+// ---------------------------------------------------------------------------
+// Densities and the Winslow drift b = -grad w / w (eq. (6)).  For a Gaussian
+// bump w = 1 + A e, e = exp(-|X - c|^2 / s2):  b = (2 A / s2) e / w * (X - c).
+// ---------------------------------------------------------------------------
+enum : int { KIND_CONST = 0, KIND_BUMP = 1, KIND_MOVING = 2, KIND_TWO = 3, KIND_RIDGE = 5 };
+enum : int { TIME_BACKWARD = 0, TIME_FROZEN = 1 };
+
+struct DensityRegs {
+    float amp, nscale, a2s;
+    float cx, cy;        // centre (static) / orbit centre
+    float orbit_r, omega_rev;
+};
+
+// Bump centre offset (R cos(omega tau), R sin(omega tau)).
+__device__ __forceinline__ void orbit(const DensityRegs &d, float tau, float &ox, float &oy) {
+    const float rev = tau * d.omega_rev;
+    ox = d.orbit_r * hw_cos_rev(rev);
+    oy = d.orbit_r * hw_sin_rev(rev);
+}
+
+// Drift at (x, y); (ox, oy) is the centre offset (zero for static kinds).
+template <int KIND>
+__device__ __forceinline__ void drift(const DensityRegs &d, float ox, float oy, float x, float y,
+                                      float &bx, float &by) {
+    if constexpr (KIND == KIND_CONST) {
+        bx = 0.f;
+        by = 0.f;
+    } else if constexpr (KIND == KIND_BUMP || KIND == KIND_MOVING) {
+        const float dx = x - (d.cx + ox);
+        const float dy = y - (d.cy + oy);
+        const float r2 = fmaf(dx, dx, dy * dy);
+        const float e = hw_exp2(r2 * d.nscale);
+        const float f = e * d.a2s * hw_rcp(fmaf(d.amp, e, 1.f));
+        bx = f * dx;
+        by = f * dy;
+    } else if constexpr (KIND == KIND_TWO) {
+        const float dy = y - (d.cy + oy);
+        const float d1x = x - (d.cx + ox);
+        const float d2x = x - (d.cx - ox);
+        const float dy2 = dy * dy;
+        const float e1 = hw_exp2(fmaf(d1x, d1x, dy2) * d.nscale);
+        const float e2 = hw_exp2(fmaf(d2x, d2x, dy2) * d.nscale);
+        const float f = d.a2s * hw_rcp(fmaf(d.amp, e1 + e2, 1.f));
+        bx = f * fmaf(e1, d1x, e2 * d2x);
+        by = f * (e1 + e2) * dy;
+    } else {  // KIND_RIDGE: depends on x only
+        const float dx = x - d.cx;
+        const float e = hw_exp2(dx * dx * d.nscale);
+        bx = e * d.a2s * hw_rcp(fmaf(d.amp, e, 1.f)) * dx;
+        by = 0.f;
+    }
+}
+
+// sin(pi x) sin(pi y) via the revolution-argument sine.
+__device__ __forceinline__ float sin_mode(float x, float y) {
+    return hw_sin_rev(0.5f * x) * hw_sin_rev(0.5f * y);
+}
+
+}  // namespace fk

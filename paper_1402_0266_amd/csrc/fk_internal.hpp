@@ -1,0 +1,83 @@
+// fk_internal.hpp -- device-side tables and kernel arguments shared by the
+// library's own translation units (not part of the public ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fk.h"
+
+namespace fk {
+
+// Per time level: horizon, step sizes and density parameters, pre-folded into
+// the FP32 constants the path kernel uses.
+struct alignas(16) LevelDev {
+    float tend;        // PDE time at path start: t_init + t
+    float horizon;     // t: elapsed time since the initial data at path start
+    float dt;          // step size of all steps but the last
+    float dt_last;     // t - (K-1) dt
+    float cbm;         // -4 ln2 dt: sqrt(cbm * log2(u1)) = sqrt(2 dt) * sqrt(-2 ln u1)
+    float cbm_last;    // same for dt_last
+    int32_t K;         // number of steps
+    uint32_t ctr3;     // Philox counter word 3: (level_id << 4) | stream
+    float amp;         // density amplitude A
+    float nscale;      // -log2(e) / width2 (argument scale of exp2)
+    float a2s;         // 2 A / width2
+    float cx, cy;      // centre (static) or orbit centre (moving)
+    float orbit_r;     // orbit radius
+    float omega_rev;   // omega / (2 pi): angular speed in revolutions per unit time
+    float t_freeze;    // frozen density time
+};
+
+// One interface node, in launch (cost-sorted) order.
+struct alignas(16) NodeDev {
+    float x, y;        // start point, hi parts
+    float xlo, ylo;    // start point, lo parts (x + xlo is the FP64 node to ~2^-48)
+    uint32_t nid;      // Philox counter word 2: index of the node in its level
+    uint32_t level;    // index into the level table
+    uint64_t out;      // output row: per-path records live at out * n_paths + path
+};
+
+// One output row: the shift the per-path records are stored relative to.
+struct alignas(16) OutDev {
+    double shift_x, shift_y;
+    int64_t K;
+    int64_t pad;
+};
+
+struct PathArgs {
+    const LevelDev *levels;
+    const NodeDev *nodes;
+    float2 *scores;                  // [n_out * n_paths]
+    int32_t *exit_step;              // [n_out * n_paths] or nullptr
+    uint32_t *queue;                 // chunk counter (zeroed before launch)
+    unsigned long long *total_steps; // accumulated Euler-Maruyama steps
+    const double *grid_xi;
+    const double *grid_eta;
+    int32_t grid_n;
+    int32_t init_kind, bdry_kind, score_mode;
+    int32_t shift;                   // identity data: store scores minus the start point
+    uint32_t key0, key1;
+    uint32_t n_paths;                // paths per node
+    uint32_t chunk;                  // paths per queue grab
+    uint32_t cpn;                    // chunks per node
+    uint32_t total_chunks;
+};
+
+struct ReduceArgs {
+    const float2 *scores;
+    const int32_t *exit_step;        // or nullptr
+    const OutDev *outs;
+    int64_t n_out;
+    int64_t n_paths;
+    double *xi, *eta, *se_xi, *se_eta;
+    int64_t *steps;                  // or nullptr
+};
+
+// Launch helpers implemented in fk_paths.hip.
+hipError_t launch_zero_u32(uint32_t *p, int n_words, hipStream_t s);
+hipError_t launch_paths(int kind, int time_mode, const PathArgs &a, int grid, int block, hipStream_t s);
+hipError_t launch_reduce(const ReduceArgs &a, hipStream_t s);
+int path_kernel_max_blocks_per_cu(int kind, int time_mode, int block);
+
+}  // namespace fk

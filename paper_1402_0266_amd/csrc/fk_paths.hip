@@ -1,0 +1,362 @@
+// fk_paths.hip -- the Monte-Carlo hot path: a persistent path kernel (one
+// path per lane, lanes refilled from a device work queue as their paths
+// end) and the FP64 estimator reduction.
+//
+// Method (Sect. 3, eqs. (5)-(7); Sect. 4): for an interface node P, a path
+// X_0 = P, X_{k+1} = X_k + b(tau_k, X_k) D_k + sqrt(2 D_k) z_k takes
+// Euler-Maruyama steps of dX = -(grad w / w) ds + sqrt(2) dW with a boundary
+// test after every step.  A path that leaves the square scores the boundary
+// data at its exit point; a path alive after K steps scores the initial data.
+// The node value is the mean of the scores over its paths.
+//
+// MI355X mapping:
+//  * The path loop is ALU-bound (Philox integer multiplies, 6-8 hardware
+//    transcendentals, ~40 FP32 ops per step) and touches no memory, so every
+//    lane keeps its whole path state in registers.
+//  * Exit times vary by two orders of magnitude between nodes and
+//    geometrically within a node; lanes therefore refill individually: a
+//    wavefront grabs `chunk` consecutive paths of one node from a global
+//    atomic queue and hands them to whichever lanes are idle, so a lane never
+//    waits for the rest of its wavefront.  Nodes are queued in decreasing
+//    expected cost so the launch ends on short paths.
+//  * Each finished path writes one 8-byte FP32 score record; the reduction
+//    kernel sums them per node in FP64 in a fixed order, so results do not
+//    depend on the launch schedule (the record traffic is < 0.1% of the
+//    kernel time at the target sizes).
+//  * Positions are FP32 pairs (hi, lo): each increment is added to lo and the
+//    pair renormalised, which keeps the position to ~2^-48 over 10^4 steps
+//    (plain FP32 accumulation drifts by ~1e-6 and flips exit decisions).
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fk_device.hpp"
+#include "fk_internal.hpp"
+
+namespace fk {
+
+__global__ void zero_u32_kernel(uint32_t *p, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0u;
+}
+
+hipError_t launch_zero_u32(uint32_t *p, int n_words, hipStream_t s) {
+    const int blocks = (n_words + 255) / 256;
+    hipLaunchKernelGGL(zero_u32_kernel, dim3(blocks), dim3(256), 0, s, p, n_words);
+    return hipGetLastError();
+}
+
+namespace {
+
+// Lane path state.
+struct Lane {
+    float xh, xl, yh, yl;  // position as hi + lo pairs
+    int32_t k;             // steps taken
+    int32_t K;             // steps allowed
+    uint32_t path, nid, ctr3;
+    uint64_t rec;          // record index
+    float px, py;          // start point (score shift for identity data)
+    float tend, horizon, dt, dt_last, cbm, cbm_last;
+    float ox, oy;          // frozen / static centre offset
+    DensityRegs dens;
+};
+
+// Adds an increment to a (hi, lo) pair and renormalises so that hi is the
+// FP32 rounding of hi + lo.
+__device__ __forceinline__ void comp_add(float &hi, float &lo, float inc) {
+    const float t = lo + inc;
+    const float s = hi + t;
+    lo = (hi - s) + t;
+    hi = s;
+}
+
+template <int KIND, int TMODE>
+__device__ __forceinline__ bool em_step(Lane &L, uint32_t ra, uint32_t rb) {
+    const bool last = (L.k == L.K - 1);
+    const float D = last ? L.dt_last : L.dt;
+    const float cb = last ? L.cbm_last : L.cbm;
+    float dwx, dwy;
+    brownian_increment(ra, rb, cb, dwx, dwy);
+    float ox = L.ox, oy = L.oy;
+    if constexpr ((KIND == KIND_MOVING || KIND == KIND_TWO) && TMODE == TIME_BACKWARD) {
+        // PDE time t_init + t - s_k, s_k = k dt (the step about to be taken).
+        orbit(L.dens, fmaf(-(float)L.k, L.dt, L.tend), ox, oy);
+    }
+    float bx, by;
+    drift<KIND>(L.dens, ox, oy, L.xh, L.yh, bx, by);
+    comp_add(L.xh, L.xl, fmaf(bx, D, dwx));
+    comp_add(L.yh, L.yl, fmaf(by, D, dwy));
+    L.k += 1;
+    // Outside the closed square.  hi is the rounded position; (hi - 1) is
+    // exact near 1, so the tests against 1 see the lo part too.
+    return (L.xh < 0.f) | (((L.xh - 1.f) + L.xl) > 0.f) | (L.yh < 0.f) | (((L.yh - 1.f) + L.yl) > 0.f);
+}
+
+__device__ __forceinline__ float grid_bilinear(const double *g, int n, float x, float y) {
+    const float fx = x * (float)n, fy = y * (float)n;
+    int i = (int)floorf(fx), j = (int)floorf(fy);
+    i = min(max(i, 0), n - 1);
+    j = min(max(j, 0), n - 1);
+    const float ax = fx - (float)i, ay = fy - (float)j;
+    const double *r0 = g + (int64_t)j * (n + 1);
+    const double *r1 = r0 + (n + 1);
+    const float v00 = (float)r0[i], v01 = (float)r0[i + 1];
+    const float v10 = (float)r1[i], v11 = (float)r1[i + 1];
+    return (1.f - ay) * ((1.f - ax) * v00 + ax * v01) + ay * ((1.f - ax) * v10 + ax * v11);
+}
+
+}  // namespace
+
+template <int KIND, int TMODE>
+__global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
+    const uint32_t lane = threadIdx.x & 63u;
+    // Wavefront-uniform queue cursor: current node slot and path range.
+    uint32_t q_slot = 0, q_next = 0, q_end = 0;
+    bool q_done = false;
+    // Philox key schedule is uniform.
+    const uint32_t key0 = a.key0, key1 = a.key1;
+
+    Lane L;
+    bool active = false;
+    uint32_t my_steps = 0;
+
+    for (;;) {
+        // ---- refill idle lanes ------------------------------------------
+        uint64_t need = __ballot(!active);
+        while (need != 0ull && !q_done) {
+            if (q_next >= q_end) {
+                uint32_t c = 0;
+                if (lane == 0) c = atomicAdd(a.queue, 1u);
+                c = __builtin_amdgcn_readfirstlane(c);
+                if (c >= a.total_chunks) {
+                    q_done = true;
+                    break;
+                }
+                q_slot = c / a.cpn;
+                q_next = (c - q_slot * a.cpn) * a.chunk;
+                q_end = min(q_next + a.chunk, a.n_paths);
+                continue;
+            }
+            const uint32_t avail = q_end - q_next;
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+            if (!active && rank < avail) {
+                const NodeDev nd = a.nodes[q_slot];
+                const LevelDev lv = a.levels[nd.level];
+                L.path = q_next + rank;
+                L.xh = nd.x;
+                L.yh = nd.y;
+                L.xl = nd.xlo;
+                L.yl = nd.ylo;
+                L.px = nd.x;
+                L.py = nd.y;
+                L.k = 0;
+                L.K = lv.K;
+                L.nid = nd.nid;
+                L.ctr3 = lv.ctr3;
+                L.rec = nd.out * (uint64_t)a.n_paths + L.path;
+                L.tend = lv.tend;
+                L.horizon = lv.horizon;
+                L.dt = lv.dt;
+                L.dt_last = lv.dt_last;
+                L.cbm = lv.cbm;
+                L.cbm_last = lv.cbm_last;
+                L.dens.amp = lv.amp;
+                L.dens.nscale = lv.nscale;
+                L.dens.a2s = lv.a2s;
+                L.dens.cx = lv.cx;
+                L.dens.cy = lv.cy;
+                L.dens.orbit_r = lv.orbit_r;
+                L.dens.omega_rev = lv.omega_rev;
+                L.ox = 0.f;
+                L.oy = 0.f;
+                if constexpr ((KIND == KIND_MOVING || KIND == KIND_TWO) && TMODE == TIME_FROZEN) {
+                    orbit(L.dens, lv.t_freeze, L.ox, L.oy);
+                }
+                active = true;
+            }
+            const uint32_t n_need = (uint32_t)__popcll(need);
+            q_next += min(n_need, avail);
+            need = __ballot(!active);
+        }
+        if (__ballot(active) == 0ull) break;
+
+        // ---- two Euler-Maruyama steps from one Philox call ----------------
+        if (active) {
+            bool out = false;
+            if (L.k < L.K) {
+                const PhiloxOut r = philox4x32_10((uint32_t)L.k >> 1, L.path, L.nid, L.ctr3, key0, key1);
+                out = em_step<KIND, TMODE>(L, r.r0, r.r1);
+                my_steps += 1;
+                if (!out && L.k < L.K) {
+                    out = em_step<KIND, TMODE>(L, r.r2, r.r3);
+                    my_steps += 1;
+                }
+            }
+            if (out || L.k >= L.K) {
+                // ---- score (eq. (7b)) --------------------------------------
+                float sx, sy;
+                const int kind = out ? a.bdry_kind : a.init_kind;
+                float x = L.xh, y = L.yh;
+                float lx = L.xl, ly = L.yl;
+                if (out && a.score_mode == FK_SCORE_PROJECT) {
+                    if (x < 0.f || x > 1.f) { x = fminf(fmaxf(x, 0.f), 1.f); lx = 0.f; }
+                    if (y < 0.f || y > 1.f) { y = fminf(fmaxf(y, 0.f), 1.f); ly = 0.f; }
+                }
+                if (kind == FK_DATA_IDENTITY) {
+                    // Relative to the start point when both data kinds are
+                    // the identity (the reduction adds it back), else absolute.
+                    const float bx0 = a.shift ? L.px : 0.f, by0 = a.shift ? L.py : 0.f;
+                    sx = (x - bx0) + lx;
+                    sy = (y - by0) + ly;
+                } else if (kind == FK_DATA_SIN) {
+                    float v = sin_mode(x, y);
+                    if (out) {
+                        // elapsed time since the initial data: t - s_kappa
+                        const float s = (L.k >= L.K) ? L.horizon : (float)L.k * L.dt;
+                        v *= hw_exp2(-2.f * 9.8696044f * 1.44269504f * (L.horizon - s));
+                    }
+                    sx = v;
+                    sy = v;
+                } else if (kind == FK_DATA_GRID) {
+                    sx = grid_bilinear(a.grid_xi, a.grid_n, x, y);
+                    sy = grid_bilinear(a.grid_eta, a.grid_n, x, y);
+                } else {
+                    sx = 0.f;
+                    sy = 0.f;
+                }
+                a.scores[L.rec] = make_float2(sx, sy);
+                if (a.exit_step) a.exit_step[L.rec] = out ? L.k : -1;
+                active = false;
+            }
+        }
+    }
+
+    // ---- step count: wavefront sum, one atomic per wavefront --------------
+    unsigned long long st = my_steps;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) st += __shfl_xor(st, off, 64);
+    if (lane == 0 && st != 0ull) atomicAdd(a.total_steps, st);
+}
+
+namespace {
+template <int KIND, int TMODE>
+hipError_t launch_one(const PathArgs &a, int grid, int block, hipStream_t s) {
+    hipLaunchKernelGGL((fk_path_kernel<KIND, TMODE>), dim3(grid), dim3(block), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int KIND, int TMODE>
+int max_blocks(int block) {
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk_path_kernel<KIND, TMODE>, block, 0) != hipSuccess)
+        return 0;
+    return nb;
+}
+}  // namespace
+
+hipError_t launch_paths(int kind, int time_mode, const PathArgs &a, int grid, int block, hipStream_t s) {
+    const bool frozen = (time_mode == TIME_FROZEN);
+    switch (kind) {
+    case KIND_CONST: return launch_one<KIND_CONST, TIME_BACKWARD>(a, grid, block, s);
+    case KIND_BUMP: return launch_one<KIND_BUMP, TIME_BACKWARD>(a, grid, block, s);
+    case KIND_RIDGE: return launch_one<KIND_RIDGE, TIME_BACKWARD>(a, grid, block, s);
+    case KIND_MOVING:
+        return frozen ? launch_one<KIND_MOVING, TIME_FROZEN>(a, grid, block, s)
+                      : launch_one<KIND_MOVING, TIME_BACKWARD>(a, grid, block, s);
+    case KIND_TWO:
+        return frozen ? launch_one<KIND_TWO, TIME_FROZEN>(a, grid, block, s)
+                      : launch_one<KIND_TWO, TIME_BACKWARD>(a, grid, block, s);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+int path_kernel_max_blocks_per_cu(int kind, int time_mode, int block) {
+    const bool frozen = (time_mode == TIME_FROZEN);
+    switch (kind) {
+    case KIND_CONST: return max_blocks<KIND_CONST, TIME_BACKWARD>(block);
+    case KIND_BUMP: return max_blocks<KIND_BUMP, TIME_BACKWARD>(block);
+    case KIND_RIDGE: return max_blocks<KIND_RIDGE, TIME_BACKWARD>(block);
+    case KIND_MOVING: return frozen ? max_blocks<KIND_MOVING, TIME_FROZEN>(block) : max_blocks<KIND_MOVING, TIME_BACKWARD>(block);
+    case KIND_TWO: return frozen ? max_blocks<KIND_TWO, TIME_FROZEN>(block) : max_blocks<KIND_TWO, TIME_BACKWARD>(block);
+    default: return 0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Estimator reduction (Sect. 4: expectations replaced by arithmetic means).
+// One workgroup per output node: FP64 sums of the shifted scores and their
+// squares, wavefront shuffles then LDS, in a fixed order.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__global__ void __launch_bounds__(256) fk_reduce_kernel(const ReduceArgs a) {
+    const int64_t o = blockIdx.x;
+    if (o >= a.n_out) return;
+    const float2 *rec = a.scores + o * a.n_paths;
+    const int32_t *ex = a.exit_step ? a.exit_step + o * a.n_paths : nullptr;
+    const int64_t K = a.outs[o].K;
+    double s1x = 0.0, s2x = 0.0, s1y = 0.0, s2y = 0.0;
+    long long st = 0;
+    for (int64_t p = threadIdx.x; p < a.n_paths; p += blockDim.x) {
+        const float2 v = rec[p];
+        const double vx = v.x, vy = v.y;
+        s1x += vx;
+        s2x = fma(vx, vx, s2x);
+        s1y += vy;
+        s2y = fma(vy, vy, s2y);
+        if (ex) {
+            const int32_t e = ex[p];
+            st += (e < 0) ? K : e;
+        }
+    }
+    s1x = wave_sum(s1x);
+    s2x = wave_sum(s2x);
+    s1y = wave_sum(s1y);
+    s2y = wave_sum(s2y);
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) st += __shfl_xor(st, off, 64);
+    __shared__ double part[4][16];
+    __shared__ long long pst[16];
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        part[0][w] = s1x;
+        part[1][w] = s2x;
+        part[2][w] = s1y;
+        part[3][w] = s2y;
+        pst[w] = st;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int nw = (blockDim.x + 63) >> 6;
+        double t1x = 0.0, t2x = 0.0, t1y = 0.0, t2y = 0.0;
+        long long ts = 0;
+        for (int i = 0; i < nw; ++i) {
+            t1x += part[0][i];
+            t2x += part[1][i];
+            t1y += part[2][i];
+            t2y += part[3][i];
+            ts += pst[i];
+        }
+        const double N = (double)a.n_paths;
+        const double mx = t1x / N, my = t1y / N;
+        const double vx = fmax((t2x - t1x * mx) / (N - 1.0), 0.0);
+        const double vy = fmax((t2y - t1y * my) / (N - 1.0), 0.0);
+        a.xi[o] = a.outs[o].shift_x + mx;
+        a.eta[o] = a.outs[o].shift_y + my;
+        a.se_xi[o] = sqrt(vx / N);
+        a.se_eta[o] = sqrt(vy / N);
+        if (a.steps) a.steps[o] = ts;
+    }
+}
+
+hipError_t launch_reduce(const ReduceArgs &a, hipStream_t s) {
+    if (a.n_out == 0) return hipSuccess;
+    hipLaunchKernelGGL(fk_reduce_kernel, dim3((unsigned)a.n_out), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+}  // namespace fk

@@ -1,0 +1,65 @@
+"""The C ABI of libfk.so on the CPU: it loads, exports every function the
+header declares, and rejects bad arguments before touching a device."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+
+def test_exports_every_declared_function(fk):
+    names = fk.declared_functions()
+    assert "fk_interface_solve" in names
+    lib = fk.library()
+    for n in names:
+        assert hasattr(lib, n), n
+
+
+def test_version(fk):
+    assert fk.fk_version() >= 100
+
+
+def _call(fk, dens=None, data=None, pts=None, t=0.05, dt=1e-4, n_paths=16, ws_bytes=None, out_ptr=8):
+    dens = dens or W.static_bump()
+    data = data or W.Data()
+    pts = np.ascontiguousarray(pts if pts is not None else [[0.5, 0.5]], dtype=np.float64)
+    n = pts.shape[0]
+    need = fk.fk_interface_workspace_bytes(n, max(n_paths, 2))
+    ws = ws_bytes if ws_bytes is not None else need
+    lib = fk.library()
+    # Non-null dummies: every call here must fail validation before any use.
+    return lib.fk_interface_solve(ctypes.byref(fk._density(dens)), ctypes.byref(fk._data(data)),
+                                  pts.ctypes.data_as(ctypes.c_void_p), n, t, dt, n_paths, 0, 0,
+                                  out_ptr, out_ptr, out_ptr, out_ptr, None, None, None, None, None,
+                                  4096, ws, None)
+
+
+@pytest.mark.parametrize("kw,code", [
+    (dict(n_paths=1), -1),
+    (dict(dt=0.0), -1),
+    (dict(dt=float("nan")), -1),
+    (dict(t=-1.0), -1),
+    (dict(pts=[[1.5, 0.5]]), -1),
+    (dict(pts=[[0.5, float("nan")]]), -1),
+    (dict(dens=W.Density(kind=9)), -1),
+    (dict(dens=W.paper_ring()), -5),
+    (dict(data=W.Data(bdry_kind=W.DATA_GRID)), -1),
+    (dict(data=W.Data(init_kind=W.DATA_GRID)), -1),
+    (dict(ws_bytes=16), -3),
+    (dict(out_ptr=None), -1),
+])
+def test_validation_errors(fk, kw, code):
+    rc = _call(fk, **kw)
+    assert rc == code
+    assert fk.fk_last_error() != ""
+
+
+def test_empty_solve_is_a_noop(fk):
+    assert _call(fk, pts=np.zeros((0, 2))) == 0
+
+
+def test_workspace_size(fk):
+    a = fk.fk_interface_workspace_bytes(1521, 100_000)
+    assert a >= 1521 * 100_000 * 8
+    assert fk.fk_interface_workspace_bytes(10, 1) == 0

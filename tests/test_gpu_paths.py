@@ -1,0 +1,212 @@
+"""GPU parity of the Monte-Carlo interface solve against the FP64 CPU oracle.
+
+Same Philox counters on both sides.  The bar (per node, per component):
+  * exit steps identical on >= 99.9% of paths,
+  * mean within 3 standard errors AND within 1e-5 absolute of the oracle's
+    estimate on the same random stream,
+  * standard error within 1% relative.
+Plus closed forms that hold for any step size (w = 1 identity data and the
+decaying sine mode), invariants, edge cases and schedule invariance.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+THREADS = min(16, os.cpu_count() or 1)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    return torch
+
+
+def run_gpu(fk, torch, dens, data, pts, t, dt, n, seed=0, level_id=0, plan=None, grids=None):
+    print(f"[gpu] kind={dens.kind} mode={dens.time_mode} nodes={len(pts)} N={n} t={t} dt={dt} seed={seed}",
+          flush=True)
+    g = fk.fk_interface_solve(dens, data, pts, t, dt, n, seed, level_id, exit_step=True, scores=True,
+                              steps=True, plan=plan, grids=grids)
+    torch.cuda.synchronize()
+    return {k: v.cpu().numpy() for k, v in g.items() if not k.startswith("_")}
+
+
+def run_oracle(oracle_mod, dens, data, pts, t, dt, n, seed=0, level_id=0):
+    return oracle_mod.fk_solve(dens, data, pts, t, dt, n, seed, level_id, want_exit=True, threads=THREADS)
+
+
+def assert_parity(g, o, abs_tol=1e-5, match_min=0.999):
+    ex_g, ex_o = g["exit_step"], o["exit_step"]
+    match = float(np.mean(ex_g == ex_o))
+    mean_g = np.stack([g["xi"], g["eta"]], axis=1)
+    se_g = np.stack([g["se_xi"], g["se_eta"]], axis=1)
+    d = np.abs(mean_g - o["mean"])
+    print(f"exit-step match {match:.6f}; max |mean diff| {d.max():.3e}; "
+          f"max diff/se {np.max(d / np.maximum(o['se'], 1e-300)):.3f}", flush=True)
+    assert match >= match_min
+    assert np.all(d <= abs_tol)
+    assert np.all(d <= 3.0 * o["se"] + 1e-15)
+    nz = o["se"] > 0
+    assert np.all(np.abs(se_g[nz] - o["se"][nz]) <= 0.01 * o["se"][nz])
+    # per-node step counts and the total agree with the exit steps
+    assert np.array_equal(g["steps"], o["steps"]) or match < 1.0
+    assert int(g["total_steps"][0]) == int(g["steps"].sum())
+
+
+def test_static_bump_31_nodes_full(fk, torch_cuda, oracle_mod):
+    """Two sub-domains, 31 interface nodes, t = 0.05, dt = 1e-4, 10^4 paths."""
+    wl = W.STATIC_BUMP_31
+    pts = wl.nodes()
+    g = run_gpu(fk, torch_cuda, wl.density, wl.data, pts, wl.t, wl.dt, wl.n_paths)
+    o = run_oracle(oracle_mod, wl.density, wl.data, pts, wl.t, wl.dt, wl.n_paths)
+    assert_parity(g, o)
+    # invariants: means in [0, 1]; eta non-decreasing along the vertical interface
+    m = np.stack([g["xi"], g["eta"]], axis=1)
+    s = np.stack([g["se_xi"], g["se_eta"]], axis=1)
+    assert np.all(m >= -3 * s) and np.all(m <= 1 + 3 * s)
+    de = np.diff(g["eta"])
+    assert np.all(de >= -3 * np.sqrt(s[1:, 1] ** 2 + s[:-1, 1] ** 2))
+
+
+def test_moving_bump_node_subset(fk, torch_cuda, oracle_mod):
+    """Moving bump, 4x4 layout, every 32nd canonical node, t = 0.1, dt = 1e-5."""
+    wl = W.MOVING_BUMP_1521
+    pts = wl.nodes()[::32]
+    g = run_gpu(fk, torch_cuda, wl.density, wl.data, pts, wl.t, wl.dt, 512)
+    o = run_oracle(oracle_mod, wl.density, wl.data, pts, wl.t, wl.dt, 512)
+    assert_parity(g, o)
+
+
+def test_const_identity_exact(fk, torch_cuda, oracle_mod):
+    """w = 1, identity data: the discrete chain is a martingale stopped at the
+    exit (unclamped scoring), so E = P exactly for any dt."""
+    pts = W.uniform_points(40, seed=1, lo=0.0, hi=1.0)
+    g = run_gpu(fk, torch_cuda, W.CONST, W.Data(), pts, 0.08, 2e-3, 4000, seed=3)
+    o = run_oracle(oracle_mod, W.CONST, W.Data(), pts, 0.08, 2e-3, 4000, seed=3)
+    assert_parity(g, o)
+    z = (np.stack([g["xi"], g["eta"]], 1) - pts) / np.stack([g["se_xi"], g["se_eta"]], 1)
+    assert np.all(np.abs(z) < 4.5)
+
+
+def test_const_sin_mode_closed_form(fk, torch_cuda, oracle_mod):
+    """w = 1, phi = sin(pi x) sin(pi y), boundary data exp(-2 pi^2 (t-s)) phi:
+    E = exp(-2 pi^2 t) phi(P) for any dt."""
+    pts = W.uniform_points(24, seed=2)
+    data = W.Data(init_kind=W.DATA_SIN, bdry_kind=W.DATA_SIN)
+    t, dt = 0.05, 1e-3
+    g = run_gpu(fk, torch_cuda, W.CONST, data, pts, t, dt, 8000, seed=5)
+    o = run_oracle(oracle_mod, W.CONST, data, pts, t, dt, 8000, seed=5)
+    assert_parity(g, o)
+    exact = math.exp(-2 * math.pi ** 2 * t) * np.sin(math.pi * pts[:, 0]) * np.sin(math.pi * pts[:, 1])
+    assert np.all(np.abs(g["xi"] - exact) <= 4.5 * g["se_xi"] + 1e-12)
+
+
+def test_ridge_eta_exact(fk, torch_cuda, oracle_mod):
+    """w = w(x): the y-drift vanishes, so eta = y exactly for any dt."""
+    pts = W.uniform_points(24, seed=4)
+    dens = W.ridge()
+    g = run_gpu(fk, torch_cuda, dens, W.Data(), pts, 0.05, 1e-4, 4000, seed=7)
+    o = run_oracle(oracle_mod, dens, W.Data(), pts, 0.05, 1e-4, 4000, seed=7)
+    assert_parity(g, o)
+    assert np.all(np.abs(g["eta"] - pts[:, 1]) <= 4.5 * g["se_eta"])
+
+
+def test_two_bumps_frozen_grid_data(fk, torch_cuda, oracle_mod):
+    """Two counter-rotating bumps frozen at t_n, initial data bilinear in a
+    nodal grid (one mesh step), projected boundary scoring."""
+    import torch
+    n = 48
+    x = np.arange(n + 1) / n
+    X, Y = np.meshgrid(x, x)
+    gx = X + 0.02 * np.sin(np.pi * X) * np.sin(2 * np.pi * Y)
+    gy = Y + 0.02 * np.sin(2 * np.pi * X) * np.sin(np.pi * Y)
+    dens = W.two_bumps(W.TIME_FROZEN, t_freeze=0.0375)
+    data = W.Data(init_kind=W.DATA_GRID, bdry_kind=W.DATA_IDENTITY, score_mode=W.SCORE_PROJECT,
+                  t_init=0.0375, grid_xi=gx.ravel(), grid_eta=gy.ravel())
+    pts = W.interface_nodes(4, 4, 48)[::7]
+    grids = (torch.tensor(gx.ravel(), device="cuda"), torch.tensor(gy.ravel(), device="cuda"))
+    g = run_gpu(fk, torch_cuda, dens, data, pts, 5e-4, 2.5e-5, 4000, seed=11, grids=grids)
+    o = run_oracle(oracle_mod, dens, data, pts, 5e-4, 2.5e-5, 4000, seed=11)
+    assert_parity(g, o)
+
+
+def test_moving_bump_project_and_level_id(fk, torch_cuda, oracle_mod):
+    wl = W.MOVING_BUMP_1521
+    pts = W.uniform_points(16, seed=6)
+    data = W.Data(score_mode=W.SCORE_PROJECT)
+    g = run_gpu(fk, torch_cuda, wl.density, data, pts, 0.02, 5e-5, 2000, seed=13, level_id=37)
+    o = run_oracle(oracle_mod, wl.density, data, pts, 0.02, 5e-5, 2000, seed=13, level_id=37)
+    assert_parity(g, o)
+
+
+def test_edge_cases(fk, torch_cuda, oracle_mod):
+    dens = W.static_bump()
+    # no nodes: a valid no-op
+    r = fk.fk_interface_solve(dens, W.Data(), np.zeros((0, 2)), 0.05, 1e-4, 16)
+    torch_cuda.cuda.synchronize()
+    assert r["xi"].numel() == 0
+    # t = 0: K = 0, every path scores the initial data at its start point
+    pts = np.array([[0.5, 0.25], [0.1, 0.9]])
+    g = run_gpu(fk, torch_cuda, dens, W.Data(), pts, 0.0, 1e-4, 64)
+    assert np.allclose(g["xi"], pts[:, 0], rtol=0, atol=1e-14)
+    assert np.allclose(g["eta"], pts[:, 1], rtol=0, atol=1e-14)
+    assert np.all(g["se_xi"] <= 1e-15) and np.all(g["exit_step"] == -1)
+    # odd K with a short last step; nodes on the boundary; n_paths = 2
+    pts = np.array([[0.0, 0.5], [1.0, 0.3], [0.5, 0.0], [0.37, 1.0], [0.5, 0.5]])
+    for n_paths in (2, 333):
+        g = run_gpu(fk, torch_cuda, dens, W.Data(), pts, 1.05e-3, 1e-4, n_paths, seed=17)
+        o = run_oracle(oracle_mod, dens, W.Data(), pts, 1.05e-3, 1e-4, n_paths, seed=17)
+        assert_parity(g, o)
+
+
+def test_schedule_invariance(fk, torch_cuda):
+    """Results depend only on the counters, not on the launch plan: per-path
+    records and the fixed-order FP64 reduction are bitwise identical."""
+    wl = W.STATIC_BUMP_31
+    pts = wl.nodes()
+    a = run_gpu(fk, torch_cuda, wl.density, wl.data, pts, wl.t, wl.dt, 3000)
+    b = run_gpu(fk, torch_cuda, wl.density, wl.data, pts, wl.t, wl.dt, 3000,
+                plan={"block": 64, "chunk": 7, "blocks_per_cu": 3})
+    c = run_gpu(fk, torch_cuda, wl.density, wl.data, pts, wl.t, wl.dt, 3000)
+    for k in ("xi", "eta", "se_xi", "se_eta", "exit_step", "scores", "steps"):
+        assert np.array_equal(a[k], b[k]), k
+        assert np.array_equal(a[k], c[k]), k
+
+
+def test_full_size_moving_bump_sampled(fk, torch_cuda, oracle_mod):
+    """Full moving-bump workload (1521 nodes x 10^5 paths) in the benchmark's
+    launch configuration; sampled paths recomputed one by one by the oracle,
+    and four whole nodes recomputed in full."""
+    wl = W.MOVING_BUMP_1521
+    pts = wl.nodes()
+    g = run_gpu(fk, torch_cuda, wl.density, wl.data, pts, wl.t, wl.dt, wl.n_paths)
+    rng = np.random.default_rng(123)
+    m = 256
+    ni = rng.integers(0, len(pts), m)
+    pi = rng.integers(0, wl.n_paths, m)
+    sc, ex = oracle_mod.fk_paths(wl.density, wl.data, pts[ni], ni, pi, wl.t, wl.dt, wl.seed, threads=THREADS)
+    ex_g = g["exit_step"][ni, pi]
+    sc_g = g["scores"][ni, pi].astype(np.float64) + pts[ni].astype(np.float32).astype(np.float64)
+    same = ex_g == ex
+    print(f"sampled path exit match {same.mean():.4f}", flush=True)
+    assert same.mean() >= 0.99
+    assert np.all(np.abs(sc_g[same] - sc[same]) < 2e-5)
+    # invariants over every node
+    m_ = np.stack([g["xi"], g["eta"]], 1)
+    s_ = np.stack([g["se_xi"], g["se_eta"]], 1)
+    assert np.all(m_ >= -3 * s_) and np.all(m_ <= 1 + 3 * s_)
+    assert int(g["total_steps"][0]) == int(g["steps"].sum())
+    # four whole nodes, spread over the canonical order
+    sel = np.array([0, 400, 800, 1500])
+    o = oracle_mod.fk_solve(wl.density, wl.data, pts[sel], wl.t, wl.dt, wl.n_paths, wl.seed,
+                            node_ids=sel, want_exit=True, threads=THREADS)
+    sub = {k: (g[k][sel] if k != "total_steps" else g[k]) for k in g}
+    sub["total_steps"] = np.array([sub["steps"].sum()])
+    assert_parity(sub, o)
