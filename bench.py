@@ -42,6 +42,23 @@ FP32_PEAK_TFLOPS = 157.3
 #   Euler-Maruyama update 4 (2 fma)
 FLOP_PER_STEP = 36
 
+# HBM traffic of the path kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
+# (scaled by a plain 1 GiB copy: fetch x2.0, write x1.0), per path, valid only
+# for the kernel sources it was measured on (hash below); otherwise null.
+TRAFFIC_BYTES_PER_PATH = (0.4625 * 2**20 + 1071540.40625 * 1024) / (1521 * 73858)
+TRAFFIC_SOURCE_HASH = "2253d4a70496d3d2"
+KERNEL_SOURCES = ["paper_1402_0266_amd/csrc/fk_paths.hip", "paper_1402_0266_amd/csrc/fk_device.hpp",
+                  "paper_1402_0266_amd/csrc/fk_internal.hpp"]
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
 
 def load_fd_reference(name: str):
     path = os.path.join(ROOT, "tests", "golden", f"{name}_fd.txt")
@@ -57,7 +74,8 @@ def rms_against(fd, xi, eta):
 
 
 def cpu_baseline(wl, n_star, sample_nodes=96, sample_paths=2048):
-    """The CPU oracle on a bounded sample: every 16th node, sample_paths paths,
+    """The CPU oracle on a bounded sample: sample_nodes nodes spread evenly over the
+    canonical order, sample_paths paths each,
     scaled to nodes/s at N* paths per node."""
     import oracle
     oracle.build()
@@ -80,7 +98,9 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--paths", type=int, default=0, help="fix paths/node (skip the N* pilot)")
+    ap.add_argument("--paths", type=int, default=0, help="fix paths/node and skip the N* pilot (profiling)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (scales HBM counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1"}))
@@ -88,6 +108,15 @@ def main():
 
     import torch
     import paper_1402_0266_amd as fk
+
+    if args.copy_calibration:
+        n = args.copy_calibration << 20
+        src = torch.ones(n, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes": n}))
+        return
 
     wl = W.MOVING_BUMP_1521
     pts = wl.nodes()
@@ -100,24 +129,25 @@ def main():
         return fk.fk_interface_solve(wl.density, wl.data, pts, wl.t, wl.dt, n_paths, wl.seed, workspace=ws)
 
     # ---- pilot at the configured paths/node: variance, bias, N* ----------------
-    print(f"[bench] pilot: {n_nodes} nodes x {wl.n_paths} paths", file=sys.stderr, flush=True)
-    r = solve(wl.n_paths)
-    torch.cuda.synchronize()
-    xi, eta = r["xi"].cpu().numpy(), r["eta"].cpu().numpy()
-    se = np.stack([r["se_xi"].cpu().numpy(), r["se_eta"].cpu().numpy()], 1)
-    var_mean = float(np.mean(se ** 2) * wl.n_paths)
-    pilot = {"paths": wl.n_paths, "mean_score_var": var_mean}
     n_star = args.paths or wl.n_paths
-    if fd is not None:
+    pilot = {"paths": wl.n_paths, "skipped": bool(args.paths)}
+    if not args.paths:
+        print(f"[bench] pilot: {n_nodes} nodes x {wl.n_paths} paths", file=sys.stderr, flush=True)
+        r = solve(wl.n_paths)
+        torch.cuda.synchronize()
+        xi, eta = r["xi"].cpu().numpy(), r["eta"].cpu().numpy()
+        se = np.stack([r["se_xi"].cpu().numpy(), r["se_eta"].cpu().numpy()], 1)
+        var_mean = float(np.mean(se ** 2) * wl.n_paths)
+        pilot["mean_score_var"] = var_mean
+    if fd is not None and not args.paths:
         rms0 = rms_against(fd, xi, eta)
         b2 = max(0.0, rms0 ** 2 - var_mean / wl.n_paths)
         pilot.update({"rms": rms0, "bias": math.sqrt(b2), "fd_err_est": float(fd[:, 4:6].max())})
-        if not args.paths:
-            if b2 >= 1e-6:
-                n_star = wl.n_paths
-                pilot["note"] = "bias floor reached: rate quoted at the configured paths"
-            else:
-                n_star = int(math.ceil(var_mean / (1e-6 - b2)))
+        if b2 >= 1e-6:
+            n_star = wl.n_paths
+            pilot["note"] = "bias floor reached: rate quoted at the configured paths"
+        else:
+            n_star = int(math.ceil(var_mean / (1e-6 - b2)))
     n_star = max(2, n_star)
     if n_star > wl.n_paths:
         ws = torch.empty(fk.fk_interface_workspace_bytes(n_nodes, n_star), dtype=torch.uint8, device=dev)
@@ -172,7 +202,9 @@ def main():
         },
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
-            "frac": achieved / FP32_PEAK_TFLOPS, "traffic": None,
+            "frac": achieved / FP32_PEAK_TFLOPS,
+            "traffic": (TRAFFIC_BYTES_PER_PATH * n_nodes * n_star
+                        if kernel_source_hash() == TRAFFIC_SOURCE_HASH else None),
             "flop_per_path_step": FLOP_PER_STEP,
         },
     }

@@ -146,6 +146,20 @@ int fk_interface_solve(const fk_density *w, const fk_data *d,
 int fk_timing_enable(int enable);
 int fk_timing_last(double *path_kernel_ms, double *reduce_kernel_ms);
 
+/*
+ * The path kernels' generator on its own, for bitwise checks.
+ * fk_philox_words: Philox4x32-10 (Salmon et al., SC'11) of n counters
+ *   ctr (device, [n][4] uint32) under the key (seed low word, seed high
+ *   word); out (device, [n][4] uint32).
+ * fk_normals: for word pairs (ra[i], rb[i]) (device uint32 [n]) the FP32
+ *   Brownian increments sqrt(2 D) (z0, z1) of the Box-Muller transform of
+ *   u1 = ((ra >> 8) + 1) 2^-24 and u2 = (rb >> 8) 2^-24 (Sect. 4: increments
+ *   are sqrt(step) times standard normals; sqrt(2) from the diffusion);
+ *   out (device, [n][2] FP32).
+ */
+int fk_philox_words(const uint32_t *ctr, int64_t n, uint64_t seed, uint32_t *out, hipStream_t stream);
+int fk_normals(const uint32_t *ra, const uint32_t *rb, int64_t n, double D, float *out, hipStream_t stream);
+
 /* Wait for the stream; report queued device errors as FK_E_DEVICE. */
 int fk_sync(hipStream_t stream);
 

@@ -74,6 +74,10 @@ _lib.fk_interface_solve.argtypes = [
     _P, _P, _P, _P, _P, _P, _P, _P,
     ctypes.POINTER(fk_plan), _P, ctypes.c_size_t, _P]
 _lib.fk_interface_solve.restype = ctypes.c_int
+_lib.fk_philox_words.argtypes = [_P, ctypes.c_int64, ctypes.c_uint64, _P, _P]
+_lib.fk_philox_words.restype = ctypes.c_int
+_lib.fk_normals.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_double, _P, _P]
+_lib.fk_normals.restype = ctypes.c_int
 _lib.fk_timing_enable.argtypes = [ctypes.c_int]
 _lib.fk_timing_enable.restype = ctypes.c_int
 _lib.fk_timing_last.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -127,6 +131,24 @@ def _stream(torch, device):
 
 def fk_interface_workspace_bytes(n_nodes: int, n_paths: int) -> int:
     return int(_lib.fk_interface_workspace_bytes(n_nodes, n_paths))
+
+
+def fk_philox_words(ctr, seed: int):
+    """Philox4x32-10 words of device counters ctr (int32/uint32 tensor [n, 4])."""
+    import torch
+    out = torch.empty_like(ctr)
+    _check(_lib.fk_philox_words(ctr.data_ptr(), ctr.shape[0], int(seed), out.data_ptr(),
+                                _stream(torch, ctr.device)))
+    return out
+
+
+def fk_normals(ra, rb, D: float):
+    """FP32 Brownian increments sqrt(2 D) (z0, z1) of word pairs (device tensors [n])."""
+    import torch
+    out = torch.empty((ra.shape[0], 2), dtype=torch.float32, device=ra.device)
+    _check(_lib.fk_normals(ra.data_ptr(), rb.data_ptr(), ra.shape[0], float(D), out.data_ptr(),
+                           _stream(torch, ra.device)))
+    return out
 
 
 def fk_timing_enable(enable: bool = True):

@@ -121,6 +121,11 @@ LevelDev make_level(const fk_density *w, const fk_data *d, double t, double dt, 
     L.orbit_r = (float)w->orbit_r;
     L.omega_rev = (float)(w->omega / (2.0 * 3.14159265358979323846));
     L.t_freeze = (float)w->t_freeze;
+    const double orev = w->omega / (2.0 * 3.14159265358979323846);
+    L.rev0 = (float)((d->t_init + t) * orev);
+    L.drev = (float)(dt * orev);
+    L.cos_d = (float)std::cos(dt * w->omega);
+    L.sin_d = (float)std::sin(dt * w->omega);
     return L;
 }
 
@@ -313,12 +318,14 @@ int fk_interface_solve(const fk_density *w, const fk_data *d, const double *pts,
     a.cpn = (uint32_t)cpn;
     a.total_chunks = (uint32_t)(n_nodes * cpn);
 
+    // Every step has length dt when the FP32 constants of the last step match.
+    const bool uniform = (lev.dt_last == lev.dt && lev.cbm_last == lev.cbm);
     int bpc = pl.blocks_per_cu;
-    const int occ = path_kernel_max_blocks_per_cu(w->kind, w->time_mode, pl.block);
+    const int occ = path_kernel_max_blocks_per_cu(w->kind, w->time_mode, uniform, pl.block);
     if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
     const int grid = n_cu * bpc;
     if ((e = timing_mark(0, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    if ((e = launch_paths(w->kind, w->time_mode, a, grid, pl.block, stream)) != hipSuccess)
+    if ((e = launch_paths(w->kind, w->time_mode, uniform, a, grid, pl.block, stream)) != hipSuccess)
         return hip_fail(e, "path kernel launch");
     if ((e = timing_mark(1, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
 

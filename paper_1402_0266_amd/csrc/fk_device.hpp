@@ -18,14 +18,22 @@ struct PhiloxOut {
     uint32_t r0, r1, r2, r3;
 };
 
+// a ^ b ^ k in one VALU instruction (gfx950 three-input bit operation with
+// truth table 0x96 = XOR of the three inputs); k is wave-uniform (a key word).
+__device__ __forceinline__ uint32_t xor3_uniform(uint32_t a, uint32_t b, uint32_t k) {
+    uint32_t r;
+    asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(k));
+    return r;
+}
+
 __device__ __forceinline__ PhiloxOut philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                    uint32_t k0, uint32_t k1) {
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
         const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+        const uint32_t n0 = xor3_uniform((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3_uniform((uint32_t)(p0 >> 32), c3, k1);
         c1 = (uint32_t)p1;
         c3 = (uint32_t)p0;
         c0 = n0;
@@ -51,7 +59,7 @@ __device__ __forceinline__ float hw_cos_rev(float x) { return __builtin_amdgcn_c
 // cbm = -4 ln2 D folds sqrt(2 D) and the change of logarithm base.
 __device__ __forceinline__ void brownian_increment(uint32_t ra, uint32_t rb, float cbm,
                                                    float &dwx, float &dwy) {
-    const float u1 = (float)((ra >> 8) + 1u) * 0x1p-24f;
+    const float u1 = fmaf((float)(ra >> 8), 0x1p-24f, 0x1p-24f);  // exact: ((ra >> 8) + 1) 2^-24
     const float u2 = (float)(rb >> 8) * 0x1p-24f;
     const float rad = hw_sqrt(cbm * hw_log2(u1));
     dwx = rad * hw_cos_rev(u2);

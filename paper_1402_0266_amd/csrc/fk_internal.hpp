@@ -27,6 +27,9 @@ struct alignas(16) LevelDev {
     float orbit_r;     // orbit radius
     float omega_rev;   // omega / (2 pi): angular speed in revolutions per unit time
     float t_freeze;    // frozen density time
+    float rev0;        // (t_init + t) omega_rev: orbit angle at path start, in revolutions
+    float drev;        // dt omega_rev: orbit angle step
+    float cos_d, sin_d;  // cos / sin of the orbit angle step (2 pi drev)
 };
 
 // One interface node, in launch (cost-sorted) order.
@@ -76,8 +79,9 @@ struct ReduceArgs {
 
 // Launch helpers implemented in fk_paths.hip.
 hipError_t launch_zero_u32(uint32_t *p, int n_words, hipStream_t s);
-hipError_t launch_paths(int kind, int time_mode, const PathArgs &a, int grid, int block, hipStream_t s);
+hipError_t launch_paths(int kind, int time_mode, bool uniform, const PathArgs &a, int grid, int block,
+                        hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t s);
-int path_kernel_max_blocks_per_cu(int kind, int time_mode, int block);
+int path_kernel_max_blocks_per_cu(int kind, int time_mode, bool uniform, int block);
 
 }  // namespace fk

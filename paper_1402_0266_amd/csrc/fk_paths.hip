@@ -29,6 +29,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <utility>
+
 #include "fk_device.hpp"
 #include "fk_internal.hpp"
 
@@ -55,8 +57,9 @@ struct Lane {
     uint32_t path, nid, ctr3;
     uint64_t rec;          // record index
     float px, py;          // start point (score shift for identity data)
-    float tend, horizon, dt, dt_last, cbm, cbm_last;
+    float horizon, dt, dt_last, cbm, cbm_last;
     float ox, oy;          // frozen / static centre offset
+    float rev0, drev, cos_d, sin_d;  // orbit angle at path start, step, rotation
     DensityRegs dens;
 };
 
@@ -69,18 +72,19 @@ __device__ __forceinline__ void comp_add(float &hi, float &lo, float inc) {
     hi = s;
 }
 
-template <int KIND, int TMODE>
-__device__ __forceinline__ bool em_step(Lane &L, uint32_t ra, uint32_t rb) {
-    const bool last = (L.k == L.K - 1);
-    const float D = last ? L.dt_last : L.dt;
-    const float cb = last ? L.cbm_last : L.cbm;
+// One Euler-Maruyama step with centre offset (ox, oy); returns true if the
+// new point is outside the closed unit square.  UNIFORM: every step has
+// length dt (t/dt integral), so the last-step selection is compiled out.
+template <int KIND, bool UNIFORM>
+__device__ __forceinline__ bool em_step(Lane &L, uint32_t ra, uint32_t rb, float ox, float oy) {
+    float D = L.dt, cb = L.cbm;
+    if constexpr (!UNIFORM) {
+        const bool last = (L.k == L.K - 1);
+        D = last ? L.dt_last : D;
+        cb = last ? L.cbm_last : cb;
+    }
     float dwx, dwy;
     brownian_increment(ra, rb, cb, dwx, dwy);
-    float ox = L.ox, oy = L.oy;
-    if constexpr ((KIND == KIND_MOVING || KIND == KIND_TWO) && TMODE == TIME_BACKWARD) {
-        // PDE time t_init + t - s_k, s_k = k dt (the step about to be taken).
-        orbit(L.dens, fmaf(-(float)L.k, L.dt, L.tend), ox, oy);
-    }
     float bx, by;
     drift<KIND>(L.dens, ox, oy, L.xh, L.yh, bx, by);
     comp_add(L.xh, L.xl, fmaf(bx, D, dwx));
@@ -88,7 +92,9 @@ __device__ __forceinline__ bool em_step(Lane &L, uint32_t ra, uint32_t rb) {
     L.k += 1;
     // Outside the closed square.  hi is the rounded position; (hi - 1) is
     // exact near 1, so the tests against 1 see the lo part too.
-    return (L.xh < 0.f) | (((L.xh - 1.f) + L.xl) > 0.f) | (L.yh < 0.f) | (((L.yh - 1.f) + L.yl) > 0.f);
+    const float lo = fminf(L.xh, L.yh);
+    const float hi = fmaxf((L.xh - 1.f) + L.xl, (L.yh - 1.f) + L.yl);
+    return (lo < 0.f) | (hi > 0.f);
 }
 
 __device__ __forceinline__ float grid_bilinear(const double *g, int n, float x, float y) {
@@ -106,13 +112,13 @@ __device__ __forceinline__ float grid_bilinear(const double *g, int n, float x, 
 
 }  // namespace
 
-template <int KIND, int TMODE>
+template <int KIND, int TMODE, bool UNIFORM>
 __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
+    constexpr bool kMovingBackward = (KIND == KIND_MOVING || KIND == KIND_TWO) && TMODE == TIME_BACKWARD;
     const uint32_t lane = threadIdx.x & 63u;
     // Wavefront-uniform queue cursor: current node slot and path range.
     uint32_t q_slot = 0, q_next = 0, q_end = 0;
     bool q_done = false;
-    // Philox key schedule is uniform.
     const uint32_t key0 = a.key0, key1 = a.key1;
 
     Lane L;
@@ -154,12 +160,15 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
                 L.nid = nd.nid;
                 L.ctr3 = lv.ctr3;
                 L.rec = nd.out * (uint64_t)a.n_paths + L.path;
-                L.tend = lv.tend;
                 L.horizon = lv.horizon;
                 L.dt = lv.dt;
                 L.dt_last = lv.dt_last;
                 L.cbm = lv.cbm;
                 L.cbm_last = lv.cbm_last;
+                L.rev0 = lv.rev0;
+                L.drev = lv.drev;
+                L.cos_d = lv.cos_d;
+                L.sin_d = lv.sin_d;
                 L.dens.amp = lv.amp;
                 L.dens.nscale = lv.nscale;
                 L.dens.a2s = lv.a2s;
@@ -185,10 +194,27 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
             bool out = false;
             if (L.k < L.K) {
                 const PhiloxOut r = philox4x32_10((uint32_t)L.k >> 1, L.path, L.nid, L.ctr3, key0, key1);
-                out = em_step<KIND, TMODE>(L, r.r0, r.r1);
+                float ox = L.ox, oy = L.oy, cr = 0.f, sr = 0.f;
+                if constexpr (kMovingBackward) {
+                    // Orbit angle at PDE time t_init + t - k dt, in revolutions.
+                    const float rev = fmaf(-(float)L.k, L.drev, L.rev0);
+                    cr = hw_cos_rev(rev);
+                    sr = hw_sin_rev(rev);
+                    ox = L.dens.orbit_r * cr;
+                    oy = L.dens.orbit_r * sr;
+                }
+                out = em_step<KIND, UNIFORM>(L, r.r0, r.r1, ox, oy);
                 my_steps += 1;
                 if (!out && L.k < L.K) {
-                    out = em_step<KIND, TMODE>(L, r.r2, r.r3);
+                    if constexpr (kMovingBackward) {
+                        // One step later the angle is smaller by omega dt:
+                        // rotate (cos, sin) instead of re-evaluating them.
+                        const float c2 = fmaf(cr, L.cos_d, sr * L.sin_d);
+                        const float s2 = fmaf(sr, L.cos_d, -cr * L.sin_d);
+                        ox = L.dens.orbit_r * c2;
+                        oy = L.dens.orbit_r * s2;
+                    }
+                    out = em_step<KIND, UNIFORM>(L, r.r2, r.r3, ox, oy);
                     my_steps += 1;
                 }
             }
@@ -239,47 +265,65 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
 }
 
 namespace {
-template <int KIND, int TMODE>
+template <int KIND, int TMODE, bool UNIFORM>
 hipError_t launch_one(const PathArgs &a, int grid, int block, hipStream_t s) {
-    hipLaunchKernelGGL((fk_path_kernel<KIND, TMODE>), dim3(grid), dim3(block), 0, s, a);
+    hipLaunchKernelGGL((fk_path_kernel<KIND, TMODE, UNIFORM>), dim3(grid), dim3(block), 0, s, a);
     return hipGetLastError();
 }
 
-template <int KIND, int TMODE>
+template <int KIND, int TMODE, bool UNIFORM>
 int max_blocks(int block) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk_path_kernel<KIND, TMODE>, block, 0) != hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk_path_kernel<KIND, TMODE, UNIFORM>, block, 0) !=
+        hipSuccess)
         return 0;
     return nb;
 }
-}  // namespace
 
-hipError_t launch_paths(int kind, int time_mode, const PathArgs &a, int grid, int block, hipStream_t s) {
+// Calls F<KIND, TMODE, UNIFORM>::run(args...) for the runtime triple.
+template <template <int, int, bool> class F, typename... Args>
+auto dispatch(int kind, int time_mode, bool uniform, Args &&...args) {
     const bool frozen = (time_mode == TIME_FROZEN);
+#define FK_CASE(K, T)                                                          \
+    return uniform ? F<K, T, true>::run(std::forward<Args>(args)...)          \
+                   : F<K, T, false>::run(std::forward<Args>(args)...)
     switch (kind) {
-    case KIND_CONST: return launch_one<KIND_CONST, TIME_BACKWARD>(a, grid, block, s);
-    case KIND_BUMP: return launch_one<KIND_BUMP, TIME_BACKWARD>(a, grid, block, s);
-    case KIND_RIDGE: return launch_one<KIND_RIDGE, TIME_BACKWARD>(a, grid, block, s);
+    case KIND_CONST: FK_CASE(KIND_CONST, TIME_BACKWARD);
+    case KIND_BUMP: FK_CASE(KIND_BUMP, TIME_BACKWARD);
+    case KIND_RIDGE: FK_CASE(KIND_RIDGE, TIME_BACKWARD);
     case KIND_MOVING:
-        return frozen ? launch_one<KIND_MOVING, TIME_FROZEN>(a, grid, block, s)
-                      : launch_one<KIND_MOVING, TIME_BACKWARD>(a, grid, block, s);
-    case KIND_TWO:
-        return frozen ? launch_one<KIND_TWO, TIME_FROZEN>(a, grid, block, s)
-                      : launch_one<KIND_TWO, TIME_BACKWARD>(a, grid, block, s);
-    default: return hipErrorInvalidValue;
+        if (frozen) FK_CASE(KIND_MOVING, TIME_FROZEN);
+        FK_CASE(KIND_MOVING, TIME_BACKWARD);
+    default:
+        if (frozen) FK_CASE(KIND_TWO, TIME_FROZEN);
+        FK_CASE(KIND_TWO, TIME_BACKWARD);
     }
+#undef FK_CASE
 }
 
-int path_kernel_max_blocks_per_cu(int kind, int time_mode, int block) {
-    const bool frozen = (time_mode == TIME_FROZEN);
-    switch (kind) {
-    case KIND_CONST: return max_blocks<KIND_CONST, TIME_BACKWARD>(block);
-    case KIND_BUMP: return max_blocks<KIND_BUMP, TIME_BACKWARD>(block);
-    case KIND_RIDGE: return max_blocks<KIND_RIDGE, TIME_BACKWARD>(block);
-    case KIND_MOVING: return frozen ? max_blocks<KIND_MOVING, TIME_FROZEN>(block) : max_blocks<KIND_MOVING, TIME_BACKWARD>(block);
-    case KIND_TWO: return frozen ? max_blocks<KIND_TWO, TIME_FROZEN>(block) : max_blocks<KIND_TWO, TIME_BACKWARD>(block);
-    default: return 0;
+template <int K, int T, bool U>
+struct LaunchF {
+    static hipError_t run(const PathArgs &a, int grid, int block, hipStream_t s) {
+        return launch_one<K, T, U>(a, grid, block, s);
     }
+};
+template <int K, int T, bool U>
+struct OccF {
+    static int run(int block) { return max_blocks<K, T, U>(block); }
+};
+}  // namespace
+
+hipError_t launch_paths(int kind, int time_mode, bool uniform, const PathArgs &a, int grid, int block,
+                        hipStream_t s) {
+    if (kind != KIND_CONST && kind != KIND_BUMP && kind != KIND_RIDGE && kind != KIND_MOVING && kind != KIND_TWO)
+        return hipErrorInvalidValue;
+    return dispatch<LaunchF>(kind, time_mode, uniform, a, grid, block, s);
+}
+
+int path_kernel_max_blocks_per_cu(int kind, int time_mode, bool uniform, int block) {
+    if (kind != KIND_CONST && kind != KIND_BUMP && kind != KIND_RIDGE && kind != KIND_MOVING && kind != KIND_TWO)
+        return 0;
+    return dispatch<OccF>(kind, time_mode, uniform, block);
 }
 
 // ---------------------------------------------------------------------------
