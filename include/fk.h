@@ -137,6 +137,58 @@ int fk_interface_solve(const fk_density *w, const fk_data *d,
                        hipStream_t stream);
 
 /*
+ * Batched interface solves: several time levels, each with its own density
+ * parameters, horizon and node slice (e.g. a different sub-domain layout),
+ * run as one persistent launch over one work queue.  Every level has the
+ * semantics of one fk_interface_solve call on its nodes with the same seed,
+ * dt, n_paths and data, and its own level_id, so the per-node results are
+ * bitwise those of the single calls.  All levels must share the density kind
+ * and time mode (FK_E_UNSUPPORTED otherwise).
+ */
+typedef struct fk_level {
+    fk_density w;         /* density of the level */
+    double t;             /* horizon of the level */
+    double t_init;        /* PDE time of the level's initial data */
+    int64_t node_offset;  /* first node of the level in pts and in the outputs */
+    int64_t n_nodes;      /* nodes of the level; the slices must tile [0, n_total) */
+    uint32_t level_id;    /* Philox counter tag, < 2^28 */
+    uint32_t reserved;
+} fk_level;
+
+typedef struct fk_batch *fk_batch_t;
+
+/* Builds the device tables (cost-ordered nodes, level constants) once;
+ * pts is host [n_total][2]; the data's grid pointers must outlive the batch.
+ * Allocates device memory for the tables (freed by fk_batch_destroy). */
+int fk_batch_create(const fk_level *levels, int32_t n_levels, const double *pts, int64_t n_total,
+                    const fk_data *d, double dt, int64_t n_paths, uint64_t seed, fk_batch_t *out);
+/* Device workspace of fk_batch_run when no scores buffer is given (0 for NULL). */
+size_t fk_batch_workspace_bytes(fk_batch_t b);
+int fk_batch_set_plan(fk_batch_t b, const fk_plan *plan);
+int fk_batch_get_plan(fk_batch_t b, fk_plan *plan);
+/* Times the launch with probe_paths paths per node for each candidate shape
+ * (block 64/128/256 x chunk 32/128/512 x full/half occupancy), keeps the
+ * fastest as the batch's plan and returns it in *chosen (may be NULL).
+ * Results are cached per process by device and problem shape.  Synchronous;
+ * allocates and frees a small probe output buffer.  Every candidate computes
+ * the same result: the plan only changes the schedule. */
+int fk_batch_autotune(fk_batch_t b, int64_t probe_paths, void *workspace, size_t workspace_bytes,
+                      hipStream_t stream, fk_plan *chosen);
+/* Outputs as in fk_interface_solve, over n_total nodes in node-list order. */
+int fk_batch_run(fk_batch_t b, double *xi, double *eta, double *se_xi, double *se_eta, int32_t *exit_step,
+                 float *scores, uint64_t *total_steps, void *workspace, size_t workspace_bytes,
+                 hipStream_t stream);
+/* Captures fk_batch_run with these buffers into a HIP graph (stream must not
+ * be the default stream; nothing runs during capture); fk_batch_replay
+ * launches it.  The captured sequence clears its counters with a kernel, so
+ * replays are independent. */
+int fk_batch_capture(fk_batch_t b, double *xi, double *eta, double *se_xi, double *se_eta, int32_t *exit_step,
+                     float *scores, uint64_t *total_steps, void *workspace, size_t workspace_bytes,
+                     hipStream_t stream);
+int fk_batch_replay(fk_batch_t b, hipStream_t stream);
+void fk_batch_destroy(fk_batch_t b);
+
+/*
  * Kernel timing.  While enabled (per calling thread), fk_interface_solve
  * records HIP events on its stream around the path kernel and around the
  * reduction kernel; fk_timing_last waits for the last recorded events and

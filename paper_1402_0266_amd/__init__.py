@@ -61,6 +61,12 @@ class fk_plan(ctypes.Structure):
                 ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
+class fk_level(ctypes.Structure):
+    _fields_ = [("w", fk_density), ("t", ctypes.c_double), ("t_init", ctypes.c_double),
+                ("node_offset", ctypes.c_int64), ("n_nodes", ctypes.c_int64),
+                ("level_id", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
 _P = ctypes.c_void_p
 _lib.fk_version.restype = ctypes.c_int
 _lib.fk_last_error.restype = ctypes.c_char_p
@@ -78,6 +84,26 @@ _lib.fk_philox_words.argtypes = [_P, ctypes.c_int64, ctypes.c_uint64, _P, _P]
 _lib.fk_philox_words.restype = ctypes.c_int
 _lib.fk_normals.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_double, _P, _P]
 _lib.fk_normals.restype = ctypes.c_int
+_lib.fk_batch_create.argtypes = [ctypes.POINTER(fk_level), ctypes.c_int32, _P, ctypes.c_int64,
+                                 ctypes.POINTER(fk_data), ctypes.c_double, ctypes.c_int64, ctypes.c_uint64,
+                                 ctypes.POINTER(_P)]
+_lib.fk_batch_create.restype = ctypes.c_int
+_lib.fk_batch_workspace_bytes.argtypes = [_P]
+_lib.fk_batch_workspace_bytes.restype = ctypes.c_size_t
+_lib.fk_batch_set_plan.argtypes = [_P, ctypes.POINTER(fk_plan)]
+_lib.fk_batch_set_plan.restype = ctypes.c_int
+_lib.fk_batch_get_plan.argtypes = [_P, ctypes.POINTER(fk_plan)]
+_lib.fk_batch_get_plan.restype = ctypes.c_int
+_lib.fk_batch_autotune.argtypes = [_P, ctypes.c_int64, _P, ctypes.c_size_t, _P, ctypes.POINTER(fk_plan)]
+_lib.fk_batch_autotune.restype = ctypes.c_int
+_lib.fk_batch_run.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
+_lib.fk_batch_run.restype = ctypes.c_int
+_lib.fk_batch_capture.argtypes = [_P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
+_lib.fk_batch_capture.restype = ctypes.c_int
+_lib.fk_batch_replay.argtypes = [_P, _P]
+_lib.fk_batch_replay.restype = ctypes.c_int
+_lib.fk_batch_destroy.argtypes = [_P]
+_lib.fk_batch_destroy.restype = None
 _lib.fk_timing_enable.argtypes = [ctypes.c_int]
 _lib.fk_timing_enable.restype = ctypes.c_int
 _lib.fk_timing_last.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -198,9 +224,7 @@ def fk_interface_solve(density, data, pts, t, dt, n_paths, seed=0, level_id=0, *
     need = _lib.fk_interface_workspace_bytes(n, n_paths)
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
-    pl = None
-    if plan is not None:
-        pl = fk_plan(int(plan.get("block", 0)), int(plan.get("blocks_per_cu", 0)), int(plan.get("chunk", 0)), 0)
+    pl = _plan_struct(plan)
 
     def ptr(k):
         v = out.get(k)
@@ -215,3 +239,101 @@ def fk_interface_solve(density, data, pts, t, dt, n_paths, seed=0, level_id=0, *
     _check(rc)
     out["_workspace"] = workspace
     return out
+
+
+def _plan_struct(plan):
+    if plan is None:
+        return None
+    return fk_plan(int(plan.get("block", 0)), int(plan.get("blocks_per_cu", 0)), int(plan.get("chunk", 0)), 0)
+
+
+def _plan_dict(p: fk_plan) -> dict:
+    return {"block": p.block, "blocks_per_cu": p.blocks_per_cu, "chunk": p.chunk}
+
+
+class FkBatch:
+    """Batched interface solve (C: ``fk_batch_*``).
+
+    ``levels`` is a list of (density, t, t_init, pts[n_l, 2], level_id); the
+    node slices are concatenated in that order.  Outputs are device tensors
+    over all nodes.
+    """
+
+    def __init__(self, levels, data, dt, n_paths, seed=0, device="cuda"):
+        import torch
+        self.device = torch.device(device)
+        pts, arr, off = [], (fk_level * len(levels))(), 0
+        for i, (dens, t, t_init, p, level_id) in enumerate(levels):
+            p = np.ascontiguousarray(p, dtype=np.float64).reshape(-1, 2)
+            arr[i] = fk_level(_density(dens), float(t), float(t_init), off, p.shape[0], int(level_id), 0)
+            pts.append(p)
+            off += p.shape[0]
+        self.pts = np.ascontiguousarray(np.concatenate(pts) if pts else np.zeros((0, 2)))
+        self.n_total = off
+        self.n_paths = int(n_paths)
+        self.offsets = np.cumsum([0] + [len(p) for p in pts])
+        self._data = _data(data)
+        h = ctypes.c_void_p()
+        _check(_lib.fk_batch_create(arr, len(levels), self.pts.ctypes.data_as(ctypes.c_void_p), self.n_total,
+                                    ctypes.byref(self._data), float(dt), self.n_paths, int(seed), ctypes.byref(h)))
+        self._h = h
+        self.workspace = torch.empty(max(int(_lib.fk_batch_workspace_bytes(h)), 256), dtype=torch.uint8,
+                                     device=self.device)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.fk_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def plan(self) -> dict:
+        p = fk_plan()
+        _check(_lib.fk_batch_get_plan(self._h, ctypes.byref(p)))
+        return _plan_dict(p)
+
+    @plan.setter
+    def plan(self, plan: dict):
+        _check(_lib.fk_batch_set_plan(self._h, _plan_struct(plan)))
+
+    def autotune(self, probe_paths: int) -> dict:
+        import torch
+        p = fk_plan()
+        _check(_lib.fk_batch_autotune(self._h, int(probe_paths), self.workspace.data_ptr(), self.workspace.numel(),
+                                      _stream(torch, self.device), ctypes.byref(p)))
+        return _plan_dict(p)
+
+    def outputs(self, exit_step=False, scores=False):
+        import torch
+        n, dev = self.n_total, self.device
+        out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("xi", "eta", "se_xi", "se_eta")}
+        out["total_steps"] = torch.zeros(1, dtype=torch.int64, device=dev)
+        if exit_step:
+            out["exit_step"] = torch.empty((n, self.n_paths), dtype=torch.int32, device=dev)
+        if scores:
+            out["scores"] = torch.empty((n, self.n_paths, 2), dtype=torch.float32, device=dev)
+        return out
+
+    def _args(self, out):
+        def ptr(k):
+            v = out.get(k)
+            return None if v is None else v.data_ptr()
+        return (ptr("xi"), ptr("eta"), ptr("se_xi"), ptr("se_eta"), ptr("exit_step"), ptr("scores"),
+                ptr("total_steps"), self.workspace.data_ptr(), self.workspace.numel())
+
+    def run(self, out=None, exit_step=False, scores=False):
+        import torch
+        out = out if out is not None else self.outputs(exit_step, scores)
+        _check(_lib.fk_batch_run(self._h, *self._args(out), _stream(torch, self.device)))
+        return out
+
+    def capture(self, out, stream):
+        """Capture run(out) into a HIP graph on ``stream`` (a torch.cuda.Stream)."""
+        _check(_lib.fk_batch_capture(self._h, *self._args(out), ctypes.c_void_p(stream.cuda_stream)))
+
+    def replay(self, stream=None):
+        import torch
+        s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream(torch, self.device)
+        _check(_lib.fk_batch_replay(self._h, s))

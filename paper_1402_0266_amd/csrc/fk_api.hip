@@ -1,6 +1,6 @@
 // fk_api.hip -- C ABI of libfk.so: argument validation, host-side planning
-// (cost-ordered node tables, level constants, launch shape) and the launches
-// of the Monte-Carlo interface solve.
+// (cost-ordered node tables, level constants, launch shape) and the launch
+// sequence of the Monte-Carlo interface solve.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -19,7 +19,6 @@ namespace fk {
 
 thread_local std::string g_last_error;
 
-int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
 int fail(int code, const char *fmt, ...) {
     char buf[512];
     va_list ap;
@@ -30,35 +29,11 @@ int fail(int code, const char *fmt, ...) {
     return code;
 }
 
-int hip_fail(hipError_t e, const char *what) {
-    return fail(FK_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
-}
+int hip_fail(hipError_t e, const char *what) { return fail(FK_E_DEVICE, "%s: %s", what, hipGetErrorString(e)); }
 
-static size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
+size_t align256(size_t n) { return (n + 255) & ~(size_t)255; }
 
-// Workspace layout of one interface solve.
-struct WsLayout {
-    size_t counters, levels, nodes, outs, scores, total;
-};
-
-static WsLayout ws_layout(int64_t n_levels, int64_t n_nodes, int64_t n_paths, bool own_scores) {
-    WsLayout L{};
-    size_t off = 0;
-    L.counters = off;
-    off += 256;
-    L.levels = off;
-    off += align256(sizeof(LevelDev) * (size_t)n_levels);
-    L.nodes = off;
-    off += align256(sizeof(NodeDev) * (size_t)n_nodes);
-    L.outs = off;
-    off += align256(sizeof(OutDev) * (size_t)n_nodes);
-    L.scores = off;
-    if (own_scores) off += align256(sizeof(float2) * (size_t)n_nodes * (size_t)n_paths);
-    L.total = off;
-    return L;
-}
-
-static int64_t step_count(double t, double dt) {
+int64_t step_count(double t, double dt) {
     if (t <= 0.0) return 0;
     return (int64_t)std::ceil(t / dt - 1e-9);
 }
@@ -87,24 +62,67 @@ int validate_density(const fk_density *w) {
 int validate_data(const fk_data *d) {
     if (!d) return fail(FK_E_INVAL, "data is NULL");
     if (d->init_kind < 0 || d->init_kind > FK_DATA_GRID) return fail(FK_E_INVAL, "unknown init kind %d", d->init_kind);
-    if (d->bdry_kind < 0 || d->bdry_kind > FK_DATA_ZERO) return fail(FK_E_INVAL, "unknown boundary kind %d", d->bdry_kind);
+    if (d->bdry_kind < 0 || d->bdry_kind > FK_DATA_ZERO)
+        return fail(FK_E_INVAL, "unknown boundary kind %d", d->bdry_kind);
     if (d->score_mode != FK_SCORE_UNCLAMPED && d->score_mode != FK_SCORE_PROJECT)
         return fail(FK_E_INVAL, "unknown score mode %d", d->score_mode);
     if (!std::isfinite(d->t_init)) return fail(FK_E_INVAL, "t_init is not finite");
     if (d->init_kind == FK_DATA_GRID) {
-        if (d->grid_n < 1 || !d->grid_xi || !d->grid_eta) return fail(FK_E_INVAL, "grid initial data needs grid_n >= 1 and both grids");
+        if (d->grid_n < 1 || !d->grid_xi || !d->grid_eta)
+            return fail(FK_E_INVAL, "grid initial data needs grid_n >= 1 and both grids");
     }
     return FK_OK;
 }
 
+int validate_common(int64_t n_paths, double dt) {
+    if (n_paths < 2 || n_paths > 0x7fffffff) return fail(FK_E_INVAL, "n_paths must be in [2, 2^31)");
+    if (!std::isfinite(dt) || !(dt > 0.0)) return fail(FK_E_INVAL, "dt must be finite and > 0");
+    return FK_OK;
+}
+
+int validate_horizon(double t, double t_init, double dt, uint32_t level_id) {
+    if (!std::isfinite(t) || t < 0.0) return fail(FK_E_INVAL, "t must be finite and >= 0");
+    if (!std::isfinite(t_init)) return fail(FK_E_INVAL, "t_init is not finite");
+    if (level_id >= (1u << 28)) return fail(FK_E_INVAL, "level_id must be < 2^28");
+    if (step_count(t, dt) > 0x7ffffffe) return fail(FK_E_INVAL, "t/dt too large");
+    return FK_OK;
+}
+
+int validate_points(const double *pts, int64_t n) {
+    if (n < 0) return fail(FK_E_INVAL, "negative node count");
+    if (n > 0 && !pts) return fail(FK_E_INVAL, "pts is NULL");
+    for (int64_t i = 0; i < n; ++i) {
+        const double x = pts[2 * i], y = pts[2 * i + 1];
+        if (!(x >= 0.0 && x <= 1.0 && y >= 0.0 && y <= 1.0))
+            return fail(FK_E_INVAL, "node %lld (%g, %g) is not in the closed unit square", (long long)i, x, y);
+    }
+    return FK_OK;
+}
+
+int resolve_plan(const fk_plan *plan, fk_plan *out) {
+    fk_plan pl{256, 0, 128, 0};
+    if (plan) {
+        if (plan->block) pl.block = plan->block;
+        if (plan->blocks_per_cu) pl.blocks_per_cu = plan->blocks_per_cu;
+        if (plan->chunk) pl.chunk = plan->chunk;
+    }
+    if (pl.block < 64 || pl.block > 256 || pl.block % 64)
+        return fail(FK_E_INVAL, "plan block must be 64, 128, 192 or 256");
+    if (pl.chunk < 1 || pl.chunk > (1 << 20)) return fail(FK_E_INVAL, "plan chunk out of range");
+    if (pl.blocks_per_cu < 0 || pl.blocks_per_cu > 64) return fail(FK_E_INVAL, "plan blocks_per_cu out of range");
+    *out = pl;
+    return FK_OK;
+}
+
 // Level constants in the FP32 form the path kernel uses.
-LevelDev make_level(const fk_density *w, const fk_data *d, double t, double dt, uint32_t level_id,
-                    uint32_t stream) {
+LevelDev make_level(const fk_density *w, double t_init, double t, double dt, uint32_t level_id, uint32_t stream) {
     LevelDev L{};
     const int64_t K = step_count(t, dt);
     const double dl = K > 0 ? t - (double)(K - 1) * dt : dt;
     const double ln2 = 0.69314718055994530942;
-    L.tend = (float)(d->t_init + t);
+    const double log2e = 1.44269504088896340736;
+    const double orev = w->omega / (2.0 * 3.14159265358979323846);
+    L.tend = (float)(t_init + t);
     L.horizon = (float)t;
     L.dt = (float)dt;
     L.dt_last = (float)dl;
@@ -112,17 +130,15 @@ LevelDev make_level(const fk_density *w, const fk_data *d, double t, double dt, 
     L.cbm_last = (float)(-4.0 * ln2 * dl);
     L.K = (int32_t)K;
     L.ctr3 = (level_id << 4) | (stream & 15u);
-    const double log2e = 1.44269504088896340736;
     L.amp = (float)w->amp;
     L.nscale = w->kind == FK_DENSITY_CONST ? 0.f : (float)(-log2e / w->width2);
     L.a2s = w->kind == FK_DENSITY_CONST ? 0.f : (float)(2.0 * w->amp / w->width2);
     L.cx = (float)w->cx;
     L.cy = (float)w->cy;
     L.orbit_r = (float)w->orbit_r;
-    L.omega_rev = (float)(w->omega / (2.0 * 3.14159265358979323846));
+    L.omega_rev = (float)orev;
     L.t_freeze = (float)w->t_freeze;
-    const double orev = w->omega / (2.0 * 3.14159265358979323846);
-    L.rev0 = (float)((d->t_init + t) * orev);
+    L.rev0 = (float)((t_init + t) * orev);
     L.drev = (float)(dt * orev);
     L.cos_d = (float)std::cos(dt * w->omega);
     L.sin_d = (float)std::sin(dt * w->omega);
@@ -138,17 +154,54 @@ double node_cost(double x, double y, double t) {
     return std::min(t, tau);
 }
 
-// Optional per-kernel event timing of the calling thread.
-struct Timing {
-    bool enabled = false;
-    bool recorded = false;
-    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
-};
-thread_local Timing g_timing;
-
-static hipError_t timing_mark(int i, hipStream_t s) {
-    if (!g_timing.enabled) return hipSuccess;
-    return hipEventRecord(g_timing.ev[i], s);
+int build_tables(const LevelSpec *lv, int n_levels, const double *pts, int64_t n_total, const fk_data *d, double dt,
+                 Tables &T) {
+    T.levels.resize((size_t)n_levels);
+    T.nodes.resize((size_t)n_total);
+    T.outs.resize((size_t)n_total);
+    T.shift = (d->init_kind == FK_DATA_IDENTITY && d->bdry_kind == FK_DATA_IDENTITY);
+    T.kind = lv[0].w.kind;
+    T.time_mode = lv[0].w.time_mode;
+    T.uniform = true;
+    std::vector<double> cost((size_t)n_total);
+    std::vector<int32_t> level_of((size_t)n_total, -1);
+    for (int l = 0; l < n_levels; ++l) {
+        T.levels[(size_t)l] = make_level(&lv[l].w, lv[l].t_init, lv[l].t, dt, lv[l].level_id, 0u);
+        const LevelDev &L = T.levels[(size_t)l];
+        if (!(L.dt_last == L.dt && L.cbm_last == L.cbm)) T.uniform = false;
+        for (int64_t i = 0; i < lv[l].n_nodes; ++i) {
+            const int64_t g = lv[l].node_offset + i;
+            if (level_of[(size_t)g] >= 0) return fail(FK_E_INVAL, "levels overlap at node %lld", (long long)g);
+            level_of[(size_t)g] = l;
+            cost[(size_t)g] = node_cost(pts[2 * g], pts[2 * g + 1], lv[l].t);
+        }
+    }
+    for (int64_t g = 0; g < n_total; ++g)
+        if (level_of[(size_t)g] < 0) return fail(FK_E_INVAL, "node %lld belongs to no level", (long long)g);
+    std::vector<int64_t> order((size_t)n_total);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int64_t a, int64_t b) { return cost[(size_t)a] > cost[(size_t)b]; });
+    for (int64_t s = 0; s < n_total; ++s) {
+        const int64_t g = order[(size_t)s];
+        const int l = level_of[(size_t)g];
+        NodeDev &nd = T.nodes[(size_t)s];
+        // Start point as an FP32 (hi, lo) pair holding the FP64 node to ~2^-48.
+        nd.x = (float)pts[2 * g];
+        nd.y = (float)pts[2 * g + 1];
+        nd.xlo = (float)(pts[2 * g] - (double)nd.x);
+        nd.ylo = (float)(pts[2 * g + 1] - (double)nd.y);
+        nd.nid = (uint32_t)(g - lv[l].node_offset);
+        nd.level = (uint32_t)l;
+        nd.out = (uint64_t)g;
+        OutDev &od = T.outs[(size_t)g];
+        // The kernel stores scores minus the hi part of the start point; the
+        // shift adds that same value back.
+        od.shift_x = T.shift ? (double)nd.x : 0.0;
+        od.shift_y = T.shift ? (double)nd.y : 0.0;
+        od.K = T.levels[(size_t)l].K;
+    }
+    return FK_OK;
 }
 
 int device_cus(int *n_cu) {
@@ -158,6 +211,100 @@ int device_cus(int *n_cu) {
     e = hipDeviceGetAttribute(n_cu, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
     return FK_OK;
+}
+
+// Optional per-kernel event timing of the calling thread.
+struct Timing {
+    bool enabled = false;
+    bool recorded = false;
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+};
+thread_local Timing g_timing;
+
+static hipError_t timing_mark(bool on, int i, hipStream_t s) {
+    if (!on) return hipSuccess;
+    return hipEventRecord(g_timing.ev[i], s);
+}
+
+int check_chunks(int64_t n_nodes, int64_t n_paths, const fk_plan &pl) {
+    const int64_t cpn = (n_paths + pl.chunk - 1) / pl.chunk;
+    if (n_nodes * cpn >= 0xffffffffLL) return fail(FK_E_INVAL, "too many work chunks; raise plan chunk");
+    return FK_OK;
+}
+
+int enqueue_solve(const SolveLaunch &S, hipStream_t stream, bool allow_timing) {
+    int n_cu = 0;
+    int rc;
+    if ((rc = device_cus(&n_cu)) != FK_OK) return rc;
+    if ((rc = check_chunks(S.n_nodes, S.n_paths, S.plan)) != FK_OK) return rc;
+    const bool timed = allow_timing && g_timing.enabled;
+    hipError_t e;
+    if ((e = launch_zero_u32(S.counters, 64, stream)) != hipSuccess) return hip_fail(e, "zero counters");
+    PathArgs a = S.args;
+    if (S.total_steps) {
+        if ((e = launch_zero_u32((uint32_t *)S.total_steps, 2, stream)) != hipSuccess)
+            return hip_fail(e, "zero total_steps");
+        a.total_steps = (unsigned long long *)S.total_steps;
+    } else {
+        a.total_steps = (unsigned long long *)(S.counters + 2);
+    }
+    a.queue = S.counters;
+    const int64_t cpn = (S.n_paths + S.plan.chunk - 1) / S.plan.chunk;
+    a.n_paths = (uint32_t)S.n_paths;
+    a.chunk = (uint32_t)S.plan.chunk;
+    a.cpn = (uint32_t)cpn;
+    a.total_chunks = (uint32_t)(S.n_nodes * cpn);
+    int bpc = S.plan.blocks_per_cu;
+    const int occ = path_kernel_max_blocks_per_cu(S.kind, S.time_mode, S.uniform, S.plan.block);
+    if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
+    const int grid = n_cu * bpc;
+    if ((e = timing_mark(timed, 0, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if ((e = launch_paths(S.kind, S.time_mode, S.uniform, a, grid, S.plan.block, stream)) != hipSuccess)
+        return hip_fail(e, "path kernel launch");
+    if ((e = timing_mark(timed, 1, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    ReduceArgs r = S.reduce;
+    r.scores = a.scores;
+    r.n_paths = S.n_paths;
+    r.n_out = S.n_nodes;
+    if ((e = launch_reduce(r, stream)) != hipSuccess) return hip_fail(e, "reduce kernel launch");
+    if ((e = timing_mark(timed, 2, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if (timed) g_timing.recorded = true;
+    return FK_OK;
+}
+
+void fill_common_args(SolveLaunch &S, const fk_data *d, bool shift, uint64_t seed) {
+    PathArgs &a = S.args;
+    a.grid_xi = d->grid_xi;
+    a.grid_eta = d->grid_eta;
+    a.grid_n = d->grid_n;
+    a.init_kind = d->init_kind;
+    a.bdry_kind = d->bdry_kind;
+    a.score_mode = d->score_mode;
+    a.shift = shift ? 1 : 0;
+    a.key0 = (uint32_t)seed;
+    a.key1 = (uint32_t)(seed >> 32);
+}
+
+// Workspace layout of one single-call interface solve.
+struct WsLayout {
+    size_t counters, levels, nodes, outs, scores, total;
+};
+
+static WsLayout ws_layout(int64_t n_levels, int64_t n_nodes, int64_t n_paths, bool own_scores) {
+    WsLayout L{};
+    size_t off = 0;
+    L.counters = off;
+    off += 256;
+    L.levels = off;
+    off += align256(sizeof(LevelDev) * (size_t)n_levels);
+    L.nodes = off;
+    off += align256(sizeof(NodeDev) * (size_t)n_nodes);
+    L.outs = off;
+    off += align256(sizeof(OutDev) * (size_t)n_nodes);
+    L.scores = off;
+    if (own_scores) off += align256(sizeof(float2) * (size_t)n_nodes * (size_t)n_paths);
+    L.total = off;
+    return L;
 }
 
 }  // namespace fk
@@ -194,8 +341,10 @@ int fk_timing_last(double *path_kernel_ms, double *reduce_kernel_ms) {
     hipError_t e = hipEventSynchronize(g_timing.ev[2]);
     if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
     float a = 0.f, b = 0.f;
-    if ((e = hipEventElapsedTime(&a, g_timing.ev[0], g_timing.ev[1])) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
-    if ((e = hipEventElapsedTime(&b, g_timing.ev[1], g_timing.ev[2])) != hipSuccess) return hip_fail(e, "hipEventElapsedTime");
+    if ((e = hipEventElapsedTime(&a, g_timing.ev[0], g_timing.ev[1])) != hipSuccess)
+        return hip_fail(e, "hipEventElapsedTime");
+    if ((e = hipEventElapsedTime(&b, g_timing.ev[1], g_timing.ev[2])) != hipSuccess)
+        return hip_fail(e, "hipEventElapsedTime");
     if (path_kernel_ms) *path_kernel_ms = a;
     if (reduce_kernel_ms) *reduce_kernel_ms = b;
     return FK_OK;
@@ -218,132 +367,58 @@ int fk_interface_solve(const fk_density *w, const fk_data *d, const double *pts,
     int rc;
     if ((rc = validate_density(w)) != FK_OK) return rc;
     if ((rc = validate_data(d)) != FK_OK) return rc;
-    if (n_nodes < 0) return fail(FK_E_INVAL, "n_nodes < 0");
-    if (n_paths < 2 || n_paths > 0x7fffffff) return fail(FK_E_INVAL, "n_paths must be in [2, 2^31)");
-    if (!std::isfinite(t) || t < 0.0) return fail(FK_E_INVAL, "t must be finite and >= 0");
-    if (!std::isfinite(dt) || !(dt > 0.0)) return fail(FK_E_INVAL, "dt must be finite and > 0");
-    if (level_id >= (1u << 28)) return fail(FK_E_INVAL, "level_id must be < 2^28");
-    const int64_t K = step_count(t, dt);
-    if (K > 0x7ffffffe) return fail(FK_E_INVAL, "t/dt too large");
-    if (n_nodes > 0 && !pts) return fail(FK_E_INVAL, "pts is NULL");
-    for (int64_t i = 0; i < n_nodes; ++i) {
-        const double x = pts[2 * i], y = pts[2 * i + 1];
-        if (!(x >= 0.0 && x <= 1.0 && y >= 0.0 && y <= 1.0))
-            return fail(FK_E_INVAL, "node %lld (%g, %g) is not in the closed unit square", (long long)i, x, y);
-    }
+    if ((rc = validate_common(n_paths, dt)) != FK_OK) return rc;
+    if ((rc = validate_horizon(t, d->t_init, dt, level_id)) != FK_OK) return rc;
+    if ((rc = validate_points(pts, n_nodes)) != FK_OK) return rc;
     if (n_nodes > 0 && (!xi || !eta || !se_xi || !se_eta)) return fail(FK_E_INVAL, "an output pointer is NULL");
     if (steps && !exit_step) return fail(FK_E_INVAL, "per-node steps need exit_step");
-    fk_plan pl{256, 0, 128, 0};
-    if (plan) {
-        if (plan->block) pl.block = plan->block;
-        if (plan->blocks_per_cu) pl.blocks_per_cu = plan->blocks_per_cu;
-        if (plan->chunk) pl.chunk = plan->chunk;
-    }
-    if (pl.block < 64 || pl.block > 256 || pl.block % 64) return fail(FK_E_INVAL, "plan block must be 64, 128, 192 or 256");
-    if (pl.chunk < 1 || pl.chunk > (1 << 20)) return fail(FK_E_INVAL, "plan chunk out of range");
-    if (pl.blocks_per_cu < 0 || pl.blocks_per_cu > 64) return fail(FK_E_INVAL, "plan blocks_per_cu out of range");
-    const int64_t cpn = (n_paths + pl.chunk - 1) / pl.chunk;
-    if (n_nodes * cpn >= 0xffffffffLL) return fail(FK_E_INVAL, "too many work chunks; raise plan chunk");
+    fk_plan pl;
+    if ((rc = resolve_plan(plan, &pl)) != FK_OK) return rc;
+    if ((rc = check_chunks(n_nodes, n_paths, pl)) != FK_OK) return rc;
     const WsLayout lay = ws_layout(1, n_nodes, n_paths, scores == nullptr);
     if (!workspace || workspace_bytes < lay.total)
         return fail(FK_E_NOMEM, "workspace too small: need %zu bytes", lay.total);
     if (((uintptr_t)workspace & 255u) != 0) return fail(FK_E_INVAL, "workspace must be 256-byte aligned");
     if (n_nodes == 0) return FK_OK;
 
-    int n_cu = 0;
-    if ((rc = device_cus(&n_cu)) != FK_OK) return rc;
-
-    // ---- host tables --------------------------------------------------------
-    const LevelDev lev = make_level(w, d, t, dt, level_id, 0u);
-    std::vector<int64_t> order((size_t)n_nodes);
-    std::iota(order.begin(), order.end(), 0);
-    std::vector<double> cost((size_t)n_nodes);
-    for (int64_t i = 0; i < n_nodes; ++i) cost[(size_t)i] = node_cost(pts[2 * i], pts[2 * i + 1], t);
-    std::stable_sort(order.begin(), order.end(), [&](int64_t a, int64_t b) { return cost[(size_t)a] > cost[(size_t)b]; });
-    std::vector<NodeDev> nodes((size_t)n_nodes);
-    std::vector<OutDev> outs((size_t)n_nodes);
-    const bool shift = (d->init_kind == FK_DATA_IDENTITY && d->bdry_kind == FK_DATA_IDENTITY);
-    for (int64_t s = 0; s < n_nodes; ++s) {
-        const int64_t i = order[(size_t)s];
-        NodeDev &nd = nodes[(size_t)s];
-        // Start point as an FP32 (hi, lo) pair holding the FP64 node exactly
-        // to ~2^-48.
-        nd.x = (float)pts[2 * i];
-        nd.y = (float)pts[2 * i + 1];
-        nd.xlo = (float)(pts[2 * i] - (double)nd.x);
-        nd.ylo = (float)(pts[2 * i + 1] - (double)nd.y);
-        nd.nid = (uint32_t)i;
-        nd.level = 0;
-        nd.out = (uint64_t)i;
-        OutDev &od = outs[(size_t)i];
-        // The kernel stores scores minus the hi part of the start point; the
-        // shift adds that same value back.
-        od.shift_x = shift ? (double)nd.x : 0.0;
-        od.shift_y = shift ? (double)nd.y : 0.0;
-        od.K = K;
-    }
+    LevelSpec spec{*w, t, d->t_init, 0, n_nodes, level_id};
+    Tables T;
+    if ((rc = build_tables(&spec, 1, pts, n_nodes, d, dt, T)) != FK_OK) return rc;
 
     char *ws = (char *)workspace;
     hipError_t e;
-    if ((e = hipMemcpyAsync(ws + lay.levels, &lev, sizeof lev, hipMemcpyHostToDevice, stream)) != hipSuccess)
+    if ((e = hipMemcpyAsync(ws + lay.levels, T.levels.data(), sizeof(LevelDev) * T.levels.size(),
+                            hipMemcpyHostToDevice, stream)) != hipSuccess)
         return hip_fail(e, "upload level table");
-    if ((e = hipMemcpyAsync(ws + lay.nodes, nodes.data(), sizeof(NodeDev) * nodes.size(), hipMemcpyHostToDevice, stream)) != hipSuccess)
+    if ((e = hipMemcpyAsync(ws + lay.nodes, T.nodes.data(), sizeof(NodeDev) * T.nodes.size(), hipMemcpyHostToDevice,
+                            stream)) != hipSuccess)
         return hip_fail(e, "upload node table");
-    if ((e = hipMemcpyAsync(ws + lay.outs, outs.data(), sizeof(OutDev) * outs.size(), hipMemcpyHostToDevice, stream)) != hipSuccess)
+    if ((e = hipMemcpyAsync(ws + lay.outs, T.outs.data(), sizeof(OutDev) * T.outs.size(), hipMemcpyHostToDevice,
+                            stream)) != hipSuccess)
         return hip_fail(e, "upload output table");
-    uint32_t *counters = (uint32_t *)(ws + lay.counters);
-    if ((e = launch_zero_u32(counters, 64, stream)) != hipSuccess) return hip_fail(e, "zero counters");
 
-    PathArgs a{};
-    a.levels = (const LevelDev *)(ws + lay.levels);
-    a.nodes = (const NodeDev *)(ws + lay.nodes);
-    a.scores = scores ? (float2 *)scores : (float2 *)(ws + lay.scores);
-    a.exit_step = exit_step;
-    a.queue = counters;
-    a.total_steps = total_steps ? (unsigned long long *)total_steps : (unsigned long long *)(counters + 2);
-    if (total_steps) {
-        if ((e = launch_zero_u32((uint32_t *)total_steps, 2, stream)) != hipSuccess) return hip_fail(e, "zero total_steps");
-    }
-    a.grid_xi = d->grid_xi;
-    a.grid_eta = d->grid_eta;
-    a.grid_n = d->grid_n;
-    a.init_kind = d->init_kind;
-    a.bdry_kind = d->bdry_kind;
-    a.score_mode = d->score_mode;
-    a.shift = shift ? 1 : 0;
-    a.key0 = (uint32_t)seed;
-    a.key1 = (uint32_t)(seed >> 32);
-    a.n_paths = (uint32_t)n_paths;
-    a.chunk = (uint32_t)pl.chunk;
-    a.cpn = (uint32_t)cpn;
-    a.total_chunks = (uint32_t)(n_nodes * cpn);
-
-    // Every step has length dt when the FP32 constants of the last step match.
-    const bool uniform = (lev.dt_last == lev.dt && lev.cbm_last == lev.cbm);
-    int bpc = pl.blocks_per_cu;
-    const int occ = path_kernel_max_blocks_per_cu(w->kind, w->time_mode, uniform, pl.block);
-    if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
-    const int grid = n_cu * bpc;
-    if ((e = timing_mark(0, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    if ((e = launch_paths(w->kind, w->time_mode, uniform, a, grid, pl.block, stream)) != hipSuccess)
-        return hip_fail(e, "path kernel launch");
-    if ((e = timing_mark(1, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-
-    ReduceArgs r{};
-    r.scores = a.scores;
-    r.exit_step = exit_step;
-    r.outs = (const OutDev *)(ws + lay.outs);
-    r.n_out = n_nodes;
-    r.n_paths = n_paths;
-    r.xi = xi;
-    r.eta = eta;
-    r.se_xi = se_xi;
-    r.se_eta = se_eta;
-    r.steps = steps;
-    if ((e = launch_reduce(r, stream)) != hipSuccess) return hip_fail(e, "reduce kernel launch");
-    if ((e = timing_mark(2, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    if (g_timing.enabled) g_timing.recorded = true;
-    return FK_OK;
+    SolveLaunch S{};
+    S.kind = T.kind;
+    S.time_mode = T.time_mode;
+    S.uniform = T.uniform;
+    S.plan = pl;
+    S.n_nodes = n_nodes;
+    S.n_paths = n_paths;
+    S.counters = (uint32_t *)(ws + lay.counters);
+    S.total_steps = total_steps;
+    fill_common_args(S, d, T.shift, seed);
+    S.args.levels = (const LevelDev *)(ws + lay.levels);
+    S.args.nodes = (const NodeDev *)(ws + lay.nodes);
+    S.args.scores = scores ? (float2 *)scores : (float2 *)(ws + lay.scores);
+    S.args.exit_step = exit_step;
+    S.reduce.exit_step = exit_step;
+    S.reduce.outs = (const OutDev *)(ws + lay.outs);
+    S.reduce.xi = xi;
+    S.reduce.eta = eta;
+    S.reduce.se_xi = se_xi;
+    S.reduce.se_eta = se_eta;
+    S.reduce.steps = steps;
+    return enqueue_solve(S, stream, true);
 }
 
 }  // extern "C"

@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+#include <vector>
+
 #include "fk.h"
 
 namespace fk {
@@ -76,6 +79,60 @@ struct ReduceArgs {
     double *xi, *eta, *se_xi, *se_eta;
     int64_t *steps;                  // or nullptr
 };
+
+// ---- host-side planning (fk_api.hip) ---------------------------------------
+
+// One time level of a solve: density, horizon and its slice of the node list.
+struct LevelSpec {
+    fk_density w;
+    double t;
+    double t_init;
+    int64_t node_offset;
+    int64_t n_nodes;
+    uint32_t level_id;
+};
+
+// Device tables of a solve, built on the host.
+struct Tables {
+    std::vector<LevelDev> levels;
+    std::vector<NodeDev> nodes;  // launch (cost) order
+    std::vector<OutDev> outs;    // output order
+    int kind = 0, time_mode = 0;
+    bool uniform = true;         // every step has length dt
+    bool shift = false;          // scores stored relative to the start point
+};
+
+// Everything one enqueue of the solve sequence needs.
+struct SolveLaunch {
+    PathArgs args;       // tables, scores, data; counters and sizes filled by enqueue_solve
+    ReduceArgs reduce;   // outputs; sizes filled by enqueue_solve
+    int kind, time_mode;
+    bool uniform;
+    fk_plan plan;
+    int64_t n_nodes, n_paths;
+    uint32_t *counters;  // 256 B of device scratch (queue, step count)
+    uint64_t *total_steps;
+};
+
+extern thread_local std::string g_last_error;
+int fail(int code, const char *fmt, ...) __attribute__((format(printf, 2, 3)));
+int hip_fail(hipError_t e, const char *what);
+size_t align256(size_t n);
+int64_t step_count(double t, double dt);
+int validate_density(const fk_density *w);
+int validate_data(const fk_data *d);
+int validate_common(int64_t n_paths, double dt);
+int validate_horizon(double t, double t_init, double dt, uint32_t level_id);
+int validate_points(const double *pts, int64_t n);
+int resolve_plan(const fk_plan *plan, fk_plan *out);
+int check_chunks(int64_t n_nodes, int64_t n_paths, const fk_plan &pl);
+int build_tables(const LevelSpec *lv, int n_levels, const double *pts, int64_t n_total, const fk_data *d, double dt,
+                 Tables &T);
+void fill_common_args(SolveLaunch &S, const fk_data *d, bool shift, uint64_t seed);
+int device_cus(int *n_cu);
+// Queues zero-counters, path kernel and reduction on the stream.  With
+// allow_timing, records the timing events when timing is enabled.
+int enqueue_solve(const SolveLaunch &S, hipStream_t stream, bool allow_timing);
 
 // Launch helpers implemented in fk_paths.hip.
 hipError_t launch_zero_u32(uint32_t *p, int n_words, hipStream_t s);

@@ -5,10 +5,9 @@
 
 #include "fk.h"
 #include "fk_device.hpp"
+#include "fk_internal.hpp"
 
 namespace fk {
-int fail(int code, const char *fmt, ...);
-int hip_fail(hipError_t e, const char *what);
 
 __global__ void philox_words_kernel(const uint4 *ctr, int64_t n, uint32_t k0, uint32_t k1, uint4 *out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

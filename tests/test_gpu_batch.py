@@ -1,0 +1,138 @@
+"""Batched persistent launch: many time levels with uneven node sets in one
+launch must give, node for node, exactly the single-call results; plans
+(autotuned or not) and graph replays must not change a bit; the full
+64-level workload is checked on sampled paths against the oracle."""
+import os
+
+import numpy as np
+import pytest
+
+import workloads as W
+from parity import assert_parity
+
+pytestmark = pytest.mark.gpu
+THREADS = min(16, os.cpu_count() or 1)
+
+
+def small_levels(n_levels=6, G=16, dt_level=0.01):
+    dens = W.moving_bump()
+    return [(dens, t, 0.0, pts, k) for k, (t, px, py, pts) in
+            enumerate(W.batched_levels(n_levels, G=G, dt_level=dt_level), start=1)]
+
+
+def to_np(out):
+    return {k: v.cpu().numpy() for k, v in out.items()}
+
+
+def test_batched_equals_single_calls(fk):
+    import torch
+    levels = small_levels()
+    N, dt = 256, 1e-4
+    print(f"[gpu] batch of {len(levels)} levels, N={N}", flush=True)
+    b = fk.FkBatch(levels, W.Data(), dt, N, seed=5)
+    got = to_np(b.run(exit_step=True, scores=True))
+    torch.cuda.synchronize()
+    for li, (dens, t, t0, pts, lid) in enumerate(levels):
+        a, z = b.offsets[li], b.offsets[li + 1]
+        s = fk.fk_interface_solve(dens, W.Data(t_init=t0), pts, t, dt, N, 5, lid, exit_step=True, scores=True)
+        torch.cuda.synchronize()
+        s = to_np(s)
+        for k in ("xi", "eta", "se_xi", "se_eta", "exit_step", "scores"):
+            assert np.array_equal(got[k][a:z], s[k]), (li, k)
+    b.close()
+
+
+def test_plans_and_autotune_do_not_change_results(fk):
+    import torch
+    levels = small_levels(4)
+    b = fk.FkBatch(levels, W.Data(), 1e-4, 512, seed=1)
+    ref = to_np(b.run(exit_step=True))
+    for plan in ({"block": 64, "chunk": 16}, {"block": 128, "chunk": 1000, "blocks_per_cu": 1},
+                 {"block": 256, "chunk": 32, "blocks_per_cu": 2}):
+        b.plan = plan
+        out = to_np(b.run(exit_step=True))
+        torch.cuda.synchronize()
+        for k in ("xi", "eta", "se_xi", "se_eta", "exit_step"):
+            assert np.array_equal(out[k], ref[k]), (plan, k)
+    chosen = b.autotune(64)
+    print(f"autotuned plan {chosen}", flush=True)
+    assert b.plan == chosen and chosen["block"] in (64, 128, 256)
+    out = to_np(b.run(exit_step=True))
+    for k in ("xi", "eta", "se_xi", "se_eta", "exit_step"):
+        assert np.array_equal(out[k], ref[k]), k
+    # the cache answers the same question without re-timing
+    assert b.autotune(64) == chosen
+    b.close()
+
+
+def test_graph_capture_and_replay(fk):
+    import torch
+    levels = small_levels(3)
+    b = fk.FkBatch(levels, W.Data(), 1e-4, 300, seed=2)
+    eager = to_np(b.run(exit_step=True))
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    out = b.outputs(exit_step=True)
+    b.capture(out, s)
+    for rep in range(3):
+        for v in out.values():
+            v.zero_()                     # eager work between replays
+        torch.cuda.synchronize()
+        b.replay(s)
+        s.synchronize()
+        got = to_np(out)
+        for k in ("xi", "eta", "se_xi", "se_eta", "exit_step", "total_steps"):
+            assert np.array_equal(got[k], eager[k]), (rep, k)
+    b.close()
+
+
+def test_batched_against_oracle(fk, oracle_mod):
+    levels = small_levels(5)
+    N, dt = 1000, 1e-4
+    b = fk.FkBatch(levels, W.Data(), dt, N, seed=9)
+    got = to_np(b.run(exit_step=True, scores=True))
+    for li in (0, 2, 4):
+        dens, t, t0, pts, lid = levels[li]
+        a, z = b.offsets[li], b.offsets[li + 1]
+        o = oracle_mod.fk_solve(dens, W.Data(t_init=t0), pts, t, dt, N, 9, lid, want_exit=True, want_scores=True,
+                                threads=THREADS)
+        g = {k: got[k][a:z] for k in ("xi", "eta", "se_xi", "se_eta", "exit_step", "scores")}
+        assert_parity(g, o, pts, label=f"level {lid}:")
+    b.close()
+
+
+def test_full_size_batched_levels_sampled(fk, oracle_mod):
+    """64 time levels t_k = 0.01 k, random 2x2..8x8 layouts on G = 128
+    (66047 nodes), dt = 1e-5, 2^16 paths per node, one launch."""
+    import torch
+    dens = W.moving_bump()
+    lv = W.batched_levels(64, G=128)
+    levels = [(dens, t, 0.0, pts, k) for k, (t, px, py, pts) in enumerate(lv, start=1)]
+    N, dt = 1 << 16, 1e-5
+    b = fk.FkBatch(levels, W.Data(), dt, N, seed=0)
+    print(f"[gpu] full batched workload: {b.n_total} nodes x {N} paths", flush=True)
+    out = b.run(exit_step=True)
+    torch.cuda.synchronize()
+    got = {k: v.cpu().numpy() for k, v in out.items() if k != "exit_step"}
+    rng = np.random.default_rng(321)
+    m = 256
+    gi = rng.integers(0, b.n_total, m)
+    pi = rng.integers(0, N, m)
+    ex_g = out["exit_step"][torch.from_numpy(gi).cuda(), torch.from_numpy(pi).cuda()].cpu().numpy()
+    del out
+    lvl = np.searchsorted(b.offsets, gi, side="right") - 1
+    ex_o = np.zeros(m, dtype=np.int32)
+    for L in np.unique(lvl):
+        sel = np.where(lvl == L)[0]
+        t = levels[L][1]
+        nid = gi[sel] - b.offsets[L]
+        _, e = oracle_mod.fk_paths(dens, W.Data(), b.pts[gi[sel]], nid, pi[sel], t, dt, 0, level_id=L + 1,
+                                   threads=THREADS)
+        ex_o[sel] = e
+    match = np.mean(ex_g == ex_o)
+    print(f"sampled exit match {match:.4f}; total steps {int(got['total_steps'][0]):.4e}", flush=True)
+    assert match >= 0.99
+    m_ = np.stack([got["xi"], got["eta"]], 1)
+    s_ = np.stack([got["se_xi"], got["se_eta"]], 1)
+    assert np.all(np.isfinite(m_)) and np.all(m_ >= -3 * s_) and np.all(m_ <= 1 + 3 * s_)
+    b.close()

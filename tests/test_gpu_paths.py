@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 import workloads as W
+from parity import assert_parity
 
 pytestmark = pytest.mark.gpu
 
@@ -39,25 +40,8 @@ def run_gpu(fk, torch, dens, data, pts, t, dt, n, seed=0, level_id=0, plan=None,
 
 
 def run_oracle(oracle_mod, dens, data, pts, t, dt, n, seed=0, level_id=0):
-    return oracle_mod.fk_solve(dens, data, pts, t, dt, n, seed, level_id, want_exit=True, threads=THREADS)
-
-
-def assert_parity(g, o, abs_tol=1e-5, match_min=0.999):
-    ex_g, ex_o = g["exit_step"], o["exit_step"]
-    match = float(np.mean(ex_g == ex_o))
-    mean_g = np.stack([g["xi"], g["eta"]], axis=1)
-    se_g = np.stack([g["se_xi"], g["se_eta"]], axis=1)
-    d = np.abs(mean_g - o["mean"])
-    print(f"exit-step match {match:.6f}; max |mean diff| {d.max():.3e}; "
-          f"max diff/se {np.max(d / np.maximum(o['se'], 1e-300)):.3f}", flush=True)
-    assert match >= match_min
-    assert np.all(d <= abs_tol)
-    assert np.all(d <= 3.0 * o["se"] + 1e-15)
-    nz = o["se"] > 0
-    assert np.all(np.abs(se_g[nz] - o["se"][nz]) <= 0.01 * o["se"][nz])
-    # per-node step counts and the total agree with the exit steps
-    assert np.array_equal(g["steps"], o["steps"]) or match < 1.0
-    assert int(g["total_steps"][0]) == int(g["steps"].sum())
+    return oracle_mod.fk_solve(dens, data, pts, t, dt, n, seed, level_id, want_exit=True, want_scores=True,
+                               threads=THREADS)
 
 
 def test_static_bump_31_nodes_full(fk, torch_cuda, oracle_mod):
@@ -66,7 +50,7 @@ def test_static_bump_31_nodes_full(fk, torch_cuda, oracle_mod):
     pts = wl.nodes()
     g = run_gpu(fk, torch_cuda, wl.density, wl.data, pts, wl.t, wl.dt, wl.n_paths)
     o = run_oracle(oracle_mod, wl.density, wl.data, pts, wl.t, wl.dt, wl.n_paths)
-    assert_parity(g, o)
+    assert_parity(g, o, pts)
     # invariants: means in [0, 1]; eta non-decreasing along the vertical interface
     m = np.stack([g["xi"], g["eta"]], axis=1)
     s = np.stack([g["se_xi"], g["se_eta"]], axis=1)
@@ -81,7 +65,7 @@ def test_moving_bump_node_subset(fk, torch_cuda, oracle_mod):
     pts = wl.nodes()[::32]
     g = run_gpu(fk, torch_cuda, wl.density, wl.data, pts, wl.t, wl.dt, 512)
     o = run_oracle(oracle_mod, wl.density, wl.data, pts, wl.t, wl.dt, 512)
-    assert_parity(g, o)
+    assert_parity(g, o, pts)
 
 
 def test_const_identity_exact(fk, torch_cuda, oracle_mod):
@@ -90,7 +74,7 @@ def test_const_identity_exact(fk, torch_cuda, oracle_mod):
     pts = W.uniform_points(40, seed=1, lo=0.0, hi=1.0)
     g = run_gpu(fk, torch_cuda, W.CONST, W.Data(), pts, 0.08, 2e-3, 4000, seed=3)
     o = run_oracle(oracle_mod, W.CONST, W.Data(), pts, 0.08, 2e-3, 4000, seed=3)
-    assert_parity(g, o)
+    assert_parity(g, o, pts)
     z = (np.stack([g["xi"], g["eta"]], 1) - pts) / np.stack([g["se_xi"], g["se_eta"]], 1)
     assert np.all(np.abs(z) < 4.5)
 
@@ -103,7 +87,7 @@ def test_const_sin_mode_closed_form(fk, torch_cuda, oracle_mod):
     t, dt = 0.05, 1e-3
     g = run_gpu(fk, torch_cuda, W.CONST, data, pts, t, dt, 8000, seed=5)
     o = run_oracle(oracle_mod, W.CONST, data, pts, t, dt, 8000, seed=5)
-    assert_parity(g, o)
+    assert_parity(g, o, pts, shifted=False)
     exact = math.exp(-2 * math.pi ** 2 * t) * np.sin(math.pi * pts[:, 0]) * np.sin(math.pi * pts[:, 1])
     assert np.all(np.abs(g["xi"] - exact) <= 4.5 * g["se_xi"] + 1e-12)
 
@@ -114,7 +98,7 @@ def test_ridge_eta_exact(fk, torch_cuda, oracle_mod):
     dens = W.ridge()
     g = run_gpu(fk, torch_cuda, dens, W.Data(), pts, 0.05, 1e-4, 4000, seed=7)
     o = run_oracle(oracle_mod, dens, W.Data(), pts, 0.05, 1e-4, 4000, seed=7)
-    assert_parity(g, o)
+    assert_parity(g, o, pts)
     assert np.all(np.abs(g["eta"] - pts[:, 1]) <= 4.5 * g["se_eta"])
 
 
@@ -134,7 +118,7 @@ def test_two_bumps_frozen_grid_data(fk, torch_cuda, oracle_mod):
     grids = (torch.tensor(gx.ravel(), device="cuda"), torch.tensor(gy.ravel(), device="cuda"))
     g = run_gpu(fk, torch_cuda, dens, data, pts, 5e-4, 2.5e-5, 4000, seed=11, grids=grids)
     o = run_oracle(oracle_mod, dens, data, pts, 5e-4, 2.5e-5, 4000, seed=11)
-    assert_parity(g, o)
+    assert_parity(g, o, pts, shifted=False)
 
 
 def test_moving_bump_project_and_level_id(fk, torch_cuda, oracle_mod):
@@ -143,7 +127,7 @@ def test_moving_bump_project_and_level_id(fk, torch_cuda, oracle_mod):
     data = W.Data(score_mode=W.SCORE_PROJECT)
     g = run_gpu(fk, torch_cuda, wl.density, data, pts, 0.02, 5e-5, 2000, seed=13, level_id=37)
     o = run_oracle(oracle_mod, wl.density, data, pts, 0.02, 5e-5, 2000, seed=13, level_id=37)
-    assert_parity(g, o)
+    assert_parity(g, o, pts)
 
 
 def test_edge_cases(fk, torch_cuda, oracle_mod):
@@ -163,7 +147,7 @@ def test_edge_cases(fk, torch_cuda, oracle_mod):
     for n_paths in (2, 333):
         g = run_gpu(fk, torch_cuda, dens, W.Data(), pts, 1.05e-3, 1e-4, n_paths, seed=17)
         o = run_oracle(oracle_mod, dens, W.Data(), pts, 1.05e-3, 1e-4, n_paths, seed=17)
-        assert_parity(g, o)
+        assert_parity(g, o, pts)
 
 
 def test_schedule_invariance(fk, torch_cuda):
@@ -206,7 +190,7 @@ def test_full_size_moving_bump_sampled(fk, torch_cuda, oracle_mod):
     # four whole nodes, spread over the canonical order
     sel = np.array([0, 400, 800, 1500])
     o = oracle_mod.fk_solve(wl.density, wl.data, pts[sel], wl.t, wl.dt, wl.n_paths, wl.seed,
-                            node_ids=sel, want_exit=True, threads=THREADS)
+                            node_ids=sel, want_exit=True, want_scores=True, threads=THREADS)
     sub = {k: (g[k][sel] if k != "total_steps" else g[k]) for k in g}
     sub["total_steps"] = np.array([sub["steps"].sum()])
-    assert_parity(sub, o)
+    assert_parity(sub, o, pts[sel])
