@@ -1,0 +1,145 @@
+"""TEST INFRASTRUCTURE -- FP64 SciPy oracle of the deterministic sub-domain
+solves and of the mesh-quality measures.
+
+Deterministic single-domain solver (Sect. 4): the interface values found by
+the stochastic solver are Dirichlet data for an implicit finite-difference
+discretisation of the relaxed Winslow system (Sect. 2, eq. (3)), solved by
+LU factorisation.  Reading taken here (the paper gives no more detail): one
+backward-Euler step per mesh step,
+
+    (u^{n+1} - u^n) / D = L_h u^{n+1},
+    L_h u = (u_E + u_W + u_N + u_S - 4 u_P) / h^2
+            + b_x (u_E - u_W) / (2h) + b_y (u_N - u_S) / (2h),
+
+with b = -grad w / w (eq. (6)) at the node, w held at one time t_w over the
+step (Sect. 4 freezes the density over a mesh step), on the uniform nodal
+grid x = i/N, y = j/N.  Outer boundary data: the identity (xi = x, eta = y)
+or zero.  ``global_be_step`` solves the whole grid; ``subdomain_be_step``
+solves each of px x px sub-domains (m cells a side, N = px m) with the
+interface nodes as Dirichlet data.  Both use scipy.sparse LU (splu).
+
+Grids are [(N+1), (N+1)] arrays indexed [j, i].
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+import scipy.sparse.linalg as spla
+
+import oracle as _oracle
+
+
+def _drift_grid(dens, t_w, N):
+    x = np.arange(N + 1) / N
+    X, Y = np.meshgrid(x, x)
+    pts = np.stack([X.ravel(), Y.ravel()], 1)
+    _, b = _oracle.density(dens, t_w, pts)
+    return b[:, 0].reshape(N + 1, N + 1), b[:, 1].reshape(N + 1, N + 1)
+
+
+def boundary_grid(N, bdry: str = "identity"):
+    """Grids holding the outer boundary data (interior entries unspecified = 0)."""
+    x = np.arange(N + 1) / N
+    X, Y = np.meshgrid(x, x)
+    gx, gy = np.zeros_like(X), np.zeros_like(X)
+    if bdry == "identity":
+        for g, v in ((gx, X), (gy, Y)):
+            g[0, :], g[-1, :], g[:, 0], g[:, -1] = v[0, :], v[-1, :], v[:, 0], v[:, -1]
+    return gx, gy
+
+
+def _be_solve_region(bx, by, D, h, i0, i1, j0, j1, rhs_grids, bc_grids):
+    """Backward-Euler solve on the interior nodes i0 < i < i1, j0 < j < j1;
+    every node on the region's edge is Dirichlet data from bc_grids."""
+    ni, nj = i1 - i0 - 1, j1 - j0 - 1
+    n = ni * nj
+    idx = lambda i, j: (j - j0 - 1) * ni + (i - i0 - 1)  # noqa: E731
+    rows, cols, vals = [], [], []
+    rhs = [np.zeros(n) for _ in rhs_grids]
+    c0 = D / h ** 2
+    for j in range(j0 + 1, j1):
+        for i in range(i0 + 1, i1):
+            r = idx(i, j)
+            rows.append(r), cols.append(r), vals.append(1.0 + 4.0 * c0)
+            for k, g in enumerate(rhs_grids):
+                rhs[k][r] += g[j, i]
+            cx = D * bx[j, i] / (2 * h)
+            cy = D * by[j, i] / (2 * h)
+            for (ii, jj, coef) in ((i + 1, j, -c0 - cx), (i - 1, j, -c0 + cx),
+                                   (i, j + 1, -c0 - cy), (i, j - 1, -c0 + cy)):
+                if i0 < ii < i1 and j0 < jj < j1:
+                    rows.append(r), cols.append(idx(ii, jj)), vals.append(coef)
+                else:
+                    for k, g in enumerate(bc_grids):
+                        rhs[k][r] -= coef * g[jj, ii]
+    A = sp.csc_matrix((vals, (rows, cols)), shape=(n, n))
+    lu = spla.splu(A)
+    return [lu.solve(v).reshape(nj, ni) for v in rhs]
+
+
+def global_be_step(dens, t_w, D, N, xi_n, eta_n, bdry="identity"):
+    """One backward-Euler step on the whole grid."""
+    h = 1.0 / N
+    bx, by = _drift_grid(dens, t_w, N)
+    gx, gy = boundary_grid(N, bdry)
+    sx, sy = _be_solve_region(bx, by, D, h, 0, N, 0, N, [xi_n, eta_n], [gx, gy])
+    xi, eta = gx.copy(), gy.copy()
+    xi[1:N, 1:N], eta[1:N, 1:N] = sx, sy
+    return xi, eta
+
+
+def interface_index(px, m):
+    """Grid indices (i, j) of the interface nodes in canonical order (vertical
+    lines, then horizontal lines without the crossings), for N = px m."""
+    N = px * m
+    out = []
+    for a in range(1, px):
+        for j in range(1, N):
+            out.append((a * m, j))
+    for c in range(1, px):
+        for i in range(1, N):
+            if i % m == 0:
+                continue
+            out.append((i, c * m))
+    return np.array(out, dtype=np.int64)
+
+
+def subdomain_be_step(dens, t_w, D, px, m, xi_n, eta_n, iface_xi, iface_eta, bdry="identity"):
+    """Backward-Euler step on each of px x px sub-domains with the interface
+    values (canonical order) as Dirichlet data; returns the assembled grids."""
+    N = px * m
+    h = 1.0 / N
+    bx, by = _drift_grid(dens, t_w, N)
+    xi, eta = boundary_grid(N, bdry)
+    ij = interface_index(px, m)
+    xi[ij[:, 1], ij[:, 0]] = iface_xi
+    eta[ij[:, 1], ij[:, 0]] = iface_eta
+    for sj in range(px):
+        for si in range(px):
+            i0, i1, j0, j1 = si * m, (si + 1) * m, sj * m, (sj + 1) * m
+            sx, sy = _be_solve_region(bx, by, D, h, i0, i1, j0, j1, [xi_n, eta_n], [xi, eta])
+            xi[j0 + 1:j1, i0 + 1:i1], eta[j0 + 1:j1, i0 + 1:i1] = sx, sy
+    return xi, eta
+
+
+def mesh_quality(xi, eta):
+    """(min Jacobian, max skewness) over the cells of a mesh map (xi, eta).
+
+    Cell-centred differences: for the cell with lower-left node (i, j),
+    u_x = average of the two x-differences along its bottom and top edges
+    over h, u_y likewise; J = xi_x eta_y - xi_y eta_x;
+    skew = |grad xi . grad eta| / (|grad xi| |grad eta|).
+    """
+    N = xi.shape[0] - 1
+    h = 1.0 / N
+
+    def grads(u):
+        ux = ((u[:-1, 1:] - u[:-1, :-1]) + (u[1:, 1:] - u[1:, :-1])) / (2 * h)
+        uy = ((u[1:, :-1] - u[:-1, :-1]) + (u[1:, 1:] - u[:-1, 1:])) / (2 * h)
+        return ux, uy
+
+    xx, xy = grads(xi)
+    ex, ey = grads(eta)
+    J = xx * ey - xy * ex
+    skew = np.abs(xx * ex + xy * ey) / (np.hypot(xx, xy) * np.hypot(ex, ey))
+    return float(J.min()), float(skew.max())
