@@ -189,6 +189,40 @@ int fk_batch_replay(fk_batch_t b, hipStream_t stream);
 void fk_batch_destroy(fk_batch_t b);
 
 /*
+ * Deterministic sub-domain solves (Sect. 4): the unit square is split into
+ * px x px sub-domains of m x m cells on the nodal grid x = i/N, y = j/N,
+ * N = px m.  With the interface values as Dirichlet data, every sub-domain
+ * takes one backward-Euler step of length dt_mesh of the relaxed Winslow
+ * system (Sect. 2, eq. (3)), central differences, density frozen at t_w:
+ *   (u - u^n)/dt_mesh = Laplacian_h u + b . grad_h u,  b = -grad w / w.
+ * Each sub-domain system is solved by banded LU without pivoting, in FP64;
+ * xi and eta share the factorisation.  Requires |b| h / 2 < 1 (checked from
+ * the density's bound; FK_E_UNSUPPORTED otherwise) and m - 1 < 128.
+ *   xi_n, eta_n        device [(N+1)^2] FP64, row-major [j][i]: the mesh at t^n
+ *   iface_xi/eta       device FP64, interface nodes in canonical order
+ *                      (vertical lines x = a/px with y = j/N ascending, then
+ *                      horizontal lines without their crossings)
+ *   bdry_kind          FK_DATA_IDENTITY (xi = x, eta = y) or FK_DATA_ZERO on
+ *                      the outer boundary
+ *   xi_out, eta_out    device [(N+1)^2] FP64: the new mesh (boundary, interface
+ *                      and sub-domain interiors); must not alias xi_n / eta_n
+ *   workspace          device, subdomain_workspace_bytes(px, m) bytes, 256-B aligned
+ */
+size_t subdomain_workspace_bytes(int32_t px, int32_t m);
+int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px, int32_t m, int32_t bdry_kind,
+                    const double *xi_n, const double *eta_n, const double *iface_xi, const double *iface_eta,
+                    double *xi_out, double *eta_out, void *workspace, size_t workspace_bytes,
+                    hipStream_t stream);
+
+/*
+ * Mesh quality of a nodal map (xi, eta) on an (n+1)^2 grid: out[0] = minimum
+ * over cells of the Jacobian xi_x eta_y - xi_y eta_x, out[1] = maximum of the
+ * skewness |grad xi . grad eta| / (|grad xi| |grad eta|), both from
+ * cell-centred differences.  out is device FP64 [2].
+ */
+int fk_mesh_quality(const double *xi, const double *eta, int32_t n, double *out, hipStream_t stream);
+
+/*
  * Kernel timing.  While enabled (per calling thread), fk_interface_solve
  * records HIP events on its stream around the path kernel and around the
  * reduction kernel; fk_timing_last waits for the last recorded events and

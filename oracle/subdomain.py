@@ -101,7 +101,7 @@ def interface_index(px, m):
             if i % m == 0:
                 continue
             out.append((i, c * m))
-    return np.array(out, dtype=np.int64)
+    return np.array(out, dtype=np.int64).reshape(-1, 2)
 
 
 def subdomain_be_step(dens, t_w, D, px, m, xi_n, eta_n, iface_xi, iface_eta, bdry="identity"):

@@ -104,6 +104,13 @@ _lib.fk_batch_replay.argtypes = [_P, _P]
 _lib.fk_batch_replay.restype = ctypes.c_int
 _lib.fk_batch_destroy.argtypes = [_P]
 _lib.fk_batch_destroy.restype = None
+_lib.subdomain_workspace_bytes.argtypes = [ctypes.c_int32, ctypes.c_int32]
+_lib.subdomain_workspace_bytes.restype = ctypes.c_size_t
+_lib.subdomain_solve.argtypes = [ctypes.POINTER(fk_density), ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                 ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
+_lib.subdomain_solve.restype = ctypes.c_int
+_lib.fk_mesh_quality.argtypes = [_P, _P, ctypes.c_int32, _P, _P]
+_lib.fk_mesh_quality.restype = ctypes.c_int
 _lib.fk_timing_enable.argtypes = [ctypes.c_int]
 _lib.fk_timing_enable.restype = ctypes.c_int
 _lib.fk_timing_last.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -337,3 +344,36 @@ class FkBatch:
         import torch
         s = ctypes.c_void_p(stream.cuda_stream) if stream is not None else _stream(torch, self.device)
         _check(_lib.fk_batch_replay(self._h, s))
+
+
+def subdomain_workspace_bytes(px: int, m: int) -> int:
+    return int(_lib.subdomain_workspace_bytes(px, m))
+
+
+def subdomain_solve(density, t_w, dt_mesh, px, m, xi_n, eta_n, iface_xi, iface_eta, bdry_kind=0,
+                    out=None, workspace=None):
+    """Sub-domain backward-Euler solves (C: ``subdomain_solve``).  Grids are
+    device FP64 tensors [(px m + 1)^2] (or 2-D views); returns (xi, eta)."""
+    import torch
+    dev = xi_n.device
+    N1 = px * m + 1
+    if out is None:
+        out = (torch.empty((N1, N1), dtype=torch.float64, device=dev),
+               torch.empty((N1, N1), dtype=torch.float64, device=dev))
+    need = _lib.subdomain_workspace_bytes(px, m)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    _check(_lib.subdomain_solve(ctypes.byref(_density(density)), float(t_w), float(dt_mesh), int(px), int(m),
+                                int(bdry_kind), xi_n.data_ptr(), eta_n.data_ptr(), iface_xi.data_ptr(),
+                                iface_eta.data_ptr(), out[0].data_ptr(), out[1].data_ptr(), workspace.data_ptr(),
+                                workspace.numel(), _stream(torch, dev)))
+    return out
+
+
+def fk_mesh_quality(xi, eta):
+    """(min Jacobian, max skewness) device tensor [2] of a nodal map."""
+    import torch
+    n = int(round(xi.numel() ** 0.5)) - 1
+    out = torch.empty(2, dtype=torch.float64, device=xi.device)
+    _check(_lib.fk_mesh_quality(xi.data_ptr(), eta.data_ptr(), n, out.data_ptr(), _stream(torch, xi.device)))
+    return out

@@ -1,0 +1,408 @@
+// fk_subdomain.hip -- deterministic sub-domain solves (Sect. 4): with the
+// interface values from the stochastic solver as Dirichlet data, each
+// sub-domain takes one backward-Euler step of the relaxed Winslow system
+// (Sect. 2, eq. (3)) discretised by central differences,
+//
+//   (1 + 4c) u_P - (c + cx) u_E - (c - cx) u_W - (c + cy) u_N - (c - cy) u_S = u^n_P,
+//   c = D/h^2,  cx = D b_x / (2h),  cy = D b_y / (2h),  b = -grad w / w (eq. (6)),
+//
+// and the system is solved by LU factorisation without pivoting (strictly
+// diagonally dominant while |b| h / 2 < 1).  Plus the mesh-quality reduction.
+//
+// MI355X mapping: one workgroup per sub-domain.  With the q x q interior
+// unknowns in row-major order the matrix is banded with half-bandwidth
+// p = q, and the fill of the LU stays in the band; elimination step k only
+// touches rows and columns k..k+p.  That (p+1)^2 FP64 window lives in LDS
+// (74 KB for q = 95) and is indexed circularly, so each step slides it by one
+// row and one column: the new row and column enter with their original
+// stencil values (at most five non-zeros), computed on the fly.  Both
+// right-hand sides (xi and eta) are eliminated with the same multipliers.
+// Finished U rows go to the workspace; one wavefront then back-substitutes,
+// prefetching the next U row while it reduces the current one.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+
+#include "fk.h"
+#include "fk_internal.hpp"
+
+namespace fk {
+
+struct SubArgs {
+    const double *xi_n, *eta_n;  // previous mesh, (N+1)^2
+    double *xi_out, *eta_out;    // Dirichlet data pre-filled; interior written
+    double *ubuf;                // per sub-domain: n * (p+1) doubles
+    double *ybuf;                // per sub-domain: 2 n doubles
+    int N, m, px;
+    double c, half_d_over_h;     // D/h^2 and D/(2h)
+    int kind;
+    double amp, width2, cx, cy, orbit_r, omega, t_w;
+};
+
+// -grad w / w in FP64 at (x, y), density frozen at t_w.
+__device__ void drift_f64(const SubArgs &a, double x, double y, double &bx, double &by) {
+    const double A = a.amp, s2 = a.width2;
+    if (a.kind == FK_DENSITY_CONST) {
+        bx = 0.0;
+        by = 0.0;
+        return;
+    }
+    double ccx = a.cx, ccy = a.cy, ox = 0.0, oy = 0.0;
+    if (a.kind == FK_DENSITY_MOVING_BUMP || a.kind == FK_DENSITY_TWO_BUMPS) {
+        ox = a.orbit_r * cos(a.omega * a.t_w);
+        oy = a.orbit_r * sin(a.omega * a.t_w);
+    }
+    if (a.kind == FK_DENSITY_TWO_BUMPS) {
+        const double dy = y - (ccy + oy);
+        const double d1 = x - (ccx + ox), d2 = x - (ccx - ox);
+        const double e1 = exp(-(d1 * d1 + dy * dy) / s2), e2 = exp(-(d2 * d2 + dy * dy) / s2);
+        const double f = 2.0 * A / s2 / (1.0 + A * (e1 + e2));
+        bx = f * (e1 * d1 + e2 * d2);
+        by = f * (e1 + e2) * dy;
+        return;
+    }
+    const double dx = x - (ccx + ox);
+    const double dy = (a.kind == FK_DENSITY_RIDGE) ? 0.0 : y - (ccy + oy);
+    const double e = exp(-(dx * dx + dy * dy) / s2);
+    const double f = 2.0 * A / s2 * e / (1.0 + A * e);
+    bx = f * dx;
+    by = f * dy;
+}
+
+constexpr int kMaxP1 = 128;  // window side limit: q <= 127 interior nodes per side
+
+__global__ void __launch_bounds__(256) subdomain_be_kernel(const SubArgs a) {
+    extern __shared__ double lds[];
+    const int q = a.m - 1, p = q, P1 = p + 1, n = q * q;
+    const int si = blockIdx.x % a.px, sj = blockIdx.x / a.px;
+    const int i0 = si * a.m, j0 = sj * a.m;
+    const int N1 = a.N + 1;
+    const double h = 1.0 / a.N;
+    double *W = lds;                     // P1 x P1 window
+    double *rx = W + P1 * P1;            // rhs ring, xi
+    double *ry = rx + P1;                // rhs ring, eta
+    double *kx = ry + P1;                // cx of the rows in the window
+    double *ky = kx + P1;                // cy of the rows in the window
+    double *U = a.ubuf + (int64_t)blockIdx.x * n * P1;
+    double *Y = a.ybuf + (int64_t)blockIdx.x * 2 * n;
+    const int tid = threadIdx.x, nth = blockDim.x;
+
+    // Row r enters the window: its drift coefficients, its right-hand side
+    // with the Dirichlet neighbours moved over, and its lower entries (W, S)
+    // in window column coordinates relative to step k.
+    auto row_enter = [&](int r, int k) {
+        const int ii = r % q, jj = r / q;
+        const int gi = i0 + 1 + ii, gj = j0 + 1 + jj;
+        double bx, by;
+        drift_f64(a, gi * h, gj * h, bx, by);
+        const double cxr = a.half_d_over_h * bx, cyr = a.half_d_over_h * by;
+        const int s = r % P1;
+        kx[s] = cxr;
+        ky[s] = cyr;
+        const int64_t g = (int64_t)gj * N1 + gi;
+        double fx = a.xi_n[g], fy = a.eta_n[g];
+        const double cE = -a.c - cxr, cW = -a.c + cxr, cN = -a.c - cyr, cS = -a.c + cyr;
+        if (ii == q - 1) { fx -= cE * a.xi_out[g + 1]; fy -= cE * a.eta_out[g + 1]; }
+        if (ii == 0) { fx -= cW * a.xi_out[g - 1]; fy -= cW * a.eta_out[g - 1]; }
+        if (jj == q - 1) { fx -= cN * a.xi_out[g + N1]; fy -= cN * a.eta_out[g + N1]; }
+        if (jj == 0) { fx -= cS * a.xi_out[g - N1]; fy -= cS * a.eta_out[g - N1]; }
+        rx[s] = fx;
+        ry[s] = fy;
+        double *row = W + s * P1;
+        row[r % P1] = 1.0 + 4.0 * a.c;
+        if (ii > 0 && r - 1 >= k) row[(r - 1) % P1] = cW;
+        if (jj > 0 && r - q >= k) row[(r - q) % P1] = cS;
+    };
+
+    // ---- initial window: rows and columns 0..p ------------------------------
+    for (int e = tid; e < P1 * P1; e += nth) W[e] = 0.0;
+    __syncthreads();
+    for (int r = tid; r < P1 && r < n; r += nth) row_enter(r, 0);
+    __syncthreads();
+    // upper entries (E, N) of rows 0..p that fall inside the window
+    for (int r = tid; r < P1 && r < n; r += nth) {
+        const int ii = r % q, jj = r / q;
+        double *row = W + (r % P1) * P1;
+        if (ii < q - 1 && r + 1 <= p) row[(r + 1) % P1] = -a.c - kx[r % P1];
+        if (jj < q - 1 && r + q <= p) row[(r + q) % P1] = -a.c - ky[r % P1];
+    }
+    __syncthreads();
+
+    // ---- forward elimination ------------------------------------------------
+    for (int k = 0; k < n; ++k) {
+        const int s0 = k % P1;
+        const double *prow = W + s0 * P1;
+        const double inv = 1.0 / prow[s0];
+        const int span = min(p, n - 1 - k);  // rows/cols below and right of the pivot
+        // save the U row and the eliminated right-hand side of step k
+        for (int c = tid; c <= p; c += nth) U[(int64_t)k * P1 + c] = (c <= span) ? prow[(k + c) % P1] : 0.0;
+        if (tid == 0) {
+            Y[k] = rx[s0];
+            Y[n + k] = ry[s0];
+        }
+        // rank-1 update of the window, and the right-hand sides
+        const int tot = span * span;
+        for (int e = tid; e < tot; e += nth) {
+            const int r = 1 + e / span, c = 1 + e % span;
+            double *row = W + ((k + r) % P1) * P1;
+            const double l = row[s0] * inv;
+            row[(k + c) % P1] -= l * prow[(k + c) % P1];
+        }
+        for (int r = 1 + tid; r <= span; r += nth) {
+            const int s = (k + r) % P1;
+            const double l = W[s * P1 + s0] * inv;
+            rx[s] -= l * rx[s0];
+            ry[s] -= l * ry[s0];
+        }
+        __syncthreads();
+        // slide: slot s0 becomes row / column k + P1
+        const int R = k + P1;
+        if (R < n) {
+            for (int e = tid; e < P1; e += nth) {
+                W[s0 * P1 + e] = 0.0;   // the new row
+                W[e * P1 + s0] = 0.0;   // the new column
+            }
+            __syncthreads();
+            if (tid == 0) row_enter(R, k + 1);
+            if (tid == 1) {
+                // new column entries: E of row R-1, N of row R-q
+                const int r1 = R - 1, rq = R - q;
+                if (r1 % q < q - 1) W[(r1 % P1) * P1 + s0] = -a.c - kx[r1 % P1];
+                if (rq >= k + 1 && (rq / q) < q - 1) W[(rq % P1) * P1 + s0] = -a.c - ky[rq % P1];
+            }
+        }
+        __syncthreads();
+    }
+
+    // ---- back substitution (one wavefront) ----------------------------------
+    if (tid < 64) {
+        double *xw = W;            // x ring (xi), reuse of the window storage
+        double *yw = W + P1;       // x ring (eta)
+        const int lane = tid;
+        double u0 = 0.0, u1 = 0.0, ud = 1.0;
+        int k = n - 1;
+        // prefetch row n-1
+        if (k >= 0) {
+            u0 = (lane + 1 <= p) ? U[(int64_t)k * P1 + lane + 1] : 0.0;
+            u1 = (lane + 65 <= p) ? U[(int64_t)k * P1 + lane + 65] : 0.0;
+            ud = U[(int64_t)k * P1];
+        }
+        for (; k >= 0; --k) {
+            double n0 = 0.0, n1 = 0.0, nd = 1.0;
+            if (k > 0) {
+                n0 = (lane + 1 <= p) ? U[(int64_t)(k - 1) * P1 + lane + 1] : 0.0;
+                n1 = (lane + 65 <= p) ? U[(int64_t)(k - 1) * P1 + lane + 65] : 0.0;
+                nd = U[(int64_t)(k - 1) * P1];
+            }
+            double sx = 0.0, sy = 0.0;
+            if (lane + 1 <= p && k + lane + 1 < n) {
+                sx += u0 * xw[(k + lane + 1) % P1];
+                sy += u0 * yw[(k + lane + 1) % P1];
+            }
+            if (lane + 65 <= p && k + lane + 65 < n) {
+                sx += u1 * xw[(k + lane + 65) % P1];
+                sy += u1 * yw[(k + lane + 65) % P1];
+            }
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                sx += __shfl_xor(sx, off, 64);
+                sy += __shfl_xor(sy, off, 64);
+            }
+            const double xk = (Y[k] - sx) / ud, yk = (Y[n + k] - sy) / ud;
+            if (lane == 0) {
+                xw[k % P1] = xk;
+                yw[k % P1] = yk;
+                const int ii = k % q, jj = k / q;
+                const int64_t g = (int64_t)(j0 + 1 + jj) * N1 + (i0 + 1 + ii);
+                a.xi_out[g] = xk;
+                a.eta_out[g] = yk;
+            }
+            __builtin_amdgcn_wave_barrier();
+            u0 = n0;
+            u1 = n1;
+            ud = nd;
+        }
+    }
+}
+
+// Dirichlet data of the output grids: outer boundary and interface nodes.
+__global__ void dirichlet_kernel(const double *iface_xi, const double *iface_eta, int64_t n_iface, int N, int m,
+                                 int px, int bdry_kind, double *xi_out, double *eta_out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int N1 = N + 1;
+    const int64_t n_bd = 4 * (int64_t)N;
+    if (t < n_bd) {
+        // boundary nodes walked as four edges of N nodes each
+        const int side = (int)(t / N), o = (int)(t % N);
+        int i, j;
+        if (side == 0) { i = o; j = 0; }
+        else if (side == 1) { i = N; j = o; }
+        else if (side == 2) { i = N - o; j = N; }
+        else { i = 0; j = N - o; }
+        const int64_t g = (int64_t)j * N1 + i;
+        const bool ident = (bdry_kind == FK_DATA_IDENTITY);
+        xi_out[g] = ident ? (double)i / N : 0.0;
+        eta_out[g] = ident ? (double)j / N : 0.0;
+        return;
+    }
+    const int64_t f = t - n_bd;
+    if (f >= n_iface) return;
+    // canonical order: vertical lines x = a/px (nodes y = j/N), then
+    // horizontal lines y = c/px without the crossings
+    const int64_t nv = (int64_t)(px - 1) * (N - 1);
+    int i, j;
+    if (f < nv) {
+        i = (int)(f / (N - 1) + 1) * m;
+        j = (int)(f % (N - 1)) + 1;
+    } else {
+        const int64_t h = f - nv;
+        const int per = N - px;  // non-crossing nodes per horizontal line
+        const int c = (int)(h / per) + 1;
+        const int r = (int)(h % per);
+        i = r + 1 + r / (m - 1);
+        j = c * m;
+    }
+    const int64_t g = (int64_t)j * N1 + i;
+    xi_out[g] = iface_xi[f];
+    eta_out[g] = iface_eta[f];
+}
+
+// min Jacobian and max skewness over all cells (cell-centred differences).
+__global__ void __launch_bounds__(1024) quality_kernel(const double *xi, const double *eta, int n, double *out) {
+    const int N1 = n + 1;
+    const double inv2h = 0.5 * n;
+    double jmin = INFINITY, smax = 0.0;
+    const int64_t cells = (int64_t)n * n;
+    for (int64_t c = threadIdx.x; c < cells; c += blockDim.x) {
+        const int i = (int)(c % n), j = (int)(c / n);
+        const int64_t g = (int64_t)j * N1 + i;
+        const double a0 = xi[g], a1 = xi[g + 1], a2 = xi[g + N1], a3 = xi[g + N1 + 1];
+        const double b0 = eta[g], b1 = eta[g + 1], b2 = eta[g + N1], b3 = eta[g + N1 + 1];
+        const double xx = ((a1 - a0) + (a3 - a2)) * inv2h, xy = ((a2 - a0) + (a3 - a1)) * inv2h;
+        const double ex = ((b1 - b0) + (b3 - b2)) * inv2h, ey = ((b2 - b0) + (b3 - b1)) * inv2h;
+        const double J = xx * ey - xy * ex;
+        const double sk = fabs(xx * ex + xy * ey) / (sqrt(xx * xx + xy * xy) * sqrt(ex * ex + ey * ey));
+        jmin = fmin(jmin, J);
+        smax = fmax(smax, sk);
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        jmin = fmin(jmin, __shfl_xor(jmin, off, 64));
+        smax = fmax(smax, __shfl_xor(smax, off, 64));
+    }
+    __shared__ double pj[16], ps[16];
+    if ((threadIdx.x & 63) == 0) {
+        pj[threadIdx.x >> 6] = jmin;
+        ps[threadIdx.x >> 6] = smax;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+            jmin = fmin(jmin, pj[w]);
+            smax = fmax(smax, ps[w]);
+        }
+        out[0] = jmin;
+        out[1] = smax;
+    }
+}
+
+static size_t sub_ws_bytes(int px, int m) {
+    const size_t q = (size_t)m - 1, n = q * q, P1 = q + 1;
+    const size_t blocks = (size_t)px * px;
+    return align256(blocks * n * P1 * sizeof(double)) + align256(blocks * 2 * n * sizeof(double));
+}
+
+}  // namespace fk
+
+using namespace fk;
+
+extern "C" {
+
+size_t subdomain_workspace_bytes(int32_t px, int32_t m) {
+    if (px < 1 || m < 2 || m - 1 >= kMaxP1) return 0;
+    return sub_ws_bytes(px, m);
+}
+
+int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px, int32_t m, int32_t bdry_kind,
+                    const double *xi_n, const double *eta_n, const double *iface_xi, const double *iface_eta,
+                    double *xi_out, double *eta_out, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    int rc;
+    if ((rc = validate_density(w)) != FK_OK) return rc;
+    if (px < 1 || m < 2) return fail(FK_E_INVAL, "need px >= 1 and m >= 2");
+    if (m - 1 >= kMaxP1) return fail(FK_E_UNSUPPORTED, "sub-domain side m must be <= %d", kMaxP1);
+    if (!std::isfinite(t_w) || !std::isfinite(dt_mesh) || !(dt_mesh > 0.0))
+        return fail(FK_E_INVAL, "t_w must be finite and dt_mesh > 0");
+    if (bdry_kind != FK_DATA_IDENTITY && bdry_kind != FK_DATA_ZERO)
+        return fail(FK_E_INVAL, "outer boundary data must be FK_DATA_IDENTITY or FK_DATA_ZERO");
+    const int N = px * m;
+    const int64_t n_iface = 2 * (int64_t)(px - 1) * (N - 1) - (int64_t)(px - 1) * (px - 1);
+    if (!xi_n || !eta_n || !xi_out || !eta_out || (n_iface > 0 && (!iface_xi || !iface_eta)))
+        return fail(FK_E_INVAL, "NULL array");
+    const size_t need = sub_ws_bytes(px, m);
+    if (!workspace || workspace_bytes < need) return fail(FK_E_NOMEM, "workspace too small: need %zu bytes", need);
+    if (((uintptr_t)workspace & 255u) != 0) return fail(FK_E_INVAL, "workspace must be 256-byte aligned");
+    const double h = 1.0 / N;
+    // Diagonal dominance (LU without pivoting) needs |b| h / 2 < 1.  For one
+    // bump |b| = (2A/s2) r e / (1 + A e), e = exp(-r^2/s2), maximised over r
+    // on a fine sample; two bumps are bounded by twice that.
+    if (w->kind != FK_DENSITY_CONST) {
+        double bmax = 0.0;
+        const double A = std::fabs(w->amp), s2 = w->width2, rs = 4.0 * std::sqrt(s2);
+        for (int i = 1; i <= 4000; ++i) {
+            const double r = rs * i / 4000.0, e = std::exp(-r * r / s2);
+            bmax = std::max(bmax, 2.0 * A / s2 * r * e / (1.0 - (w->amp < 0 ? A : -A) * e));
+        }
+        if (w->kind == FK_DENSITY_TWO_BUMPS) bmax *= 2.0;
+        if (bmax * h / 2.0 >= 1.0) return fail(FK_E_UNSUPPORTED, "grid too coarse for the drift (|b| h / 2 >= 1)");
+    }
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(FK_E_NODEVICE, "no HIP device: %s", hipGetErrorString(e));
+
+    const int64_t nthr = 4 * (int64_t)N + n_iface;
+    hipLaunchKernelGGL(dirichlet_kernel, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, stream, iface_xi,
+                       iface_eta, n_iface, N, m, px, (int)bdry_kind, xi_out, eta_out);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "dirichlet kernel launch");
+
+    SubArgs a{};
+    a.xi_n = xi_n;
+    a.eta_n = eta_n;
+    a.xi_out = xi_out;
+    a.eta_out = eta_out;
+    const size_t q = (size_t)m - 1, n = q * q, P1 = q + 1;
+    a.ubuf = (double *)workspace;
+    a.ybuf = (double *)((char *)workspace + align256((size_t)px * px * n * P1 * sizeof(double)));
+    a.N = N;
+    a.m = m;
+    a.px = px;
+    a.c = dt_mesh / (h * h);
+    a.half_d_over_h = dt_mesh / (2.0 * h);
+    a.kind = w->kind;
+    a.amp = w->amp;
+    a.width2 = w->width2;
+    a.cx = w->cx;
+    a.cy = w->cy;
+    a.orbit_r = w->orbit_r;
+    a.omega = w->omega;
+    a.t_w = t_w;
+    const size_t lds = (P1 * P1 + 4 * P1) * sizeof(double);
+    if ((e = hipFuncSetAttribute((const void *)subdomain_be_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds)) != hipSuccess)
+        return hip_fail(e, "hipFuncSetAttribute (LDS)");
+    hipLaunchKernelGGL(subdomain_be_kernel, dim3((unsigned)(px * px)), dim3(256), lds, stream, a);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "sub-domain kernel launch");
+    return FK_OK;
+}
+
+int fk_mesh_quality(const double *xi, const double *eta, int32_t n, double *out, hipStream_t stream) {
+    g_last_error.clear();
+    if (n < 1 || !xi || !eta || !out) return fail(FK_E_INVAL, "need n >= 1 and non-NULL arrays");
+    hipLaunchKernelGGL(quality_kernel, dim3(1), dim3(1024), 0, stream, xi, eta, n, out);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FK_OK : hip_fail(e, "quality kernel launch");
+}
+
+}  // extern "C"
