@@ -67,6 +67,17 @@ def lib():
                                   ctypes.c_double, ctypes.c_double, ctypes.c_uint64,
                                   ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int, P, P]
         L.or_fk_paths.restype = ctypes.c_int
+        L.or_mlp_eval.argtypes = [P, ctypes.c_double, P, ctypes.c_int64, P]
+        L.or_mlp_eval.restype = ctypes.c_int
+        L.or_fk_solve_cv.argtypes = [ctypes.c_int, ctypes.c_int, P,
+                                     ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
+                                     P, P, ctypes.c_int,
+                                     P, P, ctypes.c_int64,
+                                     ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64,
+                                     ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
+                                     ctypes.c_int, P, ctypes.c_double, ctypes.c_int,
+                                     P, P, P, P, P, P]
+        L.or_fk_solve_cv.restype = ctypes.c_int
         L.or_fd_solve.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, ctypes.c_int,
                                   ctypes.c_double, ctypes.c_double, ctypes.c_int, ctypes.c_double,
                                   P, P, ctypes.c_int, P, P]
@@ -172,6 +183,52 @@ def fk_paths(dens, data, pts, node_ids, path_ids, t, dt, seed=0, level_id=0, str
     if rc != 0:
         raise ValueError("oracle rejected its arguments")
     return sc, ex
+
+
+UHAT_MLP, UHAT_LINEAR, UHAT_SIN, UHAT_ZERO = 0, 1, 2, 3
+
+
+def mlp_eval_c(flat, t_scale, txy) -> np.ndarray:
+    """The C oracle's forward-mode MLP: [n, 2, 5] (value, dx, dy, dt, lap)."""
+    flat = np.ascontiguousarray(flat, dtype=np.float64)
+    txy = np.ascontiguousarray(txy, dtype=np.float64).reshape(-1, 3)
+    out = np.zeros((txy.shape[0], 2, 5))
+    lib().or_mlp_eval(_ptr(flat), t_scale, _ptr(txy), txy.shape[0], _ptr(out))
+    return out
+
+
+def fk_solve_cv(dens, data, pts, t, dt, n_paths, seed=0, level_id=0, stream=0, node_ids=None,
+                uhat=UHAT_MLP, flat=None, t_scale=0.1, stride=1, want_scores=False, want_exit=False, threads=0):
+    """Control-variate oracle (Dynkin form).  Returns dict: mean/se (CV),
+    plain_mean/plain_se (same paths), optional cv_scores [n,N,2], exit_step."""
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 2)
+    n = pts.shape[0]
+    par = dens.params()
+    out = {k: np.zeros((n, 2)) for k in ("mean", "se", "plain_mean", "plain_se")}
+    cs = np.zeros((n, n_paths, 2)) if want_scores else None
+    ex = np.zeros((n, n_paths), dtype=np.int32) if want_exit else None
+    ids = None if node_ids is None else np.ascontiguousarray(node_ids, dtype=np.int64)
+    fl = None if flat is None else np.ascontiguousarray(flat, dtype=np.float64)
+    gx = gy = None
+    gn = 0
+    if data.grid_xi is not None:
+        gx = np.ascontiguousarray(data.grid_xi, dtype=np.float64)
+        gy = np.ascontiguousarray(data.grid_eta, dtype=np.float64)
+        gn = data.grid_n
+    rc = lib().or_fk_solve_cv(dens.kind, dens.time_mode, _ptr(par),
+                              data.init_kind, data.bdry_kind, data.score_mode, data.t_init,
+                              _ptr(gx), _ptr(gy), gn, _ptr(pts), _ptr(ids), n,
+                              t, dt, n_paths, seed, level_id, stream, threads,
+                              uhat, _ptr(fl), t_scale, stride,
+                              _ptr(out["mean"]), _ptr(out["se"]), _ptr(out["plain_mean"]), _ptr(out["plain_se"]),
+                              _ptr(cs), _ptr(ex))
+    if rc != 0:
+        raise ValueError("oracle rejected its arguments")
+    if want_scores:
+        out["cv_scores"] = cs
+    if want_exit:
+        out["exit_step"] = ex
+    return out
 
 
 def fd_solve(dens, data, t, n, dtau, threads=0):

@@ -432,3 +432,259 @@ int or_fk_paths(int kind, int time_mode, const double *par,
     }
     return 0;
 }
+
+/* ---------------------------------------------------------------------------
+ * Control-variate (Dynkin-form) estimator.  For a smooth function
+ * u_hat(tau, X) of PDE time and position, V(s, X) = u_hat(t_init + t - s, X)
+ * satisfies, along the diffusion, E[V(end)] = V(0, P) + E[integral of
+ * (L u_hat - d_tau u_hat) ds], L = Laplacian + b . grad.  So
+ *
+ *   u(P) = u_hat(t_init + t, P) + E[ score - u_hat(tau_end, X_end)
+ *                                    + sum_j r(tau_j, X_j) (s_{j+1} - s_j) ],
+ *
+ * with r = Laplacian u_hat + b . grad u_hat - d_tau u_hat evaluated at the
+ * pre-step state of every stride-th Euler-Maruyama step (left-point rule;
+ * the last interval ends at the path's end).  This is the reading of the
+ * exact control-variate estimator this build uses; the same paths also give
+ * the plain estimate.
+ *
+ * u_hat kinds: 0 the tanh MLP 3-64-64-64-2 (flat FP64 parameters, input
+ * z = (2 tau / T - 1, 2x - 1, 2y - 1)); 1 the linear maps (x, y); 2 the
+ * decaying sine mode exp(-2 pi^2 (tau - t_init)) sin(pi x) sin(pi y) for
+ * both components; 3 zero.
+ * ------------------------------------------------------------------------- */
+typedef struct {
+    const double *W1, *b1, *W2, *b2, *W3, *b3, *W4, *b4;
+    double t_scale;
+} or_mlp;
+
+static void mlp_bind(or_mlp *m, const double *flat, double t_scale)
+{
+    m->W1 = flat;
+    m->b1 = m->W1 + 64 * 3;
+    m->W2 = m->b1 + 64;
+    m->b2 = m->W2 + 64 * 64;
+    m->W3 = m->b2 + 64;
+    m->b3 = m->W3 + 64 * 64;
+    m->W4 = m->b3 + 64;
+    m->b4 = m->W4 + 2 * 64;
+    m->t_scale = t_scale;
+}
+
+/* out[c][0..4] = value, d/dx, d/dy, d/dtau, Laplacian of output c. */
+static void mlp_forward_mode(const or_mlp *m, double tau, double x, double y, double out[2][5])
+{
+    double z0 = 2.0 * tau / m->t_scale - 1.0, z1 = 2.0 * x - 1.0, z2 = 2.0 * y - 1.0;
+    /* channels: 0 value, 1 d/dx, 2 d/dy, 3 d/dtau, 4 Laplacian */
+    double h[5][64], a[5][64];
+    for (int j = 0; j < 64; ++j) {
+        const double *w = m->W1 + 3 * j;
+        a[0][j] = w[0] * z0 + w[1] * z1 + w[2] * z2 + m->b1[j];
+        a[1][j] = 2.0 * w[1];
+        a[2][j] = 2.0 * w[2];
+        a[3][j] = 2.0 / m->t_scale * w[0];
+        a[4][j] = 0.0;
+    }
+    const double *Ws[2] = {m->W2, m->W3}, *bs[2] = {m->b2, m->b3};
+    for (int layer = 0; layer < 3; ++layer) {
+        if (layer > 0) {
+            const double *W = Ws[layer - 1], *b = bs[layer - 1];
+            for (int j = 0; j < 64; ++j) {
+                double acc[5] = {b[j], 0.0, 0.0, 0.0, 0.0};
+                for (int k = 0; k < 64; ++k)
+                    for (int c = 0; c < 5; ++c) acc[c] += W[64 * j + k] * h[c][k];
+                for (int c = 0; c < 5; ++c) a[c][j] = acc[c];
+            }
+        }
+        for (int j = 0; j < 64; ++j) {
+            double v = tanh(a[0][j]), s = 1.0 - v * v;
+            h[0][j] = v;
+            h[1][j] = s * a[1][j];
+            h[2][j] = s * a[2][j];
+            h[3][j] = s * a[3][j];
+            h[4][j] = -2.0 * v * s * (a[1][j] * a[1][j] + a[2][j] * a[2][j]) + s * a[4][j];
+        }
+    }
+    for (int o = 0; o < 2; ++o)
+        for (int c = 0; c < 5; ++c) {
+            double acc = (c == 0) ? m->b4[o] : 0.0;
+            for (int k = 0; k < 64; ++k) acc += m->W4[64 * o + k] * h[c][k];
+            out[o][c] = acc;
+        }
+}
+
+int or_mlp_eval(const double *flat, double t_scale, const double *txy, int64_t n, double *out)
+{
+    or_mlp m;
+    mlp_bind(&m, flat, t_scale);
+    for (int64_t i = 0; i < n; ++i) {
+        double o[2][5];
+        mlp_forward_mode(&m, txy[3 * i], txy[3 * i + 1], txy[3 * i + 2], o);
+        for (int c = 0; c < 2; ++c)
+            for (int k = 0; k < 5; ++k) out[10 * i + 5 * c + k] = o[c][k];
+    }
+    return 0;
+}
+
+typedef struct {
+    int kind;
+    or_mlp mlp;
+    double t_init;
+} or_uhat;
+
+static void uhat_eval(const or_uhat *u, double tau, double x, double y, double out[2][5])
+{
+    switch (u->kind) {
+    case 0: mlp_forward_mode(&u->mlp, tau, x, y, out); return;
+    case 1:
+        out[0][0] = x; out[0][1] = 1.0; out[0][2] = 0.0; out[0][3] = 0.0; out[0][4] = 0.0;
+        out[1][0] = y; out[1][1] = 0.0; out[1][2] = 1.0; out[1][3] = 0.0; out[1][4] = 0.0;
+        return;
+    case 2: {
+        double e = exp(-2.0 * OR_PI * OR_PI * (tau - u->t_init));
+        double sx = sin(OR_PI * x), sy = sin(OR_PI * y), cx = cos(OR_PI * x), cy = cos(OR_PI * y);
+        for (int c = 0; c < 2; ++c) {
+            out[c][0] = e * sx * sy;
+            out[c][1] = e * OR_PI * cx * sy;
+            out[c][2] = e * OR_PI * sx * cy;
+            out[c][3] = -2.0 * OR_PI * OR_PI * e * sx * sy;
+            out[c][4] = -2.0 * OR_PI * OR_PI * e * sx * sy;
+        }
+        return;
+    }
+    default:
+        for (int c = 0; c < 2; ++c)
+            for (int k = 0; k < 5; ++k) out[c][k] = 0.0;
+        return;
+    }
+}
+
+/* One path with the control variate; returns the exit step (-1 survived). */
+static int64_t run_path_cv(const or_problem *pb, const or_uhat *u, int stride, double px, double py,
+                           uint32_t path, uint32_t node, double plain[2], double cv[2])
+{
+    double x = px, y = py, s = 0.0;
+    uint32_t r[4] = {0, 0, 0, 0};
+    double integ[2] = {0.0, 0.0}, rlast[2] = {0.0, 0.0}, s_last = 0.0;
+    int64_t exit_k = -1;
+    for (int64_t k = 0; k < pb->K; ++k) {
+        if ((k & 1) == 0) {
+            uint32_t ctr[4] = {(uint32_t)(k >> 1), path, node, pb->ctr3};
+            or_philox4x32_10(ctr, pb->key, r);
+        }
+        double z0, z1;
+        if ((k & 1) == 0) box_muller(r[0], r[1], &z0, &z1);
+        else box_muller(r[2], r[3], &z0, &z1);
+        double D = (k == pb->K - 1) ? pb->t - (double)(pb->K - 1) * pb->dt : pb->dt;
+        double tau = (pb->time_mode == 0) ? pb->t_init + pb->t - s : pb->par[6];
+        double bx, by;
+        drift(pb->kind, pb->par, tau, x, y, &bx, &by);
+        if (k % stride == 0) {
+            /* close the previous interval, open a new one at this state */
+            integ[0] += rlast[0] * (s - s_last);
+            integ[1] += rlast[1] * (s - s_last);
+            double e[2][5];
+            uhat_eval(u, pb->t_init + pb->t - s, x, y, e);
+            for (int c = 0; c < 2; ++c) rlast[c] = e[c][4] + bx * e[c][1] + by * e[c][2] - e[c][3];
+            s_last = s;
+        }
+        double sd = sqrt(2.0 * D);
+        x = x + bx * D + sd * z0;
+        y = y + by * D + sd * z1;
+        s = s + D;
+        if (x < 0.0 || x > 1.0 || y < 0.0 || y > 1.0) {
+            boundary_value(&pb->data, pb->t - s, x, y, &plain[0], &plain[1]);
+            exit_k = k + 1;
+            break;
+        }
+    }
+    if (exit_k < 0) initial_value(&pb->data, x, y, &plain[0], &plain[1]);
+    integ[0] += rlast[0] * (s - s_last);
+    integ[1] += rlast[1] * (s - s_last);
+    double e[2][5];
+    uhat_eval(u, pb->t_init + pb->t - s, x, y, e);
+    cv[0] = plain[0] - e[0][0] + integ[0];
+    cv[1] = plain[1] - e[1][0] + integ[1];
+    return exit_k;
+}
+
+static void two_pass(const double *sc, int64_t i, int64_t n_paths, double *mean, double *se)
+{
+    for (int c = 0; c < 2; ++c) {
+        double sum = 0.0;
+        for (int64_t p = 0; p < n_paths; ++p) sum += sc[2 * (i * n_paths + p) + c];
+        double m = sum / (double)n_paths, ss = 0.0;
+        for (int64_t p = 0; p < n_paths; ++p) {
+            double d = sc[2 * (i * n_paths + p) + c] - m;
+            ss += d * d;
+        }
+        mean[2 * i + c] = m;
+        se[2 * i + c] = sqrt(ss / (double)(n_paths - 1) / (double)n_paths);
+    }
+}
+
+/*
+ * Control-variate solve.  mean/se: the CV estimate u_hat(t_init + t, P) +
+ * mean(cv score) and its standard error; plain_mean/plain_se: the plain
+ * estimate from the same paths.  cv_scores [n][N][2] and exit_step [n][N]
+ * optional.
+ */
+int or_fk_solve_cv(int kind, int time_mode, const double *par,
+                   int init_kind, int bdry_kind, int score_mode, double t_init,
+                   const double *grid_xi, const double *grid_eta, int grid_n,
+                   const double *pts, const int64_t *node_ids, int64_t n_nodes,
+                   double t, double dt, int64_t n_paths, uint64_t seed, uint32_t level_id,
+                   uint32_t stream, int n_threads,
+                   int uhat_kind, const double *flat, double t_scale, int stride,
+                   double *mean, double *se, double *plain_mean, double *plain_se,
+                   double *cv_scores, int32_t *exit_step)
+{
+    if (n_nodes < 0 || n_paths < 2 || !(dt > 0.0) || !(t >= 0.0) || stride < 1) return -1;
+    if (uhat_kind == 0 && !flat) return -1;
+    or_problem pb;
+    pb.kind = kind;
+    pb.time_mode = time_mode;
+    pb.par = par;
+    pb.data.init_kind = init_kind;
+    pb.data.bdry_kind = bdry_kind;
+    pb.data.score_mode = score_mode;
+    pb.data.grid_xi = grid_xi;
+    pb.data.grid_eta = grid_eta;
+    pb.data.grid_n = grid_n;
+    pb.t_init = t_init;
+    pb.t = t;
+    pb.dt = dt;
+    pb.K = n_steps(t, dt);
+    pb.key[0] = (uint32_t)seed;
+    pb.key[1] = (uint32_t)(seed >> 32);
+    pb.ctr3 = (level_id << 4) | (stream & 15u);
+    or_uhat u;
+    u.kind = uhat_kind;
+    u.t_init = t_init;
+    if (uhat_kind == 0) mlp_bind(&u.mlp, flat, t_scale);
+    const int64_t total = n_nodes * n_paths;
+    double *pl = (double *)malloc(sizeof(double) * 2 * (size_t)(total > 0 ? total : 1));
+    double *cs = cv_scores ? cv_scores : (double *)malloc(sizeof(double) * 2 * (size_t)(total > 0 ? total : 1));
+    if (!pl || !cs) { free(pl); if (!cv_scores) free(cs); return -1; }
+#ifdef _OPENMP
+    if (n_threads > 0) omp_set_num_threads(n_threads);
+#pragma omp parallel for schedule(dynamic, 16)
+#endif
+    for (int64_t g = 0; g < total; ++g) {
+        int64_t i = g / n_paths, p = g % n_paths;
+        uint32_t nid = (uint32_t)(node_ids ? node_ids[i] : i);
+        int64_t e = run_path_cv(&pb, &u, stride, pts[2 * i], pts[2 * i + 1], (uint32_t)p, nid, &pl[2 * g], &cs[2 * g]);
+        if (exit_step) exit_step[g] = (int32_t)e;
+    }
+    for (int64_t i = 0; i < n_nodes; ++i) {
+        two_pass(pl, i, n_paths, plain_mean, plain_se);
+        two_pass(cs, i, n_paths, mean, se);
+        double e[2][5];
+        uhat_eval(&u, t_init + t, pts[2 * i], pts[2 * i + 1], e);
+        mean[2 * i] += e[0][0];
+        mean[2 * i + 1] += e[1][0];
+    }
+    free(pl);
+    if (!cv_scores) free(cs);
+    return 0;
+}

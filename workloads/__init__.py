@@ -186,3 +186,31 @@ def uniform_points(n: int, seed: int, lo: float = 0.02, hi: float = 0.98) -> np.
     """n seeded uniform points inside the unit square (parity tests)."""
     rng = np.random.default_rng(seed)
     return rng.uniform(lo, hi, size=(n, 2))
+
+
+# ---------------------------------------------------------------------------
+# Control-variate network inputs: initial weights and the training set.
+# ---------------------------------------------------------------------------
+MLP_SHAPES = [(64, 3), (64,), (64, 64), (64,), (64, 64), (64,), (2, 64), (2,)]
+MLP_N_PARAMS = 8706
+CV_T_SCALE = 0.1     # network time input z0 = 2 t / T - 1 over [0, T]
+
+
+def mlp_init(seed: int = 0) -> np.ndarray:
+    """Flat initial parameters: Glorot-uniform weights, zero biases (FP32 values)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for shape in MLP_SHAPES:
+        if len(shape) == 2:
+            a = math.sqrt(6.0 / (shape[0] + shape[1]))
+            out.append(rng.uniform(-a, a, size=shape).astype(np.float32).ravel())
+        else:
+            out.append(np.zeros(shape, dtype=np.float32))
+    flat = np.concatenate(out)
+    assert flat.size == MLP_N_PARAMS
+    return flat
+
+
+def cv_label_levels(n_levels: int = 132, t_max: float = 0.1):
+    """Time levels t_m = t_max m / (n_levels - 1), m = 0..n_levels-1, of the training labels."""
+    return [t_max * m / (n_levels - 1) for m in range(n_levels)]
