@@ -223,6 +223,62 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
 int fk_mesh_quality(const double *xi, const double *eta, int32_t n, double *out, hipStream_t stream);
 
 /*
+ * Learned control variate.  A tanh MLP u_hat(t, x, y) -> (xi_hat, eta_hat),
+ * 3 -> 64 -> 64 -> 64 -> 2 with linear outputs, on the normalised input
+ * z = (2 t / t_scale - 1, 2 x - 1, 2 y - 1).  Parameters (8706 FP32, in the
+ * order W1[64][3] b1[64] W2[64][64] b2[64] W3[64][64] b3[64] W4[2][64] b4[2],
+ * row-major) are kept as FP32 master weights with Adam moments; every kernel
+ * uses their BF16 rounding ("the network").  Training and evaluation run on
+ * BF16 MFMA with FP32 accumulation.  Handles own device memory (freed by
+ * fk_cv_destroy); create/get/set synchronise the device.
+ */
+typedef struct fk_cv *fk_cv_t;
+#define FK_CV_N_PARAMS 8706
+
+int fk_cv_create(const float *params /* host [8706] */, double t_scale, fk_cv_t *out);
+void fk_cv_destroy(fk_cv_t cv);
+/* params: host [8706] FP32 master weights or NULL; bf16_params: host [8706]
+ * BF16 bit patterns of the network or NULL. */
+int fk_cv_get_params(fk_cv_t cv, float *params, uint16_t *bf16_params);
+int fk_cv_set_params(fk_cv_t cv, const float *params /* host [8706] */);
+/* Forward-mode evaluation at n points txy (device [n][3]: t, x, y):
+ * out (device [n][2][5]) = for each output: value, d/dx, d/dy, d/dt,
+ * Laplacian in (x, y). */
+int fk_cv_eval(fk_cv_t cv, const float *txy, int64_t n, float *out, hipStream_t stream);
+/* Gradient of the mean-squared error over all n samples (device txy [n][3],
+ * target [n][2]) at the current network: grad device [8706], loss device [1]
+ * (mean over samples and both outputs) or NULL.  Parity hook. */
+int fk_cv_grad(fk_cv_t cv, const float *txy, const float *target, int64_t n, float *grad, float *loss,
+               hipStream_t stream);
+/* One Adam step (lr; beta = 0.9, 0.999; eps = 1e-8; bias-corrected) with a
+ * given gradient (device [8706]).  Parity hook. */
+int fk_cv_adam_apply(fk_cv_t cv, const float *grad, float lr, hipStream_t stream);
+/* `steps` Adam steps on minibatches of `batch` samples drawn with
+ * Philox4x32-10 (key = seed, counter (j, step, 0, 2)) modulo n; loss_out
+ * (device [steps] or NULL) receives each step's minibatch loss. */
+int fk_cv_train(fk_cv_t cv, const float *txy, const float *target, int64_t n, int32_t steps, int32_t batch, float lr,
+                uint64_t seed, float *loss_out, hipStream_t stream);
+
+/*
+ * Control-variate interface solve: the paths of fk_interface_solve (same
+ * counters), each scored with the Dynkin-form estimator
+ *   u(P) = u_hat(t_init + t, P) + E[ g - u_hat(tau_end, X_end) + sum_j r_j ds_j ],
+ *   r = Laplacian u_hat + b . grad u_hat - d_t u_hat,
+ * r taken at the path state every `stride` steps (even, >= 2) and at the
+ * path's end, integrated by the trapezoidal rule between those points.  xi/eta/se_*: the CV estimate;
+ * plain_*: the plain estimate from the same paths (all four or none);
+ * exit_step and cv_scores (device [n][N][2], g - u_hat(end) + sum r ds) optional.
+ * workspace: fk_interface_cv_workspace_bytes(n_nodes, n_paths).
+ */
+size_t fk_interface_cv_workspace_bytes(int64_t n_nodes, int64_t n_paths);
+int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *pts, int64_t n_nodes, double t,
+                          double dt, int64_t n_paths, uint64_t seed, uint32_t level_id, fk_cv_t cv, int32_t stride,
+                          double *xi, double *eta, double *se_xi, double *se_eta, double *plain_xi,
+                          double *plain_eta, double *plain_se_xi, double *plain_se_eta, int32_t *exit_step,
+                          float *cv_scores, uint64_t *total_steps, const fk_plan *plan, void *workspace,
+                          size_t workspace_bytes, hipStream_t stream);
+
+/*
  * Kernel timing.  While enabled (per calling thread), fk_interface_solve
  * records HIP events on its stream around the path kernel and around the
  * reduction kernel; fk_timing_last waits for the last recorded events and

@@ -443,10 +443,12 @@ int or_fk_paths(int kind, int time_mode, const double *par,
  *                                    + sum_j r(tau_j, X_j) (s_{j+1} - s_j) ],
  *
  * with r = Laplacian u_hat + b . grad u_hat - d_tau u_hat evaluated at the
- * pre-step state of every stride-th Euler-Maruyama step (left-point rule;
- * the last interval ends at the path's end).  This is the reading of the
- * exact control-variate estimator this build uses; the same paths also give
- * the plain estimate.
+ * pre-step state of every stride-th Euler-Maruyama step and at the path's
+ * end, the time integral taken by the trapezoidal rule between consecutive
+ * evaluation points (the left-point rule biases the estimate by
+ * O(stride dt); the trapezoidal rule by O((stride dt)^2)).  This is the
+ * reading of the exact control-variate estimator this build uses; the same
+ * paths also give the plain estimate.
  *
  * u_hat kinds: 0 the tanh MLP 3-64-64-64-2 (flat FP64 parameters, input
  * z = (2 tau / T - 1, 2x - 1, 2y - 1)); 1 the linear maps (x, y); 2 the
@@ -580,12 +582,14 @@ static int64_t run_path_cv(const or_problem *pb, const or_uhat *u, int stride, d
         double bx, by;
         drift(pb->kind, pb->par, tau, x, y, &bx, &by);
         if (k % stride == 0) {
-            /* close the previous interval, open a new one at this state */
-            integ[0] += rlast[0] * (s - s_last);
-            integ[1] += rlast[1] * (s - s_last);
+            /* close the previous interval (trapezoidal rule), open a new one */
             double e[2][5];
             uhat_eval(u, pb->t_init + pb->t - s, x, y, e);
-            for (int c = 0; c < 2; ++c) rlast[c] = e[c][4] + bx * e[c][1] + by * e[c][2] - e[c][3];
+            for (int c = 0; c < 2; ++c) {
+                double rn = e[c][4] + bx * e[c][1] + by * e[c][2] - e[c][3];
+                integ[c] += 0.5 * (rlast[c] + rn) * (s - s_last);
+                rlast[c] = rn;
+            }
             s_last = s;
         }
         double sd = sqrt(2.0 * D);
@@ -599,10 +603,16 @@ static int64_t run_path_cv(const or_problem *pb, const or_uhat *u, int stride, d
         }
     }
     if (exit_k < 0) initial_value(&pb->data, x, y, &plain[0], &plain[1]);
-    integ[0] += rlast[0] * (s - s_last);
-    integ[1] += rlast[1] * (s - s_last);
+    /* end point: u_hat there, and the integrand closing the last interval */
     double e[2][5];
-    uhat_eval(u, pb->t_init + pb->t - s, x, y, e);
+    const double tau_end = pb->t_init + pb->t - s;
+    uhat_eval(u, tau_end, x, y, e);
+    double bx, by;
+    drift(pb->kind, pb->par, (pb->time_mode == 0) ? tau_end : pb->par[6], x, y, &bx, &by);
+    for (int c = 0; c < 2; ++c) {
+        double rn = e[c][4] + bx * e[c][1] + by * e[c][2] - e[c][3];
+        integ[c] += 0.5 * (rlast[c] + rn) * (s - s_last);
+    }
     cv[0] = plain[0] - e[0][0] + integ[0];
     cv[1] = plain[1] - e[1][0] + integ[1];
     return exit_k;

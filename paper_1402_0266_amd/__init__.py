@@ -111,6 +111,30 @@ _lib.subdomain_solve.argtypes = [ctypes.POINTER(fk_density), ctypes.c_double, ct
 _lib.subdomain_solve.restype = ctypes.c_int
 _lib.fk_mesh_quality.argtypes = [_P, _P, ctypes.c_int32, _P, _P]
 _lib.fk_mesh_quality.restype = ctypes.c_int
+_lib.fk_cv_create.argtypes = [_P, ctypes.c_double, ctypes.POINTER(_P)]
+_lib.fk_cv_create.restype = ctypes.c_int
+_lib.fk_cv_destroy.argtypes = [_P]
+_lib.fk_cv_destroy.restype = None
+_lib.fk_cv_get_params.argtypes = [_P, _P, _P]
+_lib.fk_cv_get_params.restype = ctypes.c_int
+_lib.fk_cv_set_params.argtypes = [_P, _P]
+_lib.fk_cv_set_params.restype = ctypes.c_int
+_lib.fk_cv_eval.argtypes = [_P, _P, ctypes.c_int64, _P, _P]
+_lib.fk_cv_eval.restype = ctypes.c_int
+_lib.fk_cv_grad.argtypes = [_P, _P, _P, ctypes.c_int64, _P, _P, _P]
+_lib.fk_cv_grad.restype = ctypes.c_int
+_lib.fk_cv_adam_apply.argtypes = [_P, _P, ctypes.c_float, _P]
+_lib.fk_cv_adam_apply.restype = ctypes.c_int
+_lib.fk_cv_train.argtypes = [_P, _P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_float,
+                             ctypes.c_uint64, _P, _P]
+_lib.fk_cv_train.restype = ctypes.c_int
+_lib.fk_interface_cv_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64]
+_lib.fk_interface_cv_workspace_bytes.restype = ctypes.c_size_t
+_lib.fk_interface_solve_cv.argtypes = [
+    ctypes.POINTER(fk_density), ctypes.POINTER(fk_data), _P, ctypes.c_int64,
+    ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32, _P, ctypes.c_int32,
+    _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(fk_plan), _P, ctypes.c_size_t, _P]
+_lib.fk_interface_solve_cv.restype = ctypes.c_int
 _lib.fk_timing_enable.argtypes = [ctypes.c_int]
 _lib.fk_timing_enable.restype = ctypes.c_int
 _lib.fk_timing_last.argtypes = [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
@@ -288,9 +312,9 @@ class FkBatch:
                                      device=self.device)
 
     def close(self):
-        if getattr(self, "_h", None):
+        if getattr(self, "_h", None) and _lib is not None:
             _lib.fk_batch_destroy(self._h)
-            self._h = None
+        self._h = None
 
     def __del__(self):
         self.close()
@@ -376,4 +400,106 @@ def fk_mesh_quality(xi, eta):
     n = int(round(xi.numel() ** 0.5)) - 1
     out = torch.empty(2, dtype=torch.float64, device=xi.device)
     _check(_lib.fk_mesh_quality(xi.data_ptr(), eta.data_ptr(), n, out.data_ptr(), _stream(torch, xi.device)))
+    return out
+
+
+FK_CV_N_PARAMS = 8706
+
+
+class FkCv:
+    """The control-variate network (C: ``fk_cv_*``)."""
+
+    def __init__(self, params, t_scale=0.1):
+        p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        if p.size != FK_CV_N_PARAMS:
+            raise ValueError("need 8706 parameters")
+        h = ctypes.c_void_p()
+        _check(_lib.fk_cv_create(p.ctypes.data_as(ctypes.c_void_p), float(t_scale), ctypes.byref(h)))
+        self._h = h
+        self.t_scale = float(t_scale)
+
+    def close(self):
+        if getattr(self, "_h", None) and _lib is not None:
+            _lib.fk_cv_destroy(self._h)
+        self._h = None
+
+    def __del__(self):
+        self.close()
+
+    @property
+    def handle(self):
+        return self._h
+
+    def params(self):
+        """(FP32 master weights, BF16 network as float64) on the host."""
+        m = np.zeros(FK_CV_N_PARAMS, dtype=np.float32)
+        b = np.zeros(FK_CV_N_PARAMS, dtype=np.uint16)
+        _check(_lib.fk_cv_get_params(self._h, m.ctypes.data_as(ctypes.c_void_p), b.ctypes.data_as(ctypes.c_void_p)))
+        bf = (b.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+        return m, bf
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32).ravel()
+        _check(_lib.fk_cv_set_params(self._h, p.ctypes.data_as(ctypes.c_void_p)))
+
+    def eval(self, txy):
+        """Forward-mode outputs [n, 2, 5] (value, dx, dy, dt, lap) at device points txy [n, 3] (FP32)."""
+        import torch
+        out = torch.empty((txy.shape[0], 2, 5), dtype=torch.float32, device=txy.device)
+        _check(_lib.fk_cv_eval(self._h, txy.data_ptr(), txy.shape[0], out.data_ptr(), _stream(torch, txy.device)))
+        return out
+
+    def grad(self, txy, target):
+        import torch
+        g = torch.empty(FK_CV_N_PARAMS, dtype=torch.float32, device=txy.device)
+        loss = torch.empty(1, dtype=torch.float32, device=txy.device)
+        _check(_lib.fk_cv_grad(self._h, txy.data_ptr(), target.data_ptr(), txy.shape[0], g.data_ptr(),
+                               loss.data_ptr(), _stream(torch, txy.device)))
+        return g, loss
+
+    def adam_apply(self, grad, lr):
+        import torch
+        _check(_lib.fk_cv_adam_apply(self._h, grad.data_ptr(), float(lr), _stream(torch, grad.device)))
+
+    def train(self, txy, target, steps, batch, lr=1e-3, seed=0, losses=True):
+        import torch
+        loss = torch.zeros(max(steps, 1), dtype=torch.float32, device=txy.device) if losses else None
+        _check(_lib.fk_cv_train(self._h, txy.data_ptr(), target.data_ptr(), txy.shape[0], int(steps), int(batch),
+                                float(lr), int(seed), None if loss is None else loss.data_ptr(),
+                                _stream(torch, txy.device)))
+        return loss
+
+
+def fk_interface_solve_cv(density, data, pts, t, dt, n_paths, cv, stride=2, seed=0, level_id=0, *,
+                          plain=True, exit_step=False, cv_scores=False, plan=None, device="cuda", workspace=None,
+                          grids=None):
+    """Control-variate interface solve (C: ``fk_interface_solve_cv``); returns a
+    dict of device tensors: xi, eta, se_xi, se_eta (CV), plain_* (same paths),
+    total_steps, and on request exit_step, cv_scores."""
+    import torch
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 2)
+    n = pts.shape[0]
+    dev = torch.device(device)
+    keys = ["xi", "eta", "se_xi", "se_eta"] + (["plain_xi", "plain_eta", "plain_se_xi", "plain_se_eta"] if plain else [])
+    out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in keys}
+    out["total_steps"] = torch.zeros(1, dtype=torch.int64, device=dev)
+    if exit_step:
+        out["exit_step"] = torch.empty((n, n_paths), dtype=torch.int32, device=dev)
+    if cv_scores:
+        out["cv_scores"] = torch.empty((n, n_paths, 2), dtype=torch.float32, device=dev)
+    need = _lib.fk_interface_cv_workspace_bytes(n, n_paths)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+
+    def ptr(k):
+        v = out.get(k)
+        return None if v is None else v.data_ptr()
+
+    _check(_lib.fk_interface_solve_cv(
+        ctypes.byref(_density(density)), ctypes.byref(_data(data, grids)), pts.ctypes.data_as(ctypes.c_void_p), n,
+        float(t), float(dt), int(n_paths), int(seed), int(level_id), cv.handle, int(stride),
+        ptr("xi"), ptr("eta"), ptr("se_xi"), ptr("se_eta"), ptr("plain_xi"), ptr("plain_eta"), ptr("plain_se_xi"),
+        ptr("plain_se_eta"), ptr("exit_step"), ptr("cv_scores"), ptr("total_steps"), _plan_struct(plan),
+        workspace.data_ptr(), workspace.numel(), _stream(torch, dev)))
+    out["_workspace"] = workspace
     return out

@@ -1,0 +1,1098 @@
+// fk_cv.hip -- the learned control variate: a tanh MLP u_hat(t, x, y) ->
+// (xi_hat, eta_hat), 3 -> 64 -> 64 -> 64 -> 2 on z = (2t/T - 1, 2x - 1, 2y - 1),
+// with BF16 weights.
+//
+//  * Training: mean-squared error on (t, x, y) -> Monte-Carlo interface
+//    estimates, Adam (FP32 master weights and moments).  Forward and
+//    backward run on BF16 MFMA (v_mfma_f32_16x16x16_bf16, FP32 accumulate)
+//    over LDS-resident 64-sample tiles; the per-tile weight gradients are
+//    summed in a fixed order by the Adam kernel.
+//  * Evaluation: forward-mode value, d/dx, d/dy, d/dt and Laplacian of both
+//    outputs, wavefront-wide: 16 points per round, the 5 derivative channels
+//    as 5 MFMA column blocks.  The MFMA output layout (lane = point column,
+//    4 consecutive units per lane group) is the B-operand layout of the next
+//    layer, so layers chain in registers.  Activations are split into BF16
+//    hi + lo parts (two MFMAs per product) so that the evaluation carries
+//    ~16 mantissa bits: the Dynkin-form estimator is only unbiased if value
+//    and derivative channels describe one function consistently.
+//  * The control-variate path kernel: plain Euler-Maruyama paths (same
+//    counters as fk_interface_solve) plus, every `stride` steps and at the
+//    path's end, the integrand r = Laplacian u_hat + b . grad u_hat - d_t u_hat
+//    (trapezoidal rule in between); the score is g - u_hat(end) + sum r ds.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <utility>
+#include <vector>
+
+#include "fk.h"
+#include "fk_device.hpp"
+#include "fk_internal.hpp"
+#include "fk_pathstep.hpp"
+
+typedef short fk_s4 __attribute__((ext_vector_type(4)));
+typedef float fk_f4 __attribute__((ext_vector_type(4)));
+
+namespace fk {
+
+constexpr int kNP = 8706;
+constexpr int OW1 = 0, OB1 = 192, OW2 = 256, OB2 = 4352, OW3 = 4416, OB3 = 8512, OW4 = 8576, OB4 = 8704;
+constexpr int kWS = 68;  // padded LDS row stride (bf16 elements) of W2 / W3
+
+struct CvState {
+    float *master = nullptr;   // [kNP] FP32
+    float *m = nullptr;        // Adam first moment
+    float *v = nullptr;        // Adam second moment
+    uint16_t *bf = nullptr;    // [kNP] BF16 bits: the network every kernel uses
+    float *partial = nullptr;  // [cap_tiles][kNP + 1] per-tile gradients (+ loss)
+    int cap_tiles = 0;
+};
+
+}  // namespace fk
+
+struct fk_cv {
+    int device = 0;
+    float t_scale = 0.1f;
+    int64_t steps_done = 0;
+    fk::CvState s;
+};
+
+namespace fk {
+
+__device__ __forceinline__ float bf2f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
+
+// ---------------------------------------------------------------------------
+// The network in LDS.
+// ---------------------------------------------------------------------------
+struct NetLds {
+    float w1[64 * 3];
+    float b1[64], b2[64], b3[64];
+    float w4[128];
+    float b4[2];
+    uint16_t w2[64 * kWS];
+    uint16_t w3[64 * kWS];
+};
+
+__device__ void load_net(NetLds &N, const uint16_t *bf) {
+    for (int i = threadIdx.x; i < 192; i += blockDim.x) N.w1[i] = bf2f(bf[OW1 + i]);
+    for (int i = threadIdx.x; i < 64; i += blockDim.x) {
+        N.b1[i] = bf2f(bf[OB1 + i]);
+        N.b2[i] = bf2f(bf[OB2 + i]);
+        N.b3[i] = bf2f(bf[OB3 + i]);
+    }
+    for (int i = threadIdx.x; i < 128; i += blockDim.x) N.w4[i] = bf2f(bf[OW4 + i]);
+    if (threadIdx.x < 2) N.b4[threadIdx.x] = bf2f(bf[OB4 + threadIdx.x]);
+    for (int i = threadIdx.x; i < 4096; i += blockDim.x) {
+        const int r = i >> 6, c = i & 63;
+        N.w2[r * kWS + c] = bf[OW2 + i];
+        N.w3[r * kWS + c] = bf[OW3 + i];
+    }
+}
+
+// tanh and its forward-mode channels: h = tanh(a), s = 1 - h^2 = 4 e / (1+e)^2
+// with e = exp(2a); dh = s da; Laplacian h = s (Laplacian a - 2 h |grad a|^2).
+__device__ __forceinline__ void act5(float a, float ax, float ay, float at, float al, float &h, float &hx,
+                                     float &hy, float &ht, float &hl) {
+    const float ac = fminf(fmaxf(a, -15.f), 15.f);
+    const float e = hw_exp2(ac * 2.8853900817779268f);
+    const float r = hw_rcp(1.f + e);
+    h = fmaf(-2.f, r, 1.f);
+    const float s = 4.f * e * r * r;
+    hx = s * ax;
+    hy = s * ay;
+    ht = s * at;
+    hl = s * fmaf(-2.f * h, fmaf(ax, ax, ay * ay), al);
+}
+
+// BF16 hi + lo split of an FP32 value.
+__device__ __forceinline__ void split_bf16(float v, short &hi, short &lo) {
+    const __bf16 h = (__bf16)v;
+    hi = __builtin_bit_cast(short, h);
+    lo = __builtin_bit_cast(short, (__bf16)(v - (float)h));
+}
+
+__device__ __forceinline__ fk_f4 mfma16(fk_s4 a, fk_s4 b, fk_f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// A operand (16x16 tile) of a padded BF16 weight matrix: lane holds
+// W[16 mt + (lane % 16)][16 kt + 4 (lane / 16) + 0..3].
+__device__ __forceinline__ fk_s4 load_a(const uint16_t *W, int mt, int kt, int n, int g) {
+    const uint16_t *p = W + (16 * mt + n) * kWS + 16 * kt + 4 * g;
+    fk_s4 a;
+    a[0] = (short)p[0];
+    a[1] = (short)p[1];
+    a[2] = (short)p[2];
+    a[3] = (short)p[3];
+    return a;
+}
+
+// Wavefront-wide forward-mode evaluation.  Every lane of the wavefront must
+// call it.  Lane l's point is (tau, x, y); on return out[o][c] holds, for
+// output o, channel c = value, d/dx, d/dy, d/dtau, Laplacian (x, y).
+//
+// Register budget: per round (16 points) at most the layer-2 accumulators
+// (4 output tiles x 5 channels x 4) plus one operand block are live; layer 1
+// is computed per K block as it is consumed, and layer 3 per output tile from
+// the BF16 hi/lo operands of all four K blocks.
+__device__ void net_eval_wave(const NetLds &N, float tscale2, float tau, float x, float y, float out[2][5]) {
+    const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
+#pragma unroll 1
+    for (int r = 0; r < 4; ++r) {
+        const int src = 16 * r + n;
+        const float z0 = __shfl(tau, src, 64) * tscale2 - 1.f;
+        const float z1 = 2.f * __shfl(x, src, 64) - 1.f;
+        const float z2 = 2.f * __shfl(y, src, 64) - 1.f;
+        // ---- layer 2 pre-activations, K block by K block ---------------------
+        fk_f4 acc[4][5];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) acc[mt][c] = fk_f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt) {
+            // layer 1 (VALU) for units 16 kt + 4 g + i of point n
+            fk_s4 Bh[5], Bl[5];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int u = 16 * kt + 4 * g + i;
+                const float w0 = N.w1[3 * u], w1 = N.w1[3 * u + 1], w2 = N.w1[3 * u + 2];
+                const float a = fmaf(w0, z0, fmaf(w1, z1, fmaf(w2, z2, N.b1[u])));
+                float ch[5];
+                act5(a, 2.f * w1, 2.f * w2, tscale2 * w0, 0.f, ch[0], ch[1], ch[2], ch[3], ch[4]);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    short hi, lo;
+                    split_bf16(ch[c], hi, lo);
+                    Bh[c][i] = hi;
+                    Bl[c][i] = lo;
+                }
+            }
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const fk_s4 A = load_a(N.w2, mt, kt, n, g);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    acc[mt][c] = mfma16(A, Bh[c], acc[mt][c]);
+                    acc[mt][c] = mfma16(A, Bl[c], acc[mt][c]);
+                }
+            }
+        }
+        // ---- layer 2 activations -> layer 3 operands -------------------------
+        fk_s4 Ch[4][5], Cl[4][5];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int u = 16 * mt + 4 * g + i;
+                float ch[5];
+                act5(acc[mt][0][i] + N.b2[u], acc[mt][1][i], acc[mt][2][i], acc[mt][3][i], acc[mt][4][i], ch[0], ch[1],
+                     ch[2], ch[3], ch[4]);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    short hi, lo;
+                    split_bf16(ch[c], hi, lo);
+                    Ch[mt][c][i] = hi;
+                    Cl[mt][c][i] = lo;
+                }
+            }
+        // ---- layer 3, one output tile at a time, into the output layer -------
+        float po[2][5];
+#pragma unroll
+        for (int o = 0; o < 2; ++o)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) po[o][c] = 0.f;
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            fk_f4 a3[5];
+#pragma unroll
+            for (int c = 0; c < 5; ++c) a3[c] = fk_f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kt = 0; kt < 4; ++kt) {
+                const fk_s4 A = load_a(N.w3, mt, kt, n, g);
+#pragma unroll
+                for (int c = 0; c < 5; ++c) {
+                    a3[c] = mfma16(A, Ch[kt][c], a3[c]);
+                    a3[c] = mfma16(A, Cl[kt][c], a3[c]);
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int u = 16 * mt + 4 * g + i;
+                float ch[5];
+                act5(a3[0][i] + N.b3[u], a3[1][i], a3[2][i], a3[3][i], a3[4][i], ch[0], ch[1], ch[2], ch[3], ch[4]);
+#pragma unroll
+                for (int o = 0; o < 2; ++o) {
+                    const float w = N.w4[64 * o + u];
+#pragma unroll
+                    for (int c = 0; c < 5; ++c) po[o][c] = fmaf(w, ch[c], po[o][c]);
+                }
+            }
+        }
+        // ---- output layer: sum over the four lane groups of point n ---------
+#pragma unroll
+        for (int o = 0; o < 2; ++o)
+#pragma unroll
+            for (int c = 0; c < 5; ++c) {
+                float v = po[o][c];
+                v += __shfl_xor(v, 16, 64);
+                v += __shfl_xor(v, 32, 64);
+                if (c == 0) v += N.b4[o];
+                if (g == r) out[o][c] = v;
+            }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Evaluation at given points (also the parity hook of the path evaluation).
+// ---------------------------------------------------------------------------
+__global__ void __launch_bounds__(256) cv_eval_kernel(const uint16_t *bf, float tscale2, const float *txy, int64_t n,
+                                                      float *out) {
+    __shared__ NetLds N;
+    load_net(N, bf);
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool ok = i < n;
+    const float t = ok ? txy[3 * i] : 0.f, x = ok ? txy[3 * i + 1] : 0.5f, y = ok ? txy[3 * i + 2] : 0.5f;
+    float o[2][5];
+    net_eval_wave(N, tscale2, t, x, y, o);
+    if (ok)
+        for (int c = 0; c < 2; ++c)
+            for (int k = 0; k < 5; ++k) out[10 * i + 5 * c + k] = o[c][k];
+}
+
+// ---------------------------------------------------------------------------
+// Control-variate path kernel.
+// ---------------------------------------------------------------------------
+struct CvArgs {
+    const uint16_t *bf;
+    float tscale2;               // 2 / T
+    uint32_t stride_iters;       // network evaluations every stride_iters iterations (2 steps each)
+    const float2 *r0;            // [n_out] integrand at the start point of each node
+    float2 *cv_scores;           // [n_out * n_paths]
+};
+
+template <int KIND, int TMODE, bool UNIFORM>
+__device__ __forceinline__ void drift_at(const Lane &L, float &bx, float &by) {
+    float ox = L.ox, oy = L.oy;
+    if constexpr ((KIND == KIND_MOVING || KIND == KIND_TWO) && TMODE == TIME_BACKWARD) {
+        const float rev = fmaf(-(float)L.k, L.drev, L.rev0);
+        ox = L.dens.orbit_r * hw_cos_rev(rev);
+        oy = L.dens.orbit_r * hw_sin_rev(rev);
+    }
+    drift<KIND>(L.dens, ox, oy, L.xh, L.yh, bx, by);
+}
+
+// Drift at the lane's position and PDE time tau (end states).
+template <int KIND, int TMODE>
+__device__ __forceinline__ void drift_at_tau(const Lane &L, float tau, float &bx, float &by) {
+    float ox = L.ox, oy = L.oy;
+    if constexpr ((KIND == KIND_MOVING || KIND == KIND_TWO) && TMODE == TIME_BACKWARD) {
+        const float rev = tau * L.dens.omega_rev;
+        ox = L.dens.orbit_r * hw_cos_rev(rev);
+        oy = L.dens.orbit_r * hw_sin_rev(rev);
+    }
+    drift<KIND>(L.dens, ox, oy, L.xh, L.yh, bx, by);
+}
+
+template <int KIND, int TMODE, bool UNIFORM>
+__global__ void __launch_bounds__(256) fk_cv_path_kernel(const PathArgs a, const CvArgs c) {
+    constexpr bool kMovingBackward = (KIND == KIND_MOVING || KIND == KIND_TWO) && TMODE == TIME_BACKWARD;
+    __shared__ NetLds N;
+    load_net(N, c.bf);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t q_slot = 0, q_next = 0, q_end = 0;
+    bool q_done = false;
+    const uint32_t key0 = a.key0, key1 = a.key1;
+    Lane L;
+    bool active = false, parked = false, out = false;
+    float plx = 0.f, ply = 0.f;              // plain score of a parked path
+    float Ix = 0.f, Iy = 0.f;                // sum of r ds
+    float rx = 0.f, ry = 0.f;                // integrand at the last evaluation
+    int32_t k_last = 0;
+    float tend = 0.f;                        // PDE time at path start
+    uint32_t my_steps = 0;
+    uint32_t iter = 0;
+
+    for (;; ++iter) {
+        if (iter % c.stride_iters == 0) {
+            // ---- evaluation point: integrand of running paths, end value of
+            //      parked ones (every lane of the wavefront joins) ------------
+            if (__ballot(active || parked) != 0ull) {
+                const bool ev = active || parked;
+                const float sk = (parked && L.k >= L.K) ? L.horizon : (float)L.k * L.dt;
+                const float tau = ev ? tend - sk : 0.f;
+                float o[2][5];
+                net_eval_wave(N, c.tscale2, tau, ev ? L.xh : 0.5f, ev ? L.yh : 0.5f, o);
+                // integrand at this state; for a parked path its end state,
+                // with the drift at the end time
+                float bx = 0.f, by = 0.f;
+                if (active) drift_at<KIND, TMODE, UNIFORM>(L, bx, by);
+                if (parked) drift_at_tau<KIND, TMODE>(L, tau, bx, by);
+                const float rnx = o[0][4] + fmaf(bx, o[0][1], by * o[0][2]) - o[0][3];
+                const float rny = o[1][4] + fmaf(bx, o[1][1], by * o[1][2]) - o[1][3];
+                if (ev) {
+                    // trapezoidal rule over the interval since the last evaluation
+                    const float ds = sk - (float)k_last * L.dt;
+                    Ix = fmaf(0.5f * (rx + rnx), ds, Ix);
+                    Iy = fmaf(0.5f * (ry + rny), ds, Iy);
+                    rx = rnx;
+                    ry = rny;
+                    k_last = L.k;
+                }
+                if (parked) {
+                    // plain scores may be stored relative to the start point;
+                    // the CV record is g - u_hat(end) + sum r ds, absolute
+                    const float sx0 = a.shift ? L.px : 0.f, sy0 = a.shift ? L.py : 0.f;
+                    a.scores[L.rec] = make_float2(plx, ply);
+                    c.cv_scores[L.rec] = make_float2((plx - (o[0][0] - sx0)) + Ix, (ply - (o[1][0] - sy0)) + Iy);
+                    if (a.exit_step) a.exit_step[L.rec] = out ? L.k : -1;
+                    parked = false;
+                }
+            }
+            // ---- refill idle lanes (paths start only at evaluation points) ----
+            uint64_t need = __ballot(!active && !parked);
+            while (need != 0ull && !q_done) {
+                if (q_next >= q_end) {
+                    uint32_t cc = 0;
+                    if (lane == 0) cc = atomicAdd(a.queue, 1u);
+                    cc = __builtin_amdgcn_readfirstlane(cc);
+                    if (cc >= a.total_chunks) {
+                        q_done = true;
+                        break;
+                    }
+                    q_slot = cc / a.cpn;
+                    q_next = (cc - q_slot * a.cpn) * a.chunk;
+                    q_end = min(q_next + a.chunk, a.n_paths);
+                    continue;
+                }
+                const uint32_t avail = q_end - q_next;
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+                if (!active && !parked && rank < avail) {
+                    const NodeDev nd = a.nodes[q_slot];
+                    lane_start<KIND, TMODE>(L, nd, a.levels, q_next + rank, a.n_paths);
+                    tend = a.levels[nd.level].tend;
+                    const float2 r0 = c.r0[nd.out];
+                    rx = r0.x;
+                    ry = r0.y;
+                    Ix = 0.f;
+                    Iy = 0.f;
+                    k_last = 0;
+                    active = true;
+                }
+                q_next += min((uint32_t)__popcll(need), avail);
+                need = __ballot(!active && !parked);
+            }
+        }
+        if (__ballot(active || parked) == 0ull && q_done) break;
+
+        if (active) {
+            out = false;
+            if (L.k < L.K) {
+                const PhiloxOut r = philox4x32_10((uint32_t)L.k >> 1, L.path, L.nid, L.ctr3, key0, key1);
+                float ox = L.ox, oy = L.oy, cr = 0.f, sr = 0.f;
+                if constexpr (kMovingBackward) {
+                    const float rev = fmaf(-(float)L.k, L.drev, L.rev0);
+                    cr = hw_cos_rev(rev);
+                    sr = hw_sin_rev(rev);
+                    ox = L.dens.orbit_r * cr;
+                    oy = L.dens.orbit_r * sr;
+                }
+                out = em_step<KIND, UNIFORM>(L, r.r0, r.r1, ox, oy);
+                my_steps += 1;
+                if (!out && L.k < L.K) {
+                    if constexpr (kMovingBackward) {
+                        const float c2 = fmaf(cr, L.cos_d, sr * L.sin_d);
+                        const float s2 = fmaf(sr, L.cos_d, -cr * L.sin_d);
+                        ox = L.dens.orbit_r * c2;
+                        oy = L.dens.orbit_r * s2;
+                    }
+                    out = em_step<KIND, UNIFORM>(L, r.r2, r.r3, ox, oy);
+                    my_steps += 1;
+                }
+            }
+            if (out || L.k >= L.K) {
+                // the last interval is closed at the next evaluation point,
+                // where u_hat and the integrand at the end state are known
+                score_path(a, L, out, plx, ply);
+                active = false;
+                parked = true;
+            }
+        }
+    }
+    unsigned long long st = my_steps;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) st += __shfl_xor(st, off, 64);
+    if (lane == 0 && st != 0ull) atomicAdd(a.total_steps, st);
+}
+
+// Per node: u_hat at the start (the shift of the CV estimate) and the
+// integrand r0 there.
+struct CvNodeArgs {
+    const NodeDev *nodes;
+    const LevelDev *levels;
+    int64_t n_nodes;
+    OutDev *outs_cv;   // shift_x/shift_y <- u_hat(t_init + t, P)
+    float2 *r0;
+    int kind, time_mode;
+};
+
+template <int KIND, int TMODE>
+__global__ void __launch_bounds__(256) cv_node_kernel(const CvNodeArgs na, const uint16_t *bf, float tscale2) {
+    __shared__ NetLds N;
+    load_net(N, bf);
+    __syncthreads();
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool ok = s < na.n_nodes;
+    Lane L;
+    float tend = 0.f;
+    if (ok) {
+        const NodeDev nd = na.nodes[s];
+        lane_start<KIND, TMODE>(L, nd, na.levels, 0, 1);
+        tend = na.levels[nd.level].tend;
+    } else {
+        L.xh = 0.5f;
+        L.yh = 0.5f;
+    }
+    float o[2][5];
+    net_eval_wave(N, tscale2, tend, L.xh, L.yh, o);
+    if (ok) {
+        const NodeDev nd = na.nodes[s];
+        float bx, by;
+        drift_at<KIND, TMODE, true>(L, bx, by);
+        na.outs_cv[nd.out].shift_x = (double)o[0][0];
+        na.outs_cv[nd.out].shift_y = (double)o[1][0];
+        na.r0[nd.out] = make_float2(o[0][4] + fmaf(bx, o[0][1], by * o[0][2]) - o[0][3],
+                                    o[1][4] + fmaf(bx, o[1][1], by * o[1][2]) - o[1][3]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Training: per-tile forward + backward on MFMA, then Adam.
+// ---------------------------------------------------------------------------
+constexpr int kTS = 65;  // LDS row stride (floats) of the 64 x 64 activation tiles
+
+struct TrainLds {
+    NetLds net;
+    float z[3][64];
+    float y[2][64];
+    float dout[2][64];
+    float H1[64 * kTS], H2[64 * kTS], H3[64 * kTS];
+    float D[64 * kTS], E[64 * kTS];
+    float red[256];
+};
+
+struct TrainArgs {
+    const uint16_t *bf;
+    const float *txy;      // [n][3]
+    const float *target;   // [n][2]
+    int64_t n;
+    int64_t batch;         // samples in this step (loss normalisation)
+    int full;              // 1: tile b takes samples 64 b .. 64 b + 63; 0: Philox minibatch
+    uint32_t step, key0, key1;
+    float tscale2;
+    float *partial;        // [tiles][kNP + 1]
+};
+
+// C[M = 64][N = 64] = A[64 x K] B[K x 64] with K = 64, A and B given by
+// element accessors, on MFMA; each wavefront computes four 16 x 16 tiles
+// and hands each result fragment to `sink(row, col, value)`.
+template <typename FA, typename FB, typename FS>
+__device__ __forceinline__ void wave_gemm64(FA A, FB B, FS sink) {
+    const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15, w = threadIdx.x >> 6;
+#pragma unroll 1
+    for (int t = 0; t < 4; ++t) {
+        const int tile = 4 * w + t, mt = tile >> 2, nt = tile & 3;
+        fk_f4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt) {
+            fk_s4 a, b;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                a[i] = (short)f2bf(A(16 * mt + n, 16 * kt + 4 * g + i));
+                b[i] = (short)f2bf(B(16 * kt + 4 * g + i, 16 * nt + n));
+            }
+            acc = mfma16(a, b, acc);
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i) sink(16 * mt + 4 * g + i, 16 * nt + n, acc[i]);
+    }
+}
+
+__global__ void __launch_bounds__(256) cv_grad_kernel(const TrainArgs ta) {
+    extern __shared__ char smem[];
+    TrainLds &S = *reinterpret_cast<TrainLds *>(smem);
+    const int tid = threadIdx.x;
+    load_net(S.net, ta.bf);
+    float *P = ta.partial + (int64_t)blockIdx.x * (kNP + 1);
+    // ---- the tile's samples ----------------------------------------------------
+    if (tid < 64) {
+        int64_t idx;
+        bool valid = true;
+        if (ta.full) {
+            idx = (int64_t)blockIdx.x * 64 + tid;
+            valid = idx < ta.n;
+            if (!valid) idx = 0;
+        } else {
+            const int64_t j = (int64_t)blockIdx.x * 64 + tid;
+            const PhiloxOut r = philox4x32_10((uint32_t)j, ta.step, 0u, 2u, ta.key0, ta.key1);
+            idx = (int64_t)(r.r0 % (uint32_t)ta.n);
+            valid = j < ta.batch;
+        }
+        S.z[0][tid] = ta.txy[3 * idx] * ta.tscale2 - 1.f;
+        S.z[1][tid] = 2.f * ta.txy[3 * idx + 1] - 1.f;
+        S.z[2][tid] = 2.f * ta.txy[3 * idx + 2] - 1.f;
+        S.y[0][tid] = ta.target[2 * idx];
+        S.y[1][tid] = ta.target[2 * idx + 1];
+        S.dout[0][tid] = valid ? 1.f : 0.f;  // validity mask until the residual is known
+    }
+    __syncthreads();
+    // ---- forward ------------------------------------------------------------------
+    for (int e = tid; e < 4096; e += 256) {
+        const int u = e >> 6, s = e & 63;
+        const float a = fmaf(S.net.w1[3 * u], S.z[0][s],
+                             fmaf(S.net.w1[3 * u + 1], S.z[1][s], fmaf(S.net.w1[3 * u + 2], S.z[2][s], S.net.b1[u])));
+        S.H1[u * kTS + s] = tanhf(a);
+    }
+    __syncthreads();
+    wave_gemm64([&](int m, int k) { return bf2f(S.net.w2[m * kWS + k]); }, [&](int k, int n) { return S.H1[k * kTS + n]; },
+                [&](int m, int n, float v) { S.H2[m * kTS + n] = tanhf(v + S.net.b2[m]); });
+    __syncthreads();
+    wave_gemm64([&](int m, int k) { return bf2f(S.net.w3[m * kWS + k]); }, [&](int k, int n) { return S.H2[k * kTS + n]; },
+                [&](int m, int n, float v) { S.H3[m * kTS + n] = tanhf(v + S.net.b3[m]); });
+    __syncthreads();
+    // outputs, residuals and d loss / d out (mean over batch and both outputs)
+    float lsum = 0.f;
+    if (tid < 128) {
+        const int o = tid >> 6, s = tid & 63;
+        float acc = S.net.b4[o];
+        for (int u = 0; u < 64; ++u) acc = fmaf(S.net.w4[64 * o + u], S.H3[u * kTS + s], acc);
+        const float valid = S.dout[0][s];
+        const float res = (acc - S.y[o][s]) * valid;
+        lsum = res * res;
+        S.red[tid] = 2.f * res / (2.f * (float)ta.batch);
+    }
+    __syncthreads();
+    if (tid < 128) S.dout[tid >> 6][tid & 63] = S.red[tid];
+    // loss of the tile
+    {
+        float v = lsum;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+        __syncthreads();
+        if ((tid & 63) == 0) S.red[tid >> 6] = v;
+        __syncthreads();
+        if (tid == 0) P[kNP] = S.red[0] + S.red[1] + S.red[2] + S.red[3];
+    }
+    __syncthreads();
+    // ---- backward -----------------------------------------------------------------
+    // W4, b4
+    if (tid < 128) {
+        const int o = tid >> 6, u = tid & 63;
+        float acc = 0.f;
+        for (int s = 0; s < 64; ++s) acc = fmaf(S.dout[o][s], S.H3[u * kTS + s], acc);
+        P[OW4 + 64 * o + u] = acc;
+    } else if (tid < 130) {
+        const int o = tid - 128;
+        float acc = 0.f;
+        for (int s = 0; s < 64; ++s) acc += S.dout[o][s];
+        P[OB4 + o] = acc;
+    }
+    // dA3 = (W4^T dout) (1 - H3^2)
+    for (int e = tid; e < 4096; e += 256) {
+        const int u = e >> 6, s = e & 63;
+        const float h = S.H3[u * kTS + s];
+        S.D[u * kTS + s] = fmaf(S.net.w4[u], S.dout[0][s], S.net.w4[64 + u] * S.dout[1][s]) * (1.f - h * h);
+    }
+    __syncthreads();
+    // dW3 = dA3 H2^T, db3
+    wave_gemm64([&](int m, int k) { return S.D[m * kTS + k]; }, [&](int k, int n) { return S.H2[n * kTS + k]; },
+                [&](int m, int n, float v) { P[OW3 + 64 * m + n] = v; });
+    if (tid < 64) {
+        float acc = 0.f;
+        for (int s = 0; s < 64; ++s) acc += S.D[tid * kTS + s];
+        P[OB3 + tid] = acc;
+    }
+    // dA2 = (W3^T dA3) (1 - H2^2)
+    wave_gemm64([&](int m, int k) { return bf2f(S.net.w3[k * kWS + m]); }, [&](int k, int n) { return S.D[k * kTS + n]; },
+                [&](int m, int n, float v) {
+                    const float h = S.H2[m * kTS + n];
+                    S.E[m * kTS + n] = v * (1.f - h * h);
+                });
+    __syncthreads();
+    // dW2 = dA2 H1^T, db2
+    wave_gemm64([&](int m, int k) { return S.E[m * kTS + k]; }, [&](int k, int n) { return S.H1[n * kTS + k]; },
+                [&](int m, int n, float v) { P[OW2 + 64 * m + n] = v; });
+    if (tid < 64) {
+        float acc = 0.f;
+        for (int s = 0; s < 64; ++s) acc += S.E[tid * kTS + s];
+        P[OB2 + tid] = acc;
+    }
+    // dA1 = (W2^T dA2) (1 - H1^2)
+    wave_gemm64([&](int m, int k) { return bf2f(S.net.w2[k * kWS + m]); }, [&](int k, int n) { return S.E[k * kTS + n]; },
+                [&](int m, int n, float v) {
+                    const float h = S.H1[m * kTS + n];
+                    S.D[m * kTS + n] = v * (1.f - h * h);
+                });
+    __syncthreads();
+    // dW1 = dA1 Z^T, db1
+    if (tid < 192) {
+        const int u = tid / 3, j = tid % 3;
+        float acc = 0.f;
+        for (int s = 0; s < 64; ++s) acc = fmaf(S.D[u * kTS + s], S.z[j][s], acc);
+        P[OW1 + tid] = acc;
+    } else {
+        for (int u = tid - 192; u < 64; u += 64) {
+            float acc = 0.f;
+            for (int s = 0; s < 64; ++s) acc += S.D[u * kTS + s];
+            P[OB1 + u] = acc;
+        }
+    }
+}
+
+// Sum of the tiles' gradients in a fixed order: grad[i] (and the loss).
+__global__ void cv_sum_kernel(const float *partial, int tiles, float *grad, float *loss, float loss_scale) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > kNP) return;
+    float acc = 0.f;
+    for (int t = 0; t < tiles; ++t) acc += partial[(int64_t)t * (kNP + 1) + i];
+    if (i < kNP) {
+        if (grad) grad[i] = acc;
+    } else if (loss) {
+        *loss = acc * loss_scale;
+    }
+}
+
+struct AdamArgs {
+    float *master, *m, *v;
+    uint16_t *bf;
+    const float *partial;   // per-tile gradients, or nullptr with `grad`
+    const float *grad;
+    int tiles;
+    float lr, c1, c2;       // c1 = 1 - beta1^step, c2 = 1 - beta2^step
+    float *loss_out;        // or nullptr
+    float loss_scale;
+};
+
+__global__ void cv_adam_kernel(const AdamArgs A) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > kNP) return;
+    float g = 0.f;
+    if (A.partial) {
+        for (int t = 0; t < A.tiles; ++t) g += A.partial[(int64_t)t * (kNP + 1) + i];
+    } else if (i < kNP) {
+        g = A.grad[i];
+    }
+    if (i == kNP) {
+        if (A.loss_out) *A.loss_out = g * A.loss_scale;
+        return;
+    }
+    const float m = 0.9f * A.m[i] + 0.1f * g;
+    const float v = 0.999f * A.v[i] + 0.001f * g * g;
+    A.m[i] = m;
+    A.v[i] = v;
+    const float p = A.master[i] - A.lr * (m / A.c1) / (sqrtf(v / A.c2) + 1e-8f);
+    A.master[i] = p;
+    A.bf[i] = f2bf(p);
+}
+
+__global__ void cv_to_bf16_kernel(const float *master, uint16_t *bf) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < kNP) bf[i] = f2bf(master[i]);
+}
+
+static int ensure_partial(fk_cv *cv, int tiles) {
+    if (tiles <= cv->s.cap_tiles) return FK_OK;
+    if (cv->s.partial) hipFree(cv->s.partial);
+    cv->s.partial = nullptr;
+    cv->s.cap_tiles = 0;
+    hipError_t e = hipMalloc(&cv->s.partial, sizeof(float) * (size_t)tiles * (kNP + 1));
+    if (e != hipSuccess) return fail(FK_E_NOMEM, "hipMalloc of gradient partials: %s", hipGetErrorString(e));
+    cv->s.cap_tiles = tiles;
+    return FK_OK;
+}
+
+static hipError_t launch_grad(const TrainArgs &ta, int tiles, hipStream_t s) {
+    const size_t lds = sizeof(TrainLds);
+    hipError_t e = hipFuncSetAttribute((const void *)cv_grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(cv_grad_kernel, dim3(tiles), dim3(256), lds, s, ta);
+    return hipGetLastError();
+}
+
+// Launches of the control-variate path kernel.
+template <int K, int T, bool U>
+struct CvLaunchF {
+    static hipError_t run(const PathArgs &a, const CvArgs &c, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((fk_cv_path_kernel<K, T, U>), dim3(grid), dim3(256), 0, s, a, c);
+        return hipGetLastError();
+    }
+};
+template <int K, int T, bool U>
+struct CvOccF {
+    static int run() {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk_cv_path_kernel<K, T, U>, 256, 0) != hipSuccess)
+            return 0;
+        return nb;
+    }
+};
+template <int K, int T, bool U>
+struct CvNodeF {
+    static hipError_t run(const CvNodeArgs &na, const uint16_t *bf, float ts2, hipStream_t s) {
+        const int blocks = (int)((na.n_nodes + 255) / 256);
+        hipLaunchKernelGGL((cv_node_kernel<K, T>), dim3(blocks), dim3(256), 0, s, na, bf, ts2);
+        return hipGetLastError();
+    }
+};
+
+template <template <int, int, bool> class F, typename... Args>
+auto cv_dispatch(int kind, int time_mode, bool uniform, Args &&...args) {
+    const bool frozen = (time_mode == TIME_FROZEN);
+#define FK_CV_CASE(K, T)                                                       \
+    return uniform ? F<K, T, true>::run(std::forward<Args>(args)...)          \
+                   : F<K, T, false>::run(std::forward<Args>(args)...)
+    switch (kind) {
+    case KIND_CONST: FK_CV_CASE(KIND_CONST, TIME_BACKWARD);
+    case KIND_BUMP: FK_CV_CASE(KIND_BUMP, TIME_BACKWARD);
+    case KIND_RIDGE: FK_CV_CASE(KIND_RIDGE, TIME_BACKWARD);
+    case KIND_MOVING:
+        if (frozen) FK_CV_CASE(KIND_MOVING, TIME_FROZEN);
+        FK_CV_CASE(KIND_MOVING, TIME_BACKWARD);
+    default:
+        if (frozen) FK_CV_CASE(KIND_TWO, TIME_FROZEN);
+        FK_CV_CASE(KIND_TWO, TIME_BACKWARD);
+    }
+#undef FK_CV_CASE
+}
+
+// Workspace of one control-variate solve.
+struct CvWs {
+    size_t counters, levels, nodes, outs, outs_cv, r0, scores, cv_scores, total;
+};
+
+static CvWs cv_ws_layout(int64_t n_nodes, int64_t n_paths, bool own_cv) {
+    CvWs L{};
+    size_t off = 0;
+    L.counters = off;
+    off += 256;
+    L.levels = off;
+    off += align256(sizeof(LevelDev));
+    L.nodes = off;
+    off += align256(sizeof(NodeDev) * (size_t)n_nodes);
+    L.outs = off;
+    off += align256(sizeof(OutDev) * (size_t)n_nodes);
+    L.outs_cv = off;
+    off += align256(sizeof(OutDev) * (size_t)n_nodes);
+    L.r0 = off;
+    off += align256(sizeof(float2) * (size_t)n_nodes);
+    L.scores = off;
+    off += align256(sizeof(float2) * (size_t)n_nodes * (size_t)n_paths);
+    L.cv_scores = off;
+    if (own_cv) off += align256(sizeof(float2) * (size_t)n_nodes * (size_t)n_paths);
+    L.total = off;
+    return L;
+}
+
+}  // namespace fk
+
+using namespace fk;
+
+extern "C" {
+
+int fk_cv_create(const float *params, double t_scale, fk_cv_t *out) {
+    g_last_error.clear();
+    if (!out || !params) return fail(FK_E_INVAL, "NULL argument");
+    *out = nullptr;
+    if (!(t_scale > 0.0) || !std::isfinite(t_scale)) return fail(FK_E_INVAL, "t_scale must be > 0");
+    for (int i = 0; i < kNP; ++i)
+        if (!std::isfinite(params[i])) return fail(FK_E_INVAL, "parameter %d is not finite", i);
+    fk_cv *cv = new fk_cv();
+    hipError_t e = hipGetDevice(&cv->device);
+    if (e != hipSuccess) {
+        delete cv;
+        return fail(FK_E_NODEVICE, "no HIP device: %s", hipGetErrorString(e));
+    }
+    cv->t_scale = (float)t_scale;
+    float *buf = nullptr;
+    if ((e = hipMalloc(&buf, sizeof(float) * 3 * kNP + sizeof(uint16_t) * kNP + 256)) != hipSuccess) {
+        delete cv;
+        return fail(FK_E_NOMEM, "hipMalloc of network state: %s", hipGetErrorString(e));
+    }
+    cv->s.master = buf;
+    cv->s.m = buf + kNP;
+    cv->s.v = buf + 2 * kNP;
+    cv->s.bf = (uint16_t *)(buf + 3 * kNP);
+    std::vector<float> zeros(2 * kNP, 0.f);
+    if ((e = hipMemcpy(cv->s.master, params, sizeof(float) * kNP, hipMemcpyHostToDevice)) != hipSuccess ||
+        (e = hipMemcpy(cv->s.m, zeros.data(), sizeof(float) * 2 * kNP, hipMemcpyHostToDevice)) != hipSuccess) {
+        hipFree(buf);
+        delete cv;
+        return hip_fail(e, "upload network");
+    }
+    hipLaunchKernelGGL(cv_to_bf16_kernel, dim3((kNP + 255) / 256), dim3(256), 0, 0, cv->s.master, cv->s.bf);
+    if ((e = hipDeviceSynchronize()) != hipSuccess) {
+        hipFree(buf);
+        delete cv;
+        return hip_fail(e, "convert network");
+    }
+    *out = cv;
+    return FK_OK;
+}
+
+void fk_cv_destroy(fk_cv_t cv) {
+    if (!cv) return;
+    if (cv->s.master) hipFree(cv->s.master);
+    if (cv->s.partial) hipFree(cv->s.partial);
+    delete cv;
+}
+
+int fk_cv_get_params(fk_cv_t cv, float *params, uint16_t *bf16_params) {
+    g_last_error.clear();
+    if (!cv) return fail(FK_E_INVAL, "network is NULL");
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "synchronise");
+    if (params && (e = hipMemcpy(params, cv->s.master, sizeof(float) * kNP, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "download master weights");
+    if (bf16_params && (e = hipMemcpy(bf16_params, cv->s.bf, sizeof(uint16_t) * kNP, hipMemcpyDeviceToHost)) != hipSuccess)
+        return hip_fail(e, "download BF16 weights");
+    return FK_OK;
+}
+
+int fk_cv_set_params(fk_cv_t cv, const float *params) {
+    g_last_error.clear();
+    if (!cv || !params) return fail(FK_E_INVAL, "NULL argument");
+    hipError_t e = hipMemcpy(cv->s.master, params, sizeof(float) * kNP, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(e, "upload weights");
+    hipLaunchKernelGGL(cv_to_bf16_kernel, dim3((kNP + 255) / 256), dim3(256), 0, 0, cv->s.master, cv->s.bf);
+    if ((e = hipDeviceSynchronize()) != hipSuccess) return hip_fail(e, "convert network");
+    return FK_OK;
+}
+
+int fk_cv_eval(fk_cv_t cv, const float *txy, int64_t n, float *out, hipStream_t stream) {
+    g_last_error.clear();
+    if (!cv) return fail(FK_E_INVAL, "network is NULL");
+    if (n < 0) return fail(FK_E_INVAL, "n < 0");
+    if (n == 0) return FK_OK;
+    if (!txy || !out) return fail(FK_E_INVAL, "NULL array");
+    const int64_t blocks = (n + 255) / 256;
+    hipLaunchKernelGGL(cv_eval_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, cv->s.bf, 2.f / cv->t_scale, txy,
+                       n, out);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FK_OK : hip_fail(e, "eval kernel launch");
+}
+
+int fk_cv_grad(fk_cv_t cv, const float *txy, const float *target, int64_t n, float *grad, float *loss,
+               hipStream_t stream) {
+    g_last_error.clear();
+    if (!cv) return fail(FK_E_INVAL, "network is NULL");
+    if (n < 1 || n > (int64_t)1 << 31) return fail(FK_E_INVAL, "n out of range");
+    if (!txy || !target || !grad) return fail(FK_E_INVAL, "NULL array");
+    const int tiles = (int)((n + 63) / 64);
+    int rc;
+    if ((rc = ensure_partial(cv, tiles)) != FK_OK) return rc;
+    TrainArgs ta{};
+    ta.bf = cv->s.bf;
+    ta.txy = txy;
+    ta.target = target;
+    ta.n = n;
+    ta.batch = n;
+    ta.full = 1;
+    ta.tscale2 = 2.f / cv->t_scale;
+    ta.partial = cv->s.partial;
+    hipError_t e = launch_grad(ta, tiles, stream);
+    if (e != hipSuccess) return hip_fail(e, "gradient kernel launch");
+    // the tiles' loss entries are sums of squared residuals: report the mean
+    hipLaunchKernelGGL(cv_sum_kernel, dim3((kNP + 256) / 256), dim3(256), 0, stream, cv->s.partial, tiles, grad,
+                       loss, 1.f / (2.f * (float)n));
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "sum kernel launch");
+    return FK_OK;
+}
+
+int fk_cv_adam_apply(fk_cv_t cv, const float *grad, float lr, hipStream_t stream) {
+    g_last_error.clear();
+    if (!cv || !grad) return fail(FK_E_INVAL, "NULL argument");
+    const int64_t step = ++cv->steps_done;
+    AdamArgs A{};
+    A.master = cv->s.master;
+    A.m = cv->s.m;
+    A.v = cv->s.v;
+    A.bf = cv->s.bf;
+    A.grad = grad;
+    A.lr = lr;
+    A.c1 = (float)(1.0 - std::pow(0.9, (double)step));
+    A.c2 = (float)(1.0 - std::pow(0.999, (double)step));
+    hipLaunchKernelGGL(cv_adam_kernel, dim3((kNP + 256) / 256), dim3(256), 0, stream, A);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FK_OK : hip_fail(e, "adam kernel launch");
+}
+
+int fk_cv_train(fk_cv_t cv, const float *txy, const float *target, int64_t n, int32_t steps, int32_t batch, float lr,
+                uint64_t seed, float *loss_out, hipStream_t stream) {
+    g_last_error.clear();
+    if (!cv) return fail(FK_E_INVAL, "network is NULL");
+    if (n < 1 || n > 0xffffffffLL) return fail(FK_E_INVAL, "n out of range");
+    if (steps < 0 || batch < 1 || batch > (1 << 24)) return fail(FK_E_INVAL, "steps >= 0 and batch in [1, 2^24]");
+    if (!(lr > 0.f)) return fail(FK_E_INVAL, "lr must be > 0");
+    if (!txy || !target) return fail(FK_E_INVAL, "NULL array");
+    const int tiles = (batch + 63) / 64;
+    int rc;
+    if ((rc = ensure_partial(cv, tiles)) != FK_OK) return rc;
+    for (int s = 0; s < steps; ++s) {
+        TrainArgs ta{};
+        ta.bf = cv->s.bf;
+        ta.txy = txy;
+        ta.target = target;
+        ta.n = n;
+        ta.batch = batch;
+        ta.full = 0;
+        ta.step = (uint32_t)(cv->steps_done + 1);
+        ta.key0 = (uint32_t)seed;
+        ta.key1 = (uint32_t)(seed >> 32);
+        ta.tscale2 = 2.f / cv->t_scale;
+        ta.partial = cv->s.partial;
+        hipError_t e = launch_grad(ta, tiles, stream);
+        if (e != hipSuccess) return hip_fail(e, "gradient kernel launch");
+        const int64_t step = ++cv->steps_done;
+        AdamArgs A{};
+        A.master = cv->s.master;
+        A.m = cv->s.m;
+        A.v = cv->s.v;
+        A.bf = cv->s.bf;
+        A.partial = cv->s.partial;
+        A.tiles = tiles;
+        A.lr = lr;
+        A.c1 = (float)(1.0 - std::pow(0.9, (double)step));
+        A.c2 = (float)(1.0 - std::pow(0.999, (double)step));
+        A.loss_out = loss_out ? loss_out + s : nullptr;
+        A.loss_scale = 1.f / (2.f * (float)batch);
+        hipLaunchKernelGGL(cv_adam_kernel, dim3((kNP + 256) / 256), dim3(256), 0, stream, A);
+        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "adam kernel launch");
+    }
+    return FK_OK;
+}
+
+size_t fk_interface_cv_workspace_bytes(int64_t n_nodes, int64_t n_paths) {
+    if (n_nodes < 0 || n_paths < 2) return 0;
+    return cv_ws_layout(n_nodes, n_paths, true).total;
+}
+
+int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *pts, int64_t n_nodes, double t,
+                          double dt, int64_t n_paths, uint64_t seed, uint32_t level_id, fk_cv_t cv, int32_t stride,
+                          double *xi, double *eta, double *se_xi, double *se_eta, double *plain_xi,
+                          double *plain_eta, double *plain_se_xi, double *plain_se_eta, int32_t *exit_step,
+                          float *cv_scores, uint64_t *total_steps, const fk_plan *plan, void *workspace,
+                          size_t workspace_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    int rc;
+    if (!cv) return fail(FK_E_INVAL, "network is NULL");
+    if ((rc = validate_density(w)) != FK_OK) return rc;
+    if ((rc = validate_data(d)) != FK_OK) return rc;
+    if ((rc = validate_common(n_paths, dt)) != FK_OK) return rc;
+    if ((rc = validate_horizon(t, d->t_init, dt, level_id)) != FK_OK) return rc;
+    if ((rc = validate_points(pts, n_nodes)) != FK_OK) return rc;
+    if (stride < 2 || stride % 2 != 0 || stride > (1 << 20)) return fail(FK_E_INVAL, "stride must be even and >= 2");
+    if (n_nodes > 0 && (!xi || !eta || !se_xi || !se_eta)) return fail(FK_E_INVAL, "an output pointer is NULL");
+    fk_plan pl;
+    if ((rc = resolve_plan(plan, &pl)) != FK_OK) return rc;
+    pl.block = 256;
+    if ((rc = check_chunks(n_nodes, n_paths, pl)) != FK_OK) return rc;
+    const CvWs lay = cv_ws_layout(n_nodes, n_paths, cv_scores == nullptr);
+    if (!workspace || workspace_bytes < lay.total)
+        return fail(FK_E_NOMEM, "workspace too small: need %zu bytes", lay.total);
+    if (((uintptr_t)workspace & 255u) != 0) return fail(FK_E_INVAL, "workspace must be 256-byte aligned");
+    if (n_nodes == 0) return FK_OK;
+    int n_cu = 0;
+    if ((rc = device_cus(&n_cu)) != FK_OK) return rc;
+
+    LevelSpec spec{*w, t, d->t_init, 0, n_nodes, level_id};
+    Tables T;
+    if ((rc = build_tables(&spec, 1, pts, n_nodes, d, dt, T)) != FK_OK) return rc;
+    char *ws = (char *)workspace;
+    hipError_t e;
+    if ((e = hipMemcpyAsync(ws + lay.levels, T.levels.data(), sizeof(LevelDev), hipMemcpyHostToDevice, stream)) !=
+            hipSuccess ||
+        (e = hipMemcpyAsync(ws + lay.nodes, T.nodes.data(), sizeof(NodeDev) * T.nodes.size(), hipMemcpyHostToDevice,
+                            stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(ws + lay.outs, T.outs.data(), sizeof(OutDev) * T.outs.size(), hipMemcpyHostToDevice,
+                            stream)) != hipSuccess ||
+        (e = hipMemcpyAsync(ws + lay.outs_cv, T.outs.data(), sizeof(OutDev) * T.outs.size(), hipMemcpyHostToDevice,
+                            stream)) != hipSuccess)
+        return hip_fail(e, "upload tables");
+    uint32_t *counters = (uint32_t *)(ws + lay.counters);
+    if ((e = launch_zero_u32(counters, 64, stream)) != hipSuccess) return hip_fail(e, "zero counters");
+    if (total_steps && (e = launch_zero_u32((uint32_t *)total_steps, 2, stream)) != hipSuccess)
+        return hip_fail(e, "zero total_steps");
+
+    // per-node u_hat and integrand at the start
+    CvNodeArgs na{};
+    na.nodes = (const NodeDev *)(ws + lay.nodes);
+    na.levels = (const LevelDev *)(ws + lay.levels);
+    na.n_nodes = n_nodes;
+    na.outs_cv = (OutDev *)(ws + lay.outs_cv);
+    na.r0 = (float2 *)(ws + lay.r0);
+    const float ts2 = 2.f / cv->t_scale;
+    if ((e = cv_dispatch<CvNodeF>(T.kind, T.time_mode, true, na, (const uint16_t *)cv->s.bf, ts2, stream)) !=
+        hipSuccess)
+        return hip_fail(e, "node kernel launch");
+
+    PathArgs a{};
+    SolveLaunch S{};
+    S.args = a;
+    fill_common_args(S, d, T.shift, seed);
+    a = S.args;
+    a.levels = (const LevelDev *)(ws + lay.levels);
+    a.nodes = (const NodeDev *)(ws + lay.nodes);
+    a.scores = (float2 *)(ws + lay.scores);
+    a.exit_step = exit_step;
+    a.queue = counters;
+    a.total_steps = total_steps ? (unsigned long long *)total_steps : (unsigned long long *)(counters + 2);
+    const int64_t cpn = (n_paths + pl.chunk - 1) / pl.chunk;
+    a.n_paths = (uint32_t)n_paths;
+    a.chunk = (uint32_t)pl.chunk;
+    a.cpn = (uint32_t)cpn;
+    a.total_chunks = (uint32_t)(n_nodes * cpn);
+    CvArgs c{};
+    c.bf = cv->s.bf;
+    c.tscale2 = ts2;
+    c.stride_iters = (uint32_t)(stride / 2);
+    c.r0 = (const float2 *)(ws + lay.r0);
+    c.cv_scores = cv_scores ? (float2 *)cv_scores : (float2 *)(ws + lay.cv_scores);
+    int bpc = pl.blocks_per_cu;
+    const int occ = cv_dispatch<CvOccF>(T.kind, T.time_mode, T.uniform);
+    if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
+    if ((e = cv_dispatch<CvLaunchF>(T.kind, T.time_mode, T.uniform, a, c, n_cu * bpc, stream)) != hipSuccess)
+        return hip_fail(e, "control-variate path kernel launch");
+
+    ReduceArgs r{};
+    r.scores = c.cv_scores;
+    r.exit_step = nullptr;
+    r.outs = (const OutDev *)(ws + lay.outs_cv);
+    r.n_out = n_nodes;
+    r.n_paths = n_paths;
+    r.xi = xi;
+    r.eta = eta;
+    r.se_xi = se_xi;
+    r.se_eta = se_eta;
+    if ((e = launch_reduce(r, stream)) != hipSuccess) return hip_fail(e, "reduce kernel launch");
+    if (plain_xi && plain_eta && plain_se_xi && plain_se_eta) {
+        ReduceArgs q = r;
+        q.scores = a.scores;
+        q.outs = (const OutDev *)(ws + lay.outs);
+        q.xi = plain_xi;
+        q.eta = plain_eta;
+        q.se_xi = plain_se_xi;
+        q.se_eta = plain_se_eta;
+        if ((e = launch_reduce(q, stream)) != hipSuccess) return hip_fail(e, "reduce kernel launch");
+    }
+    return FK_OK;
+}
+
+}  // extern "C"

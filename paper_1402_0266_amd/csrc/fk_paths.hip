@@ -33,6 +33,7 @@
 
 #include "fk_device.hpp"
 #include "fk_internal.hpp"
+#include "fk_pathstep.hpp"
 
 namespace fk {
 
@@ -47,70 +48,6 @@ hipError_t launch_zero_u32(uint32_t *p, int n_words, hipStream_t s) {
     return hipGetLastError();
 }
 
-namespace {
-
-// Lane path state.
-struct Lane {
-    float xh, xl, yh, yl;  // position as hi + lo pairs
-    int32_t k;             // steps taken
-    int32_t K;             // steps allowed
-    uint32_t path, nid, ctr3;
-    uint64_t rec;          // record index
-    float px, py;          // start point (score shift for identity data)
-    float horizon, dt, dt_last, cbm, cbm_last;
-    float ox, oy;          // frozen / static centre offset
-    float rev0, drev, cos_d, sin_d;  // orbit angle at path start, step, rotation
-    DensityRegs dens;
-};
-
-// Adds an increment to a (hi, lo) pair and renormalises so that hi is the
-// FP32 rounding of hi + lo.
-__device__ __forceinline__ void comp_add(float &hi, float &lo, float inc) {
-    const float t = lo + inc;
-    const float s = hi + t;
-    lo = (hi - s) + t;
-    hi = s;
-}
-
-// One Euler-Maruyama step with centre offset (ox, oy); returns true if the
-// new point is outside the closed unit square.  UNIFORM: every step has
-// length dt (t/dt integral), so the last-step selection is compiled out.
-template <int KIND, bool UNIFORM>
-__device__ __forceinline__ bool em_step(Lane &L, uint32_t ra, uint32_t rb, float ox, float oy) {
-    float D = L.dt, cb = L.cbm;
-    if constexpr (!UNIFORM) {
-        const bool last = (L.k == L.K - 1);
-        D = last ? L.dt_last : D;
-        cb = last ? L.cbm_last : cb;
-    }
-    float dwx, dwy;
-    brownian_increment(ra, rb, cb, dwx, dwy);
-    float bx, by;
-    drift<KIND>(L.dens, ox, oy, L.xh, L.yh, bx, by);
-    comp_add(L.xh, L.xl, fmaf(bx, D, dwx));
-    comp_add(L.yh, L.yl, fmaf(by, D, dwy));
-    L.k += 1;
-    // Outside the closed square.  hi is the rounded position; (hi - 1) is
-    // exact near 1, so the tests against 1 see the lo part too.
-    const float lo = fminf(L.xh, L.yh);
-    const float hi = fmaxf((L.xh - 1.f) + L.xl, (L.yh - 1.f) + L.yl);
-    return (lo < 0.f) | (hi > 0.f);
-}
-
-__device__ __forceinline__ float grid_bilinear(const double *g, int n, float x, float y) {
-    const float fx = x * (float)n, fy = y * (float)n;
-    int i = (int)floorf(fx), j = (int)floorf(fy);
-    i = min(max(i, 0), n - 1);
-    j = min(max(j, 0), n - 1);
-    const float ax = fx - (float)i, ay = fy - (float)j;
-    const double *r0 = g + (int64_t)j * (n + 1);
-    const double *r1 = r0 + (n + 1);
-    const float v00 = (float)r0[i], v01 = (float)r0[i + 1];
-    const float v10 = (float)r1[i], v11 = (float)r1[i + 1];
-    return (1.f - ay) * ((1.f - ax) * v00 + ax * v01) + ay * ((1.f - ax) * v10 + ax * v11);
-}
-
-}  // namespace
 
 template <int KIND, int TMODE, bool UNIFORM>
 __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
@@ -146,41 +83,7 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
             const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
             if (!active && rank < avail) {
-                const NodeDev nd = a.nodes[q_slot];
-                const LevelDev lv = a.levels[nd.level];
-                L.path = q_next + rank;
-                L.xh = nd.x;
-                L.yh = nd.y;
-                L.xl = nd.xlo;
-                L.yl = nd.ylo;
-                L.px = nd.x;
-                L.py = nd.y;
-                L.k = 0;
-                L.K = lv.K;
-                L.nid = nd.nid;
-                L.ctr3 = lv.ctr3;
-                L.rec = nd.out * (uint64_t)a.n_paths + L.path;
-                L.horizon = lv.horizon;
-                L.dt = lv.dt;
-                L.dt_last = lv.dt_last;
-                L.cbm = lv.cbm;
-                L.cbm_last = lv.cbm_last;
-                L.rev0 = lv.rev0;
-                L.drev = lv.drev;
-                L.cos_d = lv.cos_d;
-                L.sin_d = lv.sin_d;
-                L.dens.amp = lv.amp;
-                L.dens.nscale = lv.nscale;
-                L.dens.a2s = lv.a2s;
-                L.dens.cx = lv.cx;
-                L.dens.cy = lv.cy;
-                L.dens.orbit_r = lv.orbit_r;
-                L.dens.omega_rev = lv.omega_rev;
-                L.ox = 0.f;
-                L.oy = 0.f;
-                if constexpr ((KIND == KIND_MOVING || KIND == KIND_TWO) && TMODE == TIME_FROZEN) {
-                    orbit(L.dens, lv.t_freeze, L.ox, L.oy);
-                }
+                lane_start<KIND, TMODE>(L, a.nodes[q_slot], a.levels, q_next + rank, a.n_paths);
                 active = true;
             }
             const uint32_t n_need = (uint32_t)__popcll(need);
@@ -221,35 +124,7 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
             if (out || L.k >= L.K) {
                 // ---- score (eq. (7b)) --------------------------------------
                 float sx, sy;
-                const int kind = out ? a.bdry_kind : a.init_kind;
-                float x = L.xh, y = L.yh;
-                float lx = L.xl, ly = L.yl;
-                if (out && a.score_mode == FK_SCORE_PROJECT) {
-                    if (x < 0.f || x > 1.f) { x = fminf(fmaxf(x, 0.f), 1.f); lx = 0.f; }
-                    if (y < 0.f || y > 1.f) { y = fminf(fmaxf(y, 0.f), 1.f); ly = 0.f; }
-                }
-                if (kind == FK_DATA_IDENTITY) {
-                    // Relative to the start point when both data kinds are
-                    // the identity (the reduction adds it back), else absolute.
-                    const float bx0 = a.shift ? L.px : 0.f, by0 = a.shift ? L.py : 0.f;
-                    sx = (x - bx0) + lx;
-                    sy = (y - by0) + ly;
-                } else if (kind == FK_DATA_SIN) {
-                    float v = sin_mode(x, y);
-                    if (out) {
-                        // elapsed time since the initial data: t - s_kappa
-                        const float s = (L.k >= L.K) ? L.horizon : (float)L.k * L.dt;
-                        v *= hw_exp2(-2.f * 9.8696044f * 1.44269504f * (L.horizon - s));
-                    }
-                    sx = v;
-                    sy = v;
-                } else if (kind == FK_DATA_GRID) {
-                    sx = grid_bilinear(a.grid_xi, a.grid_n, x, y);
-                    sy = grid_bilinear(a.grid_eta, a.grid_n, x, y);
-                } else {
-                    sx = 0.f;
-                    sy = 0.f;
-                }
+                score_path(a, L, out, sx, sy);
                 a.scores[L.rec] = make_float2(sx, sy);
                 if (a.exit_step) a.exit_step[L.rec] = out ? L.k : -1;
                 active = false;

@@ -1,0 +1,140 @@
+"""The control-variate network on the GPU against the FP64 oracle evaluated
+with the same BF16 weights: forward-mode channels, the training gradient,
+Adam, training progress, and the control-variate interface solve."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle.mlp as M
+import workloads as W
+from parity import assert_parity
+
+pytestmark = pytest.mark.gpu
+THREADS = min(16, os.cpu_count() or 1)
+T = W.CV_T_SCALE
+
+
+def curved_params(seed=1):
+    rng = np.random.default_rng(seed)
+    return (W.mlp_init(seed) * 2.5 + 0.05 * rng.standard_normal(M.N_PARAMS)).astype(np.float32)
+
+
+def cuda32(a):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a, dtype=np.float32), device="cuda")
+
+
+def test_eval_matches_oracle(fk):
+    import torch
+    cv = fk.FkCv(curved_params(), T)
+    _, bf = cv.params()
+    assert np.array_equal(bf, M.bf16_round(curved_params()))
+    rng = np.random.default_rng(0)
+    n = 1000                                   # ragged: 15 full wavefronts and a partial one
+    txy = np.stack([rng.uniform(0, T, n), rng.uniform(0, 1, n), rng.uniform(0, 1, n)], 1).astype(np.float32)
+    print(f"[gpu] cv eval n={n}", flush=True)
+    g = cv.eval(cuda32(txy))
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    t64 = txy.astype(np.float64)
+    fm = M.forward_mode(bf, t64[:, 0], t64[:, 1], t64[:, 2], T)
+    for k, key in enumerate(("val", "dx", "dy", "dt", "lap")):
+        scale = np.abs(fm[key]).max()
+        err = np.abs(g[:, :, k] - fm[key]).max() / scale
+        print(f"channel {key}: max rel err {err:.2e} (scale {scale:.3g})", flush=True)
+        assert err < 2e-4, key
+    cv.close()
+
+
+def test_grad_matches_oracle(fk):
+    import torch
+    cv = fk.FkCv(curved_params(2), T)
+    _, bf = cv.params()
+    rng = np.random.default_rng(4)
+    n = 700                                    # ragged last tile
+    txy = np.stack([rng.uniform(0, T, n), rng.uniform(0, 1, n), rng.uniform(0, 1, n)], 1).astype(np.float32)
+    target = np.stack([txy[:, 1] + 0.05 * np.sin(6 * txy[:, 2]), txy[:, 2] - 0.03 * txy[:, 0] / T], 1)
+    g, loss = cv.grad(cuda32(txy), cuda32(target))
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    ref_loss, ref = M.loss_and_grad(bf, txy.astype(np.float64), target.astype(np.float32).astype(np.float64), T)
+    cos = float(g @ ref / (np.linalg.norm(g) * np.linalg.norm(ref)))
+    rel = float(np.linalg.norm(g - ref) / np.linalg.norm(ref))
+    print(f"grad cosine {cos:.6f}, rel err {rel:.2e}; loss {float(loss.item()):.6e} vs {ref_loss:.6e}", flush=True)
+    assert cos >= 0.999 and rel <= 2e-2
+    assert abs(float(loss.item()) - ref_loss) <= 1e-2 * ref_loss
+    cv.close()
+
+
+def test_adam_matches_oracle(fk):
+    import torch
+    p0 = curved_params(3)
+    cv = fk.FkCv(p0, T)
+    rng = np.random.default_rng(5)
+    p, m, v = p0.astype(np.float64), np.zeros(M.N_PARAMS), np.zeros(M.N_PARAMS)
+    for step in range(1, 11):
+        grad = (rng.standard_normal(M.N_PARAMS) * 1e-2).astype(np.float32)
+        cv.adam_apply(cuda32(grad), 1e-3)
+        p, m, v = M.adam_step(p, grad.astype(np.float64), m, v, step, 1e-3)
+    torch.cuda.synchronize()
+    master, bf = cv.params()
+    assert np.abs(master - p).max() <= 1e-6 * max(1.0, np.abs(p).max())
+    assert np.array_equal(bf, M.bf16_round(master))
+    cv.close()
+
+
+def test_training_reduces_loss(fk):
+    import torch
+    cv = fk.FkCv(W.mlp_init(0), T)
+    rng = np.random.default_rng(6)
+    n = 20000
+    txy = np.stack([rng.uniform(0, T, n), rng.uniform(0, 1, n), rng.uniform(0, 1, n)], 1).astype(np.float32)
+    target = np.stack([txy[:, 1] + 0.05 * np.sin(np.pi * txy[:, 1]) * np.sin(np.pi * txy[:, 2]),
+                       txy[:, 2] - 0.04 * np.sin(np.pi * txy[:, 1]) * txy[:, 0] / T], 1).astype(np.float32)
+    loss = cv.train(cuda32(txy), cuda32(target), steps=600, batch=2048, lr=3e-3, seed=1)
+    torch.cuda.synchronize()
+    loss = loss.cpu().numpy()
+    print(f"training loss {loss[0]:.3e} -> {loss[-1]:.3e}", flush=True)
+    assert np.all(np.isfinite(loss)) and loss[-20:].mean() < 0.05 * loss[:5].mean()
+    # the trained network, evaluated in FP64 by the oracle, fits the targets
+    _, bf = cv.params()
+    fit = M.forward(bf, *txy.astype(np.float64).T, T)
+    assert np.sqrt(np.mean((fit - target) ** 2)) < 0.02
+    cv.close()
+
+
+@pytest.mark.parametrize("stride", [2, 6])
+def test_cv_solve_against_oracle(fk, oracle_mod, stride):
+    import torch
+    params = W.mlp_init(7)          # initial-scale network: moderate derivatives
+    cv = fk.FkCv(params, T)
+    _, bf = cv.params()
+    dens = W.moving_bump()
+    pts = W.interface_nodes(4, 4, 16)[::3]
+    t, dt, N = 0.01, 1e-4, 256
+    print(f"[gpu] cv solve stride={stride} nodes={len(pts)} N={N}", flush=True)
+    g = fk.fk_interface_solve_cv(dens, W.Data(), pts, t, dt, N, cv, stride=stride, seed=3, exit_step=True,
+                                 cv_scores=True)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in g.items() if not k.startswith("_")}
+    o = oracle_mod.fk_solve_cv(dens, W.Data(), pts, t, dt, N, seed=3, uhat=oracle_mod.UHAT_MLP, flat=bf,
+                               t_scale=T, stride=stride, want_scores=True, want_exit=True, threads=THREADS)
+    # plain part: the same paths as the plain solver, to the plain contract
+    plain = {"xi": g["plain_xi"], "eta": g["plain_eta"], "se_xi": g["plain_se_xi"], "se_eta": g["plain_se_eta"],
+             "exit_step": g["exit_step"]}
+    po = {"mean": o["plain_mean"], "se": o["plain_se"], "exit_step": o["exit_step"]}
+    assert_parity(plain, po, pts, label="plain part:")
+    # CV part: per-path scores and node estimates
+    same = g["exit_step"] == o["exit_step"]
+    ds = np.abs(g["cv_scores"].astype(np.float64) - o["cv_scores"])[same]
+    mean_g = np.stack([g["xi"], g["eta"]], 1)
+    d = np.abs(mean_g - o["mean"])
+    # The GPU network carries ~1e-5 relative error (split BF16 on MFMA,
+    # FP32 accumulation), so a score sum(r ds) of size S is good to ~1e-5 S.
+    smax = np.abs(o["cv_scores"]).max()
+    print(f"cv: max |score diff| {ds.max():.2e} (max |score| {smax:.3g}), max |mean diff| {d.max():.2e}, "
+          f"se ratio cv/plain {np.median(o['se'] / o['plain_se']):.3f}", flush=True)
+    assert ds.max() < 2e-5 * max(1.0, smax)
+    assert np.all(d <= 3 * o["se"]) and np.all(d <= 1e-5 * max(1.0, smax))
+    cv.close()
