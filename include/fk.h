@@ -281,8 +281,9 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
 /*
  * Kernel timing.  While enabled (per calling thread), fk_interface_solve
  * records HIP events on its stream around the path kernel and around the
- * reduction kernel; fk_timing_last waits for the last recorded events and
- * returns their durations in milliseconds.  Disabled by default (no events
+ * reduction kernel (fk_interface_solve_cv: around its start-point network
+ * kernel plus path kernel, and around its reductions); fk_timing_last waits
+ * for the last recorded events and returns their durations in milliseconds.  Disabled by default (no events
  * are recorded).  fk_timing_last returns FK_E_INVAL if nothing was recorded.
  */
 int fk_timing_enable(int enable);

@@ -75,7 +75,7 @@ def lib():
                                      P, P, ctypes.c_int64,
                                      ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64,
                                      ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
-                                     ctypes.c_int, P, ctypes.c_double, ctypes.c_int,
+                                     ctypes.c_int, P, ctypes.c_double, ctypes.c_int, ctypes.c_int,
                                      P, P, P, P, P, P]
         L.or_fk_solve_cv.restype = ctypes.c_int
         L.or_fd_solve.argtypes = [ctypes.c_int, ctypes.c_int, P, ctypes.c_int, ctypes.c_int,
@@ -186,6 +186,7 @@ def fk_paths(dens, data, pts, node_ids, path_ids, t, dt, seed=0, level_id=0, str
 
 
 UHAT_MLP, UHAT_LINEAR, UHAT_SIN, UHAT_ZERO = 0, 1, 2, 3
+CV_DYNKIN, CV_MARTINGALE = 0, 1   # forms of the control-variate estimator
 
 
 def mlp_eval_c(flat, t_scale, txy) -> np.ndarray:
@@ -198,9 +199,11 @@ def mlp_eval_c(flat, t_scale, txy) -> np.ndarray:
 
 
 def fk_solve_cv(dens, data, pts, t, dt, n_paths, seed=0, level_id=0, stream=0, node_ids=None,
-                uhat=UHAT_MLP, flat=None, t_scale=0.1, stride=1, want_scores=False, want_exit=False, threads=0):
-    """Control-variate oracle (Dynkin form).  Returns dict: mean/se (CV),
-    plain_mean/plain_se (same paths), optional cv_scores [n,N,2], exit_step."""
+                uhat=UHAT_MLP, flat=None, t_scale=0.1, stride=1, form=CV_DYNKIN, want_scores=False, want_exit=False,
+                threads=0):
+    """Control-variate oracle, Dynkin form (form=CV_DYNKIN) or martingale
+    form (CV_MARTINGALE).  Returns dict: mean/se (CV), plain_mean/plain_se
+    (same paths), optional cv_scores [n,N,2], exit_step."""
     pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 2)
     n = pts.shape[0]
     par = dens.params()
@@ -219,7 +222,7 @@ def fk_solve_cv(dens, data, pts, t, dt, n_paths, seed=0, level_id=0, stream=0, n
                               data.init_kind, data.bdry_kind, data.score_mode, data.t_init,
                               _ptr(gx), _ptr(gy), gn, _ptr(pts), _ptr(ids), n,
                               t, dt, n_paths, seed, level_id, stream, threads,
-                              uhat, _ptr(fl), t_scale, stride,
+                              uhat, _ptr(fl), t_scale, stride, form,
                               _ptr(out["mean"]), _ptr(out["se"]), _ptr(out["plain_mean"]), _ptr(out["plain_se"]),
                               _ptr(cs), _ptr(ex))
     if rc != 0:

@@ -618,6 +618,65 @@ static int64_t run_path_cv(const or_problem *pb, const or_uhat *u, int stride, d
     return exit_k;
 }
 
+/*
+ * One path with the control variate in martingale form (Ito's formula
+ * applied to u_hat along the path): the score is g - sum_j G_j . dB_j, where
+ * dB_j is the Brownian part (the sum of the sqrt(2 D_k) z_k) of the path's
+ * steps in block j and G_j = grad u_hat at the block's first state, blocks
+ * starting every `stride` steps from the path's start and the last one
+ * closed at the path's end.  Each G_j is fixed before the increments it
+ * multiplies, so the sum has mean zero for the discrete chain itself.
+ */
+static int64_t run_path_mg(const or_problem *pb, const or_uhat *u, int stride, double px, double py,
+                           uint32_t path, uint32_t node, double plain[2], double cv[2])
+{
+    double x = px, y = py, s = 0.0;
+    uint32_t r[4] = {0, 0, 0, 0};
+    double G[2][2] = {{0.0, 0.0}, {0.0, 0.0}}, dB[2] = {0.0, 0.0}, M[2] = {0.0, 0.0};
+    int64_t exit_k = -1;
+    for (int64_t k = 0; k < pb->K; ++k) {
+        if ((k & 1) == 0) {
+            uint32_t ctr[4] = {(uint32_t)(k >> 1), path, node, pb->ctr3};
+            or_philox4x32_10(ctr, pb->key, r);
+        }
+        double z0, z1;
+        if ((k & 1) == 0) box_muller(r[0], r[1], &z0, &z1);
+        else box_muller(r[2], r[3], &z0, &z1);
+        double D = (k == pb->K - 1) ? pb->t - (double)(pb->K - 1) * pb->dt : pb->dt;
+        double tau = (pb->time_mode == 0) ? pb->t_init + pb->t - s : pb->par[6];
+        double bx, by;
+        drift(pb->kind, pb->par, tau, x, y, &bx, &by);
+        if (k % stride == 0) {
+            double e[2][5];
+            for (int c = 0; c < 2; ++c) M[c] += G[c][0] * dB[0] + G[c][1] * dB[1];
+            dB[0] = dB[1] = 0.0;
+            uhat_eval(u, pb->t_init + pb->t - s, x, y, e);
+            for (int c = 0; c < 2; ++c) {
+                G[c][0] = e[c][1];
+                G[c][1] = e[c][2];
+            }
+        }
+        double sd = sqrt(2.0 * D);
+        double w0 = sd * z0, w1 = sd * z1;
+        x = x + bx * D + w0;
+        y = y + by * D + w1;
+        s = s + D;
+        dB[0] += w0;
+        dB[1] += w1;
+        if (x < 0.0 || x > 1.0 || y < 0.0 || y > 1.0) {
+            boundary_value(&pb->data, pb->t - s, x, y, &plain[0], &plain[1]);
+            exit_k = k + 1;
+            break;
+        }
+    }
+    if (exit_k < 0) initial_value(&pb->data, x, y, &plain[0], &plain[1]);
+    for (int c = 0; c < 2; ++c) {
+        M[c] += G[c][0] * dB[0] + G[c][1] * dB[1];
+        cv[c] = plain[c] - M[c];
+    }
+    return exit_k;
+}
+
 static void two_pass(const double *sc, int64_t i, int64_t n_paths, double *mean, double *se)
 {
     for (int c = 0; c < 2; ++c) {
@@ -634,10 +693,10 @@ static void two_pass(const double *sc, int64_t i, int64_t n_paths, double *mean,
 }
 
 /*
- * Control-variate solve.  mean/se: the CV estimate u_hat(t_init + t, P) +
- * mean(cv score) and its standard error; plain_mean/plain_se: the plain
- * estimate from the same paths.  cv_scores [n][N][2] and exit_step [n][N]
- * optional.
+ * Control-variate solve.  form 0 (Dynkin): mean/se are the CV estimate
+ * u_hat(t_init + t, P) + mean(cv score) and its standard error; form 1
+ * (martingale): mean(cv score).  plain_mean/plain_se: the plain estimate from
+ * the same paths.  cv_scores [n][N][2] and exit_step [n][N] optional.
  */
 int or_fk_solve_cv(int kind, int time_mode, const double *par,
                    int init_kind, int bdry_kind, int score_mode, double t_init,
@@ -645,11 +704,12 @@ int or_fk_solve_cv(int kind, int time_mode, const double *par,
                    const double *pts, const int64_t *node_ids, int64_t n_nodes,
                    double t, double dt, int64_t n_paths, uint64_t seed, uint32_t level_id,
                    uint32_t stream, int n_threads,
-                   int uhat_kind, const double *flat, double t_scale, int stride,
+                   int uhat_kind, const double *flat, double t_scale, int stride, int form,
                    double *mean, double *se, double *plain_mean, double *plain_se,
                    double *cv_scores, int32_t *exit_step)
 {
     if (n_nodes < 0 || n_paths < 2 || !(dt > 0.0) || !(t >= 0.0) || stride < 1) return -1;
+    if (form != 0 && form != 1) return -1;
     if (uhat_kind == 0 && !flat) return -1;
     or_problem pb;
     pb.kind = kind;
@@ -683,12 +743,15 @@ int or_fk_solve_cv(int kind, int time_mode, const double *par,
     for (int64_t g = 0; g < total; ++g) {
         int64_t i = g / n_paths, p = g % n_paths;
         uint32_t nid = (uint32_t)(node_ids ? node_ids[i] : i);
-        int64_t e = run_path_cv(&pb, &u, stride, pts[2 * i], pts[2 * i + 1], (uint32_t)p, nid, &pl[2 * g], &cs[2 * g]);
+        int64_t e = form == 0
+                        ? run_path_cv(&pb, &u, stride, pts[2 * i], pts[2 * i + 1], (uint32_t)p, nid, &pl[2 * g], &cs[2 * g])
+                        : run_path_mg(&pb, &u, stride, pts[2 * i], pts[2 * i + 1], (uint32_t)p, nid, &pl[2 * g], &cs[2 * g]);
         if (exit_step) exit_step[g] = (int32_t)e;
     }
     for (int64_t i = 0; i < n_nodes; ++i) {
         two_pass(pl, i, n_paths, plain_mean, plain_se);
         two_pass(cs, i, n_paths, mean, se);
+        if (form == 1) continue;
         double e[2][5];
         uhat_eval(&u, t_init + t, pts[2 * i], pts[2 * i + 1], e);
         mean[2 * i] += e[0][0];

@@ -1,0 +1,69 @@
+"""TEST INFRASTRUCTURE -- FP64 oracle of one stochastic domain-decomposition
+mesh step (Sect. 4), composed of the pinned pieces in the paper's order:
+
+1. the density is frozen at t^n;
+2. the interface values at t^{n+1} = t^n + dt_mesh are Feynman-Kac Monte-Carlo
+   estimates (Sect. 3) with the mesh at t^n as initial data, bilinear in the
+   nodal grid, and the identity map as boundary data -- plain (fk_solve) or,
+   given a network, the control-variate form (fk_solve_cv);
+3. each sub-domain takes one backward-Euler step with those interface values
+   as Dirichlet data (subdomain_be_step).
+
+Only tests, the package's smoke check and the benchmark's CPU baseline use it.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+import oracle as _oracle
+import oracle.subdomain as _sub
+
+DATA_IDENTITY = 0
+DATA_GRID = 3
+UHAT_MLP = 1
+
+
+class _GridData:
+    """The fields the oracle's solvers read for grid initial data."""
+
+    def __init__(self, t_init, xi, eta):
+        self.init_kind = DATA_GRID
+        self.bdry_kind = DATA_IDENTITY
+        self.score_mode = 0
+        self.t_init = float(t_init)
+        self.grid_xi = np.ascontiguousarray(xi, dtype=np.float64)
+        self.grid_eta = np.ascontiguousarray(eta, dtype=np.float64)
+        self.grid_n = self.grid_xi.shape[0] - 1
+
+
+def interface_points(px: int, m: int) -> np.ndarray:
+    """Coordinates of the interface nodes in the sub-domain solve's order."""
+    ij = _sub.interface_index(px, m)
+    return ij.astype(np.float64) / (px * m)
+
+
+def interface_solve(dens, tn, dt_mesh, substeps, px, m, xi_n, eta_n, n_paths, seed=0, level_id=0,
+                    node_ids=None, flat=None, t_scale=0.1, stride=10, threads=0):
+    """Step 2: interface estimates (dict with mean [n, 2], se [n, 2]) at the
+    nodes node_ids (default all) of px x px sub-domains."""
+    pts = interface_points(px, m)
+    if node_ids is not None:
+        # the nodes keep their indices in the full set: those key the paths' counters
+        node_ids = np.asarray(node_ids, dtype=np.int64)
+        pts = pts[node_ids]
+    data = _GridData(tn, xi_n, eta_n)
+    dt = dt_mesh / substeps
+    if flat is None:
+        return _oracle.fk_solve(dens, data, pts, dt_mesh, dt, n_paths, seed=seed, level_id=level_id,
+                                node_ids=node_ids, threads=threads)
+    return _oracle.fk_solve_cv(dens, data, pts, dt_mesh, dt, n_paths, seed=seed, level_id=level_id,
+                               node_ids=node_ids, uhat=UHAT_MLP, flat=flat, t_scale=t_scale, stride=stride,
+                               threads=threads)
+
+
+def dd_step(dens, tn, dt_mesh, substeps, px, m, xi_n, eta_n, n_paths, seed=0, level_id=0, threads=0):
+    """One plain mesh step: returns (xi, eta, interface estimates)."""
+    mc = interface_solve(dens, tn, dt_mesh, substeps, px, m, xi_n, eta_n, n_paths, seed=seed,
+                         level_id=level_id, threads=threads)
+    xi, eta = _sub.subdomain_be_step(dens, tn, dt_mesh, px, m, xi_n, eta_n, mc["mean"][:, 0], mc["mean"][:, 1])
+    return xi, eta, mc

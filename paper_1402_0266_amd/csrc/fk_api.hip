@@ -226,6 +226,12 @@ static hipError_t timing_mark(bool on, int i, hipStream_t s) {
     return hipEventRecord(g_timing.ev[i], s);
 }
 
+hipError_t timing_record(int i, hipStream_t s) {
+    hipError_t e = timing_mark(g_timing.enabled, i, s);
+    if (e == hipSuccess && i == 2 && g_timing.enabled) g_timing.recorded = true;
+    return e;
+}
+
 int check_chunks(int64_t n_nodes, int64_t n_paths, const fk_plan &pl) {
     const int64_t cpn = (n_paths + pl.chunk - 1) / pl.chunk;
     if (n_nodes * cpn >= 0xffffffffLL) return fail(FK_E_INVAL, "too many work chunks; raise plan chunk");

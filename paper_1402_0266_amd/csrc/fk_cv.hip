@@ -1039,6 +1039,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     na.outs_cv = (OutDev *)(ws + lay.outs_cv);
     na.r0 = (float2 *)(ws + lay.r0);
     const float ts2 = 2.f / cv->t_scale;
+    if ((e = timing_record(0, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     if ((e = cv_dispatch<CvNodeF>(T.kind, T.time_mode, true, na, (const uint16_t *)cv->s.bf, ts2, stream)) !=
         hipSuccess)
         return hip_fail(e, "node kernel launch");
@@ -1070,6 +1071,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
     if ((e = cv_dispatch<CvLaunchF>(T.kind, T.time_mode, T.uniform, a, c, n_cu * bpc, stream)) != hipSuccess)
         return hip_fail(e, "control-variate path kernel launch");
+    if ((e = timing_record(1, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
 
     ReduceArgs r{};
     r.scores = c.cv_scores;
@@ -1092,6 +1094,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         q.se_eta = plain_se_eta;
         if ((e = launch_reduce(q, stream)) != hipSuccess) return hip_fail(e, "reduce kernel launch");
     }
+    if ((e = timing_record(2, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     return FK_OK;
 }
 

@@ -133,6 +133,9 @@ int device_cus(int *n_cu);
 // Queues zero-counters, path kernel and reduction on the stream.  With
 // allow_timing, records the timing events when timing is enabled.
 int enqueue_solve(const SolveLaunch &S, hipStream_t stream, bool allow_timing);
+// Timing events of the calling thread (no-ops while timing is disabled):
+// 0 before the path kernels, 1 after them, 2 after the reductions.
+hipError_t timing_record(int i, hipStream_t s);
 
 // Launch helpers implemented in fk_paths.hip.
 hipError_t launch_zero_u32(uint32_t *p, int n_words, hipStream_t s);

@@ -1,0 +1,245 @@
+"""Time-dependent mesh generation by stochastic domain decomposition (Sect. 4).
+
+One mesh step advances the nodal map (xi, eta) from t^n to t^{n+1} =
+t^n + dt_mesh:
+
+1. the density is frozen at t^n (Sect. 4);
+2. the interface values at t^{n+1} come from the Feynman-Kac Monte-Carlo
+   solve (Sect. 3), with the current mesh as initial data (bilinear in the
+   device grid) and the identity map as outer boundary data; with a trained
+   network the control-variate form of the estimator is used;
+3. every sub-domain takes one implicit backward-Euler step with those
+   interface values as Dirichlet data (Sect. 4);
+4. the mesh quality (minimum Jacobian, maximum skewness) is recorded.
+
+The network u_hat(t, x, y) is refitted every `refit_every` steps on labels
+the run has produced (at their times t^{n+1}), starting from the initial mesh
+at t = 0: either the interface estimates themselves, or (default) the mesh
+values at the grid nodes within `band` of an interface line, where the paths
+travel -- interface estimates fix the network along the lines only, while the
+estimator needs its derivatives across them too.  All arithmetic runs in libfk.so
+kernels on one stream; this module sequences the calls and keeps the label
+buffers.  The run stays on the device between steps: nothing is copied to
+the host until `qualities()` / `mesh()` are called.
+"""
+from __future__ import annotations
+
+from dataclasses import dataclass
+
+import numpy as np
+
+from . import (FkCv, fk_interface_solve, fk_interface_solve_cv, fk_mesh_quality, subdomain_solve,
+               subdomain_workspace_bytes)
+
+DATA_GRID = 3
+DATA_IDENTITY = 0
+KIND_TWO_BUMPS = 3
+TIME_FROZEN = 1
+
+
+@dataclass(frozen=True)
+class MeshRunConfig:
+    px: int = 8                 # px x px sub-domains
+    m: int = 96                 # cells per sub-domain side; grid N = px m
+    dt_mesh: float = 5e-4
+    substeps: int = 20          # Euler-Maruyama steps per mesh step
+    n_steps: int = 200
+    n_paths: int = 1 << 14
+    refit_every: int = 20       # 0: plain Monte Carlo throughout
+    cv_stride: int = 10
+    train_steps: int = 2000
+    train_batch: int = 8192
+    lr: float = 1e-3
+    t_scale: float = 0.1        # network time input range [0, t_scale]
+    labels: str = "band"        # "band": mesh values near the interfaces; "interface": the MC estimates
+    band: float = 0.06          # half-width of the label band around each interface line
+    band_stride: int = 3        # grid stride of the band samples
+    label_levels: int = 40      # most recent label levels kept for training
+    seed: int = 0
+
+
+@dataclass(frozen=True)
+class Density:
+    """Fields of the C struct fk_density."""
+    kind: int
+    time_mode: int
+    amp: float
+    width2: float
+    cx: float
+    cy: float
+    orbit_r: float
+    omega: float
+    t_freeze: float
+
+
+@dataclass(frozen=True)
+class GridData:
+    """Fields of the C struct fk_data for grid initial data and identity
+    boundary data (the grid pointers are passed separately)."""
+    t_init: float
+    init_kind: int = DATA_GRID
+    bdry_kind: int = DATA_IDENTITY
+    score_mode: int = 0
+
+
+def two_bump_density(t_freeze: float) -> Density:
+    """Two counter-rotating bumps (amplitude 30, width^2 0.003, orbit radius
+    1/4 about the centre, one turn per unit time) frozen at t_freeze."""
+    return Density(KIND_TWO_BUMPS, TIME_FROZEN, amp=30.0, width2=0.003, cx=0.5, cy=0.5, orbit_r=0.25,
+                   omega=2.0 * np.pi, t_freeze=t_freeze)
+
+
+def interface_nodes(px: int, m: int) -> np.ndarray:
+    """Interface nodes of px x px sub-domains on the (px m)-cell grid, in the
+    order the sub-domain solve reads its Dirichlet data (vertical lines, then
+    horizontal lines without the crossings)."""
+    N = px * m
+    pts = [(a / px, j / N) for a in range(1, px) for j in range(1, N)]
+    pts += [(i / N, c / px) for c in range(1, px) for i in range(1, N) if i % m]
+    return np.array(pts, dtype=np.float64).reshape(-1, 2)
+
+
+def band_index(px: int, m: int, band: float, stride: int) -> np.ndarray:
+    """Flat grid indices j (N+1) + i of the nodes on every stride-th grid line
+    that lie within `band` of an interface line x = a/px or y = c/px."""
+    N = px * m
+    k = np.arange(0, N + 1, stride)
+    c = k / N
+    lines = np.arange(1, px) / px
+    near = np.abs(c[:, None] - lines[None, :]).min(1) <= band + 1e-12
+    jj, ii = np.meshgrid(k, k, indexing="ij")
+    mask = near[:, None] | near[None, :]
+    return (jj[mask] * (N + 1) + ii[mask]).astype(np.int64)
+
+
+class MeshRun:
+    """The mesh-step driver on one GPU.
+
+    `density_fn(t)` returns the density frozen at t (default: the two
+    counter-rotating bumps).  `init_params` seeds the network (FP32 [8706]);
+    it is required when refit_every > 0.
+    """
+
+    def __init__(self, cfg: MeshRunConfig, init_params=None, density_fn=two_bump_density, device="cuda"):
+        import torch
+        self.torch = torch
+        self.cfg = cfg
+        self.dev = torch.device(device)
+        self.density_fn = density_fn
+        self.N = cfg.px * cfg.m
+        self.pts = interface_nodes(cfg.px, cfg.m)
+        self.n_nodes = self.pts.shape[0]
+        x = torch.arange(self.N + 1, dtype=torch.float64, device=self.dev) / self.N
+        self.xi = x.repeat(self.N + 1, 1).contiguous()            # [j][i] = x_i
+        self.eta = x[:, None].repeat(1, self.N + 1).contiguous()  # [j][i] = y_j
+        self.spare = (torch.empty_like(self.xi), torch.empty_like(self.eta))
+        self.n = 0
+        self._quality = torch.zeros((cfg.n_steps, 2), dtype=torch.float64, device=self.dev)
+        self._iface = torch.zeros((cfg.n_steps, self.n_nodes, 2), dtype=torch.float64, device=self.dev)
+        self._se = torch.zeros((cfg.n_steps, self.n_nodes, 2), dtype=torch.float64, device=self.dev)
+        self.cv = None
+        self.used_cv = np.zeros(cfg.n_steps, dtype=bool)
+        self.workspace = None
+        self.sub_workspace = torch.empty(max(subdomain_workspace_bytes(cfg.px, cfg.m), 256), dtype=torch.uint8,
+                                         device=self.dev)
+        self.losses = []
+        if cfg.refit_every > 0:
+            if init_params is None:
+                raise ValueError("refit_every > 0 needs initial network parameters")
+            self.cv = FkCv(init_params, cfg.t_scale)
+            if cfg.labels == "interface":
+                lab_pts = self.pts
+                self._band_idx = None
+            elif cfg.labels == "band":
+                idx = band_index(cfg.px, cfg.m, cfg.band, cfg.band_stride)
+                lab_pts = np.stack([idx % (self.N + 1), idx // (self.N + 1)], 1) / self.N
+                self._band_idx = torch.tensor(idx, dtype=torch.int64, device=self.dev)
+            else:
+                raise ValueError("labels must be 'band' or 'interface'")
+            # label ring: level-major (t, x, y) and (xi, eta); level 0 is the initial mesh
+            L, n_lab = cfg.label_levels, lab_pts.shape[0]
+            self._lab_txy = torch.zeros((L, n_lab, 3), dtype=torch.float32, device=self.dev)
+            self._lab_val = torch.zeros((L, n_lab, 2), dtype=torch.float32, device=self.dev)
+            self._lab_count = 0
+            p = torch.tensor(lab_pts, dtype=torch.float32, device=self.dev)
+            self._lab_pts = p
+            self._add_labels(0.0, p[:, 0], p[:, 1])
+
+    # -- labels ----------------------------------------------------------------
+    def _add_labels(self, t, xi, eta):
+        L = self.cfg.label_levels
+        slot = self._lab_count % L
+        self._lab_txy[slot, :, 0] = float(t)
+        self._lab_txy[slot, :, 1:] = self._lab_pts
+        self._lab_val[slot, :, 0] = xi.to(self.torch.float32)
+        self._lab_val[slot, :, 1] = eta.to(self.torch.float32)
+        self._lab_count += 1
+
+    def refit(self):
+        """Train the network on the label levels held (Adam state carries over)."""
+        k = min(self._lab_count, self.cfg.label_levels)
+        txy = self._lab_txy[:k].reshape(-1, 3)
+        val = self._lab_val[:k].reshape(-1, 2)
+        loss = self.cv.train(txy, val, steps=self.cfg.train_steps, batch=self.cfg.train_batch, lr=self.cfg.lr,
+                             seed=self.cfg.seed + 7919 * (self.n + 1))
+        self.losses.append(loss)
+
+    # -- one mesh step -----------------------------------------------------------
+    def step(self):
+        cfg = self.cfg
+        if self.n >= cfg.n_steps:
+            raise RuntimeError("the run has taken all its steps")
+        tn = self.n * cfg.dt_mesh
+        dens = self.density_fn(tn)
+        data = GridData(t_init=tn)
+        grids = (self.xi.view(-1), self.eta.view(-1))
+        if self.cv is not None and self.n % cfg.refit_every == 0:
+            self.refit()
+        dt = cfg.dt_mesh / cfg.substeps
+        if self.cv is not None:
+            out = fk_interface_solve_cv(dens, data, self.pts, cfg.dt_mesh, dt, cfg.n_paths, self.cv,
+                                        stride=cfg.cv_stride, seed=cfg.seed, level_id=self.n, plain=False,
+                                        device=self.dev, workspace=self.workspace, grids=grids)
+            self.used_cv[self.n] = True
+        else:
+            out = fk_interface_solve(dens, data, self.pts, cfg.dt_mesh, dt, cfg.n_paths, seed=cfg.seed,
+                                     level_id=self.n, device=self.dev, workspace=self.workspace, grids=grids)
+        self.workspace = out["_workspace"]
+        xi_new, eta_new = subdomain_solve(dens, tn, cfg.dt_mesh, cfg.px, cfg.m, self.xi, self.eta, out["xi"],
+                                          out["eta"], bdry_kind=DATA_IDENTITY, out=self.spare,
+                                          workspace=self.sub_workspace)
+        self._quality[self.n] = fk_mesh_quality(xi_new, eta_new)
+        self._iface[self.n, :, 0] = out["xi"]
+        self._iface[self.n, :, 1] = out["eta"]
+        self._se[self.n, :, 0] = out["se_xi"]
+        self._se[self.n, :, 1] = out["se_eta"]
+        if self.cv is not None:
+            if self._band_idx is None:
+                self._add_labels(tn + cfg.dt_mesh, out["xi"], out["eta"])
+            else:
+                self._add_labels(tn + cfg.dt_mesh, xi_new.view(-1)[self._band_idx], eta_new.view(-1)[self._band_idx])
+        self.spare = (self.xi, self.eta)
+        self.xi, self.eta = xi_new, eta_new
+        self.n += 1
+
+    def run(self, n_steps=None):
+        for _ in range(self.cfg.n_steps - self.n if n_steps is None else n_steps):
+            self.step()
+
+    # -- results (these synchronise) ---------------------------------------------
+    def qualities(self) -> np.ndarray:
+        """[steps taken, 2]: minimum Jacobian and maximum skewness after each step."""
+        return self._quality[:self.n].cpu().numpy()
+
+    def interface_values(self):
+        """([steps, nodes, 2] estimates, [steps, nodes, 2] standard errors)."""
+        return self._iface[:self.n].cpu().numpy(), self._se[:self.n].cpu().numpy()
+
+    def mesh(self):
+        """The current (xi, eta) grids on the host, [N+1, N+1] each, indexed [j][i]."""
+        return self.xi.cpu().numpy(), self.eta.cpu().numpy()
+
+    def close(self):
+        if self.cv is not None:
+            self.cv.close()
+            self.cv = None

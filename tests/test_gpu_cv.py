@@ -138,3 +138,40 @@ def test_cv_solve_against_oracle(fk, oracle_mod, stride):
     assert ds.max() < 2e-5 * max(1.0, smax)
     assert np.all(d <= 3 * o["se"]) and np.all(d <= 1e-5 * max(1.0, smax))
     cv.close()
+
+
+def test_trained_network_gain(fk):
+    """What the trained network buys on the moving-bump workload: labels from
+    plain Monte Carlo, training on the GPU, then the control-variate solve at
+    t = 0.1 on every 8th node, judged against the finite-difference
+    reference and against plain Monte Carlo on the same paths."""
+    import torch
+    from paper_1402_0266_amd import cv_pipeline as P
+    wl = W.MOVING_BUMP_1521
+    nodes = wl.nodes()
+    print("[gpu] cv gain: labels, training, solve", flush=True)
+    txy, target = P.make_labels(wl.density, wl.data, nodes, W.cv_label_levels(33, W.CV_T_SCALE), wl.dt, 256, seed=1)
+    cv = fk.FkCv(W.mlp_init(0), T)
+    loss = P.train(cv, txy, target, steps=1000, batch=8192, lr=1e-3, seed=2)
+    sub = np.arange(0, len(nodes), 8)
+    g = fk.fk_interface_solve_cv(wl.density, wl.data, nodes[sub], wl.t, wl.dt, 2048, cv, stride=20, seed=3)
+    torch.cuda.synchronize()
+    loss = loss.cpu().numpy()
+    fd = np.loadtxt(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"{wl.name}_fd.txt"))[sub]
+    ref = fd[:, 2:4]
+    assert np.abs(fd[:, :2] - nodes[sub]).max() < 1e-12
+    cvm = np.stack([g["xi"].cpu().numpy(), g["eta"].cpu().numpy()], 1)
+    plm = np.stack([g["plain_xi"].cpu().numpy(), g["plain_eta"].cpu().numpy()], 1)
+    cvs = np.stack([g["se_xi"].cpu().numpy(), g["se_eta"].cpu().numpy()], 1)
+    pls = np.stack([g["plain_se_xi"].cpu().numpy(), g["plain_se_eta"].cpu().numpy()], 1)
+    rms_cv = float(np.sqrt(np.mean((cvm - ref) ** 2)))
+    rms_pl = float(np.sqrt(np.mean((plm - ref) ** 2)))
+    ratio = float(np.mean(cvs ** 2) / np.mean(pls ** 2))
+    print(f"loss {loss[0]:.3e} -> {loss[-50:].mean():.3e}; variance ratio cv/plain {ratio:.4f}; "
+          f"RMS vs FD: cv {rms_cv:.2e}, plain {rms_pl:.2e}", flush=True)
+    assert ratio < 0.25                       # at least 4x fewer paths for the same error
+    assert rms_cv < 0.6 * rms_pl
+    # the control-variate estimate is unbiased: within its error of the FD reference
+    z = (cvm - ref) / np.sqrt(cvs ** 2 + fd[:, 4:6] ** 2)
+    assert abs(float(z.mean())) < 0.5 and float(np.sqrt(np.mean(z ** 2))) < 1.5
+    cv.close()

@@ -1,0 +1,97 @@
+"""The time-dependent mesh run on the GPU (two counter-rotating bumps, 8 x 8
+sub-domains on a 96-cell grid) against the oracle, step by step, each step
+checked from the mesh the GPU held before it:
+
+* interface estimates against the oracle's Monte-Carlo solve with the same
+  counters on a subset of the nodes (plain: 3 standard errors and 1e-5; CV:
+  with the network the GPU used in that step);
+* the assembled mesh against the oracle's sub-domain solves with the GPU's
+  interface values (FP64 round-off);
+* the recorded quality against the oracle's measures of the GPU's mesh, and
+  against the quality of the global backward-Euler step from the same mesh.
+"""
+import os
+
+import numpy as np
+import pytest
+
+import oracle.mesh_step as MS
+import oracle.subdomain as S
+import workloads as W
+
+pytestmark = pytest.mark.gpu
+THREADS = min(16, os.cpu_count() or 1)
+PX, M, D = 8, 12, 5e-4
+
+
+def _check_step(run, n, xi_n, eta_n, o_mean, o_se, sub):
+    iface, se = run.interface_values()
+    tn = n * D
+    dens = W.two_bumps(W.TIME_FROZEN, tn)
+    d = np.abs(iface[n, sub] - o_mean)
+    print(f"step {n}: max |gpu - oracle| {d.max():.2e}, max d/se {(d / o_se).max():.2f}", flush=True)
+    assert np.all(d <= 3 * o_se) and np.all(d <= 1e-5)
+    # the sub-domain solves from the GPU's interface values
+    sx, sy = S.subdomain_be_step(dens, tn, D, PX, M, xi_n, eta_n, iface[n, :, 0], iface[n, :, 1])
+    gx, gy = run.mesh()
+    assert np.abs(gx - sx).max() < 1e-12 and np.abs(gy - sy).max() < 1e-12
+    # quality: the GPU's measures of its mesh, and the global step's quality
+    q = run.qualities()[n]
+    jo, so = S.mesh_quality(gx, gy)
+    assert abs(q[0] - jo) < 1e-12 and abs(q[1] - so) < 1e-12
+    gxi, geta = S.global_be_step(dens, tn, D, PX * M, xi_n, eta_n)
+    jg, sg = S.mesh_quality(gxi, geta)
+    print(f"step {n}: quality min J {q[0]:.4f} (global step {jg:.4f}), max skew {q[1]:.4f} (global {sg:.4f})",
+          flush=True)
+    return q, (jg, sg)
+
+
+def test_plain_mesh_run_against_oracle(fk, oracle_mod):
+    from paper_1402_0266_amd.mesh_run import MeshRun, MeshRunConfig
+    n_paths = 1 << 16
+    run = MeshRun(MeshRunConfig(px=PX, m=M, n_steps=3, n_paths=n_paths, refit_every=0))
+    sub = np.arange(0, run.n_nodes, 9)
+    assert np.array_equal(run.pts, MS.interface_points(PX, M))
+    for n in range(3):
+        xi_n, eta_n = run.mesh()
+        print(f"[gpu] mesh run plain step {n}, {run.n_nodes} nodes, N={n_paths}", flush=True)
+        run.step()
+        o = MS.interface_solve(W.two_bumps(W.TIME_FROZEN, n * D), n * D, D, 20, PX, M, xi_n, eta_n, n_paths,
+                               level_id=n, node_ids=sub, threads=THREADS)
+        q, (jg, sg) = _check_step(run, n, xi_n, eta_n, o["mean"], o["se"], sub)
+        # Interface noise of 2 SE / h moves J by ~3% at this size.  From the
+        # identity mesh the first step also carries the stiff initial layer,
+        # where the exact-flow interface values and one backward-Euler step
+        # inside differ (the oracle tests pin that ten sub-steps remove it).
+        tol = 0.10 if n == 0 else 0.05
+        assert q[0] > 0 and abs(q[0] - jg) <= tol * jg and abs(q[1] - sg) <= 0.02
+    run.close()
+
+
+def test_cv_mesh_run_against_oracle(fk, oracle_mod):
+    from paper_1402_0266_amd.mesh_run import MeshRun, MeshRunConfig
+    n_paths, stride = 4096, 10
+    cfg = MeshRunConfig(px=PX, m=M, n_steps=3, n_paths=n_paths, refit_every=2, cv_stride=stride, train_steps=300,
+                        train_batch=4096, lr=3e-3)
+    run = MeshRun(cfg, init_params=W.mlp_init(0))
+    sub = np.arange(0, run.n_nodes, 11)
+    for n in range(3):
+        xi_n, eta_n = run.mesh()
+        print(f"[gpu] mesh run cv step {n}, {run.n_nodes} nodes, N={n_paths}", flush=True)
+        run.step()
+        _, bf = run.cv.params()                  # the network this step used (refits come first)
+        data = W.Data(init_kind=W.DATA_GRID, t_init=n * D, grid_xi=xi_n, grid_eta=eta_n)
+        o = oracle_mod.fk_solve_cv(W.two_bumps(W.TIME_FROZEN, n * D), data, run.pts[sub], D, D / 20, n_paths,
+                                   level_id=n, node_ids=sub, flat=bf, t_scale=W.CV_T_SCALE, stride=stride,
+                                   want_scores=True, threads=THREADS)
+        iface, se = run.interface_values()
+        smax = np.abs(o["cv_scores"]).max()
+        d = np.abs(iface[n, sub] - o["mean"])
+        ratio = np.median(o["se"] / o["plain_se"])
+        print(f"step {n}: cv max |gpu - oracle| {d.max():.2e}, score scale {smax:.3g}, se cv/plain {ratio:.3f}",
+              flush=True)
+        assert np.all(d <= 3 * o["se"]) and np.all(d <= 1e-5 * max(1.0, smax))
+        assert np.all(np.abs(se[n, sub] - o["se"]) <= 0.02 * o["se"] + 1e-7)
+        assert ratio < 0.5                       # the network pays off from the first step
+        assert run.qualities()[n][0] > 0
+    run.close()

@@ -1,4 +1,4 @@
-"""Pins of the control-variate (Dynkin-form) oracle.
+"""Pins of the control-variate oracle, Dynkin form then martingale form.
 
 * u_hat = 0 reproduces the plain estimate bit for bit.
 * w = 1 with the exact solution as u_hat (identity data and u_hat = (x, y);
@@ -10,6 +10,17 @@
   (and the CV variance is lower where the drift is strong).
 * A trained-looking network: CV and plain agree within 3 combined standard
   errors on the same paths.
+
+Martingale form:
+
+* u_hat = 0 reproduces the plain estimate bit for bit.
+* w = 1, identity data, grad u_hat = I: every path scores its start point,
+  for any stride, with exits and a short last step (the Brownian part is
+  accumulated exactly as the path moves).
+* w = 1, the sine mode with its exact solution: the remaining variance is
+  the stochastic integral's discretisation, falling like sqrt(dt).
+* A curved network under a strong drift, strides 2 and 50: cv - plain on the
+  same paths has mean zero (z-scores), i.e. no stride bias.
 """
 import math
 
@@ -58,3 +69,63 @@ def test_network_uhat_agrees_with_plain(oracle_mod):
                                uhat=oracle_mod.UHAT_MLP, flat=flat, t_scale=W.CV_T_SCALE, stride=2)
     d = np.abs(r["mean"] - r["plain_mean"])
     assert np.all(d <= 3 * np.sqrt(r["se"] ** 2 + r["plain_se"] ** 2) + 1e-3)
+
+
+# ---- martingale form --------------------------------------------------------
+# score = g - sum_j grad u_hat(X_{k_j}) . (B_{k_{j+1}} - B_{k_j}), B the
+# Brownian part of the Euler-Maruyama path.
+
+def test_martingale_zero_uhat_is_plain(oracle_mod):
+    pts = W.uniform_points(6, seed=1)
+    cv = oracle_mod.fk_solve_cv(W.static_bump(), W.Data(), pts, 0.02, 1e-4, 500, seed=3,
+                                uhat=oracle_mod.UHAT_ZERO, form=oracle_mod.CV_MARTINGALE, stride=4)
+    pl = oracle_mod.fk_solve(W.static_bump(), W.Data(), pts, 0.02, 1e-4, 500, seed=3)
+    assert np.array_equal(cv["mean"], pl["mean"]) and np.array_equal(cv["se"], pl["se"])
+
+
+def test_martingale_linear_uhat_w1_is_exact_on_every_path(oracle_mod):
+    """w = 1, identity data scored unclamped: g(X_tau) = X_tau = P + B_tau, so
+    with grad u_hat = I the score is P on every path, whatever the stride, the
+    exits and the short last step (0.05 / 2e-3 is not a whole number of steps
+    for 0.051)."""
+    pts = W.uniform_points(8, seed=2)
+    for stride in (1, 3, 1000):
+        r = oracle_mod.fk_solve_cv(W.CONST, W.Data(), pts, 0.051, 2e-3, 400, seed=1, uhat=oracle_mod.UHAT_LINEAR,
+                                   stride=stride, form=oracle_mod.CV_MARTINGALE, want_scores=True, want_exit=True)
+        assert np.any(r["exit_step"] >= 0)
+        assert np.abs(r["cv_scores"] - pts[:, None, :]).max() < 1e-14
+        assert np.all(r["plain_se"] > 1e-3)
+
+
+def test_martingale_exact_sine_solution_removes_the_variance(oracle_mod):
+    """With the exact solution's gradient every step, what is left is the
+    discretisation of the stochastic integral: the CV standard error falls
+    like sqrt(dt) relative to the plain one, and the estimate stays exact."""
+    pts = W.uniform_points(6, seed=5)
+    d = W.Data(init_kind=W.DATA_SIN, bdry_kind=W.DATA_SIN)
+    exact = math.exp(-2 * math.pi ** 2 * 0.05) * np.sin(math.pi * pts[:, 0]) * np.sin(math.pi * pts[:, 1])
+    ratio = []
+    for dt in (1e-3, 1e-4):
+        r = oracle_mod.fk_solve_cv(W.CONST, d, pts, 0.05, dt, 2000, seed=1, uhat=oracle_mod.UHAT_SIN, stride=1,
+                                   form=oracle_mod.CV_MARTINGALE)
+        assert np.all(np.abs(r["mean"][:, 0] - exact) <= 4 * r["se"][:, 0])
+        ratio.append(np.median(r["se"][:, 0] / r["plain_se"][:, 0]))
+    assert ratio[1] < 0.08 and 0.25 < ratio[1] / ratio[0] < 0.4     # 1/sqrt(10) = 0.316
+
+
+def test_martingale_form_is_unbiased_at_any_stride(oracle_mod):
+    """The martingale sum has mean zero for the discrete chain, for any
+    network and stride: cv - plain on the same paths is a zero-mean sum."""
+    flat = M.bf16_round(W.mlp_init(1) * 2.5)
+    pts = W.interface_nodes(4, 4, 8)[::2]
+    z = []
+    for stride in (2, 50):
+        r = oracle_mod.fk_solve_cv(W.moving_bump(), W.Data(), pts, 0.01, 1e-4, 1500, seed=6, uhat=oracle_mod.UHAT_MLP,
+                                   flat=flat, t_scale=W.CV_T_SCALE, stride=stride, form=oracle_mod.CV_MARTINGALE,
+                                   want_scores=True)
+        pl = oracle_mod.fk_solve(W.moving_bump(), W.Data(), pts, 0.01, 1e-4, 1500, seed=6, want_scores=True)
+        diff = r["cv_scores"] - pl["scores"]
+        z.append(diff.mean(1) / (diff.std(1, ddof=1) / math.sqrt(diff.shape[1])))
+        assert np.all(np.abs(r["mean"] - diff.mean(1) - pl["mean"]) < 1e-12)
+    z = np.concatenate(z).ravel()
+    assert np.abs(z).max() < 4.0 and abs(z.mean()) < 4 / math.sqrt(z.size)
