@@ -67,6 +67,10 @@ extern "C" {
 
 #define FK_SCORE_UNCLAMPED 0  /* boundary data at the first point outside the square */
 #define FK_SCORE_PROJECT 1    /* ... after clamping that point onto the square */
+#define FK_SCORE_EXTEND 2     /* the FK_DATA_GRID initial data continued bilinearly from its edge cells to
+                                 that point: for a grid whose edge nodes hold the boundary data, the data
+                                 extended by the grid's own normal slope (a first-order correction of the
+                                 overshoot of the discrete exit test); needs grid initial data */
 
 /* Density parameters (plain values). */
 typedef struct fk_density {
@@ -261,19 +265,31 @@ int fk_cv_train(fk_cv_t cv, const float *txy, const float *target, int64_t n, in
 
 /*
  * Control-variate interface solve: the paths of fk_interface_solve (same
- * counters), each scored with the Dynkin-form estimator
- *   u(P) = u_hat(t_init + t, P) + E[ g - u_hat(tau_end, X_end) + sum_j r_j ds_j ],
- *   r = Laplacian u_hat + b . grad u_hat - d_t u_hat,
- * r taken at the path state every `stride` steps (even, >= 2) and at the
- * path's end, integrated by the trapezoidal rule between those points.  xi/eta/se_*: the CV estimate;
- * plain_*: the plain estimate from the same paths (all four or none);
- * exit_step and cv_scores (device [n][N][2], g - u_hat(end) + sum r ds) optional.
+ * counters), each scored with a control variate built from the network u_hat.
+ * Two forms of one estimator (they agree in continuous time by Ito's formula
+ * applied to u_hat along the path; u_hat's time argument runs backward from
+ * t_init + t like the density's):
+ *   FK_CV_DYNKIN       u(P) = u_hat(t_init + t, P) + E[ g - u_hat(tau_end, X_end) + sum_j r_j ds_j ],
+ *                      r = Laplacian u_hat + b . grad u_hat - d_t u_hat taken at
+ *                      the path state every `stride` steps and at the path's
+ *                      end, integrated by the trapezoidal rule between those
+ *                      points (a quadrature bias that grows with stride dt);
+ *   FK_CV_MARTINGALE   u(P) = E[ g - sum_j grad u_hat(X_{k_j}) . dB_j ], dB_j the
+ *                      Brownian part sqrt(2 dt) z of the steps from k_j (every
+ *                      `stride` steps from the start) to the next k_j or the
+ *                      path's end: mean zero for the discrete chain at any stride.
+ * stride is even, >= 2.  xi/eta/se_*: the CV estimate; plain_*: the plain
+ * estimate from the same paths (all four or none); exit_step and cv_scores
+ * (device [n][N][2], the per-path CV scores whose mean, plus u_hat(t_init + t, P)
+ * in the Dynkin form, is the estimate) optional.
  * workspace: fk_interface_cv_workspace_bytes(n_nodes, n_paths).
  */
+#define FK_CV_DYNKIN 0
+#define FK_CV_MARTINGALE 1
 size_t fk_interface_cv_workspace_bytes(int64_t n_nodes, int64_t n_paths);
 int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *pts, int64_t n_nodes, double t,
                           double dt, int64_t n_paths, uint64_t seed, uint32_t level_id, fk_cv_t cv, int32_t stride,
-                          double *xi, double *eta, double *se_xi, double *se_eta, double *plain_xi,
+                          int32_t form, double *xi, double *eta, double *se_xi, double *se_eta, double *plain_xi,
                           double *plain_eta, double *plain_se_xi, double *plain_se_eta, int32_t *exit_step,
                           float *cv_scores, uint64_t *total_steps, const fk_plan *plan, void *workspace,
                           size_t workspace_bytes, hipStream_t stream);

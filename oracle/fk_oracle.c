@@ -243,6 +243,13 @@ static void initial_value(const or_data *d, double x, double y, double *xi, doub
 static void boundary_value(const or_data *d, double elapsed, double x, double y,
                            double *xi, double *eta)
 {
+    if (d->score_mode == 2) {
+        /* the grid initial data continued bilinearly from its edge cells: the
+           boundary data (the grid's edge nodes) extended by the grid's slope */
+        *xi = bilinear(d->grid_xi, d->grid_n, x, y);
+        *eta = bilinear(d->grid_eta, d->grid_n, x, y);
+        return;
+    }
     if (d->score_mode == 1) {
         x = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
         y = y < 0.0 ? 0.0 : (y > 1.0 ? 1.0 : y);
@@ -331,6 +338,8 @@ int or_fk_solve(int kind, int time_mode, const double *par,
     pb.data.init_kind = init_kind;
     pb.data.bdry_kind = bdry_kind;
     pb.data.score_mode = score_mode;
+    if (score_mode < 0 || score_mode > 2 || (score_mode == 2 && (init_kind != D_GRID || !grid_xi || !grid_eta)))
+        return -1;
     pb.data.grid_xi = grid_xi;
     pb.data.grid_eta = grid_eta;
     pb.data.grid_n = grid_n;
@@ -409,6 +418,8 @@ int or_fk_paths(int kind, int time_mode, const double *par,
     pb.data.init_kind = init_kind;
     pb.data.bdry_kind = bdry_kind;
     pb.data.score_mode = score_mode;
+    if (score_mode < 0 || score_mode > 2 || (score_mode == 2 && (init_kind != D_GRID || !grid_xi || !grid_eta)))
+        return -1;
     pb.data.grid_xi = grid_xi;
     pb.data.grid_eta = grid_eta;
     pb.data.grid_n = grid_n;
@@ -718,6 +729,8 @@ int or_fk_solve_cv(int kind, int time_mode, const double *par,
     pb.data.init_kind = init_kind;
     pb.data.bdry_kind = bdry_kind;
     pb.data.score_mode = score_mode;
+    if (score_mode < 0 || score_mode > 2 || (score_mode == 2 && (init_kind != D_GRID || !grid_xi || !grid_eta)))
+        return -1;
     pb.data.grid_xi = grid_xi;
     pb.data.grid_eta = grid_eta;
     pb.data.grid_n = grid_n;

@@ -4,8 +4,10 @@ mesh step (Sect. 4), composed of the pinned pieces in the paper's order:
 1. the density is frozen at t^n;
 2. the interface values at t^{n+1} = t^n + dt_mesh are Feynman-Kac Monte-Carlo
    estimates (Sect. 3) with the mesh at t^n as initial data, bilinear in the
-   nodal grid, and the identity map as boundary data -- plain (fk_solve) or,
-   given a network, the control-variate form (fk_solve_cv);
+   nodal grid, and the identity map as boundary data, an exit scored with
+   the mesh continued past the edge (its edge nodes hold the identity data)
+   -- plain (fk_solve) or, given a network, a control-variate form
+   (fk_solve_cv);
 3. each sub-domain takes one backward-Euler step with those interface values
    as Dirichlet data (subdomain_be_step).
 
@@ -20,16 +22,17 @@ import oracle.subdomain as _sub
 
 DATA_IDENTITY = 0
 DATA_GRID = 3
+SCORE_EXTEND = 2      # exits: the grid continued bilinearly past the edge
 UHAT_MLP = 1
 
 
 class _GridData:
     """The fields the oracle's solvers read for grid initial data."""
 
-    def __init__(self, t_init, xi, eta):
+    def __init__(self, t_init, xi, eta, score_mode):
         self.init_kind = DATA_GRID
         self.bdry_kind = DATA_IDENTITY
-        self.score_mode = 0
+        self.score_mode = score_mode
         self.t_init = float(t_init)
         self.grid_xi = np.ascontiguousarray(xi, dtype=np.float64)
         self.grid_eta = np.ascontiguousarray(eta, dtype=np.float64)
@@ -43,27 +46,29 @@ def interface_points(px: int, m: int) -> np.ndarray:
 
 
 def interface_solve(dens, tn, dt_mesh, substeps, px, m, xi_n, eta_n, n_paths, seed=0, level_id=0,
-                    node_ids=None, flat=None, t_scale=0.1, stride=10, threads=0):
+                    node_ids=None, flat=None, t_scale=0.1, stride=10, form=0, score_mode=SCORE_EXTEND, threads=0):
     """Step 2: interface estimates (dict with mean [n, 2], se [n, 2]) at the
-    nodes node_ids (default all) of px x px sub-domains."""
+    nodes node_ids (default all) of px x px sub-domains.  Exits score the
+    mesh continued bilinearly past the edge by default (score_mode)."""
     pts = interface_points(px, m)
     if node_ids is not None:
         # the nodes keep their indices in the full set: those key the paths' counters
         node_ids = np.asarray(node_ids, dtype=np.int64)
         pts = pts[node_ids]
-    data = _GridData(tn, xi_n, eta_n)
+    data = _GridData(tn, xi_n, eta_n, score_mode)
     dt = dt_mesh / substeps
     if flat is None:
         return _oracle.fk_solve(dens, data, pts, dt_mesh, dt, n_paths, seed=seed, level_id=level_id,
                                 node_ids=node_ids, threads=threads)
     return _oracle.fk_solve_cv(dens, data, pts, dt_mesh, dt, n_paths, seed=seed, level_id=level_id,
                                node_ids=node_ids, uhat=UHAT_MLP, flat=flat, t_scale=t_scale, stride=stride,
-                               threads=threads)
+                               form=form, threads=threads)
 
 
-def dd_step(dens, tn, dt_mesh, substeps, px, m, xi_n, eta_n, n_paths, seed=0, level_id=0, threads=0):
+def dd_step(dens, tn, dt_mesh, substeps, px, m, xi_n, eta_n, n_paths, seed=0, level_id=0,
+            score_mode=SCORE_EXTEND, threads=0):
     """One plain mesh step: returns (xi, eta, interface estimates)."""
     mc = interface_solve(dens, tn, dt_mesh, substeps, px, m, xi_n, eta_n, n_paths, seed=seed,
-                         level_id=level_id, threads=threads)
+                         level_id=level_id, score_mode=score_mode, threads=threads)
     xi, eta = _sub.subdomain_be_step(dens, tn, dt_mesh, px, m, xi_n, eta_n, mc["mean"][:, 0], mc["mean"][:, 1])
     return xi, eta, mc

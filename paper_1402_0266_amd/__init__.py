@@ -133,7 +133,7 @@ _lib.fk_interface_cv_workspace_bytes.restype = ctypes.c_size_t
 _lib.fk_interface_solve_cv.argtypes = [
     ctypes.POINTER(fk_density), ctypes.POINTER(fk_data), _P, ctypes.c_int64,
     ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32, _P, ctypes.c_int32,
-    _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(fk_plan), _P, ctypes.c_size_t, _P]
+    ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(fk_plan), _P, ctypes.c_size_t, _P]
 _lib.fk_interface_solve_cv.restype = ctypes.c_int
 _lib.fk_timing_enable.argtypes = [ctypes.c_int]
 _lib.fk_timing_enable.restype = ctypes.c_int
@@ -470,12 +470,16 @@ class FkCv:
         return loss
 
 
+FK_CV_DYNKIN, FK_CV_MARTINGALE = 0, 1
+
+
 def fk_interface_solve_cv(density, data, pts, t, dt, n_paths, cv, stride=2, seed=0, level_id=0, *,
-                          plain=True, exit_step=False, cv_scores=False, plan=None, device="cuda", workspace=None,
-                          grids=None):
-    """Control-variate interface solve (C: ``fk_interface_solve_cv``); returns a
-    dict of device tensors: xi, eta, se_xi, se_eta (CV), plain_* (same paths),
-    total_steps, and on request exit_step, cv_scores."""
+                          form=FK_CV_DYNKIN, plain=True, exit_step=False, cv_scores=False, plan=None, device="cuda",
+                          workspace=None, grids=None):
+    """Control-variate interface solve (C: ``fk_interface_solve_cv``), Dynkin
+    or martingale form; returns a dict of device tensors: xi, eta, se_xi,
+    se_eta (CV), plain_* (same paths), total_steps, and on request exit_step,
+    cv_scores."""
     import torch
     pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 2)
     n = pts.shape[0]
@@ -497,7 +501,7 @@ def fk_interface_solve_cv(density, data, pts, t, dt, n_paths, cv, stride=2, seed
 
     _check(_lib.fk_interface_solve_cv(
         ctypes.byref(_density(density)), ctypes.byref(_data(data, grids)), pts.ctypes.data_as(ctypes.c_void_p), n,
-        float(t), float(dt), int(n_paths), int(seed), int(level_id), cv.handle, int(stride),
+        float(t), float(dt), int(n_paths), int(seed), int(level_id), cv.handle, int(stride), int(form),
         ptr("xi"), ptr("eta"), ptr("se_xi"), ptr("se_eta"), ptr("plain_xi"), ptr("plain_eta"), ptr("plain_se_xi"),
         ptr("plain_se_eta"), ptr("exit_step"), ptr("cv_scores"), ptr("total_steps"), _plan_struct(plan),
         workspace.data_ptr(), workspace.numel(), _stream(torch, dev)))

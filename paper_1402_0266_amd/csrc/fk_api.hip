@@ -64,8 +64,10 @@ int validate_data(const fk_data *d) {
     if (d->init_kind < 0 || d->init_kind > FK_DATA_GRID) return fail(FK_E_INVAL, "unknown init kind %d", d->init_kind);
     if (d->bdry_kind < 0 || d->bdry_kind > FK_DATA_ZERO)
         return fail(FK_E_INVAL, "unknown boundary kind %d", d->bdry_kind);
-    if (d->score_mode != FK_SCORE_UNCLAMPED && d->score_mode != FK_SCORE_PROJECT)
+    if (d->score_mode != FK_SCORE_UNCLAMPED && d->score_mode != FK_SCORE_PROJECT && d->score_mode != FK_SCORE_EXTEND)
         return fail(FK_E_INVAL, "unknown score mode %d", d->score_mode);
+    if (d->score_mode == FK_SCORE_EXTEND && d->init_kind != FK_DATA_GRID)
+        return fail(FK_E_INVAL, "score mode EXTEND needs grid initial data");
     if (!std::isfinite(d->t_init)) return fail(FK_E_INVAL, "t_init is not finite");
     if (d->init_kind == FK_DATA_GRID) {
         if (d->grid_n < 1 || !d->grid_xi || !d->grid_eta)

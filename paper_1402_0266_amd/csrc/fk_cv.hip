@@ -143,6 +143,11 @@ __device__ void net_eval_wave(const NetLds &N, float tscale2, float tau, float x
     const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
 #pragma unroll 1
     for (int r = 0; r < 4; ++r) {
+        // an index offset the compiler cannot see through: keeps the weight
+        // reads inside the loop instead of hoisting them into registers
+        int lz = 0;
+        asm volatile("" : "+s"(lz));
+        const NetLds &M = *reinterpret_cast<const NetLds *>(reinterpret_cast<const char *>(&N) + lz);
         const int src = 16 * r + n;
         const float z0 = __shfl(tau, src, 64) * tscale2 - 1.f;
         const float z1 = 2.f * __shfl(x, src, 64) - 1.f;
@@ -160,8 +165,8 @@ __device__ void net_eval_wave(const NetLds &N, float tscale2, float tau, float x
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 const int u = 16 * kt + 4 * g + i;
-                const float w0 = N.w1[3 * u], w1 = N.w1[3 * u + 1], w2 = N.w1[3 * u + 2];
-                const float a = fmaf(w0, z0, fmaf(w1, z1, fmaf(w2, z2, N.b1[u])));
+                const float w0 = M.w1[3 * u], w1 = M.w1[3 * u + 1], w2 = M.w1[3 * u + 2];
+                const float a = fmaf(w0, z0, fmaf(w1, z1, fmaf(w2, z2, M.b1[u])));
                 float ch[5];
                 act5(a, 2.f * w1, 2.f * w2, tscale2 * w0, 0.f, ch[0], ch[1], ch[2], ch[3], ch[4]);
 #pragma unroll
@@ -174,7 +179,7 @@ __device__ void net_eval_wave(const NetLds &N, float tscale2, float tau, float x
             }
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
-                const fk_s4 A = load_a(N.w2, mt, kt, n, g);
+                const fk_s4 A = load_a(M.w2, mt, kt, n, g);
 #pragma unroll
                 for (int c = 0; c < 5; ++c) {
                     acc[mt][c] = mfma16(A, Bh[c], acc[mt][c]);
@@ -190,7 +195,7 @@ __device__ void net_eval_wave(const NetLds &N, float tscale2, float tau, float x
             for (int i = 0; i < 4; ++i) {
                 const int u = 16 * mt + 4 * g + i;
                 float ch[5];
-                act5(acc[mt][0][i] + N.b2[u], acc[mt][1][i], acc[mt][2][i], acc[mt][3][i], acc[mt][4][i], ch[0], ch[1],
+                act5(acc[mt][0][i] + M.b2[u], acc[mt][1][i], acc[mt][2][i], acc[mt][3][i], acc[mt][4][i], ch[0], ch[1],
                      ch[2], ch[3], ch[4]);
 #pragma unroll
                 for (int c = 0; c < 5; ++c) {
@@ -213,7 +218,7 @@ __device__ void net_eval_wave(const NetLds &N, float tscale2, float tau, float x
             for (int c = 0; c < 5; ++c) a3[c] = fk_f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
             for (int kt = 0; kt < 4; ++kt) {
-                const fk_s4 A = load_a(N.w3, mt, kt, n, g);
+                const fk_s4 A = load_a(M.w3, mt, kt, n, g);
 #pragma unroll
                 for (int c = 0; c < 5; ++c) {
                     a3[c] = mfma16(A, Ch[kt][c], a3[c]);
@@ -224,10 +229,10 @@ __device__ void net_eval_wave(const NetLds &N, float tscale2, float tau, float x
             for (int i = 0; i < 4; ++i) {
                 const int u = 16 * mt + 4 * g + i;
                 float ch[5];
-                act5(a3[0][i] + N.b3[u], a3[1][i], a3[2][i], a3[3][i], a3[4][i], ch[0], ch[1], ch[2], ch[3], ch[4]);
+                act5(a3[0][i] + M.b3[u], a3[1][i], a3[2][i], a3[3][i], a3[4][i], ch[0], ch[1], ch[2], ch[3], ch[4]);
 #pragma unroll
                 for (int o = 0; o < 2; ++o) {
-                    const float w = N.w4[64 * o + u];
+                    const float w = M.w4[64 * o + u];
 #pragma unroll
                     for (int c = 0; c < 5; ++c) po[o][c] = fmaf(w, ch[c], po[o][c]);
                 }
@@ -241,7 +246,128 @@ __device__ void net_eval_wave(const NetLds &N, float tscale2, float tau, float x
                 float v = po[o][c];
                 v += __shfl_xor(v, 16, 64);
                 v += __shfl_xor(v, 32, 64);
-                if (c == 0) v += N.b4[o];
+                if (c == 0) v += M.b4[o];
+                if (g == r) out[o][c] = v;
+            }
+    }
+}
+
+// tanh with its first derivatives: h = tanh(a), dh = (1 - h^2) da.
+__device__ __forceinline__ void act3(float a, float ax, float ay, float &h, float &hx, float &hy) {
+    const float ac = fminf(fmaxf(a, -15.f), 15.f);
+    const float e = hw_exp2(ac * 2.8853900817779268f);
+    const float r = hw_rcp(1.f + e);
+    h = fmaf(-2.f, r, 1.f);
+    const float s = 4.f * e * r * r;
+    hx = s * ax;
+    hy = s * ay;
+}
+
+// Wavefront-wide gradient of both outputs in (x, y) at lane l's point, for
+// the martingale form: out[o] = (d/dx, d/dy) of output o.  Three channels
+// (value, d/dx, d/dy); the operands are split into BF16 hi + lo parts as in
+// net_eval_wave, so the gradient matches the FP64 evaluation of the network
+// to ~1e-5 relative (plain BF16 operands would leave ~1e-2 absolute).
+__device__ void net_grad_wave(const NetLds &N, float tscale2, float tau, float x, float y, float out[2][2]) {
+    const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
+#pragma unroll 1
+    for (int r = 0; r < 4; ++r) {
+        // an index offset the compiler cannot see through: keeps the weight
+        // reads inside the loop instead of hoisting ~200 registers of them
+        int lz = 0;
+        asm volatile("" : "+s"(lz));
+        const NetLds &M = *reinterpret_cast<const NetLds *>(reinterpret_cast<const char *>(&N) + lz);
+        const int src = 16 * r + n;
+        const float z0 = __shfl(tau, src, 64) * tscale2 - 1.f;
+        const float z1 = 2.f * __shfl(x, src, 64) - 1.f;
+        const float z2 = 2.f * __shfl(y, src, 64) - 1.f;
+        fk_f4 acc[4][3];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) acc[mt][c] = fk_f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt) {
+            fk_s4 Bh[3], Bl[3];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int u = 16 * kt + 4 * g + i;
+                const float a = fmaf(M.w1[3 * u], z0, fmaf(M.w1[3 * u + 1], z1, fmaf(M.w1[3 * u + 2], z2, M.b1[u])));
+                float ch[3];
+                act3(a, 2.f * M.w1[3 * u + 1], 2.f * M.w1[3 * u + 2], ch[0], ch[1], ch[2]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    short hi, lo;
+                    split_bf16(ch[c], hi, lo);
+                    Bh[c][i] = hi;
+                    Bl[c][i] = lo;
+                }
+            }
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const fk_s4 A = load_a(M.w2, mt, kt, n, g);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    acc[mt][c] = mfma16(A, Bh[c], acc[mt][c]);
+                    acc[mt][c] = mfma16(A, Bl[c], acc[mt][c]);
+                }
+            }
+        }
+        // ---- layer 3: layer-2 output tile kt is layer 3's K block kt, so its
+        //      activations are consumed as soon as they are formed ----------
+        fk_f4 a3[4][3];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int c = 0; c < 3; ++c) a3[mt][c] = fk_f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int kt = 0; kt < 4; ++kt) {
+            fk_s4 Ch[3], Cl[3];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int u = 16 * kt + 4 * g + i;
+                float ch[3];
+                act3(acc[kt][0][i] + M.b2[u], acc[kt][1][i], acc[kt][2][i], ch[0], ch[1], ch[2]);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    short hi, lo;
+                    split_bf16(ch[c], hi, lo);
+                    Ch[c][i] = hi;
+                    Cl[c][i] = lo;
+                }
+            }
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) {
+                const fk_s4 A = load_a(M.w3, mt, kt, n, g);
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    a3[mt][c] = mfma16(A, Ch[c], a3[mt][c]);
+                    a3[mt][c] = mfma16(A, Cl[c], a3[mt][c]);
+                }
+            }
+        }
+        float po[2][2] = {{0.f, 0.f}, {0.f, 0.f}};
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const int u = 16 * mt + 4 * g + i;
+                float h, hx, hy;
+                act3(a3[mt][0][i] + M.b3[u], a3[mt][1][i], a3[mt][2][i], h, hx, hy);
+#pragma unroll
+                for (int o = 0; o < 2; ++o) {
+                    const float w = M.w4[64 * o + u];
+                    po[o][0] = fmaf(w, hx, po[o][0]);
+                    po[o][1] = fmaf(w, hy, po[o][1]);
+                }
+            }
+#pragma unroll
+        for (int o = 0; o < 2; ++o)
+#pragma unroll
+            for (int c = 0; c < 2; ++c) {
+                float v = po[o][c];
+                v += __shfl_xor(v, 16, 64);
+                v += __shfl_xor(v, 32, 64);
                 if (g == r) out[o][c] = v;
             }
     }
@@ -300,7 +426,7 @@ __device__ __forceinline__ void drift_at_tau(const Lane &L, float tau, float &bx
 }
 
 template <int KIND, int TMODE, bool UNIFORM>
-__global__ void __launch_bounds__(256) fk_cv_path_kernel(const PathArgs a, const CvArgs c) {
+__global__ void __launch_bounds__(256, 2) fk_cv_path_kernel(const PathArgs a, const CvArgs c) {
     constexpr bool kMovingBackward = (KIND == KIND_MOVING || KIND == KIND_TWO) && TMODE == TIME_BACKWARD;
     __shared__ NetLds N;
     load_net(N, c.bf);
@@ -432,14 +558,151 @@ __global__ void __launch_bounds__(256) fk_cv_path_kernel(const PathArgs a, const
     if (lane == 0 && st != 0ull) atomicAdd(a.total_steps, st);
 }
 
+// Martingale-form path kernel.  The score is g - sum_j G_j . dB_j: dB_j is the
+// Brownian part of the path's steps in block j, G_j the gradient of u_hat at
+// the block's first state.  Blocks start at the path's start (G_0 from the
+// node table) and every stride steps after it, and the last one closes at
+// the path's end, so a finished path is scored at once.  Paths start only at
+// evaluation points, which keeps every path's blocks at fixed step offsets
+// and the result independent of the schedule.
+struct MgArgs {
+    const uint16_t *bf;
+    float tscale2;
+    uint32_t stride_iters;
+    const float4 *g0;            // [n_out] (dxi/dx, dxi/dy, deta/dx, deta/dy) at the start point
+    float2 *cv_scores;           // [n_out * n_paths], absolute
+};
+
+template <int KIND, int TMODE, bool UNIFORM>
+__global__ void __launch_bounds__(256, 2) fk_mg_path_kernel(const PathArgs a, const MgArgs c) {
+    constexpr bool kMovingBackward = (KIND == KIND_MOVING || KIND == KIND_TWO) && TMODE == TIME_BACKWARD;
+    __shared__ NetLds N;
+    load_net(N, c.bf);
+    __syncthreads();
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t q_slot = 0, q_next = 0, q_end = 0;
+    bool q_done = false;
+    const uint32_t key0 = a.key0, key1 = a.key1;
+    Lane L;
+    bool active = false;
+    float gxx = 0.f, gxy = 0.f, gyx = 0.f, gyy = 0.f;   // gradient of (xi_hat, eta_hat) held over the block
+    float dbx = 0.f, dby = 0.f;                         // Brownian part of the block so far
+    float mx = 0.f, my = 0.f;                           // the martingale sum of the closed blocks
+    float tend = 0.f;
+    uint32_t my_steps = 0;
+
+    for (uint32_t iter = 0;; ++iter) {
+        if (iter % c.stride_iters == 0) {
+            // ---- block boundary of running paths (every lane joins) ---------
+            if (__ballot(active) != 0ull) {
+                const float tau = active ? tend - (float)L.k * L.dt : 0.f;
+                float o[2][2];
+                net_grad_wave(N, c.tscale2, tau, active ? L.xh : 0.5f, active ? L.yh : 0.5f, o);
+                if (active) {
+                    mx = fmaf(gxx, dbx, fmaf(gxy, dby, mx));
+                    my = fmaf(gyx, dbx, fmaf(gyy, dby, my));
+                    dbx = dby = 0.f;
+                    gxx = o[0][0];
+                    gxy = o[0][1];
+                    gyx = o[1][0];
+                    gyy = o[1][1];
+                }
+            }
+            // ---- refill idle lanes ------------------------------------------
+            uint64_t need = __ballot(!active);
+            while (need != 0ull && !q_done) {
+                if (q_next >= q_end) {
+                    uint32_t cc = 0;
+                    if (lane == 0) cc = atomicAdd(a.queue, 1u);
+                    cc = __builtin_amdgcn_readfirstlane(cc);
+                    if (cc >= a.total_chunks) {
+                        q_done = true;
+                        break;
+                    }
+                    q_slot = cc / a.cpn;
+                    q_next = (cc - q_slot * a.cpn) * a.chunk;
+                    q_end = min(q_next + a.chunk, a.n_paths);
+                    continue;
+                }
+                const uint32_t avail = q_end - q_next;
+                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
+                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+                if (!active && rank < avail) {
+                    const NodeDev nd = a.nodes[q_slot];
+                    lane_start<KIND, TMODE>(L, nd, a.levels, q_next + rank, a.n_paths);
+                    tend = a.levels[nd.level].tend;
+                    const float4 g0 = c.g0[nd.out];
+                    gxx = g0.x;
+                    gxy = g0.y;
+                    gyx = g0.z;
+                    gyy = g0.w;
+                    dbx = dby = mx = my = 0.f;
+                    active = true;
+                }
+                q_next += min((uint32_t)__popcll(need), avail);
+                need = __ballot(!active);
+            }
+        }
+        if (__ballot(active) == 0ull && q_done) break;
+
+        if (active) {
+            bool out = false;
+            if (L.k < L.K) {
+                const PhiloxOut r = philox4x32_10((uint32_t)L.k >> 1, L.path, L.nid, L.ctr3, key0, key1);
+                float ox = L.ox, oy = L.oy, cr = 0.f, sr = 0.f;
+                if constexpr (kMovingBackward) {
+                    const float rev = fmaf(-(float)L.k, L.drev, L.rev0);
+                    cr = hw_cos_rev(rev);
+                    sr = hw_sin_rev(rev);
+                    ox = L.dens.orbit_r * cr;
+                    oy = L.dens.orbit_r * sr;
+                }
+                float wx, wy;
+                out = em_step_w<KIND, UNIFORM>(L, r.r0, r.r1, ox, oy, wx, wy);
+                dbx += wx;
+                dby += wy;
+                my_steps += 1;
+                if (!out && L.k < L.K) {
+                    if constexpr (kMovingBackward) {
+                        const float c2 = fmaf(cr, L.cos_d, sr * L.sin_d);
+                        const float s2 = fmaf(sr, L.cos_d, -cr * L.sin_d);
+                        ox = L.dens.orbit_r * c2;
+                        oy = L.dens.orbit_r * s2;
+                    }
+                    out = em_step_w<KIND, UNIFORM>(L, r.r2, r.r3, ox, oy, wx, wy);
+                    dbx += wx;
+                    dby += wy;
+                    my_steps += 1;
+                }
+            }
+            if (out || L.k >= L.K) {
+                float plx, ply;
+                score_path(a, L, out, plx, ply);
+                mx = fmaf(gxx, dbx, fmaf(gxy, dby, mx));
+                my = fmaf(gyx, dbx, fmaf(gyy, dby, my));
+                const float sx0 = a.shift ? L.px : 0.f, sy0 = a.shift ? L.py : 0.f;
+                a.scores[L.rec] = make_float2(plx, ply);
+                c.cv_scores[L.rec] = make_float2((plx + sx0) - mx, (ply + sy0) - my);
+                if (a.exit_step) a.exit_step[L.rec] = out ? L.k : -1;
+                active = false;
+            }
+        }
+    }
+    unsigned long long st = my_steps;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) st += __shfl_xor(st, off, 64);
+    if (lane == 0 && st != 0ull) atomicAdd(a.total_steps, st);
+}
+
 // Per node: u_hat at the start (the shift of the CV estimate) and the
 // integrand r0 there.
 struct CvNodeArgs {
     const NodeDev *nodes;
     const LevelDev *levels;
     int64_t n_nodes;
-    OutDev *outs_cv;   // shift_x/shift_y <- u_hat(t_init + t, P)
-    float2 *r0;
+    OutDev *outs_cv;   // shift_x/shift_y <- u_hat(t_init + t, P), or NULL
+    float2 *r0;        // integrand at P, or NULL
+    float4 *g0;        // gradient of both outputs at P, or NULL
     int kind, time_mode;
 };
 
@@ -466,10 +729,14 @@ __global__ void __launch_bounds__(256) cv_node_kernel(const CvNodeArgs na, const
         const NodeDev nd = na.nodes[s];
         float bx, by;
         drift_at<KIND, TMODE, true>(L, bx, by);
-        na.outs_cv[nd.out].shift_x = (double)o[0][0];
-        na.outs_cv[nd.out].shift_y = (double)o[1][0];
-        na.r0[nd.out] = make_float2(o[0][4] + fmaf(bx, o[0][1], by * o[0][2]) - o[0][3],
-                                    o[1][4] + fmaf(bx, o[1][1], by * o[1][2]) - o[1][3]);
+        if (na.outs_cv) {
+            na.outs_cv[nd.out].shift_x = (double)o[0][0];
+            na.outs_cv[nd.out].shift_y = (double)o[1][0];
+        }
+        if (na.r0)
+            na.r0[nd.out] = make_float2(o[0][4] + fmaf(bx, o[0][1], by * o[0][2]) - o[0][3],
+                                        o[1][4] + fmaf(bx, o[1][1], by * o[1][2]) - o[1][3]);
+        if (na.g0) na.g0[nd.out] = make_float4(o[0][1], o[0][2], o[1][1], o[1][2]);
     }
 }
 
@@ -745,6 +1012,22 @@ struct CvOccF {
     }
 };
 template <int K, int T, bool U>
+struct MgLaunchF {
+    static hipError_t run(const PathArgs &a, const MgArgs &c, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((fk_mg_path_kernel<K, T, U>), dim3(grid), dim3(256), 0, s, a, c);
+        return hipGetLastError();
+    }
+};
+template <int K, int T, bool U>
+struct MgOccF {
+    static int run() {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk_mg_path_kernel<K, T, U>, 256, 0) != hipSuccess)
+            return 0;
+        return nb;
+    }
+};
+template <int K, int T, bool U>
 struct CvNodeF {
     static hipError_t run(const CvNodeArgs &na, const uint16_t *bf, float ts2, hipStream_t s) {
         const int blocks = (int)((na.n_nodes + 255) / 256);
@@ -775,7 +1058,7 @@ auto cv_dispatch(int kind, int time_mode, bool uniform, Args &&...args) {
 
 // Workspace of one control-variate solve.
 struct CvWs {
-    size_t counters, levels, nodes, outs, outs_cv, r0, scores, cv_scores, total;
+    size_t counters, levels, nodes, outs, outs_cv, r0, g0, scores, cv_scores, total;
 };
 
 static CvWs cv_ws_layout(int64_t n_nodes, int64_t n_paths, bool own_cv) {
@@ -793,6 +1076,8 @@ static CvWs cv_ws_layout(int64_t n_nodes, int64_t n_paths, bool own_cv) {
     off += align256(sizeof(OutDev) * (size_t)n_nodes);
     L.r0 = off;
     off += align256(sizeof(float2) * (size_t)n_nodes);
+    L.g0 = off;
+    off += align256(sizeof(float4) * (size_t)n_nodes);
     L.scores = off;
     off += align256(sizeof(float2) * (size_t)n_nodes * (size_t)n_paths);
     L.cv_scores = off;
@@ -986,7 +1271,7 @@ size_t fk_interface_cv_workspace_bytes(int64_t n_nodes, int64_t n_paths) {
 
 int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *pts, int64_t n_nodes, double t,
                           double dt, int64_t n_paths, uint64_t seed, uint32_t level_id, fk_cv_t cv, int32_t stride,
-                          double *xi, double *eta, double *se_xi, double *se_eta, double *plain_xi,
+                          int32_t form, double *xi, double *eta, double *se_xi, double *se_eta, double *plain_xi,
                           double *plain_eta, double *plain_se_xi, double *plain_se_eta, int32_t *exit_step,
                           float *cv_scores, uint64_t *total_steps, const fk_plan *plan, void *workspace,
                           size_t workspace_bytes, hipStream_t stream) {
@@ -999,6 +1284,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     if ((rc = validate_horizon(t, d->t_init, dt, level_id)) != FK_OK) return rc;
     if ((rc = validate_points(pts, n_nodes)) != FK_OK) return rc;
     if (stride < 2 || stride % 2 != 0 || stride > (1 << 20)) return fail(FK_E_INVAL, "stride must be even and >= 2");
+    if (form != FK_CV_DYNKIN && form != FK_CV_MARTINGALE) return fail(FK_E_INVAL, "unknown control-variate form");
     if (n_nodes > 0 && (!xi || !eta || !se_xi || !se_eta)) return fail(FK_E_INVAL, "an output pointer is NULL");
     fk_plan pl;
     if ((rc = resolve_plan(plan, &pl)) != FK_OK) return rc;
@@ -1016,6 +1302,11 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     Tables T;
     if ((rc = build_tables(&spec, 1, pts, n_nodes, d, dt, T)) != FK_OK) return rc;
     char *ws = (char *)workspace;
+    // CV records are absolute: the Dynkin form's shift is u_hat at the node
+    // (the node kernel writes it), the martingale form's is zero
+    std::vector<OutDev> outs_cv = T.outs;
+    for (OutDev &o : outs_cv) o.shift_x = o.shift_y = 0.0;
+    const bool mg = (form == FK_CV_MARTINGALE);
     hipError_t e;
     if ((e = hipMemcpyAsync(ws + lay.levels, T.levels.data(), sizeof(LevelDev), hipMemcpyHostToDevice, stream)) !=
             hipSuccess ||
@@ -1023,7 +1314,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
                             stream)) != hipSuccess ||
         (e = hipMemcpyAsync(ws + lay.outs, T.outs.data(), sizeof(OutDev) * T.outs.size(), hipMemcpyHostToDevice,
                             stream)) != hipSuccess ||
-        (e = hipMemcpyAsync(ws + lay.outs_cv, T.outs.data(), sizeof(OutDev) * T.outs.size(), hipMemcpyHostToDevice,
+        (e = hipMemcpyAsync(ws + lay.outs_cv, outs_cv.data(), sizeof(OutDev) * outs_cv.size(), hipMemcpyHostToDevice,
                             stream)) != hipSuccess)
         return hip_fail(e, "upload tables");
     uint32_t *counters = (uint32_t *)(ws + lay.counters);
@@ -1036,8 +1327,9 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     na.nodes = (const NodeDev *)(ws + lay.nodes);
     na.levels = (const LevelDev *)(ws + lay.levels);
     na.n_nodes = n_nodes;
-    na.outs_cv = (OutDev *)(ws + lay.outs_cv);
-    na.r0 = (float2 *)(ws + lay.r0);
+    na.outs_cv = mg ? nullptr : (OutDev *)(ws + lay.outs_cv);
+    na.r0 = mg ? nullptr : (float2 *)(ws + lay.r0);
+    na.g0 = mg ? (float4 *)(ws + lay.g0) : nullptr;
     const float ts2 = 2.f / cv->t_scale;
     if ((e = timing_record(0, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     if ((e = cv_dispatch<CvNodeF>(T.kind, T.time_mode, true, na, (const uint16_t *)cv->s.bf, ts2, stream)) !=
@@ -1060,21 +1352,35 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     a.chunk = (uint32_t)pl.chunk;
     a.cpn = (uint32_t)cpn;
     a.total_chunks = (uint32_t)(n_nodes * cpn);
-    CvArgs c{};
-    c.bf = cv->s.bf;
-    c.tscale2 = ts2;
-    c.stride_iters = (uint32_t)(stride / 2);
-    c.r0 = (const float2 *)(ws + lay.r0);
-    c.cv_scores = cv_scores ? (float2 *)cv_scores : (float2 *)(ws + lay.cv_scores);
+    float2 *cv_rec = cv_scores ? (float2 *)cv_scores : (float2 *)(ws + lay.cv_scores);
     int bpc = pl.blocks_per_cu;
-    const int occ = cv_dispatch<CvOccF>(T.kind, T.time_mode, T.uniform);
-    if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
-    if ((e = cv_dispatch<CvLaunchF>(T.kind, T.time_mode, T.uniform, a, c, n_cu * bpc, stream)) != hipSuccess)
-        return hip_fail(e, "control-variate path kernel launch");
+    if (!mg) {
+        CvArgs c{};
+        c.bf = cv->s.bf;
+        c.tscale2 = ts2;
+        c.stride_iters = (uint32_t)(stride / 2);
+        c.r0 = (const float2 *)(ws + lay.r0);
+        c.cv_scores = cv_rec;
+        const int occ = cv_dispatch<CvOccF>(T.kind, T.time_mode, T.uniform);
+        if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
+        if ((e = cv_dispatch<CvLaunchF>(T.kind, T.time_mode, T.uniform, a, c, n_cu * bpc, stream)) != hipSuccess)
+            return hip_fail(e, "control-variate path kernel launch");
+    } else {
+        MgArgs c{};
+        c.bf = cv->s.bf;
+        c.tscale2 = ts2;
+        c.stride_iters = (uint32_t)(stride / 2);
+        c.g0 = (const float4 *)(ws + lay.g0);
+        c.cv_scores = cv_rec;
+        const int occ = cv_dispatch<MgOccF>(T.kind, T.time_mode, T.uniform);
+        if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
+        if ((e = cv_dispatch<MgLaunchF>(T.kind, T.time_mode, T.uniform, a, c, n_cu * bpc, stream)) != hipSuccess)
+            return hip_fail(e, "control-variate path kernel launch");
+    }
     if ((e = timing_record(1, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
 
     ReduceArgs r{};
-    r.scores = c.cv_scores;
+    r.scores = cv_rec;
     r.exit_step = nullptr;
     r.outs = (const OutDev *)(ws + lay.outs_cv);
     r.n_out = n_nodes;

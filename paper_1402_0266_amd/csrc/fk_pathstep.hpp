@@ -35,17 +35,18 @@ __device__ __forceinline__ void comp_add(float &hi, float &lo, float inc) {
 }
 
 // One Euler-Maruyama step with centre offset (ox, oy); returns true if the
-// new point is outside the closed unit square.  UNIFORM: every step has
-// length dt (t/dt integral), so the last-step selection is compiled out.
+// new point is outside the closed unit square, and the step's Brownian part
+// sqrt(2 D) z in (dwx, dwy).  UNIFORM: every step has length dt (t/dt
+// integral), so the last-step selection is compiled out.
 template <int KIND, bool UNIFORM>
-__device__ __forceinline__ bool em_step(Lane &L, uint32_t ra, uint32_t rb, float ox, float oy) {
+__device__ __forceinline__ bool em_step_w(Lane &L, uint32_t ra, uint32_t rb, float ox, float oy, float &dwx,
+                                          float &dwy) {
     float D = L.dt, cb = L.cbm;
     if constexpr (!UNIFORM) {
         const bool last = (L.k == L.K - 1);
         D = last ? L.dt_last : D;
         cb = last ? L.cbm_last : cb;
     }
-    float dwx, dwy;
     brownian_increment(ra, rb, cb, dwx, dwy);
     float bx, by;
     drift<KIND>(L.dens, ox, oy, L.xh, L.yh, bx, by);
@@ -59,6 +60,14 @@ __device__ __forceinline__ bool em_step(Lane &L, uint32_t ra, uint32_t rb, float
     return (lo < 0.f) | (hi > 0.f);
 }
 
+template <int KIND, bool UNIFORM>
+__device__ __forceinline__ bool em_step(Lane &L, uint32_t ra, uint32_t rb, float ox, float oy) {
+    float dwx, dwy;
+    return em_step_w<KIND, UNIFORM>(L, ra, rb, ox, oy, dwx, dwy);
+}
+
+// Bilinear interpolation in a nodal grid; off the grid, the nearest cell's
+// bilinear function continued (linear extrapolation).
 __device__ __forceinline__ float grid_bilinear(const double *g, int n, float x, float y) {
     const float fx = x * (float)n, fy = y * (float)n;
     int i = (int)floorf(fx), j = (int)floorf(fy);
@@ -116,8 +125,10 @@ __device__ __forceinline__ void lane_start(Lane &L, const NodeDev &nd, const Lev
 // Score of a finished path (eq. (7b)): boundary data at the exit point if
 // it left the square (out), else the initial data at its end point.  With
 // a.shift the identity scores are stored relative to the start point.
+// FK_SCORE_EXTEND scores an exit with the grid initial data extrapolated
+// bilinearly to the exit point (grid_bilinear extrapolates off the grid).
 __device__ __forceinline__ void score_path(const PathArgs &a, const Lane &L, bool out, float &sx, float &sy) {
-    const int kind = out ? a.bdry_kind : a.init_kind;
+    const int kind = out ? (a.score_mode == FK_SCORE_EXTEND ? FK_DATA_GRID : a.bdry_kind) : a.init_kind;
     float x = L.xh, y = L.yh;
     float lx = L.xl, ly = L.yl;
     if (out && a.score_mode == FK_SCORE_PROJECT) {

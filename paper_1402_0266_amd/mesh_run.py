@@ -7,7 +7,9 @@ t^n + dt_mesh:
 2. the interface values at t^{n+1} come from the Feynman-Kac Monte-Carlo
    solve (Sect. 3), with the current mesh as initial data (bilinear in the
    device grid) and the identity map as outer boundary data; with a trained
-   network the control-variate form of the estimator is used;
+   network a control-variate form of the estimator is used (by default the
+   martingale form, which stays unbiased when the network's gradient is
+   taken only every `cv_stride` steps);
 3. every sub-domain takes one implicit backward-Euler step with those
    interface values as Dirichlet data (Sect. 4);
 4. the mesh quality (minimum Jacobian, maximum skewness) is recorded.
@@ -28,8 +30,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import (FkCv, fk_interface_solve, fk_interface_solve_cv, fk_mesh_quality, subdomain_solve,
-               subdomain_workspace_bytes)
+from . import (FK_CV_DYNKIN, FK_CV_MARTINGALE, FkCv, fk_interface_solve, fk_interface_solve_cv, fk_mesh_quality,
+               subdomain_solve, subdomain_workspace_bytes)
 
 DATA_GRID = 3
 DATA_IDENTITY = 0
@@ -46,11 +48,13 @@ class MeshRunConfig:
     n_steps: int = 200
     n_paths: int = 1 << 14
     refit_every: int = 20       # 0: plain Monte Carlo throughout
-    cv_stride: int = 10
+    cv_form: str = "martingale"  # or "dynkin"
+    cv_stride: int = 20
     train_steps: int = 2000
     train_batch: int = 8192
     lr: float = 1e-3
     t_scale: float = 0.1        # network time input range [0, t_scale]
+    score_mode: int = 2         # exits: 2 the mesh extended past the edge; 1 projected; 0 unclamped identity
     labels: str = "band"        # "band": mesh values near the interfaces; "interface": the MC estimates
     band: float = 0.06          # half-width of the label band around each interface line
     band_stride: int = 3        # grid stride of the band samples
@@ -75,11 +79,23 @@ class Density:
 @dataclass(frozen=True)
 class GridData:
     """Fields of the C struct fk_data for grid initial data and identity
-    boundary data (the grid pointers are passed separately)."""
+    boundary data (the grid pointers are passed separately).
+
+    Exits are scored with the mesh continued bilinearly past the edge
+    (FK_SCORE_EXTEND): the discrete exit test sees a path only after a
+    step's overshoot of O(sqrt(dt)) beyond the edge, and scoring there is
+    unbiased to first order only if the data are continued with the
+    solution's own normal slope.  The identity continued unclamped has slope
+    1 where a relaxed mesh meets the boundary at a very different slope, and
+    a projected exit point drops the overshoot altogether; both bias the
+    interface values next to the boundary -- on a 768-cell grid enough to
+    fold the cells where an interface line meets the boundary.  The mesh's
+    edge nodes hold the identity boundary data, so its continuation is that
+    data extended by the mesh's slope."""
     t_init: float
     init_kind: int = DATA_GRID
     bdry_kind: int = DATA_IDENTITY
-    score_mode: int = 0
+    score_mode: int = 2
 
 
 def two_bump_density(t_freeze: float) -> Density:
@@ -191,15 +207,16 @@ class MeshRun:
             raise RuntimeError("the run has taken all its steps")
         tn = self.n * cfg.dt_mesh
         dens = self.density_fn(tn)
-        data = GridData(t_init=tn)
+        data = GridData(t_init=tn, score_mode=cfg.score_mode)
         grids = (self.xi.view(-1), self.eta.view(-1))
         if self.cv is not None and self.n % cfg.refit_every == 0:
             self.refit()
         dt = cfg.dt_mesh / cfg.substeps
         if self.cv is not None:
+            form = FK_CV_MARTINGALE if cfg.cv_form == "martingale" else FK_CV_DYNKIN
             out = fk_interface_solve_cv(dens, data, self.pts, cfg.dt_mesh, dt, cfg.n_paths, self.cv,
-                                        stride=cfg.cv_stride, seed=cfg.seed, level_id=self.n, plain=False,
-                                        device=self.dev, workspace=self.workspace, grids=grids)
+                                        stride=cfg.cv_stride, seed=cfg.seed, level_id=self.n, form=form,
+                                        plain=False, device=self.dev, workspace=self.workspace, grids=grids)
             self.used_cv[self.n] = True
         else:
             out = fk_interface_solve(dens, data, self.pts, cfg.dt_mesh, dt, cfg.n_paths, seed=cfg.seed,

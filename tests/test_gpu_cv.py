@@ -175,3 +175,41 @@ def test_trained_network_gain(fk):
     z = (cvm - ref) / np.sqrt(cvs ** 2 + fd[:, 4:6] ** 2)
     assert abs(float(z.mean())) < 0.5 and float(np.sqrt(np.mean(z ** 2))) < 1.5
     cv.close()
+
+
+@pytest.mark.parametrize("stride", [2, 20])
+def test_cv_martingale_against_oracle(fk, oracle_mod, stride):
+    """Martingale form: the same paths; the GPU takes the network's gradient
+    with BF16 activations (relative error ~1e-2), which changes each path's
+    martingale sum a little but not its zero mean."""
+    import torch
+    cv = fk.FkCv(W.mlp_init(7), T)
+    _, bf = cv.params()
+    dens = W.moving_bump()
+    pts = W.interface_nodes(4, 4, 16)[::3]
+    t, dt, N = 0.01, 1e-4, 512
+    print(f"[gpu] cv martingale stride={stride} nodes={len(pts)} N={N}", flush=True)
+    g = fk.fk_interface_solve_cv(dens, W.Data(), pts, t, dt, N, cv, stride=stride, seed=3, form=fk.FK_CV_MARTINGALE,
+                                 exit_step=True, cv_scores=True)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in g.items() if not k.startswith("_")}
+    o = oracle_mod.fk_solve_cv(dens, W.Data(), pts, t, dt, N, seed=3, uhat=oracle_mod.UHAT_MLP, flat=bf, t_scale=T,
+                               stride=stride, form=oracle_mod.CV_MARTINGALE, want_scores=True, want_exit=True,
+                               threads=THREADS)
+    plain = {"xi": g["plain_xi"], "eta": g["plain_eta"], "se_xi": g["plain_se_xi"], "se_eta": g["plain_se_eta"],
+             "exit_step": g["exit_step"]}
+    assert_parity(plain, {"mean": o["plain_mean"], "se": o["plain_se"], "exit_step": o["exit_step"]}, pts,
+                  label="plain part:")
+    same = g["exit_step"] == o["exit_step"]
+    po = oracle_mod.fk_solve(dens, W.Data(), pts, t, dt, N, seed=3, want_scores=True, threads=THREADS)["scores"]
+    msum = np.abs(po - o["cv_scores"])[same]           # |martingale sum| per path (oracle)
+    ds = np.abs(g["cv_scores"].astype(np.float64) - o["cv_scores"])[same]
+    rel = ds.max(axis=-1) / np.maximum(msum.max(axis=-1), 1e-3)
+    mean_g = np.stack([g["xi"], g["eta"]], 1)
+    d = np.abs(mean_g - o["mean"])
+    print(f"martingale: max |score diff| {ds.max():.2e} (max |sum| {msum.max():.3g}, max rel {rel.max():.2e}), "
+          f"max |mean diff| {d.max():.2e}, se ratio cv/plain {np.median(o['se'] / o['plain_se']):.3f}", flush=True)
+    assert rel.max() < 0.05
+    assert np.all(d <= 3 * o["se"]) and np.all(d <= 1e-5)
+    assert np.all(np.abs(np.stack([g["se_xi"], g["se_eta"]], 1) - o["se"]) <= 0.05 * o["se"])
+    cv.close()

@@ -68,11 +68,12 @@ def test_plain_mesh_run_against_oracle(fk, oracle_mod):
     run.close()
 
 
-def test_cv_mesh_run_against_oracle(fk, oracle_mod):
+@pytest.mark.parametrize("form", ["martingale", "dynkin"])
+def test_cv_mesh_run_against_oracle(fk, oracle_mod, form):
     from paper_1402_0266_amd.mesh_run import MeshRun, MeshRunConfig
     n_paths, stride = 4096, 10
     cfg = MeshRunConfig(px=PX, m=M, n_steps=3, n_paths=n_paths, refit_every=2, cv_stride=stride, train_steps=300,
-                        train_batch=4096, lr=3e-3)
+                        train_batch=4096, lr=3e-3, cv_form=form)
     run = MeshRun(cfg, init_params=W.mlp_init(0))
     sub = np.arange(0, run.n_nodes, 11)
     for n in range(3):
@@ -80,12 +81,16 @@ def test_cv_mesh_run_against_oracle(fk, oracle_mod):
         print(f"[gpu] mesh run cv step {n}, {run.n_nodes} nodes, N={n_paths}", flush=True)
         run.step()
         _, bf = run.cv.params()                  # the network this step used (refits come first)
-        data = W.Data(init_kind=W.DATA_GRID, t_init=n * D, grid_xi=xi_n, grid_eta=eta_n)
+        data = W.Data(init_kind=W.DATA_GRID, score_mode=W.SCORE_EXTEND, t_init=n * D, grid_xi=xi_n,
+                      grid_eta=eta_n)
         o = oracle_mod.fk_solve_cv(W.two_bumps(W.TIME_FROZEN, n * D), data, run.pts[sub], D, D / 20, n_paths,
                                    level_id=n, node_ids=sub, flat=bf, t_scale=W.CV_T_SCALE, stride=stride,
+                                   form=oracle_mod.CV_MARTINGALE if form == "martingale" else oracle_mod.CV_DYNKIN,
                                    want_scores=True, threads=THREADS)
         iface, se = run.interface_values()
-        smax = np.abs(o["cv_scores"]).max()
+        # Dynkin-form scores g - u_hat(end) + sum r ds carry the network's
+        # relative evaluation error (~1e-5) on their own scale
+        smax = np.abs(o["cv_scores"]).max() if form == "dynkin" else 1.0
         d = np.abs(iface[n, sub] - o["mean"])
         ratio = np.median(o["se"] / o["plain_se"])
         print(f"step {n}: cv max |gpu - oracle| {d.max():.2e}, score scale {smax:.3g}, se cv/plain {ratio:.3f}",

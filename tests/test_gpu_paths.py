@@ -102,9 +102,11 @@ def test_ridge_eta_exact(fk, torch_cuda, oracle_mod):
     assert np.all(np.abs(g["eta"] - pts[:, 1]) <= 4.5 * g["se_eta"])
 
 
-def test_two_bumps_frozen_grid_data(fk, torch_cuda, oracle_mod):
+@pytest.mark.parametrize("score_mode", [W.SCORE_PROJECT, W.SCORE_EXTEND])
+def test_two_bumps_frozen_grid_data(fk, torch_cuda, oracle_mod, score_mode):
     """Two counter-rotating bumps frozen at t_n, initial data bilinear in a
-    nodal grid (one mesh step), projected boundary scoring."""
+    nodal grid (one mesh step), exits scored on the projected point or with
+    the grid continued past the edge; nodes next to the edges included."""
     import torch
     n = 48
     x = np.arange(n + 1) / n
@@ -112,9 +114,11 @@ def test_two_bumps_frozen_grid_data(fk, torch_cuda, oracle_mod):
     gx = X + 0.02 * np.sin(np.pi * X) * np.sin(2 * np.pi * Y)
     gy = Y + 0.02 * np.sin(2 * np.pi * X) * np.sin(np.pi * Y)
     dens = W.two_bumps(W.TIME_FROZEN, t_freeze=0.0375)
-    data = W.Data(init_kind=W.DATA_GRID, bdry_kind=W.DATA_IDENTITY, score_mode=W.SCORE_PROJECT,
+    data = W.Data(init_kind=W.DATA_GRID, bdry_kind=W.DATA_IDENTITY, score_mode=score_mode,
                   t_init=0.0375, grid_xi=gx.ravel(), grid_eta=gy.ravel())
-    pts = W.interface_nodes(4, 4, 48)[::7]
+    nodes = W.interface_nodes(4, 4, 48)
+    near_edge = np.minimum(nodes, 1 - nodes).min(1) < 0.05
+    pts = np.concatenate([nodes[::7], nodes[near_edge][::3]])
     grids = (torch.tensor(gx.ravel(), device="cuda"), torch.tensor(gy.ravel(), device="cuda"))
     g = run_gpu(fk, torch_cuda, dens, data, pts, 5e-4, 2.5e-5, 4000, seed=11, grids=grids)
     o = run_oracle(oracle_mod, dens, data, pts, 5e-4, 2.5e-5, 4000, seed=11)

@@ -144,3 +144,31 @@ def test_two_bump_dd_keeps_global_quality(oracle_mod):
         jd, sd = S.mesh_quality(xi, eta)
         assert jd > 0 and abs(jd - jg) <= 0.05 * jg and abs(sd - sg) <= 0.02, (n, jd, jg, sd, sg)
         assert jg < 0.95                         # the bumps really deform the mesh
+
+
+def test_exit_scoring_near_a_compressed_boundary(oracle_mod):
+    """w = 1 and a mesh whose normal slope at x = 0 is 1/2 (xi = x (1 + x) / 2).
+    The discrete exit test sees a path one step's overshoot past the edge.
+    The identity continued unclamped has slope 1 there, and a projected exit
+    point drops the overshoot: both bias the nodes next to the edge.  The
+    mesh continued bilinearly (its edge nodes hold the identity data) has the
+    solution's slope and is unbiased to first order.  Reference: the global
+    solve over the mesh step in 10 backward-Euler sub-steps."""
+    px, m, D = 4, 16, 5e-4
+    N = px * m
+    X, Y = nodal(N)
+    xi0, eta0 = X * (1 + X) / 2, Y.copy()
+    a, b = xi0, eta0
+    for _ in range(10):
+        a, b = S.global_be_step(W.CONST, 0.0, D / 10, N, a, b)
+    ij_all = S.interface_index(px, m)
+    ids = np.array([k for k, (i, j) in enumerate(ij_all) if i in (1, 2) and j == 2 * m])
+    ij = ij_all[ids]
+    ref = a[ij[:, 1], ij[:, 0]]
+    z = {}
+    for mode in (W.SCORE_UNCLAMPED, W.SCORE_PROJECT, W.SCORE_EXTEND):
+        mc = MS.interface_solve(W.CONST, 0.0, D, 20, px, m, xi0, eta0, 200000, node_ids=ids, score_mode=mode,
+                                threads=THREADS)
+        z[mode] = (mc["mean"][:, 0] - ref) / mc["se"][:, 0]
+    assert np.all(np.abs(z[W.SCORE_EXTEND]) < 4), z
+    assert z[W.SCORE_UNCLAMPED][0] < -8 and z[W.SCORE_PROJECT][0] > 8, z

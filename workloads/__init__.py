@@ -46,6 +46,7 @@ DATA_GRID = 3         # initial data bilinear in a (n+1)^2 nodal grid (initial d
 
 SCORE_UNCLAMPED = 0   # evaluate the boundary data at the (unclamped) first outside point
 SCORE_PROJECT = 1     # clamp that point onto the closed square first
+SCORE_EXTEND = 2      # the grid initial data continued bilinearly to that point
 
 # Philox stream tags (low 4 bits of the last counter word).
 STREAM_PATHS = 0
