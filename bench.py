@@ -12,7 +12,23 @@ solve at the configured 10^5 paths/node gives the mean per-node score variance
 s2 and the bias b^2 = max(0, RMS^2 - s2/N); the paths needed for RMS 1e-3 are
 N* = ceil(s2 / (1e-6 - b^2)); each timed step is one full solve at N*.
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+The same line reports, as extra objects:
+
+* "cv": the learned control variate on the same workload -- training labels
+  from batched plain solves (132 time levels in [0, 0.1] x 1521 nodes x 1024
+  paths), 2000 Adam steps on the GPU, then the control-variate solve in its
+  martingale form at the stride that reaches RMS 1e-3 fastest (pilot at 4096
+  paths), timed at its own N*; the Dynkin form at stride 50 beside it.
+  Throughput is quoted for the solve alone and with the labels and training
+  counted once.
+* "mesh_run": the time-dependent run -- 8 x 8 sub-domains on a 768-cell
+  grid, two counter-rotating bumps, 200 mesh steps of 5e-4 with 20
+  Euler-Maruyama steps each, 2^14 paths per interface node (10689 nodes),
+  64 FP64 sub-domain solves per step; with the network refitted every 20
+  steps, and plain for comparison; mesh quality is recorded every step (the
+  tests compare it with the oracle's global step).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-cv] [--no-mesh-run]
 """
 from __future__ import annotations
 
@@ -45,10 +61,10 @@ FLOP_PER_STEP = 36
 # HBM traffic of the path kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
 # (scaled by a plain 1 GiB copy: fetch x2.0, write x1.0), per path, valid only
 # for the kernel sources it was measured on (hash below); otherwise null.
-TRAFFIC_BYTES_PER_PATH = (0.4625 * 2**20 + 1071540.40625 * 1024) / (1521 * 73858)
-TRAFFIC_SOURCE_HASH = "2253d4a70496d3d2"
+TRAFFIC_BYTES_PER_PATH = (2.0 * 238.5 + 1.0 * 1054600.71875) * 1024 / (1521 * 73858)
+TRAFFIC_SOURCE_HASH = "3cd9f7900147089f"
 KERNEL_SOURCES = ["paper_1402_0266_amd/csrc/fk_paths.hip", "paper_1402_0266_amd/csrc/fk_device.hpp",
-                  "paper_1402_0266_amd/csrc/fk_internal.hpp"]
+                  "paper_1402_0266_amd/csrc/fk_internal.hpp", "paper_1402_0266_amd/csrc/fk_pathstep.hpp"]
 
 
 def kernel_source_hash() -> str:
@@ -92,12 +108,121 @@ def cpu_baseline(wl, n_star, sample_nodes=96, sample_paths=2048):
                       f"{el:.2f}s, scaled by {sample_paths}/{n_star} paths"}
 
 
+def _stack(r, keys):
+    return np.stack([r[keys[0]].cpu().numpy(), r[keys[1]].cpu().numpy()], 1)
+
+
+def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=4096):
+    """Labels, training and the control-variate solve; nodes/s at RMS 1e-3."""
+    import torch
+    from paper_1402_0266_amd import cv_pipeline as P
+    n_nodes = len(pts)
+    ref = fd[:, 2:4]
+    print("[bench] cv: labels", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    txy, target = P.make_labels(wl.density, wl.data, pts, W.cv_label_levels(132, W.CV_T_SCALE), wl.dt, label_paths,
+                                seed=1)
+    torch.cuda.synchronize()
+    t_labels = time.perf_counter() - t0
+    cv = fk.FkCv(W.mlp_init(0), W.CV_T_SCALE)
+    t0 = time.perf_counter()
+    loss = P.train(cv, txy, target, steps=2000, batch=8192, lr=1e-3, seed=2)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    loss = loss.cpu().numpy()
+
+    def solve(n_paths, form, stride):
+        return fk.fk_interface_solve_cv(wl.density, wl.data, pts, wl.t, wl.dt, n_paths, cv, stride=stride,
+                                        seed=wl.seed, form=form)
+
+    def pilot(form, stride):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = solve(pilot_paths, form, stride)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        est, se = _stack(r, ("xi", "eta")), _stack(r, ("se_xi", "se_eta"))
+        var = float(np.mean(se ** 2) * pilot_paths)
+        pse = _stack(r, ("plain_se_xi", "plain_se_eta"))
+        b2 = max(0.0, float(np.mean((est - ref) ** 2)) - var / pilot_paths)
+        n_star = int(math.ceil(var / (1e-6 - b2))) if b2 < 1e-6 else None
+        return {"form": "martingale" if form == fk.FK_CV_MARTINGALE else "dynkin", "stride": stride,
+                "pilot_s": el, "var": var, "var_ratio": float(np.mean(pse ** 2) / np.mean(se ** 2)),
+                "bias": math.sqrt(b2), "n_star": n_star,
+                "predicted_s": None if n_star is None else el * n_star / pilot_paths}
+
+    solve(256, fk.FK_CV_MARTINGALE, 20)         # first-launch costs out of the pilots
+    pilots = [pilot(fk.FK_CV_MARTINGALE, s) for s in (20, 100, 500, 2000)] + [pilot(fk.FK_CV_DYNKIN, 50)]
+    best = min((p for p in pilots if p["form"] == "martingale" and p["n_star"]),
+               key=lambda p: p["predicted_s"])
+    form, stride, n_star = fk.FK_CV_MARTINGALE, best["stride"], max(2, best["n_star"])
+    print(f"[bench] cv: martingale stride {stride}, N* = {n_star}", file=sys.stderr, flush=True)
+    for _ in range(warmup):
+        solve(n_star, form, stride)
+    torch.cuda.synchronize()
+    fk.fk_timing_enable(True)
+    kern = []
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = solve(n_star, form, stride)
+        kern.append(fk.fk_timing_last()[0])
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    fk.fk_timing_enable(False)
+    rms = float(np.sqrt(np.mean((_stack(r, ("xi", "eta")) - ref) ** 2)))
+    cv.close()
+    return {
+        "form": "martingale", "stride": stride, "paths_per_node": n_star, "rms_err": rms,
+        "s_per_solve": wall, "path_kernel_ms": float(np.mean(kern)),
+        "nodes_per_s": n_nodes / wall,
+        "nodes_per_s_incl_labels_and_training": n_nodes / (wall + t_labels + t_train),
+        "labels": {"levels": 132, "paths": label_paths, "n": int(txy.shape[0]), "s": t_labels},
+        "training": {"steps": 2000, "batch": 8192, "lr": 1e-3, "s": t_train, "loss_first": float(loss[0]),
+                     "loss_last50": float(loss[-50:].mean())},
+        "pilots": pilots,
+    }
+
+
+def measure_mesh_run():
+    """The time-dependent mesh run, with the network and plain."""
+    import torch
+    from paper_1402_0266_amd.mesh_run import MeshRun, MeshRunConfig
+    res = {}
+    for name, kw in (("cv", {}), ("plain", {"refit_every": 0})):
+        cfg = MeshRunConfig(**kw)
+        print(f"[bench] mesh run ({name}): {cfg.n_steps} steps", file=sys.stderr, flush=True)
+        run = MeshRun(cfg, init_params=W.mlp_init(0) if cfg.refit_every else None)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for n in range(cfg.n_steps):
+            run.step()
+            if n % 50 == 49:
+                print(f"[bench] mesh run ({name}): step {n + 1}", file=sys.stderr, flush=True)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        q = run.qualities()
+        _, se = run.interface_values()
+        run.close()
+        res[name] = {"s_total": wall, "ms_per_step": wall / cfg.n_steps * 1e3,
+                     "min_jac_min": float(q[:, 0].min()), "min_jac_final": float(q[-1, 0]),
+                     "max_skew_max": float(q[:, 1].max()), "max_skew_final": float(q[-1, 1]),
+                     "min_jac_every_20": q[19::20, 0].round(4).tolist(),
+                     "se_median": float(np.median(se)), "se_max": float(se.max())}
+    res["config"] = ("8x8 sub-domains, 768-cell grid, 10689 interface nodes, two counter-rotating bumps A=30 "
+                     "s2=0.003 frozen per step, 200 steps of 5e-4, 20 EM steps each, 2^14 paths/node; cv: "
+                     "martingale form, stride 20, refit every 20 steps on mesh labels near the interfaces")
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cv", action="store_true", help="skip the control-variate measurement")
+    ap.add_argument("--no-mesh-run", action="store_true", help="skip the time-dependent mesh run")
     ap.add_argument("--paths", type=int, default=0, help="fix paths/node and skip the N* pilot (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scales HBM counters) and exit")
@@ -208,6 +333,10 @@ def main():
             "flop_per_path_step": FLOP_PER_STEP,
         },
     }
+    if not args.no_cv and fd is not None:
+        out["cv"] = measure_cv(fk, wl, pts, fd, args.steps, args.warmup)
+    if not args.no_mesh_run:
+        out["mesh_run"] = measure_mesh_run()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, n_star)

@@ -100,3 +100,47 @@ def test_cv_mesh_run_against_oracle(fk, oracle_mod, form):
         assert ratio < 0.5                       # the network pays off from the first step
         assert run.qualities()[n][0] > 0
     run.close()
+
+
+def test_full_size_first_step_against_oracle(fk, oracle_mod):
+    """The full run's configuration (8 x 8 sub-domains on a 768-cell grid,
+    10689 interface nodes, 2^14 paths, martingale control variate at stride
+    20): its first step against the oracle -- interface values on every 97th
+    node, the sub-domain solves, and the quality of the global step.
+
+    From the identity mesh the first step crosses the flow's stiff initial
+    layer: the interface values follow the flow itself, the interiors one
+    backward-Euler step, and next to the interfaces the composed map bends
+    between the two.  At 768 cells that puts its minimum Jacobian ~15% below
+    the global one-step solve's (0.84; the flow's own, from ten sub-steps,
+    is 0.80), hence 20% here."""
+    import time
+    from paper_1402_0266_amd.mesh_run import MeshRun, MeshRunConfig
+    cfg = MeshRunConfig(n_steps=1)
+    run = MeshRun(cfg, init_params=W.mlp_init(0))
+    xi0, eta0 = run.mesh()
+    print(f"[gpu] full-size mesh step: {run.n_nodes} nodes x {cfg.n_paths} paths", flush=True)
+    t0 = time.perf_counter()
+    run.step()
+    iface, se = run.interface_values()
+    print(f"gpu step {time.perf_counter() - t0:.2f}s", flush=True)
+    _, bf = run.cv.params()
+    sub = np.arange(0, run.n_nodes, 97)
+    dens = W.two_bumps(W.TIME_FROZEN, 0.0)
+    data = W.Data(init_kind=W.DATA_GRID, score_mode=W.SCORE_EXTEND, t_init=0.0, grid_xi=xi0, grid_eta=eta0)
+    o = oracle_mod.fk_solve_cv(dens, data, run.pts[sub], cfg.dt_mesh, cfg.dt_mesh / cfg.substeps, cfg.n_paths,
+                               node_ids=sub, flat=bf, t_scale=cfg.t_scale, stride=cfg.cv_stride,
+                               form=oracle_mod.CV_MARTINGALE, threads=THREADS)
+    d = np.abs(iface[0, sub] - o["mean"])
+    print(f"interface: max |gpu - oracle| {d.max():.2e}, max d/se {(d / o['se']).max():.2f}, "
+          f"se cv/plain {np.median(o['se'] / o['plain_se']):.3f}", flush=True)
+    assert np.all(d <= 3 * o["se"]) and np.all(d <= 1e-5)
+    gx, gy = run.mesh()
+    sx, sy = S.subdomain_be_step(dens, 0.0, cfg.dt_mesh, cfg.px, cfg.m, xi0, eta0, iface[0, :, 0], iface[0, :, 1])
+    assert np.abs(gx - sx).max() < 1e-12 and np.abs(gy - sy).max() < 1e-12
+    q = run.qualities()[0]
+    assert abs(q[0] - S.mesh_quality(gx, gy)[0]) < 1e-12
+    jg, sg = S.mesh_quality(*S.global_be_step(dens, 0.0, cfg.dt_mesh, cfg.px * cfg.m, xi0, eta0))
+    print(f"quality: min J {q[0]:.4f} (global step {jg:.4f}), max skew {q[1]:.4f} (global {sg:.4f})", flush=True)
+    assert q[0] > 0 and abs(q[0] - jg) <= 0.20 * jg and abs(q[1] - sg) <= 0.02
+    run.close()
