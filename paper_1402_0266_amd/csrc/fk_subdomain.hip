@@ -12,13 +12,14 @@
 // MI355X mapping: one workgroup per sub-domain.  With the q x q interior
 // unknowns in row-major order the matrix is banded with half-bandwidth
 // p = q, and the fill of the LU stays in the band; elimination step k only
-// touches rows and columns k..k+p.  That (p+1)^2 FP64 window lives in LDS
-// (74 KB for q = 95) and is indexed circularly, so each step slides it by one
-// row and one column: the new row and column enter with their original
-// stencil values (at most five non-zeros), computed on the fly.  Both
-// right-hand sides (xi and eta) are eliminated with the same multipliers.
-// Finished U rows go to the workspace; one wavefront then back-substitutes,
-// prefetching the next U row while it reduces the current one.
+// touches rows and columns k..k+p, and the new row and column that enter
+// the (p+1)^2 window carry their original stencil values (at most five
+// non-zeros).  Both right-hand sides (xi and eta) are eliminated with the
+// same multipliers.  For the sub-domain sizes it is built for, the window
+// lives in registers, one column per thread (subdomain_lu_kernel); other
+// sizes keep it in LDS, indexed circularly (subdomain_be_kernel).  Finished U
+// rows go to the workspace; one wavefront then back-substitutes, prefetching
+// the next U row while it reduces the current one.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -35,6 +36,8 @@ struct SubArgs {
     double *xi_out, *eta_out;    // Dirichlet data pre-filled; interior written
     double *ubuf;                // per sub-domain: n * (p+1) doubles
     double *ybuf;                // per sub-domain: 2 n doubles
+    double *cbuf;                // per sub-domain: 4 n doubles, (E, W, N, S) coefficients of each row
+    double *rbuf;                // per sub-domain: 2 n doubles, right-hand sides (xi, eta) of each row
     int N, m, px;
     double c, half_d_over_h;     // D/h^2 and D/(2h)
     int kind;
@@ -72,6 +75,276 @@ __device__ void drift_f64(const SubArgs &a, double x, double y, double &bx, doub
 }
 
 constexpr int kMaxP1 = 128;  // window side limit: q <= 127 interior nodes per side
+
+constexpr int kB = 32;   // steps per staging batch of the register-window kernel
+
+// Back substitution by one wavefront: x_k = (y_k - sum_j U[k][k+j] x_{k+j}) /
+// U[k][k] for k = n-1 .. 0.  Lane l holds x_{k+l+1} and x_{k+l+65} in
+// registers (shifted down one lane per row), and the U rows and y values are
+// loaded kD rows at a time, the next block while the current one is reduced.
+template <int P1>
+__device__ __forceinline__ void back_substitute_blocked(const SubArgs &a, const double *U, const double *Y, int n,
+                                                        int i0, int j0) {
+    constexpr int p = P1 - 1, q = P1 - 1, kD = 8;
+    const int N1 = a.N + 1;
+    const int lane = threadIdx.x & 63;
+    double xr0 = 0.0, xr1 = 0.0;   // x_{k+lane+1}, x_{k+lane+65} (0 beyond n)
+    double c0[kD], c1[kD], cd[kD], cyx[kD], cyy[kD];
+    double n0[kD], n1[kD], nd[kD], nyx[kD], nyy[kD];
+    auto load = [&](int top, double *u0, double *u1, double *ud, double *yx, double *yy) {
+#pragma unroll
+        for (int j = 0; j < kD; ++j) {
+            const int k = top - j;
+            const bool ok = k >= 0;
+            const double *row = U + (int64_t)(ok ? k : 0) * P1;
+            u0[j] = (ok && lane + 1 <= p) ? row[lane + 1] : 0.0;
+            u1[j] = (ok && lane + 65 <= p) ? row[lane + 65] : 0.0;
+            ud[j] = ok ? row[0] : 1.0;
+            yx[j] = ok ? Y[k] : 0.0;
+            yy[j] = ok ? Y[n + k] : 0.0;
+        }
+    };
+    load(n - 1, c0, c1, cd, cyx, cyy);
+    double yr0 = 0.0, yr1 = 0.0;   // the same for eta
+    for (int top = n - 1; top >= 0; top -= kD) {
+        load(top - kD, n0, n1, nd, nyx, nyy);
+#pragma unroll
+        for (int j = 0; j < kD; ++j) {
+            const int k = top - j;
+            if (k < 0) break;
+            // U entries of columns beyond n are zero, and so is the ring there
+            double sx = fma(c0[j], xr0, c1[j] * xr1);
+            double sy = fma(c0[j], yr0, c1[j] * yr1);
+#pragma unroll
+            for (int off = 32; off > 0; off >>= 1) {
+                sx += __shfl_xor(sx, off, 64);
+                sy += __shfl_xor(sy, off, 64);
+            }
+            const double xk = (cyx[j] - sx) / cd[j], yk = (cyy[j] - sy) / cd[j];
+            const double x_top = __shfl(xr0, 63, 64), y_top = __shfl(yr0, 63, 64);
+            const double x1 = __shfl_up(xr1, 1, 64), y1 = __shfl_up(yr1, 1, 64);
+            const double x0 = __shfl_up(xr0, 1, 64), y0 = __shfl_up(yr0, 1, 64);
+            xr1 = (lane == 0) ? x_top : x1;
+            yr1 = (lane == 0) ? y_top : y1;
+            xr0 = (lane == 0) ? xk : x0;
+            yr0 = (lane == 0) ? yk : y0;
+            if (lane == 0) {
+                const int ii = k % q, jj = k / q;
+                const int64_t g = (int64_t)(j0 + 1 + jj) * N1 + (i0 + 1 + ii);
+                a.xi_out[g] = xk;
+                a.eta_out[g] = yk;
+            }
+        }
+#pragma unroll
+        for (int j = 0; j < kD; ++j) {
+            c0[j] = n0[j];
+            c1[j] = n1[j];
+            cd[j] = nd[j];
+            cyx[j] = nyx[j];
+            cyy[j] = nyy[j];
+        }
+    }
+}
+
+// Banded LU with the window in registers.  For P1 = q + 1 the window of
+// elimination step k is rows and columns k .. k + q.  Column slot t < P1
+// holds the columns c = t (mod P1), split over two lanes: the upper lane
+// keeps window rows 0 .. H-1 (H = P1/2) in v[0 .. H-1], the lower lane rows
+// H .. P1-1; four more lanes hold the two right-hand sides the same way.
+// Step k: the two lanes of the pivot column's slot write it to LDS (1/pivot
+// in place of the pivot), every upper lane publishes its row-k entry u and
+// every lower lane its first row, then one barrier; each lane updates and
+// shifts its rows in one pass,
+//   v[i] = v[i + 1] - pivotcol[i + 1] * (u / pivot),
+// the upper lane's last row taking the lower lane's first, the lower lane's
+// last row taking the original entry of the row k + P1 that enters.  The
+// pivot column becomes exactly zero and its slot takes the entering column
+// k + P1: non-zero only in rows k + 1 (north neighbour), k + q (east
+// neighbour) and k + P1 (diagonal).  LDS buffers alternate between steps, so
+// one barrier per step suffices; every register index is a compile-time
+// constant.  Rows and columns beyond n are identity padding.
+template <int P1>
+__global__ void __launch_bounds__(256) subdomain_lu_kernel(const SubArgs a) {
+    constexpr int q = P1 - 1, H = P1 / 2;
+    static_assert(P1 % 2 == 0 && H >= 2, "even window of at least 4");
+    __shared__ __align__(16) double Vs[2][P1];   // pivot column, 1/pivot first
+    __shared__ double Us[2][P1 + 2];    // row-k entry of every column and rhs
+    __shared__ double Ls[2][P1 + 2];    // first lower row of every column and rhs
+    __shared__ double Ust[2][kB][P1];   // U rows of a batch
+    __shared__ double2 Yst[2][kB];      // y values (xi, eta) of a batch
+    __shared__ double4 Cst[2][kB];      // coefficients of the entering rows R
+    __shared__ double2 Rst[2][kB];      // right-hand sides of the entering rows R
+    __shared__ double Nst[2][kB];       // north coefficients of the rows k + 1
+    const int n = q * q;
+    const int si = blockIdx.x % a.px, sj = blockIdx.x / a.px;
+    const int i0 = si * a.m, j0 = sj * a.m;
+    const int N1 = a.N + 1;
+    const double h = 1.0 / a.N;
+    double *U = a.ubuf + (int64_t)blockIdx.x * n * P1;
+    double *Y = a.ybuf + (int64_t)blockIdx.x * 2 * n;
+    double4 *cf = reinterpret_cast<double4 *>(a.cbuf + (int64_t)blockIdx.x * 4 * n);
+    double2 *rh = reinterpret_cast<double2 *>(a.rbuf + (int64_t)blockIdx.x * 2 * n);
+    const int tid = threadIdx.x;
+
+    // ---- every row's coefficients (Dirichlet neighbours moved to the rhs) --
+    for (int r = tid; r < n; r += blockDim.x) {
+        const int ii = r % q, jj = r / q;
+        const int gi = i0 + 1 + ii, gj = j0 + 1 + jj;
+        double bx, by;
+        drift_f64(a, gi * h, gj * h, bx, by);
+        const double cxr = a.half_d_over_h * bx, cyr = a.half_d_over_h * by;
+        const double cE = -a.c - cxr, cW = -a.c + cxr, cN = -a.c - cyr, cS = -a.c + cyr;
+        const int64_t g = (int64_t)gj * N1 + gi;
+        double fx = a.xi_n[g], fy = a.eta_n[g];
+        if (ii == q - 1) { fx -= cE * a.xi_out[g + 1]; fy -= cE * a.eta_out[g + 1]; }
+        if (ii == 0) { fx -= cW * a.xi_out[g - 1]; fy -= cW * a.eta_out[g - 1]; }
+        if (jj == q - 1) { fx -= cN * a.xi_out[g + N1]; fy -= cN * a.eta_out[g + N1]; }
+        if (jj == 0) { fx -= cS * a.xi_out[g - N1]; fy -= cS * a.eta_out[g - N1]; }
+        cf[r] = make_double4(ii < q - 1 ? cE : 0.0, ii > 0 ? cW : 0.0, jj < q - 1 ? cN : 0.0, jj > 0 ? cS : 0.0);
+        rh[r] = make_double2(fx, fy);
+    }
+    __threadfence_block();
+    __syncthreads();
+
+    const double diag = 1.0 + 4.0 * a.c;
+    // original matrix entry (r, c); identity beyond n
+    auto entry = [&](int r, int c) -> double {
+        if (r >= n || c >= n) return r == c ? 1.0 : 0.0;
+        const int d = c - r;
+        if (d == 0) return diag;
+        if (d != 1 && d != -1 && d != q && d != -q) return 0.0;
+        const double4 f = cf[r];
+        return d == 1 ? f.x : d == -1 ? f.y : d == q ? f.z : f.w;
+    };
+    // roles: column slot / right-hand side, and which half of the rows
+    const bool is_col = tid < 2 * P1;
+    const bool is_rhs = !is_col && tid < 2 * P1 + 4;
+    const int slot = is_col ? tid % P1 : 0;
+    const int rhs_c = is_rhs ? (tid - 2 * P1) & 1 : 0;            // 0: xi, 1: eta
+    const bool lower = is_col ? tid >= P1 : (is_rhs && tid - 2 * P1 >= 2);
+    const int pub = is_col ? slot : P1 + rhs_c;                    // index in Us / Ls
+    const int r0 = lower ? H : 0;                                  // first window row held
+    int col = slot;
+    double v[H];
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+        double e = 0.0;
+        if (is_col) e = entry(r0 + i, col);
+        else if (is_rhs && r0 + i < n) e = rhs_c == 0 ? rh[r0 + i].x : rh[r0 + i].y;
+        v[i] = e;
+    }
+
+    // Per-step memory traffic goes through LDS in batches of kB steps, so no
+    // step waits on global memory: the coefficients of the rows that enter
+    // (row R = k + P1: west, south, east and rhs; row k + 1: north) are
+    // loaded a batch ahead by the first kB lanes and staged in LDS; the U rows
+    // and y values a batch produces are staged in LDS and written out by the
+    // whole workgroup, coalesced, at the next batch boundary.
+    const int nb = (n + kB - 1) / kB;
+    auto load_batch = [&](int bt, double4 &c4, double2 &r2, double &cn) {
+        const int j = tid, kk = bt * kB + j, R = kk + P1;
+        const bool ok = tid < kB && bt < nb;
+        c4 = (ok && R < n) ? cf[R] : make_double4(0.0, 0.0, 0.0, 0.0);
+        r2 = (ok && R < n) ? rh[R] : make_double2(0.0, 0.0);
+        cn = (ok && kk + 1 < n) ? cf[kk + 1].z : 0.0;
+    };
+    double4 pc4;
+    double2 pr2;
+    double pcn;
+    load_batch(0, pc4, pr2, pcn);
+    double cE_Rm1 = (P1 - 1 < n) ? cf[P1 - 1].x : 0.0;   // east coefficient of row R - 1
+
+    int owner = 0;
+    for (int k = 0; k < n; ++k) {
+        const int b = k & 1;
+        const int R = k + P1;
+        const int j = k % kB, bt = k / kB, bb = bt & 1;
+        if (j == 0) {
+            // batch boundary: stage this batch's coefficients, fetch the next
+            if (tid < kB) {
+                Cst[bb][tid] = pc4;
+                Rst[bb][tid] = pr2;
+                Nst[bb][tid] = pcn;
+            }
+            load_batch(bt + 1, pc4, pr2, pcn);
+        }
+        if (is_col || is_rhs) {
+            if (lower) Ls[b][pub] = v[0];
+            else Us[b][pub] = v[0];
+        }
+        if (is_col && slot == owner) {
+            double2 *dst = reinterpret_cast<double2 *>(&Vs[b][r0]);
+            dst[0] = make_double2(lower ? v[0] : 1.0 / v[0], v[1]);
+#pragma unroll
+            for (int i = 2; i < H; i += 2) dst[i / 2] = make_double2(v[i], (i + 1 < H) ? v[i + 1] : 0.0);
+        }
+        __syncthreads();
+        if (j == 0 && bt > 0) {
+            // write out the previous batch's U rows and y values
+            const int kp = (bt - 1) * kB;
+            const double *src = &Ust[bb ^ 1][0][0];
+            double *dstU = U + (int64_t)kp * P1;
+            for (int e = tid; e < kB * P1; e += blockDim.x) dstU[e] = src[e];
+            if (tid < kB) {
+                Y[kp + tid] = Yst[bb ^ 1][tid].x;
+                Y[n + kp + tid] = Yst[bb ^ 1][tid].y;
+            }
+        }
+        if (is_col || is_rhs) {
+            const double u = lower ? Us[b][pub] : v[0];
+            if (!lower) {
+                if (is_col) Ust[bb][j][col - k] = u;
+                else if (rhs_c == 0) Yst[bb][j].x = u;
+                else Yst[bb][j].y = u;
+            }
+            // the pivot column itself: scale exactly 1, so it becomes exactly zero
+            const double sc = (is_col && slot == owner) ? 1.0 : u * Vs[b][0];
+            const double nxt = lower ? 0.0 : Ls[b][pub];        // the row below the upper half
+#pragma unroll
+            for (int i = 0; i < H - 1; ++i) {
+                if (i % 16 == 0) asm volatile("" ::: "memory");
+                v[i] = fma(-Vs[b][r0 + i + 1], sc, v[i + 1]);
+            }
+            const bool live = R < n;
+            if (!lower) {
+                v[H - 1] = fma(-Vs[b][H], sc, nxt);
+                if (is_col && slot == owner) {
+                    v[0] = live ? Nst[bb][j] : 0.0;                        // entering column, row k + 1
+                    col = R;
+                }
+            } else if (is_col) {
+                if (slot == owner) {
+                    col = R;
+                    v[H - 2] = live ? cE_Rm1 : 0.0;                        // row R - 1
+                    v[H - 1] = live ? diag : 1.0;                          // row R
+                } else {
+                    const double4 cR = Cst[bb][j];
+                    v[H - 1] = (live && col < n) ? (col == R - 1 ? cR.y : (col == R - q ? cR.w : 0.0)) : 0.0;
+                }
+            } else {
+                v[H - 1] = rhs_c == 0 ? Rst[bb][j].x : Rst[bb][j].y;
+            }
+        }
+        cE_Rm1 = Cst[bb][j].x;
+        owner = (owner + 1 == P1) ? 0 : owner + 1;
+    }
+    __syncthreads();
+    {
+        // the last batch
+        const int bt = (n - 1) / kB, bb = bt & 1, kp = bt * kB, cnt = n - kp;
+        const double *src = &Ust[bb][0][0];
+        double *dstU = U + (int64_t)kp * P1;
+        for (int e = tid; e < cnt * P1; e += blockDim.x) dstU[e] = src[e];
+        if (tid < cnt) {
+            Y[kp + tid] = Yst[bb][tid].x;
+            Y[n + kp + tid] = Yst[bb][tid].y;
+        }
+    }
+    __threadfence_block();
+    __syncthreads();
+    if (tid < 64) back_substitute_blocked<P1>(a, U, Y, n, i0, j0);
+}
+
 
 __global__ void __launch_bounds__(256) subdomain_be_kernel(const SubArgs a) {
     extern __shared__ double lds[];
@@ -311,7 +584,28 @@ __global__ void __launch_bounds__(1024) quality_kernel(const double *xi, const d
 static size_t sub_ws_bytes(int px, int m) {
     const size_t q = (size_t)m - 1, n = q * q, P1 = q + 1;
     const size_t blocks = (size_t)px * px;
-    return align256(blocks * n * P1 * sizeof(double)) + align256(blocks * 2 * n * sizeof(double));
+    return align256(blocks * n * P1 * sizeof(double)) + align256(blocks * 2 * n * sizeof(double)) +
+           align256(blocks * 4 * n * sizeof(double)) + align256(blocks * 2 * n * sizeof(double));
+}
+
+// Launch of the register-window kernel for the window widths it is built
+// for; false if m is not one of them.
+static bool launch_lu(const SubArgs &a, int blocks, hipStream_t s, hipError_t *err) {
+    auto go = [&](auto kern, int P1) {
+        const int threads = ((2 * P1 + 4 + 63) / 64) * 64;
+        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(threads), 0, s, a);
+        *err = hipGetLastError();
+        return true;
+    };
+    switch (a.m) {
+    case 8: return go(subdomain_lu_kernel<8>, 8);
+    case 16: return go(subdomain_lu_kernel<16>, 16);
+    case 32: return go(subdomain_lu_kernel<32>, 32);
+    case 48: return go(subdomain_lu_kernel<48>, 48);
+    case 64: return go(subdomain_lu_kernel<64>, 64);
+    case 96: return go(subdomain_lu_kernel<96>, 96);
+    default: return false;
+    }
 }
 
 }  // namespace fk
@@ -373,8 +667,15 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
     a.xi_out = xi_out;
     a.eta_out = eta_out;
     const size_t q = (size_t)m - 1, n = q * q, P1 = q + 1;
-    a.ubuf = (double *)workspace;
-    a.ybuf = (double *)((char *)workspace + align256((size_t)px * px * n * P1 * sizeof(double)));
+    const size_t blocks = (size_t)px * px;
+    char *ws = (char *)workspace;
+    a.ubuf = (double *)ws;
+    ws += align256(blocks * n * P1 * sizeof(double));
+    a.ybuf = (double *)ws;
+    ws += align256(blocks * 2 * n * sizeof(double));
+    a.cbuf = (double *)ws;
+    ws += align256(blocks * 4 * n * sizeof(double));
+    a.rbuf = (double *)ws;
     a.N = N;
     a.m = m;
     a.px = px;
@@ -388,6 +689,11 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
     a.orbit_r = w->orbit_r;
     a.omega = w->omega;
     a.t_w = t_w;
+    if (launch_lu(a, px * px, stream, &e)) {
+        if (e != hipSuccess) return hip_fail(e, "sub-domain kernel launch");
+        return FK_OK;
+    }
+    // other sub-domain sizes: the window in LDS
     const size_t lds = (P1 * P1 + 4 * P1) * sizeof(double);
     if ((e = hipFuncSetAttribute((const void *)subdomain_be_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)lds)) != hipSuccess)
