@@ -21,6 +21,9 @@ The same line reports, as extra objects:
   paths), timed at its own N*; the Dynkin form at stride 50 beside it.
   Throughput is quoted for the solve alone and with the labels and training
   counted once.
+* "batched": 64 time levels t_k = 0.01 k of the moving bump with random
+  2x2..8x8 layouts on G = 128 (66047 nodes), 2^16 paths per node, autotuned
+  and captured in a HIP graph; one replay timed.
 * "mesh_run": the time-dependent run -- 8 x 8 sub-domains on a 768-cell
   grid, two counter-rotating bumps, 200 mesh steps of 5e-4 with 20
   Euler-Maruyama steps each, 2^14 paths per interface node (10689 nodes),
@@ -29,6 +32,7 @@ The same line reports, as extra objects:
   tests compare it with the oracle's global step).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-cv] [--no-mesh-run]
+                    [--no-batched]
 """
 from __future__ import annotations
 
@@ -184,6 +188,41 @@ def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=409
     }
 
 
+def measure_batched(fk, probe_paths=512):
+    """64 time levels of the moving bump with random 2x2..8x8 layouts on
+    G = 128 (66047 nodes), dt = 1e-5, 2^16 paths per node: autotuned plan,
+    captured in a HIP graph, one replay timed."""
+    import torch
+    dens = W.moving_bump()
+    lv = W.batched_levels(64, G=128)
+    levels = [(dens, t, 0.0, pts, k) for k, (t, px, py, pts) in enumerate(lv, start=1)]
+    n_paths, dt = 1 << 16, 1e-5
+    b = fk.FkBatch(levels, W.Data(), dt, n_paths, seed=0)
+    print(f"[bench] batched: {b.n_total} nodes, autotune at {probe_paths} paths", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan = b.autotune(probe_paths)
+    torch.cuda.synchronize()
+    t_tune = time.perf_counter() - t0
+    out = b.outputs()
+    stream = torch.cuda.Stream()
+    b.capture(out, stream)
+    print(f"[bench] batched: replay with plan {plan}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    b.replay(stream)
+    stream.synchronize()
+    wall = time.perf_counter() - t0
+    steps = int(out["total_steps"].item())
+    b.close()
+    return {"workload": "64 levels t_k = 0.01 k of the moving bump, random 2x2..8x8 layouts on G = 128, "
+                        "dt = 1e-5, 2^16 paths/node, one graph-captured persistent launch",
+            "levels": 64, "nodes": int(b.n_total), "paths_per_node": n_paths, "plan": plan,
+            "autotune_s": t_tune, "s": wall, "nodes_per_s": b.n_total / wall,
+            "path_steps": steps, "path_steps_per_s": steps / wall,
+            "fp32_frac": FLOP_PER_STEP * steps / wall / 1e12 / FP32_PEAK_TFLOPS}
+
+
 def measure_mesh_run():
     """The time-dependent mesh run, with the network and plain."""
     import torch
@@ -223,6 +262,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-cv", action="store_true", help="skip the control-variate measurement")
     ap.add_argument("--no-mesh-run", action="store_true", help="skip the time-dependent mesh run")
+    ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-level launch")
     ap.add_argument("--paths", type=int, default=0, help="fix paths/node and skip the N* pilot (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scales HBM counters) and exit")
@@ -337,6 +377,8 @@ def main():
         out["cv"] = measure_cv(fk, wl, pts, fd, args.steps, args.warmup)
     if not args.no_mesh_run:
         out["mesh_run"] = measure_mesh_run()
+    if not args.no_batched:
+        out["batched"] = measure_batched(fk)
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, n_star)
