@@ -24,6 +24,9 @@ The same line reports, as extra objects:
 * "batched": 64 time levels t_k = 0.01 k of the moving bump with random
   2x2..8x8 layouts on G = 128 (66047 nodes), 2^16 paths per node, autotuned
   and captured in a HIP graph; one replay timed.
+* "paper_run": the paper's own run (Sect. 5) -- the moving ring w = 1/rho
+  on 41 x 41 nodes in 2 x 2 sub-domains, mesh step 1e-3 in 20 sub-steps,
+  10^4 paths on all interface nodes, equidistributed edges, t <= 0.75.
 * "mesh_run": the time-dependent run -- 8 x 8 sub-domains on a 768-cell
   grid, two counter-rotating bumps, 200 mesh steps of 5e-4 with 20
   Euler-Maruyama steps each, 2^14 paths per interface node (10689 nodes),
@@ -32,7 +35,7 @@ The same line reports, as extra objects:
   tests compare it with the oracle's global step).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-cv] [--no-mesh-run]
-                    [--no-batched]
+                    [--no-batched] [--no-paper-run]
 """
 from __future__ import annotations
 
@@ -223,6 +226,32 @@ def measure_batched(fk, probe_paths=512):
             "fp32_frac": FLOP_PER_STEP * steps / wall / 1e12 / FP32_PEAK_TFLOPS}
 
 
+def measure_paper_run():
+    """The paper's run (Sect. 5): the moving ring w = 1/rho on 41 x 41 nodes
+    in 2 x 2 sub-domains, mesh step 1e-3 in 20 sub-steps, 10^4 paths per
+    interface node (all 77), equidistributed edges, up to t = 0.75."""
+    import torch
+    from paper_1402_0266_amd.mesh_run import PAPER_RING_RUN, MeshRun, MeshRunConfig, paper_ring_density
+    cfg = MeshRunConfig(**PAPER_RING_RUN)
+    print(f"[bench] paper run: {cfg.n_steps} steps", file=sys.stderr, flush=True)
+    run = MeshRun(cfg, density_fn=paper_ring_density)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    run.run()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    q = run.qualities()
+    _, se = run.interface_values()
+    run.close()
+    snaps = {f"t={0.25 * k:.2f}": {"min_jac": float(q[250 * k - 1, 0]), "max_skew": float(q[250 * k - 1, 1])}
+             for k in (1, 2, 3)}
+    return {"workload": "paper's run: ring w = 1/rho (alpha 10, beta -50), 41x41 nodes, 2x2 sub-domains, "
+                        "dt_mesh 1e-3 / 20 sub-steps, 1e4 paths on all 77 interface nodes, t <= 0.75",
+            "steps": cfg.n_steps, "s_total": wall, "ms_per_step": wall / cfg.n_steps * 1e3,
+            "min_jac_min": float(q[:, 0].min()), "max_skew_max": float(q[:, 1].max()),
+            "se_median": float(np.median(se)), "quality": snaps}
+
+
 def measure_mesh_run():
     """The time-dependent mesh run, with the network and plain."""
     import torch
@@ -263,6 +292,7 @@ def main():
     ap.add_argument("--no-cv", action="store_true", help="skip the control-variate measurement")
     ap.add_argument("--no-mesh-run", action="store_true", help="skip the time-dependent mesh run")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-level launch")
+    ap.add_argument("--no-paper-run", action="store_true", help="skip the paper's ring run")
     ap.add_argument("--paths", type=int, default=0, help="fix paths/node and skip the N* pilot (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scales HBM counters) and exit")
@@ -379,6 +409,8 @@ def main():
         out["mesh_run"] = measure_mesh_run()
     if not args.no_batched:
         out["batched"] = measure_batched(fk)
+    if not args.no_paper_run:
+        out["paper_run"] = measure_paper_run()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, n_star)

@@ -52,6 +52,8 @@ extern "C" {
 #define FK_DENSITY_BUMP 1         /* w = 1 + amp exp(-|X - (cx,cy)|^2 / width2) */
 #define FK_DENSITY_MOVING_BUMP 2  /* centre (cx + orbit_r cos(omega tau), cy + orbit_r sin(omega tau)) */
 #define FK_DENSITY_TWO_BUMPS 3    /* w = 1 + amp (e1 + e2); e2 centred at (cx - orbit_r cos, cy + orbit_r sin) */
+#define FK_DENSITY_RING 4         /* w = 1/rho, rho = 1 + amp exp(width2 |r^2 - 1/100|), r the distance to
+                                     the moving centre: the paper's ring (Sect. 5; amp = alpha, width2 = beta) */
 #define FK_DENSITY_RIDGE 5        /* w = 1 + amp exp(-(x - cx)^2 / width2) */
 
 /* Time argument of w along a path. */
@@ -64,6 +66,11 @@ extern "C" {
                                data exp(-2 pi^2 (t - s)) phi(X) extended off the square */
 #define FK_DATA_ZERO 2      /* boundary data 0 */
 #define FK_DATA_GRID 3      /* initial data only: bilinear in (grid_n+1)^2 nodal FP64 grids */
+#define FK_DATA_EQUIDISTRIBUTED 4  /* subdomain_solve's outer boundary only: xi = 0 / 1 on the left / right
+                                      edges, eta = 0 / 1 on the bottom / top edges, and on the other edges
+                                      the 1-D equidistribution of w along the edge, xi(x) = int_0^x w /
+                                      int_0^1 w (Sect. 3: the 1-D version of eq. (2)); the interface solve
+                                      reads it from the mesh grid with FK_SCORE_EXTEND */
 
 #define FK_SCORE_UNCLAMPED 0  /* boundary data at the first point outside the square */
 #define FK_SCORE_PROJECT 1    /* ... after clamping that point onto the square */
@@ -206,8 +213,8 @@ void fk_batch_destroy(fk_batch_t b);
  *   iface_xi/eta       device FP64, interface nodes in canonical order
  *                      (vertical lines x = a/px with y = j/N ascending, then
  *                      horizontal lines without their crossings)
- *   bdry_kind          FK_DATA_IDENTITY (xi = x, eta = y) or FK_DATA_ZERO on
- *                      the outer boundary
+ *   bdry_kind          FK_DATA_IDENTITY (xi = x, eta = y), FK_DATA_ZERO or
+ *                      FK_DATA_EQUIDISTRIBUTED (at t_w) on the outer boundary
  *   xi_out, eta_out    device [(N+1)^2] FP64: the new mesh (boundary, interface
  *                      and sub-domain interiors); must not alias xi_n / eta_n
  *   workspace          device, subdomain_workspace_bytes(px, m) bytes, 256-B aligned

@@ -13,8 +13,8 @@ backward-Euler step per mesh step,
 
 with b = -grad w / w (eq. (6)) at the node, w held at one time t_w over the
 step (Sect. 4 freezes the density over a mesh step), on the uniform nodal
-grid x = i/N, y = j/N.  Outer boundary data: the identity (xi = x, eta = y)
-or zero.  ``global_be_step`` solves the whole grid; ``subdomain_be_step``
+grid x = i/N, y = j/N.  Outer boundary data: the identity (xi = x, eta = y),
+zero, or the paper's equidistributed edges (Sect. 3).  ``global_be_step`` solves the whole grid; ``subdomain_be_step``
 solves each of px x px sub-domains (m cells a side, N = px m) with the
 interface nodes as Dirichlet data.  Both use scipy.sparse LU (splu).
 
@@ -37,14 +37,40 @@ def _drift_grid(dens, t_w, N):
     return b[:, 0].reshape(N + 1, N + 1), b[:, 1].reshape(N + 1, N + 1)
 
 
-def boundary_grid(N, bdry: str = "identity"):
-    """Grids holding the outer boundary data (interior entries unspecified = 0)."""
+def _edge_equidistribution(dens, t_w, s, edge, horizontal):
+    """int_0^s w / int_0^1 w along the edge y = edge (horizontal) or x = edge."""
+    import scipy.integrate as si
+
+    def w(u):
+        p = np.array([[u, edge]] if horizontal else [[edge, u]], dtype=np.float64)
+        return float(_oracle.density(dens, t_w, p)[0][0])
+
+    kw = dict(epsabs=1e-14, epsrel=1e-13, limit=400)
+    return si.quad(w, 0.0, s, **kw)[0] / si.quad(w, 0.0, 1.0, **kw)[0]
+
+
+def boundary_grid(N, bdry: str = "identity", dens=None, t_w=0.0):
+    """Grids holding the outer boundary data (interior entries unspecified = 0).
+
+    "equidistributed" (Sect. 3): xi = 0 / 1 on the left / right edges, eta = 0
+    / 1 on the bottom / top edges, and on the other edges the 1-D version of
+    eq. (2), whose solution is xi(x) = int_0^x w / int_0^1 w, for w frozen at
+    t_w (adaptive quadrature)."""
     x = np.arange(N + 1) / N
     X, Y = np.meshgrid(x, x)
     gx, gy = np.zeros_like(X), np.zeros_like(X)
     if bdry == "identity":
         for g, v in ((gx, X), (gy, Y)):
             g[0, :], g[-1, :], g[:, 0], g[:, -1] = v[0, :], v[-1, :], v[:, 0], v[:, -1]
+    elif bdry == "equidistributed":
+        gx[:, -1] = 1.0
+        gy[-1, :] = 1.0
+        for i in range(1, N):
+            gx[0, i] = _edge_equidistribution(dens, t_w, x[i], 0.0, True)
+            gx[-1, i] = _edge_equidistribution(dens, t_w, x[i], 1.0, True)
+        for j in range(1, N):
+            gy[j, 0] = _edge_equidistribution(dens, t_w, x[j], 0.0, False)
+            gy[j, -1] = _edge_equidistribution(dens, t_w, x[j], 1.0, False)
     return gx, gy
 
 
@@ -81,7 +107,7 @@ def global_be_step(dens, t_w, D, N, xi_n, eta_n, bdry="identity"):
     """One backward-Euler step on the whole grid."""
     h = 1.0 / N
     bx, by = _drift_grid(dens, t_w, N)
-    gx, gy = boundary_grid(N, bdry)
+    gx, gy = boundary_grid(N, bdry, dens, t_w)
     sx, sy = _be_solve_region(bx, by, D, h, 0, N, 0, N, [xi_n, eta_n], [gx, gy])
     xi, eta = gx.copy(), gy.copy()
     xi[1:N, 1:N], eta[1:N, 1:N] = sx, sy
@@ -110,7 +136,7 @@ def subdomain_be_step(dens, t_w, D, px, m, xi_n, eta_n, iface_xi, iface_eta, bdr
     N = px * m
     h = 1.0 / N
     bx, by = _drift_grid(dens, t_w, N)
-    xi, eta = boundary_grid(N, bdry)
+    xi, eta = boundary_grid(N, bdry, dens, t_w)
     ij = interface_index(px, m)
     xi[ij[:, 1], ij[:, 0]] = iface_xi
     eta[ij[:, 1], ij[:, 0]] = iface_eta

@@ -40,19 +40,21 @@ int64_t step_count(double t, double dt) {
 
 static bool kind_supported(int32_t kind) {
     return kind == FK_DENSITY_CONST || kind == FK_DENSITY_BUMP || kind == FK_DENSITY_MOVING_BUMP ||
-           kind == FK_DENSITY_TWO_BUMPS || kind == FK_DENSITY_RIDGE;
+           kind == FK_DENSITY_TWO_BUMPS || kind == FK_DENSITY_RING || kind == FK_DENSITY_RIDGE;
 }
 
 int validate_density(const fk_density *w) {
     if (!w) return fail(FK_E_INVAL, "density is NULL");
-    if (w->kind == 4) return fail(FK_E_UNSUPPORTED, "density kind 4 (ring) is not implemented on the GPU");
     if (!kind_supported(w->kind)) return fail(FK_E_INVAL, "unknown density kind %d", w->kind);
     if (w->time_mode != FK_TIME_BACKWARD && w->time_mode != FK_TIME_FROZEN)
         return fail(FK_E_INVAL, "unknown time mode %d", w->time_mode);
     const double v[] = {w->amp, w->width2, w->cx, w->cy, w->orbit_r, w->omega, w->t_freeze};
     for (double x : v)
         if (!std::isfinite(x)) return fail(FK_E_INVAL, "density parameter is not finite");
-    if (w->kind != FK_DENSITY_CONST) {
+    if (w->kind == FK_DENSITY_RING) {
+        if (!(w->amp >= 0.0)) return fail(FK_E_INVAL, "ring amplitude (alpha) must be >= 0");
+        if (!(w->width2 <= 0.0)) return fail(FK_E_INVAL, "ring exponent (beta) must be <= 0");
+    } else if (w->kind != FK_DENSITY_CONST) {
         if (!(w->width2 > 0.0)) return fail(FK_E_INVAL, "density width2 must be > 0");
         if (!(w->amp > -1.0)) return fail(FK_E_INVAL, "density amplitude must be > -1 (w > 0)");
     }
@@ -133,8 +135,13 @@ LevelDev make_level(const fk_density *w, double t_init, double t, double dt, uin
     L.K = (int32_t)K;
     L.ctr3 = (level_id << 4) | (stream & 15u);
     L.amp = (float)w->amp;
-    L.nscale = w->kind == FK_DENSITY_CONST ? 0.f : (float)(-log2e / w->width2);
-    L.a2s = w->kind == FK_DENSITY_CONST ? 0.f : (float)(2.0 * w->amp / w->width2);
+    if (w->kind == FK_DENSITY_RING) {
+        L.nscale = (float)(w->width2 * log2e);
+        L.a2s = (float)(2.0 * w->amp * w->width2);
+    } else {
+        L.nscale = w->kind == FK_DENSITY_CONST ? 0.f : (float)(-log2e / w->width2);
+        L.a2s = w->kind == FK_DENSITY_CONST ? 0.f : (float)(2.0 * w->amp / w->width2);
+    }
     L.cx = (float)w->cx;
     L.cy = (float)w->cy;
     L.orbit_r = (float)w->orbit_r;

@@ -405,7 +405,7 @@ struct CvArgs {
 template <int KIND, int TMODE, bool UNIFORM>
 __device__ __forceinline__ void drift_at(const Lane &L, float &bx, float &by) {
     float ox = L.ox, oy = L.oy;
-    if constexpr ((KIND == KIND_MOVING || KIND == KIND_TWO) && TMODE == TIME_BACKWARD) {
+    if constexpr (moving_kind(KIND) && TMODE == TIME_BACKWARD) {
         const float rev = fmaf(-(float)L.k, L.drev, L.rev0);
         ox = L.dens.orbit_r * hw_cos_rev(rev);
         oy = L.dens.orbit_r * hw_sin_rev(rev);
@@ -417,7 +417,7 @@ __device__ __forceinline__ void drift_at(const Lane &L, float &bx, float &by) {
 template <int KIND, int TMODE>
 __device__ __forceinline__ void drift_at_tau(const Lane &L, float tau, float &bx, float &by) {
     float ox = L.ox, oy = L.oy;
-    if constexpr ((KIND == KIND_MOVING || KIND == KIND_TWO) && TMODE == TIME_BACKWARD) {
+    if constexpr (moving_kind(KIND) && TMODE == TIME_BACKWARD) {
         const float rev = tau * L.dens.omega_rev;
         ox = L.dens.orbit_r * hw_cos_rev(rev);
         oy = L.dens.orbit_r * hw_sin_rev(rev);
@@ -427,7 +427,7 @@ __device__ __forceinline__ void drift_at_tau(const Lane &L, float tau, float &bx
 
 template <int KIND, int TMODE, bool UNIFORM>
 __global__ void __launch_bounds__(256, 2) fk_cv_path_kernel(const PathArgs a, const CvArgs c) {
-    constexpr bool kMovingBackward = (KIND == KIND_MOVING || KIND == KIND_TWO) && TMODE == TIME_BACKWARD;
+    constexpr bool kMovingBackward = moving_kind(KIND) && TMODE == TIME_BACKWARD;
     __shared__ NetLds N;
     load_net(N, c.bf);
     __syncthreads();
@@ -575,7 +575,7 @@ struct MgArgs {
 
 template <int KIND, int TMODE, bool UNIFORM>
 __global__ void __launch_bounds__(256, 2) fk_mg_path_kernel(const PathArgs a, const MgArgs c) {
-    constexpr bool kMovingBackward = (KIND == KIND_MOVING || KIND == KIND_TWO) && TMODE == TIME_BACKWARD;
+    constexpr bool kMovingBackward = moving_kind(KIND) && TMODE == TIME_BACKWARD;
     __shared__ NetLds N;
     load_net(N, c.bf);
     __syncthreads();
@@ -1049,6 +1049,9 @@ auto cv_dispatch(int kind, int time_mode, bool uniform, Args &&...args) {
     case KIND_MOVING:
         if (frozen) FK_CV_CASE(KIND_MOVING, TIME_FROZEN);
         FK_CV_CASE(KIND_MOVING, TIME_BACKWARD);
+    case KIND_RING:
+        if (frozen) FK_CV_CASE(KIND_RING, TIME_FROZEN);
+        FK_CV_CASE(KIND_RING, TIME_BACKWARD);
     default:
         if (frozen) FK_CV_CASE(KIND_TWO, TIME_FROZEN);
         FK_CV_CASE(KIND_TWO, TIME_BACKWARD);

@@ -70,7 +70,10 @@ __device__ __forceinline__ void brownian_increment(uint32_t ra, uint32_t rb, flo
 // Densities and the Winslow drift b = -grad w / w (eq. (6)).  For a Gaussian
 // bump w = 1 + A e, e = exp(-|X - c|^2 / s2):  b = (2 A / s2) e / w * (X - c).
 // ---------------------------------------------------------------------------
-enum : int { KIND_CONST = 0, KIND_BUMP = 1, KIND_MOVING = 2, KIND_TWO = 3, KIND_RIDGE = 5 };
+enum : int { KIND_CONST = 0, KIND_BUMP = 1, KIND_MOVING = 2, KIND_TWO = 3, KIND_RING = 4, KIND_RIDGE = 5 };
+
+// Kinds whose centre moves on the orbit (R cos(omega tau), R sin(omega tau)).
+constexpr bool moving_kind(int k) { return k == KIND_MOVING || k == KIND_TWO || k == KIND_RING; }
 enum : int { TIME_BACKWARD = 0, TIME_FROZEN = 1 };
 
 struct DensityRegs {
@@ -111,6 +114,18 @@ __device__ __forceinline__ void drift(const DensityRegs &d, float ox, float oy, 
         const float f = d.a2s * hw_rcp(fmaf(d.amp, e1 + e2, 1.f));
         bx = f * fmaf(e1, d1x, e2 * d2x);
         by = f * (e1 + e2) * dy;
+    } else if constexpr (KIND == KIND_RING) {
+        // w = 1/rho, rho = 1 + A e, e = exp(beta |q|), q = |X - c|^2 - 1/100:
+        // b = -grad w / w = grad rho / rho = 2 A beta sgn(q) e (X - c) / rho
+        // (nscale = beta log2(e), a2s = 2 A beta).
+        const float dx = x - (d.cx + ox);
+        const float dy = y - (d.cy + oy);
+        const float q = fmaf(dx, dx, fmaf(dy, dy, -0.01f));
+        const float e = hw_exp2(fabsf(q) * d.nscale);
+        const float sg = q > 0.f ? 1.f : (q < 0.f ? -1.f : 0.f);
+        const float f = sg * e * d.a2s * hw_rcp(fmaf(d.amp, e, 1.f));
+        bx = f * dx;
+        by = f * dy;
     } else {  // KIND_RIDGE: depends on x only
         const float dx = x - d.cx;
         const float e = hw_exp2(dx * dx * d.nscale);

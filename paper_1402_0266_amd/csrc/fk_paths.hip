@@ -51,7 +51,7 @@ hipError_t launch_zero_u32(uint32_t *p, int n_words, hipStream_t s) {
 
 template <int KIND, int TMODE, bool UNIFORM>
 __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
-    constexpr bool kMovingBackward = (KIND == KIND_MOVING || KIND == KIND_TWO) && TMODE == TIME_BACKWARD;
+    constexpr bool kMovingBackward = moving_kind(KIND) && TMODE == TIME_BACKWARD;
     const uint32_t lane = threadIdx.x & 63u;
     // Wavefront-uniform queue cursor: current node slot and path range.
     uint32_t q_slot = 0, q_next = 0, q_end = 0;
@@ -169,6 +169,9 @@ auto dispatch(int kind, int time_mode, bool uniform, Args &&...args) {
     case KIND_MOVING:
         if (frozen) FK_CASE(KIND_MOVING, TIME_FROZEN);
         FK_CASE(KIND_MOVING, TIME_BACKWARD);
+    case KIND_RING:
+        if (frozen) FK_CASE(KIND_RING, TIME_FROZEN);
+        FK_CASE(KIND_RING, TIME_BACKWARD);
     default:
         if (frozen) FK_CASE(KIND_TWO, TIME_FROZEN);
         FK_CASE(KIND_TWO, TIME_BACKWARD);
@@ -190,13 +193,15 @@ struct OccF {
 
 hipError_t launch_paths(int kind, int time_mode, bool uniform, const PathArgs &a, int grid, int block,
                         hipStream_t s) {
-    if (kind != KIND_CONST && kind != KIND_BUMP && kind != KIND_RIDGE && kind != KIND_MOVING && kind != KIND_TWO)
+    if (kind != KIND_CONST && kind != KIND_BUMP && kind != KIND_RIDGE && kind != KIND_MOVING && kind != KIND_TWO &&
+        kind != KIND_RING)
         return hipErrorInvalidValue;
     return dispatch<LaunchF>(kind, time_mode, uniform, a, grid, block, s);
 }
 
 int path_kernel_max_blocks_per_cu(int kind, int time_mode, bool uniform, int block) {
-    if (kind != KIND_CONST && kind != KIND_BUMP && kind != KIND_RIDGE && kind != KIND_MOVING && kind != KIND_TWO)
+    if (kind != KIND_CONST && kind != KIND_BUMP && kind != KIND_RIDGE && kind != KIND_MOVING && kind != KIND_TWO &&
+        kind != KIND_RING)
         return 0;
     return dispatch<OccF>(kind, time_mode, uniform, block);
 }

@@ -117,7 +117,7 @@ __device__ __forceinline__ void lane_start(Lane &L, const NodeDev &nd, const Lev
     L.dens.omega_rev = lv.omega_rev;
     L.ox = 0.f;
     L.oy = 0.f;
-    if constexpr ((KIND == KIND_MOVING || KIND == KIND_TWO) && TMODE == TIME_FROZEN) {
+    if constexpr (moving_kind(KIND) && TMODE == TIME_FROZEN) {
         orbit(L.dens, lv.t_freeze, L.ox, L.oy);
     }
 }

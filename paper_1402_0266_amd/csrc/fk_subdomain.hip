@@ -53,9 +53,20 @@ __device__ void drift_f64(const SubArgs &a, double x, double y, double &bx, doub
         return;
     }
     double ccx = a.cx, ccy = a.cy, ox = 0.0, oy = 0.0;
-    if (a.kind == FK_DENSITY_MOVING_BUMP || a.kind == FK_DENSITY_TWO_BUMPS) {
+    if (a.kind == FK_DENSITY_MOVING_BUMP || a.kind == FK_DENSITY_TWO_BUMPS || a.kind == FK_DENSITY_RING) {
         ox = a.orbit_r * cos(a.omega * a.t_w);
         oy = a.orbit_r * sin(a.omega * a.t_w);
+    }
+    if (a.kind == FK_DENSITY_RING) {
+        // w = 1/rho, rho = 1 + A exp(beta |q|): b = grad rho / rho (beta = width2)
+        const double dx = x - (ccx + ox), dy = y - (ccy + oy);
+        const double q = dx * dx + dy * dy - 0.01;
+        const double e = exp(s2 * fabs(q));
+        const double sg = q > 0.0 ? 1.0 : (q < 0.0 ? -1.0 : 0.0);
+        const double f = 2.0 * A * s2 * sg * e / (1.0 + A * e);
+        bx = f * dx;
+        by = f * dy;
+        return;
     }
     if (a.kind == FK_DENSITY_TWO_BUMPS) {
         const double dy = y - (ccy + oy);
@@ -75,6 +86,60 @@ __device__ void drift_f64(const SubArgs &a, double x, double y, double &bx, doub
 }
 
 constexpr int kMaxP1 = 128;  // window side limit: q <= 127 interior nodes per side
+
+// The density w in FP64 at (x, y), frozen at t_w.
+__device__ double density_f64(const SubArgs &a, double x, double y) {
+    const double A = a.amp, s2 = a.width2;
+    if (a.kind == FK_DENSITY_CONST) return 1.0;
+    double ox = 0.0, oy = 0.0;
+    if (a.kind == FK_DENSITY_MOVING_BUMP || a.kind == FK_DENSITY_TWO_BUMPS || a.kind == FK_DENSITY_RING) {
+        ox = a.orbit_r * cos(a.omega * a.t_w);
+        oy = a.orbit_r * sin(a.omega * a.t_w);
+    }
+    if (a.kind == FK_DENSITY_RING) {
+        const double dx = x - (a.cx + ox), dy = y - (a.cy + oy);
+        return 1.0 / (1.0 + A * exp(s2 * fabs(dx * dx + dy * dy - 0.01)));
+    }
+    if (a.kind == FK_DENSITY_TWO_BUMPS) {
+        const double dy = y - (a.cy + oy), d1 = x - (a.cx + ox), d2 = x - (a.cx - ox);
+        return 1.0 + A * (exp(-(d1 * d1 + dy * dy) / s2) + exp(-(d2 * d2 + dy * dy) / s2));
+    }
+    const double dx = x - (a.cx + ox), dy = (a.kind == FK_DENSITY_RIDGE) ? 0.0 : y - (a.cy + oy);
+    return 1.0 + A * exp(-(dx * dx + dy * dy) / s2);
+}
+
+// Integrals of w over the grid cells along the four edges (composite
+// Simpson, 256 panels per cell): edge 0 y = 0, 1 y = 1 (over x), 2 x = 0,
+// 3 x = 1 (over y).  cells[e * N + c] is the integral over cell c.
+__global__ void edge_cells_kernel(const SubArgs a, double *cells) {
+    constexpr int M = 256;
+    const int N = a.N;
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * N) return;
+    const int e = t / N, c = t % N;
+    const bool horizontal = e < 2;
+    const double fixed = (e == 1 || e == 3) ? 1.0 : 0.0;
+    const double u0 = (double)c / N, hq = 1.0 / ((double)N * M);
+    double acc = 0.0;
+    for (int i = 0; i <= M; ++i) {
+        const double u = u0 + i * hq;
+        const double w = horizontal ? density_f64(a, u, fixed) : density_f64(a, fixed, u);
+        acc += w * ((i == 0 || i == M) ? 1.0 : ((i & 1) ? 4.0 : 2.0));
+    }
+    cells[t] = acc * hq / 3.0;
+}
+
+// int_0^{i/N} w / int_0^1 w along edge e, from the cell integrals (summed in
+// a fixed order).
+__device__ double edge_fraction(const double *cells, int N, int e, int i) {
+    double part = 0.0, total = 0.0;
+    for (int c = 0; c < N; ++c) {
+        const double v = cells[e * N + c];
+        if (c < i) part += v;
+        total += v;
+    }
+    return part / total;
+}
 
 constexpr int kB = 32;   // steps per staging batch of the register-window kernel
 
@@ -179,7 +244,6 @@ __global__ void __launch_bounds__(256) subdomain_lu_kernel(const SubArgs a) {
     const int si = blockIdx.x % a.px, sj = blockIdx.x / a.px;
     const int i0 = si * a.m, j0 = sj * a.m;
     const int N1 = a.N + 1;
-    const double h = 1.0 / a.N;
     double *U = a.ubuf + (int64_t)blockIdx.x * n * P1;
     double *Y = a.ybuf + (int64_t)blockIdx.x * 2 * n;
     double4 *cf = reinterpret_cast<double4 *>(a.cbuf + (int64_t)blockIdx.x * 4 * n);
@@ -191,7 +255,7 @@ __global__ void __launch_bounds__(256) subdomain_lu_kernel(const SubArgs a) {
         const int ii = r % q, jj = r / q;
         const int gi = i0 + 1 + ii, gj = j0 + 1 + jj;
         double bx, by;
-        drift_f64(a, gi * h, gj * h, bx, by);
+        drift_f64(a, (double)gi / a.N, (double)gj / a.N, bx, by);  // i/N exactly, as the grid is defined
         const double cxr = a.half_d_over_h * bx, cyr = a.half_d_over_h * by;
         const double cE = -a.c - cxr, cW = -a.c + cxr, cN = -a.c - cyr, cS = -a.c + cyr;
         const int64_t g = (int64_t)gj * N1 + gi;
@@ -352,7 +416,6 @@ __global__ void __launch_bounds__(256) subdomain_be_kernel(const SubArgs a) {
     const int si = blockIdx.x % a.px, sj = blockIdx.x / a.px;
     const int i0 = si * a.m, j0 = sj * a.m;
     const int N1 = a.N + 1;
-    const double h = 1.0 / a.N;
     double *W = lds;                     // P1 x P1 window
     double *rx = W + P1 * P1;            // rhs ring, xi
     double *ry = rx + P1;                // rhs ring, eta
@@ -369,7 +432,7 @@ __global__ void __launch_bounds__(256) subdomain_be_kernel(const SubArgs a) {
         const int ii = r % q, jj = r / q;
         const int gi = i0 + 1 + ii, gj = j0 + 1 + jj;
         double bx, by;
-        drift_f64(a, gi * h, gj * h, bx, by);
+        drift_f64(a, (double)gi / a.N, (double)gj / a.N, bx, by);  // i/N exactly, as the grid is defined
         const double cxr = a.half_d_over_h * bx, cyr = a.half_d_over_h * by;
         const int s = r % P1;
         kx[s] = cxr;
@@ -501,8 +564,9 @@ __global__ void __launch_bounds__(256) subdomain_be_kernel(const SubArgs a) {
 }
 
 // Dirichlet data of the output grids: outer boundary and interface nodes.
-__global__ void dirichlet_kernel(const double *iface_xi, const double *iface_eta, int64_t n_iface, int N, int m,
-                                 int px, int bdry_kind, double *xi_out, double *eta_out) {
+__global__ void dirichlet_kernel(const SubArgs a, const double *iface_xi, const double *iface_eta, int64_t n_iface,
+                                 int bdry_kind, const double *edge_cells, double *xi_out, double *eta_out) {
+    const int N = a.N, m = a.m, px = a.px;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int N1 = N + 1;
     const int64_t n_bd = 4 * (int64_t)N;
@@ -515,9 +579,22 @@ __global__ void dirichlet_kernel(const double *iface_xi, const double *iface_eta
         else if (side == 2) { i = N - o; j = N; }
         else { i = 0; j = N - o; }
         const int64_t g = (int64_t)j * N1 + i;
-        const bool ident = (bdry_kind == FK_DATA_IDENTITY);
-        xi_out[g] = ident ? (double)i / N : 0.0;
-        eta_out[g] = ident ? (double)j / N : 0.0;
+        double xv = 0.0, ev = 0.0;
+        if (bdry_kind == FK_DATA_IDENTITY) {
+            xv = (double)i / N;
+            ev = (double)j / N;
+        } else if (bdry_kind == FK_DATA_EQUIDISTRIBUTED) {
+            // xi = 0 / 1 on the left / right edges, eta = 0 / 1 on the bottom /
+            // top edges; on the others the 1-D equidistribution of w
+            if (i == 0) xv = 0.0;
+            else if (i == N) xv = 1.0;
+            else xv = edge_fraction(edge_cells, N, j == 0 ? 0 : 1, i);
+            if (j == 0) ev = 0.0;
+            else if (j == N) ev = 1.0;
+            else ev = edge_fraction(edge_cells, N, i == 0 ? 2 : 3, j);
+        }
+        xi_out[g] = xv;
+        eta_out[g] = ev;
         return;
     }
     const int64_t f = t - n_bd;
@@ -583,9 +660,10 @@ __global__ void __launch_bounds__(1024) quality_kernel(const double *xi, const d
 
 static size_t sub_ws_bytes(int px, int m) {
     const size_t q = (size_t)m - 1, n = q * q, P1 = q + 1;
-    const size_t blocks = (size_t)px * px;
+    const size_t blocks = (size_t)px * px, N = (size_t)px * m;
     return align256(blocks * n * P1 * sizeof(double)) + align256(blocks * 2 * n * sizeof(double)) +
-           align256(blocks * 4 * n * sizeof(double)) + align256(blocks * 2 * n * sizeof(double));
+           align256(blocks * 4 * n * sizeof(double)) + align256(blocks * 2 * n * sizeof(double)) +
+           align256(4 * N * sizeof(double));
 }
 
 // Launch of the register-window kernel for the window widths it is built
@@ -629,8 +707,8 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
     if (m - 1 >= kMaxP1) return fail(FK_E_UNSUPPORTED, "sub-domain side m must be <= %d", kMaxP1);
     if (!std::isfinite(t_w) || !std::isfinite(dt_mesh) || !(dt_mesh > 0.0))
         return fail(FK_E_INVAL, "t_w must be finite and dt_mesh > 0");
-    if (bdry_kind != FK_DATA_IDENTITY && bdry_kind != FK_DATA_ZERO)
-        return fail(FK_E_INVAL, "outer boundary data must be FK_DATA_IDENTITY or FK_DATA_ZERO");
+    if (bdry_kind != FK_DATA_IDENTITY && bdry_kind != FK_DATA_ZERO && bdry_kind != FK_DATA_EQUIDISTRIBUTED)
+        return fail(FK_E_INVAL, "outer boundary data must be FK_DATA_IDENTITY, _ZERO or _EQUIDISTRIBUTED");
     const int N = px * m;
     const int64_t n_iface = 2 * (int64_t)(px - 1) * (N - 1) - (int64_t)(px - 1) * (px - 1);
     if (!xi_n || !eta_n || !xi_out || !eta_out || (n_iface > 0 && (!iface_xi || !iface_eta)))
@@ -641,8 +719,18 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
     const double h = 1.0 / N;
     // Diagonal dominance (LU without pivoting) needs |b| h / 2 < 1.  For one
     // bump |b| = (2A/s2) r e / (1 + A e), e = exp(-r^2/s2), maximised over r
-    // on a fine sample; two bumps are bounded by twice that.
-    if (w->kind != FK_DENSITY_CONST) {
+    // on a fine sample; two bumps are bounded by twice that.  For the ring
+    // |b| = 2 A |beta| r e / (1 + A e), e = exp(beta |r^2 - 1/100|), over r
+    // up to the square's diagonal.
+    if (w->kind == FK_DENSITY_RING) {
+        double bmax = 0.0;
+        const double A = w->amp, be = w->width2;
+        for (int i = 1; i <= 20000; ++i) {
+            const double r = 1.5 * i / 20000.0, e = std::exp(be * std::fabs(r * r - 0.01));
+            bmax = std::max(bmax, 2.0 * A * std::fabs(be) * r * e / (1.0 + A * e));
+        }
+        if (bmax * h / 2.0 >= 1.0) return fail(FK_E_UNSUPPORTED, "grid too coarse for the drift (|b| h / 2 >= 1)");
+    } else if (w->kind != FK_DENSITY_CONST) {
         double bmax = 0.0;
         const double A = std::fabs(w->amp), s2 = w->width2, rs = 4.0 * std::sqrt(s2);
         for (int i = 1; i <= 4000; ++i) {
@@ -655,11 +743,6 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
     int dev = 0;
     hipError_t e = hipGetDevice(&dev);
     if (e != hipSuccess) return fail(FK_E_NODEVICE, "no HIP device: %s", hipGetErrorString(e));
-
-    const int64_t nthr = 4 * (int64_t)N + n_iface;
-    hipLaunchKernelGGL(dirichlet_kernel, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, stream, iface_xi,
-                       iface_eta, n_iface, N, m, px, (int)bdry_kind, xi_out, eta_out);
-    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "dirichlet kernel launch");
 
     SubArgs a{};
     a.xi_n = xi_n;
@@ -676,6 +759,8 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
     a.cbuf = (double *)ws;
     ws += align256(blocks * 4 * n * sizeof(double));
     a.rbuf = (double *)ws;
+    ws += align256(blocks * 2 * n * sizeof(double));
+    double *edge_cells = (double *)ws;
     a.N = N;
     a.m = m;
     a.px = px;
@@ -689,6 +774,15 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
     a.orbit_r = w->orbit_r;
     a.omega = w->omega;
     a.t_w = t_w;
+    if (bdry_kind == FK_DATA_EQUIDISTRIBUTED) {
+        hipLaunchKernelGGL(edge_cells_kernel, dim3((unsigned)((4 * N + 255) / 256)), dim3(256), 0, stream, a,
+                           edge_cells);
+        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "edge integral kernel launch");
+    }
+    const int64_t nthr = 4 * (int64_t)N + n_iface;
+    hipLaunchKernelGGL(dirichlet_kernel, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, stream, a, iface_xi,
+                       iface_eta, n_iface, (int)bdry_kind, (const double *)edge_cells, xi_out, eta_out);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "dirichlet kernel launch");
     if (launch_lu(a, px * px, stream, &e)) {
         if (e != hipSuccess) return hip_fail(e, "sub-domain kernel launch");
         return FK_OK;

@@ -35,7 +35,9 @@ from . import (FK_CV_DYNKIN, FK_CV_MARTINGALE, FkCv, fk_interface_solve, fk_inte
 
 DATA_GRID = 3
 DATA_IDENTITY = 0
+DATA_EQUIDISTRIBUTED = 4
 KIND_TWO_BUMPS = 3
+KIND_RING = 4
 TIME_FROZEN = 1
 
 
@@ -59,6 +61,7 @@ class MeshRunConfig:
     band: float = 0.06          # half-width of the label band around each interface line
     band_stride: int = 3        # grid stride of the band samples
     label_levels: int = 40      # most recent label levels kept for training
+    bdry: int = DATA_IDENTITY   # outer boundary data of the sub-domain solves (the mesh's edge nodes)
     seed: int = 0
 
 
@@ -103,6 +106,20 @@ def two_bump_density(t_freeze: float) -> Density:
     1/4 about the centre, one turn per unit time) frozen at t_freeze."""
     return Density(KIND_TWO_BUMPS, TIME_FROZEN, amp=30.0, width2=0.003, cx=0.5, cy=0.5, orbit_r=0.25,
                    omega=2.0 * np.pi, t_freeze=t_freeze)
+
+
+def paper_ring_density(t_freeze: float) -> Density:
+    """The paper's density (Sect. 5): w = 1/rho, rho = 1 + 10 exp(-50 |r^2 - 1/100|),
+    r the distance to (1/2 + cos(2 pi t)/4, 1/2 + sin(2 pi t)/4), frozen at t_freeze."""
+    return Density(KIND_RING, TIME_FROZEN, amp=10.0, width2=-50.0, cx=0.5, cy=0.5, orbit_r=0.25,
+                   omega=2.0 * np.pi, t_freeze=t_freeze)
+
+
+# The paper's run (Sect. 5): 41 x 41 nodes in 2 x 2 sub-domains, mesh step
+# 1e-3 in 20 sub-steps, 10^4 paths, up to t = 0.75, equidistributed edges;
+# every interface node is simulated (no key points, no interpolation).
+PAPER_RING_RUN = dict(px=2, m=20, dt_mesh=1e-3, substeps=20, n_steps=750, n_paths=10000, refit_every=0,
+                      bdry=DATA_EQUIDISTRIBUTED, labels="interface")
 
 
 def interface_nodes(px: int, m: int) -> np.ndarray:
@@ -223,7 +240,7 @@ class MeshRun:
                                      level_id=self.n, device=self.dev, workspace=self.workspace, grids=grids)
         self.workspace = out["_workspace"]
         xi_new, eta_new = subdomain_solve(dens, tn, cfg.dt_mesh, cfg.px, cfg.m, self.xi, self.eta, out["xi"],
-                                          out["eta"], bdry_kind=DATA_IDENTITY, out=self.spare,
+                                          out["eta"], bdry_kind=cfg.bdry, out=self.spare,
                                           workspace=self.sub_workspace)
         self._quality[self.n] = fk_mesh_quality(xi_new, eta_new)
         self._iface[self.n, :, 0] = out["xi"]

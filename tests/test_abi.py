@@ -43,7 +43,8 @@ def _call(fk, dens=None, data=None, pts=None, t=0.05, dt=1e-4, n_paths=16, ws_by
     (dict(pts=[[1.5, 0.5]]), -1),
     (dict(pts=[[0.5, float("nan")]]), -1),
     (dict(dens=W.Density(kind=9)), -1),
-    (dict(dens=W.paper_ring()), -5),
+    (dict(dens=W.Density(kind=W.KIND_RING, amp=10.0, width2=50.0)), -1),   # ring needs beta <= 0
+    (dict(dens=W.Density(kind=W.KIND_RING, amp=-1.0, width2=-50.0)), -1),  # and alpha >= 0
     (dict(data=W.Data(bdry_kind=W.DATA_GRID)), -1),
     (dict(data=W.Data(init_kind=W.DATA_GRID)), -1),
     (dict(ws_bytes=16), -3),

@@ -10,6 +10,7 @@ checked from the mesh the GPU held before it:
 * the recorded quality against the oracle's measures of the GPU's mesh, and
   against the quality of the global backward-Euler step from the same mesh.
 """
+import math
 import os
 
 import numpy as np
@@ -18,6 +19,7 @@ import pytest
 import oracle.mesh_step as MS
 import oracle.subdomain as S
 import workloads as W
+from parity import assert_parity
 
 pytestmark = pytest.mark.gpu
 THREADS = min(16, os.cpu_count() or 1)
@@ -143,4 +145,60 @@ def test_full_size_first_step_against_oracle(fk, oracle_mod):
     jg, sg = S.mesh_quality(*S.global_be_step(dens, 0.0, cfg.dt_mesh, cfg.px * cfg.m, xi0, eta0))
     print(f"quality: min J {q[0]:.4f} (global step {jg:.4f}), max skew {q[1]:.4f} (global {sg:.4f})", flush=True)
     assert q[0] > 0 and abs(q[0] - jg) <= 0.20 * jg and abs(q[1] - sg) <= 0.02
+    run.close()
+
+
+def test_paper_ring_run_against_oracle(fk, oracle_mod):
+    """The paper's run (Sect. 5): the moving ring on a 41 x 41 grid in 2 x 2
+    sub-domains, mesh step 1e-3 in 20 sub-steps, 10^4 paths, equidistributed
+    edges: three steps against the oracle (all 77 interface nodes).
+
+    The drift jumps across the ring (w = 1/rho with |r^2 - 1/100|), and at
+    t = 0 the ring passes exactly through two interface nodes, (0.65, 1/2)
+    and (0.85, 1/2): there r^2 - 1/100 rounds to +4e-9 in FP32 and -4e-18 in
+    FP64, so every path of those nodes takes the other side's drift on its
+    first step -- both legitimate on the discontinuity.  Nodes within 1e-6 of
+    the ring at the step's density time are held to 3 standard errors only;
+    all others to the full contract on the same counters."""
+    from paper_1402_0266_amd import fk_interface_solve
+    from paper_1402_0266_amd.mesh_run import PAPER_RING_RUN, GridData, MeshRun, MeshRunConfig, paper_ring_density
+    import torch
+    cfg = MeshRunConfig(**{**PAPER_RING_RUN, "n_steps": 3})
+    run = MeshRun(cfg, density_fn=paper_ring_density)
+    D = cfg.dt_mesh
+    for n in range(3):
+        xi_n, eta_n = run.mesh()
+        tn = n * D
+        # the driver's interface solve, with exit steps and scores
+        g = fk_interface_solve(paper_ring_density(tn), GridData(t_init=tn, score_mode=cfg.score_mode), run.pts, D,
+                               D / cfg.substeps, cfg.n_paths, seed=cfg.seed, level_id=n, exit_step=True, scores=True,
+                               grids=(run.xi.view(-1), run.eta.view(-1)))
+        print(f"[gpu] paper ring run step {n}", flush=True)
+        run.step()
+        torch.cuda.synchronize()
+        g = {k: v.cpu().numpy() for k, v in g.items() if not k.startswith("_")}
+        iface, _ = run.interface_values()
+        assert np.array_equal(iface[n, :, 0], g["xi"]) and np.array_equal(iface[n, :, 1], g["eta"])
+        dens = W.paper_ring(W.TIME_FROZEN, tn)
+        data = W.Data(init_kind=W.DATA_GRID, score_mode=W.SCORE_EXTEND, t_init=tn, grid_xi=xi_n, grid_eta=eta_n)
+        o = oracle_mod.fk_solve(dens, data, run.pts, D, D / cfg.substeps, cfg.n_paths, level_id=n, want_exit=True,
+                                want_scores=True, threads=THREADS)
+        c = (0.5 + 0.25 * math.cos(2 * math.pi * tn), 0.5 + 0.25 * math.sin(2 * math.pi * tn))
+        on_ring = np.abs((run.pts[:, 0] - c[0]) ** 2 + (run.pts[:, 1] - c[1]) ** 2 - 0.01) < 1e-6
+        d = np.abs(np.stack([g["xi"], g["eta"]], 1) - o["mean"])
+        assert np.all(d[on_ring] <= 3 * o["se"][on_ring])
+        keep = ~on_ring
+        sub = {k: (v[keep] if k != "total_steps" else v) for k, v in g.items() if k != "steps"}
+        assert_parity(sub, {k: v[keep] for k, v in o.items() if k in ("mean", "se", "exit_step", "scores")},
+                      run.pts[keep], shifted=False, label=f"step {n} ({int(on_ring.sum())} nodes on the ring):")
+        sx, sy = S.subdomain_be_step(dens, tn, D, cfg.px, cfg.m, xi_n, eta_n, iface[n, :, 0], iface[n, :, 1],
+                                     bdry="equidistributed")
+        gx, gy = run.mesh()
+        ex, ey = np.abs(gx - sx), np.abs(gy - sy)
+        print(f"step {n}: mesh max |gpu - oracle| xi {ex.max():.2e} at {np.unravel_index(ex.argmax(), ex.shape)}, "
+              f"eta {ey.max():.2e} at {np.unravel_index(ey.argmax(), ey.shape)}", flush=True)
+        assert ex.max() < 1e-11 and ey.max() < 1e-11
+        q = run.qualities()[n]
+        jo, so = S.mesh_quality(gx, gy)
+        assert abs(q[0] - jo) < 1e-12 and abs(q[1] - so) < 1e-12 and q[0] > 0
     run.close()

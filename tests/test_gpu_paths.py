@@ -198,3 +198,16 @@ def test_full_size_moving_bump_sampled(fk, torch_cuda, oracle_mod):
     sub = {k: (g[k][sel] if k != "total_steps" else g[k]) for k in g}
     sub["total_steps"] = np.array([sub["steps"].sum()])
     assert_parity(sub, o, pts[sel])
+
+
+@pytest.mark.parametrize("time_mode", [W.TIME_BACKWARD, W.TIME_FROZEN])
+def test_paper_ring(fk, torch_cuda, oracle_mod, time_mode):
+    """The paper's density w = 1/rho with the moving ring (Sect. 5), on the
+    interface nodes of its 2 x 2 layout of a 41 x 41 grid; the drift jumps
+    across the ring."""
+    dens = W.paper_ring(time_mode, t_freeze=0.3)
+    pts = W.interface_nodes(2, 2, 40)
+    data = W.Data(t_init=0.25)
+    g = run_gpu(fk, torch_cuda, dens, data, pts, 0.02, 5e-5, 2000, seed=21, level_id=3)
+    o = run_oracle(oracle_mod, dens, data, pts, 0.02, 5e-5, 2000, seed=21, level_id=3)
+    assert_parity(g, o, pts)

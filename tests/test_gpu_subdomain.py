@@ -52,6 +52,29 @@ def test_subdomain_against_oracle(fk, px, m, dens, t_w, D):
     assert err < 1e-12
 
 
+@pytest.mark.parametrize("px,m,dens,t_w,D", [
+    (2, 20, W.paper_ring(W.TIME_FROZEN, 0.3), 0.3, 1e-3),   # the paper's 41 x 41 grid, 2 x 2 layout
+    (4, 8, W.ridge(), 0.0, 0.01),
+    (2, 32, W.two_bumps(W.TIME_FROZEN, 0.02), 0.02, 5e-4),
+])
+def test_equidistributed_edges_against_oracle(fk, px, m, dens, t_w, D):
+    """Outer boundary data from the 1-D equidistribution of w along the
+    edges (Sect. 3): GPU Simpson quadrature against adaptive quadrature."""
+    import torch
+    N = px * m
+    xi0, eta0 = prev_mesh(N)
+    ij = S.interface_index(px, m)
+    ix, iy = xi0[ij[:, 1], ij[:, 0]], eta0[ij[:, 1], ij[:, 0]]
+    print(f"[gpu] subdomain equidistributed edges px={px} m={m} kind={dens.kind}", flush=True)
+    gx, gy = fk.subdomain_solve(dens, t_w, D, px, m, cuda(xi0), cuda(eta0), cuda(ix), cuda(iy),
+                                bdry_kind=W.DATA_EQUIDISTRIBUTED)
+    torch.cuda.synchronize()
+    ox, oy = S.subdomain_be_step(dens, t_w, D, px, m, xi0, eta0, ix, iy, bdry="equidistributed")
+    err = max(np.abs(gx.cpu().numpy() - ox).max(), np.abs(gy.cpu().numpy() - oy).max())
+    print(f"max |gpu - oracle| = {err:.3e}", flush=True)
+    assert err < 1e-11
+
+
 def test_domain_decomposition_identity_on_gpu(fk):
     import torch
     px, m = 4, 16

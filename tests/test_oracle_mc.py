@@ -42,13 +42,25 @@ def grad_log_w(oracle_mod, dens, tau, pts, h=1e-6):
     return b
 
 
-@pytest.mark.parametrize("dens", [W.static_bump(), W.moving_bump(), W.two_bumps(W.TIME_BACKWARD), W.ridge()],
-                         ids=["bump", "moving", "two", "ridge"])
+@pytest.mark.parametrize("dens", [W.static_bump(), W.moving_bump(), W.two_bumps(W.TIME_BACKWARD), W.ridge(),
+                                  W.paper_ring(W.TIME_BACKWARD)],
+                         ids=["bump", "moving", "two", "ridge", "ring"])
 def test_drift_is_minus_grad_log_w(oracle_mod, dens):
     pts = W.uniform_points(50, seed=3)
     for tau in (0.0, 0.037, 0.3):
         _, b = oracle_mod.density(dens, tau, pts)
         assert np.allclose(b, grad_log_w(oracle_mod, dens, tau, pts), rtol=1e-6, atol=1e-6)
+
+
+def test_ring_special_values(oracle_mod):
+    # the paper's ring (Sect. 5): w = 1/rho, rho = 1 + 10 exp(-50 |r^2 - 1/100|);
+    # on the ring r = 1/10 rho = 11, at the moving centre rho = 1 + 10 exp(-1/2)
+    ring = W.paper_ring(W.TIME_BACKWARD)
+    tau = 0.2
+    c = (0.5 + 0.25 * math.cos(2 * math.pi * tau), 0.5 + 0.25 * math.sin(2 * math.pi * tau))
+    w, b = oracle_mod.density(ring, tau, [[c[0], c[1]], [c[0] + 0.1, c[1]], [c[0], c[1] - 0.1]])
+    assert w[0] == pytest.approx(1 / (1 + 10 * math.exp(-0.5)), rel=1e-14) and np.allclose(b[0], 0.0)
+    assert w[1] == pytest.approx(1 / 11, rel=1e-12) and w[2] == pytest.approx(1 / 11, rel=1e-12)
 
 
 def test_density_special_values(oracle_mod):

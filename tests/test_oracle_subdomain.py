@@ -9,6 +9,9 @@
   global solve, the sub-domain solves reproduce the global solution.
 * Mesh quality: identity gives J = 1, skew = 0; an affine map gives its
   determinant and the angle between its rows.
+* Equidistributed edges (Sect. 3): w = 1 gives the identity; w = w(x) gives
+  xi = int_0^x w / int_0^1 w in closed form (erf) on the bottom and top
+  edges and eta = y on the left and right ones.
 """
 import math
 
@@ -78,3 +81,22 @@ def test_mesh_quality_closed_forms():
     jac, skew = S.mesh_quality(a * X + b * Y, c * X + d * Y)
     assert jac == pytest.approx(a * d - b * c, abs=1e-12)
     assert skew == pytest.approx(abs(a * c + b * d) / (math.hypot(a, b) * math.hypot(c, d)), abs=1e-12)
+
+
+def test_equidistributed_edges_closed_forms():
+    N = 16
+    gx, gy = S.boundary_grid(N, "equidistributed", W.CONST, 0.0)
+    ix, iy = S.boundary_grid(N, "identity")
+    edge = np.zeros((N + 1, N + 1), dtype=bool)
+    edge[0, :] = edge[-1, :] = edge[:, 0] = edge[:, -1] = True
+    assert np.abs(gx - ix)[edge].max() < 1e-13 and np.abs(gy - iy)[edge].max() < 1e-13
+    A, s2, c = 10.0, 0.01, 0.35
+    dens = W.ridge(A, s2, c)
+    gx, gy = S.boundary_grid(N, "equidistributed", dens, 0.0)
+    x = np.arange(N + 1) / N
+    F = lambda u: u + A * math.sqrt(math.pi * s2) / 2 * (math.erf((u - c) / math.sqrt(s2)) + math.erf(c / math.sqrt(s2)))  # noqa: E731
+    exact = np.array([F(u) / F(1.0) for u in x])
+    assert np.abs(gx[0, :] - exact).max() < 1e-12 and np.abs(gx[-1, :] - exact).max() < 1e-12
+    assert np.abs(gy[:, 0] - x).max() < 1e-12 and np.abs(gy[:, -1] - x).max() < 1e-12
+    assert np.all(gx[:, 0] == 0.0) and np.all(gx[:, -1] == 1.0)
+    assert np.all(gy[0, :] == 0.0) and np.all(gy[-1, :] == 1.0)

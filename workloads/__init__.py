@@ -43,6 +43,7 @@ DATA_SIN = 1          # both components phi = sin(pi x) sin(pi y); boundary data
                       # decaying mode exp(-2 pi^2 s') phi extended off the square
 DATA_ZERO = 2         # boundary data 0
 DATA_GRID = 3         # initial data bilinear in a (n+1)^2 nodal grid (initial data only)
+DATA_EQUIDISTRIBUTED = 4  # outer boundary of the sub-domain solves: 1-D equidistribution on two edges
 
 SCORE_UNCLAMPED = 0   # evaluate the boundary data at the (unclamped) first outside point
 SCORE_PROJECT = 1     # clamp that point onto the closed square first
