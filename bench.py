@@ -31,8 +31,9 @@ The same line reports, as extra objects:
   grid, two counter-rotating bumps, 200 mesh steps of 5e-4 with 20
   Euler-Maruyama steps each, 2^14 paths per interface node (10689 nodes),
   64 FP64 sub-domain solves per step; with the network refitted every 20
-  steps, and plain for comparison; mesh quality is recorded every step (the
-  tests compare it with the oracle's global step).
+  steps, with the mesh's own gradient as the control, and plain; mesh
+  quality is recorded every step (the tests compare it with the oracle's
+  global step).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-cv] [--no-mesh-run]
                     [--no-batched] [--no-paper-run]
@@ -257,7 +258,7 @@ def measure_mesh_run():
     import torch
     from paper_1402_0266_amd.mesh_run import MeshRun, MeshRunConfig
     res = {}
-    for name, kw in (("cv", {}), ("plain", {"refit_every": 0})):
+    for name, kw in (("cv", {}), ("grid_cv", {"cv_form": "grid", "cv_stride": 2}), ("plain", {"refit_every": 0})):
         cfg = MeshRunConfig(**kw)
         print(f"[bench] mesh run ({name}): {cfg.n_steps} steps", file=sys.stderr, flush=True)
         run = MeshRun(cfg, init_params=W.mlp_init(0) if cfg.refit_every else None)
@@ -279,7 +280,8 @@ def measure_mesh_run():
                      "se_median": float(np.median(se)), "se_max": float(se.max())}
     res["config"] = ("8x8 sub-domains, 768-cell grid, 10689 interface nodes, two counter-rotating bumps A=30 "
                      "s2=0.003 frozen per step, 200 steps of 5e-4, 20 EM steps each, 2^14 paths/node; cv: "
-                     "martingale form, stride 20, refit every 20 steps on mesh labels near the interfaces")
+                     "martingale form, stride 20, refit every 20 steps on mesh labels near the interfaces; grid_cv: "
+                     "martingale form with the mesh's own gradient every 2 steps (no network)")
     return res
 
 

@@ -284,7 +284,11 @@ int fk_cv_train(fk_cv_t cv, const float *txy, const float *target, int64_t n, in
  *   FK_CV_MARTINGALE   u(P) = E[ g - sum_j grad u_hat(X_{k_j}) . dB_j ], dB_j the
  *                      Brownian part sqrt(2 dt) z of the steps from k_j (every
  *                      `stride` steps from the start) to the next k_j or the
- *                      path's end: mean zero for the discrete chain at any stride.
+ *                      path's end: mean zero for the discrete chain at any stride
+ *                      and for any gradient, so also
+ *   FK_CV_MARTINGALE_GRID  with the gradient of the grid initial data in place
+ *                      of the network's (over one mesh step the solution stays
+ *                      close to the mesh it starts from).
  * stride is even, >= 2.  xi/eta/se_*: the CV estimate; plain_*: the plain
  * estimate from the same paths (all four or none); exit_step and cv_scores
  * (device [n][N][2], the per-path CV scores whose mean, plus u_hat(t_init + t, P)
@@ -293,6 +297,9 @@ int fk_cv_train(fk_cv_t cv, const float *txy, const float *target, int64_t n, in
  */
 #define FK_CV_DYNKIN 0
 #define FK_CV_MARTINGALE 1
+#define FK_CV_MARTINGALE_GRID 2   /* the martingale form with G = gradient of the bilinear interpolant of the
+                                     grid initial data at the path's position (no network: cv may be NULL;
+                                     needs FK_DATA_GRID initial data); every `stride` steps of each path */
 size_t fk_interface_cv_workspace_bytes(int64_t n_nodes, int64_t n_paths);
 int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *pts, int64_t n_nodes, double t,
                           double dt, int64_t n_paths, uint64_t seed, uint32_t level_id, fk_cv_t cv, int32_t stride,

@@ -543,10 +543,40 @@ typedef struct {
     int kind;
     or_mlp mlp;
     double t_init;
+    const double *grid_xi, *grid_eta;   /* kind 4: the grid initial data */
+    int grid_n;
 } or_uhat;
+
+/* Partial derivatives of the bilinear interpolant of a nodal grid at (x, y),
+   in the cell bilinear() uses. */
+static void bilinear_grad(const double *g, int n, double x, double y, double *gx, double *gy)
+{
+    double fx = x * n, fy = y * n;
+    int i = (int)floor(fx), j = (int)floor(fy);
+    if (i < 0) i = 0;
+    if (i > n - 1) i = n - 1;
+    if (j < 0) j = 0;
+    if (j > n - 1) j = n - 1;
+    double ax = fx - i, ay = fy - j;
+    const double *r0 = g + (int64_t)j * (n + 1), *r1 = r0 + (n + 1);
+    *gx = n * ((1 - ay) * (r0[i + 1] - r0[i]) + ay * (r1[i + 1] - r1[i]));
+    *gy = n * ((1 - ax) * (r1[i] - r0[i]) + ax * (r1[i + 1] - r0[i + 1]));
+}
 
 static void uhat_eval(const or_uhat *u, double tau, double x, double y, double out[2][5])
 {
+    if (u->kind == 4) {
+        /* the grid initial data, bilinear: value and gradient (the martingale
+           form uses only the gradient) */
+        const double *g[2] = {u->grid_xi, u->grid_eta};
+        for (int c = 0; c < 2; ++c) {
+            out[c][0] = bilinear(g[c], u->grid_n, x, y);
+            bilinear_grad(g[c], u->grid_n, x, y, &out[c][1], &out[c][2]);
+            out[c][3] = 0.0;
+            out[c][4] = 0.0;
+        }
+        return;
+    }
     switch (u->kind) {
     case 0: mlp_forward_mode(&u->mlp, tau, x, y, out); return;
     case 1:
@@ -744,7 +774,12 @@ int or_fk_solve_cv(int kind, int time_mode, const double *par,
     or_uhat u;
     u.kind = uhat_kind;
     u.t_init = t_init;
+    u.grid_xi = grid_xi;
+    u.grid_eta = grid_eta;
+    u.grid_n = grid_n;
     if (uhat_kind == 0) mlp_bind(&u.mlp, flat, t_scale);
+    /* the grid's bilinear interpolant has no Laplacian: martingale form only */
+    if (uhat_kind == 4 && (form != 1 || init_kind != D_GRID || !grid_xi || !grid_eta)) return -1;
     const int64_t total = n_nodes * n_paths;
     double *pl = (double *)malloc(sizeof(double) * 2 * (size_t)(total > 0 ? total : 1));
     double *cs = cv_scores ? cv_scores : (double *)malloc(sizeof(double) * 2 * (size_t)(total > 0 ? total : 1));

@@ -470,7 +470,7 @@ class FkCv:
         return loss
 
 
-FK_CV_DYNKIN, FK_CV_MARTINGALE = 0, 1
+FK_CV_DYNKIN, FK_CV_MARTINGALE, FK_CV_MARTINGALE_GRID = 0, 1, 2
 
 
 def fk_interface_solve_cv(density, data, pts, t, dt, n_paths, cv, stride=2, seed=0, level_id=0, *,
@@ -501,7 +501,8 @@ def fk_interface_solve_cv(density, data, pts, t, dt, n_paths, cv, stride=2, seed
 
     _check(_lib.fk_interface_solve_cv(
         ctypes.byref(_density(density)), ctypes.byref(_data(data, grids)), pts.ctypes.data_as(ctypes.c_void_p), n,
-        float(t), float(dt), int(n_paths), int(seed), int(level_id), cv.handle, int(stride), int(form),
+        float(t), float(dt), int(n_paths), int(seed), int(level_id), None if cv is None else cv.handle, int(stride),
+        int(form),
         ptr("xi"), ptr("eta"), ptr("se_xi"), ptr("se_eta"), ptr("plain_xi"), ptr("plain_eta"), ptr("plain_se_xi"),
         ptr("plain_se_eta"), ptr("exit_step"), ptr("cv_scores"), ptr("total_steps"), _plan_struct(plan),
         workspace.data_ptr(), workspace.numel(), _stream(torch, dev)))

@@ -694,6 +694,132 @@ __global__ void __launch_bounds__(256, 2) fk_mg_path_kernel(const PathArgs a, co
     if (lane == 0 && st != 0ull) atomicAdd(a.total_steps, st);
 }
 
+// Gradient of the bilinear interpolant of a nodal grid at (x, y) (the cell
+// grid_bilinear uses); differences taken in FP64.
+__device__ __forceinline__ void grid_gradient(const double *g, int n, float x, float y, float &gx, float &gy) {
+    const float fx = x * (float)n, fy = y * (float)n;
+    int i = (int)floorf(fx), j = (int)floorf(fy);
+    i = min(max(i, 0), n - 1);
+    j = min(max(j, 0), n - 1);
+    const float ax = fx - (float)i, ay = fy - (float)j;
+    const double *r0 = g + (int64_t)j * (n + 1);
+    const double *r1 = r0 + (n + 1);
+    const float d0x = (float)(r0[i + 1] - r0[i]), d1x = (float)(r1[i + 1] - r1[i]);
+    const float d0y = (float)(r1[i] - r0[i]), d1y = (float)(r1[i + 1] - r0[i + 1]);
+    gx = (float)n * fmaf(ay, d1x - d0x, d0x);
+    gy = (float)n * fmaf(ax, d1y - d0y, d0y);
+}
+
+// Martingale form with the grid initial data as the control: every `stride`
+// steps of a path (from its start) the lane takes G = the gradient of the
+// bilinear interpolant of (grid_xi, grid_eta) at its position, and the score
+// is g - sum_j G_j . dB_j.  No network: lanes need no common evaluation
+// points, so they start new paths at once, and each path's blocks sit at
+// fixed offsets from its start (schedule-independent results).
+struct MggArgs {
+    uint32_t stride;             // steps (even)
+    float2 *cv_scores;           // [n_out * n_paths], absolute
+};
+
+template <int KIND, int TMODE, bool UNIFORM>
+__global__ void __launch_bounds__(256) fk_mgg_path_kernel(const PathArgs a, const MggArgs c) {
+    constexpr bool kMovingBackward = moving_kind(KIND) && TMODE == TIME_BACKWARD;
+    const uint32_t lane = threadIdx.x & 63u;
+    uint32_t q_slot = 0, q_next = 0, q_end = 0;
+    bool q_done = false;
+    const uint32_t key0 = a.key0, key1 = a.key1;
+    Lane L;
+    bool active = false;
+    float gxx = 0.f, gxy = 0.f, gyx = 0.f, gyy = 0.f;
+    float dbx = 0.f, dby = 0.f, mx = 0.f, my = 0.f;
+    uint32_t my_steps = 0;
+
+    for (;;) {
+        uint64_t need = __ballot(!active);
+        while (need != 0ull && !q_done) {
+            if (q_next >= q_end) {
+                uint32_t cc = 0;
+                if (lane == 0) cc = atomicAdd(a.queue, 1u);
+                cc = __builtin_amdgcn_readfirstlane(cc);
+                if (cc >= a.total_chunks) {
+                    q_done = true;
+                    break;
+                }
+                q_slot = cc / a.cpn;
+                q_next = (cc - q_slot * a.cpn) * a.chunk;
+                q_end = min(q_next + a.chunk, a.n_paths);
+                continue;
+            }
+            const uint32_t avail = q_end - q_next;
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+            if (!active && rank < avail) {
+                lane_start<KIND, TMODE>(L, a.nodes[q_slot], a.levels, q_next + rank, a.n_paths);
+                dbx = dby = mx = my = 0.f;
+                active = true;
+            }
+            q_next += min((uint32_t)__popcll(need), avail);
+            need = __ballot(!active);
+        }
+        if (__ballot(active) == 0ull) break;
+
+        if (active) {
+            bool out = false;
+            if (L.k < L.K) {
+                if ((uint32_t)L.k % c.stride == 0) {
+                    // block boundary: close the block, take the gradient here
+                    mx = fmaf(gxx, dbx, fmaf(gxy, dby, mx));
+                    my = fmaf(gyx, dbx, fmaf(gyy, dby, my));
+                    dbx = dby = 0.f;
+                    grid_gradient(a.grid_xi, a.grid_n, L.xh, L.yh, gxx, gxy);
+                    grid_gradient(a.grid_eta, a.grid_n, L.xh, L.yh, gyx, gyy);
+                }
+                const PhiloxOut r = philox4x32_10((uint32_t)L.k >> 1, L.path, L.nid, L.ctr3, key0, key1);
+                float ox = L.ox, oy = L.oy, cr = 0.f, sr = 0.f;
+                if constexpr (kMovingBackward) {
+                    const float rev = fmaf(-(float)L.k, L.drev, L.rev0);
+                    cr = hw_cos_rev(rev);
+                    sr = hw_sin_rev(rev);
+                    ox = L.dens.orbit_r * cr;
+                    oy = L.dens.orbit_r * sr;
+                }
+                float wx, wy;
+                out = em_step_w<KIND, UNIFORM>(L, r.r0, r.r1, ox, oy, wx, wy);
+                dbx += wx;
+                dby += wy;
+                my_steps += 1;
+                if (!out && L.k < L.K) {
+                    if constexpr (kMovingBackward) {
+                        const float c2 = fmaf(cr, L.cos_d, sr * L.sin_d);
+                        const float s2 = fmaf(sr, L.cos_d, -cr * L.sin_d);
+                        ox = L.dens.orbit_r * c2;
+                        oy = L.dens.orbit_r * s2;
+                    }
+                    out = em_step_w<KIND, UNIFORM>(L, r.r2, r.r3, ox, oy, wx, wy);
+                    dbx += wx;
+                    dby += wy;
+                    my_steps += 1;
+                }
+            }
+            if (out || L.k >= L.K) {
+                float plx, ply;
+                score_path(a, L, out, plx, ply);
+                mx = fmaf(gxx, dbx, fmaf(gxy, dby, mx));
+                my = fmaf(gyx, dbx, fmaf(gyy, dby, my));
+                const float sx0 = a.shift ? L.px : 0.f, sy0 = a.shift ? L.py : 0.f;
+                a.scores[L.rec] = make_float2(plx, ply);
+                c.cv_scores[L.rec] = make_float2((plx + sx0) - mx, (ply + sy0) - my);
+                if (a.exit_step) a.exit_step[L.rec] = out ? L.k : -1;
+                active = false;
+            }
+        }
+    }
+    unsigned long long st = my_steps;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) st += __shfl_xor(st, off, 64);
+    if (lane == 0 && st != 0ull) atomicAdd(a.total_steps, st);
+}
+
 // Per node: u_hat at the start (the shift of the CV estimate) and the
 // integrand r0 there.
 struct CvNodeArgs {
@@ -1028,6 +1154,22 @@ struct MgOccF {
     }
 };
 template <int K, int T, bool U>
+struct MggLaunchF {
+    static hipError_t run(const PathArgs &a, const MggArgs &c, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((fk_mgg_path_kernel<K, T, U>), dim3(grid), dim3(256), 0, s, a, c);
+        return hipGetLastError();
+    }
+};
+template <int K, int T, bool U>
+struct MggOccF {
+    static int run() {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk_mgg_path_kernel<K, T, U>, 256, 0) != hipSuccess)
+            return 0;
+        return nb;
+    }
+};
+template <int K, int T, bool U>
 struct CvNodeF {
     static hipError_t run(const CvNodeArgs &na, const uint16_t *bf, float ts2, hipStream_t s) {
         const int blocks = (int)((na.n_nodes + 255) / 256);
@@ -1280,14 +1422,18 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
                           size_t workspace_bytes, hipStream_t stream) {
     g_last_error.clear();
     int rc;
-    if (!cv) return fail(FK_E_INVAL, "network is NULL");
+    const bool grid_ctl = (form == FK_CV_MARTINGALE_GRID);
+    if (!cv && !grid_ctl) return fail(FK_E_INVAL, "network is NULL");
     if ((rc = validate_density(w)) != FK_OK) return rc;
     if ((rc = validate_data(d)) != FK_OK) return rc;
     if ((rc = validate_common(n_paths, dt)) != FK_OK) return rc;
     if ((rc = validate_horizon(t, d->t_init, dt, level_id)) != FK_OK) return rc;
     if ((rc = validate_points(pts, n_nodes)) != FK_OK) return rc;
     if (stride < 2 || stride % 2 != 0 || stride > (1 << 20)) return fail(FK_E_INVAL, "stride must be even and >= 2");
-    if (form != FK_CV_DYNKIN && form != FK_CV_MARTINGALE) return fail(FK_E_INVAL, "unknown control-variate form");
+    if (form != FK_CV_DYNKIN && form != FK_CV_MARTINGALE && form != FK_CV_MARTINGALE_GRID)
+        return fail(FK_E_INVAL, "unknown control-variate form");
+    if (grid_ctl && d->init_kind != FK_DATA_GRID)
+        return fail(FK_E_INVAL, "the grid control needs grid initial data");
     if (n_nodes > 0 && (!xi || !eta || !se_xi || !se_eta)) return fail(FK_E_INVAL, "an output pointer is NULL");
     fk_plan pl;
     if ((rc = resolve_plan(plan, &pl)) != FK_OK) return rc;
@@ -1309,7 +1455,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     // (the node kernel writes it), the martingale form's is zero
     std::vector<OutDev> outs_cv = T.outs;
     for (OutDev &o : outs_cv) o.shift_x = o.shift_y = 0.0;
-    const bool mg = (form == FK_CV_MARTINGALE);
+    const bool mg = (form != FK_CV_DYNKIN);
     hipError_t e;
     if ((e = hipMemcpyAsync(ws + lay.levels, T.levels.data(), sizeof(LevelDev), hipMemcpyHostToDevice, stream)) !=
             hipSuccess ||
@@ -1333,10 +1479,11 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     na.outs_cv = mg ? nullptr : (OutDev *)(ws + lay.outs_cv);
     na.r0 = mg ? nullptr : (float2 *)(ws + lay.r0);
     na.g0 = mg ? (float4 *)(ws + lay.g0) : nullptr;
-    const float ts2 = 2.f / cv->t_scale;
+    const float ts2 = grid_ctl ? 0.f : 2.f / cv->t_scale;
     if ((e = timing_record(0, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    if ((e = cv_dispatch<CvNodeF>(T.kind, T.time_mode, true, na, (const uint16_t *)cv->s.bf, ts2, stream)) !=
-        hipSuccess)
+    if (!grid_ctl &&
+        (e = cv_dispatch<CvNodeF>(T.kind, T.time_mode, true, na, (const uint16_t *)cv->s.bf, ts2, stream)) !=
+            hipSuccess)
         return hip_fail(e, "node kernel launch");
 
     PathArgs a{};
@@ -1367,6 +1514,14 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         const int occ = cv_dispatch<CvOccF>(T.kind, T.time_mode, T.uniform);
         if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
         if ((e = cv_dispatch<CvLaunchF>(T.kind, T.time_mode, T.uniform, a, c, n_cu * bpc, stream)) != hipSuccess)
+            return hip_fail(e, "control-variate path kernel launch");
+    } else if (grid_ctl) {
+        MggArgs c{};
+        c.stride = (uint32_t)stride;
+        c.cv_scores = cv_rec;
+        const int occ = cv_dispatch<MggOccF>(T.kind, T.time_mode, T.uniform);
+        if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
+        if ((e = cv_dispatch<MggLaunchF>(T.kind, T.time_mode, T.uniform, a, c, n_cu * bpc, stream)) != hipSuccess)
             return hip_fail(e, "control-variate path kernel launch");
     } else {
         MgArgs c{};

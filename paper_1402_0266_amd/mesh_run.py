@@ -14,7 +14,10 @@ t^n + dt_mesh:
    interface values as Dirichlet data (Sect. 4);
 4. the mesh quality (minimum Jacobian, maximum skewness) is recorded.
 
-The network u_hat(t, x, y) is refitted every `refit_every` steps on labels
+With `cv_form="grid"` the control is the mesh's own gradient (bilinear in
+the grid, taken every `cv_stride` steps of each path) in the martingale
+form: no network.  Otherwise the network u_hat(t, x, y) is refitted every
+`refit_every` steps on labels
 the run has produced (at their times t^{n+1}), starting from the initial mesh
 at t = 0: either the interface estimates themselves, or (default) the mesh
 values at the grid nodes within `band` of an interface line, where the paths
@@ -30,8 +33,8 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import (FK_CV_DYNKIN, FK_CV_MARTINGALE, FkCv, fk_interface_solve, fk_interface_solve_cv, fk_mesh_quality,
-               subdomain_solve, subdomain_workspace_bytes)
+from . import (FK_CV_DYNKIN, FK_CV_MARTINGALE, FK_CV_MARTINGALE_GRID, FkCv, fk_interface_solve,
+               fk_interface_solve_cv, fk_mesh_quality, subdomain_solve, subdomain_workspace_bytes)
 
 DATA_GRID = 3
 DATA_IDENTITY = 0
@@ -50,7 +53,8 @@ class MeshRunConfig:
     n_steps: int = 200
     n_paths: int = 1 << 14
     refit_every: int = 20       # 0: plain Monte Carlo throughout
-    cv_form: str = "martingale"  # or "dynkin"
+    cv_form: str = "martingale"  # "dynkin"; or "grid": the martingale form with the mesh's own gradient
+                                 # (no network, refit_every ignored)
     cv_stride: int = 20
     train_steps: int = 2000
     train_batch: int = 8192
@@ -176,7 +180,7 @@ class MeshRun:
         self.sub_workspace = torch.empty(max(subdomain_workspace_bytes(cfg.px, cfg.m), 256), dtype=torch.uint8,
                                          device=self.dev)
         self.losses = []
-        if cfg.refit_every > 0:
+        if cfg.refit_every > 0 and cfg.cv_form != "grid":
             if init_params is None:
                 raise ValueError("refit_every > 0 needs initial network parameters")
             self.cv = FkCv(init_params, cfg.t_scale)
@@ -229,7 +233,13 @@ class MeshRun:
         if self.cv is not None and self.n % cfg.refit_every == 0:
             self.refit()
         dt = cfg.dt_mesh / cfg.substeps
-        if self.cv is not None:
+        if cfg.cv_form == "grid":
+            out = fk_interface_solve_cv(dens, data, self.pts, cfg.dt_mesh, dt, cfg.n_paths, None,
+                                        stride=cfg.cv_stride, seed=cfg.seed, level_id=self.n,
+                                        form=FK_CV_MARTINGALE_GRID, plain=False, device=self.dev,
+                                        workspace=self.workspace, grids=grids)
+            self.used_cv[self.n] = True
+        elif self.cv is not None:
             form = FK_CV_MARTINGALE if cfg.cv_form == "martingale" else FK_CV_DYNKIN
             out = fk_interface_solve_cv(dens, data, self.pts, cfg.dt_mesh, dt, cfg.n_paths, self.cv,
                                         stride=cfg.cv_stride, seed=cfg.seed, level_id=self.n, form=form,

@@ -213,3 +213,49 @@ def test_cv_martingale_against_oracle(fk, oracle_mod, stride):
     assert np.all(d <= 3 * o["se"]) and np.all(d <= 1e-5)
     assert np.all(np.abs(np.stack([g["se_xi"], g["se_eta"]], 1) - o["se"]) <= 0.05 * o["se"])
     cv.close()
+
+
+@pytest.mark.parametrize("stride", [2, 20])
+def test_cv_grid_control_against_oracle(fk, oracle_mod, stride):
+    """Martingale form with the grid initial data's gradient as the control
+    (no network): a deformed mesh under two frozen bumps, exits scored with
+    the grid continued past the edge, one mesh step."""
+    import torch
+    n = 48
+    x = np.arange(n + 1) / n
+    X, Y = np.meshgrid(x, x)
+    gx = X + 0.02 * np.sin(np.pi * X) * np.sin(2 * np.pi * Y)
+    gy = Y + 0.015 * np.sin(2 * np.pi * X) * np.sin(np.pi * Y)
+    dens = W.two_bumps(W.TIME_FROZEN, 0.0375)
+    data = W.Data(init_kind=W.DATA_GRID, score_mode=W.SCORE_EXTEND, t_init=0.0375, grid_xi=gx.ravel(),
+                  grid_eta=gy.ravel())
+    nodes = W.interface_nodes(4, 4, 48)
+    pts = np.concatenate([nodes[::7], nodes[np.minimum(nodes, 1 - nodes).min(1) < 0.05][::3]])
+    t, dt, N = 5e-4, 2.5e-5, 2048
+    grids = (torch.tensor(gx.ravel(), device="cuda"), torch.tensor(gy.ravel(), device="cuda"))
+    print(f"[gpu] cv grid control stride={stride} nodes={len(pts)} N={N}", flush=True)
+    g = fk.fk_interface_solve_cv(dens, data, pts, t, dt, N, None, stride=stride, seed=5, level_id=2,
+                                 form=fk.FK_CV_MARTINGALE_GRID, exit_step=True, cv_scores=True, grids=grids)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in g.items() if not k.startswith("_")}
+    o = oracle_mod.fk_solve_cv(dens, data, pts, t, dt, N, seed=5, level_id=2, uhat=oracle_mod.UHAT_GRID,
+                               stride=stride, form=oracle_mod.CV_MARTINGALE, want_scores=True, want_exit=True,
+                               threads=THREADS)
+    plain = {"xi": g["plain_xi"], "eta": g["plain_eta"], "se_xi": g["plain_se_xi"], "se_eta": g["plain_se_eta"],
+             "exit_step": g["exit_step"]}
+    assert_parity(plain, {"mean": o["plain_mean"], "se": o["plain_se"], "exit_step": o["exit_step"]}, pts,
+                  shifted=False, label="plain part:")
+    same = g["exit_step"] == o["exit_step"]
+    ds = np.abs(g["cv_scores"].astype(np.float64) - o["cv_scores"])[same]
+    d = np.abs(np.stack([g["xi"], g["eta"]], 1) - o["mean"])
+    ratio = np.median(o["se"] / o["plain_se"])
+    print(f"grid control: max |score diff| {ds.max():.2e}, max |mean diff| {d.max():.2e}, se cv/plain {ratio:.3f}",
+          flush=True)
+    # The bilinear gradient jumps across cell edges: where FP32 and FP64
+    # positions sit on opposite sides of one, the path's G differs by that
+    # jump times its block's Brownian part; like exit steps, such paths are
+    # rare (99.9% agree to 1e-6) and their differences bounded.
+    assert np.mean(ds.max(axis=-1) < 1e-6) >= 0.999 and ds.max() < 1e-3
+    assert np.all(d <= 3 * o["se"]) and np.all(d <= 1e-5)
+    assert np.all(np.abs(np.stack([g["se_xi"], g["se_eta"]], 1) - o["se"]) <= 0.01 * o["se"] + 1e-9)
+    assert ratio < (0.1 if stride == 2 else 0.5)

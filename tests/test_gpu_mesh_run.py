@@ -70,7 +70,7 @@ def test_plain_mesh_run_against_oracle(fk, oracle_mod):
     run.close()
 
 
-@pytest.mark.parametrize("form", ["martingale", "dynkin"])
+@pytest.mark.parametrize("form", ["martingale", "dynkin", "grid"])
 def test_cv_mesh_run_against_oracle(fk, oracle_mod, form):
     from paper_1402_0266_amd.mesh_run import MeshRun, MeshRunConfig
     n_paths, stride = 4096, 10
@@ -82,13 +82,16 @@ def test_cv_mesh_run_against_oracle(fk, oracle_mod, form):
         xi_n, eta_n = run.mesh()
         print(f"[gpu] mesh run cv step {n}, {run.n_nodes} nodes, N={n_paths}", flush=True)
         run.step()
-        _, bf = run.cv.params()                  # the network this step used (refits come first)
         data = W.Data(init_kind=W.DATA_GRID, score_mode=W.SCORE_EXTEND, t_init=n * D, grid_xi=xi_n,
                       grid_eta=eta_n)
+        if form == "grid":
+            ctl = dict(uhat=oracle_mod.UHAT_GRID, form=oracle_mod.CV_MARTINGALE)
+        else:
+            _, bf = run.cv.params()              # the network this step used (refits come first)
+            ctl = dict(uhat=oracle_mod.UHAT_MLP, flat=bf, t_scale=W.CV_T_SCALE,
+                       form=oracle_mod.CV_MARTINGALE if form == "martingale" else oracle_mod.CV_DYNKIN)
         o = oracle_mod.fk_solve_cv(W.two_bumps(W.TIME_FROZEN, n * D), data, run.pts[sub], D, D / 20, n_paths,
-                                   level_id=n, node_ids=sub, flat=bf, t_scale=W.CV_T_SCALE, stride=stride,
-                                   form=oracle_mod.CV_MARTINGALE if form == "martingale" else oracle_mod.CV_DYNKIN,
-                                   want_scores=True, threads=THREADS)
+                                   level_id=n, node_ids=sub, stride=stride, want_scores=True, threads=THREADS, **ctl)
         iface, se = run.interface_values()
         # Dynkin-form scores g - u_hat(end) + sum r ds carry the network's
         # relative evaluation error (~1e-5) on their own scale
@@ -97,9 +100,13 @@ def test_cv_mesh_run_against_oracle(fk, oracle_mod, form):
         ratio = np.median(o["se"] / o["plain_se"])
         print(f"step {n}: cv max |gpu - oracle| {d.max():.2e}, score scale {smax:.3g}, se cv/plain {ratio:.3f}",
               flush=True)
-        assert np.all(d <= 3 * o["se"]) and np.all(d <= 1e-5 * max(1.0, smax))
+        # With the mesh's gradient as the control, nodes away from the bumps
+        # keep almost no variance (se ~1e-18): the floor there is the FP32
+        # rounding of the per-path score records (~3e-8 of values ~1).
+        floor = 1e-7 if form == "grid" else 0.0
+        assert np.all(d <= 3 * o["se"] + floor) and np.all(d <= 1e-5 * max(1.0, smax))
         assert np.all(np.abs(se[n, sub] - o["se"]) <= 0.02 * o["se"] + 1e-7)
-        assert ratio < 0.5                       # the network pays off from the first step
+        assert ratio < (0.1 if form == "grid" else 0.5)   # the control pays off from the first step
         assert run.qualities()[n][0] > 0
     run.close()
 

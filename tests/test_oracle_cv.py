@@ -25,6 +25,7 @@ Martingale form:
 import math
 
 import numpy as np
+import pytest
 
 import oracle.mlp as M
 import workloads as W
@@ -129,3 +130,55 @@ def test_martingale_form_is_unbiased_at_any_stride(oracle_mod):
         assert np.all(np.abs(r["mean"] - diff.mean(1) - pl["mean"]) < 1e-12)
     z = np.concatenate(z).ravel()
     assert np.abs(z).max() < 4.0 and abs(z.mean()) < 4 / math.sqrt(z.size)
+
+
+# ---- martingale form with the grid initial data as the control ----------------
+# G = gradient of the bilinear interpolant of the (xi, eta) grids at the path.
+
+def _nodal(n):
+    x = np.arange(n + 1) / n
+    return np.meshgrid(x, x)
+
+
+def test_grid_control_of_the_identity_mesh_is_exact(oracle_mod):
+    """The identity mesh's interpolant has gradient I, so under w = 1 with
+    identity boundary data every path scores its start point, any stride."""
+    X, Y = _nodal(32)
+    pts = W.uniform_points(8, seed=9)
+    data = W.Data(init_kind=W.DATA_GRID, grid_xi=X, grid_eta=Y)
+    for stride in (1, 4, 1000):
+        r = oracle_mod.fk_solve_cv(W.CONST, data, pts, 0.051, 2e-3, 300, seed=2, uhat=oracle_mod.UHAT_GRID,
+                                   stride=stride, form=oracle_mod.CV_MARTINGALE, want_scores=True, want_exit=True)
+        assert np.any(r["exit_step"] >= 0)
+        assert np.abs(r["cv_scores"] - pts[:, None, :]).max() < 1e-13
+
+
+def test_grid_control_is_unbiased_and_reduces_variance(oracle_mod):
+    """A deformed mesh under two frozen bumps: cv - plain on the same paths
+    has mean zero at strides 2 and 20, and the control removes most of the
+    variance."""
+    X, Y = _nodal(48)
+    xi = X + 0.02 * np.sin(math.pi * X) * np.sin(2 * math.pi * Y)
+    eta = Y + 0.015 * np.sin(2 * math.pi * X) * np.sin(math.pi * Y)
+    data = W.Data(init_kind=W.DATA_GRID, score_mode=W.SCORE_EXTEND, grid_xi=xi, grid_eta=eta)
+    dens = W.two_bumps(W.TIME_FROZEN, 0.01)
+    pts = W.interface_nodes(4, 4, 48)[::9]
+    pl = oracle_mod.fk_solve(dens, data, pts, 5e-4, 2.5e-5, 2000, seed=4, want_scores=True)
+    z = []
+    for stride in (2, 20):
+        r = oracle_mod.fk_solve_cv(dens, data, pts, 5e-4, 2.5e-5, 2000, seed=4, uhat=oracle_mod.UHAT_GRID,
+                                   stride=stride, form=oracle_mod.CV_MARTINGALE, want_scores=True)
+        diff = r["cv_scores"] - pl["scores"]
+        z.append(diff.mean(1) / (diff.std(1, ddof=1) / math.sqrt(diff.shape[1])))
+        ratio = np.median(r["se"] / pl["se"])
+        assert ratio < (0.1 if stride == 2 else 0.5), (stride, ratio)
+    z = np.concatenate(z).ravel()
+    assert np.abs(z).max() < 4.0 and abs(z.mean()) < 4 / math.sqrt(z.size)
+
+
+def test_grid_control_needs_the_martingale_form(oracle_mod):
+    X, Y = _nodal(8)
+    data = W.Data(init_kind=W.DATA_GRID, grid_xi=X, grid_eta=Y)
+    with pytest.raises(ValueError):
+        oracle_mod.fk_solve_cv(W.CONST, data, [[0.5, 0.5]], 0.01, 1e-3, 10, uhat=oracle_mod.UHAT_GRID,
+                               form=oracle_mod.CV_DYNKIN)
