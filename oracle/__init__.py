@@ -49,10 +49,11 @@ def lib():
         P = ctypes.c_void_p
         L.or_philox_batch.argtypes = [P, P, ctypes.c_int64, P]
         L.or_normals_batch.argtypes = [P, P, ctypes.c_int64, P]
-        L.or_density_batch.argtypes = [ctypes.c_int, P, ctypes.c_double, P, ctypes.c_int64, P, P]
+        L.or_density_batch.argtypes = [ctypes.c_int, P, P, ctypes.c_int, ctypes.c_double, P, ctypes.c_int64, P, P]
+        L.or_density_batch.restype = ctypes.c_int
         L.or_n_steps.argtypes = [ctypes.c_double, ctypes.c_double]
         L.or_n_steps.restype = ctypes.c_int64
-        L.or_fk_solve.argtypes = [ctypes.c_int, ctypes.c_int, P,
+        L.or_fk_solve.argtypes = [ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int,
                                   ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                   P, P, ctypes.c_int,
                                   P, P, ctypes.c_int64,
@@ -60,7 +61,7 @@ def lib():
                                   ctypes.c_uint32, ctypes.c_uint32, ctypes.c_int,
                                   P, P, P, P, P]
         L.or_fk_solve.restype = ctypes.c_int
-        L.or_fk_paths.argtypes = [ctypes.c_int, ctypes.c_int, P,
+        L.or_fk_paths.argtypes = [ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int,
                                   ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                   P, P, ctypes.c_int,
                                   P, P, P, ctypes.c_int64,
@@ -69,7 +70,7 @@ def lib():
         L.or_fk_paths.restype = ctypes.c_int
         L.or_mlp_eval.argtypes = [P, ctypes.c_double, P, ctypes.c_int64, P]
         L.or_mlp_eval.restype = ctypes.c_int
-        L.or_fk_solve_cv.argtypes = [ctypes.c_int, ctypes.c_int, P,
+        L.or_fk_solve_cv.argtypes = [ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int,
                                      ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double,
                                      P, P, ctypes.c_int,
                                      P, P, ctypes.c_int64,
@@ -108,14 +109,32 @@ def normals(ra, rb) -> np.ndarray:
     return out
 
 
+def _wgrid(dens):
+    """The nodal samples of a grid density (or None) and its cell count."""
+    if dens.w_grid is None:
+        return None, 0
+    return np.ascontiguousarray(dens.w_grid, dtype=np.float64), dens.w_n
+
+
 def density(dens, tau: float, pts):
     """(w[n], b[n,2]) of a ``workloads.Density`` at PDE time tau."""
     pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 2)
     par = dens.params()
+    wg, wn = _wgrid(dens)
     w = np.zeros(pts.shape[0])
     b = np.zeros_like(pts)
-    lib().or_density_batch(dens.kind, _ptr(par), tau, _ptr(pts), pts.shape[0], _ptr(w), _ptr(b))
+    if lib().or_density_batch(dens.kind, _ptr(par), _ptr(wg), wn, tau, _ptr(pts), pts.shape[0], _ptr(w), _ptr(b)):
+        raise ValueError("oracle rejected the density")
     return w, b
+
+
+def sample_density(dens, tau: float, n: int) -> np.ndarray:
+    """w of an analytic density at the nodes of an n-cell grid, [(n+1), (n+1)]
+    indexed [j, i] with x = i/n, y = j/n."""
+    x = np.arange(n + 1) / n
+    X, Y = np.meshgrid(x, x)
+    w, _ = density(dens, tau, np.stack([X.ravel(), Y.ravel()], 1))
+    return w.reshape(n + 1, n + 1)
 
 
 def n_steps(t: float, dt: float) -> int:
@@ -142,7 +161,8 @@ def fk_solve(dens, data, pts, t, dt, n_paths, seed=0, level_id=0, stream=0,
         gx = np.ascontiguousarray(data.grid_xi, dtype=np.float64)
         gy = np.ascontiguousarray(data.grid_eta, dtype=np.float64)
         gn = data.grid_n
-    rc = lib().or_fk_solve(dens.kind, dens.time_mode, _ptr(par),
+    wg, wn = _wgrid(dens)
+    rc = lib().or_fk_solve(dens.kind, dens.time_mode, _ptr(par), _ptr(wg), wn,
                            data.init_kind, data.bdry_kind, data.score_mode, data.t_init,
                            _ptr(gx), _ptr(gy), gn,
                            _ptr(pts), _ptr(ids), n,
@@ -176,7 +196,8 @@ def fk_paths(dens, data, pts, node_ids, path_ids, t, dt, seed=0, level_id=0, str
         gx = np.ascontiguousarray(data.grid_xi, dtype=np.float64)
         gy = np.ascontiguousarray(data.grid_eta, dtype=np.float64)
         gn = data.grid_n
-    rc = lib().or_fk_paths(dens.kind, dens.time_mode, _ptr(par),
+    wg, wn = _wgrid(dens)
+    rc = lib().or_fk_paths(dens.kind, dens.time_mode, _ptr(par), _ptr(wg), wn,
                            data.init_kind, data.bdry_kind, data.score_mode, data.t_init,
                            _ptr(gx), _ptr(gy), gn, _ptr(pts), _ptr(ids), _ptr(pids), m,
                            t, dt, seed, level_id, stream, threads, _ptr(sc), _ptr(ex))
@@ -218,7 +239,8 @@ def fk_solve_cv(dens, data, pts, t, dt, n_paths, seed=0, level_id=0, stream=0, n
         gx = np.ascontiguousarray(data.grid_xi, dtype=np.float64)
         gy = np.ascontiguousarray(data.grid_eta, dtype=np.float64)
         gn = data.grid_n
-    rc = lib().or_fk_solve_cv(dens.kind, dens.time_mode, _ptr(par),
+    wg, wn = _wgrid(dens)
+    rc = lib().or_fk_solve_cv(dens.kind, dens.time_mode, _ptr(par), _ptr(wg), wn,
                               data.init_kind, data.bdry_kind, data.score_mode, data.t_init,
                               _ptr(gx), _ptr(gy), gn, _ptr(pts), _ptr(ids), n,
                               t, dt, n_paths, seed, level_id, stream, threads,
@@ -237,6 +259,8 @@ def fk_solve_cv(dens, data, pts, t, dt, n_paths, seed=0, level_id=0, stream=0, n
 def fd_solve(dens, data, t, n, dtau, threads=0):
     """Finite-difference (ADI) solution; returns (xi, eta) as [(n+1), (n+1)]
     arrays indexed [j, i] with x = i/n, y = j/n."""
+    if dens.w_grid is not None:
+        raise ValueError("the FD reference takes analytic densities only")
     par = dens.params()
     xi = np.zeros((n + 1) * (n + 1))
     eta = np.zeros_like(xi)

@@ -112,7 +112,16 @@ void or_normals_batch(const uint32_t *ra, const uint32_t *rb, int64_t n, double 
  * Densities w(tau, x, y) and the Winslow drift b = -grad w / w (eq. (6)).
  * par = {amp, width2, cx, cy, orbit_r, omega, t_freeze}.
  * ------------------------------------------------------------------------- */
-enum { K_CONST = 0, K_BUMP = 1, K_MOVING = 2, K_TWO = 3, K_RING = 4, K_RIDGE = 5 };
+enum { K_CONST = 0, K_BUMP = 1, K_MOVING = 2, K_TWO = 3, K_RING = 4, K_RIDGE = 5, K_GRID = 6 };
+
+/* A density: its kind and parameters, and for K_GRID its nodal samples. */
+typedef struct {
+    int kind;
+    const double *par;
+    const double *wg;  /* K_GRID: w at the nodes of an n-cell grid, [(n+1)^2] row-major [j][i], x = i/n */
+    int wn;
+} or_dens;
+
 
 /* w and its gradient, analytically. */
 static void density(int kind, const double *par, double tau, double x, double y,
@@ -178,25 +187,115 @@ static void density(int kind, const double *par, double tau, double x, double y,
     }
 }
 
-static void drift(int kind, const double *par, double tau, double x, double y,
-                  double *bx, double *by)
+/* ---------------------------------------------------------------------------
+ * The paper's data path for w (Sect. 4): w is known only at the nodes of a
+ * grid; the derivatives in grad w are finite differences there and b is
+ * interpolated bilinearly between the nodes.  Readings: central differences
+ * at interior nodes, the second-order one-sided formula on the edges
+ * (f'(0) ~ (-3 f0 + 4 f1 - f2) / 2h), b = -grad w / w at each node, and the
+ * bilinear interpolant of those nodal drifts inside each cell.
+ * ------------------------------------------------------------------------- */
+
+/* Derivative at index i of the n+1 values v[0], v[step], ..., v[n step]
+   spaced h = 1/n apart. */
+static double fd_derivative(const double *v, int n, int i, int64_t step)
 {
+    const double h = 1.0 / n;
+    if (i == 0) return (-3.0 * v[0] + 4.0 * v[step] - v[2 * step]) / (2.0 * h);
+    if (i == n) return (3.0 * v[n * step] - 4.0 * v[(n - 1) * step] + v[(n - 2) * step]) / (2.0 * h);
+    return (v[(i + 1) * step] - v[(i - 1) * step]) / (2.0 * h);
+}
+
+/* b = -grad w / w at grid node (i, j). */
+static void grid_node_drift(const double *wg, int n, int i, int j, double *bx, double *by)
+{
+    const double *row = wg + (int64_t)j * (n + 1);  /* w(., y_j) */
+    const double *col = wg + i;                    /* w(x_i, .) */
+    const double w = row[i];
+    *bx = -fd_derivative(row, n, i, 1) / w;
+    *by = -fd_derivative(col, n, j, n + 1) / w;
+}
+
+/* The cell of point (x, y) in an n-cell grid (the edge cells continued
+   outside) and the local coordinates in it. */
+static void grid_cell(int n, double x, double y, int *i, int *j, double *ax, double *ay)
+{
+    double fx = x * n, fy = y * n;
+    int ci = (int)floor(fx), cj = (int)floor(fy);
+    if (ci < 0) ci = 0;
+    if (ci > n - 1) ci = n - 1;
+    if (cj < 0) cj = 0;
+    if (cj > n - 1) cj = n - 1;
+    *i = ci;
+    *j = cj;
+    *ax = fx - ci;
+    *ay = fy - cj;
+}
+
+static void grid_drift(const double *wg, int n, double x, double y, double *bx, double *by)
+{
+    int i, j;
+    double ax, ay, b[2][2][2];
+    grid_cell(n, x, y, &i, &j, &ax, &ay);
+    for (int dj = 0; dj < 2; ++dj)
+        for (int di = 0; di < 2; ++di) grid_node_drift(wg, n, i + di, j + dj, &b[dj][di][0], &b[dj][di][1]);
+    double out[2];
+    for (int c = 0; c < 2; ++c)
+        out[c] = (1 - ay) * ((1 - ax) * b[0][0][c] + ax * b[0][1][c]) + ay * ((1 - ax) * b[1][0][c] + ax * b[1][1][c]);
+    *bx = out[0];
+    *by = out[1];
+}
+
+/* w itself between the nodes of a grid density: bilinear. */
+static double grid_w(const double *wg, int n, double x, double y)
+{
+    int i, j;
+    double ax, ay;
+    grid_cell(n, x, y, &i, &j, &ax, &ay);
+    const double *r0 = wg + (int64_t)j * (n + 1), *r1 = r0 + (n + 1);
+    return (1 - ay) * ((1 - ax) * r0[i] + ax * r0[i + 1]) + ay * ((1 - ax) * r1[i] + ax * r1[i + 1]);
+}
+
+static void drift(const or_dens *d, double tau, double x, double y, double *bx, double *by)
+{
+    if (d->kind == K_GRID) {
+        grid_drift(d->wg, d->wn, x, y, bx, by);
+        return;
+    }
     double w, wx, wy;
-    density(kind, par, tau, x, y, &w, &wx, &wy);
+    density(d->kind, d->par, tau, x, y, &w, &wx, &wy);
     *bx = -wx / w;
     *by = -wy / w;
 }
 
-void or_density_batch(int kind, const double *par, double tau, const double *pts, int64_t n,
-                      double *w, double *b)
+static int dens_bind(or_dens *d, int kind, const double *par, const double *wg, int wn)
 {
+    d->kind = kind;
+    d->par = par;
+    d->wg = wg;
+    d->wn = wn;
+    if (kind < K_CONST || kind > K_GRID) return -1;
+    if (kind == K_GRID && (!wg || wn < 2)) return -1;
+    return 0;
+}
+
+/* w and b at n points; w_grid / w_n are read for kind 6 only. */
+int or_density_batch(int kind, const double *par, const double *w_grid, int w_n, double tau,
+                     const double *pts, int64_t n, double *w, double *b)
+{
+    or_dens d;
+    if (dens_bind(&d, kind, par, w_grid, w_n) != 0) return -1;
     for (int64_t i = 0; i < n; ++i) {
-        double ww, wx, wy;
-        density(kind, par, tau, pts[2 * i], pts[2 * i + 1], &ww, &wx, &wy);
-        w[i] = ww;
-        b[2 * i] = -wx / ww;
-        b[2 * i + 1] = -wy / ww;
+        const double x = pts[2 * i], y = pts[2 * i + 1];
+        if (kind == K_GRID) {
+            w[i] = grid_w(w_grid, w_n, x, y);
+        } else {
+            double wx, wy;
+            density(kind, par, tau, x, y, &w[i], &wx, &wy);
+        }
+        drift(&d, tau, x, y, &b[2 * i], &b[2 * i + 1]);
     }
+    return 0;
 }
 
 /* ---------------------------------------------------------------------------
@@ -267,6 +366,7 @@ static void boundary_value(const or_data *d, double elapsed, double x, double y,
 typedef struct {
     int kind, time_mode;
     const double *par;
+    or_dens dens;
     or_data data;
     double t_init, t, dt;
     int64_t K;
@@ -290,7 +390,7 @@ static int64_t run_path(const or_problem *pb, double px, double py, uint32_t pat
         double D = (k == pb->K - 1) ? pb->t - (double)(pb->K - 1) * pb->dt : pb->dt;
         double tau = (pb->time_mode == 0) ? pb->t_init + pb->t - s : pb->par[6];
         double bx, by;
-        drift(pb->kind, pb->par, tau, x, y, &bx, &by);
+        drift(&pb->dens, tau, x, y, &bx, &by);
         double sd = sqrt(2.0 * D);
         x = x + bx * D + sd * z0;
         y = y + by * D + sd * z1;
@@ -322,7 +422,7 @@ int64_t or_n_steps(double t, double dt) { return n_steps(t, dt); }
  *   steps      [n_nodes] or NULL      Euler-Maruyama steps taken in total
  * Returns 0, or -1 on bad arguments.
  */
-int or_fk_solve(int kind, int time_mode, const double *par,
+int or_fk_solve(int kind, int time_mode, const double *par, const double *w_grid, int w_n,
                 int init_kind, int bdry_kind, int score_mode, double t_init,
                 const double *grid_xi, const double *grid_eta, int grid_n,
                 const double *pts, const int64_t *node_ids, int64_t n_nodes,
@@ -335,6 +435,7 @@ int or_fk_solve(int kind, int time_mode, const double *par,
     pb.kind = kind;
     pb.time_mode = time_mode;
     pb.par = par;
+    if (dens_bind(&pb.dens, kind, par, w_grid, w_n) != 0) return -1;
     pb.data.init_kind = init_kind;
     pb.data.bdry_kind = bdry_kind;
     pb.data.score_mode = score_mode;
@@ -403,7 +504,7 @@ int or_fk_solve(int kind, int time_mode, const double *par,
  * out of reach: path path_ids[j] of the node at pts[j] with counter word 2
  * node_ids[j].  Outputs the scores [m][2] and exit steps [m] (-1 = survived).
  */
-int or_fk_paths(int kind, int time_mode, const double *par,
+int or_fk_paths(int kind, int time_mode, const double *par, const double *w_grid, int w_n,
                 int init_kind, int bdry_kind, int score_mode, double t_init,
                 const double *grid_xi, const double *grid_eta, int grid_n,
                 const double *pts, const int64_t *node_ids, const int64_t *path_ids, int64_t m,
@@ -415,6 +516,7 @@ int or_fk_paths(int kind, int time_mode, const double *par,
     pb.kind = kind;
     pb.time_mode = time_mode;
     pb.par = par;
+    if (dens_bind(&pb.dens, kind, par, w_grid, w_n) != 0) return -1;
     pb.data.init_kind = init_kind;
     pb.data.bdry_kind = bdry_kind;
     pb.data.score_mode = score_mode;
@@ -621,7 +723,7 @@ static int64_t run_path_cv(const or_problem *pb, const or_uhat *u, int stride, d
         double D = (k == pb->K - 1) ? pb->t - (double)(pb->K - 1) * pb->dt : pb->dt;
         double tau = (pb->time_mode == 0) ? pb->t_init + pb->t - s : pb->par[6];
         double bx, by;
-        drift(pb->kind, pb->par, tau, x, y, &bx, &by);
+        drift(&pb->dens, tau, x, y, &bx, &by);
         if (k % stride == 0) {
             /* close the previous interval (trapezoidal rule), open a new one */
             double e[2][5];
@@ -649,7 +751,7 @@ static int64_t run_path_cv(const or_problem *pb, const or_uhat *u, int stride, d
     const double tau_end = pb->t_init + pb->t - s;
     uhat_eval(u, tau_end, x, y, e);
     double bx, by;
-    drift(pb->kind, pb->par, (pb->time_mode == 0) ? tau_end : pb->par[6], x, y, &bx, &by);
+    drift(&pb->dens, (pb->time_mode == 0) ? tau_end : pb->par[6], x, y, &bx, &by);
     for (int c = 0; c < 2; ++c) {
         double rn = e[c][4] + bx * e[c][1] + by * e[c][2] - e[c][3];
         integ[c] += 0.5 * (rlast[c] + rn) * (s - s_last);
@@ -686,7 +788,7 @@ static int64_t run_path_mg(const or_problem *pb, const or_uhat *u, int stride, d
         double D = (k == pb->K - 1) ? pb->t - (double)(pb->K - 1) * pb->dt : pb->dt;
         double tau = (pb->time_mode == 0) ? pb->t_init + pb->t - s : pb->par[6];
         double bx, by;
-        drift(pb->kind, pb->par, tau, x, y, &bx, &by);
+        drift(&pb->dens, tau, x, y, &bx, &by);
         if (k % stride == 0) {
             double e[2][5];
             for (int c = 0; c < 2; ++c) M[c] += G[c][0] * dB[0] + G[c][1] * dB[1];
@@ -739,7 +841,7 @@ static void two_pass(const double *sc, int64_t i, int64_t n_paths, double *mean,
  * (martingale): mean(cv score).  plain_mean/plain_se: the plain estimate from
  * the same paths.  cv_scores [n][N][2] and exit_step [n][N] optional.
  */
-int or_fk_solve_cv(int kind, int time_mode, const double *par,
+int or_fk_solve_cv(int kind, int time_mode, const double *par, const double *w_grid, int w_n,
                    int init_kind, int bdry_kind, int score_mode, double t_init,
                    const double *grid_xi, const double *grid_eta, int grid_n,
                    const double *pts, const int64_t *node_ids, int64_t n_nodes,
@@ -756,6 +858,7 @@ int or_fk_solve_cv(int kind, int time_mode, const double *par,
     pb.kind = kind;
     pb.time_mode = time_mode;
     pb.par = par;
+    if (dens_bind(&pb.dens, kind, par, w_grid, w_n) != 0) return -1;
     pb.data.init_kind = init_kind;
     pb.data.bdry_kind = bdry_kind;
     pb.data.score_mode = score_mode;

@@ -46,7 +46,17 @@ def _edge_equidistribution(dens, t_w, s, edge, horizontal):
         return float(_oracle.density(dens, t_w, p)[0][0])
 
     kw = dict(epsabs=1e-14, epsrel=1e-13, limit=400)
-    return si.quad(w, 0.0, s, **kw)[0] / si.quad(w, 0.0, 1.0, **kw)[0]
+    if dens.w_grid is None:
+        return si.quad(w, 0.0, s, **kw)[0] / si.quad(w, 0.0, 1.0, **kw)[0]
+    # a grid density is piecewise linear along the edge: split at its nodes
+    n = dens.w_n
+    kw["limit"] = max(400, 8 * n)
+
+    def integral(b):
+        brk = [k / n for k in range(1, n) if k / n < b]
+        return si.quad(w, 0.0, b, points=brk or None, **kw)[0]
+
+    return integral(s) / integral(1.0)
 
 
 def boundary_grid(N, bdry: str = "identity", dens=None, t_w=0.0):

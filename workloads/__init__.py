@@ -32,6 +32,7 @@ KIND_MOVING_BUMP = 2  # centre (cx + R cos(omega tau), cy + R sin(omega tau))
 KIND_TWO_BUMPS = 3    # second centre mirrored in x: (cx - R cos(omega tau), cy + R sin(omega tau))
 KIND_RING = 4         # the paper's w = 1/rho moving ring (Sect. 5); amp = alpha, width2 = beta
 KIND_RIDGE = 5        # w = 1 + A exp(-(x - cx)^2 / s2): depends on x only
+KIND_GRID = 6         # w known at the nodes of a grid only (Sect. 4): samples in Density.w_grid
 
 # Which time argument the density takes along a path.
 TIME_BACKWARD = 0     # w(t_init + t - s): the Feynman-Kac time reversal
@@ -67,6 +68,11 @@ class Density:
     orbit_r: float = 0.0
     omega: float = 0.0
     t_freeze: float = 0.0
+    w_grid: np.ndarray | None = field(default=None, compare=False)   # KIND_GRID: [(n+1), (n+1)] [j, i]
+
+    @property
+    def w_n(self) -> int:
+        return 0 if self.w_grid is None else int(self.w_grid.shape[0]) - 1
 
     def params(self) -> np.ndarray:
         """The 7 real parameters in the order both implementations read them."""
