@@ -55,6 +55,11 @@ extern "C" {
 #define FK_DENSITY_RING 4         /* w = 1/rho, rho = 1 + amp exp(width2 |r^2 - 1/100|), r the distance to
                                      the moving centre: the paper's ring (Sect. 5; amp = alpha, width2 = beta) */
 #define FK_DENSITY_RIDGE 5        /* w = 1 + amp exp(-(x - cx)^2 / width2) */
+#define FK_DENSITY_GRID 6         /* w known only at the nodes of a grid (Sect. 4): samples grid_w; grad w by
+                                     finite differences at the nodes (central inside, second-order one-sided
+                                     on the edges), b = -grad w / w there, and b bilinear between the nodes
+                                     (table grid_b from fk_density_grid_drift).  Static: the time mode and
+                                     the analytic parameters are ignored */
 
 /* Time argument of w along a path. */
 #define FK_TIME_BACKWARD 0  /* w(t_init + t - s): the time reversal of the Feynman-Kac formula (eq. (5)) */
@@ -79,11 +84,19 @@ extern "C" {
                                  extended by the grid's own normal slope (a first-order correction of the
                                  overshoot of the discrete exit test); needs grid initial data */
 
-/* Density parameters (plain values). */
+/* Density parameters (plain values; for FK_DENSITY_GRID also two device arrays). */
 typedef struct fk_density {
     int32_t kind;       /* FK_DENSITY_* */
     int32_t time_mode;  /* FK_TIME_* */
     double amp, width2, cx, cy, orbit_r, omega, t_freeze;
+    /* FK_DENSITY_GRID only (0 / NULL otherwise): */
+    int32_t grid_n;          /* grid cells per side, >= 2 */
+    int32_t grid_reserved;   /* 0 */
+    const double *grid_w;    /* device [(grid_n+1)^2] FP64 samples of w (> 0), row-major [j][i] at
+                                (i/grid_n, j/grid_n) */
+    const float *grid_b;     /* device [(grid_n+1)^2][2] FP32 nodal drift (b_x, b_y) of grid_w, written by
+                                fk_density_grid_drift; 8-byte aligned.  Both arrays are read by every call
+                                that takes the density and must stay unchanged until those calls finish */
 } fk_density;
 
 /* Initial and boundary data. */
@@ -104,6 +117,37 @@ typedef struct fk_plan {
     int32_t chunk;          /* paths handed to a wavefront per queue grab (>= 1) */
     int32_t reserved;
 } fk_plan;
+
+/*
+ * Samples of an analytic density at the nodes of an n-cell grid (for the
+ * grid data path of Sect. 4: w available at grid points only).
+ *
+ *   w      analytic density (kind FK_DENSITY_CONST .. FK_DENSITY_RIDGE)
+ *   tau    PDE time at which w is sampled (the time mode is ignored)
+ *   n      cells per side, >= 1
+ *   w_out  device [(n+1)^2] FP64, row-major [j][i]: w(tau, i/n, j/n)
+ *
+ * FK_E_INVAL for a grid density, n < 1 or NULL output.
+ */
+int fk_density_sample(const fk_density *w, double tau, int32_t n, double *w_out, hipStream_t stream);
+
+/*
+ * Nodal drift table of a grid density (Sect. 4: the derivatives in grad w
+ * are approximated by finite differences at the grid points): at node
+ * (i, j), w_x by the central difference (w[i+1] - w[i-1]) / 2h for
+ * 0 < i < n and by the second-order one-sided differences
+ * (-3 w[0] + 4 w[1] - w[2]) / 2h, (3 w[n] - 4 w[n-1] + w[n-2]) / 2h on the
+ * edges (the same in y), h = 1/n; b = -grad w / w, computed in FP64 and
+ * stored as FP32 pairs.
+ *
+ *   grid_w  device [(n+1)^2] FP64 samples, row-major [j][i]
+ *   n       cells per side, >= 2
+ *   grid_b  device [(n+1)^2][2] FP32, 8-byte aligned (output)
+ *
+ * FK_E_INVAL for n < 2, NULL or misaligned arrays.  Samples <= 0 give
+ * non-finite or sign-flipped drifts: the caller supplies w > 0.
+ */
+int fk_density_grid_drift(const double *grid_w, int32_t n, float *grid_b, hipStream_t stream);
 
 /*
  * Bytes of device workspace fk_interface_solve needs for n_nodes x n_paths
@@ -208,7 +252,12 @@ void fk_batch_destroy(fk_batch_t b);
  *   (u - u^n)/dt_mesh = Laplacian_h u + b . grad_h u,  b = -grad w / w.
  * Each sub-domain system is solved by banded LU without pivoting, in FP64;
  * xi and eta share the factorisation.  Requires |b| h / 2 < 1 (checked from
- * the density's bound; FK_E_UNSUPPORTED otherwise) and m - 1 < 128.
+ * the density's bound; FK_E_UNSUPPORTED otherwise) and m - 1 < 128.  A grid
+ * density (FK_DENSITY_GRID) must be sampled on this mesh's grid
+ * (grid_n == N, else FK_E_INVAL): its FP64 finite-difference drift is taken
+ * at the nodes, the equidistributed edge data integrates w as linear between
+ * the nodes, and |b| h / 2 = |w[i+1] - w[i-1]| / (4 w[i]) < 1 is the
+ * caller's to ensure (the samples stay in device memory).
  *   xi_n, eta_n        device [(N+1)^2] FP64, row-major [j][i]: the mesh at t^n
  *   iface_xi/eta       device FP64, interface nodes in canonical order
  *                      (vertical lines x = a/px with y = j/N ascending, then

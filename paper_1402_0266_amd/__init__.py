@@ -47,7 +47,8 @@ class fk_density(ctypes.Structure):
     _fields_ = [("kind", ctypes.c_int32), ("time_mode", ctypes.c_int32),
                 ("amp", ctypes.c_double), ("width2", ctypes.c_double), ("cx", ctypes.c_double),
                 ("cy", ctypes.c_double), ("orbit_r", ctypes.c_double), ("omega", ctypes.c_double),
-                ("t_freeze", ctypes.c_double)]
+                ("t_freeze", ctypes.c_double), ("grid_n", ctypes.c_int32), ("grid_reserved", ctypes.c_int32),
+                ("grid_w", ctypes.c_void_p), ("grid_b", ctypes.c_void_p)]
 
 
 class fk_data(ctypes.Structure):
@@ -109,6 +110,10 @@ _lib.subdomain_workspace_bytes.restype = ctypes.c_size_t
 _lib.subdomain_solve.argtypes = [ctypes.POINTER(fk_density), ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                  ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
 _lib.subdomain_solve.restype = ctypes.c_int
+_lib.fk_density_sample.argtypes = [ctypes.POINTER(fk_density), ctypes.c_double, ctypes.c_int32, _P, _P]
+_lib.fk_density_sample.restype = ctypes.c_int
+_lib.fk_density_grid_drift.argtypes = [_P, ctypes.c_int32, _P, _P]
+_lib.fk_density_grid_drift.restype = ctypes.c_int
 _lib.fk_mesh_quality.argtypes = [_P, _P, ctypes.c_int32, _P, _P]
 _lib.fk_mesh_quality.restype = ctypes.c_int
 _lib.fk_cv_create.argtypes = [_P, ctypes.c_double, ctypes.POINTER(_P)]
@@ -167,9 +172,60 @@ def fk_last_error() -> str:
     return _lib.fk_last_error().decode()
 
 
+FK_DENSITY_GRID = 6
+
+
 def _density(d) -> fk_density:
+    """fk_density of an object with its fields; a grid density (``GridDensity``)
+    carries the device samples and drift table."""
+    if int(d.kind) == FK_DENSITY_GRID:
+        return fk_density(FK_DENSITY_GRID, 0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, int(d.grid_n), 0,
+                          d.grid_w.data_ptr(), d.grid_b.data_ptr())
     return fk_density(int(d.kind), int(d.time_mode), float(d.amp), float(d.width2), float(d.cx),
                       float(d.cy), float(d.orbit_r), float(d.omega), float(d.t_freeze))
+
+
+def fk_density_sample(density, tau: float, n: int, device=None, out=None):
+    """w of an analytic density at the nodes of an n-cell grid: device FP64
+    [(n+1), (n+1)] indexed [j, i] (x = i/n, y = j/n), into `out` if given."""
+    import torch
+    if out is None:
+        out = torch.empty((n + 1, n + 1), dtype=torch.float64, device=device or "cuda")
+    elif out.dtype != torch.float64 or out.shape != (n + 1, n + 1) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous [(n+1), (n+1)] FP64 tensor")
+    w = _density(density)
+    _check(_lib.fk_density_sample(ctypes.byref(w), float(tau), int(n), out.data_ptr(), _stream(torch, out.device)))
+    return out
+
+
+def fk_density_grid_drift(grid_w, out=None):
+    """Nodal finite-difference drift table of device samples grid_w
+    [(n+1), (n+1)] FP64: device FP32 [(n+1), (n+1), 2], into `out` if given."""
+    import torch
+    n = grid_w.shape[0] - 1
+    if grid_w.dtype != torch.float64 or grid_w.shape != (n + 1, n + 1) or not grid_w.is_contiguous():
+        raise ValueError("grid_w must be a contiguous square FP64 tensor")
+    if out is None:
+        out = torch.empty((n + 1, n + 1, 2), dtype=torch.float32, device=grid_w.device)
+    elif out.dtype != torch.float32 or out.shape != (n + 1, n + 1, 2) or not out.is_contiguous():
+        raise ValueError("out must be a contiguous [(n+1), (n+1), 2] FP32 tensor")
+    _check(_lib.fk_density_grid_drift(grid_w.data_ptr(), int(n), out.data_ptr(), _stream(torch, grid_w.device)))
+    return out
+
+
+class GridDensity:
+    """A density known only at grid nodes (Sect. 4): device FP64 samples
+    ``grid_w`` [(n+1), (n+1)] and their drift table ``grid_b`` (computed here
+    by ``fk_density_grid_drift``).  The tensors must outlive the calls that
+    use the density."""
+    kind = FK_DENSITY_GRID
+    time_mode = 0
+
+    def __init__(self, grid_w, grid_b=None):
+        import torch
+        self.grid_w = grid_w.to(torch.float64).contiguous()
+        self.grid_n = int(self.grid_w.shape[0]) - 1
+        self.grid_b = fk_density_grid_drift(self.grid_w, out=grid_b)
 
 
 def _data(d, grids=None) -> fk_data:

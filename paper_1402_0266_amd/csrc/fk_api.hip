@@ -40,7 +40,8 @@ int64_t step_count(double t, double dt) {
 
 static bool kind_supported(int32_t kind) {
     return kind == FK_DENSITY_CONST || kind == FK_DENSITY_BUMP || kind == FK_DENSITY_MOVING_BUMP ||
-           kind == FK_DENSITY_TWO_BUMPS || kind == FK_DENSITY_RING || kind == FK_DENSITY_RIDGE;
+           kind == FK_DENSITY_TWO_BUMPS || kind == FK_DENSITY_RING || kind == FK_DENSITY_RIDGE ||
+           kind == FK_DENSITY_GRID;
 }
 
 int validate_density(const fk_density *w) {
@@ -51,7 +52,11 @@ int validate_density(const fk_density *w) {
     const double v[] = {w->amp, w->width2, w->cx, w->cy, w->orbit_r, w->omega, w->t_freeze};
     for (double x : v)
         if (!std::isfinite(x)) return fail(FK_E_INVAL, "density parameter is not finite");
-    if (w->kind == FK_DENSITY_RING) {
+    if (w->kind == FK_DENSITY_GRID) {
+        if (w->grid_n < 2 || w->grid_n > 65535) return fail(FK_E_INVAL, "grid density needs 2 <= grid_n <= 65535");
+        if (!w->grid_w || !w->grid_b) return fail(FK_E_INVAL, "grid density needs grid_w and grid_b");
+        if (((uintptr_t)w->grid_b & 7u) != 0) return fail(FK_E_INVAL, "grid_b must be 8-byte aligned");
+    } else if (w->kind == FK_DENSITY_RING) {
         if (!(w->amp >= 0.0)) return fail(FK_E_INVAL, "ring amplitude (alpha) must be >= 0");
         if (!(w->width2 <= 0.0)) return fail(FK_E_INVAL, "ring exponent (beta) must be <= 0");
     } else if (w->kind != FK_DENSITY_CONST) {
@@ -151,6 +156,12 @@ LevelDev make_level(const fk_density *w, double t_init, double t, double dt, uin
     L.drev = (float)(dt * orev);
     L.cos_d = (float)std::cos(dt * w->omega);
     L.sin_d = (float)std::sin(dt * w->omega);
+    if (w->kind == FK_DENSITY_GRID) {
+        L.gb = (const float2 *)w->grid_b;
+        L.gn = w->grid_n;
+        L.fn = (float)w->grid_n;
+        L.nscale = L.a2s = 0.f;
+    }
     return L;
 }
 

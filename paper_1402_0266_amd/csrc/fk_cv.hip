@@ -1188,6 +1188,7 @@ auto cv_dispatch(int kind, int time_mode, bool uniform, Args &&...args) {
     case KIND_CONST: FK_CV_CASE(KIND_CONST, TIME_BACKWARD);
     case KIND_BUMP: FK_CV_CASE(KIND_BUMP, TIME_BACKWARD);
     case KIND_RIDGE: FK_CV_CASE(KIND_RIDGE, TIME_BACKWARD);
+    case KIND_GRID: FK_CV_CASE(KIND_GRID, TIME_BACKWARD);
     case KIND_MOVING:
         if (frozen) FK_CV_CASE(KIND_MOVING, TIME_FROZEN);
         FK_CV_CASE(KIND_MOVING, TIME_BACKWARD);

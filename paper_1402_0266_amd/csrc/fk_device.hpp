@@ -70,7 +70,7 @@ __device__ __forceinline__ void brownian_increment(uint32_t ra, uint32_t rb, flo
 // Densities and the Winslow drift b = -grad w / w (eq. (6)).  For a Gaussian
 // bump w = 1 + A e, e = exp(-|X - c|^2 / s2):  b = (2 A / s2) e / w * (X - c).
 // ---------------------------------------------------------------------------
-enum : int { KIND_CONST = 0, KIND_BUMP = 1, KIND_MOVING = 2, KIND_TWO = 3, KIND_RING = 4, KIND_RIDGE = 5 };
+enum : int { KIND_CONST = 0, KIND_BUMP = 1, KIND_MOVING = 2, KIND_TWO = 3, KIND_RING = 4, KIND_RIDGE = 5, KIND_GRID = 6 };
 
 // Kinds whose centre moves on the orbit (R cos(omega tau), R sin(omega tau)).
 constexpr bool moving_kind(int k) { return k == KIND_MOVING || k == KIND_TWO || k == KIND_RING; }
@@ -80,6 +80,9 @@ struct DensityRegs {
     float amp, nscale, a2s;
     float cx, cy;        // centre (static) / orbit centre
     float orbit_r, omega_rev;
+    const float2 *gb;    // grid density: nodal drift table, row-major [j][i]
+    int gn;              // grid density: cells per side
+    float fn;            // (float) gn
 };
 
 // Bump centre offset (R cos(omega tau), R sin(omega tau)).
@@ -126,6 +129,21 @@ __device__ __forceinline__ void drift(const DensityRegs &d, float ox, float oy, 
         const float f = sg * e * d.a2s * hw_rcp(fmaf(d.amp, e, 1.f));
         bx = f * dx;
         by = f * dy;
+    } else if constexpr (KIND == KIND_GRID) {
+        // w known at grid nodes only (Sect. 4): the nodal drifts of the
+        // finite-difference table, bilinear in the cell.  The cell index is
+        // clamped, so a point outside the square (a Dynkin-form end point)
+        // takes the edge cell's bilinear function continued.
+        const float fx = x * d.fn, fy = y * d.fn;
+        const int i = min(max((int)floorf(fx), 0), d.gn - 1);
+        const int j = min(max((int)floorf(fy), 0), d.gn - 1);
+        const float ax = fx - (float)i, ay = fy - (float)j;
+        const float2 *r0 = d.gb + (j * (d.gn + 1) + i);
+        const float2 b00 = r0[0], b01 = r0[1], b10 = r0[d.gn + 1], b11 = r0[d.gn + 2];
+        const float lx0 = fmaf(ax, b01.x - b00.x, b00.x), lx1 = fmaf(ax, b11.x - b10.x, b10.x);
+        const float ly0 = fmaf(ax, b01.y - b00.y, b00.y), ly1 = fmaf(ax, b11.y - b10.y, b10.y);
+        bx = fmaf(ay, lx1 - lx0, lx0);
+        by = fmaf(ay, ly1 - ly0, ly0);
     } else {  // KIND_RIDGE: depends on x only
         const float dx = x - d.cx;
         const float e = hw_exp2(dx * dx * d.nscale);

@@ -33,6 +33,9 @@ struct alignas(16) LevelDev {
     float rev0;        // (t_init + t) omega_rev: orbit angle at path start, in revolutions
     float drev;        // dt omega_rev: orbit angle step
     float cos_d, sin_d;  // cos / sin of the orbit angle step (2 pi drev)
+    const float2 *gb;  // grid density: nodal drift table [(gn+1)^2], else nullptr
+    int32_t gn;        // grid density: cells per side
+    float fn;          // (float) gn
 };
 
 // One interface node, in launch (cost-sorted) order.

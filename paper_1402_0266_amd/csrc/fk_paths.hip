@@ -166,6 +166,7 @@ auto dispatch(int kind, int time_mode, bool uniform, Args &&...args) {
     case KIND_CONST: FK_CASE(KIND_CONST, TIME_BACKWARD);
     case KIND_BUMP: FK_CASE(KIND_BUMP, TIME_BACKWARD);
     case KIND_RIDGE: FK_CASE(KIND_RIDGE, TIME_BACKWARD);
+    case KIND_GRID: FK_CASE(KIND_GRID, TIME_BACKWARD);
     case KIND_MOVING:
         if (frozen) FK_CASE(KIND_MOVING, TIME_FROZEN);
         FK_CASE(KIND_MOVING, TIME_BACKWARD);
@@ -194,14 +195,14 @@ struct OccF {
 hipError_t launch_paths(int kind, int time_mode, bool uniform, const PathArgs &a, int grid, int block,
                         hipStream_t s) {
     if (kind != KIND_CONST && kind != KIND_BUMP && kind != KIND_RIDGE && kind != KIND_MOVING && kind != KIND_TWO &&
-        kind != KIND_RING)
+        kind != KIND_RING && kind != KIND_GRID)
         return hipErrorInvalidValue;
     return dispatch<LaunchF>(kind, time_mode, uniform, a, grid, block, s);
 }
 
 int path_kernel_max_blocks_per_cu(int kind, int time_mode, bool uniform, int block) {
     if (kind != KIND_CONST && kind != KIND_BUMP && kind != KIND_RIDGE && kind != KIND_MOVING && kind != KIND_TWO &&
-        kind != KIND_RING)
+        kind != KIND_RING && kind != KIND_GRID)
         return 0;
     return dispatch<OccF>(kind, time_mode, uniform, block);
 }

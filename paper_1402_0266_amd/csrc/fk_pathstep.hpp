@@ -115,6 +115,11 @@ __device__ __forceinline__ void lane_start(Lane &L, const NodeDev &nd, const Lev
     L.dens.cy = lv.cy;
     L.dens.orbit_r = lv.orbit_r;
     L.dens.omega_rev = lv.omega_rev;
+    if constexpr (KIND == KIND_GRID) {
+        L.dens.gb = lv.gb;
+        L.dens.gn = lv.gn;
+        L.dens.fn = lv.fn;
+    }
     L.ox = 0.f;
     L.oy = 0.f;
     if constexpr (moving_kind(KIND) && TMODE == TIME_FROZEN) {

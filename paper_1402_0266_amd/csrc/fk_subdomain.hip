@@ -42,7 +42,39 @@ struct SubArgs {
     double c, half_d_over_h;     // D/h^2 and D/(2h)
     int kind;
     double amp, width2, cx, cy, orbit_r, omega, t_w;
+    const double *wg;            // FK_DENSITY_GRID: samples of w on this grid, (N+1)^2
 };
+
+// ---------------------------------------------------------------------------
+// Grid densities (Sect. 4: w known at the grid points only; the derivatives
+// in grad w by finite differences).  h = 1/n; central differences at interior
+// nodes, second-order one-sided differences on the edges.
+// ---------------------------------------------------------------------------
+// d/ds of the samples v[0], v[stride], ..., v[n stride] at index i.
+__device__ double grid_fd(const double *v, int n, int i, int stride) {
+    const double inv2h = 0.5 * n;
+    if (i == 0) return (4.0 * v[stride] - 3.0 * v[0] - v[2 * stride]) * inv2h;
+    if (i == n) return (3.0 * v[n * stride] - 4.0 * v[(n - 1) * stride] + v[(n - 2) * stride]) * inv2h;
+    return (v[(i + 1) * stride] - v[(i - 1) * stride]) * inv2h;
+}
+
+// b = -grad w / w at node (i, j) of the n-cell grid of samples wg.
+__device__ void grid_node_drift_f64(const double *wg, int n, int i, int j, double &bx, double &by) {
+    const double *row = wg + (int64_t)j * (n + 1);
+    const double inv_w = 1.0 / row[i];
+    bx = -grid_fd(row, n, i, 1) * inv_w;
+    by = -grid_fd(wg + i, n, j, n + 1) * inv_w;
+}
+
+// Nodal drift table of a grid density, FP32 pairs.
+__global__ void grid_drift_kernel(const double *wg, int n, float2 *b) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n1 = n + 1;
+    if (t >= n1 * n1) return;
+    double bx, by;
+    grid_node_drift_f64(wg, n, (int)(t % n1), (int)(t / n1), bx, by);
+    b[t] = make_float2((float)bx, (float)by);
+}
 
 // -grad w / w in FP64 at (x, y), density frozen at t_w.
 __device__ void drift_f64(const SubArgs &a, double x, double y, double &bx, double &by) {
@@ -85,6 +117,16 @@ __device__ void drift_f64(const SubArgs &a, double x, double y, double &bx, doub
     by = f * dy;
 }
 
+// Drift at grid node (gi, gj) of the mesh: the finite-difference drift of a
+// grid density, else the analytic drift at (gi/N, gj/N).
+__device__ void node_drift_f64(const SubArgs &a, int gi, int gj, double &bx, double &by) {
+    if (a.kind == FK_DENSITY_GRID) {
+        grid_node_drift_f64(a.wg, a.N, gi, gj, bx, by);
+        return;
+    }
+    drift_f64(a, (double)gi / a.N, (double)gj / a.N, bx, by);  // i/N exactly, as the grid is defined
+}
+
 constexpr int kMaxP1 = 128;  // window side limit: q <= 127 interior nodes per side
 
 // The density w in FP64 at (x, y), frozen at t_w.
@@ -119,6 +161,14 @@ __global__ void edge_cells_kernel(const SubArgs a, double *cells) {
     const int e = t / N, c = t % N;
     const bool horizontal = e < 2;
     const double fixed = (e == 1 || e == 3) ? 1.0 : 0.0;
+    if (a.kind == FK_DENSITY_GRID) {
+        // samples along the edge; w is linear between them: trapezoid, exact
+        const int64_t N1 = N + 1;
+        const int64_t at = horizontal ? (e == 1 ? (int64_t)N * N1 : 0) + c : (int64_t)c * N1 + (e == 3 ? N : 0);
+        const int64_t next = horizontal ? 1 : N1;
+        cells[t] = 0.5 * (a.wg[at] + a.wg[at + next]) / N;
+        return;
+    }
     const double u0 = (double)c / N, hq = 1.0 / ((double)N * M);
     double acc = 0.0;
     for (int i = 0; i <= M; ++i) {
@@ -127,6 +177,14 @@ __global__ void edge_cells_kernel(const SubArgs a, double *cells) {
         acc += w * ((i == 0 || i == M) ? 1.0 : ((i & 1) ? 4.0 : 2.0));
     }
     cells[t] = acc * hq / 3.0;
+}
+
+// w(t_w, i/n, j/n) at the nodes of an n-cell grid.
+__global__ void density_sample_kernel(const SubArgs a, int n, double *out) {
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n1 = n + 1;
+    if (t >= n1 * n1) return;
+    out[t] = density_f64(a, (double)(t % n1) / n, (double)(t / n1) / n);
 }
 
 // int_0^{i/N} w / int_0^1 w along edge e, from the cell integrals (summed in
@@ -255,7 +313,7 @@ __global__ void __launch_bounds__(256) subdomain_lu_kernel(const SubArgs a) {
         const int ii = r % q, jj = r / q;
         const int gi = i0 + 1 + ii, gj = j0 + 1 + jj;
         double bx, by;
-        drift_f64(a, (double)gi / a.N, (double)gj / a.N, bx, by);  // i/N exactly, as the grid is defined
+        node_drift_f64(a, gi, gj, bx, by);
         const double cxr = a.half_d_over_h * bx, cyr = a.half_d_over_h * by;
         const double cE = -a.c - cxr, cW = -a.c + cxr, cN = -a.c - cyr, cS = -a.c + cyr;
         const int64_t g = (int64_t)gj * N1 + gi;
@@ -432,7 +490,7 @@ __global__ void __launch_bounds__(256) subdomain_be_kernel(const SubArgs a) {
         const int ii = r % q, jj = r / q;
         const int gi = i0 + 1 + ii, gj = j0 + 1 + jj;
         double bx, by;
-        drift_f64(a, (double)gi / a.N, (double)gj / a.N, bx, by);  // i/N exactly, as the grid is defined
+        node_drift_f64(a, gi, gj, bx, by);
         const double cxr = a.half_d_over_h * bx, cyr = a.half_d_over_h * by;
         const int s = r % P1;
         kx[s] = cxr;
@@ -717,6 +775,8 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
     if (!workspace || workspace_bytes < need) return fail(FK_E_NOMEM, "workspace too small: need %zu bytes", need);
     if (((uintptr_t)workspace & 255u) != 0) return fail(FK_E_INVAL, "workspace must be 256-byte aligned");
     const double h = 1.0 / N;
+    if (w->kind == FK_DENSITY_GRID && w->grid_n != N)
+        return fail(FK_E_INVAL, "a grid density must be sampled on the mesh grid (grid_n %d != N %d)", w->grid_n, N);
     // Diagonal dominance (LU without pivoting) needs |b| h / 2 < 1.  For one
     // bump |b| = (2A/s2) r e / (1 + A e), e = exp(-r^2/s2), maximised over r
     // on a fine sample; two bumps are bounded by twice that.  For the ring
@@ -730,7 +790,7 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
             bmax = std::max(bmax, 2.0 * A * std::fabs(be) * r * e / (1.0 + A * e));
         }
         if (bmax * h / 2.0 >= 1.0) return fail(FK_E_UNSUPPORTED, "grid too coarse for the drift (|b| h / 2 >= 1)");
-    } else if (w->kind != FK_DENSITY_CONST) {
+    } else if (w->kind != FK_DENSITY_CONST && w->kind != FK_DENSITY_GRID) {
         double bmax = 0.0;
         const double A = std::fabs(w->amp), s2 = w->width2, rs = 4.0 * std::sqrt(s2);
         for (int i = 1; i <= 4000; ++i) {
@@ -774,6 +834,7 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
     a.orbit_r = w->orbit_r;
     a.omega = w->omega;
     a.t_w = t_w;
+    a.wg = w->kind == FK_DENSITY_GRID ? w->grid_w : nullptr;
     if (bdry_kind == FK_DATA_EQUIDISTRIBUTED) {
         hipLaunchKernelGGL(edge_cells_kernel, dim3((unsigned)((4 * N + 255) / 256)), dim3(256), 0, stream, a,
                            edge_cells);
@@ -795,6 +856,40 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
     hipLaunchKernelGGL(subdomain_be_kernel, dim3((unsigned)(px * px)), dim3(256), lds, stream, a);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "sub-domain kernel launch");
     return FK_OK;
+}
+
+int fk_density_sample(const fk_density *w, double tau, int32_t n, double *w_out, hipStream_t stream) {
+    g_last_error.clear();
+    int rc;
+    if ((rc = validate_density(w)) != FK_OK) return rc;
+    if (w->kind == FK_DENSITY_GRID) return fail(FK_E_INVAL, "fk_density_sample takes an analytic density");
+    if (n < 1 || n > 65535 || !w_out) return fail(FK_E_INVAL, "need 1 <= n <= 65535 and a non-NULL output");
+    if (!std::isfinite(tau)) return fail(FK_E_INVAL, "tau is not finite");
+    SubArgs a{};
+    a.kind = w->kind;
+    a.amp = w->amp;
+    a.width2 = w->width2;
+    a.cx = w->cx;
+    a.cy = w->cy;
+    a.orbit_r = w->orbit_r;
+    a.omega = w->omega;
+    a.t_w = tau;
+    const int64_t total = (int64_t)(n + 1) * (n + 1);
+    hipLaunchKernelGGL(density_sample_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, a, (int)n,
+                       w_out);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FK_OK : hip_fail(e, "density sample kernel launch");
+}
+
+int fk_density_grid_drift(const double *grid_w, int32_t n, float *grid_b, hipStream_t stream) {
+    g_last_error.clear();
+    if (n < 2 || n > 65535 || !grid_w || !grid_b) return fail(FK_E_INVAL, "need 2 <= n <= 65535 and non-NULL arrays");
+    if (((uintptr_t)grid_b & 7u) != 0) return fail(FK_E_INVAL, "grid_b must be 8-byte aligned");
+    const int64_t total = (int64_t)(n + 1) * (n + 1);
+    hipLaunchKernelGGL(grid_drift_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, stream, grid_w,
+                       (int)n, (float2 *)grid_b);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FK_OK : hip_fail(e, "grid drift kernel launch");
 }
 
 int fk_mesh_quality(const double *xi, const double *eta, int32_t n, double *out, hipStream_t stream) {

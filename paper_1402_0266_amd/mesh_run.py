@@ -14,6 +14,11 @@ t^n + dt_mesh:
    interface values as Dirichlet data (Sect. 4);
 4. the mesh quality (minimum Jacobian, maximum skewness) is recorded.
 
+With `density_data="grid"` the density enters as the paper has it
+(Sect. 4): sampled at t^n on the mesh's nodes, the drift from finite
+differences at the nodes and bilinear between them, in both the interface
+solve and the sub-domain solves.
+
 With `cv_form="grid"` the control is the mesh's own gradient (bilinear in
 the grid, taken every `cv_stride` steps of each path) in the martingale
 form: no network.  Otherwise the network u_hat(t, x, y) is refitted every
@@ -33,8 +38,9 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import (FK_CV_DYNKIN, FK_CV_MARTINGALE, FK_CV_MARTINGALE_GRID, FkCv, fk_interface_solve,
-               fk_interface_solve_cv, fk_mesh_quality, subdomain_solve, subdomain_workspace_bytes)
+from . import (FK_CV_DYNKIN, FK_CV_MARTINGALE, FK_CV_MARTINGALE_GRID, FkCv, GridDensity, fk_density_sample,
+               fk_interface_solve, fk_interface_solve_cv, fk_mesh_quality, subdomain_solve,
+               subdomain_workspace_bytes)
 
 DATA_GRID = 3
 DATA_IDENTITY = 0
@@ -66,6 +72,8 @@ class MeshRunConfig:
     band_stride: int = 3        # grid stride of the band samples
     label_levels: int = 40      # most recent label levels kept for training
     bdry: int = DATA_IDENTITY   # outer boundary data of the sub-domain solves (the mesh's edge nodes)
+    density_data: str = "analytic"  # "grid": w sampled at t^n on the mesh's nodes only, drift by finite
+                                    # differences there and bilinear in between (the paper's data path)
     seed: int = 0
 
 
@@ -180,6 +188,11 @@ class MeshRun:
         self.sub_workspace = torch.empty(max(subdomain_workspace_bytes(cfg.px, cfg.m), 256), dtype=torch.uint8,
                                          device=self.dev)
         self.losses = []
+        if cfg.density_data not in ("analytic", "grid"):
+            raise ValueError("density_data must be 'analytic' or 'grid'")
+        if cfg.density_data == "grid":
+            self._wg = torch.empty((self.N + 1, self.N + 1), dtype=torch.float64, device=self.dev)
+            self._wb = torch.empty((self.N + 1, self.N + 1, 2), dtype=torch.float32, device=self.dev)
         if cfg.refit_every > 0 and cfg.cv_form != "grid":
             if init_params is None:
                 raise ValueError("refit_every > 0 needs initial network parameters")
@@ -228,6 +241,9 @@ class MeshRun:
             raise RuntimeError("the run has taken all its steps")
         tn = self.n * cfg.dt_mesh
         dens = self.density_fn(tn)
+        if cfg.density_data == "grid":
+            fk_density_sample(dens, tn, self.N, out=self._wg)
+            dens = GridDensity(self._wg, grid_b=self._wb)
         data = GridData(t_init=tn, score_mode=cfg.score_mode)
         grids = (self.xi.view(-1), self.eta.view(-1))
         if self.cv is not None and self.n % cfg.refit_every == 0:

@@ -64,3 +64,45 @@ def test_workspace_size(fk):
     a = fk.fk_interface_workspace_bytes(1521, 100_000)
     assert a >= 1521 * 100_000 * 8
     assert fk.fk_interface_workspace_bytes(10, 1) == 0
+
+
+class _Ptr:
+    def __init__(self, p):
+        self.p = p
+
+    def data_ptr(self):
+        return self.p
+
+
+class _FakeGrid:
+    """A grid density with dummy device addresses (never dereferenced: every
+    call below fails validation first)."""
+    kind = 6
+    time_mode = 0
+
+    def __init__(self, n, w_ptr=4096, b_ptr=8192):
+        self.grid_n = n
+        self.grid_w = _Ptr(w_ptr)
+        self.grid_b = _Ptr(b_ptr)
+
+
+@pytest.mark.parametrize("grid", [_FakeGrid(1), _FakeGrid(16, w_ptr=0), _FakeGrid(16, b_ptr=0),
+                                  _FakeGrid(16, b_ptr=8196)])
+def test_grid_density_validation(fk, grid):
+    assert _call(fk, dens=grid) == -1
+    assert "grid" in fk.fk_last_error()
+
+
+def test_grid_density_entry_points_validate(fk):
+    lib = fk.library()
+    assert lib.fk_density_sample(ctypes.byref(fk._density(_FakeGrid(8))), 0.0, 8, 4096, None) == -1
+    assert lib.fk_density_sample(ctypes.byref(fk._density(W.static_bump())), 0.0, 0, 4096, None) == -1
+    assert lib.fk_density_sample(ctypes.byref(fk._density(W.static_bump())), 0.0, 8, None, None) == -1
+    assert lib.fk_density_grid_drift(4096, 1, 8192, None) == -1
+    assert lib.fk_density_grid_drift(4096, 8, 8196, None) == -1
+    assert lib.fk_density_grid_drift(None, 8, 8192, None) == -1
+    # sub-domain solves need the density sampled on the mesh grid (N = px m = 16)
+    need = lib.subdomain_workspace_bytes(2, 8)
+    rc = lib.subdomain_solve(ctypes.byref(fk._density(_FakeGrid(12))), 0.0, 1e-3, 2, 8, 0, 4096, 4096, 4096, 4096,
+                             4096, 4096, 4096, need, None)
+    assert rc == -1 and "mesh grid" in fk.fk_last_error()
