@@ -26,7 +26,9 @@ The same line reports, as extra objects:
   and captured in a HIP graph; one replay timed.
 * "paper_run": the paper's own run (Sect. 5) -- the moving ring w = 1/rho
   on 41 x 41 nodes in 2 x 2 sub-domains, mesh step 1e-3 in 20 sub-steps,
-  10^4 paths on all interface nodes, equidistributed edges, t <= 0.75.
+  10^4 paths on all interface nodes, equidistributed edges, t <= 0.75; with
+  the analytic drift and with the paper's data path (w sampled on the grid,
+  finite-difference drift, bilinear between nodes).
 * "mesh_run": the time-dependent run -- 8 x 8 sub-domains on a 768-cell
   grid, two counter-rotating bumps, 200 mesh steps of 5e-4 with 20
   Euler-Maruyama steps each, 2^14 paths per interface node (10689 nodes),
@@ -230,27 +232,34 @@ def measure_batched(fk, probe_paths=512):
 def measure_paper_run():
     """The paper's run (Sect. 5): the moving ring w = 1/rho on 41 x 41 nodes
     in 2 x 2 sub-domains, mesh step 1e-3 in 20 sub-steps, 10^4 paths per
-    interface node (all 77), equidistributed edges, up to t = 0.75."""
+    interface node (all 77), equidistributed edges, up to t = 0.75; with the
+    analytic drift, and with the paper's data path (w sampled on the mesh
+    grid at each step, drift by finite differences, bilinear)."""
     import torch
     from paper_1402_0266_amd.mesh_run import PAPER_RING_RUN, MeshRun, MeshRunConfig, paper_ring_density
-    cfg = MeshRunConfig(**PAPER_RING_RUN)
-    print(f"[bench] paper run: {cfg.n_steps} steps", file=sys.stderr, flush=True)
-    run = MeshRun(cfg, density_fn=paper_ring_density)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    run.run()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
-    q = run.qualities()
-    _, se = run.interface_values()
-    run.close()
-    snaps = {f"t={0.25 * k:.2f}": {"min_jac": float(q[250 * k - 1, 0]), "max_skew": float(q[250 * k - 1, 1])}
-             for k in (1, 2, 3)}
-    return {"workload": "paper's run: ring w = 1/rho (alpha 10, beta -50), 41x41 nodes, 2x2 sub-domains, "
-                        "dt_mesh 1e-3 / 20 sub-steps, 1e4 paths on all 77 interface nodes, t <= 0.75",
-            "steps": cfg.n_steps, "s_total": wall, "ms_per_step": wall / cfg.n_steps * 1e3,
-            "min_jac_min": float(q[:, 0].min()), "max_skew_max": float(q[:, 1].max()),
-            "se_median": float(np.median(se)), "quality": snaps}
+    res = {"workload": "paper's run: ring w = 1/rho (alpha 10, beta -50), 41x41 nodes, 2x2 sub-domains, "
+                       "dt_mesh 1e-3 / 20 sub-steps, 1e4 paths on all 77 interface nodes, t <= 0.75"}
+    meshes = {}
+    for name in ("analytic", "grid"):
+        cfg = MeshRunConfig(**{**PAPER_RING_RUN, "density_data": name})
+        print(f"[bench] paper run ({name} density): {cfg.n_steps} steps", file=sys.stderr, flush=True)
+        run = MeshRun(cfg, density_fn=paper_ring_density)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        run.run()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        q = run.qualities()
+        _, se = run.interface_values()
+        meshes[name] = run.mesh()
+        run.close()
+        snaps = {f"t={0.25 * k:.2f}": {"min_jac": float(q[250 * k - 1, 0]), "max_skew": float(q[250 * k - 1, 1])}
+                 for k in (1, 2, 3)}
+        res[name] = {"steps": cfg.n_steps, "s_total": wall, "ms_per_step": wall / cfg.n_steps * 1e3,
+                     "min_jac_min": float(q[:, 0].min()), "max_skew_max": float(q[:, 1].max()),
+                     "se_median": float(np.median(se)), "quality": snaps}
+    res["final_mesh_max_diff"] = float(max(np.abs(meshes["analytic"][c] - meshes["grid"][c]).max() for c in (0, 1)))
+    return res
 
 
 def measure_mesh_run():

@@ -18,6 +18,7 @@ from __future__ import annotations
 import numpy as np
 
 import oracle as _oracle
+import oracle.keypoints as _keys
 import oracle.subdomain as _sub
 
 DATA_IDENTITY = 0
@@ -72,3 +73,21 @@ def dd_step(dens, tn, dt_mesh, substeps, px, m, xi_n, eta_n, n_paths, seed=0, le
                          level_id=level_id, score_mode=score_mode, threads=threads)
     xi, eta = _sub.subdomain_be_step(dens, tn, dt_mesh, px, m, xi_n, eta_n, mc["mean"][:, 0], mc["mean"][:, 1])
     return xi, eta, mc
+
+
+def dd_step_keys(dens, tn, dt_mesh, substeps, px, m, xi_n, eta_n, n_paths, w_grid, tol=1e-2, max_gap=None,
+                 bdry="identity", seed=0, level_id=0, score_mode=SCORE_EXTEND, threads=0):
+    """One plain mesh step with key points (Sect. 4 speed-up): the Monte-Carlo
+    solve at the key points chosen from w_grid (the density's samples at t^n
+    on the mesh grid), their paths keyed by their position in the key list;
+    the other interface nodes by the interpolant along their line through the
+    boundary data at its ends; then the sub-domain solves.  Returns (xi, eta,
+    key estimates, key mask)."""
+    mask, pts = _keys.key_points(w_grid, px, m, tol, max_gap)
+    data = _GridData(tn, xi_n, eta_n, score_mode)
+    mc = _oracle.fk_solve(dens, data, pts, dt_mesh, dt_mesh / substeps, n_paths, seed=seed, level_id=level_id,
+                          threads=threads)
+    gx, gy = _sub.boundary_grid(px * m, bdry, dens, tn)
+    iface = _keys.interpolate_interface(px, m, mask, mc["mean"], gx, gy)
+    xi, eta = _sub.subdomain_be_step(dens, tn, dt_mesh, px, m, xi_n, eta_n, iface[:, 0], iface[:, 1], bdry=bdry)
+    return xi, eta, mc, mask
