@@ -275,6 +275,72 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
                     hipStream_t stream);
 
 /*
+ * Outer boundary data of one mesh step on an n-cell grid (the values the
+ * sub-domain solve writes to the boundary nodes): the 4n edge nodes of
+ * xi_out / eta_out (device [(n+1)^2] FP64, row-major [j][i]) are set, the
+ * rest is untouched.  bdry_kind as for subdomain_solve (FK_DATA_IDENTITY,
+ * FK_DATA_ZERO, FK_DATA_EQUIDISTRIBUTED with w frozen at t_w); a grid density
+ * must have grid_n == n.  The equidistributed data needs a device workspace
+ * of fk_boundary_workspace_bytes(n) bytes, 256-byte aligned (else it may be
+ * NULL).  Used to supply the line ends of fk_interface_interpolate.
+ */
+size_t fk_boundary_workspace_bytes(int32_t n);
+int fk_boundary_data(const fk_density *w, double t_w, int32_t n, int32_t bdry_kind, double *xi_out, double *eta_out,
+                     void *workspace, size_t workspace_bytes, hipStream_t stream);
+
+/*
+ * Key points on the interfaces (Sect. 4, further speed-up; Sect. 5): the
+ * stochastic solution is needed only near the maxima and minima of rho_x,
+ * rho_xx along horizontal interfaces and rho_y, rho_yy along vertical ones;
+ * here rho = 1/w.  On each interface line of px x px sub-domains
+ * (N = px m), from rho at the line's nodes k = 0 .. N, the unscaled central
+ * differences f1_k = rho_{k+1} - rho_{k-1} and
+ * f2_k = (rho_{k+1} + rho_{k-1}) - 2 rho_k at k = 1 .. N-1; node k
+ * (2 <= k <= N-2) is a key point where f1 or f2 has a discrete extremum
+ * (f_k > f_{k-1} and f_k >= f_{k+1}, or f_k < f_{k-1} and f_k <= f_{k+1}) with
+ * |f_k| >= tol max |f| over the line.  Crossings of interface lines are key
+ * points, and a gap of g > max_gap positions between consecutive knots (key
+ * points and the line's two ends) gets ceil(g / max_gap) - 1 more key points
+ * at prev + floor(r g / q).
+ *
+ *   grid_w   device [(N+1)^2] FP64 samples of w > 0 at the step's density time,
+ *            row-major [j][i] (fk_density_sample, or a grid density's samples)
+ *   mask     device [n_iface] uint8, canonical interface order (output):
+ *            1 at key points, 0 elsewhere
+ *
+ * FK_E_INVAL for px < 2, m < 2, px m > 65535, tol < 0 or not finite,
+ * max_gap < 1, NULL arrays.
+ */
+int fk_key_points(const double *grid_w, int32_t px, int32_t m, double tol, int32_t max_gap, uint8_t *mask,
+                  hipStream_t stream);
+
+/*
+ * Interface values from key points (Sect. 4; Sect. 5 uses piecewise cubic
+ * Hermite interpolation): on each interface line, the monotone piecewise
+ * cubic Hermite interpolant (Fritsch & Carlson 1980; slopes of Fritsch &
+ * Butland 1984: 0 at an interior knot whose secants differ in sign, else
+ * their weighted harmonic mean with weights 2 h_right + h_left and
+ * h_right + 2 h_left; at an end the three-point formula, 0 if its sign
+ * differs from the end secant's and limited to 3 times it where the secants
+ * change sign; two knots give a straight line) through the boundary data at
+ * the line's two ends and its key points, in the node coordinate k/N,
+ * evaluated at the other nodes of the line.
+ *
+ *   slot               device [n_iface] int32, canonical order: the node's
+ *                      index into key_xi / key_eta, or -1 (not a key point);
+ *                      indices >= n_keys yield NaN
+ *   key_xi, key_eta    device [n_keys] FP64: the key points' values
+ *   edge_xi, edge_eta  device [(N+1)^2] FP64 grids whose edge nodes hold the
+ *                      boundary data (fk_boundary_data)
+ *   iface_xi/eta       device [n_iface] FP64 (output): every interface node
+ *
+ * FK_E_INVAL for px < 2, m < 2, px m > 65535, n_keys < 0, NULL arrays.
+ */
+int fk_interface_interpolate(int32_t px, int32_t m, const int32_t *slot, int64_t n_keys, const double *key_xi,
+                             const double *key_eta, const double *edge_xi, const double *edge_eta, double *iface_xi,
+                             double *iface_eta, hipStream_t stream);
+
+/*
  * Mesh quality of a nodal map (xi, eta) on an (n+1)^2 grid: out[0] = minimum
  * over cells of the Jacobian xi_x eta_y - xi_y eta_x, out[1] = maximum of the
  * skewness |grad xi . grad eta| / (|grad xi| |grad eta|), both from

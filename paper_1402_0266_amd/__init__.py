@@ -114,6 +114,16 @@ _lib.fk_density_sample.argtypes = [ctypes.POINTER(fk_density), ctypes.c_double, 
 _lib.fk_density_sample.restype = ctypes.c_int
 _lib.fk_density_grid_drift.argtypes = [_P, ctypes.c_int32, _P, _P]
 _lib.fk_density_grid_drift.restype = ctypes.c_int
+_lib.fk_boundary_workspace_bytes.argtypes = [ctypes.c_int32]
+_lib.fk_boundary_workspace_bytes.restype = ctypes.c_size_t
+_lib.fk_boundary_data.argtypes = [ctypes.POINTER(fk_density), ctypes.c_double, ctypes.c_int32, ctypes.c_int32, _P, _P,
+                                  _P, ctypes.c_size_t, _P]
+_lib.fk_boundary_data.restype = ctypes.c_int
+_lib.fk_key_points.argtypes = [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, ctypes.c_int32, _P, _P]
+_lib.fk_key_points.restype = ctypes.c_int
+_lib.fk_interface_interpolate.argtypes = [ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, _P, _P, _P, _P,
+                                          _P]
+_lib.fk_interface_interpolate.restype = ctypes.c_int
 _lib.fk_mesh_quality.argtypes = [_P, _P, ctypes.c_int32, _P, _P]
 _lib.fk_mesh_quality.restype = ctypes.c_int
 _lib.fk_cv_create.argtypes = [_P, ctypes.c_double, ctypes.POINTER(_P)]
@@ -210,6 +220,56 @@ def fk_density_grid_drift(grid_w, out=None):
     elif out.dtype != torch.float32 or out.shape != (n + 1, n + 1, 2) or not out.is_contiguous():
         raise ValueError("out must be a contiguous [(n+1), (n+1), 2] FP32 tensor")
     _check(_lib.fk_density_grid_drift(grid_w.data_ptr(), int(n), out.data_ptr(), _stream(torch, grid_w.device)))
+    return out
+
+
+def n_interface_nodes(px: int, m: int) -> int:
+    """Interface nodes of px x px sub-domains on the (px m)-cell grid."""
+    N = px * m
+    return 2 * (px - 1) * (N - 1) - (px - 1) ** 2
+
+
+def fk_boundary_data(density, t_w, n, bdry_kind, xi_out, eta_out, workspace=None):
+    """Writes the outer boundary data of one mesh step into the edge nodes of
+    the device grids xi_out / eta_out ([(n+1), (n+1)] FP64)."""
+    import torch
+    need = int(_lib.fk_boundary_workspace_bytes(int(n)))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=xi_out.device)
+    w = _density(density)
+    _check(_lib.fk_boundary_data(ctypes.byref(w), float(t_w), int(n), int(bdry_kind), xi_out.data_ptr(),
+                                 eta_out.data_ptr(), workspace.data_ptr(), workspace.numel(),
+                                 _stream(torch, xi_out.device)))
+    return workspace
+
+
+def fk_key_points(grid_w, px, m, tol=1e-2, max_gap=None, out=None):
+    """Key-point mask (device uint8 [n_iface], canonical order) from device
+    samples grid_w [(px m + 1), (px m + 1)] of w at the step's density time."""
+    import torch
+    n_if = n_interface_nodes(px, m)
+    if out is None:
+        out = torch.empty(n_if, dtype=torch.uint8, device=grid_w.device)
+    max_gap = max(1, m // 2) if max_gap is None else int(max_gap)
+    _check(_lib.fk_key_points(grid_w.data_ptr(), int(px), int(m), float(tol), max_gap, out.data_ptr(),
+                              _stream(torch, grid_w.device)))
+    return out
+
+
+def fk_interface_interpolate(px, m, slot, key_xi, key_eta, edge_xi, edge_eta, out=None):
+    """Every interface value from the key points' values (device FP64 [n_keys])
+    and the boundary data in the edge nodes of edge_xi / edge_eta; ``slot``:
+    device int32 [n_iface], the node's index into the key arrays or -1."""
+    import torch
+    n_if = n_interface_nodes(px, m)
+    dev = slot.device
+    if out is None:
+        out = (torch.empty(n_if, dtype=torch.float64, device=dev), torch.empty(n_if, dtype=torch.float64, device=dev))
+    n_keys = int(key_xi.numel())
+    _check(_lib.fk_interface_interpolate(int(px), int(m), slot.data_ptr(), n_keys,
+                                         key_xi.data_ptr() if n_keys else None, key_eta.data_ptr() if n_keys else None,
+                                         edge_xi.data_ptr(), edge_eta.data_ptr(), out[0].data_ptr(), out[1].data_ptr(),
+                                         _stream(torch, dev)))
     return out
 
 

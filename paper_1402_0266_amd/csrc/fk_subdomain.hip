@@ -858,6 +858,57 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
     return FK_OK;
 }
 
+size_t fk_boundary_workspace_bytes(int32_t n) {
+    if (n < 2 || n > 65535) return 0;
+    return align256((size_t)4 * n * sizeof(double));
+}
+
+int fk_boundary_data(const fk_density *w, double t_w, int32_t n, int32_t bdry_kind, double *xi_out, double *eta_out,
+                     void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    int rc;
+    if ((rc = validate_density(w)) != FK_OK) return rc;
+    if (n < 2 || n > 65535) return fail(FK_E_INVAL, "need 2 <= n <= 65535");
+    if (!std::isfinite(t_w)) return fail(FK_E_INVAL, "t_w is not finite");
+    if (bdry_kind != FK_DATA_IDENTITY && bdry_kind != FK_DATA_ZERO && bdry_kind != FK_DATA_EQUIDISTRIBUTED)
+        return fail(FK_E_INVAL, "outer boundary data must be FK_DATA_IDENTITY, _ZERO or _EQUIDISTRIBUTED");
+    if (w->kind == FK_DENSITY_GRID && w->grid_n != n)
+        return fail(FK_E_INVAL, "a grid density must be sampled on this grid (grid_n %d != n %d)", w->grid_n, n);
+    if (!xi_out || !eta_out) return fail(FK_E_INVAL, "NULL array");
+    const size_t need = fk_boundary_workspace_bytes(n);
+    if (bdry_kind == FK_DATA_EQUIDISTRIBUTED) {
+        if (!workspace || workspace_bytes < need) return fail(FK_E_NOMEM, "workspace too small: need %zu bytes", need);
+        if (((uintptr_t)workspace & 255u) != 0) return fail(FK_E_INVAL, "workspace must be 256-byte aligned");
+    }
+    SubArgs a{};
+    a.xi_out = xi_out;
+    a.eta_out = eta_out;
+    a.N = n;
+    a.m = n;
+    a.px = 1;
+    a.kind = w->kind;
+    a.amp = w->amp;
+    a.width2 = w->width2;
+    a.cx = w->cx;
+    a.cy = w->cy;
+    a.orbit_r = w->orbit_r;
+    a.omega = w->omega;
+    a.t_w = t_w;
+    a.wg = w->kind == FK_DENSITY_GRID ? w->grid_w : nullptr;
+    double *edge_cells = (double *)workspace;
+    hipError_t e;
+    if (bdry_kind == FK_DATA_EQUIDISTRIBUTED) {
+        hipLaunchKernelGGL(edge_cells_kernel, dim3((unsigned)((4 * n + 255) / 256)), dim3(256), 0, stream, a,
+                           edge_cells);
+        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "edge integral kernel launch");
+    }
+    hipLaunchKernelGGL(dirichlet_kernel, dim3((unsigned)((4 * n + 255) / 256)), dim3(256), 0, stream, a,
+                       (const double *)nullptr, (const double *)nullptr, (int64_t)0, (int)bdry_kind,
+                       (const double *)edge_cells, xi_out, eta_out);
+    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "boundary kernel launch");
+    return FK_OK;
+}
+
 int fk_density_sample(const fk_density *w, double tau, int32_t n, double *w_out, hipStream_t stream) {
     g_last_error.clear();
     int rc;

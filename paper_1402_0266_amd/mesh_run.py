@@ -17,7 +17,12 @@ t^n + dt_mesh:
 With `density_data="grid"` the density enters as the paper has it
 (Sect. 4): sampled at t^n on the mesh's nodes, the drift from finite
 differences at the nodes and bilinear between them, in both the interface
-solve and the sub-domain solves.
+solve and the sub-domain solves.  With `key_points=True` only the key points
+of each interface line (near the extrema of the first and second
+derivatives of rho = 1/w along it, plus crossings and gap fill) are
+simulated, and the other interface nodes follow from the monotone piecewise
+cubic Hermite interpolant through the line's boundary data and key values
+(Sect. 4, further speed-up; the paper's run, Sect. 5).
 
 With `cv_form="grid"` the control is the mesh's own gradient (bilinear in
 the grid, taken every `cv_stride` steps of each path) in the martingale
@@ -38,9 +43,9 @@ from dataclasses import dataclass
 
 import numpy as np
 
-from . import (FK_CV_DYNKIN, FK_CV_MARTINGALE, FK_CV_MARTINGALE_GRID, FkCv, GridDensity, fk_density_sample,
-               fk_interface_solve, fk_interface_solve_cv, fk_mesh_quality, subdomain_solve,
-               subdomain_workspace_bytes)
+from . import (FK_CV_DYNKIN, FK_CV_MARTINGALE, FK_CV_MARTINGALE_GRID, FkCv, GridDensity, fk_boundary_data,
+               fk_density_sample, fk_interface_interpolate, fk_interface_solve, fk_interface_solve_cv, fk_key_points,
+               fk_mesh_quality, subdomain_solve, subdomain_workspace_bytes)
 
 DATA_GRID = 3
 DATA_IDENTITY = 0
@@ -74,6 +79,9 @@ class MeshRunConfig:
     bdry: int = DATA_IDENTITY   # outer boundary data of the sub-domain solves (the mesh's edge nodes)
     density_data: str = "analytic"  # "grid": w sampled at t^n on the mesh's nodes only, drift by finite
                                     # differences there and bilinear in between (the paper's data path)
+    key_points: bool = False    # simulate only the key points; interpolate the other interface nodes
+    key_tol: float = 1e-2       # significance of a derivative extremum, relative to the line's largest
+    key_gap: int = 0            # largest gap between knots along a line (0: m // 2)
     seed: int = 0
 
 
@@ -190,9 +198,17 @@ class MeshRun:
         self.losses = []
         if cfg.density_data not in ("analytic", "grid"):
             raise ValueError("density_data must be 'analytic' or 'grid'")
-        if cfg.density_data == "grid":
+        if cfg.density_data == "grid" or cfg.key_points:
             self._wg = torch.empty((self.N + 1, self.N + 1), dtype=torch.float64, device=self.dev)
+        if cfg.density_data == "grid":
             self._wb = torch.empty((self.N + 1, self.N + 1, 2), dtype=torch.float32, device=self.dev)
+        self.n_keys = []
+        if cfg.key_points:
+            self._mask = torch.empty(self.n_nodes, dtype=torch.uint8, device=self.dev)
+            self._slot = torch.empty(self.n_nodes, dtype=torch.int32, device=self.dev)
+            self._iface_buf = (torch.empty(self.n_nodes, dtype=torch.float64, device=self.dev),
+                               torch.empty(self.n_nodes, dtype=torch.float64, device=self.dev))
+            self._bdry_ws = None
         if cfg.refit_every > 0 and cfg.cv_form != "grid":
             if init_params is None:
                 raise ValueError("refit_every > 0 needs initial network parameters")
@@ -241,41 +257,67 @@ class MeshRun:
             raise RuntimeError("the run has taken all its steps")
         tn = self.n * cfg.dt_mesh
         dens = self.density_fn(tn)
-        if cfg.density_data == "grid":
+        if cfg.density_data == "grid" or cfg.key_points:
             fk_density_sample(dens, tn, self.N, out=self._wg)
+        if cfg.density_data == "grid":
             dens = GridDensity(self._wg, grid_b=self._wb)
         data = GridData(t_init=tn, score_mode=cfg.score_mode)
         grids = (self.xi.view(-1), self.eta.view(-1))
         if self.cv is not None and self.n % cfg.refit_every == 0:
             self.refit()
         dt = cfg.dt_mesh / cfg.substeps
+        pts, idx = self.pts, None
+        if cfg.key_points:
+            fk_key_points(self._wg, cfg.px, cfg.m, cfg.key_tol, cfg.key_gap or None, out=self._mask)
+            idx = np.flatnonzero(self._mask.cpu().numpy())           # synchronises: the node list is host input
+            slot = np.full(self.n_nodes, -1, dtype=np.int32)
+            slot[idx] = np.arange(idx.size, dtype=np.int32)
+            self._slot.copy_(self.torch.from_numpy(slot))
+            pts = self.pts[idx]
+            self.n_keys.append(int(idx.size))
         if cfg.cv_form == "grid":
-            out = fk_interface_solve_cv(dens, data, self.pts, cfg.dt_mesh, dt, cfg.n_paths, None,
+            out = fk_interface_solve_cv(dens, data, pts, cfg.dt_mesh, dt, cfg.n_paths, None,
                                         stride=cfg.cv_stride, seed=cfg.seed, level_id=self.n,
                                         form=FK_CV_MARTINGALE_GRID, plain=False, device=self.dev,
                                         workspace=self.workspace, grids=grids)
             self.used_cv[self.n] = True
         elif self.cv is not None:
             form = FK_CV_MARTINGALE if cfg.cv_form == "martingale" else FK_CV_DYNKIN
-            out = fk_interface_solve_cv(dens, data, self.pts, cfg.dt_mesh, dt, cfg.n_paths, self.cv,
+            out = fk_interface_solve_cv(dens, data, pts, cfg.dt_mesh, dt, cfg.n_paths, self.cv,
                                         stride=cfg.cv_stride, seed=cfg.seed, level_id=self.n, form=form,
                                         plain=False, device=self.dev, workspace=self.workspace, grids=grids)
             self.used_cv[self.n] = True
         else:
-            out = fk_interface_solve(dens, data, self.pts, cfg.dt_mesh, dt, cfg.n_paths, seed=cfg.seed,
+            out = fk_interface_solve(dens, data, pts, cfg.dt_mesh, dt, cfg.n_paths, seed=cfg.seed,
                                      level_id=self.n, device=self.dev, workspace=self.workspace, grids=grids)
         self.workspace = out["_workspace"]
-        xi_new, eta_new = subdomain_solve(dens, tn, cfg.dt_mesh, cfg.px, cfg.m, self.xi, self.eta, out["xi"],
-                                          out["eta"], bdry_kind=cfg.bdry, out=self.spare,
+        if cfg.key_points:
+            # the line ends: this step's outer boundary data, in the grids the
+            # sub-domain solve then fills
+            self._bdry_ws = fk_boundary_data(dens, tn, self.N, cfg.bdry, self.spare[0], self.spare[1],
+                                             workspace=self._bdry_ws)
+            iface_xi, iface_eta = fk_interface_interpolate(cfg.px, cfg.m, self._slot, out["xi"], out["eta"],
+                                                           self.spare[0], self.spare[1], out=self._iface_buf)
+        else:
+            iface_xi, iface_eta = out["xi"], out["eta"]
+        xi_new, eta_new = subdomain_solve(dens, tn, cfg.dt_mesh, cfg.px, cfg.m, self.xi, self.eta, iface_xi,
+                                          iface_eta, bdry_kind=cfg.bdry, out=self.spare,
                                           workspace=self.sub_workspace)
         self._quality[self.n] = fk_mesh_quality(xi_new, eta_new)
-        self._iface[self.n, :, 0] = out["xi"]
-        self._iface[self.n, :, 1] = out["eta"]
-        self._se[self.n, :, 0] = out["se_xi"]
-        self._se[self.n, :, 1] = out["se_eta"]
+        self._iface[self.n, :, 0] = iface_xi
+        self._iface[self.n, :, 1] = iface_eta
+        if idx is None:
+            self._se[self.n, :, 0] = out["se_xi"]
+            self._se[self.n, :, 1] = out["se_eta"]
+        else:
+            # standard errors exist at the key points only
+            self._se[self.n].fill_(float("nan"))
+            it = self.torch.from_numpy(idx).to(self.dev)
+            self._se[self.n, it, 0] = out["se_xi"]
+            self._se[self.n, it, 1] = out["se_eta"]
         if self.cv is not None:
             if self._band_idx is None:
-                self._add_labels(tn + cfg.dt_mesh, out["xi"], out["eta"])
+                self._add_labels(tn + cfg.dt_mesh, iface_xi, iface_eta)
             else:
                 self._add_labels(tn + cfg.dt_mesh, xi_new.view(-1)[self._band_idx], eta_new.view(-1)[self._band_idx])
         self.spare = (self.xi, self.eta)
@@ -292,7 +334,8 @@ class MeshRun:
         return self._quality[:self.n].cpu().numpy()
 
     def interface_values(self):
-        """([steps, nodes, 2] estimates, [steps, nodes, 2] standard errors)."""
+        """([steps, nodes, 2] interface values, [steps, nodes, 2] standard
+        errors; with key points, NaN at the interpolated nodes)."""
         return self._iface[:self.n].cpu().numpy(), self._se[:self.n].cpu().numpy()
 
     def mesh(self):
