@@ -34,7 +34,10 @@
  *    boundary count as inside (eq. (5) uses strict inequalities).
  *  - a path that exits scores the boundary data at its first outside point,
  *    unclamped, with the data extended off the square (identity data extends
- *    as xi = x, eta = y); a PROJECT mode clamps the point first.
+ *    as xi = x, eta = y); a PROJECT mode clamps the point first; a BRIDGE
+ *    mode adds the Brownian-bridge crossing test within each step (see
+ *    bridge_exit) and scores every exit at the point projected onto the
+ *    square.
  *  - the normal generator: Philox4x32-10 (Salmon, Moraes, Dror & Shaw,
  *    SC'11), key = (seed low word, seed high word), counter = (k/2, path,
  *    node, (level << 4) | stream); one call serves two steps (words 0,1 for
@@ -349,13 +352,20 @@ static void boundary_value(const or_data *d, double elapsed, double x, double y,
         *eta = bilinear(d->grid_eta, d->grid_n, x, y);
         return;
     }
-    if (d->score_mode == 1) {
+    if (d->score_mode == 1 || d->score_mode == 3) {
         x = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
         y = y < 0.0 ? 0.0 : (y > 1.0 ? 1.0 : y);
     }
+
     switch (d->bdry_kind) {
     case D_IDENTITY: *xi = x; *eta = y; return;
     case D_SIN: *xi = *eta = exp(-2.0 * OR_PI * OR_PI * elapsed) * sin_mode(x, y); return;
+    case D_GRID:
+        /* the grid initial data on the square's edge (its edge nodes hold the
+           boundary data), at the projected exit point */
+        *xi = bilinear(d->grid_xi, d->grid_n, x, y);
+        *eta = bilinear(d->grid_eta, d->grid_n, x, y);
+        return;
     default: *xi = *eta = 0.0; return;
     }
 }
@@ -373,6 +383,45 @@ typedef struct {
     uint32_t key[2];
     uint32_t ctr3;
 } or_problem;
+
+/* ---------------------------------------------------------------------------
+ * Brownian-bridge exit test (score mode 3).  Between two inside points X_k
+ * and X_{k+1} of a step of length D, the diffusion sqrt(2) dW, pinned at both
+ * ends, crosses a straight side at distances d0 and d1 with probability
+ * exp(-2 d0 d1 / (2 D)) = exp(-d0 d1 / D); the four sides of the square are
+ * taken as independent, p = 1 - prod (1 - p_side).  Reading: a side's
+ * probability is taken as 0 where d0 d1 / D > 17 (below the resolution
+ * 2^-24 of the uniforms); the uniform of step k is word (k & 1) of
+ * Philox(k/2, path, node, ctr3 | 4), u = ((r >> 8) + 1) 2^-24 in (0, 1]; the
+ * path exits within the step if u < p, at the end point projected onto the
+ * side with the largest crossing probability.  Returns 1 on an exit and
+ * moves (x, y) there.
+ * ------------------------------------------------------------------------- */
+static int bridge_exit(const or_problem *pb, int64_t k, uint32_t path, uint32_t node, double D,
+                       double x0, double y0, double *x, double *y)
+{
+    const double d0[4] = {x0, 1.0 - x0, y0, 1.0 - y0};
+    const double d1[4] = {*x, 1.0 - *x, *y, 1.0 - *y};
+    double surv = 1.0, pmax = 0.0;
+    int side = -1;
+    for (int i = 0; i < 4; ++i) {
+        const double e = d0[i] * d1[i] / D;
+        if (e > 17.0) continue;
+        const double ps = exp(-e);
+        surv *= 1.0 - ps;
+        if (ps > pmax) { pmax = ps; side = i; }
+    }
+    if (side < 0) return 0;
+    uint32_t ctr[4] = {(uint32_t)(k >> 1), path, node, pb->ctr3 | 4u}, r[4];
+    or_philox4x32_10(ctr, pb->key, r);
+    const double u = ((double)(r[k & 1] >> 8) + 1.0) * 0x1p-24;
+    if (!(u < 1.0 - surv)) return 0;
+    if (side == 0) *x = 0.0;
+    else if (side == 1) *x = 1.0;
+    else if (side == 2) *y = 0.0;
+    else *y = 1.0;
+    return 1;
+}
 
 static int64_t run_path(const or_problem *pb, double px, double py, uint32_t path, uint32_t node,
                         double *score_xi, double *score_eta)
@@ -392,10 +441,12 @@ static int64_t run_path(const or_problem *pb, double px, double py, uint32_t pat
         double bx, by;
         drift(&pb->dens, tau, x, y, &bx, &by);
         double sd = sqrt(2.0 * D);
+        const double x0 = x, y0 = y;
         x = x + bx * D + sd * z0;
         y = y + by * D + sd * z1;
         s = s + D;
-        if (x < 0.0 || x > 1.0 || y < 0.0 || y > 1.0) {
+        if (x < 0.0 || x > 1.0 || y < 0.0 || y > 1.0 ||
+            (pb->data.score_mode == 3 && bridge_exit(pb, k, path, node, D, x0, y0, &x, &y))) {
             boundary_value(&pb->data, pb->t - s, x, y, score_xi, score_eta);
             return k + 1;
         }
@@ -439,7 +490,8 @@ int or_fk_solve(int kind, int time_mode, const double *par, const double *w_grid
     pb.data.init_kind = init_kind;
     pb.data.bdry_kind = bdry_kind;
     pb.data.score_mode = score_mode;
-    if (score_mode < 0 || score_mode > 2 || (score_mode == 2 && (init_kind != D_GRID || !grid_xi || !grid_eta)))
+    if (score_mode < 0 || score_mode > 3 || (score_mode == 2 && (init_kind != D_GRID || !grid_xi || !grid_eta)) ||
+        (bdry_kind == D_GRID && (init_kind != D_GRID || (score_mode != 1 && score_mode != 3))))
         return -1;
     pb.data.grid_xi = grid_xi;
     pb.data.grid_eta = grid_eta;
@@ -520,7 +572,8 @@ int or_fk_paths(int kind, int time_mode, const double *par, const double *w_grid
     pb.data.init_kind = init_kind;
     pb.data.bdry_kind = bdry_kind;
     pb.data.score_mode = score_mode;
-    if (score_mode < 0 || score_mode > 2 || (score_mode == 2 && (init_kind != D_GRID || !grid_xi || !grid_eta)))
+    if (score_mode < 0 || score_mode > 3 || (score_mode == 2 && (init_kind != D_GRID || !grid_xi || !grid_eta)) ||
+        (bdry_kind == D_GRID && (init_kind != D_GRID || (score_mode != 1 && score_mode != 3))))
         return -1;
     pb.data.grid_xi = grid_xi;
     pb.data.grid_eta = grid_eta;

@@ -30,9 +30,9 @@ UHAT_MLP = 1
 class _GridData:
     """The fields the oracle's solvers read for grid initial data."""
 
-    def __init__(self, t_init, xi, eta, score_mode):
+    def __init__(self, t_init, xi, eta, score_mode, bdry_kind=DATA_IDENTITY):
         self.init_kind = DATA_GRID
-        self.bdry_kind = DATA_IDENTITY
+        self.bdry_kind = bdry_kind
         self.score_mode = score_mode
         self.t_init = float(t_init)
         self.grid_xi = np.ascontiguousarray(xi, dtype=np.float64)
@@ -47,16 +47,19 @@ def interface_points(px: int, m: int) -> np.ndarray:
 
 
 def interface_solve(dens, tn, dt_mesh, substeps, px, m, xi_n, eta_n, n_paths, seed=0, level_id=0,
-                    node_ids=None, flat=None, t_scale=0.1, stride=10, form=0, score_mode=SCORE_EXTEND, threads=0):
+                    node_ids=None, flat=None, t_scale=0.1, stride=10, form=0, score_mode=SCORE_EXTEND,
+                    bdry_kind=DATA_IDENTITY, threads=0):
     """Step 2: interface estimates (dict with mean [n, 2], se [n, 2]) at the
     nodes node_ids (default all) of px x px sub-domains.  Exits score the
-    mesh continued bilinearly past the edge by default (score_mode)."""
+    mesh continued bilinearly past the edge by default (score_mode); with a
+    projecting score mode, bdry_kind DATA_GRID scores the mesh itself at the
+    projected exit point."""
     pts = interface_points(px, m)
     if node_ids is not None:
         # the nodes keep their indices in the full set: those key the paths' counters
         node_ids = np.asarray(node_ids, dtype=np.int64)
         pts = pts[node_ids]
-    data = _GridData(tn, xi_n, eta_n, score_mode)
+    data = _GridData(tn, xi_n, eta_n, score_mode, bdry_kind)
     dt = dt_mesh / substeps
     if flat is None:
         return _oracle.fk_solve(dens, data, pts, dt_mesh, dt, n_paths, seed=seed, level_id=level_id,

@@ -152,8 +152,10 @@ def test_exit_scoring_near_a_compressed_boundary(oracle_mod):
     The identity continued unclamped has slope 1 there, and a projected exit
     point drops the overshoot: both bias the nodes next to the edge.  The
     mesh continued bilinearly (its edge nodes hold the identity data) has the
-    solution's slope and is unbiased to first order.  Reference: the global
-    solve over the mesh step in 10 backward-Euler sub-steps."""
+    solution's slope and is unbiased to first order; so is the Brownian-bridge
+    test, which finds the crossings within a step and scores the mesh's edge
+    at them.  Reference: the global solve over the mesh step in 10
+    backward-Euler sub-steps."""
     px, m, D = 4, 16, 5e-4
     N = px * m
     X, Y = nodal(N)
@@ -166,9 +168,11 @@ def test_exit_scoring_near_a_compressed_boundary(oracle_mod):
     ij = ij_all[ids]
     ref = a[ij[:, 1], ij[:, 0]]
     z = {}
-    for mode in (W.SCORE_UNCLAMPED, W.SCORE_PROJECT, W.SCORE_EXTEND):
+    for mode in (W.SCORE_UNCLAMPED, W.SCORE_PROJECT, W.SCORE_EXTEND, W.SCORE_BRIDGE):
         mc = MS.interface_solve(W.CONST, 0.0, D, 20, px, m, xi0, eta0, 200000, node_ids=ids, score_mode=mode,
+                                bdry_kind=W.DATA_GRID if mode == W.SCORE_BRIDGE else W.DATA_IDENTITY,
                                 threads=THREADS)
         z[mode] = (mc["mean"][:, 0] - ref) / mc["se"][:, 0]
     assert np.all(np.abs(z[W.SCORE_EXTEND]) < 4), z
+    assert np.all(np.abs(z[W.SCORE_BRIDGE]) < 4), z
     assert z[W.SCORE_UNCLAMPED][0] < -8 and z[W.SCORE_PROJECT][0] > 8, z

@@ -49,6 +49,7 @@ DATA_EQUIDISTRIBUTED = 4  # outer boundary of the sub-domain solves: 1-D equidis
 SCORE_UNCLAMPED = 0   # evaluate the boundary data at the (unclamped) first outside point
 SCORE_PROJECT = 1     # clamp that point onto the closed square first
 SCORE_EXTEND = 2      # the grid initial data continued bilinearly to that point
+SCORE_BRIDGE = 3      # Brownian-bridge exit test within each step; exits scored at the projected point
 
 # Philox stream tags (low 4 bits of the last counter word).
 STREAM_PATHS = 0
