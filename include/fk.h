@@ -70,7 +70,9 @@ extern "C" {
 #define FK_DATA_SIN 1       /* test mode: phi = sin(pi x) sin(pi y) for both components; boundary
                                data exp(-2 pi^2 (t - s)) phi(X) extended off the square */
 #define FK_DATA_ZERO 2      /* boundary data 0 */
-#define FK_DATA_GRID 3      /* initial data only: bilinear in (grid_n+1)^2 nodal FP64 grids */
+#define FK_DATA_GRID 3      /* initial data: bilinear in (grid_n+1)^2 nodal FP64 grids; as boundary data
+                               (with grid initial data and FK_SCORE_PROJECT / FK_SCORE_BRIDGE) the same
+                               grids at the projected exit point, i.e. their edge nodes' data */
 #define FK_DATA_EQUIDISTRIBUTED 4  /* subdomain_solve's outer boundary only: xi = 0 / 1 on the left / right
                                       edges, eta = 0 / 1 on the bottom / top edges, and on the other edges
                                       the 1-D equidistribution of w along the edge, xi(x) = int_0^x w /
@@ -83,6 +85,16 @@ extern "C" {
                                  that point: for a grid whose edge nodes hold the boundary data, the data
                                  extended by the grid's own normal slope (a first-order correction of the
                                  overshoot of the discrete exit test); needs grid initial data */
+#define FK_SCORE_BRIDGE 3     /* the Brownian-bridge exit test within every step that ends inside, on top
+                                 of the discrete one: the diffusion pinned at the step's two ends crosses
+                                 a side at distances d0, d1 with probability exp(-d0 d1 / dt); the four
+                                 sides combine as independent, a side with d0 d1 / dt > 17 counts as 0;
+                                 the step's uniform is word (k & 1) of Philox(k/2, path, node,
+                                 ctr3 | 4), u = ((r >> 8) + 1) 2^-24, and u < p ends the path within the
+                                 step at its end point projected onto the side of largest probability.
+                                 Every exit is scored at the point clamped onto the square.  For w = 1
+                                 the killed chain then has the law of the killed diffusion at any step
+                                 size.  Plain solves only (fk_interface_solve, batches) */
 
 /* Density parameters (plain values; for FK_DENSITY_GRID also two device arrays). */
 typedef struct fk_density {

@@ -69,10 +69,14 @@ int validate_density(const fk_density *w) {
 int validate_data(const fk_data *d) {
     if (!d) return fail(FK_E_INVAL, "data is NULL");
     if (d->init_kind < 0 || d->init_kind > FK_DATA_GRID) return fail(FK_E_INVAL, "unknown init kind %d", d->init_kind);
-    if (d->bdry_kind < 0 || d->bdry_kind > FK_DATA_ZERO)
+    if (d->bdry_kind < 0 || d->bdry_kind > FK_DATA_GRID)
         return fail(FK_E_INVAL, "unknown boundary kind %d", d->bdry_kind);
-    if (d->score_mode != FK_SCORE_UNCLAMPED && d->score_mode != FK_SCORE_PROJECT && d->score_mode != FK_SCORE_EXTEND)
+    if (d->score_mode != FK_SCORE_UNCLAMPED && d->score_mode != FK_SCORE_PROJECT && d->score_mode != FK_SCORE_EXTEND &&
+        d->score_mode != FK_SCORE_BRIDGE)
         return fail(FK_E_INVAL, "unknown score mode %d", d->score_mode);
+    if (d->bdry_kind == FK_DATA_GRID &&
+        (d->init_kind != FK_DATA_GRID || (d->score_mode != FK_SCORE_PROJECT && d->score_mode != FK_SCORE_BRIDGE)))
+        return fail(FK_E_INVAL, "grid boundary data needs grid initial data and a projecting score mode");
     if (d->score_mode == FK_SCORE_EXTEND && d->init_kind != FK_DATA_GRID)
         return fail(FK_E_INVAL, "score mode EXTEND needs grid initial data");
     if (!std::isfinite(d->t_init)) return fail(FK_E_INVAL, "t_init is not finite");
@@ -281,7 +285,8 @@ int enqueue_solve(const SolveLaunch &S, hipStream_t stream, bool allow_timing) {
     a.cpn = (uint32_t)cpn;
     a.total_chunks = (uint32_t)(S.n_nodes * cpn);
     int bpc = S.plan.blocks_per_cu;
-    const int occ = path_kernel_max_blocks_per_cu(S.kind, S.time_mode, S.uniform, S.plan.block);
+    const int occ = path_kernel_max_blocks_per_cu(S.kind, S.time_mode, S.uniform, a.score_mode == FK_SCORE_BRIDGE,
+                                                  S.plan.block);
     if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
     const int grid = n_cu * bpc;
     if ((e = timing_mark(timed, 0, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");

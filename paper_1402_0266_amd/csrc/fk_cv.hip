@@ -1427,6 +1427,8 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     if (!cv && !grid_ctl) return fail(FK_E_INVAL, "network is NULL");
     if ((rc = validate_density(w)) != FK_OK) return rc;
     if ((rc = validate_data(d)) != FK_OK) return rc;
+    if (d->score_mode == FK_SCORE_BRIDGE)
+        return fail(FK_E_UNSUPPORTED, "the Brownian-bridge exit test is for plain solves only");
     if ((rc = validate_common(n_paths, dt)) != FK_OK) return rc;
     if ((rc = validate_horizon(t, d->t_init, dt, level_id)) != FK_OK) return rc;
     if ((rc = validate_points(pts, n_nodes)) != FK_OK) return rc;

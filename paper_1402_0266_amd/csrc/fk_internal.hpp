@@ -145,6 +145,6 @@ hipError_t launch_zero_u32(uint32_t *p, int n_words, hipStream_t s);
 hipError_t launch_paths(int kind, int time_mode, bool uniform, const PathArgs &a, int grid, int block,
                         hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t s);
-int path_kernel_max_blocks_per_cu(int kind, int time_mode, bool uniform, int block);
+int path_kernel_max_blocks_per_cu(int kind, int time_mode, bool uniform, bool bridge, int block);
 
 }  // namespace fk

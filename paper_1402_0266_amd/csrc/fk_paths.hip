@@ -49,7 +49,9 @@ hipError_t launch_zero_u32(uint32_t *p, int n_words, hipStream_t s) {
 }
 
 
-template <int KIND, int TMODE, bool UNIFORM>
+// BRIDGE: the Brownian-bridge crossing test after every step that stays
+// inside (score mode FK_SCORE_BRIDGE).
+template <int KIND, int TMODE, bool UNIFORM, bool BRIDGE>
 __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
     constexpr bool kMovingBackward = moving_kind(KIND) && TMODE == TIME_BACKWARD;
     const uint32_t lane = threadIdx.x & 63u;
@@ -106,7 +108,14 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
                     ox = L.dens.orbit_r * cr;
                     oy = L.dens.orbit_r * sr;
                 }
+                float x0h = 0.f, x0l = 0.f, y0h = 0.f, y0l = 0.f;
+                if constexpr (BRIDGE) {
+                    x0h = L.xh; x0l = L.xl; y0h = L.yh; y0l = L.yl;
+                }
                 out = em_step<KIND, UNIFORM>(L, r.r0, r.r1, ox, oy);
+                if constexpr (BRIDGE) {
+                    if (!out) out = bridge_exit<UNIFORM>(L, x0h, x0l, y0h, y0l, key0, key1);
+                }
                 my_steps += 1;
                 if (!out && L.k < L.K) {
                     if constexpr (kMovingBackward) {
@@ -117,7 +126,13 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
                         ox = L.dens.orbit_r * c2;
                         oy = L.dens.orbit_r * s2;
                     }
+                    if constexpr (BRIDGE) {
+                        x0h = L.xh; x0l = L.xl; y0h = L.yh; y0l = L.yl;
+                    }
                     out = em_step<KIND, UNIFORM>(L, r.r2, r.r3, ox, oy);
+                    if constexpr (BRIDGE) {
+                        if (!out) out = bridge_exit<UNIFORM>(L, x0h, x0l, y0h, y0l, key0, key1);
+                    }
                     my_steps += 1;
                 }
             }
@@ -140,71 +155,75 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
 }
 
 namespace {
-template <int KIND, int TMODE, bool UNIFORM>
+template <int KIND, int TMODE, bool UNIFORM, bool BRIDGE>
 hipError_t launch_one(const PathArgs &a, int grid, int block, hipStream_t s) {
-    hipLaunchKernelGGL((fk_path_kernel<KIND, TMODE, UNIFORM>), dim3(grid), dim3(block), 0, s, a);
+    hipLaunchKernelGGL((fk_path_kernel<KIND, TMODE, UNIFORM, BRIDGE>), dim3(grid), dim3(block), 0, s, a);
     return hipGetLastError();
 }
 
-template <int KIND, int TMODE, bool UNIFORM>
+template <int KIND, int TMODE, bool UNIFORM, bool BRIDGE>
 int max_blocks(int block) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk_path_kernel<KIND, TMODE, UNIFORM>, block, 0) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk_path_kernel<KIND, TMODE, UNIFORM, BRIDGE>, block, 0) !=
         hipSuccess)
         return 0;
     return nb;
 }
 
-// Calls F<KIND, TMODE, UNIFORM>::run(args...) for the runtime triple.
-template <template <int, int, bool> class F, typename... Args>
-auto dispatch(int kind, int time_mode, bool uniform, Args &&...args) {
+// Calls F<KIND, TMODE, UNIFORM, BRIDGE>::run(args...) for the runtime values.
+template <template <int, int, bool, bool> class F, typename... Args>
+auto dispatch(int kind, int time_mode, bool uniform, bool bridge, Args &&...args) {
     const bool frozen = (time_mode == TIME_FROZEN);
-#define FK_CASE(K, T)                                                          \
-    return uniform ? F<K, T, true>::run(std::forward<Args>(args)...)          \
-                   : F<K, T, false>::run(std::forward<Args>(args)...)
+#define FK_CASE(K, T)                                                                          \
+    if (bridge)                                                                                \
+        return uniform ? F<K, T, true, true>::run(std::forward<Args>(args)...)                \
+                       : F<K, T, false, true>::run(std::forward<Args>(args)...);              \
+    return uniform ? F<K, T, true, false>::run(std::forward<Args>(args)...)                   \
+                   : F<K, T, false, false>::run(std::forward<Args>(args)...)
     switch (kind) {
     case KIND_CONST: FK_CASE(KIND_CONST, TIME_BACKWARD);
     case KIND_BUMP: FK_CASE(KIND_BUMP, TIME_BACKWARD);
     case KIND_RIDGE: FK_CASE(KIND_RIDGE, TIME_BACKWARD);
     case KIND_GRID: FK_CASE(KIND_GRID, TIME_BACKWARD);
     case KIND_MOVING:
-        if (frozen) FK_CASE(KIND_MOVING, TIME_FROZEN);
+        if (frozen) { FK_CASE(KIND_MOVING, TIME_FROZEN); }
         FK_CASE(KIND_MOVING, TIME_BACKWARD);
     case KIND_RING:
-        if (frozen) FK_CASE(KIND_RING, TIME_FROZEN);
+        if (frozen) { FK_CASE(KIND_RING, TIME_FROZEN); }
         FK_CASE(KIND_RING, TIME_BACKWARD);
     default:
-        if (frozen) FK_CASE(KIND_TWO, TIME_FROZEN);
+        if (frozen) { FK_CASE(KIND_TWO, TIME_FROZEN); }
         FK_CASE(KIND_TWO, TIME_BACKWARD);
     }
 #undef FK_CASE
 }
 
-template <int K, int T, bool U>
+template <int K, int T, bool U, bool B>
 struct LaunchF {
     static hipError_t run(const PathArgs &a, int grid, int block, hipStream_t s) {
-        return launch_one<K, T, U>(a, grid, block, s);
+        return launch_one<K, T, U, B>(a, grid, block, s);
     }
 };
-template <int K, int T, bool U>
+template <int K, int T, bool U, bool B>
 struct OccF {
-    static int run(int block) { return max_blocks<K, T, U>(block); }
+    static int run(int block) { return max_blocks<K, T, U, B>(block); }
 };
+
+bool kind_known(int kind) {
+    return kind == KIND_CONST || kind == KIND_BUMP || kind == KIND_RIDGE || kind == KIND_MOVING || kind == KIND_TWO ||
+           kind == KIND_RING || kind == KIND_GRID;
+}
 }  // namespace
 
 hipError_t launch_paths(int kind, int time_mode, bool uniform, const PathArgs &a, int grid, int block,
                         hipStream_t s) {
-    if (kind != KIND_CONST && kind != KIND_BUMP && kind != KIND_RIDGE && kind != KIND_MOVING && kind != KIND_TWO &&
-        kind != KIND_RING && kind != KIND_GRID)
-        return hipErrorInvalidValue;
-    return dispatch<LaunchF>(kind, time_mode, uniform, a, grid, block, s);
+    if (!kind_known(kind)) return hipErrorInvalidValue;
+    return dispatch<LaunchF>(kind, time_mode, uniform, a.score_mode == FK_SCORE_BRIDGE, a, grid, block, s);
 }
 
-int path_kernel_max_blocks_per_cu(int kind, int time_mode, bool uniform, int block) {
-    if (kind != KIND_CONST && kind != KIND_BUMP && kind != KIND_RIDGE && kind != KIND_MOVING && kind != KIND_TWO &&
-        kind != KIND_RING && kind != KIND_GRID)
-        return 0;
-    return dispatch<OccF>(kind, time_mode, uniform, block);
+int path_kernel_max_blocks_per_cu(int kind, int time_mode, bool uniform, bool bridge, int block) {
+    if (!kind_known(kind)) return 0;
+    return dispatch<OccF>(kind, time_mode, uniform, bridge, block);
 }
 
 // ---------------------------------------------------------------------------
