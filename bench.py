@@ -21,6 +21,9 @@ The same line reports, as extra objects:
   paths), timed at its own N*; the Dynkin form at stride 50 beside it.
   Throughput is quoted for the solve alone and with the labels and training
   counted once.
+* "bridge": the same workload with the Brownian-bridge exit test (bias and
+  rate at RMS 1e-3) at dt = 1e-5 and at coarser steps, the discrete test
+  beside it.
 * "batched": 64 time levels t_k = 0.01 k of the moving bump with random
   2x2..8x8 layouts on G = 128 (66047 nodes), 2^16 paths per node, autotuned
   and captured in a HIP graph; one replay timed.
@@ -39,7 +42,7 @@ The same line reports, as extra objects:
   global step).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-cv] [--no-mesh-run]
-                    [--no-batched] [--no-paper-run]
+                    [--no-batched] [--no-paper-run] [--no-bridge]
 """
 from __future__ import annotations
 
@@ -268,6 +271,44 @@ def measure_paper_run():
     return res
 
 
+def measure_bridge(fk, wl, pts, fd, pilot_paths=100000):
+    """The headline workload with the Brownian-bridge exit test, at the
+    configured dt and at coarser steps (plain discrete test beside it): a
+    pilot gives the variance and the bias against the FD reference, N* the
+    paths for RMS 1e-3, and one timed solve at N* the rate."""
+    import dataclasses
+
+    import torch
+    res = []
+    for dt, bridge in ((1e-5, True), (4e-5, False), (4e-5, True), (1e-4, False), (1e-4, True)):
+        data = dataclasses.replace(wl.data, score_mode=W.SCORE_BRIDGE if bridge else wl.data.score_mode)
+        print(f"[bench] bridge leg: dt {dt:g}, bridge {bridge}", file=sys.stderr, flush=True)
+        r = fk.fk_interface_solve(wl.density, data, pts, wl.t, dt, pilot_paths, wl.seed)
+        est, se = _stack(r, ("xi", "eta")), _stack(r, ("se_xi", "se_eta"))
+        var = float(np.mean(se ** 2) * pilot_paths)
+        b2 = max(0.0, float(np.mean((est - fd[:, 2:4]) ** 2)) - var / pilot_paths)
+        row = {"dt": dt, "bridge": bridge, "var": var, "bias": math.sqrt(b2)}
+        if b2 < 0.9e-6:
+            n_star = int(math.ceil(var / (1e-6 - b2)))
+            fk.fk_timing_enable(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            r = fk.fk_interface_solve(wl.density, data, pts, wl.t, dt, n_star, wl.seed)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            kms, _ = fk.fk_timing_last()
+            fk.fk_timing_enable(False)
+            est = _stack(r, ("xi", "eta"))
+            row.update({"n_star": n_star, "s_per_solve": wall, "path_kernel_ms": kms,
+                        "nodes_per_s": len(pts) / wall,
+                        "rms_err": float(np.sqrt(np.mean((est - fd[:, 2:4]) ** 2)))})
+        else:
+            row["note"] = "bias above 0.95e-3: RMS 1e-3 out of reach at this dt"
+        res.append(row)
+    return {"workload": "moving_bump_1521 (t = 0.1), identity data; bridge: Brownian-bridge exit test, "
+                        "exits projected; pilot 1e5 paths", "runs": res}
+
+
 def measure_mesh_run():
     """The time-dependent mesh run, with the network and plain."""
     import torch
@@ -315,6 +356,7 @@ def main():
     ap.add_argument("--no-mesh-run", action="store_true", help="skip the time-dependent mesh run")
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-level launch")
     ap.add_argument("--no-paper-run", action="store_true", help="skip the paper's ring run")
+    ap.add_argument("--no-bridge", action="store_true", help="skip the Brownian-bridge exit-test leg")
     ap.add_argument("--paths", type=int, default=0, help="fix paths/node and skip the N* pilot (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scales HBM counters) and exit")
@@ -427,6 +469,8 @@ def main():
     }
     if not args.no_cv and fd is not None:
         out["cv"] = measure_cv(fk, wl, pts, fd, args.steps, args.warmup)
+    if not args.no_bridge and fd is not None:
+        out["bridge"] = measure_bridge(fk, wl, pts, fd)
     if not args.no_mesh_run:
         out["mesh_run"] = measure_mesh_run()
     if not args.no_batched:
