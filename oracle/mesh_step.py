@@ -94,3 +94,35 @@ def dd_step_keys(dens, tn, dt_mesh, substeps, px, m, xi_n, eta_n, n_paths, w_gri
     iface = _keys.interpolate_interface(px, m, mask, mc["mean"], gx, gy)
     xi, eta = _sub.subdomain_be_step(dens, tn, dt_mesh, px, m, xi_n, eta_n, iface[:, 0], iface[:, 1], bdry=bdry)
     return xi, eta, mc, mask
+
+
+SCORE_BRIDGE = 3
+DATA_GRID_BOUNDARY = 3   # boundary data read from the grid at the projected exit point
+
+
+def steady_start(px, m, bdry, dens):
+    """The grid a steady solve starts from: the identity map with the outer
+    boundary data on its edge nodes."""
+    N = px * m
+    x = np.arange(N + 1) / N
+    X, Y = np.meshgrid(x, x)
+    gx, gy = _sub.boundary_grid(N, bdry, dens, 0.0)
+    edge = np.zeros((N + 1, N + 1), dtype=bool)
+    edge[0, :] = edge[-1, :] = edge[:, 0] = edge[:, -1] = True
+    return np.where(edge, gx, X), np.where(edge, gy, Y)
+
+
+def steady_dd(dens, px, m, n_paths, dt, horizon, bdry="identity", seed=0, threads=0):
+    """The elliptic (steady) stochastic domain decomposition (eq. (2)): paths
+    run until they leave the square (Brownian-bridge exit test, the grid's
+    edge nodes as boundary data; the horizon only caps the rare long path,
+    which then scores the start grid), then each sub-domain solves the
+    steady system with the interface values as Dirichlet data.  The density
+    is static (frozen).  Returns (xi, eta, interface estimates)."""
+    sx, sy = steady_start(px, m, bdry, dens)
+    data = _GridData(0.0, sx, sy, SCORE_BRIDGE, bdry_kind=DATA_GRID_BOUNDARY)
+    mc = _oracle.fk_solve(dens, data, interface_points(px, m), horizon, dt, n_paths, seed=seed, want_exit=True,
+                          threads=threads)
+    xi, eta = _sub.subdomain_be_step(dens, 0.0, np.inf, px, m, sx, sy, mc["mean"][:, 0], mc["mean"][:, 1],
+                                     bdry=bdry)
+    return xi, eta, mc

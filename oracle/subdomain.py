@@ -86,21 +86,27 @@ def boundary_grid(N, bdry: str = "identity", dens=None, t_w=0.0):
 
 def _be_solve_region(bx, by, D, h, i0, i1, j0, j1, rhs_grids, bc_grids):
     """Backward-Euler solve on the interior nodes i0 < i < i1, j0 < j < j1;
-    every node on the region's edge is Dirichlet data from bc_grids."""
+    every node on the region's edge is Dirichlet data from bc_grids.  With
+    D = inf the steady problem -L_h u = 0 (the elliptic system, eq. (2)):
+    rows (4 u_P - sum of neighbours) / h^2 - b . grad_h u = 0, no previous
+    values."""
     ni, nj = i1 - i0 - 1, j1 - j0 - 1
     n = ni * nj
     idx = lambda i, j: (j - j0 - 1) * ni + (i - i0 - 1)  # noqa: E731
     rows, cols, vals = [], [], []
     rhs = [np.zeros(n) for _ in rhs_grids]
-    c0 = D / h ** 2
+    steady = bool(np.isinf(D))
+    scale = 1.0 if steady else D          # the steady rows are the transient ones divided by D, D -> inf
+    c0 = scale / h ** 2
     for j in range(j0 + 1, j1):
         for i in range(i0 + 1, i1):
             r = idx(i, j)
-            rows.append(r), cols.append(r), vals.append(1.0 + 4.0 * c0)
-            for k, g in enumerate(rhs_grids):
-                rhs[k][r] += g[j, i]
-            cx = D * bx[j, i] / (2 * h)
-            cy = D * by[j, i] / (2 * h)
+            rows.append(r), cols.append(r), vals.append((0.0 if steady else 1.0) + 4.0 * c0)
+            if not steady:
+                for k, g in enumerate(rhs_grids):
+                    rhs[k][r] += g[j, i]
+            cx = scale * bx[j, i] / (2 * h)
+            cy = scale * by[j, i] / (2 * h)
             for (ii, jj, coef) in ((i + 1, j, -c0 - cx), (i - 1, j, -c0 + cx),
                                    (i, j + 1, -c0 - cy), (i, j - 1, -c0 + cy)):
                 if i0 < ii < i1 and j0 < jj < j1:
@@ -114,7 +120,8 @@ def _be_solve_region(bx, by, D, h, i0, i1, j0, j1, rhs_grids, bc_grids):
 
 
 def global_be_step(dens, t_w, D, N, xi_n, eta_n, bdry="identity"):
-    """One backward-Euler step on the whole grid."""
+    """One backward-Euler step on the whole grid (D = inf: the steady solve;
+    xi_n, eta_n are then not read)."""
     h = 1.0 / N
     bx, by = _drift_grid(dens, t_w, N)
     gx, gy = boundary_grid(N, bdry, dens, t_w)
