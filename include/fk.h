@@ -262,6 +262,9 @@ void fk_batch_destroy(fk_batch_t b);
  * takes one backward-Euler step of length dt_mesh of the relaxed Winslow
  * system (Sect. 2, eq. (3)), central differences, density frozen at t_w:
  *   (u - u^n)/dt_mesh = Laplacian_h u + b . grad_h u,  b = -grad w / w.
+ * dt_mesh = +INFINITY solves the steady (elliptic) system of eq. (2),
+ * Laplacian_h u + b . grad_h u = 0; xi_n / eta_n are then not read (may be
+ * NULL).
  * Each sub-domain system is solved by banded LU without pivoting, in FP64;
  * xi and eta share the factorisation.  Requires |b| h / 2 < 1 (checked from
  * the density's bound; FK_E_UNSUPPORTED otherwise) and m - 1 < 128.  A grid

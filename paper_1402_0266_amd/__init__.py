@@ -493,9 +493,10 @@ def subdomain_workspace_bytes(px: int, m: int) -> int:
 def subdomain_solve(density, t_w, dt_mesh, px, m, xi_n, eta_n, iface_xi, iface_eta, bdry_kind=0,
                     out=None, workspace=None):
     """Sub-domain backward-Euler solves (C: ``subdomain_solve``).  Grids are
-    device FP64 tensors [(px m + 1)^2] (or 2-D views); returns (xi, eta)."""
+    device FP64 tensors [(px m + 1)^2] (or 2-D views); returns (xi, eta).
+    dt_mesh = inf: the steady solves (xi_n, eta_n may be None)."""
     import torch
-    dev = xi_n.device
+    dev = iface_xi.device
     N1 = px * m + 1
     if out is None:
         out = (torch.empty((N1, N1), dtype=torch.float64, device=dev),
@@ -504,7 +505,8 @@ def subdomain_solve(density, t_w, dt_mesh, px, m, xi_n, eta_n, iface_xi, iface_e
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
     _check(_lib.subdomain_solve(ctypes.byref(_density(density)), float(t_w), float(dt_mesh), int(px), int(m),
-                                int(bdry_kind), xi_n.data_ptr(), eta_n.data_ptr(), iface_xi.data_ptr(),
+                                int(bdry_kind), None if xi_n is None else xi_n.data_ptr(),
+                                None if eta_n is None else eta_n.data_ptr(), iface_xi.data_ptr(),
                                 iface_eta.data_ptr(), out[0].data_ptr(), out[1].data_ptr(), workspace.data_ptr(),
                                 workspace.numel(), _stream(torch, dev)))
     return out

@@ -39,7 +39,9 @@ struct SubArgs {
     double *cbuf;                // per sub-domain: 4 n doubles, (E, W, N, S) coefficients of each row
     double *rbuf;                // per sub-domain: 2 n doubles, right-hand sides (xi, eta) of each row
     int N, m, px;
-    double c, half_d_over_h;     // D/h^2 and D/(2h)
+    double c, half_d_over_h;     // D/h^2 and D/(2h); steady: 1/h^2 and 1/(2h)
+    double diag0;                // 1 (backward Euler), 0 (steady: the rows divided by D, D -> inf)
+    int steady;                  // no previous values in the right-hand side
     int kind;
     double amp, width2, cx, cy, orbit_r, omega, t_w;
     const double *wg;            // FK_DENSITY_GRID: samples of w on this grid, (N+1)^2
@@ -317,7 +319,7 @@ __global__ void __launch_bounds__(256) subdomain_lu_kernel(const SubArgs a) {
         const double cxr = a.half_d_over_h * bx, cyr = a.half_d_over_h * by;
         const double cE = -a.c - cxr, cW = -a.c + cxr, cN = -a.c - cyr, cS = -a.c + cyr;
         const int64_t g = (int64_t)gj * N1 + gi;
-        double fx = a.xi_n[g], fy = a.eta_n[g];
+        double fx = a.steady ? 0.0 : a.xi_n[g], fy = a.steady ? 0.0 : a.eta_n[g];
         if (ii == q - 1) { fx -= cE * a.xi_out[g + 1]; fy -= cE * a.eta_out[g + 1]; }
         if (ii == 0) { fx -= cW * a.xi_out[g - 1]; fy -= cW * a.eta_out[g - 1]; }
         if (jj == q - 1) { fx -= cN * a.xi_out[g + N1]; fy -= cN * a.eta_out[g + N1]; }
@@ -328,7 +330,7 @@ __global__ void __launch_bounds__(256) subdomain_lu_kernel(const SubArgs a) {
     __threadfence_block();
     __syncthreads();
 
-    const double diag = 1.0 + 4.0 * a.c;
+    const double diag = a.diag0 + 4.0 * a.c;
     // original matrix entry (r, c); identity beyond n
     auto entry = [&](int r, int c) -> double {
         if (r >= n || c >= n) return r == c ? 1.0 : 0.0;
@@ -496,7 +498,7 @@ __global__ void __launch_bounds__(256) subdomain_be_kernel(const SubArgs a) {
         kx[s] = cxr;
         ky[s] = cyr;
         const int64_t g = (int64_t)gj * N1 + gi;
-        double fx = a.xi_n[g], fy = a.eta_n[g];
+        double fx = a.steady ? 0.0 : a.xi_n[g], fy = a.steady ? 0.0 : a.eta_n[g];
         const double cE = -a.c - cxr, cW = -a.c + cxr, cN = -a.c - cyr, cS = -a.c + cyr;
         if (ii == q - 1) { fx -= cE * a.xi_out[g + 1]; fy -= cE * a.eta_out[g + 1]; }
         if (ii == 0) { fx -= cW * a.xi_out[g - 1]; fy -= cW * a.eta_out[g - 1]; }
@@ -505,7 +507,7 @@ __global__ void __launch_bounds__(256) subdomain_be_kernel(const SubArgs a) {
         rx[s] = fx;
         ry[s] = fy;
         double *row = W + s * P1;
-        row[r % P1] = 1.0 + 4.0 * a.c;
+        row[r % P1] = a.diag0 + 4.0 * a.c;
         if (ii > 0 && r - 1 >= k) row[(r - 1) % P1] = cW;
         if (jj > 0 && r - q >= k) row[(r - q) % P1] = cS;
     };
@@ -763,13 +765,14 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
     if ((rc = validate_density(w)) != FK_OK) return rc;
     if (px < 1 || m < 2) return fail(FK_E_INVAL, "need px >= 1 and m >= 2");
     if (m - 1 >= kMaxP1) return fail(FK_E_UNSUPPORTED, "sub-domain side m must be <= %d", kMaxP1);
-    if (!std::isfinite(t_w) || !std::isfinite(dt_mesh) || !(dt_mesh > 0.0))
-        return fail(FK_E_INVAL, "t_w must be finite and dt_mesh > 0");
+    const bool steady = std::isinf(dt_mesh) && dt_mesh > 0.0;
+    if (!std::isfinite(t_w) || std::isnan(dt_mesh) || !(dt_mesh > 0.0))
+        return fail(FK_E_INVAL, "t_w must be finite and dt_mesh > 0 (or +inf: the steady solve)");
     if (bdry_kind != FK_DATA_IDENTITY && bdry_kind != FK_DATA_ZERO && bdry_kind != FK_DATA_EQUIDISTRIBUTED)
         return fail(FK_E_INVAL, "outer boundary data must be FK_DATA_IDENTITY, _ZERO or _EQUIDISTRIBUTED");
     const int N = px * m;
     const int64_t n_iface = 2 * (int64_t)(px - 1) * (N - 1) - (int64_t)(px - 1) * (px - 1);
-    if (!xi_n || !eta_n || !xi_out || !eta_out || (n_iface > 0 && (!iface_xi || !iface_eta)))
+    if ((!steady && (!xi_n || !eta_n)) || !xi_out || !eta_out || (n_iface > 0 && (!iface_xi || !iface_eta)))
         return fail(FK_E_INVAL, "NULL array");
     const size_t need = sub_ws_bytes(px, m);
     if (!workspace || workspace_bytes < need) return fail(FK_E_NOMEM, "workspace too small: need %zu bytes", need);
@@ -824,8 +827,12 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
     a.N = N;
     a.m = m;
     a.px = px;
-    a.c = dt_mesh / (h * h);
-    a.half_d_over_h = dt_mesh / (2.0 * h);
+    // steady: the rows divided by D (D -> inf) -- no identity term, no
+    // previous values -- and scaled by h^2
+    a.steady = steady ? 1 : 0;
+    a.diag0 = steady ? 0.0 : 1.0;
+    a.c = steady ? 1.0 : dt_mesh / (h * h);
+    a.half_d_over_h = steady ? 0.5 * h : dt_mesh / (2.0 * h);
     a.kind = w->kind;
     a.amp = w->amp;
     a.width2 = w->width2;

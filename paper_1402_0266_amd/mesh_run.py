@@ -49,6 +49,7 @@ from . import (FK_CV_DYNKIN, FK_CV_MARTINGALE, FK_CV_MARTINGALE_GRID, FkCv, Grid
 
 DATA_GRID = 3
 DATA_IDENTITY = 0
+SCORE_BRIDGE = 3
 DATA_EQUIDISTRIBUTED = 4
 KIND_TWO_BUMPS = 3
 KIND_RING = 4
@@ -346,3 +347,31 @@ class MeshRun:
         if self.cv is not None:
             self.cv.close()
             self.cv = None
+
+
+def steady_mesh(density, px: int, m: int, n_paths: int, dt: float, horizon: float, bdry: int = DATA_IDENTITY,
+                seed: int = 0, device="cuda"):
+    """The elliptic (steady) stochastic domain decomposition (eq. (2)) for a
+    static density: the interface values are Feynman-Kac estimates of the
+    steady system -- paths run until they leave the square, found by the
+    Brownian-bridge exit test and scored with the outer boundary data at the
+    crossing; `horizon` only caps the rare long path, which then scores the
+    start grid (the identity map with the boundary data on its edges) --
+    then each sub-domain solves the steady system with those values as
+    Dirichlet data.  Returns a dict of device tensors: xi, eta (the mesh),
+    iface_xi, iface_eta, se_xi, se_eta, and `survivors` (paths capped by the
+    horizon)."""
+    import torch
+    from . import fk_boundary_data
+    dev = torch.device(device)
+    N = px * m
+    x = torch.arange(N + 1, dtype=torch.float64, device=dev) / N
+    sx = x.repeat(N + 1, 1).contiguous()
+    sy = x[:, None].repeat(1, N + 1).contiguous()
+    fk_boundary_data(density, 0.0, N, bdry, sx, sy)          # edge nodes: the boundary data
+    data = GridData(t_init=0.0, bdry_kind=DATA_GRID, score_mode=SCORE_BRIDGE)
+    out = fk_interface_solve(density, data, interface_nodes(px, m), horizon, dt, n_paths, seed=seed, exit_step=True,
+                             device=dev, grids=(sx.view(-1), sy.view(-1)))
+    xi, eta = subdomain_solve(density, 0.0, float("inf"), px, m, None, None, out["xi"], out["eta"], bdry_kind=bdry)
+    return {"xi": xi, "eta": eta, "iface_xi": out["xi"], "iface_eta": out["eta"], "se_xi": out["se_xi"],
+            "se_eta": out["se_eta"], "survivors": (out["exit_step"] < 0).sum(), "start": (sx, sy)}
