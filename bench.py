@@ -33,6 +33,8 @@ The same line reports, as extra objects:
   t <= 0.75; with the analytic drift, with the paper's data path (w sampled
   on the grid, finite-difference drift, bilinear between nodes), and with
   that data path and key points (the run as the paper describes it).
+* "steady": the elliptic variant -- one-shot steady meshes of the static
+  bump (1521 interface nodes) and of the paper's ring (41 x 41 grid).
 * "mesh_run": the time-dependent run -- 8 x 8 sub-domains on a 768-cell
   grid, two counter-rotating bumps, 200 mesh steps of 5e-4 with 20
   Euler-Maruyama steps each, 2^14 paths per interface node (10689 nodes),
@@ -42,7 +44,7 @@ The same line reports, as extra objects:
   global step).
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline] [--no-cv] [--no-mesh-run]
-                    [--no-batched] [--no-paper-run] [--no-bridge]
+                    [--no-batched] [--no-paper-run] [--no-bridge] [--no-steady]
 """
 from __future__ import annotations
 
@@ -309,6 +311,36 @@ def measure_bridge(fk, wl, pts, fd, pilot_paths=100000):
                         "exits projected; pilot 1e5 paths", "runs": res}
 
 
+def measure_steady():
+    """The elliptic (steady) variant (eq. (2)): one-shot steady meshes --
+    the static bump on 4 x 4 sub-domains of a 256-cell grid (1521 interface
+    nodes, 2^16 paths, dt 1e-5) and the paper's ring at t = 0 on its 41 x 41
+    grid (2 x 2 sub-domains, 10^4 paths, dt 1e-4, equidistributed edges)."""
+    import torch
+    from paper_1402_0266_amd.mesh_run import DATA_EQUIDISTRIBUTED, DATA_IDENTITY, paper_ring_density, steady_mesh
+    import paper_1402_0266_amd as fk
+    res = {}
+    for name, dens, px, m, n_paths, dt, horizon, bdry in (
+            ("static_bump_1521", W.static_bump(), 4, 64, 1 << 16, 1e-5, 3.0, DATA_IDENTITY),
+            ("paper_ring_77", paper_ring_density(0.0), 2, 20, 10000, 1e-4, 20.0, DATA_EQUIDISTRIBUTED)):
+        print(f"[bench] steady mesh: {name}", file=sys.stderr, flush=True)
+        steady_mesh(dens, px, m, 256, dt, horizon, bdry=bdry)        # first-launch costs
+        fk.fk_timing_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        g = steady_mesh(dens, px, m, n_paths, dt, horizon, bdry=bdry)
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        kms, _ = fk.fk_timing_last()
+        fk.fk_timing_enable(False)
+        q = fk.fk_mesh_quality(g["xi"], g["eta"]).cpu().numpy()
+        se = torch.stack([g["se_xi"], g["se_eta"]]).cpu().numpy()
+        res[name] = {"nodes": int(g["iface_xi"].numel()), "paths": n_paths, "dt": dt, "horizon": horizon,
+                     "s": wall, "path_kernel_ms": kms, "survivors": int(g["survivors"]),
+                     "min_jac": float(q[0]), "max_skew": float(q[1]), "se_median": float(np.median(se))}
+    return res
+
+
 def measure_mesh_run():
     """The time-dependent mesh run, with the network and plain."""
     import torch
@@ -357,6 +389,7 @@ def main():
     ap.add_argument("--no-batched", action="store_true", help="skip the batched 64-level launch")
     ap.add_argument("--no-paper-run", action="store_true", help="skip the paper's ring run")
     ap.add_argument("--no-bridge", action="store_true", help="skip the Brownian-bridge exit-test leg")
+    ap.add_argument("--no-steady", action="store_true", help="skip the elliptic (steady) meshes")
     ap.add_argument("--paths", type=int, default=0, help="fix paths/node and skip the N* pilot (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scales HBM counters) and exit")
@@ -477,6 +510,8 @@ def main():
         out["batched"] = measure_batched(fk)
     if not args.no_paper_run:
         out["paper_run"] = measure_paper_run()
+    if not args.no_steady:
+        out["steady"] = measure_steady()
     if not args.no_cpu_baseline:
         print("[bench] cpu baseline (oracle sample)", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline(wl, n_star)

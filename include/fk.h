@@ -323,7 +323,7 @@ int fk_boundary_data(const fk_density *w, double t_w, int32_t n, int32_t bdry_ki
  *   mask     device [n_iface] uint8, canonical interface order (output):
  *            1 at key points, 0 elsewhere
  *
- * FK_E_INVAL for px < 2, m < 2, px m > 65535, tol < 0 or not finite,
+ * FK_E_INVAL for px < 2, m < 2, px m > 8192, tol < 0 or not finite,
  * max_gap < 1, NULL arrays.
  */
 int fk_key_points(const double *grid_w, int32_t px, int32_t m, double tol, int32_t max_gap, uint8_t *mask,

@@ -61,7 +61,7 @@ __device__ __forceinline__ int64_t line_grid(int px, int m, int line, int k) {
 // the left neighbour and not less than the right one, or the reverse) of
 // size at least tol times the line's largest |f|; crossings are key points;
 // gaps between consecutive knots (keys and the two ends) longer than max_gap
-// positions get ceil(g / max_gap) - 1 evenly spaced keys.  One thread per line.
+// positions get ceil(g / max_gap) - 1 evenly spaced keys.
 // ---------------------------------------------------------------------------
 struct KeyArgs {
     const double *w;
@@ -85,43 +85,68 @@ __device__ __forceinline__ bool extremum(double fl, double fk, double fr, double
     return fabs(fk) >= thr && ((fk > fl && fk >= fr) || (fk < fl && fk <= fr));
 }
 
-__global__ void key_points_kernel(const KeyArgs a) {
-    const int line = blockIdx.x * blockDim.x + threadIdx.x;
-    if (line >= 2 * (a.px - 1)) return;
+// One workgroup per line: the line's largest |f1|, |f2| by a block
+// reduction, the extremum flags of its positions in LDS, then one lane
+// walks the flags for the gap filling and the workgroup writes the mask.
+constexpr int kKeyThreads = 256;
+constexpr int kKeyMaxN = 8192;  // LDS flags: positions 0 .. N
+
+__device__ __forceinline__ double block_max(double v, double *red) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) red[wave] = v;
+    __syncthreads();
+    double r = red[0];
+    for (int w = 1; w < kKeyThreads / 64; ++w) r = fmax(r, red[w]);
+    __syncthreads();
+    return r;
+}
+
+__global__ void __launch_bounds__(kKeyThreads) key_points_kernel(const KeyArgs a) {
+    __shared__ uint8_t flag[kKeyMaxN + 1];
+    __shared__ double red[kKeyThreads / 64];
+    const int line = blockIdx.x;
     const int N = a.px * a.m;
     const bool vertical = line < a.px - 1;
     double m1 = 0.0, m2 = 0.0;
-    for (int k = 1; k < N; ++k) {
+    for (int k = 1 + threadIdx.x; k < N; k += blockDim.x) {
         double f1, f2;
         line_f(a, line, k, f1, f2);
         m1 = fmax(m1, fabs(f1));
         m2 = fmax(m2, fabs(f2));
     }
-    const double t1 = a.tol * m1, t2 = a.tol * m2;
-    // extrema and crossings; every position this line owns is written once
-    double p1 = 0.0, p2 = 0.0, c1 = 0.0, c2 = 0.0, n1 = 0.0, n2 = 0.0;
-    if (N >= 3) line_f(a, line, 1, c1, c2);
-    for (int k = 1; k < N; ++k) {
-        if (k + 1 < N) line_f(a, line, k + 1, n1, n2);
-        bool key = (k % a.m == 0);
-        if (k >= 2 && k <= N - 2)
+    const double t1 = a.tol * block_max(m1, red), t2 = a.tol * block_max(m2, red);
+    // extrema and crossings
+    for (int k = threadIdx.x; k <= N; k += blockDim.x) {
+        bool key = (k == 0) || (k == N) || (k % a.m == 0);  // knots: the ends and the crossings
+        if (k >= 2 && k <= N - 2) {
+            double p1, p2, c1, c2, n1, n2;
+            line_f(a, line, k - 1, p1, p2);
+            line_f(a, line, k, c1, c2);
+            line_f(a, line, k + 1, n1, n2);
             key = key || (t1 > 0.0 && extremum(p1, c1, n1, t1)) || (t2 > 0.0 && extremum(p2, c2, n2, t2));
-        if (vertical || k % a.m != 0) a.mask[line_node(a.px, a.m, line, k)] = key ? 1 : 0;
-        p1 = c1; p2 = c2;
-        c1 = n1; c2 = n2;
-    }
-    // gap filling between consecutive knots (this thread's own writes above)
-    int prev = 0;
-    for (int k = 1; k <= N; ++k) {
-        const bool knot = (k == N) || (k % a.m == 0) || a.mask[line_node(a.px, a.m, line, k)] != 0;
-        if (!knot) continue;
-        const int g = k - prev;
-        if (g > a.max_gap) {
-            const int q = (g + a.max_gap - 1) / a.max_gap;
-            for (int r = 1; r < q; ++r) a.mask[line_node(a.px, a.m, line, prev + (r * g) / q)] = 1;
         }
-        prev = k;
+        flag[k] = key ? 1 : 0;
     }
+    __syncthreads();
+    // gap filling between consecutive knots
+    if (threadIdx.x == 0) {
+        int prev = 0;
+        for (int k = 1; k <= N; ++k) {
+            if (!flag[k]) continue;
+            const int g = k - prev;
+            if (g > a.max_gap) {
+                const int q = (g + a.max_gap - 1) / a.max_gap;
+                for (int r = 1; r < q; ++r) flag[prev + (r * g) / q] = 1;
+            }
+            prev = k;
+        }
+    }
+    __syncthreads();
+    // every position this line owns, written once (a crossing belongs to its vertical line)
+    for (int k = 1 + threadIdx.x; k < N; k += blockDim.x)
+        if (vertical || k % a.m != 0) a.mask[line_node(a.px, a.m, line, k)] = flag[k];
 }
 
 // ---------------------------------------------------------------------------
@@ -234,13 +259,12 @@ int fk_key_points(const double *grid_w, int32_t px, int32_t m, double tol, int32
                   hipStream_t stream) {
     g_last_error.clear();
     if (px < 2 || m < 2) return fail(FK_E_INVAL, "need px >= 2 and m >= 2");
-    if ((int64_t)px * m > 65535) return fail(FK_E_INVAL, "grid too large (px m > 65535)");
+    if ((int64_t)px * m > kKeyMaxN) return fail(FK_E_INVAL, "grid too large (px m > %d)", kKeyMaxN);
     if (!std::isfinite(tol) || tol < 0.0) return fail(FK_E_INVAL, "tol must be finite and >= 0");
     if (max_gap < 1) return fail(FK_E_INVAL, "max_gap must be >= 1");
     if (!grid_w || !mask) return fail(FK_E_INVAL, "NULL array");
     KeyArgs a{grid_w, (int)px, (int)m, tol, (int)max_gap, mask};
-    const int lines = 2 * (px - 1);
-    hipLaunchKernelGGL(key_points_kernel, dim3((unsigned)((lines + 63) / 64)), dim3(64), 0, stream, a);
+    hipLaunchKernelGGL(key_points_kernel, dim3((unsigned)(2 * (px - 1))), dim3(kKeyThreads), 0, stream, a);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? FK_OK : hip_fail(e, "key point kernel launch");
 }

@@ -737,8 +737,12 @@ static bool launch_lu(const SubArgs &a, int blocks, hipStream_t s, hipError_t *e
     };
     switch (a.m) {
     case 8: return go(subdomain_lu_kernel<8>, 8);
+    case 12: return go(subdomain_lu_kernel<12>, 12);
     case 16: return go(subdomain_lu_kernel<16>, 16);
+    case 20: return go(subdomain_lu_kernel<20>, 20);
+    case 24: return go(subdomain_lu_kernel<24>, 24);
     case 32: return go(subdomain_lu_kernel<32>, 32);
+    case 40: return go(subdomain_lu_kernel<40>, 40);
     case 48: return go(subdomain_lu_kernel<48>, 48);
     case 64: return go(subdomain_lu_kernel<64>, 64);
     case 96: return go(subdomain_lu_kernel<96>, 96);
