@@ -203,63 +203,115 @@ __device__ double edge_fraction(const double *cells, int N, int e, int i) {
 
 constexpr int kB = 32;   // steps per staging batch of the register-window kernel
 
-// Back substitution by one wavefront: x_k = (y_k - sum_j U[k][k+j] x_{k+j}) /
-// U[k][k] for k = n-1 .. 0.  Lane l holds x_{k+l+1} and x_{k+l+65} in
-// registers (shifted down one lane per row), and the U rows and y values are
-// loaded kD rows at a time, the next block while the current one is reduced.
+// Back substitution by one wavefront, kD rows at a time: x_k = (y_k -
+// sum_j U[k][k+j] x_{k+j}) / U[k][k] for k = n-1 .. 0.  Lane l holds
+// x_{top+l+1} and x_{top+l+65} (the ring; zero beyond n).  For the block of
+// rows k_j = top - j (j < kD) every lane forms its share of the sums over the
+// columns already solved (beyond top) for all kD rows and both components,
+// and one butterfly reduces all 2 kD of them; the kD x kD triangle inside
+// the block is then solved in registers (its U entries are wave-uniform
+// loads), and the ring shifts by kD.  The next block's U entries and y
+// values are loaded while the current one is reduced.
 template <int P1>
 __device__ __forceinline__ void back_substitute_blocked(const SubArgs &a, const double *U, const double *Y, int n,
                                                         int i0, int j0) {
     constexpr int p = P1 - 1, q = P1 - 1, kD = 8;
     const int N1 = a.N + 1;
     const int lane = threadIdx.x & 63;
-    double xr0 = 0.0, xr1 = 0.0;   // x_{k+lane+1}, x_{k+lane+65} (0 beyond n)
+    double xr0 = 0.0, xr1 = 0.0, yr0 = 0.0, yr1 = 0.0;   // x_{top+lane+1}, x_{top+lane+65}; eta likewise
     double c0[kD], c1[kD], cd[kD], cyx[kD], cyy[kD];
     double n0[kD], n1[kD], nd[kD], nyx[kD], nyy[kD];
+    // rows top - j: the entries multiplying the ring, the diagonal and y
     auto load = [&](int top, double *u0, double *u1, double *ud, double *yx, double *yy) {
 #pragma unroll
         for (int j = 0; j < kD; ++j) {
             const int k = top - j;
             const bool ok = k >= 0;
             const double *row = U + (int64_t)(ok ? k : 0) * P1;
-            u0[j] = (ok && lane + 1 <= p) ? row[lane + 1] : 0.0;
-            u1[j] = (ok && lane + 65 <= p) ? row[lane + 65] : 0.0;
+            const int o0 = j + 1 + lane, o1 = j + 65 + lane;
+            u0[j] = (ok && o0 <= p) ? row[o0] : 0.0;
+            u1[j] = (ok && o1 <= p) ? row[o1] : 0.0;
             ud[j] = ok ? row[0] : 1.0;
             yx[j] = ok ? Y[k] : 0.0;
             yy[j] = ok ? Y[n + k] : 0.0;
         }
     };
     load(n - 1, c0, c1, cd, cyx, cyy);
-    double yr0 = 0.0, yr1 = 0.0;   // the same for eta
     for (int top = n - 1; top >= 0; top -= kD) {
         load(top - kD, n0, n1, nd, nyx, nyy);
+        // 2 kD partial sums per lane, reduced across the wave by a butterfly
+        // that halves the values each lane keeps (offsets 32, 16, 8, 4: lane
+        // l ends with value l >> 2 summed over the 16 lanes that share its
+        // low two bits), then offsets 2 and 1 complete the sums.
+        double v[2 * kD];
+#pragma unroll
+        for (int j = 0; j < kD; ++j) {
+            v[j] = fma(c0[j], xr0, c1[j] * xr1);
+            v[kD + j] = fma(c0[j], yr0, c1[j] * yr1);
+        }
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            const int off = 32 >> st, half = kD >> st;   // values held: 2 half
+            const bool up = (lane & off) != 0;
+#pragma unroll
+            for (int t = 0; t < half; ++t) {
+                const double keep = up ? v[half + t] : v[t];
+                const double give = up ? v[t] : v[half + t];
+                v[t] = keep + __shfl_xor(give, off, 64);
+            }
+        }
+        double tot = v[0];
+        tot += __shfl_xor(tot, 2, 64);
+        tot += __shfl_xor(tot, 1, 64);
+        double sx[kD], sy[kD];
+#pragma unroll
+        for (int j = 0; j < kD; ++j) {
+            sx[j] = __shfl(tot, 4 * j, 64);
+            sy[j] = __shfl(tot, 4 * (kD + j), 64);
+        }
+        // the triangle inside the block
+        double xb[kD], yb[kD];
 #pragma unroll
         for (int j = 0; j < kD; ++j) {
             const int k = top - j;
-            if (k < 0) break;
-            // U entries of columns beyond n are zero, and so is the ring there
-            double sx = fma(c0[j], xr0, c1[j] * xr1);
-            double sy = fma(c0[j], yr0, c1[j] * yr1);
+            double tx = cyx[j] - sx[j], ty = cyy[j] - sy[j];
+            if (k >= 0) {
+                const double *row = U + (int64_t)k * P1;
 #pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                sx += __shfl_xor(sx, off, 64);
-                sy += __shfl_xor(sy, off, 64);
+                for (int i = 0; i < j; ++i) {
+                    const double u = row[j - i];   // U[k][k + (j - i)] multiplies x_{k_i}
+                    tx = fma(-u, xb[i], tx);
+                    ty = fma(-u, yb[i], ty);
+                }
             }
-            const double xk = (cyx[j] - sx) / cd[j], yk = (cyy[j] - sy) / cd[j];
-            const double x_top = __shfl(xr0, 63, 64), y_top = __shfl(yr0, 63, 64);
-            const double x1 = __shfl_up(xr1, 1, 64), y1 = __shfl_up(yr1, 1, 64);
-            const double x0 = __shfl_up(xr0, 1, 64), y0 = __shfl_up(yr0, 1, 64);
-            xr1 = (lane == 0) ? x_top : x1;
-            yr1 = (lane == 0) ? y_top : y1;
-            xr0 = (lane == 0) ? xk : x0;
-            yr0 = (lane == 0) ? yk : y0;
-            if (lane == 0) {
+            xb[j] = tx / cd[j];
+            yb[j] = ty / cd[j];
+        }
+#pragma unroll
+        for (int j = 0; j < kD; ++j) {
+            const int k = top - j;
+            if (lane == j && k >= 0) {
                 const int ii = k % q, jj = k / q;
                 const int64_t g = (int64_t)(j0 + 1 + jj) * N1 + (i0 + 1 + ii);
-                a.xi_out[g] = xk;
-                a.eta_out[g] = yk;
+                a.xi_out[g] = xb[j];
+                a.eta_out[g] = yb[j];
             }
         }
+        // shift the ring by kD: lane l now holds x_{top-kD+1+l}
+        const int src = (lane + 64 - kD) & 63;
+        const double sx0 = __shfl(xr0, src, 64), sx1 = __shfl(xr1, src, 64);
+        const double sy0 = __shfl(yr0, src, 64), sy1 = __shfl(yr1, src, 64);
+        double bx = 0.0, by = 0.0;
+#pragma unroll
+        for (int j = 0; j < kD; ++j) {
+            bx = (lane == kD - 1 - j) ? xb[j] : bx;
+            by = (lane == kD - 1 - j) ? yb[j] : by;
+        }
+        const bool head = lane < kD;
+        xr1 = head ? sx0 : sx1;
+        yr1 = head ? sy0 : sy1;
+        xr0 = head ? bx : sx0;
+        yr0 = head ? by : sy0;
 #pragma unroll
         for (int j = 0; j < kD; ++j) {
             c0[j] = n0[j];
