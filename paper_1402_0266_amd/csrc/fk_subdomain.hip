@@ -45,7 +45,20 @@ struct SubArgs {
     int kind;
     double amp, width2, cx, cy, orbit_r, omega, t_w;
     const double *wg;            // FK_DENSITY_GRID: samples of w on this grid, (N+1)^2
+    int twisted;                 // two workgroups per sub-domain, eliminating from both ends
+    int sep;                     // twisted: the separator's first row (its grid row times q)
+    double *sbuf;                // twisted, per sub-domain: both ends' separator blocks and rhs, then x_S
 };
+
+// Twisted elimination (two workgroups per sub-domain): the top workgroup
+// eliminates rows 0 .. sep-1 in the natural order, the bottom one rows
+// n-1 .. sep+q in reverse (the same kernel on the reversed system, in which
+// east/west and north/south swap).  Both stop at the separator, the grid row
+// of rows sep .. sep+q-1, which no other row couples across, and write its
+// block of their trailing window: A_SS minus their side's contribution.
+// The separator system is then A_SS - (top part) - (bottom part) = S_top +
+// S_bot - A_SS (a dense q x q solve), and each side back-substitutes from it.
+__host__ __device__ inline size_t sep_stride(int q) { return (size_t)2 * ((size_t)q * q + 2 * q) + 2 * q; }
 
 // ---------------------------------------------------------------------------
 // Grid densities (Sect. 4: w known at the grid points only; the derivatives
@@ -212,13 +225,22 @@ constexpr int kB = 32;   // steps per staging batch of the register-window kerne
 // the block is then solved in registers (its U entries are wave-uniform
 // loads), and the ring shifts by kD.  The next block's U entries and y
 // values are loaded while the current one is reduced.
+// top0: the last row to solve; xs (or nullptr): the separator's values, the
+// q unknowns after top0 (xi then eta; in reverse for the reversed system);
+// rev: rows are those of the reversed system (natural row n - 1 - k).
 template <int P1>
 __device__ __forceinline__ void back_substitute_blocked(const SubArgs &a, const double *U, const double *Y, int n,
-                                                        int i0, int j0) {
+                                                        int top0, int i0, int j0, const double *xs, bool rev) {
     constexpr int p = P1 - 1, q = P1 - 1, kD = 8;
     const int N1 = a.N + 1;
     const int lane = threadIdx.x & 63;
-    double xr0 = 0.0, xr1 = 0.0, yr0 = 0.0, yr1 = 0.0;   // x_{top+lane+1}, x_{top+lane+65}; eta likewise
+    // the ring: x_{top+lane+1}, x_{top+lane+65}; eta likewise
+    auto sep_val = [&](int t, int comp) -> double {
+        if (!xs || t >= q) return 0.0;
+        return xs[comp * q + (rev ? q - 1 - t : t)];
+    };
+    double xr0 = sep_val(lane, 0), xr1 = sep_val(lane + 64, 0);
+    double yr0 = sep_val(lane, 1), yr1 = sep_val(lane + 64, 1);
     double c0[kD], c1[kD], cd[kD], cyx[kD], cyy[kD];
     double n0[kD], n1[kD], nd[kD], nyx[kD], nyy[kD];
     // rows top - j: the entries multiplying the ring, the diagonal and y
@@ -236,8 +258,8 @@ __device__ __forceinline__ void back_substitute_blocked(const SubArgs &a, const 
             yy[j] = ok ? Y[n + k] : 0.0;
         }
     };
-    load(n - 1, c0, c1, cd, cyx, cyy);
-    for (int top = n - 1; top >= 0; top -= kD) {
+    load(top0, c0, c1, cd, cyx, cyy);
+    for (int top = top0; top >= 0; top -= kD) {
         load(top - kD, n0, n1, nd, nyx, nyy);
         // 2 kD partial sums per lane, reduced across the wave by a butterfly
         // that halves the values each lane keeps (offsets 32, 16, 8, 4: lane
@@ -291,7 +313,8 @@ __device__ __forceinline__ void back_substitute_blocked(const SubArgs &a, const 
         for (int j = 0; j < kD; ++j) {
             const int k = top - j;
             if (lane == j && k >= 0) {
-                const int ii = k % q, jj = k / q;
+                const int r = rev ? n - 1 - k : k;
+                const int ii = r % q, jj = r / q;
                 const int64_t g = (int64_t)(j0 + 1 + jj) * N1 + (i0 + 1 + ii);
                 a.xi_out[g] = xb[j];
                 a.eta_out[g] = yb[j];
@@ -353,13 +376,19 @@ __global__ void __launch_bounds__(256) subdomain_lu_kernel(const SubArgs a) {
     __shared__ double2 Rst[2][kB];      // right-hand sides of the entering rows R
     __shared__ double Nst[2][kB];       // north coefficients of the rows k + 1
     const int n = q * q;
-    const int si = blockIdx.x % a.px, sj = blockIdx.x / a.px;
+    const int sd = a.twisted ? blockIdx.x >> 1 : blockIdx.x;   // sub-domain
+    const bool rev = a.twisted && (blockIdx.x & 1);           // the reversed (bottom) end
+    const int si = sd % a.px, sj = sd / a.px;
     const int i0 = si * a.m, j0 = sj * a.m;
     const int N1 = a.N + 1;
-    double *U = a.ubuf + (int64_t)blockIdx.x * n * P1;
-    double *Y = a.ybuf + (int64_t)blockIdx.x * 2 * n;
-    double4 *cf = reinterpret_cast<double4 *>(a.cbuf + (int64_t)blockIdx.x * 4 * n);
-    double2 *rh = reinterpret_cast<double2 *>(a.rbuf + (int64_t)blockIdx.x * 2 * n);
+    // rows eliminated here, and where this end's U rows and y values go
+    const int steps = !a.twisted ? n : (rev ? n - a.sep - q : a.sep);
+    const int off = rev ? a.sep : 0;
+    double *U = a.ubuf + (int64_t)sd * n * P1 + (int64_t)off * P1;
+    double *Y = a.ybuf + (int64_t)sd * 2 * n + off;
+    const int64_t cix = a.twisted ? 2 * (int64_t)sd + (rev ? 1 : 0) : sd;
+    double4 *cf = reinterpret_cast<double4 *>(a.cbuf + cix * 4 * n);
+    double2 *rh = reinterpret_cast<double2 *>(a.rbuf + cix * 2 * n);
     const int tid = threadIdx.x;
 
     // ---- every row's coefficients (Dirichlet neighbours moved to the rhs) --
@@ -376,8 +405,11 @@ __global__ void __launch_bounds__(256) subdomain_lu_kernel(const SubArgs a) {
         if (ii == 0) { fx -= cW * a.xi_out[g - 1]; fy -= cW * a.eta_out[g - 1]; }
         if (jj == q - 1) { fx -= cN * a.xi_out[g + N1]; fy -= cN * a.eta_out[g + N1]; }
         if (jj == 0) { fx -= cS * a.xi_out[g - N1]; fy -= cS * a.eta_out[g - N1]; }
-        cf[r] = make_double4(ii < q - 1 ? cE : 0.0, ii > 0 ? cW : 0.0, jj < q - 1 ? cN : 0.0, jj > 0 ? cS : 0.0);
-        rh[r] = make_double2(fx, fy);
+        const double e = ii < q - 1 ? cE : 0.0, w = ii > 0 ? cW : 0.0;
+        const double nn = jj < q - 1 ? cN : 0.0, ss = jj > 0 ? cS : 0.0;
+        // the reversed system: row n-1-r, east <-> west, north <-> south
+        cf[rev ? n - 1 - r : r] = rev ? make_double4(w, e, ss, nn) : make_double4(e, w, nn, ss);
+        rh[rev ? n - 1 - r : r] = make_double2(fx, fy);
     }
     __threadfence_block();
     __syncthreads();
@@ -431,7 +463,7 @@ __global__ void __launch_bounds__(256) subdomain_lu_kernel(const SubArgs a) {
     double cE_Rm1 = (P1 - 1 < n) ? cf[P1 - 1].x : 0.0;   // east coefficient of row R - 1
 
     int owner = 0;
-    for (int k = 0; k < n; ++k) {
+    for (int k = 0; k < steps; ++k) {
         const int b = k & 1;
         const int R = k + P1;
         const int j = k % kB, bt = k / kB, bb = bt & 1;
@@ -507,7 +539,7 @@ __global__ void __launch_bounds__(256) subdomain_lu_kernel(const SubArgs a) {
     __syncthreads();
     {
         // the last batch
-        const int bt = (n - 1) / kB, bb = bt & 1, kp = bt * kB, cnt = n - kp;
+        const int bt = (steps - 1) / kB, bb = bt & 1, kp = bt * kB, cnt = steps - kp;
         const double *src = &Ust[bb][0][0];
         double *dstU = U + (int64_t)kp * P1;
         for (int e = tid; e < cnt * P1; e += blockDim.x) dstU[e] = src[e];
@@ -516,9 +548,103 @@ __global__ void __launch_bounds__(256) subdomain_lu_kernel(const SubArgs a) {
             Y[n + kp + tid] = Yst[bb][tid].y;
         }
     }
+    if (a.twisted) {
+        // the separator block of the trailing window (window rows and columns
+        // 0 .. q-1 are this end's separator rows) and its right-hand sides
+        double *S = a.sbuf + (int64_t)sd * sep_stride(q) + (rev ? (size_t)q * q + 2 * q : 0);
+        if (is_col) {
+            const int c = col - steps;
+#pragma unroll
+            for (int i = 0; i < H; ++i)
+                if (r0 + i < q && c < q) S[(r0 + i) * q + c] = v[i];
+        } else if (is_rhs) {
+#pragma unroll
+            for (int i = 0; i < H; ++i)
+                if (r0 + i < q) S[(size_t)q * q + rhs_c * q + r0 + i] = v[i];
+        }
+        return;
+    }
     __threadfence_block();
     __syncthreads();
-    if (tid < 64) back_substitute_blocked<P1>(a, U, Y, n, i0, j0);
+    if (tid < 64) back_substitute_blocked<P1>(a, U, Y, n, n - 1, i0, j0, nullptr, false);
+}
+
+// The separator system of a twisted elimination, one workgroup per
+// sub-domain: S_top + S_bot - A_SS and its right-hand sides assembled in
+// LDS, LU without pivoting (the Schur complement of a diagonally dominant
+// matrix is diagonally dominant), then x_S into the workspace and the grid.
+__global__ void __launch_bounds__(256) separator_kernel(const SubArgs a) {
+    extern __shared__ double M[];   // [q][q] then the two right-hand sides [2][q]
+    const int q = a.m - 1, n = q * q, sd = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    const int si = sd % a.px, sj = sd / a.px;
+    const int i0 = si * a.m, j0 = sj * a.m, N1 = a.N + 1;
+    double *S = a.sbuf + (int64_t)sd * sep_stride(q);
+    const double *St = S, *Sb = S + (size_t)q * q + 2 * q;
+    double *xs = S + 2 * ((size_t)q * q + 2 * q);
+    const double4 *cf = reinterpret_cast<const double4 *>(a.cbuf + (int64_t)(2 * sd) * 4 * n);   // natural order
+    const double2 *rh = reinterpret_cast<const double2 *>(a.rbuf + (int64_t)(2 * sd) * 2 * n);
+    const double diag = a.diag0 + 4.0 * a.c;
+    double *b = M + (size_t)q * q;
+    for (int e = tid; e < q * q; e += nt) {
+        const int r = e / q, c = e % q;
+        const double4 f = cf[a.sep + r];
+        const double A = c == r ? diag : (c == r + 1 ? f.x : (c == r - 1 ? f.y : 0.0));
+        M[e] = St[e] + Sb[(q - 1 - r) * q + (q - 1 - c)] - A;
+    }
+    for (int e = tid; e < 2 * q; e += nt) {
+        const int comp = e / q, r = e % q;
+        const double2 f = rh[a.sep + r];
+        b[e] = St[(size_t)q * q + e] + Sb[(size_t)q * q + comp * q + (q - 1 - r)] - (comp ? f.y : f.x);
+    }
+    __syncthreads();
+    for (int k = 0; k < q; ++k) {
+        const double inv = 1.0 / M[k * q + k];
+        const int w = q - 1 - k + 2;   // columns k+1 .. q-1, then the two right-hand sides
+        for (int e = tid; e < (q - 1 - k) * w; e += nt) {
+            const int i = k + 1 + e / w, jj = e % w;
+            const double l = M[i * q + k] * inv;
+            if (jj < q - 1 - k) {
+                const int j = k + 1 + jj;
+                M[i * q + j] = fma(-l, M[k * q + j], M[i * q + j]);
+            } else {
+                const int comp = jj - (q - 1 - k);
+                b[comp * q + i] = fma(-l, b[comp * q + k], b[comp * q + i]);
+            }
+        }
+        __syncthreads();
+    }
+    for (int k = q - 1; k >= 0; --k) {
+        if (tid < 2) b[tid * q + k] = b[tid * q + k] / M[k * q + k];
+        __syncthreads();
+        for (int e = tid; e < 2 * k; e += nt) {
+            const int comp = e / k, i = e % k;
+            b[comp * q + i] = fma(-M[i * q + k], b[comp * q + k], b[comp * q + i]);
+        }
+        __syncthreads();
+    }
+    const int jj = a.sep / q;
+    for (int e = tid; e < 2 * q; e += nt) {
+        const int comp = e / q, r = e % q;
+        xs[e] = b[e];
+        const int64_t g = (int64_t)(j0 + 1 + jj) * N1 + (i0 + 1 + r);
+        (comp ? a.eta_out : a.xi_out)[g] = b[e];
+    }
+}
+
+// Back substitution of each end of a twisted elimination, from the
+// separator's values: one wavefront per (sub-domain, end).
+template <int P1>
+__global__ void __launch_bounds__(64) twisted_back_kernel(const SubArgs a) {
+    constexpr int q = P1 - 1;
+    const int n = q * q;
+    const int sd = blockIdx.x >> 1;
+    const bool rev = (blockIdx.x & 1) != 0;
+    const int steps = rev ? n - a.sep - q : a.sep, off = rev ? a.sep : 0;
+    const int si = sd % a.px, sj = sd / a.px;
+    const double *U = a.ubuf + (int64_t)sd * n * P1 + (int64_t)off * P1;
+    const double *Y = a.ybuf + (int64_t)sd * 2 * n + off;
+    const double *xs = a.sbuf + (int64_t)sd * sep_stride(q) + 2 * ((size_t)q * q + 2 * q);
+    back_substitute_blocked<P1>(a, U, Y, n, steps - 1, si * a.m, sj * a.m, xs, rev);
 }
 
 
@@ -770,20 +896,28 @@ __global__ void __launch_bounds__(1024) quality_kernel(const double *xi, const d
     }
 }
 
+// Workspace: U rows, y values, row coefficients and right-hand sides (two
+// copies per sub-domain: natural and reversed order), the separator blocks,
+// and the edge integrals.
 static size_t sub_ws_bytes(int px, int m) {
     const size_t q = (size_t)m - 1, n = q * q, P1 = q + 1;
     const size_t blocks = (size_t)px * px, N = (size_t)px * m;
     return align256(blocks * n * P1 * sizeof(double)) + align256(blocks * 2 * n * sizeof(double)) +
-           align256(blocks * 4 * n * sizeof(double)) + align256(blocks * 2 * n * sizeof(double)) +
-           align256(4 * N * sizeof(double));
+           align256(2 * blocks * 4 * n * sizeof(double)) + align256(2 * blocks * 2 * n * sizeof(double)) +
+           align256(blocks * sep_stride((int)q) * sizeof(double)) + align256(4 * N * sizeof(double));
 }
+
+// Sides from which the twisted elimination (two workgroups per sub-domain)
+// is used: below, one workgroup's sequential steps are cheap and three
+// launches would cost more than they save.
+constexpr int kTwistedMinM = 32;
 
 // Launch of the register-window kernel for the window widths it is built
 // for; false if m is not one of them.
 static bool launch_lu(const SubArgs &a, int blocks, hipStream_t s, hipError_t *err) {
     auto go = [&](auto kern, int P1) {
         const int threads = ((2 * P1 + 4 + 63) / 64) * 64;
-        hipLaunchKernelGGL(kern, dim3((unsigned)blocks), dim3(threads), 0, s, a);
+        hipLaunchKernelGGL(kern, dim3((unsigned)(a.twisted ? 2 * blocks : blocks)), dim3(threads), 0, s, a);
         *err = hipGetLastError();
         return true;
     };
@@ -799,6 +933,29 @@ static bool launch_lu(const SubArgs &a, int blocks, hipStream_t s, hipError_t *e
     case 64: return go(subdomain_lu_kernel<64>, 64);
     case 96: return go(subdomain_lu_kernel<96>, 96);
     default: return false;
+    }
+}
+
+// The separator solves and the back substitutions of a twisted elimination.
+static hipError_t launch_twisted_rest(const SubArgs &a, int blocks, hipStream_t s) {
+    const int q = a.m - 1;
+    const size_t lds = ((size_t)q * q + 2 * q) * sizeof(double);
+    hipError_t e = hipFuncSetAttribute((const void *)separator_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                       (int)lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(separator_kernel, dim3((unsigned)blocks), dim3(256), lds, s, a);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    auto back = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3((unsigned)(2 * blocks)), dim3(64), 0, s, a);
+        return hipGetLastError();
+    };
+    switch (a.m) {
+    case 32: return back(twisted_back_kernel<32>);
+    case 40: return back(twisted_back_kernel<40>);
+    case 48: return back(twisted_back_kernel<48>);
+    case 64: return back(twisted_back_kernel<64>);
+    case 96: return back(twisted_back_kernel<96>);
+    default: return hipErrorInvalidValue;
     }
 }
 
@@ -876,9 +1033,11 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
     a.ybuf = (double *)ws;
     ws += align256(blocks * 2 * n * sizeof(double));
     a.cbuf = (double *)ws;
-    ws += align256(blocks * 4 * n * sizeof(double));
+    ws += align256(2 * blocks * 4 * n * sizeof(double));
     a.rbuf = (double *)ws;
-    ws += align256(blocks * 2 * n * sizeof(double));
+    ws += align256(2 * blocks * 2 * n * sizeof(double));
+    a.sbuf = (double *)ws;
+    ws += align256(blocks * sep_stride((int)q) * sizeof(double));
     double *edge_cells = (double *)ws;
     a.N = N;
     a.m = m;
@@ -907,10 +1066,16 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
     hipLaunchKernelGGL(dirichlet_kernel, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, stream, a, iface_xi,
                        iface_eta, n_iface, (int)bdry_kind, (const double *)edge_cells, xi_out, eta_out);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "dirichlet kernel launch");
+    // two workgroups per sub-domain from the separator grid row q/2
+    a.twisted = (m >= kTwistedMinM) ? 1 : 0;
+    a.sep = (int)((q / 2) * q);
     if (launch_lu(a, px * px, stream, &e)) {
         if (e != hipSuccess) return hip_fail(e, "sub-domain kernel launch");
+        if (a.twisted && (e = launch_twisted_rest(a, px * px, stream)) != hipSuccess)
+            return hip_fail(e, "separator / back substitution launch");
         return FK_OK;
     }
+    a.twisted = 0;
     // other sub-domain sizes: the window in LDS
     const size_t lds = (P1 * P1 + 4 * P1) * sizeof(double);
     if ((e = hipFuncSetAttribute((const void *)subdomain_be_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
