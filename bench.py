@@ -495,6 +495,8 @@ def main():
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": achieved / FP32_PEAK_TFLOPS,
+            # the same against the non-packed FP32 rate (one FMA per lane per cycle)
+            "frac_of_unpacked_fp32": achieved / (FP32_PEAK_TFLOPS / 2),
             "traffic": (TRAFFIC_BYTES_PER_PATH * n_nodes * n_star
                         if kernel_source_hash() == TRAFFIC_SOURCE_HASH else None),
             "flop_per_path_step": FLOP_PER_STEP,

@@ -106,3 +106,43 @@ def test_grid_density_entry_points_validate(fk):
     rc = lib.subdomain_solve(ctypes.byref(fk._density(_FakeGrid(12))), 0.0, 1e-3, 2, 8, 0, 4096, 4096, 4096, 4096,
                              4096, 4096, 4096, need, None)
     assert rc == -1 and "mesh grid" in fk.fk_last_error()
+
+
+def test_key_point_entry_points_validate(fk):
+    lib = fk.library()
+    assert lib.fk_key_points(4096, 1, 8, 1e-2, 4, 8192, None) == -1          # px < 2
+    assert lib.fk_key_points(4096, 2, 1, 1e-2, 4, 8192, None) == -1          # m < 2
+    assert lib.fk_key_points(4096, 2, 8, -1.0, 4, 8192, None) == -1         # tol < 0
+    assert lib.fk_key_points(4096, 2, 8, float("nan"), 4, 8192, None) == -1
+    assert lib.fk_key_points(4096, 2, 8, 1e-2, 0, 8192, None) == -1          # max_gap < 1
+    assert lib.fk_key_points(None, 2, 8, 1e-2, 4, 8192, None) == -1
+    assert lib.fk_key_points(4096, 128, 128, 1e-2, 4, 8192, None) == -1      # grid too large
+    assert lib.fk_interface_interpolate(1, 8, 4096, 1, 4096, 4096, 4096, 4096, 4096, 4096, None) == -1
+    assert lib.fk_interface_interpolate(2, 8, 4096, -1, 4096, 4096, 4096, 4096, 4096, 4096, None) == -1
+    assert lib.fk_interface_interpolate(2, 8, None, 1, 4096, 4096, 4096, 4096, 4096, 4096, None) == -1
+    assert lib.fk_interface_interpolate(2, 8, 4096, 3, None, 4096, 4096, 4096, 4096, 4096, None) == -1
+    d = ctypes.byref(fk._density(W.static_bump()))
+    assert lib.fk_boundary_data(d, 0.0, 1, 0, 4096, 4096, None, 0, None) == -1          # n < 2
+    assert lib.fk_boundary_data(d, 0.0, 16, 7, 4096, 4096, None, 0, None) == -1         # unknown kind
+    assert lib.fk_boundary_data(d, 0.0, 16, 4, 4096, 4096, None, 0, None) == -3         # needs workspace
+    assert lib.fk_boundary_data(ctypes.byref(fk._density(_FakeGrid(12))), 0.0, 16, 0, 4096, 4096, None, 0,
+                                None) == -1                                             # grid_n != n
+
+
+def test_bridge_and_grid_boundary_validation(fk):
+    # grid boundary data needs grid initial data and a projecting score mode
+    assert _call(fk, data=W.Data(bdry_kind=W.DATA_GRID, score_mode=W.SCORE_BRIDGE)) == -1
+    assert _call(fk, data=W.Data(score_mode=7)) == -1
+    assert fk.library().fk_boundary_workspace_bytes(1) == 0
+    assert fk.library().fk_boundary_workspace_bytes(40) >= 4 * 40 * 8
+
+
+def test_steady_subdomain_validation(fk):
+    lib = fk.library()
+    d = ctypes.byref(fk._density(W.static_bump()))
+    need = lib.subdomain_workspace_bytes(2, 8)
+    nan, inf = float("nan"), float("inf")
+    assert lib.subdomain_solve(d, 0.0, nan, 2, 8, 0, 4096, 4096, 4096, 4096, 4096, 4096, 4096, need, None) == -1
+    assert lib.subdomain_solve(d, 0.0, -inf, 2, 8, 0, 4096, 4096, 4096, 4096, 4096, 4096, 4096, need, None) == -1
+    # transient solves need the previous mesh
+    assert lib.subdomain_solve(d, 0.0, 1e-3, 2, 8, 0, None, None, 4096, 4096, 4096, 4096, 4096, need, None) == -1
