@@ -34,7 +34,8 @@ The same line reports, as extra objects:
   on the grid, finite-difference drift, bilinear between nodes), and with
   that data path and key points (the run as the paper describes it).
 * "steady": the elliptic variant -- one-shot steady meshes of the static
-  bump (1521 interface nodes) and of the paper's ring (41 x 41 grid).
+  bump (64-cell grid) and of the paper's ring (41 x 41 grid), with the
+  global steady solve beside them.
 * "mesh_run": the time-dependent run -- 8 x 8 sub-domains on a 768-cell
   grid, two counter-rotating bumps, 200 mesh steps of 5e-4 with 20
   Euler-Maruyama steps each, 2^14 paths per interface node (10689 nodes),
@@ -312,17 +313,19 @@ def measure_bridge(fk, wl, pts, fd, pilot_paths=100000):
 
 
 def measure_steady():
-    """The elliptic (steady) variant (eq. (2)): one-shot steady meshes --
-    the static bump on 4 x 4 sub-domains of a 256-cell grid (1521 interface
-    nodes, 2^16 paths, dt 1e-5) and the paper's ring at t = 0 on its 41 x 41
-    grid (2 x 2 sub-domains, 10^4 paths, dt 1e-4, equidistributed edges)."""
+    """The elliptic (steady) variant (eq. (2)): one-shot steady meshes, with
+    the global steady solve (one sub-domain, the same banded LU) beside them
+    -- the static bump on 2 x 2 sub-domains of a 64-cell grid (125 interface
+    nodes, 2^18 paths) and the paper's ring at t = 0 on its 41 x 41 grid
+    (2 x 2 sub-domains, 10^5 paths, equidistributed edges); dt 1e-4 with the
+    bridge exit test."""
     import torch
     from paper_1402_0266_amd.mesh_run import DATA_EQUIDISTRIBUTED, DATA_IDENTITY, paper_ring_density, steady_mesh
     import paper_1402_0266_amd as fk
     res = {}
     for name, dens, px, m, n_paths, dt, horizon, bdry in (
-            ("static_bump_1521", W.static_bump(), 4, 64, 1 << 16, 1e-5, 3.0, DATA_IDENTITY),
-            ("paper_ring_77", paper_ring_density(0.0), 2, 20, 10000, 1e-4, 20.0, DATA_EQUIDISTRIBUTED)):
+            ("static_bump_125", W.static_bump(), 2, 32, 1 << 18, 1e-4, 3.0, DATA_IDENTITY),
+            ("paper_ring_77", paper_ring_density(0.0), 2, 20, 100000, 1e-4, 20.0, DATA_EQUIDISTRIBUTED)):
         print(f"[bench] steady mesh: {name}", file=sys.stderr, flush=True)
         steady_mesh(dens, px, m, 256, dt, horizon, bdry=bdry)        # first-launch costs
         fk.fk_timing_enable(True)
@@ -334,10 +337,17 @@ def measure_steady():
         kms, _ = fk.fk_timing_last()
         fk.fk_timing_enable(False)
         q = fk.fk_mesh_quality(g["xi"], g["eta"]).cpu().numpy()
+        # the global steady solve on the same grid: one sub-domain, no interfaces
+        N = px * m
+        empty = torch.empty(0, dtype=torch.float64, device="cuda")
+        gx, gy = fk.subdomain_solve(dens, 0.0, float("inf"), 1, N, None, None, empty, empty, bdry_kind=bdry)
+        qg = fk.fk_mesh_quality(gx, gy).cpu().numpy()
         se = torch.stack([g["se_xi"], g["se_eta"]]).cpu().numpy()
         res[name] = {"nodes": int(g["iface_xi"].numel()), "paths": n_paths, "dt": dt, "horizon": horizon,
                      "s": wall, "path_kernel_ms": kms, "survivors": int(g["survivors"]),
-                     "min_jac": float(q[0]), "max_skew": float(q[1]), "se_median": float(np.median(se))}
+                     "min_jac": float(q[0]), "max_skew": float(q[1]), "se_median": float(np.median(se)),
+                     "global_steady_min_jac": float(qg[0]), "global_steady_max_skew": float(qg[1]),
+                     "max_diff_vs_global": float(max((g["xi"] - gx).abs().max(), (g["eta"] - gy).abs().max()))}
     return res
 
 

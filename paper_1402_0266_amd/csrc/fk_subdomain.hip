@@ -910,7 +910,7 @@ static size_t sub_ws_bytes(int px, int m) {
 // Sides from which the twisted elimination (two workgroups per sub-domain)
 // is used: below, one workgroup's sequential steps are cheap and three
 // launches would cost more than they save.
-constexpr int kTwistedMinM = 32;
+constexpr int kTwistedMinM = 16;
 
 // Launch of the register-window kernel for the window widths it is built
 // for; false if m is not one of them.
@@ -950,6 +950,9 @@ static hipError_t launch_twisted_rest(const SubArgs &a, int blocks, hipStream_t 
         return hipGetLastError();
     };
     switch (a.m) {
+    case 16: return back(twisted_back_kernel<16>);
+    case 20: return back(twisted_back_kernel<20>);
+    case 24: return back(twisted_back_kernel<24>);
     case 32: return back(twisted_back_kernel<32>);
     case 40: return back(twisted_back_kernel<40>);
     case 48: return back(twisted_back_kernel<48>);
