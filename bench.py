@@ -129,7 +129,7 @@ def _stack(r, keys):
     return np.stack([r[keys[0]].cpu().numpy(), r[keys[1]].cpu().numpy()], 1)
 
 
-def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=4096):
+def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=4096, identity_base=False):
     """Labels, training and the control-variate solve; nodes/s at RMS 1e-3."""
     import torch
     from paper_1402_0266_amd import cv_pipeline as P
@@ -142,7 +142,7 @@ def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=409
                                 seed=1)
     torch.cuda.synchronize()
     t_labels = time.perf_counter() - t0
-    cv = fk.FkCv(W.mlp_init(0), W.CV_T_SCALE)
+    cv = fk.FkCv(W.mlp_init(0), W.CV_T_SCALE, identity_base=identity_base)
     t0 = time.perf_counter()
     loss = P.train(cv, txy, target, steps=2000, batch=8192, lr=1e-3, seed=2)
     torch.cuda.synchronize()
@@ -189,6 +189,29 @@ def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=409
     fk.fk_timing_enable(False)
     rms = float(np.sqrt(np.mean((_stack(r, ("xi", "eta")) - ref) ** 2)))
     cv.close()
+    # Beside the network: the same martingale estimator with the identity
+    # map's gradient (the linear control, no training).  The identity data
+    # posed as a 256-cell identity grid scored past the edge give the same
+    # scores; its bilinear gradient is exactly I.
+    import dataclasses
+    G = 256
+    x = torch.arange(G + 1, dtype=torch.float64, device="cuda") / G
+    gx, gy = x.repeat(G + 1, 1).contiguous(), x[:, None].repeat(1, G + 1).contiguous()
+    gdata = dataclasses.replace(wl.data, init_kind=W.DATA_GRID, score_mode=W.SCORE_EXTEND)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rl = fk.fk_interface_solve_cv(wl.density, gdata, pts, wl.t, wl.dt, pilot_paths, None, stride=1 << 20,
+                                  seed=wl.seed, form=fk.FK_CV_MARTINGALE_GRID, grids=(gx.view(-1), gy.view(-1)))
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    est, se = _stack(rl, ("xi", "eta")), _stack(rl, ("se_xi", "se_eta"))
+    pse = _stack(rl, ("plain_se_xi", "plain_se_eta"))
+    var = float(np.mean(se ** 2) * pilot_paths)
+    b2 = max(0.0, float(np.mean((est - ref) ** 2)) - var / pilot_paths)
+    n_lin = int(math.ceil(var / (1e-6 - b2))) if b2 < 1e-6 else None
+    linear = {"form": "martingale, identity gradient", "pilot_s": el, "var": var,
+              "var_ratio": float(np.mean(pse ** 2) / np.mean(se ** 2)), "bias": math.sqrt(b2), "n_star": n_lin,
+              "predicted_nodes_per_s": None if n_lin is None else n_nodes / (el * n_lin / pilot_paths)}
     return {
         "form": "martingale", "stride": stride, "paths_per_node": n_star, "rms_err": rms,
         "s_per_solve": wall, "path_kernel_ms": float(np.mean(kern)),
@@ -198,6 +221,7 @@ def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=409
         "training": {"steps": 2000, "batch": 8192, "lr": 1e-3, "s": t_train, "loss_first": float(loss[0]),
                      "loss_last50": float(loss[-50:].mean())},
         "pilots": pilots,
+        "linear_control": linear,
     }
 
 

@@ -381,6 +381,13 @@ void fk_cv_destroy(fk_cv_t cv);
 /* params: host [8706] FP32 master weights or NULL; bf16_params: host [8706]
  * BF16 bit patterns of the network or NULL. */
 int fk_cv_get_params(fk_cv_t cv, float *params, uint16_t *bf16_params);
+/* The identity base: with on = 1 the control is u_hat = (x, y) + network --
+ * the network fits the deviation of the mesh map from the identity.  Training
+ * then fits target - (x, y), and every evaluation (fk_cv_eval, the node value
+ * and the path evaluations of fk_interface_solve_cv) adds x to xi, y to eta
+ * and the identity to their gradients.  Applies to all later calls; 0 (the
+ * default) is the plain network. */
+int fk_cv_set_identity_base(fk_cv_t cv, int32_t on);
 int fk_cv_set_params(fk_cv_t cv, const float *params /* host [8706] */);
 /* Forward-mode evaluation at n points txy (device [n][3]: t, x, y):
  * out (device [n][2][5]) = for each output: value, d/dx, d/dy, d/dt,

@@ -206,7 +206,8 @@ def fk_paths(dens, data, pts, node_ids, path_ids, t, dt, seed=0, level_id=0, str
     return sc, ex
 
 
-UHAT_MLP, UHAT_LINEAR, UHAT_SIN, UHAT_ZERO, UHAT_GRID = 0, 1, 2, 3, 4   # GRID: the grid initial data
+UHAT_MLP, UHAT_LINEAR, UHAT_SIN, UHAT_ZERO, UHAT_GRID, UHAT_MLP_BASE = 0, 1, 2, 3, 4, 5
+# GRID: the grid initial data; MLP_BASE: the identity map plus the MLP
 CV_DYNKIN, CV_MARTINGALE = 0, 1   # forms of the control-variate estimator
 
 

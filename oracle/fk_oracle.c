@@ -619,7 +619,8 @@ int or_fk_paths(int kind, int time_mode, const double *par, const double *w_grid
  * u_hat kinds: 0 the tanh MLP 3-64-64-64-2 (flat FP64 parameters, input
  * z = (2 tau / T - 1, 2x - 1, 2y - 1)); 1 the linear maps (x, y); 2 the
  * decaying sine mode exp(-2 pi^2 (tau - t_init)) sin(pi x) sin(pi y) for
- * both components; 3 zero.
+ * both components; 3 zero; 4 the grid initial data (martingale form); 5 the
+ * MLP plus the identity map (the network as the deviation from it).
  * ------------------------------------------------------------------------- */
 typedef struct {
     const double *W1, *b1, *W2, *b2, *W3, *b3, *W4, *b4;
@@ -734,6 +735,15 @@ static void uhat_eval(const or_uhat *u, double tau, double x, double y, double o
     }
     switch (u->kind) {
     case 0: mlp_forward_mode(&u->mlp, tau, x, y, out); return;
+    case 5:
+        /* the network fits the deviation from the identity map:
+           u_hat = (x, y) + MLP */
+        mlp_forward_mode(&u->mlp, tau, x, y, out);
+        out[0][0] += x;
+        out[1][0] += y;
+        out[0][1] += 1.0;
+        out[1][2] += 1.0;
+        return;
     case 1:
         out[0][0] = x; out[0][1] = 1.0; out[0][2] = 0.0; out[0][3] = 0.0; out[0][4] = 0.0;
         out[1][0] = y; out[1][1] = 0.0; out[1][2] = 1.0; out[1][3] = 0.0; out[1][4] = 0.0;
@@ -906,7 +916,7 @@ int or_fk_solve_cv(int kind, int time_mode, const double *par, const double *w_g
 {
     if (n_nodes < 0 || n_paths < 2 || !(dt > 0.0) || !(t >= 0.0) || stride < 1) return -1;
     if (form != 0 && form != 1) return -1;
-    if (uhat_kind == 0 && !flat) return -1;
+    if ((uhat_kind == 0 || uhat_kind == 5) && !flat) return -1;
     or_problem pb;
     pb.kind = kind;
     pb.time_mode = time_mode;
@@ -933,7 +943,7 @@ int or_fk_solve_cv(int kind, int time_mode, const double *par, const double *w_g
     u.grid_xi = grid_xi;
     u.grid_eta = grid_eta;
     u.grid_n = grid_n;
-    if (uhat_kind == 0) mlp_bind(&u.mlp, flat, t_scale);
+    if (uhat_kind == 0 || uhat_kind == 5) mlp_bind(&u.mlp, flat, t_scale);
     /* the grid's bilinear interpolant has no Laplacian: martingale form only */
     if (uhat_kind == 4 && (form != 1 || init_kind != D_GRID || !grid_xi || !grid_eta)) return -1;
     const int64_t total = n_nodes * n_paths;

@@ -128,6 +128,8 @@ _lib.fk_mesh_quality.argtypes = [_P, _P, ctypes.c_int32, _P, _P]
 _lib.fk_mesh_quality.restype = ctypes.c_int
 _lib.fk_cv_create.argtypes = [_P, ctypes.c_double, ctypes.POINTER(_P)]
 _lib.fk_cv_create.restype = ctypes.c_int
+_lib.fk_cv_set_identity_base.argtypes = [_P, ctypes.c_int32]
+_lib.fk_cv_set_identity_base.restype = ctypes.c_int
 _lib.fk_cv_destroy.argtypes = [_P]
 _lib.fk_cv_destroy.restype = None
 _lib.fk_cv_get_params.argtypes = [_P, _P, _P]
@@ -527,7 +529,7 @@ FK_CV_N_PARAMS = 8706
 class FkCv:
     """The control-variate network (C: ``fk_cv_*``)."""
 
-    def __init__(self, params, t_scale=0.1):
+    def __init__(self, params, t_scale=0.1, identity_base=False):
         p = np.ascontiguousarray(params, dtype=np.float32).ravel()
         if p.size != FK_CV_N_PARAMS:
             raise ValueError("need 8706 parameters")
@@ -535,6 +537,9 @@ class FkCv:
         _check(_lib.fk_cv_create(p.ctypes.data_as(ctypes.c_void_p), float(t_scale), ctypes.byref(h)))
         self._h = h
         self.t_scale = float(t_scale)
+        self.identity_base = bool(identity_base)
+        if identity_base:
+            _check(_lib.fk_cv_set_identity_base(h, 1))
 
     def close(self):
         if getattr(self, "_h", None) and _lib is not None:

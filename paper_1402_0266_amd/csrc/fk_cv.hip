@@ -56,6 +56,7 @@ struct CvState {
 struct fk_cv {
     int device = 0;
     float t_scale = 0.1f;
+    float base = 0.f;    // 1: u_hat = (x, y) + network (the identity base)
     int64_t steps_done = 0;
     fk::CvState s;
 };
@@ -113,6 +114,20 @@ __device__ __forceinline__ void split_bf16(float v, short &hi, short &lo) {
     const __bf16 h = (__bf16)v;
     hi = __builtin_bit_cast(short, h);
     lo = __builtin_bit_cast(short, (__bf16)(v - (float)h));
+}
+
+// The identity base (base = 1): u_hat = (x, y) + network, so the value of
+// xi gains x and that of eta gains y, and their gradients the identity; the
+// d/dtau and Laplacian channels are unchanged.
+__device__ __forceinline__ void add_base(float base, float x, float y, float o[2][5]) {
+    o[0][0] = fmaf(base, x, o[0][0]);
+    o[1][0] = fmaf(base, y, o[1][0]);
+    o[0][1] += base;
+    o[1][2] += base;
+}
+__device__ __forceinline__ void add_base_grad(float base, float o[2][2]) {
+    o[0][0] += base;
+    o[1][1] += base;
 }
 
 __device__ __forceinline__ fk_f4 mfma16(fk_s4 a, fk_s4 b, fk_f4 c) {
@@ -376,8 +391,8 @@ __device__ void net_grad_wave(const NetLds &N, float tscale2, float tau, float x
 // ---------------------------------------------------------------------------
 // Evaluation at given points (also the parity hook of the path evaluation).
 // ---------------------------------------------------------------------------
-__global__ void __launch_bounds__(256) cv_eval_kernel(const uint16_t *bf, float tscale2, const float *txy, int64_t n,
-                                                      float *out) {
+__global__ void __launch_bounds__(256) cv_eval_kernel(const uint16_t *bf, float tscale2, float base, const float *txy,
+                                                      int64_t n, float *out) {
     __shared__ NetLds N;
     load_net(N, bf);
     __syncthreads();
@@ -386,6 +401,7 @@ __global__ void __launch_bounds__(256) cv_eval_kernel(const uint16_t *bf, float 
     const float t = ok ? txy[3 * i] : 0.f, x = ok ? txy[3 * i + 1] : 0.5f, y = ok ? txy[3 * i + 2] : 0.5f;
     float o[2][5];
     net_eval_wave(N, tscale2, t, x, y, o);
+    add_base(base, x, y, o);
     if (ok)
         for (int c = 0; c < 2; ++c)
             for (int k = 0; k < 5; ++k) out[10 * i + 5 * c + k] = o[c][k];
@@ -398,6 +414,7 @@ struct CvArgs {
     const uint16_t *bf;
     float tscale2;               // 2 / T
     uint32_t stride_iters;       // network evaluations every stride_iters iterations (2 steps each)
+    float base;                  // identity base (0 or 1)
     const float2 *r0;            // [n_out] integrand at the start point of each node
     float2 *cv_scores;           // [n_out * n_paths]
 };
@@ -455,6 +472,7 @@ __global__ void __launch_bounds__(256, 2) fk_cv_path_kernel(const PathArgs a, co
                 const float tau = ev ? tend - sk : 0.f;
                 float o[2][5];
                 net_eval_wave(N, c.tscale2, tau, ev ? L.xh : 0.5f, ev ? L.yh : 0.5f, o);
+                add_base(c.base, L.xh, L.yh, o);
                 // integrand at this state; for a parked path its end state,
                 // with the drift at the end time
                 float bx = 0.f, by = 0.f;
@@ -569,6 +587,7 @@ struct MgArgs {
     const uint16_t *bf;
     float tscale2;
     uint32_t stride_iters;
+    float base;                  // identity base (0 or 1)
     const float4 *g0;            // [n_out] (dxi/dx, dxi/dy, deta/dx, deta/dy) at the start point
     float2 *cv_scores;           // [n_out * n_paths], absolute
 };
@@ -598,6 +617,7 @@ __global__ void __launch_bounds__(256, 2) fk_mg_path_kernel(const PathArgs a, co
                 const float tau = active ? tend - (float)L.k * L.dt : 0.f;
                 float o[2][2];
                 net_grad_wave(N, c.tscale2, tau, active ? L.xh : 0.5f, active ? L.yh : 0.5f, o);
+                add_base_grad(c.base, o);
                 if (active) {
                     mx = fmaf(gxx, dbx, fmaf(gxy, dby, mx));
                     my = fmaf(gyx, dbx, fmaf(gyy, dby, my));
@@ -830,6 +850,7 @@ struct CvNodeArgs {
     float2 *r0;        // integrand at P, or NULL
     float4 *g0;        // gradient of both outputs at P, or NULL
     int kind, time_mode;
+    float base;        // identity base (0 or 1)
 };
 
 template <int KIND, int TMODE>
@@ -848,16 +869,22 @@ __global__ void __launch_bounds__(256) cv_node_kernel(const CvNodeArgs na, const
     } else {
         L.xh = 0.5f;
         L.yh = 0.5f;
+        L.xl = 0.f;
+        L.yl = 0.f;
     }
     float o[2][5];
     net_eval_wave(N, tscale2, tend, L.xh, L.yh, o);
+    // the value's base in FP64 from the node's hi + lo coordinates
+    const double vx = (double)o[0][0] + na.base * ((double)L.xh + (double)L.xl);
+    const double vy = (double)o[1][0] + na.base * ((double)L.yh + (double)L.yl);
+    add_base(na.base, L.xh, L.yh, o);
     if (ok) {
         const NodeDev nd = na.nodes[s];
         float bx, by;
         drift_at<KIND, TMODE, true>(L, bx, by);
         if (na.outs_cv) {
-            na.outs_cv[nd.out].shift_x = (double)o[0][0];
-            na.outs_cv[nd.out].shift_y = (double)o[1][0];
+            na.outs_cv[nd.out].shift_x = vx;
+            na.outs_cv[nd.out].shift_y = vy;
         }
         if (na.r0)
             na.r0[nd.out] = make_float2(o[0][4] + fmaf(bx, o[0][1], by * o[0][2]) - o[0][3],
@@ -890,6 +917,7 @@ struct TrainArgs {
     int full;              // 1: tile b takes samples 64 b .. 64 b + 63; 0: Philox minibatch
     uint32_t step, key0, key1;
     float tscale2;
+    float base;            // identity base: the network fits target - (x, y)
     float *partial;        // [tiles][kNP + 1]
 };
 
@@ -941,8 +969,8 @@ __global__ void __launch_bounds__(256) cv_grad_kernel(const TrainArgs ta) {
         S.z[0][tid] = ta.txy[3 * idx] * ta.tscale2 - 1.f;
         S.z[1][tid] = 2.f * ta.txy[3 * idx + 1] - 1.f;
         S.z[2][tid] = 2.f * ta.txy[3 * idx + 2] - 1.f;
-        S.y[0][tid] = ta.target[2 * idx];
-        S.y[1][tid] = ta.target[2 * idx + 1];
+        S.y[0][tid] = fmaf(-ta.base, ta.txy[3 * idx + 1], ta.target[2 * idx]);
+        S.y[1][tid] = fmaf(-ta.base, ta.txy[3 * idx + 2], ta.target[2 * idx + 1]);
         S.dout[0][tid] = valid ? 1.f : 0.f;  // validity mask until the residual is known
     }
     __syncthreads();
@@ -1278,6 +1306,14 @@ int fk_cv_create(const float *params, double t_scale, fk_cv_t *out) {
     return FK_OK;
 }
 
+int fk_cv_set_identity_base(fk_cv_t cv, int32_t on) {
+    g_last_error.clear();
+    if (!cv) return fail(FK_E_INVAL, "network is NULL");
+    if (on != 0 && on != 1) return fail(FK_E_INVAL, "on must be 0 or 1");
+    cv->base = (float)on;
+    return FK_OK;
+}
+
 void fk_cv_destroy(fk_cv_t cv) {
     if (!cv) return;
     if (cv->s.master) hipFree(cv->s.master);
@@ -1314,8 +1350,8 @@ int fk_cv_eval(fk_cv_t cv, const float *txy, int64_t n, float *out, hipStream_t 
     if (n == 0) return FK_OK;
     if (!txy || !out) return fail(FK_E_INVAL, "NULL array");
     const int64_t blocks = (n + 255) / 256;
-    hipLaunchKernelGGL(cv_eval_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, cv->s.bf, 2.f / cv->t_scale, txy,
-                       n, out);
+    hipLaunchKernelGGL(cv_eval_kernel, dim3((unsigned)blocks), dim3(256), 0, stream, cv->s.bf, 2.f / cv->t_scale,
+                       cv->base, txy, n, out);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? FK_OK : hip_fail(e, "eval kernel launch");
 }
@@ -1337,6 +1373,7 @@ int fk_cv_grad(fk_cv_t cv, const float *txy, const float *target, int64_t n, flo
     ta.batch = n;
     ta.full = 1;
     ta.tscale2 = 2.f / cv->t_scale;
+    ta.base = cv->base;
     ta.partial = cv->s.partial;
     hipError_t e = launch_grad(ta, tiles, stream);
     if (e != hipSuccess) return hip_fail(e, "gradient kernel launch");
@@ -1388,6 +1425,7 @@ int fk_cv_train(fk_cv_t cv, const float *txy, const float *target, int64_t n, in
         ta.key0 = (uint32_t)seed;
         ta.key1 = (uint32_t)(seed >> 32);
         ta.tscale2 = 2.f / cv->t_scale;
+        ta.base = cv->base;
         ta.partial = cv->s.partial;
         hipError_t e = launch_grad(ta, tiles, stream);
         if (e != hipSuccess) return hip_fail(e, "gradient kernel launch");
@@ -1482,6 +1520,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     na.outs_cv = mg ? nullptr : (OutDev *)(ws + lay.outs_cv);
     na.r0 = mg ? nullptr : (float2 *)(ws + lay.r0);
     na.g0 = mg ? (float4 *)(ws + lay.g0) : nullptr;
+    na.base = grid_ctl ? 0.f : cv->base;
     const float ts2 = grid_ctl ? 0.f : 2.f / cv->t_scale;
     if ((e = timing_record(0, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     if (!grid_ctl &&
@@ -1512,6 +1551,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         c.bf = cv->s.bf;
         c.tscale2 = ts2;
         c.stride_iters = (uint32_t)(stride / 2);
+        c.base = cv->base;
         c.r0 = (const float2 *)(ws + lay.r0);
         c.cv_scores = cv_rec;
         const int occ = cv_dispatch<CvOccF>(T.kind, T.time_mode, T.uniform);
@@ -1531,6 +1571,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         c.bf = cv->s.bf;
         c.tscale2 = ts2;
         c.stride_iters = (uint32_t)(stride / 2);
+        c.base = grid_ctl ? 0.f : cv->base;
         c.g0 = (const float4 *)(ws + lay.g0);
         c.cv_scores = cv_rec;
         const int occ = cv_dispatch<MgOccF>(T.kind, T.time_mode, T.uniform);

@@ -182,3 +182,28 @@ def test_grid_control_needs_the_martingale_form(oracle_mod):
     with pytest.raises(ValueError):
         oracle_mod.fk_solve_cv(W.CONST, data, [[0.5, 0.5]], 0.01, 1e-3, 10, uhat=oracle_mod.UHAT_GRID,
                                form=oracle_mod.CV_DYNKIN)
+
+
+@pytest.mark.parametrize("form", ["dynkin", "martingale"])
+def test_identity_base_is_the_identity_plus_the_network(oracle_mod, form):
+    """Both estimator forms are affine in u_hat (the martingale sum and the
+    Dynkin terms are linear in it; g enters once), so for any network, per
+    path: score(identity + network) = score(network) + score(identity) -
+    score(0).  With a zero network the base is the linear control itself."""
+    f = oracle_mod.CV_DYNKIN if form == "dynkin" else oracle_mod.CV_MARTINGALE
+    dens, pts = W.moving_bump(), W.uniform_points(6, seed=9)
+    flat = W.mlp_init(4).astype(np.float64)
+    kw = dict(seed=3, stride=4, form=f, want_scores=True, threads=4)
+
+    def run(uhat, fl=None):
+        return oracle_mod.fk_solve_cv(dens, W.Data(), pts, 0.01, 1e-3, 300, uhat=uhat, flat=fl, **kw)
+
+    base = run(oracle_mod.UHAT_MLP_BASE, flat)
+    net = run(oracle_mod.UHAT_MLP, flat)
+    lin = run(oracle_mod.UHAT_LINEAR)
+    zero = run(oracle_mod.UHAT_ZERO)
+    expect = net["cv_scores"] + lin["cv_scores"] - zero["cv_scores"]
+    assert np.abs(base["cv_scores"] - expect).max() < 1e-12
+    assert np.abs(base["mean"] - (net["mean"] + lin["mean"] - zero["mean"])).max() < 1e-12
+    zero_net = run(oracle_mod.UHAT_MLP_BASE, np.zeros_like(flat))
+    assert np.array_equal(zero_net["cv_scores"], lin["cv_scores"])
