@@ -18,9 +18,11 @@ The same line reports, as extra objects:
   from batched plain solves (132 time levels in [0, 0.1] x 1521 nodes x 1024
   paths), 2000 Adam steps on the GPU, then the control-variate solve in its
   martingale form at the stride that reaches RMS 1e-3 fastest (pilot at 4096
-  paths), timed at its own N*; the Dynkin form at stride 50 beside it.
-  Throughput is quoted for the solve alone and with the labels and training
-  counted once.
+  paths), timed at its own N*; the Dynkin form at stride 50 beside it.  The
+  network fits the deviation from the identity map (u_hat = (x, y) + MLP);
+  the same pipeline with the plain-output network, and the identity's
+  gradient alone as the control, are reported beside it.  Throughput is
+  quoted for the solve alone and with the labels and training counted once.
 * "bridge": the same workload with the Brownian-bridge exit test (bias and
   rate at RMS 1e-3) at dt = 1e-5 and at coarser steps, the discrete test
   beside it.
@@ -537,7 +539,14 @@ def main():
         },
     }
     if not args.no_cv and fd is not None:
-        out["cv"] = measure_cv(fk, wl, pts, fd, args.steps, args.warmup)
+        # the network as the deviation from the identity map (u_hat = (x, y) +
+        # MLP); the plain-output network beside it
+        out["cv"] = measure_cv(fk, wl, pts, fd, args.steps, args.warmup, identity_base=True)
+        out["cv"]["identity_base"] = True
+        pn = measure_cv(fk, wl, pts, fd, args.steps, args.warmup, identity_base=False)
+        out["cv"]["plain_output_network"] = {k: pn[k] for k in ("stride", "paths_per_node", "rms_err", "nodes_per_s")}
+        out["cv"]["plain_output_network"]["pilots"] = [{k: p[k] for k in ("form", "stride", "var_ratio", "n_star")}
+                                                       for p in pn["pilots"]]
     if not args.no_bridge and fd is not None:
         out["bridge"] = measure_bridge(fk, wl, pts, fd)
     if not args.no_mesh_run:

@@ -259,3 +259,67 @@ def test_cv_grid_control_against_oracle(fk, oracle_mod, stride):
     assert np.all(d <= 3 * o["se"]) and np.all(d <= 1e-5)
     assert np.all(np.abs(np.stack([g["se_xi"], g["se_eta"]], 1) - o["se"]) <= 0.01 * o["se"] + 1e-9)
     assert ratio < (0.1 if stride == 2 else 0.5)
+
+
+def test_identity_base_eval_and_grad(fk):
+    """The identity base: every evaluation adds (x, y) and the identity to the
+    network's values and gradients, and training fits target - (x, y)."""
+    import torch
+    cv = fk.FkCv(curved_params(3), T, identity_base=True)
+    _, bf = cv.params()
+    rng = np.random.default_rng(5)
+    n = 777
+    txy = np.stack([rng.uniform(0, T, n), rng.uniform(0, 1, n), rng.uniform(0, 1, n)], 1).astype(np.float32)
+    print(f"[gpu] cv identity base eval n={n}", flush=True)
+    g = cv.eval(cuda32(txy))
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    t64 = txy.astype(np.float64)
+    fm = M.forward_mode(bf, t64[:, 0], t64[:, 1], t64[:, 2], T)
+    fm["val"] = fm["val"] + t64[:, 1:3]
+    fm["dx"] = fm["dx"] + np.array([1.0, 0.0])
+    fm["dy"] = fm["dy"] + np.array([0.0, 1.0])
+    for k, key in enumerate(("val", "dx", "dy", "dt", "lap")):
+        scale = np.abs(fm[key]).max()
+        err = np.abs(g[:, :, k] - fm[key]).max() / scale
+        print(f"channel {key}: max rel err {err:.2e} (scale {scale:.3g})", flush=True)
+        assert err < 2e-4, key
+    target = np.stack([txy[:, 1] + 0.05 * np.sin(6 * txy[:, 2]), txy[:, 2] - 0.03 * txy[:, 0] / T], 1)
+    gg, loss = cv.grad(cuda32(txy), cuda32(target))
+    torch.cuda.synchronize()
+    gg = gg.cpu().numpy().astype(np.float64)
+    resid = target.astype(np.float32).astype(np.float64) - t64[:, 1:3]
+    ref_loss, ref = M.loss_and_grad(bf, t64, resid, T)
+    cos = float(gg @ ref / (np.linalg.norm(gg) * np.linalg.norm(ref)))
+    print(f"base grad cosine {cos:.6f}; loss {float(loss.item()):.6e} vs {ref_loss:.6e}", flush=True)
+    assert cos >= 0.999 and abs(float(loss.item()) - ref_loss) <= 1e-2 * ref_loss
+    cv.close()
+
+
+@pytest.mark.parametrize("form", ["dynkin", "martingale"])
+def test_identity_base_solve_against_oracle(fk, oracle_mod, form):
+    import torch
+    cv = fk.FkCv(W.mlp_init(7), T, identity_base=True)
+    _, bf = cv.params()
+    dens = W.moving_bump()
+    pts = W.interface_nodes(4, 4, 16)[::3]
+    t, dt, N, stride = 0.01, 1e-4, 512, 6
+    f_gpu = fk.FK_CV_DYNKIN if form == "dynkin" else fk.FK_CV_MARTINGALE
+    f_or = oracle_mod.CV_DYNKIN if form == "dynkin" else oracle_mod.CV_MARTINGALE
+    print(f"[gpu] cv identity base {form} nodes={len(pts)} N={N}", flush=True)
+    g = fk.fk_interface_solve_cv(dens, W.Data(), pts, t, dt, N, cv, stride=stride, seed=3, form=f_gpu,
+                                 exit_step=True, cv_scores=True)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in g.items() if not k.startswith("_")}
+    o = oracle_mod.fk_solve_cv(dens, W.Data(), pts, t, dt, N, seed=3, uhat=oracle_mod.UHAT_MLP_BASE, flat=bf,
+                               t_scale=T, stride=stride, form=f_or, want_scores=True, want_exit=True, threads=THREADS)
+    same = g["exit_step"] == o["exit_step"]
+    assert np.mean(same) >= 0.999
+    ds = np.abs(g["cv_scores"].astype(np.float64) - o["cv_scores"])[same]
+    smax = np.abs(o["cv_scores"]).max()
+    d = np.abs(np.stack([g["xi"], g["eta"]], 1) - o["mean"])
+    print(f"{form} with base: max |score diff| {ds.max():.2e} (max |score| {smax:.3g}), max |mean diff| {d.max():.2e}, "
+          f"se ratio cv/plain {np.median(o['se'] / o['plain_se']):.3f}", flush=True)
+    assert ds.max() < 2e-5 * max(1.0, smax)
+    assert np.all(d <= 3 * o["se"]) and np.all(d <= 1e-5 * max(1.0, smax))
+    cv.close()
