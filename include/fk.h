@@ -124,7 +124,7 @@ typedef struct fk_data {
 
 /* Launch plan of the path kernel (see fk_plan_autotune). Zero fields take defaults. */
 typedef struct fk_plan {
-    int32_t block;          /* threads per workgroup (multiple of 64, <= 1024) */
+    int32_t block;          /* threads per workgroup: 64, 128, 192 or 256 */
     int32_t blocks_per_cu;  /* resident workgroups per compute unit for the persistent grid */
     int32_t chunk;          /* paths handed to a wavefront per queue grab (>= 1) */
     int32_t reserved;

@@ -258,7 +258,9 @@ hipError_t timing_record(int i, hipStream_t s) {
 
 int check_chunks(int64_t n_nodes, int64_t n_paths, const fk_plan &pl) {
     const int64_t cpn = (n_paths + pl.chunk - 1) / pl.chunk;
-    if (n_nodes * cpn >= 0xffffffffLL) return fail(FK_E_INVAL, "too many work chunks; raise plan chunk");
+    // chunk indices run past the last chunk by up to two grid-fulls of
+    // wavefronts (each wavefront's first chunk, and its final failed grab)
+    if (n_nodes * cpn >= 0xff000000LL) return fail(FK_E_INVAL, "too many work chunks; raise plan chunk");
     return FK_OK;
 }
 
@@ -288,7 +290,7 @@ int enqueue_solve(const SolveLaunch &S, hipStream_t stream, bool allow_timing) {
     const int occ = path_kernel_max_blocks_per_cu(S.kind, S.time_mode, S.uniform, a.score_mode == FK_SCORE_BRIDGE,
                                                   S.plan.block);
     if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
-    const int grid = n_cu * bpc;
+    const int grid = cap_grid(n_cu * bpc, a.total_chunks, S.plan.block);
     if ((e = timing_mark(timed, 0, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     if ((e = launch_paths(S.kind, S.time_mode, S.uniform, a, grid, S.plan.block, stream)) != hipSuccess)
         return hip_fail(e, "path kernel launch");

@@ -449,7 +449,7 @@ __global__ void __launch_bounds__(256, 2) fk_cv_path_kernel(const PathArgs a, co
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t q_slot = 0, q_next = 0, q_end = 0;
-    bool q_done = false;
+    bool q_done = false, first_grab = true;
     const uint32_t key0 = a.key0, key1 = a.key1;
     Lane L;
     bool active = false, parked = false, out = false;
@@ -503,9 +503,7 @@ __global__ void __launch_bounds__(256, 2) fk_cv_path_kernel(const PathArgs a, co
             uint64_t need = __ballot(!active && !parked);
             while (need != 0ull && !q_done) {
                 if (q_next >= q_end) {
-                    uint32_t cc = 0;
-                    if (lane == 0) cc = atomicAdd(a.queue, 1u);
-                    cc = __builtin_amdgcn_readfirstlane(cc);
+                    const uint32_t cc = next_chunk(a, first_grab);
                     if (cc >= a.total_chunks) {
                         q_done = true;
                         break;
@@ -605,7 +603,7 @@ __global__ void __launch_bounds__(256, 4) fk_mg_path_kernel(const PathArgs a, co
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t q_slot = 0, q_next = 0, q_end = 0;
-    bool q_done = false;
+    bool q_done = false, first_grab = true;
     const uint32_t key0 = a.key0, key1 = a.key1;
     Lane L;
     bool active = false;
@@ -638,9 +636,7 @@ __global__ void __launch_bounds__(256, 4) fk_mg_path_kernel(const PathArgs a, co
             uint64_t need = __ballot(!active);
             while (need != 0ull && !q_done) {
                 if (q_next >= q_end) {
-                    uint32_t cc = 0;
-                    if (lane == 0) cc = atomicAdd(a.queue, 1u);
-                    cc = __builtin_amdgcn_readfirstlane(cc);
+                    const uint32_t cc = next_chunk(a, first_grab);
                     if (cc >= a.total_chunks) {
                         q_done = true;
                         break;
@@ -752,7 +748,7 @@ __global__ void __launch_bounds__(256) fk_mgg_path_kernel(const PathArgs a, cons
     constexpr bool kMovingBackward = moving_kind(KIND) && TMODE == TIME_BACKWARD;
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t q_slot = 0, q_next = 0, q_end = 0;
-    bool q_done = false;
+    bool q_done = false, first_grab = true;
     const uint32_t key0 = a.key0, key1 = a.key1;
     Lane L;
     bool active = false;
@@ -765,9 +761,7 @@ __global__ void __launch_bounds__(256) fk_mgg_path_kernel(const PathArgs a, cons
         uint64_t need = __ballot(!active);
         while (need != 0ull && !q_done) {
             if (q_next >= q_end) {
-                uint32_t cc = 0;
-                if (lane == 0) cc = atomicAdd(a.queue, 1u);
-                cc = __builtin_amdgcn_readfirstlane(cc);
+                const uint32_t cc = next_chunk(a, first_grab);
                 if (cc >= a.total_chunks) {
                     q_done = true;
                     break;
@@ -1567,7 +1561,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         c.cv_scores = cv_rec;
         const int occ = cv_dispatch<CvOccF>(T.kind, T.time_mode, T.uniform);
         if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
-        if ((e = cv_dispatch<CvLaunchF>(T.kind, T.time_mode, T.uniform, a, c, n_cu * bpc, stream)) != hipSuccess)
+        if ((e = cv_dispatch<CvLaunchF>(T.kind, T.time_mode, T.uniform, a, c, cap_grid(n_cu * bpc, a.total_chunks, 256), stream)) != hipSuccess)
             return hip_fail(e, "control-variate path kernel launch");
     } else if (grid_ctl) {
         MggArgs c{};
@@ -1575,7 +1569,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         c.cv_scores = cv_rec;
         const int occ = cv_dispatch<MggOccF>(T.kind, T.time_mode, T.uniform);
         if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
-        if ((e = cv_dispatch<MggLaunchF>(T.kind, T.time_mode, T.uniform, a, c, n_cu * bpc, stream)) != hipSuccess)
+        if ((e = cv_dispatch<MggLaunchF>(T.kind, T.time_mode, T.uniform, a, c, cap_grid(n_cu * bpc, a.total_chunks, 256), stream)) != hipSuccess)
             return hip_fail(e, "control-variate path kernel launch");
     } else {
         MgArgs c{};
@@ -1587,7 +1581,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         c.cv_scores = cv_rec;
         const int occ = cv_dispatch<MgOccF>(T.kind, T.time_mode, T.uniform);
         if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
-        if ((e = cv_dispatch<MgLaunchF>(T.kind, T.time_mode, T.uniform, a, c, n_cu * bpc, stream)) != hipSuccess)
+        if ((e = cv_dispatch<MgLaunchF>(T.kind, T.time_mode, T.uniform, a, c, cap_grid(n_cu * bpc, a.total_chunks, 256), stream)) != hipSuccess)
             return hip_fail(e, "control-variate path kernel launch");
     }
     if ((e = timing_record(1, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
+
 #include <string>
 #include <vector>
 
@@ -129,6 +131,14 @@ int validate_horizon(double t, double t_init, double dt, uint32_t level_id);
 int validate_points(const double *pts, int64_t n);
 int resolve_plan(const fk_plan *plan, fk_plan *out);
 int check_chunks(int64_t n_nodes, int64_t n_paths, const fk_plan &pl);
+// A persistent grid of `grid` blocks cut to no more wavefronts than there
+// are work chunks (small solves: a wavefront with no chunk only costs its
+// launch).
+inline int cap_grid(int grid, uint32_t total_chunks, int block) {
+    const int64_t wpb = block / 64;
+    const int64_t need = ((int64_t)total_chunks + wpb - 1) / wpb;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(grid, need));
+}
 int build_tables(const LevelSpec *lv, int n_levels, const double *pts, int64_t n_total, const fk_data *d, double dt,
                  Tables &T);
 void fill_common_args(SolveLaunch &S, const fk_data *d, bool shift, uint64_t seed);

@@ -126,6 +126,23 @@ __device__ __forceinline__ float grid_bilinear(const double *g, int n, float x, 
 }
 
 
+// The next work chunk of a wavefront (wave-uniform).  A wavefront's first
+// chunk is its own index in the grid, so a launch starts without every
+// wavefront contending for the one counter at once; later chunks come from
+// the counter, past the first grid-full.  Which wavefront runs which chunk
+// does not change any result: paths draw their numbers by their own
+// counters.
+__device__ __forceinline__ uint32_t next_chunk(const PathArgs &a, bool &first) {
+    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
+    if (first) {
+        first = false;
+        return blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    }
+    uint32_t c = 0;
+    if ((threadIdx.x & 63u) == 0) c = atomicAdd(a.queue, 1u);
+    return __builtin_amdgcn_readfirstlane(c) + waves;
+}
+
 // Loads path `path` of node `nd` into a lane.
 template <int KIND, int TMODE>
 __device__ __forceinline__ void lane_start(Lane &L, const NodeDev &nd, const LevelDev *levels, uint32_t path,
