@@ -114,7 +114,7 @@ typedef struct fk_density {
 /* Initial and boundary data. */
 typedef struct fk_data {
     int32_t init_kind;   /* FK_DATA_* */
-    int32_t bdry_kind;   /* FK_DATA_IDENTITY, FK_DATA_SIN or FK_DATA_ZERO */
+    int32_t bdry_kind;   /* FK_DATA_IDENTITY, FK_DATA_SIN, FK_DATA_ZERO or FK_DATA_GRID (see there) */
     int32_t score_mode;  /* FK_SCORE_* */
     int32_t grid_n;      /* FK_DATA_GRID: grid cells per side, else 0 */
     double t_init;       /* PDE time at which the initial data hold */

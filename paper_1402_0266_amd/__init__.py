@@ -514,11 +514,15 @@ def subdomain_solve(density, t_w, dt_mesh, px, m, xi_n, eta_n, iface_xi, iface_e
     return out
 
 
-def fk_mesh_quality(xi, eta):
-    """(min Jacobian, max skewness) device tensor [2] of a nodal map."""
+def fk_mesh_quality(xi, eta, out=None):
+    """(min Jacobian, max skewness) device tensor [2] of a nodal map (into
+    ``out``, a contiguous FP64 [2], if given)."""
     import torch
     n = int(round(xi.numel() ** 0.5)) - 1
-    out = torch.empty(2, dtype=torch.float64, device=xi.device)
+    if out is None:
+        out = torch.empty(2, dtype=torch.float64, device=xi.device)
+    elif out.numel() != 2 or out.dtype != torch.float64 or not out.is_contiguous():
+        raise ValueError("out must be a contiguous FP64 tensor of 2 elements")
     _check(_lib.fk_mesh_quality(xi.data_ptr(), eta.data_ptr(), n, out.data_ptr(), _stream(torch, xi.device)))
     return out
 
@@ -598,18 +602,24 @@ FK_CV_DYNKIN, FK_CV_MARTINGALE, FK_CV_MARTINGALE_GRID = 0, 1, 2
 
 def fk_interface_solve_cv(density, data, pts, t, dt, n_paths, cv, stride=2, seed=0, level_id=0, *,
                           form=FK_CV_DYNKIN, plain=True, exit_step=False, cv_scores=False, plan=None, device="cuda",
-                          workspace=None, grids=None):
+                          workspace=None, grids=None, out=None):
     """Control-variate interface solve (C: ``fk_interface_solve_cv``), Dynkin
     or martingale form; returns a dict of device tensors: xi, eta, se_xi,
     se_eta (CV), plain_* (same paths), total_steps, and on request exit_step,
-    cv_scores."""
+    cv_scores.  ``out`` may supply some of the FP64 [n] outputs (contiguous
+    device tensors, e.g. rows of a history buffer); the rest are allocated."""
     import torch
     pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 2)
     n = pts.shape[0]
     dev = torch.device(device)
     keys = ["xi", "eta", "se_xi", "se_eta"] + (["plain_xi", "plain_eta", "plain_se_xi", "plain_se_eta"] if plain else [])
-    out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in keys}
-    out["total_steps"] = torch.zeros(1, dtype=torch.int64, device=dev)
+    out = dict(out or {})
+    for k in keys:
+        if k not in out:
+            out[k] = torch.empty(n, dtype=torch.float64, device=dev)
+        elif out[k].numel() != n or out[k].dtype != torch.float64 or not out[k].is_contiguous():
+            raise ValueError(f"out[{k!r}] must be a contiguous FP64 tensor of {n} elements")
+    out.setdefault("total_steps", torch.zeros(1, dtype=torch.int64, device=dev))
     if exit_step:
         out["exit_step"] = torch.empty((n, n_paths), dtype=torch.int32, device=dev)
     if cv_scores:

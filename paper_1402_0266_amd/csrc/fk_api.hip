@@ -435,6 +435,10 @@ int fk_interface_solve(const fk_density *w, const fk_data *d, const double *pts,
     S.time_mode = T.time_mode;
     S.uniform = T.uniform;
     S.plan = pl;
+    // Default chunk: short paths (a mesh step of a few tens of sub-steps)
+    // take 256 paths per grab, which halves the wavefronts' fixed costs per
+    // path; long ones 128, for the balance of the tail.
+    if ((!plan || plan->chunk == 0) && T.levels[0].K <= 64) S.plan.chunk = 256;
     S.n_nodes = n_nodes;
     S.n_paths = n_paths;
     S.counters = (uint32_t *)(ws + lay.counters);

@@ -243,17 +243,25 @@ __global__ void __launch_bounds__(256) fk_reduce_kernel(const ReduceArgs a) {
     const int64_t K = a.outs[o].K;
     double s1x = 0.0, s2x = 0.0, s1y = 0.0, s2y = 0.0;
     long long st = 0;
-    for (int64_t p = threadIdx.x; p < a.n_paths; p += blockDim.x) {
-        const float2 v = rec[p];
+    // unrolled so that several records are in flight per thread; the sums
+    // keep their order
+    auto add = [&](const float2 v) {
         const double vx = v.x, vy = v.y;
         s1x += vx;
         s2x = fma(vx, vx, s2x);
         s1y += vy;
         s2y = fma(vy, vy, s2y);
-        if (ex) {
+    };
+    if (ex) {
+#pragma unroll 8
+        for (int64_t p = threadIdx.x; p < a.n_paths; p += blockDim.x) {
+            add(rec[p]);
             const int32_t e = ex[p];
             st += (e < 0) ? K : e;
         }
+    } else {
+#pragma unroll 8
+        for (int64_t p = threadIdx.x; p < a.n_paths; p += blockDim.x) add(rec[p]);
     }
     s1x = wave_sum(s1x);
     s2x = wave_sum(s2x);

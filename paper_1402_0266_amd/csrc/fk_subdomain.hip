@@ -214,6 +214,34 @@ __device__ double edge_fraction(const double *cells, int N, int e, int i) {
     return part / total;
 }
 
+// Lane `l` of a wave-uniform index: its FP64 value, in scalar registers.
+__device__ __forceinline__ double readlane_f64(double v, int l) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)b, l);
+    const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(b >> 32), l);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// A DPP move of an FP64 value (both halves by the same lane pattern; a lane
+// whose source is outside the pattern's range gets an unspecified value).
+template <int CTRL>
+__device__ __forceinline__ double dpp_f64(double v) {
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)b, CTRL, 0xf, 0xf, false);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_mov_dpp((int)(uint32_t)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((uint64_t)hi << 32) | lo);
+}
+
+// Sum over lanes 0 .. 31, wave-uniform: within each row of 16 lanes by DPP
+// (quad swaps 1 and 2, then the 8- and 16-lane mirrors), then the two rows.
+__device__ __forceinline__ double sum32_f64(double v) {
+    v += dpp_f64<0xB1>(v);    // quad_perm [1, 0, 3, 2]
+    v += dpp_f64<0x4E>(v);    // quad_perm [2, 3, 0, 1]
+    v += dpp_f64<0x141>(v);   // row_half_mirror
+    v += dpp_f64<0x140>(v);   // row_mirror
+    return readlane_f64(v, 0) + readlane_f64(v, 16);
+}
+
 constexpr int kB = 32;   // steps per staging batch of the register-window kernel
 
 // Back substitution by one wavefront, kD rows at a time: x_k = (y_k -
@@ -241,10 +269,11 @@ __device__ __forceinline__ void back_substitute_blocked(const SubArgs &a, const 
     };
     double xr0 = sep_val(lane, 0), xr1 = sep_val(lane + 64, 0);
     double yr0 = sep_val(lane, 1), yr1 = sep_val(lane + 64, 1);
-    double c0[kD], c1[kD], cd[kD], cyx[kD], cyy[kD];
-    double n0[kD], n1[kD], nd[kD], nyx[kD], nyy[kD];
-    // rows top - j: the entries multiplying the ring, the diagonal and y
-    auto load = [&](int top, double *u0, double *u1, double *ud, double *yx, double *yy) {
+    double c0[kD], c1[kD], cd[kD], cyx[kD], cyy[kD], ct[kD];
+    double n0[kD], n1[kD], nd[kD], nyx[kD], nyy[kD], nt[kD];
+    // rows top - j: the entries multiplying the ring, the diagonal, y, and
+    // (lane l < kD - 1) the entry U[k][k + l + 1] the block's triangle needs
+    auto load = [&](int top, double *u0, double *u1, double *ud, double *yx, double *yy, double *ut) {
 #pragma unroll
         for (int j = 0; j < kD; ++j) {
             const int k = top - j;
@@ -256,11 +285,12 @@ __device__ __forceinline__ void back_substitute_blocked(const SubArgs &a, const 
             ud[j] = ok ? row[0] : 1.0;
             yx[j] = ok ? Y[k] : 0.0;
             yy[j] = ok ? Y[n + k] : 0.0;
+            ut[j] = (ok && lane < j) ? row[lane + 1] : 0.0;
         }
     };
-    load(top0, c0, c1, cd, cyx, cyy);
+    load(top0, c0, c1, cd, cyx, cyy, ct);
     for (int top = top0; top >= 0; top -= kD) {
-        load(top - kD, n0, n1, nd, nyx, nyy);
+        load(top - kD, n0, n1, nd, nyx, nyy, nt);
         // 2 kD partial sums per lane, reduced across the wave by a butterfly
         // that halves the values each lane keeps (offsets 32, 16, 8, 4: lane
         // l ends with value l >> 2 summed over the 16 lanes that share its
@@ -295,16 +325,12 @@ __device__ __forceinline__ void back_substitute_blocked(const SubArgs &a, const 
         double xb[kD], yb[kD];
 #pragma unroll
         for (int j = 0; j < kD; ++j) {
-            const int k = top - j;
             double tx = cyx[j] - sx[j], ty = cyy[j] - sy[j];
-            if (k >= 0) {
-                const double *row = U + (int64_t)k * P1;
 #pragma unroll
-                for (int i = 0; i < j; ++i) {
-                    const double u = row[j - i];   // U[k][k + (j - i)] multiplies x_{k_i}
-                    tx = fma(-u, xb[i], tx);
-                    ty = fma(-u, yb[i], ty);
-                }
+            for (int i = 0; i < j; ++i) {
+                const double u = readlane_f64(ct[j], j - i - 1);   // U[k][k + (j - i)] multiplies x_{k_i}
+                tx = fma(-u, xb[i], tx);
+                ty = fma(-u, yb[i], ty);
             }
             xb[j] = tx / cd[j];
             yb[j] = ty / cd[j];
@@ -342,8 +368,44 @@ __device__ __forceinline__ void back_substitute_blocked(const SubArgs &a, const 
             cd[j] = nd[j];
             cyx[j] = nyx[j];
             cyy[j] = nyy[j];
+            ct[j] = nt[j];
         }
     }
+}
+
+// Every row's coefficients of a sub-domain system (Dirichlet neighbours
+// moved to the right-hand side), in the natural or the reversed order (row
+// n-1-r, east <-> west, north <-> south), by the threads of the workgroup.
+__device__ void assemble_rows(const SubArgs &a, int n, int q, int i0, int j0, bool rev, double4 *cf, double2 *rh) {
+    const int N1 = a.N + 1;
+    for (int r = threadIdx.x; r < n; r += blockDim.x) {
+        const int ii = r % q, jj = r / q;
+        const int gi = i0 + 1 + ii, gj = j0 + 1 + jj;
+        double bx, by;
+        node_drift_f64(a, gi, gj, bx, by);
+        const double cxr = a.half_d_over_h * bx, cyr = a.half_d_over_h * by;
+        const double cE = -a.c - cxr, cW = -a.c + cxr, cN = -a.c - cyr, cS = -a.c + cyr;
+        const int64_t g = (int64_t)gj * N1 + gi;
+        double fx = a.steady ? 0.0 : a.xi_n[g], fy = a.steady ? 0.0 : a.eta_n[g];
+        if (ii == q - 1) { fx -= cE * a.xi_out[g + 1]; fy -= cE * a.eta_out[g + 1]; }
+        if (ii == 0) { fx -= cW * a.xi_out[g - 1]; fy -= cW * a.eta_out[g - 1]; }
+        if (jj == q - 1) { fx -= cN * a.xi_out[g + N1]; fy -= cN * a.eta_out[g + N1]; }
+        if (jj == 0) { fx -= cS * a.xi_out[g - N1]; fy -= cS * a.eta_out[g - N1]; }
+        const double e = ii < q - 1 ? cE : 0.0, w = ii > 0 ? cW : 0.0;
+        const double nn = jj < q - 1 ? cN : 0.0, ss = jj > 0 ? cS : 0.0;
+        cf[rev ? n - 1 - r : r] = rev ? make_double4(w, e, ss, nn) : make_double4(e, w, nn, ss);
+        rh[rev ? n - 1 - r : r] = make_double2(fx, fy);
+    }
+}
+
+// Original matrix entry (r, c) of an assembled system; identity beyond n.
+__device__ __forceinline__ double band_entry(const double4 *cf, int n, int q, double diag, int r, int c) {
+    if (r >= n || c >= n) return r == c ? 1.0 : 0.0;
+    const int d = c - r;
+    if (d == 0) return diag;
+    if (d != 1 && d != -1 && d != q && d != -q) return 0.0;
+    const double4 f = cf[r];
+    return d == 1 ? f.x : d == -1 ? f.y : d == q ? f.z : f.w;
 }
 
 // Banded LU with the window in registers.  For P1 = q + 1 the window of
@@ -380,7 +442,6 @@ __global__ void __launch_bounds__(256) subdomain_lu_kernel(const SubArgs a) {
     const bool rev = a.twisted && (blockIdx.x & 1);           // the reversed (bottom) end
     const int si = sd % a.px, sj = sd / a.px;
     const int i0 = si * a.m, j0 = sj * a.m;
-    const int N1 = a.N + 1;
     // rows eliminated here, and where this end's U rows and y values go
     const int steps = !a.twisted ? n : (rev ? n - a.sep - q : a.sep);
     const int off = rev ? a.sep : 0;
@@ -391,39 +452,12 @@ __global__ void __launch_bounds__(256) subdomain_lu_kernel(const SubArgs a) {
     double2 *rh = reinterpret_cast<double2 *>(a.rbuf + cix * 2 * n);
     const int tid = threadIdx.x;
 
-    // ---- every row's coefficients (Dirichlet neighbours moved to the rhs) --
-    for (int r = tid; r < n; r += blockDim.x) {
-        const int ii = r % q, jj = r / q;
-        const int gi = i0 + 1 + ii, gj = j0 + 1 + jj;
-        double bx, by;
-        node_drift_f64(a, gi, gj, bx, by);
-        const double cxr = a.half_d_over_h * bx, cyr = a.half_d_over_h * by;
-        const double cE = -a.c - cxr, cW = -a.c + cxr, cN = -a.c - cyr, cS = -a.c + cyr;
-        const int64_t g = (int64_t)gj * N1 + gi;
-        double fx = a.steady ? 0.0 : a.xi_n[g], fy = a.steady ? 0.0 : a.eta_n[g];
-        if (ii == q - 1) { fx -= cE * a.xi_out[g + 1]; fy -= cE * a.eta_out[g + 1]; }
-        if (ii == 0) { fx -= cW * a.xi_out[g - 1]; fy -= cW * a.eta_out[g - 1]; }
-        if (jj == q - 1) { fx -= cN * a.xi_out[g + N1]; fy -= cN * a.eta_out[g + N1]; }
-        if (jj == 0) { fx -= cS * a.xi_out[g - N1]; fy -= cS * a.eta_out[g - N1]; }
-        const double e = ii < q - 1 ? cE : 0.0, w = ii > 0 ? cW : 0.0;
-        const double nn = jj < q - 1 ? cN : 0.0, ss = jj > 0 ? cS : 0.0;
-        // the reversed system: row n-1-r, east <-> west, north <-> south
-        cf[rev ? n - 1 - r : r] = rev ? make_double4(w, e, ss, nn) : make_double4(e, w, nn, ss);
-        rh[rev ? n - 1 - r : r] = make_double2(fx, fy);
-    }
+    assemble_rows(a, n, q, i0, j0, rev, cf, rh);
     __threadfence_block();
     __syncthreads();
 
     const double diag = a.diag0 + 4.0 * a.c;
-    // original matrix entry (r, c); identity beyond n
-    auto entry = [&](int r, int c) -> double {
-        if (r >= n || c >= n) return r == c ? 1.0 : 0.0;
-        const int d = c - r;
-        if (d == 0) return diag;
-        if (d != 1 && d != -1 && d != q && d != -q) return 0.0;
-        const double4 f = cf[r];
-        return d == 1 ? f.x : d == -1 ? f.y : d == q ? f.z : f.w;
-    };
+    auto entry = [&](int r, int c) -> double { return band_entry(cf, n, q, diag, r, c); };
     // roles: column slot / right-hand side, and which half of the rows
     const bool is_col = tid < 2 * P1;
     const bool is_rhs = !is_col && tid < 2 * P1 + 4;
@@ -569,6 +603,127 @@ __global__ void __launch_bounds__(256) subdomain_lu_kernel(const SubArgs a) {
     if (tid < 64) back_substitute_blocked<P1>(a, U, Y, n, n - 1, i0, j0, nullptr, false);
 }
 
+// Banded LU of a small window (P1 <= 32) in one wavefront, one lane per
+// window column: lane t < P1 holds the columns c = t (mod P1) with all P1
+// window rows in v[0 .. P1-1], lanes P1 and P1 + 1 the two right-hand sides.
+// Step k reads the pivot column from its lane into scalar registers
+// (readlane: the lane is wave-uniform), and every lane updates and shifts
+// its column in one pass, v[i] = v[i + 1] - pivotcol[i + 1] * (v[0] / pivot).
+// The pivot column becomes exactly zero and its lane takes the entering
+// column k + P1 (rows k + 1, k + q and k + P1: north neighbour, east
+// neighbour, diagonal); the row k + P1 enters at the bottom with its
+// original entries (west and south neighbours), staged in LDS a batch ahead.
+// No barrier per step, no LDS traffic for the window.  The outputs are those
+// of subdomain_lu_kernel: U rows, y values, and in twisted mode the
+// separator block of the trailing window.
+template <int P1, bool TW>
+__global__ void __launch_bounds__(64) subdomain_lu_wave_kernel(const SubArgs a) {
+    constexpr int q = P1 - 1;
+    constexpr int kW = 64;   // steps per staging batch: one entering row per lane
+    static_assert(P1 + 2 <= 64, "one lane per window column and right-hand side");
+    __shared__ double4 Cst[2][kW];   // coefficients of the entering rows R = k + P1
+    __shared__ double2 Rst[2][kW];   // their right-hand sides
+    __shared__ double Nst[2][kW];    // north coefficients of the rows k + 1
+    const int n = q * q;
+    const int sd = TW ? blockIdx.x >> 1 : blockIdx.x;
+    const bool rev = TW && (blockIdx.x & 1);
+    const int si = sd % a.px, sj = sd / a.px;
+    const int i0 = si * a.m, j0 = sj * a.m;
+    const int steps = !TW ? n : (rev ? n - a.sep - q : a.sep);
+    const int off = rev ? a.sep : 0;
+    double *U = a.ubuf + (int64_t)sd * n * P1 + (int64_t)off * P1;
+    double *Y = a.ybuf + (int64_t)sd * 2 * n + off;
+    const int64_t cix = TW ? 2 * (int64_t)sd + (rev ? 1 : 0) : sd;
+    double4 *cf = reinterpret_cast<double4 *>(a.cbuf + cix * 4 * n);
+    double2 *rh = reinterpret_cast<double2 *>(a.rbuf + cix * 2 * n);
+    const int lane = threadIdx.x;
+
+    assemble_rows(a, n, q, i0, j0, rev, cf, rh);
+    __threadfence_block();
+    __syncthreads();
+
+    const double diag = a.diag0 + 4.0 * a.c;
+    const bool is_col = lane < P1;
+    const bool is_rhs = lane == P1 || lane == P1 + 1;
+    const int rhs_c = lane - P1;                 // 0: xi, 1: eta (right-hand-side lanes)
+    int col = lane;                              // the column a column lane holds
+    double v[P1];
+#pragma unroll
+    for (int i = 0; i < P1; ++i) {
+        double e = 0.0;
+        if (is_col) e = band_entry(cf, n, q, diag, i, col);
+        else if (is_rhs && i < n) e = rhs_c == 0 ? rh[i].x : rh[i].y;
+        v[i] = e;
+    }
+    // lane j loads the entering coefficients of step bt kW + j
+    auto load_batch = [&](int bt, double4 &c4, double2 &r2, double &cn) {
+        const int kk = bt * kW + lane, R = kk + P1;
+        c4 = (kk < steps && R < n) ? cf[R] : make_double4(0.0, 0.0, 0.0, 0.0);
+        r2 = (kk < steps && R < n) ? rh[R] : make_double2(0.0, 0.0);
+        cn = (kk < steps && kk + 1 < n) ? cf[kk + 1].z : 0.0;
+    };
+    double4 pc4;
+    double2 pr2;
+    double pcn;
+    load_batch(0, pc4, pr2, pcn);
+    double cE_Rm1 = (P1 - 1 < n) ? cf[P1 - 1].x : 0.0;   // east coefficient of row R - 1
+
+    int owner = 0;
+    for (int k = 0; k < steps; ++k) {
+        const int j = k % kW, bb = (k / kW) & 1;
+        if (j == 0) {
+            Cst[bb][lane] = pc4;
+            Rst[bb][lane] = pr2;
+            Nst[bb][lane] = pcn;
+            load_batch(k / kW + 1, pc4, pr2, pcn);
+            __syncthreads();
+        }
+        // the pivot column, wave-uniform
+        double pc[P1];
+#pragma unroll
+        for (int i = 0; i < P1; ++i) pc[i] = readlane_f64(v[i], owner);
+        const double u = v[0];                   // row k of this lane's column
+        // U row k (band offset col - k) and the y values
+        if (is_col) U[(int64_t)k * P1 + (col - k)] = u;
+        else if (is_rhs) Y[rhs_c * n + k] = u;
+        const bool own = lane == owner;
+        // the pivot column itself: scale exactly 1, so it becomes exactly zero
+        const double sc = own ? 1.0 : u * (1.0 / pc[0]);
+#pragma unroll
+        for (int i = 0; i < P1 - 1; ++i) v[i] = fma(-pc[i + 1], sc, v[i + 1]);
+        const int R = k + P1;
+        const bool live = R < n;
+        const double4 cR = Cst[bb][j];
+        double last;
+        if (is_col) last = (live && col < n) ? (col == R - 1 ? cR.y : (col == R - q ? cR.w : 0.0)) : 0.0;
+        else last = rhs_c == 0 ? Rst[bb][j].x : Rst[bb][j].y;
+        if (own) {
+            // the entering column R: rows k + 1 (north of k + 1), R - 1 (east of R - 1), R
+            col = R;
+            v[0] = live ? Nst[bb][j] : 0.0;
+            v[P1 - 2] = live ? cE_Rm1 : 0.0;
+            last = live ? diag : 1.0;
+        }
+        v[P1 - 1] = last;
+        cE_Rm1 = cR.x;
+        owner = (owner + 1 == P1) ? 0 : owner + 1;
+    }
+    if constexpr (TW) {
+        // the separator block of the trailing window and its right-hand sides
+        double *S = a.sbuf + (int64_t)sd * sep_stride(q) + (rev ? (size_t)q * q + 2 * q : 0);
+        const int c = col - steps;
+#pragma unroll
+        for (int i = 0; i < q; ++i) {
+            if (is_col && c < q) S[i * q + c] = v[i];
+            else if (is_rhs) S[(size_t)q * q + rhs_c * q + i] = v[i];
+        }
+    } else {
+        __threadfence_block();
+        __syncthreads();
+        back_substitute_blocked<P1>(a, U, Y, n, n - 1, i0, j0, nullptr, false);
+    }
+}
+
 // The separator system of a twisted elimination, one workgroup per
 // sub-domain: S_top + S_bot - A_SS and its right-hand sides assembled in
 // LDS, LU without pivoting (the Schur complement of a diagonally dominant
@@ -647,6 +802,61 @@ __global__ void __launch_bounds__(64) twisted_back_kernel(const SubArgs a) {
     back_substitute_blocked<P1>(a, U, Y, n, steps - 1, si * a.m, sj * a.m, xs, rev);
 }
 
+
+// The same for windows up to 32, a row at a time: lane l < q holds
+// x_{k+l+1} (both components), each row's sum over them is a DPP reduction
+// within the first 32 lanes, and the window shifts up by one lane (DPP wave
+// shift).  U rows and y values are loaded kR rows ahead.
+template <int P1>
+__global__ void __launch_bounds__(64) twisted_back_wave_kernel(const SubArgs a) {
+    constexpr int q = P1 - 1, kR = 8;
+    static_assert(q <= 32, "the window fits the first 32 lanes");
+    const int n = q * q;
+    const int sd = blockIdx.x >> 1;
+    const bool rev = (blockIdx.x & 1) != 0;
+    const int steps = rev ? n - a.sep - q : a.sep, off = rev ? a.sep : 0;
+    const int si = sd % a.px, sj = sd / a.px;
+    const int i0 = si * a.m, j0 = sj * a.m, N1 = a.N + 1;
+    const double *U = a.ubuf + (int64_t)sd * n * P1 + (int64_t)off * P1;
+    const double *Y = a.ybuf + (int64_t)sd * 2 * n + off;
+    const double *xs = a.sbuf + (int64_t)sd * sep_stride(q) + 2 * ((size_t)q * q + 2 * q);
+    const int lane = threadIdx.x;
+    // the window starts with the separator's values, the q unknowns after the last row
+    double xw = 0.0, yw = 0.0;
+    if (lane < q) {
+        xw = xs[rev ? q - 1 - lane : lane];
+        yw = xs[q + (rev ? q - 1 - lane : lane)];
+    }
+    double ur[kR], ud[kR], fx[kR], fy[kR];
+    auto load = [&](int k, double &u, double &d, double &yx, double &yy) {
+        const bool ok = k >= 0;
+        const double *row = U + (int64_t)(ok ? k : 0) * P1;
+        u = (ok && lane < q) ? row[lane + 1] : 0.0;
+        d = ok ? row[0] : 1.0;
+        yx = ok ? Y[k] : 0.0;
+        yy = ok ? Y[n + k] : 0.0;
+    };
+#pragma unroll
+    for (int r = 0; r < kR; ++r) load(steps - 1 - r, ur[r], ud[r], fx[r], fy[r]);
+    for (int k0 = steps - 1; k0 >= 0; k0 -= kR) {
+#pragma unroll
+        for (int r = 0; r < kR; ++r) {
+            const int k = k0 - r;
+            const double sx = sum32_f64(ur[r] * xw), sy = sum32_f64(ur[r] * yw);
+            const double x = (fx[r] - sx) / ud[r], y = (fy[r] - sy) / ud[r];
+            if (lane == 0 && k >= 0) {
+                const int rr = rev ? n - 1 - k : k;
+                const int64_t g = (int64_t)(j0 + 1 + rr / q) * N1 + (i0 + 1 + rr % q);
+                a.xi_out[g] = x;
+                a.eta_out[g] = y;
+            }
+            const double ux = dpp_f64<0x138>(xw), uy = dpp_f64<0x138>(yw);   // wave_shr:1
+            xw = lane == 0 ? x : ux;
+            yw = lane == 0 ? y : uy;
+            load(k - kR, ur[r], ud[r], fx[r], fy[r]);
+        }
+    }
+}
 
 __global__ void __launch_bounds__(256) subdomain_be_kernel(const SubArgs a) {
     extern __shared__ double lds[];
@@ -921,6 +1131,27 @@ static bool launch_lu(const SubArgs &a, int blocks, hipStream_t s, hipError_t *e
         *err = hipGetLastError();
         return true;
     };
+    auto wave = [&](auto kern) {
+        hipLaunchKernelGGL(kern, dim3((unsigned)(a.twisted ? 2 * blocks : blocks)), dim3(64), 0, s, a);
+        *err = hipGetLastError();
+        return true;
+    };
+    // windows up to 32: one wavefront per elimination (both ends when twisted)
+    if (a.twisted) {
+        switch (a.m) {
+        case 16: return wave(subdomain_lu_wave_kernel<16, true>);
+        case 20: return wave(subdomain_lu_wave_kernel<20, true>);
+        case 24: return wave(subdomain_lu_wave_kernel<24, true>);
+        case 32: return wave(subdomain_lu_wave_kernel<32, true>);
+        default: break;
+        }
+    } else {
+        switch (a.m) {
+        case 8: return wave(subdomain_lu_wave_kernel<8, false>);
+        case 12: return wave(subdomain_lu_wave_kernel<12, false>);
+        default: break;
+        }
+    }
     switch (a.m) {
     case 8: return go(subdomain_lu_kernel<8>, 8);
     case 12: return go(subdomain_lu_kernel<12>, 12);
@@ -950,10 +1181,10 @@ static hipError_t launch_twisted_rest(const SubArgs &a, int blocks, hipStream_t 
         return hipGetLastError();
     };
     switch (a.m) {
-    case 16: return back(twisted_back_kernel<16>);
-    case 20: return back(twisted_back_kernel<20>);
-    case 24: return back(twisted_back_kernel<24>);
-    case 32: return back(twisted_back_kernel<32>);
+    case 16: return back(twisted_back_wave_kernel<16>);
+    case 20: return back(twisted_back_wave_kernel<20>);
+    case 24: return back(twisted_back_wave_kernel<24>);
+    case 32: return back(twisted_back_wave_kernel<32>);
     case 40: return back(twisted_back_kernel<40>);
     case 48: return back(twisted_back_kernel<48>);
     case 64: return back(twisted_back_kernel<64>);

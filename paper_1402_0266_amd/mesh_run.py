@@ -189,8 +189,9 @@ class MeshRun:
         self.spare = (torch.empty_like(self.xi), torch.empty_like(self.eta))
         self.n = 0
         self._quality = torch.zeros((cfg.n_steps, 2), dtype=torch.float64, device=self.dev)
-        self._iface = torch.zeros((cfg.n_steps, self.n_nodes, 2), dtype=torch.float64, device=self.dev)
-        self._se = torch.zeros((cfg.n_steps, self.n_nodes, 2), dtype=torch.float64, device=self.dev)
+        # per step: (xi, eta) rows, written in place by the interface solve
+        self._iface = torch.zeros((cfg.n_steps, 2, self.n_nodes), dtype=torch.float64, device=self.dev)
+        self._se = torch.zeros((cfg.n_steps, 2, self.n_nodes), dtype=torch.float64, device=self.dev)
         self.cv = None
         self.used_cv = np.zeros(cfg.n_steps, dtype=bool)
         self.workspace = None
@@ -207,8 +208,6 @@ class MeshRun:
         if cfg.key_points:
             self._mask = torch.empty(self.n_nodes, dtype=torch.uint8, device=self.dev)
             self._slot = torch.empty(self.n_nodes, dtype=torch.int32, device=self.dev)
-            self._iface_buf = (torch.empty(self.n_nodes, dtype=torch.float64, device=self.dev),
-                               torch.empty(self.n_nodes, dtype=torch.float64, device=self.dev))
             self._bdry_ws = None
         if cfg.refit_every > 0 and cfg.cv_form != "grid":
             if init_params is None:
@@ -268,6 +267,10 @@ class MeshRun:
             self.refit()
         dt = cfg.dt_mesh / cfg.substeps
         pts, idx = self.pts, None
+        rows = None                 # all nodes simulated: the solve writes the history rows
+        if not cfg.key_points:
+            rows = {"xi": self._iface[self.n, 0], "eta": self._iface[self.n, 1],
+                    "se_xi": self._se[self.n, 0], "se_eta": self._se[self.n, 1]}
         if cfg.key_points:
             fk_key_points(self._wg, cfg.px, cfg.m, cfg.key_tol, cfg.key_gap or None, out=self._mask)
             idx = np.flatnonzero(self._mask.cpu().numpy())           # synchronises: the node list is host input
@@ -280,17 +283,19 @@ class MeshRun:
             out = fk_interface_solve_cv(dens, data, pts, cfg.dt_mesh, dt, cfg.n_paths, None,
                                         stride=cfg.cv_stride, seed=cfg.seed, level_id=self.n,
                                         form=FK_CV_MARTINGALE_GRID, plain=False, device=self.dev,
-                                        workspace=self.workspace, grids=grids)
+                                        workspace=self.workspace, grids=grids, out=rows)
             self.used_cv[self.n] = True
         elif self.cv is not None:
             form = FK_CV_MARTINGALE if cfg.cv_form == "martingale" else FK_CV_DYNKIN
             out = fk_interface_solve_cv(dens, data, pts, cfg.dt_mesh, dt, cfg.n_paths, self.cv,
                                         stride=cfg.cv_stride, seed=cfg.seed, level_id=self.n, form=form,
-                                        plain=False, device=self.dev, workspace=self.workspace, grids=grids)
+                                        plain=False, device=self.dev, workspace=self.workspace, grids=grids,
+                                        out=rows)
             self.used_cv[self.n] = True
         else:
             out = fk_interface_solve(dens, data, pts, cfg.dt_mesh, dt, cfg.n_paths, seed=cfg.seed,
-                                     level_id=self.n, device=self.dev, workspace=self.workspace, grids=grids)
+                                     level_id=self.n, device=self.dev, workspace=self.workspace, grids=grids,
+                                     out=rows)
         self.workspace = out["_workspace"]
         if cfg.key_points:
             # the line ends: this step's outer boundary data, in the grids the
@@ -298,24 +303,20 @@ class MeshRun:
             self._bdry_ws = fk_boundary_data(dens, tn, self.N, cfg.bdry, self.spare[0], self.spare[1],
                                              workspace=self._bdry_ws)
             iface_xi, iface_eta = fk_interface_interpolate(cfg.px, cfg.m, self._slot, out["xi"], out["eta"],
-                                                           self.spare[0], self.spare[1], out=self._iface_buf)
+                                                           self.spare[0], self.spare[1],
+                                                           out=(self._iface[self.n, 0], self._iface[self.n, 1]))
         else:
             iface_xi, iface_eta = out["xi"], out["eta"]
         xi_new, eta_new = subdomain_solve(dens, tn, cfg.dt_mesh, cfg.px, cfg.m, self.xi, self.eta, iface_xi,
                                           iface_eta, bdry_kind=cfg.bdry, out=self.spare,
                                           workspace=self.sub_workspace)
-        self._quality[self.n] = fk_mesh_quality(xi_new, eta_new)
-        self._iface[self.n, :, 0] = iface_xi
-        self._iface[self.n, :, 1] = iface_eta
-        if idx is None:
-            self._se[self.n, :, 0] = out["se_xi"]
-            self._se[self.n, :, 1] = out["se_eta"]
-        else:
+        fk_mesh_quality(xi_new, eta_new, out=self._quality[self.n])
+        if idx is not None:
             # standard errors exist at the key points only
             self._se[self.n].fill_(float("nan"))
             it = self.torch.from_numpy(idx).to(self.dev)
-            self._se[self.n, it, 0] = out["se_xi"]
-            self._se[self.n, it, 1] = out["se_eta"]
+            self._se[self.n, 0, it] = out["se_xi"]
+            self._se[self.n, 1, it] = out["se_eta"]
         if self.cv is not None:
             if self._band_idx is None:
                 self._add_labels(tn + cfg.dt_mesh, iface_xi, iface_eta)
@@ -337,7 +338,8 @@ class MeshRun:
     def interface_values(self):
         """([steps, nodes, 2] interface values, [steps, nodes, 2] standard
         errors; with key points, NaN at the interpolated nodes)."""
-        return self._iface[:self.n].cpu().numpy(), self._se[:self.n].cpu().numpy()
+        return (self._iface[:self.n].transpose(1, 2).cpu().numpy(),
+                self._se[:self.n].transpose(1, 2).cpu().numpy())
 
     def mesh(self):
         """The current (xi, eta) grids on the host, [N+1, N+1] each, indexed [j][i]."""

@@ -146,3 +146,18 @@ def test_steady_subdomain_validation(fk):
     assert lib.subdomain_solve(d, 0.0, -inf, 2, 8, 0, 4096, 4096, 4096, 4096, 4096, 4096, 4096, need, None) == -1
     # transient solves need the previous mesh
     assert lib.subdomain_solve(d, 0.0, 1e-3, 2, 8, 0, None, None, 4096, 4096, 4096, 4096, 4096, need, None) == -1
+
+
+def test_binding_rejects_bad_output_rows(fk):
+    """Caller-supplied outputs (history rows of a mesh run) are checked in
+    the binding before any call: FP64, contiguous, the right length."""
+    import torch
+    x = torch.zeros(9, dtype=torch.float64)
+    with pytest.raises(ValueError):
+        fk.fk_mesh_quality(x, x, out=torch.zeros(3, dtype=torch.float64))
+    with pytest.raises(ValueError):
+        fk.fk_mesh_quality(x, x, out=torch.zeros(2, dtype=torch.float32))
+    with pytest.raises(ValueError):
+        fk.fk_interface_solve_cv(W.CONST, W.Data(), np.array([[0.5, 0.5], [0.25, 0.5]]), 0.01, 1e-3, 64, None,
+                                 form=fk.FK_CV_MARTINGALE_GRID, device="cpu",
+                                 out={"xi": torch.zeros((2, 2), dtype=torch.float64)[:, 0]})

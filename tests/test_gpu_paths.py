@@ -166,6 +166,20 @@ def test_schedule_invariance(fk, torch_cuda):
     for k in ("xi", "eta", "se_xi", "se_eta", "exit_step", "scores", "steps"):
         assert np.array_equal(a[k], b[k]), k
         assert np.array_equal(a[k], c[k]), k
+    # a short horizon (20 steps: the default takes 256 paths per grab) and
+    # grids cut to the chunk count, down to a single wavefront
+    ring = W.paper_ring(W.TIME_FROZEN, 0.3)
+    pts = W.interface_nodes(2, 2, 40)
+    runs = [run_gpu(fk, torch_cuda, ring, W.Data(), pts, 1e-3, 5e-5, 1000, plan=pl)
+            for pl in (None, {"chunk": 128}, {"block": 64, "chunk": 7, "blocks_per_cu": 3}, {"chunk": 1000})]
+    one = [run_gpu(fk, torch_cuda, ring, W.Data(), pts[:1], 1e-3, 5e-5, 50, plan=pl)
+           for pl in (None, {"chunk": 50})]
+    for k in ("xi", "eta", "se_xi", "se_eta", "exit_step", "scores", "steps"):
+        for r in runs[1:]:
+            assert np.array_equal(runs[0][k], r[k]), k
+        assert np.array_equal(one[0][k], one[1][k]), k
+    for k in ("exit_step", "scores"):           # the same counters: node 0's first 50 paths
+        assert np.array_equal(one[0][k][0], runs[0][k][0][:50]), k
 
 
 def test_full_size_moving_bump_sampled(fk, torch_cuda, oracle_mod):
