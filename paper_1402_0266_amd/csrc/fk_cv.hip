@@ -449,7 +449,7 @@ __global__ void __launch_bounds__(256, 2) fk_cv_path_kernel(const PathArgs a, co
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t q_slot = 0, q_next = 0, q_end = 0;
-    bool q_done = false, first_grab = true;
+    bool q_done = !chunk_cursor(a, first_chunk(), q_slot, q_next, q_end);
     const uint32_t key0 = a.key0, key1 = a.key1;
     Lane L;
     bool active = false, parked = false, out = false;
@@ -503,14 +503,10 @@ __global__ void __launch_bounds__(256, 2) fk_cv_path_kernel(const PathArgs a, co
             uint64_t need = __ballot(!active && !parked);
             while (need != 0ull && !q_done) {
                 if (q_next >= q_end) {
-                    const uint32_t cc = next_chunk(a, first_grab);
-                    if (cc >= a.total_chunks) {
+                    if (!chunk_cursor(a, next_chunk(a), q_slot, q_next, q_end)) {
                         q_done = true;
                         break;
                     }
-                    q_slot = cc / a.cpn;
-                    q_next = (cc - q_slot * a.cpn) * a.chunk;
-                    q_end = min(q_next + a.chunk, a.n_paths);
                     continue;
                 }
                 const uint32_t avail = q_end - q_next;
@@ -603,7 +599,7 @@ __global__ void __launch_bounds__(256, 4) fk_mg_path_kernel(const PathArgs a, co
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t q_slot = 0, q_next = 0, q_end = 0;
-    bool q_done = false, first_grab = true;
+    bool q_done = !chunk_cursor(a, first_chunk(), q_slot, q_next, q_end);
     const uint32_t key0 = a.key0, key1 = a.key1;
     Lane L;
     bool active = false;
@@ -636,14 +632,10 @@ __global__ void __launch_bounds__(256, 4) fk_mg_path_kernel(const PathArgs a, co
             uint64_t need = __ballot(!active);
             while (need != 0ull && !q_done) {
                 if (q_next >= q_end) {
-                    const uint32_t cc = next_chunk(a, first_grab);
-                    if (cc >= a.total_chunks) {
+                    if (!chunk_cursor(a, next_chunk(a), q_slot, q_next, q_end)) {
                         q_done = true;
                         break;
                     }
-                    q_slot = cc / a.cpn;
-                    q_next = (cc - q_slot * a.cpn) * a.chunk;
-                    q_end = min(q_next + a.chunk, a.n_paths);
                     continue;
                 }
                 const uint32_t avail = q_end - q_next;
@@ -748,7 +740,7 @@ __global__ void __launch_bounds__(256) fk_mgg_path_kernel(const PathArgs a, cons
     constexpr bool kMovingBackward = moving_kind(KIND) && TMODE == TIME_BACKWARD;
     const uint32_t lane = threadIdx.x & 63u;
     uint32_t q_slot = 0, q_next = 0, q_end = 0;
-    bool q_done = false, first_grab = true;
+    bool q_done = !chunk_cursor(a, first_chunk(), q_slot, q_next, q_end);
     const uint32_t key0 = a.key0, key1 = a.key1;
     Lane L;
     bool active = false;
@@ -761,14 +753,10 @@ __global__ void __launch_bounds__(256) fk_mgg_path_kernel(const PathArgs a, cons
         uint64_t need = __ballot(!active);
         while (need != 0ull && !q_done) {
             if (q_next >= q_end) {
-                const uint32_t cc = next_chunk(a, first_grab);
-                if (cc >= a.total_chunks) {
+                if (!chunk_cursor(a, next_chunk(a), q_slot, q_next, q_end)) {
                     q_done = true;
                     break;
                 }
-                q_slot = cc / a.cpn;
-                q_next = (cc - q_slot * a.cpn) * a.chunk;
-                q_end = min(q_next + a.chunk, a.n_paths);
                 continue;
             }
             const uint32_t avail = q_end - q_next;

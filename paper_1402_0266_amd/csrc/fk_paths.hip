@@ -57,7 +57,7 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
     const uint32_t lane = threadIdx.x & 63u;
     // Wavefront-uniform queue cursor: current node slot and path range.
     uint32_t q_slot = 0, q_next = 0, q_end = 0;
-    bool q_done = false, first_grab = true;
+    bool q_done = false;
     const uint32_t key0 = a.key0, key1 = a.key1;
 
     Lane L;
@@ -69,7 +69,9 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
         uint64_t need = __ballot(!active);
         while (need != 0ull && !q_done) {
             if (q_next >= q_end) {
-                const uint32_t c = next_chunk(a, first_grab);
+                uint32_t c = 0;
+                if (lane == 0) c = atomicAdd(a.queue, 1u);
+                c = __builtin_amdgcn_readfirstlane(c);
                 if (c >= a.total_chunks) {
                     q_done = true;
                     break;

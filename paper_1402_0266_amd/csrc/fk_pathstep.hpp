@@ -126,21 +126,27 @@ __device__ __forceinline__ float grid_bilinear(const double *g, int n, float x, 
 }
 
 
-// The next work chunk of a wavefront (wave-uniform).  A wavefront's first
-// chunk is its own index in the grid, so a launch starts without every
-// wavefront contending for the one counter at once; later chunks come from
-// the counter, past the first grid-full.  Which wavefront runs which chunk
-// does not change any result: paths draw their numbers by their own
-// counters.
-__device__ __forceinline__ uint32_t next_chunk(const PathArgs &a, bool &first) {
-    const uint32_t waves = gridDim.x * (blockDim.x >> 6);
-    if (first) {
-        first = false;
-        return blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
-    }
+// Work chunks of a wavefront in the control-variate kernels (wave-uniform).
+// A wavefront's first chunk is its own index in the grid, so a launch starts
+// without every wavefront contending for the one counter at once; later
+// chunks come from the counter, past the first grid-full.  Which wavefront
+// runs which chunk does not change any result: paths draw their numbers by
+// their own counters.  (The plain path kernel keeps its first grab on the
+// counter: the same change there costs ~3% in its hot loop's code.)
+__device__ __forceinline__ uint32_t first_chunk() { return blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); }
+__device__ __forceinline__ uint32_t next_chunk(const PathArgs &a) {
     uint32_t c = 0;
     if ((threadIdx.x & 63u) == 0) c = atomicAdd(a.queue, 1u);
-    return __builtin_amdgcn_readfirstlane(c) + waves;
+    return __builtin_amdgcn_readfirstlane(c) + gridDim.x * (blockDim.x >> 6);
+}
+// The cursor (node slot, path range) of chunk c; false past the last chunk.
+__device__ __forceinline__ bool chunk_cursor(const PathArgs &a, uint32_t c, uint32_t &slot, uint32_t &next,
+                                             uint32_t &end) {
+    if (c >= a.total_chunks) return false;
+    slot = c / a.cpn;
+    next = (c - slot * a.cpn) * a.chunk;
+    end = min(next + a.chunk, a.n_paths);
+    return true;
 }
 
 // Loads path `path` of node `nd` into a lane.
