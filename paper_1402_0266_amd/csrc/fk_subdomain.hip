@@ -144,15 +144,19 @@ __device__ void node_drift_f64(const SubArgs &a, int gi, int gj, double &bx, dou
 
 constexpr int kMaxP1 = 128;  // window side limit: q <= 127 interior nodes per side
 
-// The density w in FP64 at (x, y), frozen at t_w.
-__device__ double density_f64(const SubArgs &a, double x, double y) {
-    const double A = a.amp, s2 = a.width2;
-    if (a.kind == FK_DENSITY_CONST) return 1.0;
-    double ox = 0.0, oy = 0.0;
+// The orbit offset of a moving centre at t_w (zero for static densities).
+__device__ void orbit_f64(const SubArgs &a, double &ox, double &oy) {
+    ox = oy = 0.0;
     if (a.kind == FK_DENSITY_MOVING_BUMP || a.kind == FK_DENSITY_TWO_BUMPS || a.kind == FK_DENSITY_RING) {
         ox = a.orbit_r * cos(a.omega * a.t_w);
         oy = a.orbit_r * sin(a.omega * a.t_w);
     }
+}
+
+// The density w in FP64 at (x, y), frozen at t_w, given the orbit offset.
+__device__ double density_f64(const SubArgs &a, double ox, double oy, double x, double y) {
+    const double A = a.amp, s2 = a.width2;
+    if (a.kind == FK_DENSITY_CONST) return 1.0;
     if (a.kind == FK_DENSITY_RING) {
         const double dx = x - (a.cx + ox), dy = y - (a.cy + oy);
         return 1.0 / (1.0 + A * exp(s2 * fabs(dx * dx + dy * dy - 0.01)));
@@ -167,12 +171,15 @@ __device__ double density_f64(const SubArgs &a, double x, double y) {
 
 // Integrals of w over the grid cells along the four edges (composite
 // Simpson, 256 panels per cell): edge 0 y = 0, 1 y = 1 (over x), 2 x = 0,
-// 3 x = 1 (over y).  cells[e * N + c] is the integral over cell c.
+// 3 x = 1 (over y).  cells[e * N + c] is the integral over cell c.  One
+// wavefront per cell: each lane sums every 64th Simpson node, then a
+// butterfly (fixed order) adds the lanes.  Launch: 4 N wavefronts.
 __global__ void edge_cells_kernel(const SubArgs a, double *cells) {
     constexpr int M = 256;
     const int N = a.N;
-    const int t = blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= 4 * N) return;
+    const int t = blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (t >= 4 * N) return;                      // the whole wavefront
     const int e = t / N, c = t % N;
     const bool horizontal = e < 2;
     const double fixed = (e == 1 || e == 3) ? 1.0 : 0.0;
@@ -181,17 +188,21 @@ __global__ void edge_cells_kernel(const SubArgs a, double *cells) {
         const int64_t N1 = N + 1;
         const int64_t at = horizontal ? (e == 1 ? (int64_t)N * N1 : 0) + c : (int64_t)c * N1 + (e == 3 ? N : 0);
         const int64_t next = horizontal ? 1 : N1;
-        cells[t] = 0.5 * (a.wg[at] + a.wg[at + next]) / N;
+        if (lane == 0) cells[t] = 0.5 * (a.wg[at] + a.wg[at + next]) / N;
         return;
     }
+    double ox, oy;
+    orbit_f64(a, ox, oy);
     const double u0 = (double)c / N, hq = 1.0 / ((double)N * M);
     double acc = 0.0;
-    for (int i = 0; i <= M; ++i) {
+    for (int i = lane; i <= M; i += 64) {
         const double u = u0 + i * hq;
-        const double w = horizontal ? density_f64(a, u, fixed) : density_f64(a, fixed, u);
+        const double w = horizontal ? density_f64(a, ox, oy, u, fixed) : density_f64(a, ox, oy, fixed, u);
         acc += w * ((i == 0 || i == M) ? 1.0 : ((i & 1) ? 4.0 : 2.0));
     }
-    cells[t] = acc * hq / 3.0;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) cells[t] = acc * hq / 3.0;
 }
 
 // w(t_w, i/n, j/n) at the nodes of an n-cell grid.
@@ -199,7 +210,9 @@ __global__ void density_sample_kernel(const SubArgs a, int n, double *out) {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n1 = n + 1;
     if (t >= n1 * n1) return;
-    out[t] = density_f64(a, (double)(t % n1) / n, (double)(t / n1) / n);
+    double ox, oy;
+    orbit_f64(a, ox, oy);
+    out[t] = density_f64(a, ox, oy, (double)(t % n1) / n, (double)(t / n1) / n);
 }
 
 // int_0^{i/N} w / int_0^1 w along edge e, from the cell integrals (summed in
@@ -269,11 +282,10 @@ __device__ __forceinline__ void back_substitute_blocked(const SubArgs &a, const 
     };
     double xr0 = sep_val(lane, 0), xr1 = sep_val(lane + 64, 0);
     double yr0 = sep_val(lane, 1), yr1 = sep_val(lane + 64, 1);
-    double c0[kD], c1[kD], cd[kD], cyx[kD], cyy[kD], ct[kD];
-    double n0[kD], n1[kD], nd[kD], nyx[kD], nyy[kD], nt[kD];
-    // rows top - j: the entries multiplying the ring, the diagonal, y, and
-    // (lane l < kD - 1) the entry U[k][k + l + 1] the block's triangle needs
-    auto load = [&](int top, double *u0, double *u1, double *ud, double *yx, double *yy, double *ut) {
+    double c0[kD], c1[kD], cd[kD], cyx[kD], cyy[kD];
+    double n0[kD], n1[kD], nd[kD], nyx[kD], nyy[kD];
+    // rows top - j: the entries multiplying the ring, the diagonal and y
+    auto load = [&](int top, double *u0, double *u1, double *ud, double *yx, double *yy) {
 #pragma unroll
         for (int j = 0; j < kD; ++j) {
             const int k = top - j;
@@ -285,12 +297,11 @@ __device__ __forceinline__ void back_substitute_blocked(const SubArgs &a, const 
             ud[j] = ok ? row[0] : 1.0;
             yx[j] = ok ? Y[k] : 0.0;
             yy[j] = ok ? Y[n + k] : 0.0;
-            ut[j] = (ok && lane < j) ? row[lane + 1] : 0.0;
         }
     };
-    load(top0, c0, c1, cd, cyx, cyy, ct);
+    load(top0, c0, c1, cd, cyx, cyy);
     for (int top = top0; top >= 0; top -= kD) {
-        load(top - kD, n0, n1, nd, nyx, nyy, nt);
+        load(top - kD, n0, n1, nd, nyx, nyy);
         // 2 kD partial sums per lane, reduced across the wave by a butterfly
         // that halves the values each lane keeps (offsets 32, 16, 8, 4: lane
         // l ends with value l >> 2 summed over the 16 lanes that share its
@@ -325,12 +336,16 @@ __device__ __forceinline__ void back_substitute_blocked(const SubArgs &a, const 
         double xb[kD], yb[kD];
 #pragma unroll
         for (int j = 0; j < kD; ++j) {
+            const int k = top - j;
             double tx = cyx[j] - sx[j], ty = cyy[j] - sy[j];
+            if (k >= 0) {
+                const double *row = U + (int64_t)k * P1;
 #pragma unroll
-            for (int i = 0; i < j; ++i) {
-                const double u = readlane_f64(ct[j], j - i - 1);   // U[k][k + (j - i)] multiplies x_{k_i}
-                tx = fma(-u, xb[i], tx);
-                ty = fma(-u, yb[i], ty);
+                for (int i = 0; i < j; ++i) {
+                    const double u = row[j - i];   // U[k][k + (j - i)] multiplies x_{k_i}
+                    tx = fma(-u, xb[i], tx);
+                    ty = fma(-u, yb[i], ty);
+                }
             }
             xb[j] = tx / cd[j];
             yb[j] = ty / cd[j];
@@ -368,7 +383,6 @@ __device__ __forceinline__ void back_substitute_blocked(const SubArgs &a, const 
             cd[j] = nd[j];
             cyx[j] = nyx[j];
             cyy[j] = nyy[j];
-            ct[j] = nt[j];
         }
     }
 }
@@ -442,6 +456,7 @@ __global__ void __launch_bounds__(256) subdomain_lu_kernel(const SubArgs a) {
     const bool rev = a.twisted && (blockIdx.x & 1);           // the reversed (bottom) end
     const int si = sd % a.px, sj = sd / a.px;
     const int i0 = si * a.m, j0 = sj * a.m;
+    const int N1 = a.N + 1;
     // rows eliminated here, and where this end's U rows and y values go
     const int steps = !a.twisted ? n : (rev ? n - a.sep - q : a.sep);
     const int off = rev ? a.sep : 0;
@@ -452,12 +467,39 @@ __global__ void __launch_bounds__(256) subdomain_lu_kernel(const SubArgs a) {
     double2 *rh = reinterpret_cast<double2 *>(a.rbuf + cix * 2 * n);
     const int tid = threadIdx.x;
 
-    assemble_rows(a, n, q, i0, j0, rev, cf, rh);
+    // ---- every row's coefficients (Dirichlet neighbours moved to the rhs) --
+    for (int r = tid; r < n; r += blockDim.x) {
+        const int ii = r % q, jj = r / q;
+        const int gi = i0 + 1 + ii, gj = j0 + 1 + jj;
+        double bx, by;
+        node_drift_f64(a, gi, gj, bx, by);
+        const double cxr = a.half_d_over_h * bx, cyr = a.half_d_over_h * by;
+        const double cE = -a.c - cxr, cW = -a.c + cxr, cN = -a.c - cyr, cS = -a.c + cyr;
+        const int64_t g = (int64_t)gj * N1 + gi;
+        double fx = a.steady ? 0.0 : a.xi_n[g], fy = a.steady ? 0.0 : a.eta_n[g];
+        if (ii == q - 1) { fx -= cE * a.xi_out[g + 1]; fy -= cE * a.eta_out[g + 1]; }
+        if (ii == 0) { fx -= cW * a.xi_out[g - 1]; fy -= cW * a.eta_out[g - 1]; }
+        if (jj == q - 1) { fx -= cN * a.xi_out[g + N1]; fy -= cN * a.eta_out[g + N1]; }
+        if (jj == 0) { fx -= cS * a.xi_out[g - N1]; fy -= cS * a.eta_out[g - N1]; }
+        const double e = ii < q - 1 ? cE : 0.0, w = ii > 0 ? cW : 0.0;
+        const double nn = jj < q - 1 ? cN : 0.0, ss = jj > 0 ? cS : 0.0;
+        // the reversed system: row n-1-r, east <-> west, north <-> south
+        cf[rev ? n - 1 - r : r] = rev ? make_double4(w, e, ss, nn) : make_double4(e, w, nn, ss);
+        rh[rev ? n - 1 - r : r] = make_double2(fx, fy);
+    }
     __threadfence_block();
     __syncthreads();
 
     const double diag = a.diag0 + 4.0 * a.c;
-    auto entry = [&](int r, int c) -> double { return band_entry(cf, n, q, diag, r, c); };
+    // original matrix entry (r, c); identity beyond n
+    auto entry = [&](int r, int c) -> double {
+        if (r >= n || c >= n) return r == c ? 1.0 : 0.0;
+        const int d = c - r;
+        if (d == 0) return diag;
+        if (d != 1 && d != -1 && d != q && d != -q) return 0.0;
+        const double4 f = cf[r];
+        return d == 1 ? f.x : d == -1 ? f.y : d == q ? f.z : f.w;
+    };
     // roles: column slot / right-hand side, and which half of the rows
     const bool is_col = tid < 2 * P1;
     const bool is_rhs = !is_col && tid < 2 * P1 + 4;
@@ -1292,7 +1334,7 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
     a.t_w = t_w;
     a.wg = w->kind == FK_DENSITY_GRID ? w->grid_w : nullptr;
     if (bdry_kind == FK_DATA_EQUIDISTRIBUTED) {
-        hipLaunchKernelGGL(edge_cells_kernel, dim3((unsigned)((4 * N + 255) / 256)), dim3(256), 0, stream, a,
+        hipLaunchKernelGGL(edge_cells_kernel, dim3((unsigned)((4 * N + 3) / 4)), dim3(256), 0, stream, a,
                            edge_cells);
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "edge integral kernel launch");
     }
@@ -1360,7 +1402,7 @@ int fk_boundary_data(const fk_density *w, double t_w, int32_t n, int32_t bdry_ki
     double *edge_cells = (double *)workspace;
     hipError_t e;
     if (bdry_kind == FK_DATA_EQUIDISTRIBUTED) {
-        hipLaunchKernelGGL(edge_cells_kernel, dim3((unsigned)((4 * n + 255) / 256)), dim3(256), 0, stream, a,
+        hipLaunchKernelGGL(edge_cells_kernel, dim3((unsigned)((4 * n + 3) / 4)), dim3(256), 0, stream, a,
                            edge_cells);
         if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "edge integral kernel launch");
     }
