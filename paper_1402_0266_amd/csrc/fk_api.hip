@@ -288,11 +288,12 @@ int enqueue_solve(const SolveLaunch &S, hipStream_t stream, bool allow_timing) {
     a.total_chunks = (uint32_t)(S.n_nodes * cpn);
     int bpc = S.plan.blocks_per_cu;
     const int occ = path_kernel_max_blocks_per_cu(S.kind, S.time_mode, S.uniform, a.score_mode == FK_SCORE_BRIDGE,
-                                                  S.plan.block);
+                                                  S.first_by_index, S.plan.block);
     if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
     const int grid = cap_grid(n_cu * bpc, a.total_chunks, S.plan.block);
     if ((e = timing_mark(timed, 0, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    if ((e = launch_paths(S.kind, S.time_mode, S.uniform, a, grid, S.plan.block, stream)) != hipSuccess)
+    if ((e = launch_paths(S.kind, S.time_mode, S.uniform, S.first_by_index, a, grid, S.plan.block, stream)) !=
+        hipSuccess)
         return hip_fail(e, "path kernel launch");
     if ((e = timing_mark(timed, 1, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     ReduceArgs r = S.reduce;
@@ -435,10 +436,12 @@ int fk_interface_solve(const fk_density *w, const fk_data *d, const double *pts,
     S.time_mode = T.time_mode;
     S.uniform = T.uniform;
     S.plan = pl;
-    // Default chunk: short paths (a mesh step of a few tens of sub-steps)
-    // take 256 paths per grab, which halves the wavefronts' fixed costs per
-    // path; long ones 128, for the balance of the tail.
-    if ((!plan || plan->chunk == 0) && T.levels[0].K <= 64) S.plan.chunk = 256;
+    // Short paths (a mesh step of a few tens of sub-steps): each wavefront's
+    // first chunk by its grid index, and by default 256 paths per grab,
+    // which halves the wavefronts' fixed costs per path; long ones 128, for
+    // the balance of the tail.
+    S.first_by_index = T.levels[0].K <= 64;
+    if ((!plan || plan->chunk == 0) && S.first_by_index) S.plan.chunk = 256;
     S.n_nodes = n_nodes;
     S.n_paths = n_paths;
     S.counters = (uint32_t *)(ws + lay.counters);

@@ -213,7 +213,7 @@ int fk_batch_autotune(fk_batch_t b, int64_t probe_paths, void *workspace, size_t
             for (int dv : bpc_div) {
                 if (rc != FK_OK) break;
                 const int occ = path_kernel_max_blocks_per_cu(b->T.kind, b->T.time_mode, b->T.uniform,
-                                                              b->data.score_mode == FK_SCORE_BRIDGE, bl);
+                                                              b->data.score_mode == FK_SCORE_BRIDGE, false, bl);
                 fk_plan pl{bl, occ > 0 ? (occ + dv - 1) / dv : 0, ch, 0};
                 if (check_chunks(b->n_total, probe_paths, pl) != FK_OK) continue;
                 hipEventRecord(e0, stream);

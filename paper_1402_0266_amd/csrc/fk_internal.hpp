@@ -113,6 +113,7 @@ struct SolveLaunch {
     ReduceArgs reduce;   // outputs; sizes filled by enqueue_solve
     int kind, time_mode;
     bool uniform;
+    bool first_by_index;  // short horizons: each wavefront's first chunk by its grid index
     fk_plan plan;
     int64_t n_nodes, n_paths;
     uint32_t *counters;  // 256 B of device scratch (queue, step count)
@@ -152,9 +153,9 @@ hipError_t timing_record(int i, hipStream_t s);
 
 // Launch helpers implemented in fk_paths.hip.
 hipError_t launch_zero_u32(uint32_t *p, int n_words, hipStream_t s);
-hipError_t launch_paths(int kind, int time_mode, bool uniform, const PathArgs &a, int grid, int block,
+hipError_t launch_paths(int kind, int time_mode, bool uniform, bool first_by_index, const PathArgs &a, int grid, int block,
                         hipStream_t s);
 hipError_t launch_reduce(const ReduceArgs &a, hipStream_t s);
-int path_kernel_max_blocks_per_cu(int kind, int time_mode, bool uniform, bool bridge, int block);
+int path_kernel_max_blocks_per_cu(int kind, int time_mode, bool uniform, bool bridge, bool first_by_index, int block);
 
 }  // namespace fk

@@ -50,14 +50,19 @@ hipError_t launch_zero_u32(uint32_t *p, int n_words, hipStream_t s) {
 
 
 // BRIDGE: the Brownian-bridge crossing test after every step that stays
-// inside (score mode FK_SCORE_BRIDGE).
-template <int KIND, int TMODE, bool UNIFORM, bool BRIDGE>
+// inside (score mode FK_SCORE_BRIDGE).  FIRST_BY_INDEX (short horizons): a
+// wavefront's first chunk is its index in the grid, later ones come from the
+// counter past the first grid-full, so a launch of short paths does not open
+// with every wavefront contending for the counter.  Long horizons keep the
+// counter for every grab (the other form costs their hot loop ~3% in code).
+template <int KIND, int TMODE, bool UNIFORM, bool BRIDGE, bool FIRST_BY_INDEX = false>
 __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
     constexpr bool kMovingBackward = moving_kind(KIND) && TMODE == TIME_BACKWARD;
     const uint32_t lane = threadIdx.x & 63u;
     // Wavefront-uniform queue cursor: current node slot and path range.
     uint32_t q_slot = 0, q_next = 0, q_end = 0;
     bool q_done = false;
+    if constexpr (FIRST_BY_INDEX) q_done = !chunk_cursor(a, first_chunk(), q_slot, q_next, q_end);
     const uint32_t key0 = a.key0, key1 = a.key1;
 
     Lane L;
@@ -72,6 +77,7 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
                 uint32_t c = 0;
                 if (lane == 0) c = atomicAdd(a.queue, 1u);
                 c = __builtin_amdgcn_readfirstlane(c);
+                if constexpr (FIRST_BY_INDEX) c += gridDim.x * (blockDim.x >> 6);
                 if (c >= a.total_chunks) {
                     q_done = true;
                     break;
@@ -155,31 +161,34 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
 }
 
 namespace {
-template <int KIND, int TMODE, bool UNIFORM, bool BRIDGE>
+template <int KIND, int TMODE, bool UNIFORM, bool BRIDGE, bool FIRST>
 hipError_t launch_one(const PathArgs &a, int grid, int block, hipStream_t s) {
-    hipLaunchKernelGGL((fk_path_kernel<KIND, TMODE, UNIFORM, BRIDGE>), dim3(grid), dim3(block), 0, s, a);
+    hipLaunchKernelGGL((fk_path_kernel<KIND, TMODE, UNIFORM, BRIDGE, FIRST>), dim3(grid), dim3(block), 0, s, a);
     return hipGetLastError();
 }
 
-template <int KIND, int TMODE, bool UNIFORM, bool BRIDGE>
+template <int KIND, int TMODE, bool UNIFORM, bool BRIDGE, bool FIRST>
 int max_blocks(int block) {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk_path_kernel<KIND, TMODE, UNIFORM, BRIDGE>, block, 0) !=
-        hipSuccess)
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk_path_kernel<KIND, TMODE, UNIFORM, BRIDGE, FIRST>, block,
+                                                     0) != hipSuccess)
         return 0;
     return nb;
 }
 
-// Calls F<KIND, TMODE, UNIFORM, BRIDGE>::run(args...) for the runtime values.
-template <template <int, int, bool, bool> class F, typename... Args>
-auto dispatch(int kind, int time_mode, bool uniform, bool bridge, Args &&...args) {
+// Calls F<KIND, TMODE, UNIFORM, BRIDGE, FIRST>::run(args...) for the runtime
+// values; the first-chunk-by-index form only for uniform steps without the
+// bridge test (a mesh step's sub-steps).
+template <template <int, int, bool, bool, bool> class F, typename... Args>
+auto dispatch(int kind, int time_mode, bool uniform, bool bridge, bool first_by_index, Args &&...args) {
     const bool frozen = (time_mode == TIME_FROZEN);
 #define FK_CASE(K, T)                                                                          \
     if (bridge)                                                                                \
-        return uniform ? F<K, T, true, true>::run(std::forward<Args>(args)...)                \
-                       : F<K, T, false, true>::run(std::forward<Args>(args)...);              \
-    return uniform ? F<K, T, true, false>::run(std::forward<Args>(args)...)                   \
-                   : F<K, T, false, false>::run(std::forward<Args>(args)...)
+        return uniform ? F<K, T, true, true, false>::run(std::forward<Args>(args)...)         \
+                       : F<K, T, false, true, false>::run(std::forward<Args>(args)...);       \
+    if (uniform && first_by_index) return F<K, T, true, false, true>::run(std::forward<Args>(args)...); \
+    return uniform ? F<K, T, true, false, false>::run(std::forward<Args>(args)...)            \
+                   : F<K, T, false, false, false>::run(std::forward<Args>(args)...)
     switch (kind) {
     case KIND_CONST: FK_CASE(KIND_CONST, TIME_BACKWARD);
     case KIND_BUMP: FK_CASE(KIND_BUMP, TIME_BACKWARD);
@@ -198,15 +207,15 @@ auto dispatch(int kind, int time_mode, bool uniform, bool bridge, Args &&...args
 #undef FK_CASE
 }
 
-template <int K, int T, bool U, bool B>
+template <int K, int T, bool U, bool B, bool F>
 struct LaunchF {
     static hipError_t run(const PathArgs &a, int grid, int block, hipStream_t s) {
-        return launch_one<K, T, U, B>(a, grid, block, s);
+        return launch_one<K, T, U, B, F>(a, grid, block, s);
     }
 };
-template <int K, int T, bool U, bool B>
+template <int K, int T, bool U, bool B, bool F>
 struct OccF {
-    static int run(int block) { return max_blocks<K, T, U, B>(block); }
+    static int run(int block) { return max_blocks<K, T, U, B, F>(block); }
 };
 
 bool kind_known(int kind) {
@@ -215,15 +224,17 @@ bool kind_known(int kind) {
 }
 }  // namespace
 
-hipError_t launch_paths(int kind, int time_mode, bool uniform, const PathArgs &a, int grid, int block,
-                        hipStream_t s) {
+hipError_t launch_paths(int kind, int time_mode, bool uniform, bool first_by_index, const PathArgs &a, int grid,
+                        int block, hipStream_t s) {
     if (!kind_known(kind)) return hipErrorInvalidValue;
-    return dispatch<LaunchF>(kind, time_mode, uniform, a.score_mode == FK_SCORE_BRIDGE, a, grid, block, s);
+    return dispatch<LaunchF>(kind, time_mode, uniform, a.score_mode == FK_SCORE_BRIDGE, first_by_index, a, grid,
+                             block, s);
 }
 
-int path_kernel_max_blocks_per_cu(int kind, int time_mode, bool uniform, bool bridge, int block) {
+int path_kernel_max_blocks_per_cu(int kind, int time_mode, bool uniform, bool bridge, bool first_by_index,
+                                  int block) {
     if (!kind_known(kind)) return 0;
-    return dispatch<OccF>(kind, time_mode, uniform, bridge, block);
+    return dispatch<OccF>(kind, time_mode, uniform, bridge, first_by_index, block);
 }
 
 // ---------------------------------------------------------------------------
