@@ -278,7 +278,8 @@ int enqueue_solve(const SolveLaunch &S, hipStream_t stream, bool allow_timing) {
             return hip_fail(e, "zero total_steps");
         a.total_steps = (unsigned long long *)S.total_steps;
     } else {
-        a.total_steps = (unsigned long long *)(S.counters + 2);
+        // the short-horizon kernel skips the count when nobody asked for it
+        a.total_steps = S.first_by_index ? nullptr : (unsigned long long *)(S.counters + 2);
     }
     a.queue = S.counters;
     const int64_t cpn = (S.n_paths + S.plan.chunk - 1) / S.plan.chunk;

@@ -74,6 +74,14 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
         uint64_t need = __ballot(!active);
         while (need != 0ull && !q_done) {
             if (q_next >= q_end) {
+                if constexpr (FIRST_BY_INDEX) {
+                    // a grid no larger than the chunk count hands out no more
+                    // chunks: finish without touching the counter
+                    if (gridDim.x * (blockDim.x >> 6) >= a.total_chunks) {
+                        q_done = true;
+                        break;
+                    }
+                }
                 uint32_t c = 0;
                 if (lane == 0) c = atomicAdd(a.queue, 1u);
                 c = __builtin_amdgcn_readfirstlane(c);
@@ -157,6 +165,9 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
     unsigned long long st = my_steps;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) st += __shfl_xor(st, off, 64);
+    if constexpr (FIRST_BY_INDEX) {
+        if (!a.total_steps) return;              // the caller did not ask for the count
+    }
     if (lane == 0 && st != 0ull) atomicAdd(a.total_steps, st);
 }
 

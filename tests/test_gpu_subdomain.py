@@ -33,6 +33,13 @@ def cuda(a):
     (1, 20, W.ridge(), 0.0, 0.01),
     (4, 64, W.moving_bump(), 0.0, 0.1),          # 4x4 layout on 64x64 grids
     (8, 96, W.two_bumps(W.TIME_FROZEN, 0.05), 0.05, 5e-4),  # 8x8 layout on 96x96 grids
+    # every side of the one-wavefront eliminations: 12 (whole system), 16
+    # and 24 (both ends, separator), 48 and 40 (lane-pair kernel)
+    (3, 12, W.moving_bump(), 0.07, 0.01),
+    (2, 16, W.paper_ring(W.TIME_FROZEN, 0.6), 0.6, 1e-3),
+    (3, 24, W.two_bumps(W.TIME_FROZEN, 0.01), 0.01, 2e-3),
+    (2, 48, W.static_bump(), 0.0, 1e-3),
+    (2, 40, W.ridge(), 0.0, 0.02),
 ])
 def test_subdomain_against_oracle(fk, px, m, dens, t_w, D):
     import torch
