@@ -80,7 +80,7 @@ FLOP_PER_STEP = 36
 # HBM traffic of the path kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
 # (scaled by a plain 1 GiB copy: fetch x2.0, write x1.0), per path, valid only
 # for the kernel sources it was measured on (hash below); otherwise null.
-TRAFFIC_BYTES_PER_PATH = (2.0 * 237.5625 + 1.0 * 1056834.5625) * 1024 / (1521 * 73858)
+TRAFFIC_BYTES_PER_PATH = (2.0 * 237.6875 + 1.0 * 1056887.71875) * 1024 / (1521 * 73858)
 TRAFFIC_SOURCE_HASH = "58f7fd54ff597d97"
 KERNEL_SOURCES = ["paper_1402_0266_amd/csrc/fk_paths.hip", "paper_1402_0266_amd/csrc/fk_device.hpp",
                   "paper_1402_0266_amd/csrc/fk_internal.hpp", "paper_1402_0266_amd/csrc/fk_pathstep.hpp"]
