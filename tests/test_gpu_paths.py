@@ -180,6 +180,8 @@ def test_schedule_invariance(fk, torch_cuda):
         assert np.array_equal(one[0][k], one[1][k]), k
     for k in ("exit_step", "scores"):           # the same counters: node 0's first 50 paths
         assert np.array_equal(one[0][k][0], runs[0][k][0][:50]), k
+    for r in runs + one:                        # the short form still counts steps when asked
+        assert int(r["total_steps"][0]) == int(r["steps"].sum())
 
 
 def test_full_size_moving_bump_sampled(fk, torch_cuda, oracle_mod):
