@@ -122,7 +122,11 @@ typedef struct fk_data {
     const double *grid_eta;  /* device, same layout; or NULL */
 } fk_data;
 
-/* Launch plan of the path kernel (see fk_plan_autotune). Zero fields take defaults. */
+/* Launch plan of the path kernel (see fk_plan_autotune).  Zero fields take defaults:
+ * block 256; blocks_per_cu the kernel's occupancy (the grid is cut to no more
+ * wavefronts than there are chunks); chunk 128, or 256 for horizons of at most 64
+ * steps in fk_interface_solve and in the network forms of fk_interface_solve_cv.
+ * The plan changes speed only: results depend on the counters alone. */
 typedef struct fk_plan {
     int32_t block;          /* threads per workgroup: 64, 128, 192 or 256 */
     int32_t blocks_per_cu;  /* resident workgroups per compute unit for the persistent grid */
