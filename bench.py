@@ -214,6 +214,16 @@ def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=409
     linear = {"form": "martingale, identity gradient", "pilot_s": el, "var": var,
               "var_ratio": float(np.mean(pse ** 2) / np.mean(se ** 2)), "bias": math.sqrt(b2), "n_star": n_lin,
               "predicted_nodes_per_s": None if n_lin is None else n_nodes / (el * n_lin / pilot_paths)}
+    if n_lin:
+        # and timed at its own N*, like the network's solve
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        rl = fk.fk_interface_solve_cv(wl.density, gdata, pts, wl.t, wl.dt, max(2, n_lin), None, stride=1 << 20,
+                                      seed=wl.seed, form=fk.FK_CV_MARTINGALE_GRID, grids=(gx.view(-1), gy.view(-1)))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        linear.update({"paths_per_node": max(2, n_lin), "s_per_solve": el, "nodes_per_s": n_nodes / el,
+                       "rms_err": float(np.sqrt(np.mean((_stack(rl, ("xi", "eta")) - ref) ** 2)))})
     return {
         "form": "martingale", "stride": stride, "paths_per_node": n_star, "rms_err": rms,
         "s_per_solve": wall, "path_kernel_ms": float(np.mean(kern)),
