@@ -442,6 +442,12 @@ int fk_cv_train(fk_cv_t cv, const float *txy, const float *target, int64_t n, in
                                      grid initial data at the path's position (no network: cv may be NULL;
                                      needs FK_DATA_GRID initial data); every `stride` steps of each path */
 size_t fk_interface_cv_workspace_bytes(int64_t n_nodes, int64_t n_paths);
+/* Workspace for FK_CV_MARTINGALE_GRID on a grid_n-cell grid with room for a per-cell FP32
+ * gradient table (32 B per cell, built on the stream by the solve): the path kernel then reads
+ * one cell entry per component instead of four FP64 grid values, with bitwise the same
+ * results.  A workspace of fk_interface_cv_workspace_bytes still works, reading the grids.
+ * Returns 0 for n_paths < 2, negative n_nodes or grid_n outside 1..65535. */
+size_t fk_interface_cv_grid_workspace_bytes(int64_t n_nodes, int64_t n_paths, int32_t grid_n);
 int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *pts, int64_t n_nodes, double t,
                           double dt, int64_t n_paths, uint64_t seed, uint32_t level_id, fk_cv_t cv, int32_t stride,
                           int32_t form, double *xi, double *eta, double *se_xi, double *se_eta, double *plain_xi,

@@ -147,6 +147,8 @@ _lib.fk_cv_train.argtypes = [_P, _P, _P, ctypes.c_int64, ctypes.c_int32, ctypes.
 _lib.fk_cv_train.restype = ctypes.c_int
 _lib.fk_interface_cv_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64]
 _lib.fk_interface_cv_workspace_bytes.restype = ctypes.c_size_t
+_lib.fk_interface_cv_grid_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32]
+_lib.fk_interface_cv_grid_workspace_bytes.restype = ctypes.c_size_t
 _lib.fk_interface_solve_cv.argtypes = [
     ctypes.POINTER(fk_density), ctypes.POINTER(fk_data), _P, ctypes.c_int64,
     ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32, _P, ctypes.c_int32,
@@ -624,7 +626,14 @@ def fk_interface_solve_cv(density, data, pts, t, dt, n_paths, cv, stride=2, seed
         out["exit_step"] = torch.empty((n, n_paths), dtype=torch.int32, device=dev)
     if cv_scores:
         out["cv_scores"] = torch.empty((n, n_paths, 2), dtype=torch.float32, device=dev)
-    need = _lib.fk_interface_cv_workspace_bytes(n, n_paths)
+    need = minimum = _lib.fk_interface_cv_workspace_bytes(n, n_paths)
+    if form == FK_CV_MARTINGALE_GRID and grids is not None:
+        # a new workspace gets room for the per-cell gradient table; a given
+        # one need only hold the rest (the kernel then reads the grids)
+        grid_n = int(round(grids[0].numel() ** 0.5)) - 1
+        need = _lib.fk_interface_cv_grid_workspace_bytes(n, n_paths, grid_n)
+    if workspace is not None and workspace.numel() >= minimum:
+        need = min(need, workspace.numel())
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
 
