@@ -604,12 +604,15 @@ FK_CV_DYNKIN, FK_CV_MARTINGALE, FK_CV_MARTINGALE_GRID = 0, 1, 2
 
 def fk_interface_solve_cv(density, data, pts, t, dt, n_paths, cv, stride=2, seed=0, level_id=0, *,
                           form=FK_CV_DYNKIN, plain=True, exit_step=False, cv_scores=False, plan=None, device="cuda",
-                          workspace=None, grids=None, out=None):
+                          workspace=None, grids=None, out=None, grad_table=True):
     """Control-variate interface solve (C: ``fk_interface_solve_cv``), Dynkin
     or martingale form; returns a dict of device tensors: xi, eta, se_xi,
     se_eta (CV), plain_* (same paths), total_steps, and on request exit_step,
     cv_scores.  ``out`` may supply some of the FP64 [n] outputs (contiguous
-    device tensors, e.g. rows of a history buffer); the rest are allocated."""
+    device tensors, e.g. rows of a history buffer); the rest are allocated.
+    ``grad_table``: for FK_CV_MARTINGALE_GRID, size the workspace with room
+    for the per-cell gradient table (a smaller one is replaced); False keeps
+    a given workspace of the plain size, and the kernel reads the grids."""
     import torch
     pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 2)
     n = pts.shape[0]
@@ -626,14 +629,10 @@ def fk_interface_solve_cv(density, data, pts, t, dt, n_paths, cv, stride=2, seed
         out["exit_step"] = torch.empty((n, n_paths), dtype=torch.int32, device=dev)
     if cv_scores:
         out["cv_scores"] = torch.empty((n, n_paths, 2), dtype=torch.float32, device=dev)
-    need = minimum = _lib.fk_interface_cv_workspace_bytes(n, n_paths)
-    if form == FK_CV_MARTINGALE_GRID and grids is not None:
-        # a new workspace gets room for the per-cell gradient table; a given
-        # one need only hold the rest (the kernel then reads the grids)
+    need = _lib.fk_interface_cv_workspace_bytes(n, n_paths)
+    if form == FK_CV_MARTINGALE_GRID and grids is not None and grad_table:
         grid_n = int(round(grids[0].numel() ** 0.5)) - 1
         need = _lib.fk_interface_cv_grid_workspace_bytes(n, n_paths, grid_n)
-    if workspace is not None and workspace.numel() >= minimum:
-        need = min(need, workspace.numel())
     if workspace is None or workspace.numel() < need:
         workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
 

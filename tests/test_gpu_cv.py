@@ -259,14 +259,16 @@ def test_cv_grid_control_against_oracle(fk, oracle_mod, stride):
     assert np.all(d <= 3 * o["se"]) and np.all(d <= 1e-5)
     assert np.all(np.abs(np.stack([g["se_xi"], g["se_eta"]], 1) - o["se"]) <= 0.01 * o["se"] + 1e-9)
     assert ratio < (0.1 if stride == 2 else 0.5)
-    # a workspace without room for the per-cell gradient table: the kernel
-    # reads the grids instead, with bitwise the same results
+    # a workspace of the plain size (its own CV records leave no room for
+    # the per-cell gradient table): the kernel reads the grids instead, with
+    # bitwise the same results
     small = torch.empty(fk.library().fk_interface_cv_workspace_bytes(len(pts), N), dtype=torch.uint8, device="cuda")
     h = fk.fk_interface_solve_cv(dens, data, pts, t, dt, N, None, stride=stride, seed=5, level_id=2,
-                                 form=fk.FK_CV_MARTINGALE_GRID, exit_step=True, cv_scores=True, grids=grids,
-                                 workspace=small)
+                                 form=fk.FK_CV_MARTINGALE_GRID, exit_step=True, grids=grids, workspace=small,
+                                 grad_table=False)
     torch.cuda.synchronize()
-    for k in ("xi", "eta", "se_xi", "se_eta", "exit_step", "cv_scores"):
+    assert h["_workspace"] is small
+    for k in ("xi", "eta", "se_xi", "se_eta", "exit_step"):
         assert np.array_equal(h[k].cpu().numpy(), g[k]), k
 
 
