@@ -748,6 +748,13 @@ static void uhat_eval(const or_uhat *u, double tau, double x, double y, double o
         out[0][0] = x; out[0][1] = 1.0; out[0][2] = 0.0; out[0][3] = 0.0; out[0][4] = 0.0;
         out[1][0] = y; out[1][1] = 0.0; out[1][2] = 1.0; out[1][3] = 0.0; out[1][4] = 0.0;
         return;
+    case 6:
+        /* test function u_hat = (tau x^2, tau y^2): under w = 1 the Dynkin
+           integrand 2 tau - x^2 has a mean linear in the path time, which the
+           trapezoidal rule integrates exactly and the left-point rule not */
+        out[0][0] = tau * x * x; out[0][1] = 2.0 * tau * x; out[0][2] = 0.0; out[0][3] = x * x; out[0][4] = 2.0 * tau;
+        out[1][0] = tau * y * y; out[1][1] = 0.0; out[1][2] = 2.0 * tau * y; out[1][3] = y * y; out[1][4] = 2.0 * tau;
+        return;
     case 2: {
         double e = exp(-2.0 * OR_PI * OR_PI * (tau - u->t_init));
         double sx = sin(OR_PI * x), sy = sin(OR_PI * y), cx = cos(OR_PI * x), cy = cos(OR_PI * y);

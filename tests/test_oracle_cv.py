@@ -5,9 +5,15 @@
   the sine mode and u_hat its exact decaying solution): every path scores
   the same number, so the estimate is exact with zero variance, for any dt
   and any stride.
-* A linear u_hat with w != 1: the telescoping sum is exact in expectation,
-  so the CV estimate agrees with the plain one within their standard errors
-  (and the CV variance is lower where the drift is strong).
+* A linear u_hat with w != 1: the CV estimate agrees with the plain one
+  within their standard errors (its integrand b . grad u_hat varies along
+  the path, so this is a statistical check only), and the CV variance is
+  lower where the drift is strong.
+* The quadrature of the Dynkin integral: with w = 1 and the test function
+  u_hat = (tau x^2, tau y^2) the integrand's mean is linear in the path
+  time, so the trapezoidal rule is exact in expectation and the left-point
+  rule is off by 2 sum L_j^2 (L_j the interval lengths); cv - plain on the
+  same paths tells the two apart by many standard errors.
 * A trained-looking network: CV and plain agree within 3 combined standard
   errors on the same paths.
 
@@ -61,6 +67,39 @@ def test_linear_uhat_is_unbiased_with_drift(oracle_mod):
     assert np.all(d <= 3 * np.sqrt(r["se"] ** 2 + r["plain_se"] ** 2))
     # near the bump the CV removes the Brownian part: much lower variance
     assert np.all(r["se"][:2] < 0.5 * r["plain_se"][:2])
+
+
+@pytest.mark.parametrize("K", [100, 125])
+def test_dynkin_trapezoid_exact_for_linear_mean_integrand(oracle_mod, K):
+    """w = 1, u_hat = (tau x^2, tau y^2), t_init = 0, nodes far from the
+    boundary (a few exits in 10^5 paths).  The integrand r = Laplacian u_hat -
+    d_tau u_hat = 2 tau - x^2 has E[r(s)] = 2 (t - s) - (p^2 + 2 s), linear in
+    s, so the trapezoidal rule over [0, t] with intervals every `stride` steps
+    and the last one closed at the path's end integrates its mean exactly:
+    E[estimate - plain] = 0.  The left-point rule would add 2 sum_j L_j^2; a
+    missing end interval would drop about L E[r] ~ 6e-4.  Checked per path
+    (cv - plain on the same counters) so that the difference's standard error
+    (~1.5e-6) resolves the left-point bias (2.5e-5 for K = 100) many times."""
+    dt, stride = 5e-5, 50
+    t = K * dt
+    pts = np.array([[0.5, 0.5], [0.47, 0.53]])
+    n = 40000
+    cv = oracle_mod.fk_solve_cv(W.CONST, W.Data(), pts, t, dt, n, seed=7, uhat=oracle_mod.UHAT_QUAD,
+                                stride=stride, form=oracle_mod.CV_DYNKIN, want_scores=True, want_exit=True)
+    pl = oracle_mod.fk_solve(W.CONST, W.Data(), pts, t, dt, n, seed=7, want_scores=True)
+    assert np.mean(cv["exit_step"] >= 0) < 2e-4          # almost no path reaches the boundary
+    d = cv["cv_scores"] - pl["scores"]                  # -u_hat(end) + integral, per path
+    uhat_start = t * pts ** 2                           # u_hat(t, P), added to the CV estimate
+    err = d.mean(axis=1) + uhat_start                   # E = 0 for the trapezoidal rule
+    se = d.std(axis=1, ddof=1) / np.sqrt(n)
+    assert np.all(se < 2.5e-6)
+    assert np.all(np.abs(err) <= 4 * se), (err, se)
+    # the estimate itself: CV mean minus plain mean on the same paths
+    assert np.allclose(cv["mean"] - cv["plain_mean"], err, rtol=0, atol=1e-12)
+    lengths = [stride * dt] * (K // stride) + ([(K % stride) * dt] if K % stride else [])
+    left_bias = 2.0 * sum(L * L for L in lengths)
+    assert left_bias > 10 * se.max()                    # the test separates the two rules
+    assert np.all(np.abs(err - left_bias) > 6 * se)
 
 
 def test_network_uhat_agrees_with_plain(oracle_mod):
