@@ -108,13 +108,34 @@ def rms_against(fd, xi, eta):
     return float(np.sqrt(np.mean((est - ref) ** 2)))
 
 
+def host_cores():
+    """CPUs this process may run on: its affinity set, cut to the cgroup's CPU
+    quota when one is set; with os.cpu_count() and the CPU model."""
+    n = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    try:
+        quota, period = open("/sys/fs/cgroup/cpu.max").read().split()[:2]
+        if quota != "max":
+            n = max(1, min(n, int(int(quota) // int(period))))
+    except (OSError, ValueError):
+        pass
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return n, os.cpu_count() or 1, model
+
+
 def cpu_baseline(wl, n_star, sample_nodes=96, sample_paths=2048):
     """The CPU oracle on a bounded sample: sample_nodes nodes spread evenly over the
-    canonical order, sample_paths paths each,
-    scaled to nodes/s at N* paths per node."""
+    canonical order, sample_paths paths each, on every host core this process may
+    use, scaled to nodes/s at N* paths per node."""
     import oracle
     oracle.build()
-    threads = min(16, os.cpu_count() or 1)
+    threads, nproc, model = host_cores()
     pts = wl.nodes()
     sel = np.arange(0, len(pts), max(1, len(pts) // sample_nodes))[:sample_nodes]
     t0 = time.perf_counter()
@@ -123,6 +144,7 @@ def cpu_baseline(wl, n_star, sample_nodes=96, sample_paths=2048):
     el = time.perf_counter() - t0
     nodes_per_s = len(sel) / el * (sample_paths / n_star)
     return {"value": nodes_per_s, "unit": "nodes/s", "cores": threads, "kind": "oracle",
+            "nproc": nproc, "cpu_model": model, "build": "gcc -O3 -fopenmp",
             "sample": f"{len(sel)} nodes (every {len(pts) // sample_nodes}th) x {sample_paths} paths, "
                       f"{el:.2f}s, scaled by {sample_paths}/{n_star} paths"}
 

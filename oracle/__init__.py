@@ -28,14 +28,14 @@ _lib = None
 
 
 def build(force: bool = False) -> str:
-    """Compile the C oracle with gcc (-O2, OpenMP, no fast-math)."""
+    """Compile the C oracle with gcc (-O3, OpenMP, no fast-math)."""
     srcs = [os.path.join(_HERE, s) for s in _SOURCES]
     if not force and os.path.exists(_LIB_PATH):
         lib_m = os.path.getmtime(_LIB_PATH)
         if all(os.path.getmtime(s) <= lib_m for s in srcs):
             return _LIB_PATH
     tmp = _LIB_PATH + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-std=c11", "-O2", "-fopenmp", "-fPIC", "-shared", "-o", tmp] + srcs + ["-lm"]
+    cmd = ["gcc", "-std=c11", "-O3", "-fopenmp", "-fPIC", "-shared", "-o", tmp] + srcs + ["-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB_PATH)
     return _LIB_PATH
