@@ -125,8 +125,9 @@ typedef struct fk_data {
 /* Launch plan of the path kernel (see fk_plan_autotune).  Zero fields take defaults:
  * block 256; blocks_per_cu the kernel's occupancy (the grid is cut to no more
  * wavefronts than there are chunks); chunk 128, or 256 for horizons of at most 64
- * steps in fk_interface_solve and in the network forms of fk_interface_solve_cv.
- * The plan changes speed only: results depend on the counters alone. */
+ * steps in fk_interface_solve and in the network forms of fk_interface_solve_cv;
+ * chunk at most 2048 (FK_E_INVAL beyond).  The plan changes speed only: results
+ * depend on the counters alone. */
 typedef struct fk_plan {
     int32_t block;          /* threads per workgroup: 64, 128, 192 or 256 */
     int32_t blocks_per_cu;  /* resident workgroups per compute unit for the persistent grid */
@@ -166,9 +167,9 @@ int fk_density_sample(const fk_density *w, double tau, int32_t n, double *w_out,
 int fk_density_grid_drift(const double *grid_w, int32_t n, float *grid_b, hipStream_t stream);
 
 /*
- * Bytes of device workspace fk_interface_solve needs for n_nodes x n_paths
- * (per-path score records, queue counters and node tables).  Returns 0 for
- * invalid sizes.
+ * Bytes of device workspace fk_interface_solve needs for n_nodes nodes (queue
+ * counters, the level and node tables and the per-node estimator sums: about
+ * 144 B per node, whatever n_paths).  Returns 0 for invalid sizes.
  */
 size_t fk_interface_workspace_bytes(int64_t n_nodes, int64_t n_paths);
 
@@ -180,8 +181,15 @@ size_t fk_interface_workspace_bytes(int64_t n_nodes, int64_t n_paths);
  * paths over the horizon t with step dt (K = ceil(t/dt) steps, the last one
  * t - (K-1) dt), drawing normals from Philox4x32-10 with key = seed and
  * counter (step/2, path, i, (level_id << 4) | 0), two normals per step from
- * one Box-Muller transform.  Path arithmetic is FP32; the estimator is
- * accumulated in FP64.
+ * one Box-Muller transform.  Path arithmetic is FP32.  The estimator (Sect. 4:
+ * the expectation replaced by the mean over the paths) is summed inside the
+ * path kernel as exact fixed-point integers -- each score s (relative to the
+ * node's shift, see scores) rounded to a multiple of 2^-48 and s^2 to one of
+ * 2^-45 -- so results are bitwise independent of the launch plan and of which
+ * lane ran which path; mean, sample variance (N - 1) and standard error are
+ * then formed in FP64.  Scores must satisfy |s| < 512 (every data kind of
+ * this header keeps them within ~1.5); a node with a non-finite or larger
+ * score gets NaN outputs.
  *
  *   xi, eta        device [n_nodes] FP64  sample means
  *   se_xi, se_eta  device [n_nodes] FP64  standard errors sqrt(var/n_paths)
@@ -190,9 +198,10 @@ size_t fk_interface_workspace_bytes(int64_t n_nodes, int64_t n_paths);
  *   scores         device [n_nodes][n_paths][2] FP32 or NULL: per-path score
  *                  minus the node's shift (the FP32 rounding of the node
  *                  coordinates when initial and boundary data are both the
- *                  identity, 0 otherwise)
+ *                  identity, 0 otherwise); written only when given (the
+ *                  estimator itself keeps no per-path data)
  *   steps          device [n_nodes] int64 or NULL: Euler-Maruyama steps taken
- *                  per node (needs exit_step != NULL)
+ *                  per node
  *   total_steps    device [1] uint64 or NULL: steps taken over all nodes
  *   plan           launch plan or NULL for the default
  *   workspace      device, at least fk_interface_workspace_bytes() bytes,
@@ -233,7 +242,7 @@ typedef struct fk_batch *fk_batch_t;
  * Allocates device memory for the tables (freed by fk_batch_destroy). */
 int fk_batch_create(const fk_level *levels, int32_t n_levels, const double *pts, int64_t n_total,
                     const fk_data *d, double dt, int64_t n_paths, uint64_t seed, fk_batch_t *out);
-/* Device workspace of fk_batch_run when no scores buffer is given (0 for NULL). */
+/* Device workspace of fk_batch_run: counters and per-node estimator sums (0 for NULL). */
 size_t fk_batch_workspace_bytes(fk_batch_t b);
 int fk_batch_set_plan(fk_batch_t b, const fk_plan *plan);
 int fk_batch_get_plan(fk_batch_t b, fk_plan *plan);
@@ -431,10 +440,14 @@ int fk_cv_train(fk_cv_t cv, const float *txy, const float *target, int64_t n, in
  *                      of the network's (over one mesh step the solution stays
  *                      close to the mesh it starts from).
  * stride is even, >= 2.  xi/eta/se_*: the CV estimate; plain_*: the plain
- * estimate from the same paths (all four or none); exit_step and cv_scores
- * (device [n][N][2], the per-path CV scores whose mean, plus u_hat(t_init + t, P)
- * in the Dynkin form, is the estimate) optional.
- * workspace: fk_interface_cv_workspace_bytes(n_nodes, n_paths).
+ * estimate from the same paths (all four or none: the plain path kernel is run
+ * on the same counters after the control-variate kernel, bitwise the plain
+ * solve's result); exit_step and cv_scores (device [n][N][2], the per-path CV
+ * scores whose mean, plus u_hat(t_init + t, P) in the Dynkin form, is the
+ * estimate) optional.  The CV scores are summed in the kernel as in
+ * fk_interface_solve (|score| < 512).
+ * workspace: fk_interface_cv_workspace_bytes(n_nodes, n_paths) (per-node
+ * tables and sums, independent of n_paths).
  */
 #define FK_CV_DYNKIN 0
 #define FK_CV_MARTINGALE 1

@@ -366,7 +366,7 @@ def fk_interface_solve(density, data, pts, t, dt, n_paths, seed=0, level_id=0, *
     if out is None:
         out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("xi", "eta", "se_xi", "se_eta")}
         out["total_steps"] = torch.zeros(1, dtype=torch.int64, device=dev)
-        if exit_step or steps:
+        if exit_step:
             out["exit_step"] = torch.empty((n, n_paths), dtype=torch.int32, device=dev)
         if scores:
             out["scores"] = torch.empty((n, n_paths, 2), dtype=torch.float32, device=dev)

@@ -26,17 +26,42 @@ def sources() -> list[str]:
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
-    """Compile every HIP source of the library into libfk.so (always recompiles)."""
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["hipcc"] + HIPCC_FLAGS + ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
-                                     "-o", tmp] + sources()
-    if verbose:
-        print(" ".join(cmd), flush=True)
-    res = subprocess.run(cmd, capture_output=True, text=True)
-    if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stdout + res.stderr)
-    os.replace(tmp, LIB)
+def build(verbose: bool = False, jobs: int = 0) -> str:
+    """Compile every HIP source of the library into libfk.so (always
+    recompiles): one object per source, compiled in parallel, then linked."""
+    import concurrent.futures
+    import tempfile
+    incs = ["-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc")]
+    objdir = tempfile.mkdtemp(prefix="fk_build_")
+    srcs = sources()
+    objs = [os.path.join(objdir, os.path.basename(f) + ".o") for f in srcs]
+
+    def compile_one(src, obj):
+        cmd = ["hipcc"] + [f for f in HIPCC_FLAGS if f != "-shared"] + incs + ["-c", src, "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        return subprocess.run(cmd, capture_output=True, text=True)
+
+    jobs = jobs or min(len(srcs), max(1, os.cpu_count() or 1), 8)
+    try:
+        with concurrent.futures.ThreadPoolExecutor(jobs) as ex:
+            results = list(ex.map(compile_one, srcs, objs))
+        for src, res in zip(srcs, results):
+            if res.returncode != 0:
+                raise RuntimeError(f"hipcc failed on {src}:\n" + res.stdout + res.stderr)
+        tmp = LIB + ".tmp%d" % os.getpid()
+        cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        res = subprocess.run(cmd, capture_output=True, text=True)
+        if res.returncode != 0:
+            raise RuntimeError("hipcc link failed:\n" + res.stdout + res.stderr)
+        os.replace(tmp, LIB)
+    finally:
+        for o in objs:
+            if os.path.exists(o):
+                os.remove(o)
+        os.rmdir(objdir)
     return LIB
 
 

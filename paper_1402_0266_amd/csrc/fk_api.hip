@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "fk.h"
+#include "fk_accum.hpp"
 #include "fk_internal.hpp"
 
 namespace fk {
@@ -121,7 +122,7 @@ int resolve_plan(const fk_plan *plan, fk_plan *out) {
     }
     if (pl.block < 64 || pl.block > 256 || pl.block % 64)
         return fail(FK_E_INVAL, "plan block must be 64, 128, 192 or 256");
-    if (pl.chunk < 1 || pl.chunk > (1 << 20)) return fail(FK_E_INVAL, "plan chunk out of range");
+    if (pl.chunk < 1 || pl.chunk > (int)kMaxChunk) return fail(FK_E_INVAL, "plan chunk must be in [1, %u]", kMaxChunk);
     if (pl.blocks_per_cu < 0 || pl.blocks_per_cu > 64) return fail(FK_E_INVAL, "plan blocks_per_cu out of range");
     *out = pl;
     return FK_OK;
@@ -272,6 +273,8 @@ int enqueue_solve(const SolveLaunch &S, hipStream_t stream, bool allow_timing) {
     const bool timed = allow_timing && g_timing.enabled;
     hipError_t e;
     if ((e = launch_zero_u32(S.counters, 64, stream)) != hipSuccess) return hip_fail(e, "zero counters");
+    if ((e = launch_zero_u32((uint32_t *)S.args.acc, (int)(acc_bytes(S.n_nodes) / 4), stream)) != hipSuccess)
+        return hip_fail(e, "zero estimator sums");
     PathArgs a = S.args;
     if (S.total_steps) {
         if ((e = launch_zero_u32((uint32_t *)S.total_steps, 2, stream)) != hipSuccess)
@@ -297,11 +300,11 @@ int enqueue_solve(const SolveLaunch &S, hipStream_t stream, bool allow_timing) {
         hipSuccess)
         return hip_fail(e, "path kernel launch");
     if ((e = timing_mark(timed, 1, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    ReduceArgs r = S.reduce;
-    r.scores = a.scores;
-    r.n_paths = S.n_paths;
-    r.n_out = S.n_nodes;
-    if ((e = launch_reduce(r, stream)) != hipSuccess) return hip_fail(e, "reduce kernel launch");
+    FinalArgs f = S.fin;
+    f.acc = a.acc;
+    f.n_paths = S.n_paths;
+    f.n_out = S.n_nodes;
+    if ((e = launch_finalize(f, stream)) != hipSuccess) return hip_fail(e, "finalize kernel launch");
     if ((e = timing_mark(timed, 2, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     if (timed) g_timing.recorded = true;
     return FK_OK;
@@ -320,12 +323,13 @@ void fill_common_args(SolveLaunch &S, const fk_data *d, bool shift, uint64_t see
     a.key1 = (uint32_t)(seed >> 32);
 }
 
-// Workspace layout of one single-call interface solve.
+// Workspace layout of one single-call interface solve: queue counters, the
+// level and node tables and the per-node estimator sums (no per-path data).
 struct WsLayout {
-    size_t counters, levels, nodes, outs, scores, total;
+    size_t counters, levels, nodes, outs, acc, total;
 };
 
-static WsLayout ws_layout(int64_t n_levels, int64_t n_nodes, int64_t n_paths, bool own_scores) {
+static WsLayout ws_layout(int64_t n_levels, int64_t n_nodes) {
     WsLayout L{};
     size_t off = 0;
     L.counters = off;
@@ -336,8 +340,8 @@ static WsLayout ws_layout(int64_t n_levels, int64_t n_nodes, int64_t n_paths, bo
     off += align256(sizeof(NodeDev) * (size_t)n_nodes);
     L.outs = off;
     off += align256(sizeof(OutDev) * (size_t)n_nodes);
-    L.scores = off;
-    if (own_scores) off += align256(sizeof(float2) * (size_t)n_nodes * (size_t)n_paths);
+    L.acc = off;
+    off += align256(acc_bytes(n_nodes));
     L.total = off;
     return L;
 }
@@ -354,7 +358,7 @@ const char *fk_last_error(void) { return g_last_error.c_str(); }
 
 size_t fk_interface_workspace_bytes(int64_t n_nodes, int64_t n_paths) {
     if (n_nodes < 0 || n_paths < 2) return 0;
-    return ws_layout(1, n_nodes, n_paths, true).total;
+    return ws_layout(1, n_nodes).total;
 }
 
 int fk_timing_enable(int enable) {
@@ -406,11 +410,10 @@ int fk_interface_solve(const fk_density *w, const fk_data *d, const double *pts,
     if ((rc = validate_horizon(t, d->t_init, dt, level_id)) != FK_OK) return rc;
     if ((rc = validate_points(pts, n_nodes)) != FK_OK) return rc;
     if (n_nodes > 0 && (!xi || !eta || !se_xi || !se_eta)) return fail(FK_E_INVAL, "an output pointer is NULL");
-    if (steps && !exit_step) return fail(FK_E_INVAL, "per-node steps need exit_step");
     fk_plan pl;
     if ((rc = resolve_plan(plan, &pl)) != FK_OK) return rc;
     if ((rc = check_chunks(n_nodes, n_paths, pl)) != FK_OK) return rc;
-    const WsLayout lay = ws_layout(1, n_nodes, n_paths, scores == nullptr);
+    const WsLayout lay = ws_layout(1, n_nodes);
     if (!workspace || workspace_bytes < lay.total)
         return fail(FK_E_NOMEM, "workspace too small: need %zu bytes", lay.total);
     if (((uintptr_t)workspace & 255u) != 0) return fail(FK_E_INVAL, "workspace must be 256-byte aligned");
@@ -450,15 +453,15 @@ int fk_interface_solve(const fk_density *w, const fk_data *d, const double *pts,
     fill_common_args(S, d, T.shift, seed);
     S.args.levels = (const LevelDev *)(ws + lay.levels);
     S.args.nodes = (const NodeDev *)(ws + lay.nodes);
-    S.args.scores = scores ? (float2 *)scores : (float2 *)(ws + lay.scores);
+    S.args.acc = (NodeAcc *)(ws + lay.acc);
+    S.args.scores = (float2 *)scores;
     S.args.exit_step = exit_step;
-    S.reduce.exit_step = exit_step;
-    S.reduce.outs = (const OutDev *)(ws + lay.outs);
-    S.reduce.xi = xi;
-    S.reduce.eta = eta;
-    S.reduce.se_xi = se_xi;
-    S.reduce.se_eta = se_eta;
-    S.reduce.steps = steps;
+    S.fin.outs = (const OutDev *)(ws + lay.outs);
+    S.fin.xi = xi;
+    S.fin.eta = eta;
+    S.fin.se_xi = se_xi;
+    S.fin.se_eta = se_eta;
+    S.fin.steps = steps;
     return enqueue_solve(S, stream, true);
 }
 

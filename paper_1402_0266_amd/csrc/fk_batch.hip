@@ -12,6 +12,7 @@
 #include <vector>
 
 #include "fk.h"
+#include "fk_accum.hpp"
 #include "fk_internal.hpp"
 
 struct fk_batch {
@@ -32,17 +33,14 @@ struct fk_batch {
 
 namespace fk {
 
-static size_t batch_ws_bytes(const fk_batch *b, bool own_scores) {
-    size_t n = 256;
-    if (own_scores) n += align256(sizeof(float2) * (size_t)b->n_total * (size_t)b->n_paths);
-    return n;
-}
+// Workspace of a batch run: queue counters and the per-node estimator sums.
+static size_t batch_ws_bytes(const fk_batch *b) { return 256 + align256(acc_bytes(b->n_total)); }
 
 static int batch_launch(fk_batch *b, int64_t n_paths, const fk_plan &pl, double *xi, double *eta, double *se_xi,
                         double *se_eta, int32_t *exit_step, float *scores, uint64_t *total_steps, void *workspace,
                         size_t workspace_bytes, hipStream_t stream, bool allow_timing) {
     if (b->n_total > 0 && (!xi || !eta || !se_xi || !se_eta)) return fail(FK_E_INVAL, "an output pointer is NULL");
-    const size_t need = 256 + (scores ? 0 : align256(sizeof(float2) * (size_t)b->n_total * (size_t)n_paths));
+    const size_t need = batch_ws_bytes(b);
     if (!workspace || workspace_bytes < need) return fail(FK_E_NOMEM, "workspace too small: need %zu bytes", need);
     if (((uintptr_t)workspace & 255u) != 0) return fail(FK_E_INVAL, "workspace must be 256-byte aligned");
     if (b->n_total == 0) return FK_OK;
@@ -59,15 +57,15 @@ static int batch_launch(fk_batch *b, int64_t n_paths, const fk_plan &pl, double 
     fill_common_args(S, &b->data, b->T.shift, b->seed);
     S.args.levels = b->d_levels;
     S.args.nodes = b->d_nodes;
-    S.args.scores = scores ? (float2 *)scores : (float2 *)(ws + 256);
+    S.args.acc = (NodeAcc *)(ws + 256);
+    S.args.scores = (float2 *)scores;
     S.args.exit_step = exit_step;
-    S.reduce.exit_step = exit_step;
-    S.reduce.outs = b->d_outs;
-    S.reduce.xi = xi;
-    S.reduce.eta = eta;
-    S.reduce.se_xi = se_xi;
-    S.reduce.se_eta = se_eta;
-    S.reduce.steps = nullptr;
+    S.fin.outs = b->d_outs;
+    S.fin.xi = xi;
+    S.fin.eta = eta;
+    S.fin.se_xi = se_xi;
+    S.fin.se_eta = se_eta;
+    S.fin.steps = nullptr;
     return enqueue_solve(S, stream, allow_timing);
 }
 
@@ -146,7 +144,7 @@ int fk_batch_create(const fk_level *levels, int32_t n_levels, const double *pts,
     return FK_OK;
 }
 
-size_t fk_batch_workspace_bytes(fk_batch_t b) { return b ? batch_ws_bytes(b, true) : 0; }
+size_t fk_batch_workspace_bytes(fk_batch_t b) { return b ? batch_ws_bytes(b) : 0; }
 
 int fk_batch_set_plan(fk_batch_t b, const fk_plan *plan) {
     g_last_error.clear();

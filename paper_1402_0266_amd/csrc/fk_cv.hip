@@ -29,6 +29,7 @@
 #include <vector>
 
 #include "fk.h"
+#include "fk_accum.hpp"
 #include "fk_device.hpp"
 #include "fk_internal.hpp"
 #include "fk_pathstep.hpp"
@@ -415,7 +416,8 @@ struct CvArgs {
     uint32_t stride_iters;       // network evaluations every stride_iters iterations (2 steps each)
     float base;                  // identity base (0 or 1)
     const float2 *r0;            // [n_out] integrand at the start point of each node
-    float2 *cv_scores;           // [n_out * n_paths]
+    NodeAcc *acc_cv;             // [n_out] sums of the CV scores
+    float2 *cv_scores;           // [n_out * n_paths] or nullptr
 };
 
 template <int KIND, int TMODE, bool UNIFORM>
@@ -448,8 +450,12 @@ __global__ void __launch_bounds__(256, 2) fk_cv_path_kernel(const PathArgs a, co
     load_net(N, c.bf);
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
-    uint32_t q_slot = 0, q_next = 0, q_end = 0;
-    bool q_done = !chunk_cursor(a, first_chunk(), q_slot, q_next, q_end);
+    __shared__ AccSlot<2> slot_tab[4][kAccSlots];
+    AccSlot<2> *slots = slot_tab[threadIdx.x >> 6];
+    NodeAcc *const accs[1] = {c.acc_cv};
+    slots_init<2>(slots, lane);
+    uint32_t q_slot = 0, q_next = 0, q_end = 0, q_tag = 0, grabs = 0;
+    bool q_done = !grab_chunk<2>(a, first_chunk(), q_slot, q_next, q_end, slots, accs, q_tag, grabs, lane);
     const uint32_t key0 = a.key0, key1 = a.key1;
     Lane L;
     bool active = false, parked = false, out = false;
@@ -457,7 +463,8 @@ __global__ void __launch_bounds__(256, 2) fk_cv_path_kernel(const PathArgs a, co
     float Ix = 0.f, Iy = 0.f;                // sum of r ds
     float rx = 0.f, ry = 0.f;                // integrand at the last evaluation
     int32_t k_last = 0;
-    float tend = 0.f;                        // PDE time at path start
+    const float tend = a.levels[0].tend;     // PDE time at path start
+    uint32_t my_tag = 0;                     // accumulation tag of the path's chunk
     uint32_t my_steps = 0;
     uint32_t until_eval = 0;                 // iterations to the next evaluation point
 
@@ -489,21 +496,24 @@ __global__ void __launch_bounds__(256, 2) fk_cv_path_kernel(const PathArgs a, co
                     ry = rny;
                     k_last = L.k;
                 }
+                // plain scores may be relative to the start point; the CV
+                // score is g - u_hat(end) + sum r ds, absolute
+                const float sx0 = a.shift ? L.px : 0.f, sy0 = a.shift ? L.py : 0.f;
+                const float v[2] = {(plx - (o[0][0] - sx0)) + Ix, (ply - (o[1][0] - sy0)) + Iy};
                 if (parked) {
-                    // plain scores may be stored relative to the start point;
-                    // the CV record is g - u_hat(end) + sum r ds, absolute
-                    const float sx0 = a.shift ? L.px : 0.f, sy0 = a.shift ? L.py : 0.f;
-                    a.scores[L.rec] = make_float2(plx, ply);
-                    c.cv_scores[L.rec] = make_float2((plx - (o[0][0] - sx0)) + Ix, (ply - (o[1][0] - sy0)) + Iy);
-                    if (a.exit_step) a.exit_step[L.rec] = out ? L.k : -1;
-                    parked = false;
+                    const uint64_t rec = path_rec(L, a.n_paths);
+                    if (a.scores) a.scores[rec] = make_float2(plx, ply);
+                    if (c.cv_scores) c.cv_scores[rec] = make_float2(v[0], v[1]);
+                    if (a.exit_step) a.exit_step[rec] = out ? L.k : -1;
                 }
+                acc_wave<2>(slots, accs, parked, my_tag, L.out, v, (uint32_t)L.k, lane);
+                parked = false;
             }
             // ---- refill idle lanes (paths start only at evaluation points) ----
             uint64_t need = __ballot(!active && !parked);
             while (need != 0ull && !q_done) {
                 if (q_next >= q_end) {
-                    if (!chunk_cursor(a, next_chunk(a), q_slot, q_next, q_end)) {
+                    if (!grab_chunk<2>(a, next_chunk(a), q_slot, q_next, q_end, slots, accs, q_tag, grabs, lane)) {
                         q_done = true;
                         break;
                     }
@@ -514,8 +524,8 @@ __global__ void __launch_bounds__(256, 2) fk_cv_path_kernel(const PathArgs a, co
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
                 if (!active && !parked && rank < avail) {
                     const NodeDev nd = a.nodes[q_slot];
-                    lane_start<KIND, TMODE>(L, nd, a.levels, q_next + rank, a.n_paths);
-                    tend = a.levels[nd.level].tend;
+                    lane_start<KIND, TMODE>(L, nd, a.levels, q_next + rank);
+                    my_tag = q_tag;
                     const float2 r0 = c.r0[nd.out];
                     rx = r0.x;
                     ry = r0.y;
@@ -564,6 +574,7 @@ __global__ void __launch_bounds__(256, 2) fk_cv_path_kernel(const PathArgs a, co
             }
         }
     }
+    slots_collect<2>(slots, accs, lane);
     unsigned long long st = my_steps;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) st += __shfl_xor(st, off, 64);
@@ -583,7 +594,8 @@ struct MgArgs {
     uint32_t stride_iters;
     float base;                  // identity base (0 or 1)
     const float4 *g0;            // [n_out] (dxi/dx, dxi/dy, deta/dx, deta/dy) at the start point
-    float2 *cv_scores;           // [n_out * n_paths], absolute
+    NodeAcc *acc_cv;             // [n_out] sums of the CV scores
+    float2 *cv_scores;           // [n_out * n_paths], absolute, or nullptr
 };
 
 // Four waves per SIMD (128 VGPRs): the few values the compiler moves to
@@ -598,18 +610,28 @@ __global__ void __launch_bounds__(256, 4) fk_mg_path_kernel(const PathArgs a, co
     load_net(N, c.bf);
     __syncthreads();
     const uint32_t lane = threadIdx.x & 63u;
-    uint32_t q_slot = 0, q_next = 0, q_end = 0;
-    bool q_done = !chunk_cursor(a, first_chunk(), q_slot, q_next, q_end);
+    __shared__ AccSlot<2> slot_tab[4][kAccSlots];
+    AccSlot<2> *slots = slot_tab[threadIdx.x >> 6];
+    NodeAcc *const accs[1] = {c.acc_cv};
+    slots_init<2>(slots, lane);
+    uint32_t q_slot = 0, q_next = 0, q_end = 0, q_tag = 0, grabs = 0;
+    bool q_done = !grab_chunk<2>(a, first_chunk(), q_slot, q_next, q_end, slots, accs, q_tag, grabs, lane);
     const uint32_t key0 = a.key0, key1 = a.key1;
     Lane L;
     bool active = false;
     float gxx = 0.f, gxy = 0.f, gyx = 0.f, gyy = 0.f;   // gradient of (xi_hat, eta_hat) held over the block
     float dbx = 0.f, dby = 0.f;                         // Brownian part of the block so far
     float mx = 0.f, my = 0.f;                           // the martingale sum of the closed blocks
-    float tend = 0.f;
+    const float tend = a.levels[0].tend;                // PDE time at path start
+    uint32_t my_tag = 0;                                // accumulation tag of the path's chunk
     uint32_t my_steps = 0;
 
+    bool closed = false;                                // the lane's last path closed its chunk's slot
     for (uint32_t until_eval = 0;; --until_eval) {     // iterations to the next block boundary
+        if (__ballot(closed) != 0ull) {
+            slots_collect<2>(slots, accs, lane);
+            closed = false;
+        }
         if (until_eval == 0) {
             until_eval = c.stride_iters;
             // ---- block boundary of running paths (every lane joins) ---------
@@ -632,7 +654,7 @@ __global__ void __launch_bounds__(256, 4) fk_mg_path_kernel(const PathArgs a, co
             uint64_t need = __ballot(!active);
             while (need != 0ull && !q_done) {
                 if (q_next >= q_end) {
-                    if (!chunk_cursor(a, next_chunk(a), q_slot, q_next, q_end)) {
+                    if (!grab_chunk<2>(a, next_chunk(a), q_slot, q_next, q_end, slots, accs, q_tag, grabs, lane)) {
                         q_done = true;
                         break;
                     }
@@ -643,8 +665,8 @@ __global__ void __launch_bounds__(256, 4) fk_mg_path_kernel(const PathArgs a, co
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
                 if (!active && rank < avail) {
                     const NodeDev nd = a.nodes[q_slot];
-                    lane_start<KIND, TMODE>(L, nd, a.levels, q_next + rank, a.n_paths);
-                    tend = a.levels[nd.level].tend;
+                    lane_start<KIND, TMODE>(L, nd, a.levels, q_next + rank);
+                    my_tag = q_tag;
                     const float4 g0 = c.g0[nd.out];
                     gxx = g0.x;
                     gxy = g0.y;
@@ -695,13 +717,17 @@ __global__ void __launch_bounds__(256, 4) fk_mg_path_kernel(const PathArgs a, co
                 mx = fmaf(gxx, dbx, fmaf(gxy, dby, mx));
                 my = fmaf(gyx, dbx, fmaf(gyy, dby, my));
                 const float sx0 = a.shift ? L.px : 0.f, sy0 = a.shift ? L.py : 0.f;
-                a.scores[L.rec] = make_float2(plx, ply);
-                c.cv_scores[L.rec] = make_float2((plx + sx0) - mx, (ply + sy0) - my);
-                if (a.exit_step) a.exit_step[L.rec] = out ? L.k : -1;
+                const float v[2] = {(plx + sx0) - mx, (ply + sy0) - my};
+                closed = acc_path<2>(slots, accs, my_tag, L.out, v, (uint32_t)L.k);
+                const uint64_t rec = path_rec(L, a.n_paths);
+                if (a.scores) a.scores[rec] = make_float2(plx, ply);
+                if (c.cv_scores) c.cv_scores[rec] = make_float2(v[0], v[1]);
+                if (a.exit_step) a.exit_step[rec] = out ? L.k : -1;
                 active = false;
             }
         }
     }
+    slots_collect<2>(slots, accs, lane);
     unsigned long long st = my_steps;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) st += __shfl_xor(st, off, 64);
@@ -732,7 +758,8 @@ __device__ __forceinline__ void grid_gradient(const double *g, int n, float x, f
 // fixed offsets from its start (schedule-independent results).
 struct MggArgs {
     uint32_t stride_iters;       // the stride in iterations (2 steps each)
-    float2 *cv_scores;           // [n_out * n_paths], absolute
+    NodeAcc *acc_cv;             // [n_out] sums of the CV scores
+    float2 *cv_scores;           // [n_out * n_paths], absolute, or nullptr
     const float4 *gtab;          // per-cell gradient table (grad_table_kernel), or NULL: read the grids
 };
 
@@ -771,21 +798,31 @@ template <int KIND, int TMODE, bool UNIFORM>
 __global__ void __launch_bounds__(256) fk_mgg_path_kernel(const PathArgs a, const MggArgs c) {
     constexpr bool kMovingBackward = moving_kind(KIND) && TMODE == TIME_BACKWARD;
     const uint32_t lane = threadIdx.x & 63u;
-    uint32_t q_slot = 0, q_next = 0, q_end = 0;
-    bool q_done = !chunk_cursor(a, first_chunk(), q_slot, q_next, q_end);
+    __shared__ AccSlot<2> slot_tab[4][kAccSlots];
+    AccSlot<2> *slots = slot_tab[threadIdx.x >> 6];
+    NodeAcc *const accs[1] = {c.acc_cv};
+    slots_init<2>(slots, lane);
+    uint32_t q_slot = 0, q_next = 0, q_end = 0, q_tag = 0, grabs = 0;
+    bool q_done = !grab_chunk<2>(a, first_chunk(), q_slot, q_next, q_end, slots, accs, q_tag, grabs, lane);
     const uint32_t key0 = a.key0, key1 = a.key1;
     Lane L;
     bool active = false;
     float gxx = 0.f, gxy = 0.f, gyx = 0.f, gyy = 0.f;
     float dbx = 0.f, dby = 0.f, mx = 0.f, my = 0.f;
     uint32_t blk_left = 0;       // iterations (2 steps each) to the path's next block boundary
+    uint32_t my_tag = 0;         // accumulation tag of the path's chunk
     uint32_t my_steps = 0;
 
+    bool closed = false;         // the lane's last path closed its chunk's slot
     for (;;) {
+        if (__ballot(closed) != 0ull) {
+            slots_collect<2>(slots, accs, lane);
+            closed = false;
+        }
         uint64_t need = __ballot(!active);
         while (need != 0ull && !q_done) {
             if (q_next >= q_end) {
-                if (!chunk_cursor(a, next_chunk(a), q_slot, q_next, q_end)) {
+                if (!grab_chunk<2>(a, next_chunk(a), q_slot, q_next, q_end, slots, accs, q_tag, grabs, lane)) {
                     q_done = true;
                     break;
                 }
@@ -795,7 +832,8 @@ __global__ void __launch_bounds__(256) fk_mgg_path_kernel(const PathArgs a, cons
             const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
             if (!active && rank < avail) {
-                lane_start<KIND, TMODE>(L, a.nodes[q_slot], a.levels, q_next + rank, a.n_paths);
+                lane_start<KIND, TMODE>(L, a.nodes[q_slot], a.levels, q_next + rank);
+                my_tag = q_tag;
                 dbx = dby = mx = my = 0.f;
                 blk_left = 0;
                 active = true;
@@ -857,13 +895,17 @@ __global__ void __launch_bounds__(256) fk_mgg_path_kernel(const PathArgs a, cons
                 mx = fmaf(gxx, dbx, fmaf(gxy, dby, mx));
                 my = fmaf(gyx, dbx, fmaf(gyy, dby, my));
                 const float sx0 = a.shift ? L.px : 0.f, sy0 = a.shift ? L.py : 0.f;
-                a.scores[L.rec] = make_float2(plx, ply);
-                c.cv_scores[L.rec] = make_float2((plx + sx0) - mx, (ply + sy0) - my);
-                if (a.exit_step) a.exit_step[L.rec] = out ? L.k : -1;
+                const float v[2] = {(plx + sx0) - mx, (ply + sy0) - my};
+                closed = acc_path<2>(slots, accs, my_tag, L.out, v, (uint32_t)L.k);
+                const uint64_t rec = path_rec(L, a.n_paths);
+                if (a.scores) a.scores[rec] = make_float2(plx, ply);
+                if (c.cv_scores) c.cv_scores[rec] = make_float2(v[0], v[1]);
+                if (a.exit_step) a.exit_step[rec] = out ? L.k : -1;
                 active = false;
             }
         }
     }
+    slots_collect<2>(slots, accs, lane);
     unsigned long long st = my_steps;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) st += __shfl_xor(st, off, 64);
@@ -894,7 +936,7 @@ __global__ void __launch_bounds__(256) cv_node_kernel(const CvNodeArgs na, const
     float tend = 0.f;
     if (ok) {
         const NodeDev nd = na.nodes[s];
-        lane_start<KIND, TMODE>(L, nd, na.levels, 0, 1);
+        lane_start<KIND, TMODE>(L, nd, na.levels, 0);
         tend = na.levels[nd.level].tend;
     } else {
         L.xh = 0.5f;
@@ -1260,12 +1302,13 @@ auto cv_dispatch(int kind, int time_mode, bool uniform, Args &&...args) {
 #undef FK_CV_CASE
 }
 
-// Workspace of one control-variate solve.
+// Workspace of one control-variate solve: counters, tables, the per-node
+// start values of the control and the estimator sums (plain and CV).
 struct CvWs {
-    size_t counters, levels, nodes, outs, outs_cv, r0, g0, scores, cv_scores, total;
+    size_t counters, levels, nodes, outs, outs_cv, r0, g0, acc, acc_cv, total;
 };
 
-static CvWs cv_ws_layout(int64_t n_nodes, int64_t n_paths, bool own_cv) {
+static CvWs cv_ws_layout(int64_t n_nodes) {
     CvWs L{};
     size_t off = 0;
     L.counters = off;
@@ -1282,10 +1325,10 @@ static CvWs cv_ws_layout(int64_t n_nodes, int64_t n_paths, bool own_cv) {
     off += align256(sizeof(float2) * (size_t)n_nodes);
     L.g0 = off;
     off += align256(sizeof(float4) * (size_t)n_nodes);
-    L.scores = off;
-    off += align256(sizeof(float2) * (size_t)n_nodes * (size_t)n_paths);
-    L.cv_scores = off;
-    if (own_cv) off += align256(sizeof(float2) * (size_t)n_nodes * (size_t)n_paths);
+    L.acc = off;
+    off += align256(acc_bytes(n_nodes));
+    L.acc_cv = off;
+    off += align256(acc_bytes(n_nodes));
     L.total = off;
     return L;
 }
@@ -1480,12 +1523,12 @@ int fk_cv_train(fk_cv_t cv, const float *txy, const float *target, int64_t n, in
 
 size_t fk_interface_cv_workspace_bytes(int64_t n_nodes, int64_t n_paths) {
     if (n_nodes < 0 || n_paths < 2) return 0;
-    return cv_ws_layout(n_nodes, n_paths, true).total;
+    return cv_ws_layout(n_nodes).total;
 }
 
 size_t fk_interface_cv_grid_workspace_bytes(int64_t n_nodes, int64_t n_paths, int32_t grid_n) {
     if (n_nodes < 0 || n_paths < 2 || grid_n < 1 || grid_n > 65535) return 0;
-    return align256(cv_ws_layout(n_nodes, n_paths, true).total) + (size_t)grid_n * grid_n * 2 * sizeof(float4);
+    return align256(cv_ws_layout(n_nodes).total) + (size_t)grid_n * grid_n * 2 * sizeof(float4);
 }
 
 int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *pts, int64_t n_nodes, double t,
@@ -1515,7 +1558,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     if ((rc = resolve_plan(plan, &pl)) != FK_OK) return rc;
     pl.block = 256;
     if ((rc = check_chunks(n_nodes, n_paths, pl)) != FK_OK) return rc;
-    const CvWs lay = cv_ws_layout(n_nodes, n_paths, cv_scores == nullptr);
+    const CvWs lay = cv_ws_layout(n_nodes);
     if (!workspace || workspace_bytes < lay.total)
         return fail(FK_E_NOMEM, "workspace too small: need %zu bytes", lay.total);
     if (((uintptr_t)workspace & 255u) != 0) return fail(FK_E_INVAL, "workspace must be 256-byte aligned");
@@ -1544,6 +1587,8 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         return hip_fail(e, "upload tables");
     uint32_t *counters = (uint32_t *)(ws + lay.counters);
     if ((e = launch_zero_u32(counters, 64, stream)) != hipSuccess) return hip_fail(e, "zero counters");
+    if ((e = launch_zero_u32((uint32_t *)(ws + lay.acc_cv), (int)(acc_bytes(n_nodes) / 4), stream)) != hipSuccess)
+        return hip_fail(e, "zero estimator sums");
     if (total_steps && (e = launch_zero_u32((uint32_t *)total_steps, 2, stream)) != hipSuccess)
         return hip_fail(e, "zero total_steps");
 
@@ -1570,7 +1615,8 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     a = S.args;
     a.levels = (const LevelDev *)(ws + lay.levels);
     a.nodes = (const NodeDev *)(ws + lay.nodes);
-    a.scores = (float2 *)(ws + lay.scores);
+    a.acc = (NodeAcc *)(ws + lay.acc);
+    a.scores = nullptr;
     a.exit_step = exit_step;
     a.queue = counters;
     a.total_steps = total_steps ? (unsigned long long *)total_steps : (unsigned long long *)(counters + 2);
@@ -1583,7 +1629,8 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     a.chunk = (uint32_t)pl.chunk;
     a.cpn = (uint32_t)cpn;
     a.total_chunks = (uint32_t)(n_nodes * cpn);
-    float2 *cv_rec = cv_scores ? (float2 *)cv_scores : (float2 *)(ws + lay.cv_scores);
+    float2 *cv_rec = (float2 *)cv_scores;
+    NodeAcc *acc_cv = (NodeAcc *)(ws + lay.acc_cv);
     int bpc = pl.blocks_per_cu;
     if (!mg) {
         CvArgs c{};
@@ -1593,6 +1640,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         c.base = cv->base;
         c.r0 = (const float2 *)(ws + lay.r0);
         c.cv_scores = cv_rec;
+        c.acc_cv = acc_cv;
         const int occ = cv_dispatch<CvOccF>(T.kind, T.time_mode, T.uniform);
         if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
         if ((e = cv_dispatch<CvLaunchF>(T.kind, T.time_mode, T.uniform, a, c, cap_grid(n_cu * bpc, a.total_chunks, 256), stream)) != hipSuccess)
@@ -1601,6 +1649,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         MggArgs c{};
         c.stride_iters = (uint32_t)(stride / 2);
         c.cv_scores = cv_rec;
+        c.acc_cv = acc_cv;
         // the gradient table, when the workspace has room for it
         const size_t tab_off = align256(lay.total), tab_bytes = (size_t)d->grid_n * d->grid_n * 2 * sizeof(float4);
         if (workspace_bytes >= tab_off + tab_bytes) {
@@ -1623,6 +1672,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         c.base = grid_ctl ? 0.f : cv->base;
         c.g0 = (const float4 *)(ws + lay.g0);
         c.cv_scores = cv_rec;
+        c.acc_cv = acc_cv;
         const int occ = cv_dispatch<MgOccF>(T.kind, T.time_mode, T.uniform);
         if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
         if ((e = cv_dispatch<MgLaunchF>(T.kind, T.time_mode, T.uniform, a, c, cap_grid(n_cu * bpc, a.total_chunks, 256), stream)) != hipSuccess)
@@ -1630,28 +1680,42 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     }
     if ((e = timing_record(1, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
 
-    ReduceArgs r{};
-    r.scores = cv_rec;
-    r.exit_step = nullptr;
-    r.outs = (const OutDev *)(ws + lay.outs_cv);
-    r.n_out = n_nodes;
-    r.n_paths = n_paths;
-    r.xi = xi;
-    r.eta = eta;
-    r.se_xi = se_xi;
-    r.se_eta = se_eta;
-    if ((e = launch_reduce(r, stream)) != hipSuccess) return hip_fail(e, "reduce kernel launch");
-    if (plain_xi && plain_eta && plain_se_xi && plain_se_eta) {
-        ReduceArgs q = r;
-        q.scores = a.scores;
-        q.outs = (const OutDev *)(ws + lay.outs);
-        q.xi = plain_xi;
-        q.eta = plain_eta;
-        q.se_xi = plain_se_xi;
-        q.se_eta = plain_se_eta;
-        if ((e = launch_reduce(q, stream)) != hipSuccess) return hip_fail(e, "reduce kernel launch");
-    }
+    FinalArgs f{};
+    f.acc = acc_cv;
+    f.outs = (const OutDev *)(ws + lay.outs_cv);
+    f.n_out = n_nodes;
+    f.n_paths = n_paths;
+    f.xi = xi;
+    f.eta = eta;
+    f.se_xi = se_xi;
+    f.se_eta = se_eta;
+    if ((e = launch_finalize(f, stream)) != hipSuccess) return hip_fail(e, "finalize kernel launch");
     if ((e = timing_record(2, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
+    if (plain_xi && plain_eta && plain_se_xi && plain_se_eta) {
+        // the plain estimate from the same paths: the plain path kernel on the
+        // same tables and counters (bitwise the scores the CV kernel saw)
+        SolveLaunch P{};
+        P.args = a;
+        P.args.acc = (NodeAcc *)(ws + lay.acc);
+        P.args.scores = nullptr;
+        P.args.exit_step = nullptr;
+        P.kind = T.kind;
+        P.time_mode = T.time_mode;
+        P.uniform = T.uniform;
+        P.first_by_index = T.levels[0].K <= 64;
+        if ((rc = resolve_plan(nullptr, &P.plan)) != FK_OK) return rc;
+        if (P.first_by_index) P.plan.chunk = 256;
+        P.n_nodes = n_nodes;
+        P.n_paths = n_paths;
+        P.counters = counters;
+        P.total_steps = nullptr;
+        P.fin.outs = (const OutDev *)(ws + lay.outs);
+        P.fin.xi = plain_xi;
+        P.fin.eta = plain_eta;
+        P.fin.se_xi = plain_se_xi;
+        P.fin.se_eta = plain_se_eta;
+        if ((rc = enqueue_solve(P, stream, false)) != FK_OK) return rc;
+    }
     return FK_OK;
 }
 

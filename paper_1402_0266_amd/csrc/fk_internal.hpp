@@ -56,10 +56,13 @@ struct alignas(16) OutDev {
     int64_t pad;
 };
 
+struct NodeAcc;
+
 struct PathArgs {
     const LevelDev *levels;
     const NodeDev *nodes;
-    float2 *scores;                  // [n_out * n_paths]
+    NodeAcc *acc;                    // [n_out] estimator sums (zeroed before launch)
+    float2 *scores;                  // [n_out * n_paths] per-path scores, or nullptr
     int32_t *exit_step;              // [n_out * n_paths] or nullptr
     uint32_t *queue;                 // chunk counter (zeroed before launch)
     unsigned long long *total_steps; // accumulated Euler-Maruyama steps
@@ -75,9 +78,9 @@ struct PathArgs {
     uint32_t total_chunks;
 };
 
-struct ReduceArgs {
-    const float2 *scores;
-    const int32_t *exit_step;        // or nullptr
+// The estimator's last step: node sums -> means, standard errors, steps.
+struct FinalArgs {
+    const NodeAcc *acc;
     const OutDev *outs;
     int64_t n_out;
     int64_t n_paths;
@@ -109,8 +112,8 @@ struct Tables {
 
 // Everything one enqueue of the solve sequence needs.
 struct SolveLaunch {
-    PathArgs args;       // tables, scores, data; counters and sizes filled by enqueue_solve
-    ReduceArgs reduce;   // outputs; sizes filled by enqueue_solve
+    PathArgs args;       // tables, accumulators, data; counters and sizes filled by enqueue_solve
+    FinalArgs fin;       // outputs; sizes filled by enqueue_solve
     int kind, time_mode;
     bool uniform;
     bool first_by_index;  // short horizons: each wavefront's first chunk by its grid index
@@ -153,9 +156,11 @@ hipError_t timing_record(int i, hipStream_t s);
 
 // Launch helpers implemented in fk_paths.hip.
 hipError_t launch_zero_u32(uint32_t *p, int n_words, hipStream_t s);
-hipError_t launch_paths(int kind, int time_mode, bool uniform, bool first_by_index, const PathArgs &a, int grid, int block,
-                        hipStream_t s);
-hipError_t launch_reduce(const ReduceArgs &a, hipStream_t s);
+hipError_t launch_paths(int kind, int time_mode, bool uniform, bool first_by_index, const PathArgs &a, int grid,
+                        int block, hipStream_t s);
+hipError_t launch_finalize(const FinalArgs &a, hipStream_t s);
+// Bytes of the per-node estimator sums of n_out rows.
+size_t acc_bytes(int64_t n_out);
 int path_kernel_max_blocks_per_cu(int kind, int time_mode, bool uniform, bool bridge, bool first_by_index, int block);
 
 }  // namespace fk

@@ -19,10 +19,11 @@
 //    atomic queue and hands them to whichever lanes are idle, so a lane never
 //    waits for the rest of its wavefront.  Nodes are queued in decreasing
 //    expected cost so the launch ends on short paths.
-//  * Each finished path writes one 8-byte FP32 score record; the reduction
-//    kernel sums them per node in FP64 in a fixed order, so results do not
-//    depend on the launch schedule (the record traffic is < 0.1% of the
-//    kernel time at the target sizes).
+//  * Each finished path adds its score to its node's sums inside the kernel
+//    (fixed-point integer sums: per wavefront in LDS per work chunk, then
+//    per node in HBM), so results do not depend on the launch schedule and
+//    no per-path record is written unless the caller asks for the scores;
+//    a small kernel turns the sums into means and standard errors.
 //  * Positions are FP32 pairs (hi, lo): each increment is added to lo and the
 //    pair renormalised, which keeps the position to ~2^-48 over 10^4 steps
 //    (plain FP32 accumulation drifts by ~1e-6 and flips exit decisions).
@@ -31,6 +32,7 @@
 
 #include <utility>
 
+#include "fk_accum.hpp"
 #include "fk_device.hpp"
 #include "fk_internal.hpp"
 #include "fk_pathstep.hpp"
@@ -59,18 +61,34 @@ template <int KIND, int TMODE, bool UNIFORM, bool BRIDGE, bool FIRST_BY_INDEX = 
 __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
     constexpr bool kMovingBackward = moving_kind(KIND) && TMODE == TIME_BACKWARD;
     const uint32_t lane = threadIdx.x & 63u;
-    // Wavefront-uniform queue cursor: current node slot and path range.
-    uint32_t q_slot = 0, q_next = 0, q_end = 0;
+    __shared__ AccSlot<2> slot_tab[4][kAccSlots];
+    AccSlot<2> *slots = slot_tab[threadIdx.x >> 6];
+    NodeAcc *const accs[1] = {a.acc};
+    slots_init<2>(slots, lane);
+    // Wavefront-uniform queue cursor: current node slot and path range, and
+    // the grab number of the chunk (its accumulation slot).
+    uint32_t q_slot = 0, q_next = 0, q_end = 0, q_tag = 0, grabs = 0;
     bool q_done = false;
-    if constexpr (FIRST_BY_INDEX) q_done = !chunk_cursor(a, first_chunk(), q_slot, q_next, q_end);
+    if constexpr (FIRST_BY_INDEX) {
+        q_done = !chunk_cursor(a, first_chunk(), q_slot, q_next, q_end);
+        if (!q_done) {
+            q_tag = slot_open<2>(slots, accs, grabs++, (uint32_t)a.nodes[q_slot].out, q_end - q_next, lane);
+        }
+    }
     const uint32_t key0 = a.key0, key1 = a.key1;
 
     Lane L;
     bool active = false;
+    uint32_t my_tag = 0;      // accumulation tag of the lane's path's chunk
     uint32_t my_steps = 0;
 
+    bool closed = false;      // the lane's last path closed its chunk's slot
     for (;;) {
-        // ---- refill idle lanes ------------------------------------------
+        // ---- flush closed chunks, refill idle lanes ---------------------
+        if (__ballot(closed) != 0ull) {
+            slots_collect<2>(slots, accs, lane);
+            closed = false;
+        }
         uint64_t need = __ballot(!active);
         while (need != 0ull && !q_done) {
             if (q_next >= q_end) {
@@ -93,13 +111,15 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
                 q_slot = c / a.cpn;
                 q_next = (c - q_slot * a.cpn) * a.chunk;
                 q_end = min(q_next + a.chunk, a.n_paths);
+                q_tag = slot_open<2>(slots, accs, grabs++, (uint32_t)a.nodes[q_slot].out, q_end - q_next, lane);
                 continue;
             }
             const uint32_t avail = q_end - q_next;
             const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
             if (!active && rank < avail) {
-                lane_start<KIND, TMODE>(L, a.nodes[q_slot], a.levels, q_next + rank, a.n_paths);
+                lane_start<KIND, TMODE>(L, a.nodes[q_slot], a.levels, q_next + rank);
+                my_tag = q_tag;
                 active = true;
             }
             const uint32_t n_need = (uint32_t)__popcll(need);
@@ -151,16 +171,19 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
                 }
             }
             if (out || L.k >= L.K) {
-                // ---- score (eq. (7b)) --------------------------------------
-                float sx, sy;
-                score_path(a, L, out, sx, sy);
-                a.scores[L.rec] = make_float2(sx, sy);
-                if (a.exit_step) a.exit_step[L.rec] = out ? L.k : -1;
+                // ---- score (eq. (7b)) and its node's sums ------------------
+                float v[2];
+                score_path(a, L, out, v[0], v[1]);
+                closed = acc_path<2>(slots, accs, my_tag, L.out, v, (uint32_t)L.k);
+                if (a.scores) a.scores[path_rec(L, a.n_paths)] = make_float2(v[0], v[1]);
+                if (a.exit_step) a.exit_step[path_rec(L, a.n_paths)] = out ? L.k : -1;
                 active = false;
             }
         }
     }
 
+    // ---- the last closed chunks' sums ----------------------------------------
+    slots_collect<2>(slots, accs, lane);
     // ---- step count: wavefront sum, one atomic per wavefront --------------
     unsigned long long st = my_steps;
 #pragma unroll
@@ -249,87 +272,40 @@ int path_kernel_max_blocks_per_cu(int kind, int time_mode, bool uniform, bool br
 }
 
 // ---------------------------------------------------------------------------
-// Estimator reduction (Sect. 4: expectations replaced by arithmetic means).
-// One workgroup per output node: FP64 sums of the shifted scores and their
-// squares, wavefront shuffles then LDS, in a fixed order.
+// Estimator (Sect. 4: expectations replaced by arithmetic means): the node
+// sums of the path kernel -> mean, sample variance (N - 1), standard error,
+// in FP64; one thread per output node.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ double wave_sum(double v) {
+size_t acc_bytes(int64_t n_out) { return sizeof(NodeAcc) * (size_t)(n_out > 0 ? n_out : 0); }
+
+__global__ void __launch_bounds__(256) fk_finalize_kernel(const FinalArgs f) {
+    const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (o >= f.n_out) return;
+    const NodeAcc &A = f.acc[o];
+    const double N = (double)f.n_paths;
+    double mean[2], se[2];
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    return v;
+    for (int c = 0; c < 2; ++c) {
+        const double s1 = split_to_double(A.sum[2 * c]) * (1.0 / kQ1);
+        const double s2 = split_to_double(A.sum[2 * c + 1]) * (1.0 / kQ2);
+        const double m = s1 / N;
+        const double var = fmax((s2 - s1 * m) / (N - 1.0), 0.0);
+        mean[c] = m;
+        se[c] = sqrt(var / N);
+    }
+    const bool bad = A.bad != 0u;
+    const double nan = __builtin_nan("");
+    f.xi[o] = bad ? nan : f.outs[o].shift_x + mean[0];
+    f.eta[o] = bad ? nan : f.outs[o].shift_y + mean[1];
+    f.se_xi[o] = bad ? nan : se[0];
+    f.se_eta[o] = bad ? nan : se[1];
+    if (f.steps) f.steps[o] = (int64_t)A.steps;
 }
 
-__global__ void __launch_bounds__(256) fk_reduce_kernel(const ReduceArgs a) {
-    const int64_t o = blockIdx.x;
-    if (o >= a.n_out) return;
-    const float2 *rec = a.scores + o * a.n_paths;
-    const int32_t *ex = a.exit_step ? a.exit_step + o * a.n_paths : nullptr;
-    const int64_t K = a.outs[o].K;
-    double s1x = 0.0, s2x = 0.0, s1y = 0.0, s2y = 0.0;
-    long long st = 0;
-    // unrolled so that several records are in flight per thread; the sums
-    // keep their order
-    auto add = [&](const float2 v) {
-        const double vx = v.x, vy = v.y;
-        s1x += vx;
-        s2x = fma(vx, vx, s2x);
-        s1y += vy;
-        s2y = fma(vy, vy, s2y);
-    };
-    if (ex) {
-#pragma unroll 8
-        for (int64_t p = threadIdx.x; p < a.n_paths; p += blockDim.x) {
-            add(rec[p]);
-            const int32_t e = ex[p];
-            st += (e < 0) ? K : e;
-        }
-    } else {
-#pragma unroll 8
-        for (int64_t p = threadIdx.x; p < a.n_paths; p += blockDim.x) add(rec[p]);
-    }
-    s1x = wave_sum(s1x);
-    s2x = wave_sum(s2x);
-    s1y = wave_sum(s1y);
-    s2y = wave_sum(s2y);
-#pragma unroll
-    for (int off = 32; off > 0; off >>= 1) st += __shfl_xor(st, off, 64);
-    __shared__ double part[4][16];
-    __shared__ long long pst[16];
-    const int w = threadIdx.x >> 6;
-    if ((threadIdx.x & 63) == 0) {
-        part[0][w] = s1x;
-        part[1][w] = s2x;
-        part[2][w] = s1y;
-        part[3][w] = s2y;
-        pst[w] = st;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const int nw = (blockDim.x + 63) >> 6;
-        double t1x = 0.0, t2x = 0.0, t1y = 0.0, t2y = 0.0;
-        long long ts = 0;
-        for (int i = 0; i < nw; ++i) {
-            t1x += part[0][i];
-            t2x += part[1][i];
-            t1y += part[2][i];
-            t2y += part[3][i];
-            ts += pst[i];
-        }
-        const double N = (double)a.n_paths;
-        const double mx = t1x / N, my = t1y / N;
-        const double vx = fmax((t2x - t1x * mx) / (N - 1.0), 0.0);
-        const double vy = fmax((t2y - t1y * my) / (N - 1.0), 0.0);
-        a.xi[o] = a.outs[o].shift_x + mx;
-        a.eta[o] = a.outs[o].shift_y + my;
-        a.se_xi[o] = sqrt(vx / N);
-        a.se_eta[o] = sqrt(vy / N);
-        if (a.steps) a.steps[o] = ts;
-    }
-}
-
-hipError_t launch_reduce(const ReduceArgs &a, hipStream_t s) {
-    if (a.n_out == 0) return hipSuccess;
-    hipLaunchKernelGGL(fk_reduce_kernel, dim3((unsigned)a.n_out), dim3(256), 0, s, a);
+hipError_t launch_finalize(const FinalArgs &f, hipStream_t s) {
+    if (f.n_out == 0) return hipSuccess;
+    const unsigned blocks = (unsigned)((f.n_out + 255) / 256);
+    hipLaunchKernelGGL(fk_finalize_kernel, dim3(blocks), dim3(256), 0, s, f);
     return hipGetLastError();
 }
 

@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include "fk.h"
+#include "fk_accum.hpp"
 #include "fk_device.hpp"
 #include "fk_internal.hpp"
 
@@ -17,13 +18,18 @@ struct Lane {
     int32_t k;             // steps taken
     int32_t K;             // steps allowed
     uint32_t path, nid, ctr3;
-    uint64_t rec;          // record index
+    uint32_t out;          // output row of the path's node
     float px, py;          // start point (score shift for identity data)
     float horizon, dt, dt_last, cbm, cbm_last;
     float ox, oy;          // frozen / static centre offset
     float rev0, drev, cos_d, sin_d;  // orbit angle at path start, step, rotation
     DensityRegs dens;
 };
+
+// Index of the lane's path in the optional per-path outputs [n_out][n_paths].
+__device__ __forceinline__ uint64_t path_rec(const Lane &L, uint32_t n_paths) {
+    return (uint64_t)L.out * n_paths + L.path;
+}
 
 // Adds an increment to a (hi, lo) pair and renormalises so that hi is the
 // FP32 rounding of hi + lo.
@@ -149,23 +155,27 @@ __device__ __forceinline__ bool chunk_cursor(const PathArgs &a, uint32_t c, uint
     return true;
 }
 
-// Loads path `path` of node `nd` into a lane.
+// chunk_cursor, and on success the chunk's accumulation slot: its tag
+// (wave-uniform; every lane calls this).
+template <int NV>
+__device__ __forceinline__ bool grab_chunk(const PathArgs &a, uint32_t c, uint32_t &slot, uint32_t &next,
+                                           uint32_t &end, AccSlot<NV> *slots, NodeAcc *const *accs, uint32_t &tag,
+                                           uint32_t &grabs, uint32_t lane) {
+    if (!chunk_cursor(a, c, slot, next, end)) return false;
+    tag = slot_open<NV>(slots, accs, grabs++, (uint32_t)a.nodes[slot].out, end - next, lane);
+    return true;
+}
+
+// The level constants of a lane (horizon, step sizes, density parameters,
+// Philox counter word 3), loaded with every path: a wavefront may hold paths
+// of several levels in a batched launch.  (Held once per launch in scalar
+// registers instead, they cost the hot loop more than they save: a VALU
+// instruction reads one scalar operand, and the extra scalar pressure
+// spills.)
 template <int KIND, int TMODE>
-__device__ __forceinline__ void lane_start(Lane &L, const NodeDev &nd, const LevelDev *levels, uint32_t path,
-                                           uint32_t n_paths) {
-    const LevelDev lv = levels[nd.level];
-    L.path = path;
-    L.xh = nd.x;
-    L.yh = nd.y;
-    L.xl = nd.xlo;
-    L.yl = nd.ylo;
-    L.px = nd.x;
-    L.py = nd.y;
-    L.k = 0;
+__device__ __forceinline__ void lane_level(Lane &L, const LevelDev &lv) {
     L.K = lv.K;
-    L.nid = nd.nid;
     L.ctr3 = lv.ctr3;
-    L.rec = nd.out * (uint64_t)n_paths + L.path;
     L.horizon = lv.horizon;
     L.dt = lv.dt;
     L.dt_last = lv.dt_last;
@@ -192,6 +202,22 @@ __device__ __forceinline__ void lane_start(Lane &L, const NodeDev &nd, const Lev
     if constexpr (moving_kind(KIND) && TMODE == TIME_FROZEN) {
         orbit(L.dens, lv.t_freeze, L.ox, L.oy);
     }
+}
+
+// Loads path `path` of node `nd` into a lane, with its level's constants.
+template <int KIND, int TMODE>
+__device__ __forceinline__ void lane_start(Lane &L, const NodeDev &nd, const LevelDev *levels, uint32_t path) {
+    L.path = path;
+    L.xh = nd.x;
+    L.yh = nd.y;
+    L.xl = nd.xlo;
+    L.yl = nd.ylo;
+    L.px = nd.x;
+    L.py = nd.y;
+    L.k = 0;
+    L.nid = nd.nid;
+    L.out = (uint32_t)nd.out;
+    lane_level<KIND, TMODE>(L, levels[nd.level]);
 }
 
 // Score of a finished path (eq. (7b)): boundary data at the exit point if
@@ -224,6 +250,9 @@ __device__ __forceinline__ void score_path(const PathArgs &a, const Lane &L, boo
         sy = v;
     } else if (kind == FK_DATA_GRID) {
         sx = grid_bilinear(a.grid_xi, a.grid_n, x, y);
+        // one grid at a time: keeps the scoring's registers below the path
+        // loop's (this runs once per path)
+        __builtin_amdgcn_sched_barrier(0);
         sy = grid_bilinear(a.grid_eta, a.grid_n, x, y);
     } else {
         sx = 0.f;

@@ -20,7 +20,7 @@ def test_version(fk):
     assert fk.fk_version() >= 100
 
 
-def _call(fk, dens=None, data=None, pts=None, t=0.05, dt=1e-4, n_paths=16, ws_bytes=None, out_ptr=8):
+def _call(fk, dens=None, data=None, pts=None, t=0.05, dt=1e-4, n_paths=16, ws_bytes=None, out_ptr=8, plan=None):
     dens = dens or W.static_bump()
     data = data or W.Data()
     pts = np.ascontiguousarray(pts if pts is not None else [[0.5, 0.5]], dtype=np.float64)
@@ -31,7 +31,8 @@ def _call(fk, dens=None, data=None, pts=None, t=0.05, dt=1e-4, n_paths=16, ws_by
     # Non-null dummies: every call here must fail validation before any use.
     return lib.fk_interface_solve(ctypes.byref(fk._density(dens)), ctypes.byref(fk._data(data)),
                                   pts.ctypes.data_as(ctypes.c_void_p), n, t, dt, n_paths, 0, 0,
-                                  out_ptr, out_ptr, out_ptr, out_ptr, None, None, None, None, None,
+                                  out_ptr, out_ptr, out_ptr, out_ptr, None, None, None, None,
+                                  None if plan is None else ctypes.byref(fk._plan_struct(plan)),
                                   4096, ws, None)
 
 
@@ -48,6 +49,8 @@ def _call(fk, dens=None, data=None, pts=None, t=0.05, dt=1e-4, n_paths=16, ws_by
     (dict(data=W.Data(bdry_kind=W.DATA_GRID)), -1),
     (dict(data=W.Data(init_kind=W.DATA_GRID)), -1),
     (dict(ws_bytes=16), -3),
+    (dict(plan={"chunk": 4096}), -1),      # a chunk's sums must fit the 64-bit LDS slots
+    (dict(plan={"block": 96}), -1),
     (dict(out_ptr=None), -1),
 ])
 def test_validation_errors(fk, kw, code):
@@ -61,8 +64,13 @@ def test_empty_solve_is_a_noop(fk):
 
 
 def test_workspace_size(fk):
+    """The estimator is reduced inside the path kernel: the workspace holds
+    per-node tables and sums only (no per-path records), whatever n_paths."""
     a = fk.fk_interface_workspace_bytes(1521, 100_000)
-    assert a >= 1521 * 100_000 * 8
+    assert a == fk.fk_interface_workspace_bytes(1521, 2)
+    assert 1521 * 144 <= a <= 1521 * 160 + 4096
+    # the batched workload: 66047 nodes at 2^16 paths in a few MB
+    assert fk.fk_interface_workspace_bytes(66047, 1 << 16) < 12 << 20
     assert fk.fk_interface_workspace_bytes(10, 1) == 0
 
 

@@ -184,6 +184,39 @@ def test_schedule_invariance(fk, torch_cuda):
         assert int(r["total_steps"][0]) == int(r["steps"].sum())
 
 
+def test_in_kernel_estimator_equals_two_pass_fp64(fk, torch_cuda):
+    """The estimator is summed inside the path kernel in fixed point; against
+    a two-pass FP64 mean and sample variance of the same per-path scores
+    (dumped by the kernel) it agrees to 1e-12 relative (means) and 1e-9
+    relative (standard errors), and per-node step counts need no per-path
+    output."""
+    wl = W.MOVING_BUMP_1521
+    pts = wl.nodes()[::16]
+    for data, t, dt, n in ((wl.data, 0.02, 1e-5, 3000), (W.Data(init_kind=W.DATA_SIN, bdry_kind=W.DATA_SIN),
+                                                          0.01, 1e-4, 777)):
+        g = run_gpu(fk, torch_cuda, wl.density, data, pts, t, dt, n, seed=5)
+        sc = g["scores"].astype(np.float64)
+        shift = pts.astype(np.float32).astype(np.float64) if data.init_kind == W.DATA_IDENTITY else 0.0
+        mean = sc.mean(axis=1) + shift
+        se = sc.std(axis=1, ddof=1) / np.sqrt(n)
+        got = np.stack([g["xi"], g["eta"]], 1)
+        got_se = np.stack([g["se_xi"], g["se_eta"]], 1)
+        assert np.all(np.abs(got - mean) <= 1e-12 * np.maximum(np.abs(mean), 1e-3))
+        assert np.all(np.abs(got_se - se) <= 1e-9 * se + 1e-18)
+        steps = np.where(g["exit_step"] < 0, oracle_steps(t, dt), g["exit_step"]).sum(axis=1)
+        assert np.array_equal(g["steps"], steps)
+        only = fk.fk_interface_solve(wl.density, data, pts, t, dt, n, 5, steps=True)
+        torch_cuda.cuda.synchronize()
+        assert np.array_equal(only["steps"].cpu().numpy(), steps)
+        assert "exit_step" not in only
+        for k in ("xi", "eta", "se_xi", "se_eta"):
+            assert np.array_equal(only[k].cpu().numpy(), g[k]), k
+
+
+def oracle_steps(t, dt):
+    return int(math.ceil(t / dt - 1e-9))
+
+
 def test_full_size_moving_bump_sampled(fk, torch_cuda, oracle_mod):
     """Full moving-bump workload (1521 nodes x 10^5 paths) in the benchmark's
     launch configuration; sampled paths recomputed one by one by the oracle,
