@@ -217,6 +217,26 @@ int fk_interface_solve(const fk_density *w, const fk_data *d,
                        hipStream_t stream);
 
 /*
+ * fk_interface_solve for callers that cannot allocate device memory (code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments and results, without the workspace.  Its
+ * tables and sums live in a fixed device array inside the library (8 MiB per
+ * GPU, held until the process ends; fk_interface_noalloc_max_bytes() returns
+ * its size), which bounds n_nodes to about 58,000 -- larger requests fail
+ * with FK_E_NOMEM before anything is queued.  The call allocates nothing
+ * (no hipMalloc, hipFree or allocating library routine); what must start at
+ * zero is cleared by kernels on the stream.  Every call on one GPU uses that
+ * GPU's one array: calls that overlap on a GPU (other streams, other host
+ * threads) race and corrupt each other's results; the array keeps the last
+ * call's contents.
+ */
+size_t fk_interface_noalloc_max_bytes(void);
+int fk_interface_solve_noalloc(const fk_density *w, const fk_data *d, const double *pts, int64_t n_nodes, double t,
+                               double dt, int64_t n_paths, uint64_t seed, uint32_t level_id, double *xi,
+                               double *eta, double *se_xi, double *se_eta, int32_t *exit_step, float *scores,
+                               int64_t *steps, uint64_t *total_steps, const fk_plan *plan, hipStream_t stream);
+
+/*
  * Batched interface solves: several time levels, each with its own density
  * parameters, horizon and node slice (e.g. a different sub-domain layout),
  * run as one persistent launch over one work queue.  Every level has the

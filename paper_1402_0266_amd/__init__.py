@@ -81,6 +81,13 @@ _lib.fk_interface_solve.argtypes = [
     _P, _P, _P, _P, _P, _P, _P, _P,
     ctypes.POINTER(fk_plan), _P, ctypes.c_size_t, _P]
 _lib.fk_interface_solve.restype = ctypes.c_int
+_lib.fk_interface_noalloc_max_bytes.argtypes = []
+_lib.fk_interface_noalloc_max_bytes.restype = ctypes.c_size_t
+_lib.fk_interface_solve_noalloc.argtypes = [
+    ctypes.POINTER(fk_density), ctypes.POINTER(fk_data), _P, ctypes.c_int64,
+    ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
+    _P, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(fk_plan), _P]
+_lib.fk_interface_solve_noalloc.restype = ctypes.c_int
 _lib.fk_philox_words.argtypes = [_P, ctypes.c_int64, ctypes.c_uint64, _P, _P]
 _lib.fk_philox_words.restype = ctypes.c_int
 _lib.fk_normals.argtypes = [_P, _P, ctypes.c_int64, ctypes.c_double, _P, _P]
@@ -389,6 +396,33 @@ def fk_interface_solve(density, data, pts, t, dt, n_paths, seed=0, level_id=0, *
         workspace.data_ptr(), workspace.numel(), _stream(torch, dev))
     _check(rc)
     out["_workspace"] = workspace
+    return out
+
+
+def fk_interface_noalloc_max_bytes() -> int:
+    return int(_lib.fk_interface_noalloc_max_bytes())
+
+
+def fk_interface_solve_noalloc(density, data, pts, t, dt, n_paths, seed=0, level_id=0, *, out, plan=None,
+                               device="cuda", grids=None):
+    """``fk_interface_solve_noalloc``: the interface solve on the library's
+    static device scratch (no workspace).  ``out``: dict of caller-allocated
+    device tensors -- xi, eta, se_xi, se_eta (FP64 [n]) and optionally
+    exit_step, scores, steps, total_steps as in ``fk_interface_solve``."""
+    import torch
+    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 2)
+    pl = _plan_struct(plan)
+
+    def ptr(k):
+        v = out.get(k)
+        return None if v is None else v.data_ptr()
+
+    rc = _lib.fk_interface_solve_noalloc(
+        ctypes.byref(_density(density)), ctypes.byref(_data(data, grids)),
+        pts.ctypes.data_as(ctypes.c_void_p), pts.shape[0], float(t), float(dt), int(n_paths), int(seed),
+        int(level_id), ptr("xi"), ptr("eta"), ptr("se_xi"), ptr("se_eta"), ptr("exit_step"), ptr("scores"),
+        ptr("steps"), ptr("total_steps"), None if pl is None else ctypes.byref(pl), _stream(torch, torch.device(device)))
+    _check(rc)
     return out
 
 

@@ -4,10 +4,12 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -346,6 +348,33 @@ static WsLayout ws_layout(int64_t n_levels, int64_t n_nodes) {
     return L;
 }
 
+// ---- device scratch of fk_interface_solve_noalloc ---------------------------
+// A fixed device array in the library's code object (each GPU holds its own
+// copy until the process ends).  Host code never uses the array's name as a
+// device address: its address on each device is looked up once, with that
+// device current, and kept here.
+constexpr size_t kScratchBytes = (size_t)8 << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices] = {};
+
+static int scratch_address(void **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(FK_E_NODEVICE, "no HIP device: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices) return fail(FK_E_UNSUPPORTED, "device %d beyond the scratch table", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e, "hipGetSymbolAddress of the scratch array");
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return FK_OK;
+}
+
 }  // namespace fk
 
 using namespace fk;
@@ -463,6 +492,25 @@ int fk_interface_solve(const fk_density *w, const fk_data *d, const double *pts,
     S.fin.se_eta = se_eta;
     S.fin.steps = steps;
     return enqueue_solve(S, stream, true);
+}
+
+size_t fk_interface_noalloc_max_bytes(void) { return kScratchBytes; }
+
+int fk_interface_solve_noalloc(const fk_density *w, const fk_data *d, const double *pts, int64_t n_nodes, double t,
+                               double dt, int64_t n_paths, uint64_t seed, uint32_t level_id, double *xi,
+                               double *eta, double *se_xi, double *se_eta, int32_t *exit_step, float *scores,
+                               int64_t *steps, uint64_t *total_steps, const fk_plan *plan, hipStream_t stream) {
+    g_last_error.clear();
+    const size_t need = fk_interface_workspace_bytes(n_nodes, n_paths);
+    if (need > kScratchBytes)
+        return fail(FK_E_NOMEM, "%lld nodes need %zu bytes of scratch; the static scratch holds %zu (about %lld nodes)",
+                    (long long)n_nodes, need, kScratchBytes,
+                    (long long)(kScratchBytes / (need / (size_t)std::max<int64_t>(n_nodes, 1))));
+    void *ws = nullptr;
+    int rc;
+    if ((rc = scratch_address(&ws)) != FK_OK) return rc;
+    return fk_interface_solve(w, d, pts, n_nodes, t, dt, n_paths, seed, level_id, xi, eta, se_xi, se_eta, exit_step,
+                              scores, steps, total_steps, plan, ws, kScratchBytes, stream);
 }
 
 }  // extern "C"

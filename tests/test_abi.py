@@ -169,3 +169,19 @@ def test_binding_rejects_bad_output_rows(fk):
         fk.fk_interface_solve_cv(W.CONST, W.Data(), np.array([[0.5, 0.5], [0.25, 0.5]]), 0.01, 1e-3, 64, None,
                                  form=fk.FK_CV_MARTINGALE_GRID, device="cpu",
                                  out={"xi": torch.zeros((2, 2), dtype=torch.float64)[:, 0]})
+
+
+def test_noalloc_rejects_sizes_beyond_its_scratch(fk):
+    """fk_interface_solve_noalloc checks the size against its static scratch
+    before touching a device."""
+    lib = fk.library()
+    cap = fk.fk_interface_noalloc_max_bytes()
+    assert cap == 8 << 20
+    n = 100_000
+    assert fk.fk_interface_workspace_bytes(n, 16) > cap
+    pts = np.full((n, 2), 0.5)
+    rc = lib.fk_interface_solve_noalloc(ctypes.byref(fk._density(W.static_bump())), ctypes.byref(fk._data(W.Data())),
+                                        pts.ctypes.data_as(ctypes.c_void_p), n, 0.05, 1e-4, 16, 0, 0,
+                                        8, 8, 8, 8, None, None, None, None, None, None)
+    assert rc == -3
+    assert "scratch" in fk.fk_last_error()
