@@ -206,9 +206,10 @@ def fk_paths(dens, data, pts, node_ids, path_ids, t, dt, seed=0, level_id=0, str
     return sc, ex
 
 
-UHAT_MLP, UHAT_LINEAR, UHAT_SIN, UHAT_ZERO, UHAT_GRID, UHAT_MLP_BASE, UHAT_QUAD = 0, 1, 2, 3, 4, 5, 6
+UHAT_MLP, UHAT_LINEAR, UHAT_SIN, UHAT_ZERO, UHAT_GRID, UHAT_MLP_BASE, UHAT_QUAD, UHAT_GRID_MLP = 0, 1, 2, 3, 4, 5, 6, 7
 # GRID: the grid initial data; MLP_BASE: the identity map plus the MLP;
-# QUAD: the test function (tau x^2, tau y^2)
+# QUAD: the test function (tau x^2, tau y^2); GRID_MLP: the grid initial data
+# (bilinear) plus the MLP (martingale form)
 CV_DYNKIN, CV_MARTINGALE = 0, 1   # forms of the control-variate estimator
 
 

@@ -721,6 +721,21 @@ static void bilinear_grad(const double *g, int n, double x, double y, double *gx
 
 static void uhat_eval(const or_uhat *u, double tau, double x, double y, double out[2][5])
 {
+    if (u->kind == 7) {
+        /* the network as the deviation from the grid initial data (the mesh
+           at the step's start): u_hat = bilinear(grid) + MLP; the martingale
+           form uses only the gradient */
+        const double *g[2] = {u->grid_xi, u->grid_eta};
+        mlp_forward_mode(&u->mlp, tau, x, y, out);
+        for (int c = 0; c < 2; ++c) {
+            double gx, gy;
+            bilinear_grad(g[c], u->grid_n, x, y, &gx, &gy);
+            out[c][0] += bilinear(g[c], u->grid_n, x, y);
+            out[c][1] += gx;
+            out[c][2] += gy;
+        }
+        return;
+    }
     if (u->kind == 4) {
         /* the grid initial data, bilinear: value and gradient (the martingale
            form uses only the gradient) */
@@ -923,7 +938,7 @@ int or_fk_solve_cv(int kind, int time_mode, const double *par, const double *w_g
 {
     if (n_nodes < 0 || n_paths < 2 || !(dt > 0.0) || !(t >= 0.0) || stride < 1) return -1;
     if (form != 0 && form != 1) return -1;
-    if ((uhat_kind == 0 || uhat_kind == 5) && !flat) return -1;
+    if ((uhat_kind == 0 || uhat_kind == 5 || uhat_kind == 7) && !flat) return -1;
     or_problem pb;
     pb.kind = kind;
     pb.time_mode = time_mode;
@@ -950,9 +965,10 @@ int or_fk_solve_cv(int kind, int time_mode, const double *par, const double *w_g
     u.grid_xi = grid_xi;
     u.grid_eta = grid_eta;
     u.grid_n = grid_n;
-    if (uhat_kind == 0 || uhat_kind == 5) mlp_bind(&u.mlp, flat, t_scale);
+    if (uhat_kind == 0 || uhat_kind == 5 || uhat_kind == 7) mlp_bind(&u.mlp, flat, t_scale);
     /* the grid's bilinear interpolant has no Laplacian: martingale form only */
-    if (uhat_kind == 4 && (form != 1 || init_kind != D_GRID || !grid_xi || !grid_eta)) return -1;
+    if ((uhat_kind == 4 || uhat_kind == 7) && (form != 1 || init_kind != D_GRID || !grid_xi || !grid_eta))
+        return -1;
     const int64_t total = n_nodes * n_paths;
     double *pl = (double *)malloc(sizeof(double) * 2 * (size_t)(total > 0 ? total : 1));
     double *cs = cv_scores ? cv_scores : (double *)malloc(sizeof(double) * 2 * (size_t)(total > 0 ? total : 1));

@@ -246,3 +246,60 @@ def test_identity_base_is_the_identity_plus_the_network(oracle_mod, form):
     assert np.abs(base["mean"] - (net["mean"] + lin["mean"] - zero["mean"])).max() < 1e-12
     zero_net = run(oracle_mod.UHAT_MLP_BASE, np.zeros_like(flat))
     assert np.array_equal(zero_net["cv_scores"], lin["cv_scores"])
+
+
+# ---- martingale form with the network as the deviation from the mesh ---------
+# u_hat = bilinear(grid initial data) + MLP: G = grid gradient + network gradient.
+
+def test_grid_base_is_the_grid_plus_the_network(oracle_mod):
+    """The martingale score is affine in G, so per path: score(grid + net) =
+    score(net) + score(grid) - score(0); a zero network gives the grid
+    control bitwise; on the identity mesh the base is the identity base."""
+    X, Y = _nodal(48)
+    xi = X + 0.02 * np.sin(math.pi * X) * np.sin(2 * math.pi * Y)
+    eta = Y + 0.015 * np.sin(2 * math.pi * X) * np.sin(math.pi * Y)
+    data = W.Data(init_kind=W.DATA_GRID, score_mode=W.SCORE_EXTEND, grid_xi=xi, grid_eta=eta)
+    dens = W.two_bumps(W.TIME_FROZEN, 0.01)
+    pts = W.interface_nodes(4, 4, 48)[::11]
+    flat = W.mlp_init(4).astype(np.float64)
+    kw = dict(seed=3, stride=4, form=oracle_mod.CV_MARTINGALE, want_scores=True, threads=4)
+
+    def run(uhat, fl=None, d=data):
+        return oracle_mod.fk_solve_cv(dens, d, pts, 5e-4, 2.5e-5, 300, uhat=uhat, flat=fl, **kw)
+
+    both = run(oracle_mod.UHAT_GRID_MLP, flat)
+    expect = run(oracle_mod.UHAT_MLP, flat)["cv_scores"] + run(oracle_mod.UHAT_GRID)["cv_scores"] \
+        - run(oracle_mod.UHAT_ZERO)["cv_scores"]
+    assert np.abs(both["cv_scores"] - expect).max() < 1e-12
+    assert np.array_equal(run(oracle_mod.UHAT_GRID_MLP, np.zeros_like(flat))["cv_scores"],
+                          run(oracle_mod.UHAT_GRID)["cv_scores"])
+    ident = W.Data(init_kind=W.DATA_GRID, score_mode=W.SCORE_EXTEND, grid_xi=X, grid_eta=Y)
+    a = run(oracle_mod.UHAT_GRID_MLP, flat, ident)["cv_scores"]
+    b = oracle_mod.fk_solve_cv(dens, ident, pts, 5e-4, 2.5e-5, 300, uhat=oracle_mod.UHAT_MLP_BASE, flat=flat,
+                               **kw)["cv_scores"]
+    assert np.abs(a - b).max() < 1e-12
+    with pytest.raises(ValueError):
+        oracle_mod.fk_solve_cv(dens, data, pts, 5e-4, 2.5e-5, 10, uhat=oracle_mod.UHAT_GRID_MLP, flat=flat,
+                               form=oracle_mod.CV_DYNKIN)
+
+
+def test_grid_base_control_is_unbiased(oracle_mod):
+    """A curved network on top of a deformed mesh: cv - plain on the same
+    paths has mean zero (z-scores) at strides 2 and 20."""
+    X, Y = _nodal(48)
+    xi = X + 0.02 * np.sin(math.pi * X) * np.sin(2 * math.pi * Y)
+    eta = Y + 0.015 * np.sin(2 * math.pi * X) * np.sin(math.pi * Y)
+    data = W.Data(init_kind=W.DATA_GRID, score_mode=W.SCORE_EXTEND, grid_xi=xi, grid_eta=eta)
+    dens = W.two_bumps(W.TIME_FROZEN, 0.01)
+    pts = W.interface_nodes(4, 4, 48)[::9]
+    flat = M.bf16_round(W.mlp_init(1) * 2.5)
+    pl = oracle_mod.fk_solve(dens, data, pts, 5e-4, 2.5e-5, 2000, seed=8, want_scores=True)
+    z = []
+    for stride in (2, 20):
+        r = oracle_mod.fk_solve_cv(dens, data, pts, 5e-4, 2.5e-5, 2000, seed=8, uhat=oracle_mod.UHAT_GRID_MLP,
+                                   flat=flat, t_scale=W.CV_T_SCALE, stride=stride, form=oracle_mod.CV_MARTINGALE,
+                                   want_scores=True)
+        diff = r["cv_scores"] - pl["scores"]
+        z.append(diff.mean(1) / (diff.std(1, ddof=1) / math.sqrt(diff.shape[1])))
+    z = np.concatenate(z).ravel()
+    assert np.abs(z).max() < 4.0 and abs(z.mean()) < 4 / math.sqrt(z.size)
