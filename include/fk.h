@@ -421,6 +421,22 @@ int fk_cv_get_params(fk_cv_t cv, float *params, uint16_t *bf16_params);
  * and the identity to their gradients.  Applies to all later calls; 0 (the
  * default) is the plain network. */
 int fk_cv_set_identity_base(fk_cv_t cv, int32_t on);
+/* The base of the control: FK_CV_BASE_NONE (the network itself),
+ * FK_CV_BASE_IDENTITY (as fk_cv_set_identity_base(cv, 1)) or FK_CV_BASE_GRID:
+ * u_hat = the bilinear interpolant of the solve's grid initial data (the mesh
+ * at the step's start) + network, in the martingale form of
+ * fk_interface_solve_cv (which then needs FK_DATA_GRID initial data; the
+ * Dynkin form is FK_E_UNSUPPORTED since the interpolant has no Laplacian).
+ * Over one mesh step the solution stays close to the mesh it starts from, so
+ * the network only carries the step's change; it is trained on targets minus
+ * the base, which the caller forms (fk_cv_train and fk_cv_eval see the network
+ * alone under the grid base).  The martingale blocks then close every 2 steps,
+ * with G = the interpolant's gradient there plus the network's gradient taken
+ * every `stride` steps and held (each G still fixed before its increments). */
+#define FK_CV_BASE_NONE 0
+#define FK_CV_BASE_IDENTITY 1
+#define FK_CV_BASE_GRID 2
+int fk_cv_set_base(fk_cv_t cv, int32_t base);
 int fk_cv_set_params(fk_cv_t cv, const float *params /* host [8706] */);
 /* Forward-mode evaluation at n points txy (device [n][3]: t, x, y):
  * out (device [n][2][5]) = for each output: value, d/dx, d/dy, d/dt,

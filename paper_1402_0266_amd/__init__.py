@@ -137,6 +137,8 @@ _lib.fk_cv_create.argtypes = [_P, ctypes.c_double, ctypes.POINTER(_P)]
 _lib.fk_cv_create.restype = ctypes.c_int
 _lib.fk_cv_set_identity_base.argtypes = [_P, ctypes.c_int32]
 _lib.fk_cv_set_identity_base.restype = ctypes.c_int
+_lib.fk_cv_set_base.argtypes = [_P, ctypes.c_int32]
+_lib.fk_cv_set_base.restype = ctypes.c_int
 _lib.fk_cv_destroy.argtypes = [_P]
 _lib.fk_cv_destroy.restype = None
 _lib.fk_cv_get_params.argtypes = [_P, _P, _P]
@@ -566,10 +568,16 @@ def fk_mesh_quality(xi, eta, out=None):
 FK_CV_N_PARAMS = 8706
 
 
+FK_CV_BASES = {"none": 0, "identity": 1, "grid": 2}
+
+
 class FkCv:
     """The control-variate network (C: ``fk_cv_*``)."""
 
-    def __init__(self, params, t_scale=0.1, identity_base=False):
+    def __init__(self, params, t_scale=0.1, identity_base=False, base=None):
+        """``base``: None / "none" (the network itself), "identity" (u_hat =
+        (x, y) + network; also ``identity_base=True``) or "grid" (u_hat = the
+        solve's grid initial data, bilinear, + network; martingale solves)."""
         p = np.ascontiguousarray(params, dtype=np.float32).ravel()
         if p.size != FK_CV_N_PARAMS:
             raise ValueError("need 8706 parameters")
@@ -577,9 +585,12 @@ class FkCv:
         _check(_lib.fk_cv_create(p.ctypes.data_as(ctypes.c_void_p), float(t_scale), ctypes.byref(h)))
         self._h = h
         self.t_scale = float(t_scale)
-        self.identity_base = bool(identity_base)
-        if identity_base:
-            _check(_lib.fk_cv_set_identity_base(h, 1))
+        base = base or ("identity" if identity_base else "none")
+        if base not in FK_CV_BASES:
+            raise ValueError(f"base must be one of {sorted(FK_CV_BASES)}")
+        self.base = base
+        self.identity_base = base == "identity"
+        _check(_lib.fk_cv_set_base(h, FK_CV_BASES[base]))
 
     def close(self):
         if getattr(self, "_h", None) and _lib is not None:

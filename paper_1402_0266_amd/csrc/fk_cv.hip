@@ -58,6 +58,7 @@ struct fk_cv {
     int device = 0;
     float t_scale = 0.1f;
     float base = 0.f;    // 1: u_hat = (x, y) + network (the identity base)
+    int grid_base = 0;   // 1: u_hat = bilinear(grid initial data) + network (martingale solves)
     int64_t steps_done = 0;
     fk::CvState s;
 };
@@ -581,6 +582,53 @@ __global__ void __launch_bounds__(256, 2) fk_cv_path_kernel(const PathArgs a, co
     if (lane == 0 && st != 0ull) atomicAdd(a.total_steps, st);
 }
 
+// Gradient of the bilinear interpolant of a nodal grid at (x, y) (the cell
+// grid_bilinear uses); differences taken in FP64.
+__device__ __forceinline__ void grid_gradient(const double *g, int n, float x, float y, float &gx, float &gy) {
+    const float fx = x * (float)n, fy = y * (float)n;
+    int i = (int)floorf(fx), j = (int)floorf(fy);
+    i = min(max(i, 0), n - 1);
+    j = min(max(j, 0), n - 1);
+    const float ax = fx - (float)i, ay = fy - (float)j;
+    const double *r0 = g + (int64_t)j * (n + 1);
+    const double *r1 = r0 + (n + 1);
+    const float d0x = (float)(r0[i + 1] - r0[i]), d1x = (float)(r1[i + 1] - r1[i]);
+    const float d0y = (float)(r1[i] - r0[i]), d1y = (float)(r1[i + 1] - r0[i + 1]);
+    gx = (float)n * fmaf(ay, d1x - d0x, d0x);
+    gy = (float)n * fmaf(ax, d1y - d0y, d0y);
+}
+
+// Per cell (i, j) of the grid initial data, the FP32 terms grid_gradient
+// forms from the four corner values: (d0x, d1x - d0x, d0y, d1y - d0y) for
+// xi at tab[2 c] and for eta at tab[2 c + 1], c = j n + i.  The gradient
+// taken from the table is bitwise the one taken from the grids, at one
+// 16-byte load per component instead of four FP64 loads.
+__global__ void grad_table_kernel(const double *gxi, const double *geta, int n, float4 *tab) {
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= (int64_t)n * n) return;
+    const int i = (int)(c % n), j = (int)(c / n);
+#pragma unroll
+    for (int comp = 0; comp < 2; ++comp) {
+        const double *r0 = (comp ? geta : gxi) + (int64_t)j * (n + 1);
+        const double *r1 = r0 + (n + 1);
+        const float d0x = (float)(r0[i + 1] - r0[i]), d1x = (float)(r1[i + 1] - r1[i]);
+        const float d0y = (float)(r1[i] - r0[i]), d1y = (float)(r1[i + 1] - r0[i + 1]);
+        tab[2 * c + comp] = make_float4(d0x, d1x - d0x, d0y, d1y - d0y);
+    }
+}
+
+__device__ __forceinline__ void table_gradient(const float4 *tab, int n, int comp, float x, float y, float &gx,
+                                               float &gy) {
+    const float fx = x * (float)n, fy = y * (float)n;
+    int i = (int)floorf(fx), j = (int)floorf(fy);
+    i = min(max(i, 0), n - 1);
+    j = min(max(j, 0), n - 1);
+    const float ax = fx - (float)i, ay = fy - (float)j;
+    const float4 t = tab[2 * ((int64_t)j * n + i) + comp];
+    gx = (float)n * fmaf(ay, t.y, t.x);
+    gy = (float)n * fmaf(ax, t.w, t.z);
+}
+
 // Martingale-form path kernel.  The score is g - sum_j G_j . dB_j: dB_j is the
 // Brownian part of the path's steps in block j, G_j the gradient of u_hat at
 // the block's first state.  Blocks start at the path's start (G_0 from the
@@ -594,6 +642,10 @@ struct MgArgs {
     uint32_t stride_iters;
     float base;                  // identity base (0 or 1)
     const float4 *g0;            // [n_out] (dxi/dx, dxi/dy, deta/dx, deta/dy) at the start point
+    int32_t grid_base;           // 1: u_hat = bilinear(grid initial data) + network: blocks every
+                                 // iteration (2 steps) with the mesh's gradient there, plus the
+                                 // network's taken at the evaluation points and held
+    const float4 *gtab;          // grid base: per-cell gradient table, or NULL (read the grids)
     NodeAcc *acc_cv;             // [n_out] sums of the CV scores
     float2 *cv_scores;           // [n_out * n_paths], absolute, or nullptr
 };
@@ -622,6 +674,7 @@ __global__ void __launch_bounds__(256, 4) fk_mg_path_kernel(const PathArgs a, co
     float gxx = 0.f, gxy = 0.f, gyx = 0.f, gyy = 0.f;   // gradient of (xi_hat, eta_hat) held over the block
     float dbx = 0.f, dby = 0.f;                         // Brownian part of the block so far
     float mx = 0.f, my = 0.f;                           // the martingale sum of the closed blocks
+    float nxx = 0.f, nxy = 0.f, nyx = 0.f, nyy = 0.f;   // grid base: the network's part of the gradient
     const float tend = a.levels[0].tend;                // PDE time at path start
     uint32_t my_tag = 0;                                // accumulation tag of the path's chunk
     uint32_t my_steps = 0;
@@ -640,7 +693,14 @@ __global__ void __launch_bounds__(256, 4) fk_mg_path_kernel(const PathArgs a, co
                 float o[2][2];
                 net_grad_wave(N, c.tscale2, tau, active ? L.xh : 0.5f, active ? L.yh : 0.5f, o);
                 add_base_grad(c.base, o);
-                if (active) {
+                if (c.grid_base) {
+                    // grid base: the network's part, held until the next
+                    // evaluation point; the blocks close every iteration
+                    nxx = o[0][0];
+                    nxy = o[0][1];
+                    nyx = o[1][0];
+                    nyy = o[1][1];
+                } else if (active) {
                     mx = fmaf(gxx, dbx, fmaf(gxy, dby, mx));
                     my = fmaf(gyx, dbx, fmaf(gyy, dby, my));
                     dbx = dby = 0.f;
@@ -672,6 +732,10 @@ __global__ void __launch_bounds__(256, 4) fk_mg_path_kernel(const PathArgs a, co
                     gxy = g0.y;
                     gyx = g0.z;
                     gyy = g0.w;
+                    nxx = g0.x;
+                    nxy = g0.y;
+                    nyx = g0.z;
+                    nyy = g0.w;
                     dbx = dby = mx = my = 0.f;
                     active = true;
                 }
@@ -684,6 +748,24 @@ __global__ void __launch_bounds__(256, 4) fk_mg_path_kernel(const PathArgs a, co
         if (active) {
             bool out = false;
             if (L.k < L.K) {
+                if (c.grid_base) {
+                    // close the block (every 2 steps): G = the mesh's gradient
+                    // here + the network's part
+                    mx = fmaf(gxx, dbx, fmaf(gxy, dby, mx));
+                    my = fmaf(gyx, dbx, fmaf(gyy, dby, my));
+                    dbx = dby = 0.f;
+                    if (c.gtab) {
+                        table_gradient(c.gtab, a.grid_n, 0, L.xh, L.yh, gxx, gxy);
+                        table_gradient(c.gtab, a.grid_n, 1, L.xh, L.yh, gyx, gyy);
+                    } else {
+                        grid_gradient(a.grid_xi, a.grid_n, L.xh, L.yh, gxx, gxy);
+                        grid_gradient(a.grid_eta, a.grid_n, L.xh, L.yh, gyx, gyy);
+                    }
+                    gxx += nxx;
+                    gxy += nxy;
+                    gyx += nyx;
+                    gyy += nyy;
+                }
                 const PhiloxOut r = philox4x32_10((uint32_t)L.k >> 1, L.path, L.nid, L.ctr3, key0, key1);
                 float ox = L.ox, oy = L.oy, cr = 0.f, sr = 0.f;
                 if constexpr (kMovingBackward) {
@@ -734,22 +816,6 @@ __global__ void __launch_bounds__(256, 4) fk_mg_path_kernel(const PathArgs a, co
     if (lane == 0 && st != 0ull) atomicAdd(a.total_steps, st);
 }
 
-// Gradient of the bilinear interpolant of a nodal grid at (x, y) (the cell
-// grid_bilinear uses); differences taken in FP64.
-__device__ __forceinline__ void grid_gradient(const double *g, int n, float x, float y, float &gx, float &gy) {
-    const float fx = x * (float)n, fy = y * (float)n;
-    int i = (int)floorf(fx), j = (int)floorf(fy);
-    i = min(max(i, 0), n - 1);
-    j = min(max(j, 0), n - 1);
-    const float ax = fx - (float)i, ay = fy - (float)j;
-    const double *r0 = g + (int64_t)j * (n + 1);
-    const double *r1 = r0 + (n + 1);
-    const float d0x = (float)(r0[i + 1] - r0[i]), d1x = (float)(r1[i + 1] - r1[i]);
-    const float d0y = (float)(r1[i] - r0[i]), d1y = (float)(r1[i + 1] - r0[i + 1]);
-    gx = (float)n * fmaf(ay, d1x - d0x, d0x);
-    gy = (float)n * fmaf(ax, d1y - d0y, d0y);
-}
-
 // Martingale form with the grid initial data as the control: every `stride`
 // steps of a path (from its start) the lane takes G = the gradient of the
 // bilinear interpolant of (grid_xi, grid_eta) at its position, and the score
@@ -761,38 +827,10 @@ struct MggArgs {
     NodeAcc *acc_cv;             // [n_out] sums of the CV scores
     float2 *cv_scores;           // [n_out * n_paths], absolute, or nullptr
     const float4 *gtab;          // per-cell gradient table (grad_table_kernel), or NULL: read the grids
+    const float4 *gofs;          // [n_out] a gradient added to the mesh's at every block of the node's
+                                 // paths (the network's at the node: the grid base with the network
+                                 // taken only at the path's start), or NULL
 };
-
-// Per cell (i, j) of the grid initial data, the FP32 terms grid_gradient
-// forms from the four corner values: (d0x, d1x - d0x, d0y, d1y - d0y) for
-// xi at tab[2 c] and for eta at tab[2 c + 1], c = j n + i.  The gradient
-// taken from the table is bitwise the one taken from the grids, at one
-// 16-byte load per component instead of four FP64 loads.
-__global__ void grad_table_kernel(const double *gxi, const double *geta, int n, float4 *tab) {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= (int64_t)n * n) return;
-    const int i = (int)(c % n), j = (int)(c / n);
-#pragma unroll
-    for (int comp = 0; comp < 2; ++comp) {
-        const double *r0 = (comp ? geta : gxi) + (int64_t)j * (n + 1);
-        const double *r1 = r0 + (n + 1);
-        const float d0x = (float)(r0[i + 1] - r0[i]), d1x = (float)(r1[i + 1] - r1[i]);
-        const float d0y = (float)(r1[i] - r0[i]), d1y = (float)(r1[i + 1] - r0[i + 1]);
-        tab[2 * c + comp] = make_float4(d0x, d1x - d0x, d0y, d1y - d0y);
-    }
-}
-
-__device__ __forceinline__ void table_gradient(const float4 *tab, int n, int comp, float x, float y, float &gx,
-                                               float &gy) {
-    const float fx = x * (float)n, fy = y * (float)n;
-    int i = (int)floorf(fx), j = (int)floorf(fy);
-    i = min(max(i, 0), n - 1);
-    j = min(max(j, 0), n - 1);
-    const float ax = fx - (float)i, ay = fy - (float)j;
-    const float4 t = tab[2 * ((int64_t)j * n + i) + comp];
-    gx = (float)n * fmaf(ay, t.y, t.x);
-    gy = (float)n * fmaf(ax, t.w, t.z);
-}
 
 template <int KIND, int TMODE, bool UNIFORM>
 __global__ void __launch_bounds__(256) fk_mgg_path_kernel(const PathArgs a, const MggArgs c) {
@@ -859,6 +897,13 @@ __global__ void __launch_bounds__(256) fk_mgg_path_kernel(const PathArgs a, cons
                     } else {
                         grid_gradient(a.grid_xi, a.grid_n, L.xh, L.yh, gxx, gxy);
                         grid_gradient(a.grid_eta, a.grid_n, L.xh, L.yh, gyx, gyy);
+                    }
+                    if (c.gofs) {
+                        const float4 o = c.gofs[L.out];   // L2-resident, 16 B per node
+                        gxx += o.x;
+                        gxy += o.y;
+                        gyx += o.z;
+                        gyy += o.w;
                     }
                 }
                 --blk_left;
@@ -1333,6 +1378,22 @@ static CvWs cv_ws_layout(int64_t n_nodes) {
     return L;
 }
 
+// The per-cell gradient table of the grid initial data, built on the stream
+// in the workspace past `used` bytes when it has room (NULL otherwise: the
+// kernels then read the grids).
+static const float4 *grid_table(const fk_data *d, void *workspace, size_t workspace_bytes, size_t used,
+                                hipStream_t stream, hipError_t *err) {
+    *err = hipSuccess;
+    const size_t tab_off = align256(used), tab_bytes = (size_t)d->grid_n * d->grid_n * 2 * sizeof(float4);
+    if (workspace_bytes < tab_off + tab_bytes) return nullptr;
+    float4 *tab = (float4 *)((char *)workspace + tab_off);
+    const int64_t cells = (int64_t)d->grid_n * d->grid_n;
+    hipLaunchKernelGGL(grad_table_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, stream, d->grid_xi,
+                       d->grid_eta, d->grid_n, tab);
+    *err = hipGetLastError();
+    return tab;
+}
+
 }  // namespace fk
 
 using namespace fk;
@@ -1384,6 +1445,17 @@ int fk_cv_set_identity_base(fk_cv_t cv, int32_t on) {
     if (!cv) return fail(FK_E_INVAL, "network is NULL");
     if (on != 0 && on != 1) return fail(FK_E_INVAL, "on must be 0 or 1");
     cv->base = (float)on;
+    cv->grid_base = 0;
+    return FK_OK;
+}
+
+int fk_cv_set_base(fk_cv_t cv, int32_t base) {
+    g_last_error.clear();
+    if (!cv) return fail(FK_E_INVAL, "network is NULL");
+    if (base != FK_CV_BASE_NONE && base != FK_CV_BASE_IDENTITY && base != FK_CV_BASE_GRID)
+        return fail(FK_E_INVAL, "unknown base %d", base);
+    cv->base = base == FK_CV_BASE_IDENTITY ? 1.f : 0.f;
+    cv->grid_base = base == FK_CV_BASE_GRID ? 1 : 0;
     return FK_OK;
 }
 
@@ -1553,6 +1625,10 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         return fail(FK_E_INVAL, "unknown control-variate form");
     if (grid_ctl && d->init_kind != FK_DATA_GRID)
         return fail(FK_E_INVAL, "the grid control needs grid initial data");
+    const bool grid_base = !grid_ctl && cv->grid_base;
+    if (grid_base && form != FK_CV_MARTINGALE)
+        return fail(FK_E_UNSUPPORTED, "the grid base needs the martingale form (its interpolant has no Laplacian)");
+    if (grid_base && d->init_kind != FK_DATA_GRID) return fail(FK_E_INVAL, "the grid base needs grid initial data");
     if (n_nodes > 0 && (!xi || !eta || !se_xi || !se_eta)) return fail(FK_E_INVAL, "an output pointer is NULL");
     fk_plan pl;
     if ((rc = resolve_plan(plan, &pl)) != FK_OK) return rc;
@@ -1601,12 +1677,18 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     na.r0 = mg ? nullptr : (float2 *)(ws + lay.r0);
     na.g0 = mg ? (float4 *)(ws + lay.g0) : nullptr;
     na.base = grid_ctl ? 0.f : cv->base;
+
     const float ts2 = grid_ctl ? 0.f : 2.f / cv->t_scale;
     if ((e = timing_record(0, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     if (!grid_ctl &&
         (e = cv_dispatch<CvNodeF>(T.kind, T.time_mode, true, na, (const uint16_t *)cv->s.bf, ts2, stream)) !=
             hipSuccess)
         return hip_fail(e, "node kernel launch");
+    // The grid base with a stride of at least the horizon takes the network
+    // only at each path's start: that is the node kernel's gradient, and the
+    // grid-control kernel adds it to the mesh's at every block (bitwise the
+    // same arithmetic as the network kernel, without its evaluation points).
+    const bool base_at_start = grid_base && (int64_t)stride >= (int64_t)T.levels[0].K;
 
     PathArgs a{};
     SolveLaunch S{};
@@ -1645,21 +1727,14 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
         if ((e = cv_dispatch<CvLaunchF>(T.kind, T.time_mode, T.uniform, a, c, cap_grid(n_cu * bpc, a.total_chunks, 256), stream)) != hipSuccess)
             return hip_fail(e, "control-variate path kernel launch");
-    } else if (grid_ctl) {
+    } else if (grid_ctl || base_at_start) {
         MggArgs c{};
-        c.stride_iters = (uint32_t)(stride / 2);
+        c.stride_iters = base_at_start ? 1u : (uint32_t)(stride / 2);
+        c.gofs = base_at_start ? (const float4 *)(ws + lay.g0) : nullptr;
         c.cv_scores = cv_rec;
         c.acc_cv = acc_cv;
-        // the gradient table, when the workspace has room for it
-        const size_t tab_off = align256(lay.total), tab_bytes = (size_t)d->grid_n * d->grid_n * 2 * sizeof(float4);
-        if (workspace_bytes >= tab_off + tab_bytes) {
-            float4 *tab = (float4 *)(ws + tab_off);
-            const int64_t cells = (int64_t)d->grid_n * d->grid_n;
-            hipLaunchKernelGGL(grad_table_kernel, dim3((unsigned)((cells + 255) / 256)), dim3(256), 0, stream,
-                               d->grid_xi, d->grid_eta, d->grid_n, tab);
-            if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "gradient table kernel launch");
-            c.gtab = tab;
-        }
+        c.gtab = grid_table(d, workspace, workspace_bytes, lay.total, stream, &e);
+        if (e != hipSuccess) return hip_fail(e, "gradient table kernel launch");
         const int occ = cv_dispatch<MggOccF>(T.kind, T.time_mode, T.uniform);
         if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
         if ((e = cv_dispatch<MggLaunchF>(T.kind, T.time_mode, T.uniform, a, c, cap_grid(n_cu * bpc, a.total_chunks, 256), stream)) != hipSuccess)
@@ -1671,6 +1746,9 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         c.stride_iters = (uint32_t)(stride / 2);
         c.base = grid_ctl ? 0.f : cv->base;
         c.g0 = (const float4 *)(ws + lay.g0);
+        c.grid_base = grid_base ? 1 : 0;
+        if (grid_base) c.gtab = grid_table(d, workspace, workspace_bytes, lay.total, stream, &e);
+        if (e != hipSuccess) return hip_fail(e, "gradient table kernel launch");
         c.cv_scores = cv_rec;
         c.acc_cv = acc_cv;
         const int occ = cv_dispatch<MgOccF>(T.kind, T.time_mode, T.uniform);

@@ -26,8 +26,12 @@ cubic Hermite interpolant through the line's boundary data and key values
 
 With `cv_form="grid"` the control is the mesh's own gradient (bilinear in
 the grid, taken every `cv_stride` steps of each path) in the martingale
-form: no network.  Otherwise the network u_hat(t, x, y) is refitted every
-`refit_every` steps on labels
+form: no network.  Otherwise the network is refitted every `refit_every`
+steps; by default (`cv_base="mesh"`) the control is the mesh's own
+interpolant plus the network, which fits the change of the mesh over one
+step (new mesh minus the mesh it started from), so between refits it only
+has to carry how the step's change moves, not the moving features
+themselves.  The network is trained on labels
 the run has produced (at their times t^{n+1}), starting from the initial mesh
 at t = 0: either the interface estimates themselves, or (default) the mesh
 values at the grid nodes within `band` of an interface line, where the paths
@@ -67,6 +71,9 @@ class MeshRunConfig:
     refit_every: int = 20       # 0: plain Monte Carlo throughout
     cv_form: str = "martingale"  # "dynkin"; or "grid": the martingale form with the mesh's own gradient
                                  # (no network, refit_every ignored)
+    cv_base: str = "mesh"       # network forms: "mesh" -- the network fits the step's change of the mesh and
+                                 # the control is the mesh's own interpolant plus it (martingale form only);
+                                 # "none" -- the network fits the map itself
     cv_stride: int = 20
     train_steps: int = 2000
     train_batch: int = 8192
@@ -212,10 +219,18 @@ class MeshRun:
         if cfg.refit_every > 0 and cfg.cv_form != "grid":
             if init_params is None:
                 raise ValueError("refit_every > 0 needs initial network parameters")
-            self.cv = FkCv(init_params, cfg.t_scale)
+            if cfg.cv_base not in ("mesh", "none"):
+                raise ValueError("cv_base must be 'mesh' or 'none'")
+            if cfg.cv_base == "mesh" and cfg.cv_form != "martingale":
+                raise ValueError("the mesh base needs the martingale form")
+            self._mesh_base = cfg.cv_base == "mesh"
+            self.cv = FkCv(init_params, cfg.t_scale, base="grid" if self._mesh_base else "none")
             if cfg.labels == "interface":
                 lab_pts = self.pts
                 self._band_idx = None
+                ij = np.rint(self.pts * self.N).astype(np.int64)
+                self._iface_idx = torch.tensor(ij[:, 1] * (self.N + 1) + ij[:, 0], dtype=torch.int64,
+                                               device=self.dev)
             elif cfg.labels == "band":
                 idx = band_index(cfg.px, cfg.m, cfg.band, cfg.band_stride)
                 lab_pts = np.stack([idx % (self.N + 1), idx // (self.N + 1)], 1) / self.N
@@ -229,7 +244,11 @@ class MeshRun:
             self._lab_count = 0
             p = torch.tensor(lab_pts, dtype=torch.float32, device=self.dev)
             self._lab_pts = p
-            self._add_labels(0.0, p[:, 0], p[:, 1])
+            if self._mesh_base:
+                # the initial mesh does not change before the first step
+                self._add_labels(0.0, torch.zeros_like(p[:, 0]), torch.zeros_like(p[:, 1]))
+            else:
+                self._add_labels(0.0, p[:, 0], p[:, 1])
 
     # -- labels ----------------------------------------------------------------
     def _add_labels(self, t, xi, eta):
@@ -319,9 +338,18 @@ class MeshRun:
             self._se[self.n, 1, it] = out["se_eta"]
         if self.cv is not None:
             if self._band_idx is None:
-                self._add_labels(tn + cfg.dt_mesh, iface_xi, iface_eta)
+                lx, ly = iface_xi, iface_eta
+                if self._mesh_base:
+                    # the interface nodes lie on the grid: the step's change there
+                    lx = lx - self.xi.view(-1)[self._iface_idx]
+                    ly = ly - self.eta.view(-1)[self._iface_idx]
+                self._add_labels(tn + cfg.dt_mesh, lx, ly)
             else:
-                self._add_labels(tn + cfg.dt_mesh, xi_new.view(-1)[self._band_idx], eta_new.view(-1)[self._band_idx])
+                lx, ly = xi_new.view(-1)[self._band_idx], eta_new.view(-1)[self._band_idx]
+                if self._mesh_base:
+                    lx = lx - self.xi.view(-1)[self._band_idx]
+                    ly = ly - self.eta.view(-1)[self._band_idx]
+                self._add_labels(tn + cfg.dt_mesh, lx, ly)
         self.spare = (self.xi, self.eta)
         self.xi, self.eta = xi_new, eta_new
         self.n += 1

@@ -272,6 +272,60 @@ def test_cv_grid_control_against_oracle(fk, oracle_mod, stride):
         assert np.array_equal(h[k].cpu().numpy(), g[k]), k
 
 
+@pytest.mark.parametrize("stride", [2, 20])
+def test_cv_grid_base_against_oracle(fk, oracle_mod, stride):
+    """Martingale form with the network as the deviation from the mesh
+    (u_hat = bilinear grid initial data + network): a deformed mesh under two
+    frozen bumps, one mesh step; the same paths as the oracle's with the same
+    BF16 weights."""
+    import torch
+    n = 48
+    x = np.arange(n + 1) / n
+    X, Y = np.meshgrid(x, x)
+    gx = X + 0.02 * np.sin(np.pi * X) * np.sin(2 * np.pi * Y)
+    gy = Y + 0.015 * np.sin(2 * np.pi * X) * np.sin(np.pi * Y)
+    dens = W.two_bumps(W.TIME_FROZEN, 0.0375)
+    data = W.Data(init_kind=W.DATA_GRID, score_mode=W.SCORE_EXTEND, t_init=0.0375, grid_xi=gx.ravel(),
+                  grid_eta=gy.ravel())
+    nodes = W.interface_nodes(4, 4, 48)
+    pts = np.concatenate([nodes[::7], nodes[np.minimum(nodes, 1 - nodes).min(1) < 0.05][::3]])
+    t, dt, N = 5e-4, 2.5e-5, 2048
+    cv = fk.FkCv(W.mlp_init(7) * 0.2, T, base="grid")
+    _, bf = cv.params()
+    grids = (torch.tensor(gx.ravel(), device="cuda"), torch.tensor(gy.ravel(), device="cuda"))
+    print(f"[gpu] cv grid base stride={stride} nodes={len(pts)} N={N}", flush=True)
+    g = fk.fk_interface_solve_cv(dens, data, pts, t, dt, N, cv, stride=stride, seed=5, level_id=2,
+                                 form=fk.FK_CV_MARTINGALE, exit_step=True, cv_scores=True, grids=grids)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in g.items() if not k.startswith("_")}
+    o = oracle_mod.fk_solve_cv(dens, data, pts, t, dt, N, seed=5, level_id=2, uhat=oracle_mod.UHAT_GRID_MLP, flat=bf,
+                               t_scale=T, stride=stride, form=oracle_mod.CV_MARTINGALE, want_scores=True,
+                               want_exit=True, threads=THREADS)
+    plain = {"xi": g["plain_xi"], "eta": g["plain_eta"], "se_xi": g["plain_se_xi"], "se_eta": g["plain_se_eta"],
+             "exit_step": g["exit_step"]}
+    assert_parity(plain, {"mean": o["plain_mean"], "se": o["plain_se"], "exit_step": o["exit_step"]}, pts,
+                  shifted=False, label="plain part:")
+    same = g["exit_step"] == o["exit_step"]
+    po = oracle_mod.fk_solve(dens, data, pts, t, dt, N, seed=5, level_id=2, want_scores=True,
+                             threads=THREADS)["scores"]
+    msum = np.abs(po - o["cv_scores"])[same]
+    ds = np.abs(g["cv_scores"].astype(np.float64) - o["cv_scores"])[same]
+    rel = ds.max(axis=-1) / np.maximum(msum.max(axis=-1), 1e-3)
+    d = np.abs(np.stack([g["xi"], g["eta"]], 1) - o["mean"])
+    ratio = np.median(o["se"] / o["plain_se"])
+    print(f"grid base: max |score diff| {ds.max():.2e}, max rel {rel.max():.2e}, max |mean diff| {d.max():.2e}, "
+          f"se cv/plain {ratio:.3f}", flush=True)
+    # as for the grid control, a path whose FP32 and FP64 positions sit on
+    # opposite sides of a cell edge takes a different mesh gradient: rare
+    assert np.mean(rel < 0.05) >= 0.999 and ds.max() < 1e-3
+    assert np.all(d <= 3 * o["se"] + 1e-7) and np.all(d <= 1e-5)
+    assert np.all(np.abs(np.stack([g["se_xi"], g["se_eta"]], 1) - o["se"]) <= 0.05 * o["se"] + 1e-9)
+    # the Dynkin form has no grid base
+    with pytest.raises(fk.FkError):
+        fk.fk_interface_solve_cv(dens, data, pts, t, dt, 16, cv, stride=stride, form=fk.FK_CV_DYNKIN, grids=grids)
+    cv.close()
+
+
 def test_identity_base_eval_and_grad(fk):
     """The identity base: every evaluation adds (x, y) and the identity to the
     network's values and gradients, and training fits target - (x, y)."""

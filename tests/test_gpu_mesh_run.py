@@ -75,7 +75,7 @@ def test_cv_mesh_run_against_oracle(fk, oracle_mod, form):
     from paper_1402_0266_amd.mesh_run import MeshRun, MeshRunConfig
     n_paths, stride = 4096, 10
     cfg = MeshRunConfig(px=PX, m=M, n_steps=3, n_paths=n_paths, refit_every=2, cv_stride=stride, train_steps=300,
-                        train_batch=4096, lr=3e-3, cv_form=form)
+                        train_batch=4096, lr=3e-3, cv_form=form, cv_base="mesh" if form == "martingale" else "none")
     run = MeshRun(cfg, init_params=W.mlp_init(0))
     sub = np.arange(0, run.n_nodes, 11)
     for n in range(3):
@@ -88,7 +88,10 @@ def test_cv_mesh_run_against_oracle(fk, oracle_mod, form):
             ctl = dict(uhat=oracle_mod.UHAT_GRID, form=oracle_mod.CV_MARTINGALE)
         else:
             _, bf = run.cv.params()              # the network this step used (refits come first)
-            ctl = dict(uhat=oracle_mod.UHAT_MLP, flat=bf, t_scale=W.CV_T_SCALE,
+            # the martingale run's network fits the mesh's change over a step,
+            # on top of the mesh's own interpolant
+            ctl = dict(uhat=oracle_mod.UHAT_GRID_MLP if form == "martingale" else oracle_mod.UHAT_MLP, flat=bf,
+                       t_scale=W.CV_T_SCALE,
                        form=oracle_mod.CV_MARTINGALE if form == "martingale" else oracle_mod.CV_DYNKIN)
         o = oracle_mod.fk_solve_cv(W.two_bumps(W.TIME_FROZEN, n * D), data, run.pts[sub], D, D / 20, n_paths,
                                    level_id=n, node_ids=sub, stride=stride, want_scores=True, threads=THREADS, **ctl)
@@ -103,7 +106,7 @@ def test_cv_mesh_run_against_oracle(fk, oracle_mod, form):
         # With the mesh's gradient as the control, nodes away from the bumps
         # keep almost no variance (se ~1e-18): the floor there is the FP32
         # rounding of the per-path score records (~3e-8 of values ~1).
-        floor = 1e-7 if form == "grid" else 0.0
+        floor = 1e-7 if form in ("grid", "martingale") else 0.0
         assert np.all(d <= 3 * o["se"] + floor) and np.all(d <= 1e-5 * max(1.0, smax))
         assert np.all(np.abs(se[n, sub] - o["se"]) <= 0.02 * o["se"] + 1e-7)
         assert ratio < (0.1 if form == "grid" else 0.5)   # the control pays off from the first step
@@ -138,12 +141,12 @@ def test_full_size_first_step_against_oracle(fk, oracle_mod):
     dens = W.two_bumps(W.TIME_FROZEN, 0.0)
     data = W.Data(init_kind=W.DATA_GRID, score_mode=W.SCORE_EXTEND, t_init=0.0, grid_xi=xi0, grid_eta=eta0)
     o = oracle_mod.fk_solve_cv(dens, data, run.pts[sub], cfg.dt_mesh, cfg.dt_mesh / cfg.substeps, cfg.n_paths,
-                               node_ids=sub, flat=bf, t_scale=cfg.t_scale, stride=cfg.cv_stride,
-                               form=oracle_mod.CV_MARTINGALE, threads=THREADS)
+                               node_ids=sub, uhat=oracle_mod.UHAT_GRID_MLP, flat=bf, t_scale=cfg.t_scale,
+                               stride=cfg.cv_stride, form=oracle_mod.CV_MARTINGALE, threads=THREADS)
     d = np.abs(iface[0, sub] - o["mean"])
     print(f"interface: max |gpu - oracle| {d.max():.2e}, max d/se {(d / o['se']).max():.2f}, "
           f"se cv/plain {np.median(o['se'] / o['plain_se']):.3f}", flush=True)
-    assert np.all(d <= 3 * o["se"]) and np.all(d <= 1e-5)
+    assert np.all(d <= 3 * o["se"] + 1e-7) and np.all(d <= 1e-5)
     gx, gy = run.mesh()
     sx, sy = S.subdomain_be_step(dens, 0.0, cfg.dt_mesh, cfg.px, cfg.m, xi0, eta0, iface[0, :, 0], iface[0, :, 1])
     assert np.abs(gx - sx).max() < 1e-12 and np.abs(gy - sy).max() < 1e-12
@@ -152,6 +155,72 @@ def test_full_size_first_step_against_oracle(fk, oracle_mod):
     jg, sg = S.mesh_quality(*S.global_be_step(dens, 0.0, cfg.dt_mesh, cfg.px * cfg.m, xi0, eta0))
     print(f"quality: min J {q[0]:.4f} (global step {jg:.4f}), max skew {q[1]:.4f} (global {sg:.4f})", flush=True)
     assert q[0] > 0 and abs(q[0] - jg) <= 0.20 * jg and abs(q[1] - sg) <= 0.02
+    run.close()
+
+
+def test_full_run_learned_control_against_oracle(fk, oracle_mod):
+    """The full time-dependent run as configured (8 x 8 sub-domains on a
+    768-cell grid, two counter-rotating bumps, 200 steps of 5e-4, 2^14 paths,
+    the network control refitted every 20 steps: the mesh's interpolant plus
+    the network fitted to the mesh's change over a step, martingale form),
+    checked at steps 1, 2 and 200 from the mesh the GPU held before each:
+
+    * interface values on every 16th node against the oracle's plain
+      Monte-Carlo estimate on the same counters (4.5 combined standard
+      errors), and on every 97th node against the oracle's control-variate
+      estimate with the network the step used (the full contract);
+    * the step's mesh quality against one global backward-Euler step from the
+      same mesh: min J within 5% at step 200, max skew within 0.02.  The
+      first steps cross the flow's stiff initial layer, where the interface
+      values follow the flow itself (20 sub-steps) and the interiors one
+      backward-Euler step, so the composed map bends next to the interfaces:
+      measured 14% below the global step at step 1 and 7% at step 2 (20% and
+      10% allowed), 3% at step 200;
+    * min J > 0 at every step and >= 0.55 over the run (measured 0.591)."""
+    import time
+    from paper_1402_0266_amd.mesh_run import MeshRun, MeshRunConfig
+    cfg = MeshRunConfig()
+    assert (cfg.px, cfg.m, cfg.n_steps, cfg.n_paths, cfg.refit_every, cfg.cv_form) == (8, 96, 200, 1 << 14, 20,
+                                                                                          "martingale")
+    run = MeshRun(cfg, init_params=W.mlp_init(0))
+    sub, sub_cv = np.arange(0, run.n_nodes, 16), np.arange(0, run.n_nodes, 97)
+    t0 = time.perf_counter()
+    for n in range(cfg.n_steps):
+        check = n in (0, 1, cfg.n_steps - 1)
+        if check:
+            xi_n, eta_n = run.mesh()
+            print(f"[gpu] full run step {n + 1}: {run.n_nodes} nodes x {cfg.n_paths} paths", flush=True)
+        run.step()
+        if not check:
+            continue
+        tn = n * cfg.dt_mesh
+        dens = W.two_bumps(W.TIME_FROZEN, tn)
+        data = W.Data(init_kind=W.DATA_GRID, score_mode=W.SCORE_EXTEND, t_init=tn, grid_xi=xi_n, grid_eta=eta_n)
+        iface, se = run.interface_values()
+        dt = cfg.dt_mesh / cfg.substeps
+        o = oracle_mod.fk_solve(dens, data, run.pts[sub], cfg.dt_mesh, dt, cfg.n_paths, level_id=n, node_ids=sub,
+                                threads=THREADS)
+        d = np.abs(iface[n, sub] - o["mean"])
+        z = d / (se[n, sub] + o["se"])
+        print(f"step {n + 1}: |cv - plain oracle| max {d.max():.2e}, max z {z.max():.2f}; "
+              f"se cv/plain {np.median(se[n, sub] / o['se']):.4f}", flush=True)
+        assert np.all(z <= 4.5)
+        _, bf = run.cv.params()
+        oc = oracle_mod.fk_solve_cv(dens, data, run.pts[sub_cv], cfg.dt_mesh, dt, cfg.n_paths, level_id=n,
+                                    node_ids=sub_cv, uhat=oracle_mod.UHAT_GRID_MLP, flat=bf, t_scale=cfg.t_scale,
+                                    stride=cfg.cv_stride, form=oracle_mod.CV_MARTINGALE, threads=THREADS)
+        dc = np.abs(iface[n, sub_cv] - oc["mean"])
+        assert np.all(dc <= 3 * oc["se"] + 1e-7) and np.all(dc <= 1e-5)
+        q = run.qualities()[n]
+        jg, sg = S.mesh_quality(*S.global_be_step(dens, tn, cfg.dt_mesh, cfg.px * cfg.m, xi_n, eta_n))
+        print(f"step {n + 1}: min J {q[0]:.4f} (global step {jg:.4f}), max skew {q[1]:.4f} (global {sg:.4f})",
+              flush=True)
+        tol = {0: 0.20, 1: 0.10}.get(n, 0.05)
+        assert q[0] > 0 and abs(q[0] - jg) <= tol * jg and abs(q[1] - sg) <= 0.02
+    qs = run.qualities()
+    print(f"run: min J {qs[:, 0].min():.4f}, max skew {qs[:, 1].max():.4f}, {time.perf_counter() - t0:.1f}s",
+          flush=True)
+    assert np.all(qs[:, 0] > 0) and qs[:, 0].min() >= 0.55
     run.close()
 
 
