@@ -404,7 +404,7 @@ int fk_mesh_quality(const double *xi, const double *eta, int32_t n, double *out,
  * row-major) are kept as FP32 master weights with Adam moments; every kernel
  * uses their BF16 rounding ("the network").  Training and evaluation run on
  * BF16 MFMA with FP32 accumulation.  Handles own device memory (freed by
- * fk_cv_destroy); create/get/set synchronise the device.
+ * fk_cv_destroy); create/get/set/destroy synchronise the device.
  */
 typedef struct fk_cv *fk_cv_t;
 #define FK_CV_N_PARAMS 8706
@@ -452,7 +452,12 @@ int fk_cv_grad(fk_cv_t cv, const float *txy, const float *target, int64_t n, flo
 int fk_cv_adam_apply(fk_cv_t cv, const float *grad, float lr, hipStream_t stream);
 /* `steps` Adam steps on minibatches of `batch` samples drawn with
  * Philox4x32-10 (key = seed, counter (j, step, 0, 2)) modulo n; loss_out
- * (device [steps] or NULL) receives each step's minibatch loss. */
+ * (device [steps] or NULL) receives each step's minibatch loss.  The loop
+ * runs as a HIP graph, captured on the first call with this (steps, batch)
+ * and replayed afterwards (the call's arrays and scalars reach the kernels
+ * through a small device record written on the stream first, so the same
+ * graph serves every call).  The arrays must stay unchanged until the stream
+ * passes the call. */
 int fk_cv_train(fk_cv_t cv, const float *txy, const float *target, int64_t n, int32_t steps, int32_t batch, float lr,
                 uint64_t seed, float *loss_out, hipStream_t stream);
 

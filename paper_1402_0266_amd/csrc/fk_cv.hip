@@ -25,6 +25,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <utility>
 #include <vector>
 
@@ -43,7 +44,19 @@ constexpr int kNP = 8706;
 constexpr int OW1 = 0, OB1 = 192, OW2 = 256, OB2 = 4352, OW3 = 4416, OB3 = 8512, OW4 = 8576, OB4 = 8704;
 constexpr int kWS = 68;  // padded LDS row stride (bf16 elements) of W2 / W3
 
+struct TrainDesc;
+
+// A captured training loop: `steps` iterations of (gradient, Adam) for a
+// minibatch of `batch` samples, replayed by fk_cv_train.
+struct TrainGraph {
+    int steps = 0;
+    int64_t batch = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
 struct CvState {
+    TrainDesc *desc = nullptr; // per-call values of fk_cv_train (device)
     float *master = nullptr;   // [kNP] FP32
     float *m = nullptr;        // Adam first moment
     float *v = nullptr;        // Adam second moment
@@ -56,6 +69,8 @@ struct CvState {
 
 struct fk_cv {
     int device = 0;
+    hipStream_t capture_stream = nullptr;     // where training loops are captured (never run on)
+    std::vector<fk::TrainGraph> graphs;       // captured training loops
     float t_scale = 0.1f;
     float base = 0.f;    // 1: u_hat = (x, y) + network (the identity base)
     int grid_base = 0;   // 1: u_hat = bilinear(grid initial data) + network (martingale solves)
@@ -1025,7 +1040,25 @@ struct TrainLds {
     float red[256];
 };
 
+// Per-call values of fk_cv_train, read by the kernels from device memory so
+// that one captured graph of `steps` iterations serves every call with the
+// same step count and minibatch size.
+struct TrainDesc {
+    const float *txy;      // [n][3]
+    const float *target;   // [n][2]
+    int64_t n;
+    int64_t step0;         // Adam steps taken before the call
+    uint32_t key0, key1;   // minibatch Philox key
+    float lr;
+    float loss_scale;      // 1 / (2 batch)
+    float *loss_out;       // [steps] or nullptr
+    float tscale2, base;
+    int64_t pad;
+};
+
 struct TrainArgs {
+    const TrainDesc *desc; // iteration `iter` of fk_cv_train (the fields below from desc), or nullptr
+    uint32_t iter;
     const uint16_t *bf;
     const float *txy;      // [n][3]
     const float *target;   // [n][2]
@@ -1063,7 +1096,18 @@ __device__ __forceinline__ void wave_gemm64(FA A, FB B, FS sink) {
     }
 }
 
-__global__ void __launch_bounds__(256) cv_grad_kernel(const TrainArgs ta) {
+__global__ void __launch_bounds__(256) cv_grad_kernel(TrainArgs ta) {
+    if (ta.desc) {
+        const TrainDesc &d = *ta.desc;
+        ta.txy = d.txy;
+        ta.target = d.target;
+        ta.n = d.n;
+        ta.step = (uint32_t)(d.step0 + ta.iter + 1);
+        ta.key0 = d.key0;
+        ta.key1 = d.key1;
+        ta.tscale2 = d.tscale2;
+        ta.base = d.base;
+    }
     extern __shared__ char smem[];
     TrainLds &S = *reinterpret_cast<TrainLds *>(smem);
     const int tid = threadIdx.x;
@@ -1208,6 +1252,8 @@ __global__ void cv_sum_kernel(const float *partial, int tiles, float *grad, floa
 }
 
 struct AdamArgs {
+    const TrainDesc *desc;  // iteration `iter` of fk_cv_train (lr, c1, c2, loss_out from desc), or nullptr
+    uint32_t iter;
     float *master, *m, *v;
     uint16_t *bf;
     const float *partial;   // per-tile gradients, or nullptr with `grad`
@@ -1218,9 +1264,22 @@ struct AdamArgs {
     float loss_scale;
 };
 
-__global__ void cv_adam_kernel(const AdamArgs A) {
+// Bias corrections of Adam step `step` (>= 1), in FP64 then rounded.
+__device__ __forceinline__ void adam_corrections(int64_t step, float &c1, float &c2) {
+    c1 = (float)(1.0 - pow(0.9, (double)step));
+    c2 = (float)(1.0 - pow(0.999, (double)step));
+}
+
+__global__ void cv_adam_kernel(AdamArgs A) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i > kNP) return;
+    if (A.desc) {
+        const TrainDesc &d = *A.desc;
+        adam_corrections(d.step0 + A.iter + 1, A.c1, A.c2);
+        A.lr = d.lr;
+        A.loss_out = d.loss_out ? d.loss_out + A.iter : nullptr;
+        A.loss_scale = d.loss_scale;
+    }
     float g = 0.f;
     if (A.partial) {
         for (int t = 0; t < A.tiles; ++t) g += A.partial[(int64_t)t * (kNP + 1) + i];
@@ -1245,9 +1304,18 @@ __global__ void cv_to_bf16_kernel(const float *master, uint16_t *bf) {
     if (i < kNP) bf[i] = f2bf(master[i]);
 }
 
+static void drop_graphs(fk_cv *cv) {
+    for (TrainGraph &g : cv->graphs) {
+        if (g.exec) (void)hipGraphExecDestroy(g.exec);
+        if (g.graph) (void)hipGraphDestroy(g.graph);
+    }
+    cv->graphs.clear();
+}
+
 static int ensure_partial(fk_cv *cv, int tiles) {
     if (tiles <= cv->s.cap_tiles) return FK_OK;
-    if (cv->s.partial) hipFree(cv->s.partial);
+    drop_graphs(cv);   // they hold the old buffer's address
+    if (cv->s.partial) (void)hipFree(cv->s.partial);
     cv->s.partial = nullptr;
     cv->s.cap_tiles = 0;
     hipError_t e = hipMalloc(&cv->s.partial, sizeof(float) * (size_t)tiles * (kNP + 1));
@@ -1256,13 +1324,74 @@ static int ensure_partial(fk_cv *cv, int tiles) {
     return FK_OK;
 }
 
+// The gradient kernel's LDS (~105 KB) is above the default dynamic limit:
+// raised once per device, when a network is created there.
+static std::mutex g_attr_mu;
+static bool g_attr_done[64] = {};
+
+static hipError_t grad_kernel_attribute(int dev) {
+    std::lock_guard<std::mutex> lk(g_attr_mu);
+    if (dev >= 0 && dev < 64 && g_attr_done[dev]) return hipSuccess;
+    const hipError_t e = hipFuncSetAttribute((const void *)cv_grad_kernel,
+                                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)sizeof(TrainLds));
+    if (e == hipSuccess && dev >= 0 && dev < 64) g_attr_done[dev] = true;
+    return e;
+}
+
 static hipError_t launch_grad(const TrainArgs &ta, int tiles, hipStream_t s) {
-    const size_t lds = sizeof(TrainLds);
-    hipError_t e = hipFuncSetAttribute((const void *)cv_grad_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(cv_grad_kernel, dim3(tiles), dim3(256), lds, s, ta);
+    hipLaunchKernelGGL(cv_grad_kernel, dim3(tiles), dim3(256), sizeof(TrainLds), s, ta);
     return hipGetLastError();
+}
+
+__global__ void train_desc_kernel(const TrainDesc d, TrainDesc *out) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *out = d;
+}
+
+// Captures `steps` training iterations for minibatches of `batch` samples
+// (on the handle's own stream; nothing runs during capture).
+static int capture_training(fk_cv *cv, int steps, int64_t batch, TrainGraph &g) {
+    const int tiles = (int)((batch + 63) / 64);
+    hipError_t e = hipStreamBeginCapture(cv->capture_stream, hipStreamCaptureModeRelaxed);
+    if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+    hipError_t le = hipSuccess;
+    for (int j = 0; j < steps && le == hipSuccess; ++j) {
+        TrainArgs ta{};
+        ta.desc = cv->s.desc;
+        ta.iter = (uint32_t)j;
+        ta.bf = cv->s.bf;
+        ta.batch = batch;
+        ta.full = 0;
+        ta.partial = cv->s.partial;
+        le = launch_grad(ta, tiles, cv->capture_stream);
+        if (le != hipSuccess) break;
+        AdamArgs A{};
+        A.desc = cv->s.desc;
+        A.iter = (uint32_t)j;
+        A.master = cv->s.master;
+        A.m = cv->s.m;
+        A.v = cv->s.v;
+        A.bf = cv->s.bf;
+        A.partial = cv->s.partial;
+        A.tiles = tiles;
+        hipLaunchKernelGGL(cv_adam_kernel, dim3((kNP + 256) / 256), dim3(256), 0, cv->capture_stream, A);
+        le = hipGetLastError();
+    }
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cv->capture_stream, &graph);
+    if (le != hipSuccess || e != hipSuccess) {
+        if (graph) (void)hipGraphDestroy(graph);
+        return hip_fail(le != hipSuccess ? le : e, "capture of the training loop");
+    }
+    hipGraphExec_t exec = nullptr;
+    if ((e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0)) != hipSuccess) {
+        (void)hipGraphDestroy(graph);
+        return hip_fail(e, "hipGraphInstantiate of the training loop");
+    }
+    g.steps = steps;
+    g.batch = batch;
+    g.graph = graph;
+    g.exec = exec;
+    return FK_OK;
 }
 
 // Launches of the control-variate path kernel.
@@ -1414,8 +1543,18 @@ int fk_cv_create(const float *params, double t_scale, fk_cv_t *out) {
         return fail(FK_E_NODEVICE, "no HIP device: %s", hipGetErrorString(e));
     }
     cv->t_scale = (float)t_scale;
+    if ((e = grad_kernel_attribute(cv->device)) != hipSuccess) {
+        delete cv;
+        return hip_fail(e, "LDS limit of the gradient kernel");
+    }
+    if ((e = hipStreamCreateWithFlags(&cv->capture_stream, hipStreamNonBlocking)) != hipSuccess) {
+        delete cv;
+        return hip_fail(e, "hipStreamCreateWithFlags");
+    }
     float *buf = nullptr;
-    if ((e = hipMalloc(&buf, sizeof(float) * 3 * kNP + sizeof(uint16_t) * kNP + 256)) != hipSuccess) {
+    const size_t state = align256(sizeof(float) * 3 * kNP + sizeof(uint16_t) * kNP);
+    if ((e = hipMalloc(&buf, state + align256(sizeof(TrainDesc)))) != hipSuccess) {
+        (void)hipStreamDestroy(cv->capture_stream);
         delete cv;
         return fail(FK_E_NOMEM, "hipMalloc of network state: %s", hipGetErrorString(e));
     }
@@ -1423,16 +1562,19 @@ int fk_cv_create(const float *params, double t_scale, fk_cv_t *out) {
     cv->s.m = buf + kNP;
     cv->s.v = buf + 2 * kNP;
     cv->s.bf = (uint16_t *)(buf + 3 * kNP);
+    cv->s.desc = (TrainDesc *)((char *)buf + state);
     std::vector<float> zeros(2 * kNP, 0.f);
     if ((e = hipMemcpy(cv->s.master, params, sizeof(float) * kNP, hipMemcpyHostToDevice)) != hipSuccess ||
         (e = hipMemcpy(cv->s.m, zeros.data(), sizeof(float) * 2 * kNP, hipMemcpyHostToDevice)) != hipSuccess) {
-        hipFree(buf);
+        (void)hipFree(buf);
+        (void)hipStreamDestroy(cv->capture_stream);
         delete cv;
         return hip_fail(e, "upload network");
     }
     hipLaunchKernelGGL(cv_to_bf16_kernel, dim3((kNP + 255) / 256), dim3(256), 0, 0, cv->s.master, cv->s.bf);
     if ((e = hipDeviceSynchronize()) != hipSuccess) {
-        hipFree(buf);
+        (void)hipFree(buf);
+        (void)hipStreamDestroy(cv->capture_stream);
         delete cv;
         return hip_fail(e, "convert network");
     }
@@ -1461,6 +1603,9 @@ int fk_cv_set_base(fk_cv_t cv, int32_t base) {
 
 void fk_cv_destroy(fk_cv_t cv) {
     if (!cv) return;
+    (void)hipDeviceSynchronize();   // queued training or solves may still use the handle's memory
+    drop_graphs(cv);
+    if (cv->capture_stream) (void)hipStreamDestroy(cv->capture_stream);
     if (cv->s.master) hipFree(cv->s.master);
     if (cv->s.partial) hipFree(cv->s.partial);
     delete cv;
@@ -1555,41 +1700,37 @@ int fk_cv_train(fk_cv_t cv, const float *txy, const float *target, int64_t n, in
     if (steps < 0 || batch < 1 || batch > (1 << 24)) return fail(FK_E_INVAL, "steps >= 0 and batch in [1, 2^24]");
     if (!(lr > 0.f)) return fail(FK_E_INVAL, "lr must be > 0");
     if (!txy || !target) return fail(FK_E_INVAL, "NULL array");
+    if (steps == 0) return FK_OK;
     const int tiles = (batch + 63) / 64;
     int rc;
     if ((rc = ensure_partial(cv, tiles)) != FK_OK) return rc;
-    for (int s = 0; s < steps; ++s) {
-        TrainArgs ta{};
-        ta.bf = cv->s.bf;
-        ta.txy = txy;
-        ta.target = target;
-        ta.n = n;
-        ta.batch = batch;
-        ta.full = 0;
-        ta.step = (uint32_t)(cv->steps_done + 1);
-        ta.key0 = (uint32_t)seed;
-        ta.key1 = (uint32_t)(seed >> 32);
-        ta.tscale2 = 2.f / cv->t_scale;
-        ta.base = cv->base;
-        ta.partial = cv->s.partial;
-        hipError_t e = launch_grad(ta, tiles, stream);
-        if (e != hipSuccess) return hip_fail(e, "gradient kernel launch");
-        const int64_t step = ++cv->steps_done;
-        AdamArgs A{};
-        A.master = cv->s.master;
-        A.m = cv->s.m;
-        A.v = cv->s.v;
-        A.bf = cv->s.bf;
-        A.partial = cv->s.partial;
-        A.tiles = tiles;
-        A.lr = lr;
-        A.c1 = (float)(1.0 - std::pow(0.9, (double)step));
-        A.c2 = (float)(1.0 - std::pow(0.999, (double)step));
-        A.loss_out = loss_out ? loss_out + s : nullptr;
-        A.loss_scale = 1.f / (2.f * (float)batch);
-        hipLaunchKernelGGL(cv_adam_kernel, dim3((kNP + 256) / 256), dim3(256), 0, stream, A);
-        if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "adam kernel launch");
+    // this call's values for the kernels, in stream order
+    TrainDesc d{};
+    d.txy = txy;
+    d.target = target;
+    d.n = n;
+    d.step0 = cv->steps_done;
+    d.key0 = (uint32_t)seed;
+    d.key1 = (uint32_t)(seed >> 32);
+    d.lr = lr;
+    d.loss_scale = 1.f / (2.f * (float)batch);
+    d.loss_out = loss_out;
+    d.tscale2 = 2.f / cv->t_scale;
+    d.base = cv->base;
+    hipLaunchKernelGGL(train_desc_kernel, dim3(1), dim3(64), 0, stream, d, cv->s.desc);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(e, "training descriptor kernel launch");
+    TrainGraph *g = nullptr;
+    for (TrainGraph &c : cv->graphs)
+        if (c.steps == steps && c.batch == batch) g = &c;
+    if (!g) {
+        TrainGraph ng;
+        if ((rc = capture_training(cv, steps, batch, ng)) != FK_OK) return rc;
+        cv->graphs.push_back(ng);
+        g = &cv->graphs.back();
     }
+    if ((e = hipGraphLaunch(g->exec, stream)) != hipSuccess) return hip_fail(e, "hipGraphLaunch of the training loop");
+    cv->steps_done += steps;
     return FK_OK;
 }
 

@@ -104,6 +104,44 @@ def test_training_reduces_loss(fk):
     cv.close()
 
 
+def test_training_graph_replays_and_matches_step_by_step(fk, oracle_mod):
+    """fk_cv_train runs its loop as a captured graph that reads each call's
+    values from device memory: two calls of 3 steps (the second a replay)
+    give bitwise the weights of one call of 6, and both match a step-by-step
+    reference built from the parity hooks -- the minibatch indices from the
+    oracle's own Philox (counter (j, step, 0, 2) modulo n), the gradient of
+    each minibatch (fk_cv_grad) and one Adam step (fk_cv_adam_apply)."""
+    import torch
+    rng = np.random.default_rng(8)
+    n, batch, seed, lr = 5000, 300, 11, 2e-3
+    txy = np.stack([rng.uniform(0, T, n), rng.uniform(0, 1, n), rng.uniform(0, 1, n)], 1).astype(np.float32)
+    target = np.stack([txy[:, 1] + 0.03 * np.sin(5 * txy[:, 2]), txy[:, 2] - 0.02 * txy[:, 0] / T], 1)
+    tg, tt = cuda32(txy), cuda32(target)
+    a = fk.FkCv(curved_params(5), T)
+    la = [a.train(tg, tt, steps=3, batch=batch, lr=lr, seed=seed) for _ in range(2)]
+    b = fk.FkCv(curved_params(5), T)
+    lb = b.train(tg, tt, steps=6, batch=batch, lr=lr, seed=seed)
+    torch.cuda.synchronize()
+    ma, _ = a.params()
+    mb, _ = b.params()
+    assert np.array_equal(ma, mb)
+    assert np.array_equal(torch.cat(la).cpu().numpy(), lb.cpu().numpy())
+    c = fk.FkCv(curved_params(5), T)
+    for step in range(1, 7):
+        ctr = np.stack([np.arange(batch), np.full(batch, step), np.zeros(batch), np.full(batch, 2)], 1)
+        key = np.tile([seed & 0xffffffff, seed >> 32], (batch, 1))
+        idx = (oracle_mod.philox(ctr, key)[:, 0] % n).astype(np.int64)
+        g, _ = c.grad(cuda32(txy[idx]), cuda32(target[idx]))
+        c.adam_apply(g, lr)
+    torch.cuda.synchronize()
+    mc, _ = c.params()
+    err = np.abs(mc - mb).max() / np.abs(mb).max()
+    print(f"graph-replayed training vs step by step: max rel diff {err:.2e}", flush=True)
+    assert err < 1e-5
+    for h in (a, b, c):
+        h.close()
+
+
 @pytest.mark.parametrize("stride", [2, 6])
 def test_cv_solve_against_oracle(fk, oracle_mod, stride):
     import torch
