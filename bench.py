@@ -167,6 +167,7 @@ def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=409
     torch.cuda.synchronize()
     t_labels = time.perf_counter() - t0
     cv = fk.FkCv(W.mlp_init(0), W.CV_T_SCALE, identity_base=identity_base)
+    pts = torch.tensor(pts, dtype=torch.float64, device="cuda")     # resident coordinates
     t0 = time.perf_counter()
     loss = P.train(cv, txy, target, steps=2000, batch=8192, lr=1e-3, seed=2)
     torch.cuda.synchronize()
@@ -340,6 +341,7 @@ def measure_bridge(fk, wl, pts, fd, pilot_paths=100000):
     import dataclasses
 
     import torch
+    pts = torch.tensor(pts, dtype=torch.float64, device="cuda")     # resident coordinates
     res = []
     for dt, bridge in ((1e-5, True), (4e-5, False), (4e-5, True), (1e-4, False), (1e-4, True)):
         data = dataclasses.replace(wl.data, score_mode=W.SCORE_BRIDGE if bridge else wl.data.score_mode)
@@ -485,8 +487,10 @@ def main():
     dev = torch.device("cuda")
     ws = torch.empty(fk.fk_interface_workspace_bytes(n_nodes, wl.n_paths), dtype=torch.uint8, device=dev)
 
+    dpts = torch.tensor(pts, dtype=torch.float64, device=dev)     # node coordinates stay resident
+
     def solve(n_paths):
-        return fk.fk_interface_solve(wl.density, wl.data, pts, wl.t, wl.dt, n_paths, wl.seed, workspace=ws)
+        return fk.fk_interface_solve(wl.density, wl.data, dpts, wl.t, wl.dt, n_paths, wl.seed, workspace=ws)
 
     # ---- pilot at the configured paths/node: variance, bias, N* ----------------
     n_star = args.paths or wl.n_paths

@@ -41,7 +41,8 @@ extern "C" {
 #endif
 
 #define FK_OK 0
-#define FK_E_INVAL (-1)        /* bad shape, t < 0, dt <= 0, n_paths < 2, node outside the square, NaN */
+#define FK_E_INVAL (-1)        /* bad shape, t < 0, dt <= 0, n_paths < 2, NaN parameter, host node outside
+                                  the square (device nodes are checked by the kernels: NaN results) */
 #define FK_E_NODEVICE (-2)     /* no usable GPU */
 #define FK_E_NOMEM (-3)        /* workspace too small / allocation failed */
 #define FK_E_DEVICE (-4)       /* HIP runtime error (launch failure, fault) */
@@ -176,8 +177,9 @@ size_t fk_interface_workspace_bytes(int64_t n_nodes, int64_t n_paths);
 /*
  * Monte-Carlo interface solve (eqs. (5)-(7); Sect. 4).
  *
- * For node i (0 <= i < n_nodes) at pts[2i], pts[2i+1] (host, FP64, strictly
- * inside the closed unit square) the library runs n_paths Euler-Maruyama
+ * For node i (0 <= i < n_nodes) at pts[2i], pts[2i+1] (device, FP64, in the
+ * closed unit square), and with mask != NULL only where mask[i] != 0, the
+ * library runs n_paths Euler-Maruyama
  * paths over the horizon t with step dt (K = ceil(t/dt) steps, the last one
  * t - (K-1) dt), drawing normals from Philox4x32-10 with key = seed and
  * counter (step/2, path, i, (level_id << 4) | 0), two normals per step from
@@ -191,6 +193,18 @@ size_t fk_interface_workspace_bytes(int64_t n_nodes, int64_t n_paths);
  * this header keeps them within ~1.5); a node with a non-finite or larger
  * score gets NaN outputs.
  *
+ *   pts            device [n_nodes][2] FP64, 8-byte aligned.  The coordinates
+ *                  stay on the device (the node tables are built there, nodes
+ *                  queued in decreasing expected cost), so a caller can solve
+ *                  for node lists it computed on the device without a host
+ *                  synchronisation.  They are checked by the kernels: a node
+ *                  outside the closed square, or with a NaN coordinate, gets
+ *                  NaN means and standard errors (and no paths)
+ *   mask           device [n_nodes] uint8 or NULL: solve only the nodes with
+ *                  mask[i] != 0; the other nodes' outputs (means, standard
+ *                  errors, steps, per-path rows) are left untouched.  Node i
+ *                  keeps its Philox counter word i, so a masked solve gives
+ *                  bitwise the full solve's results at its nodes
  *   xi, eta        device [n_nodes] FP64  sample means
  *   se_xi, se_eta  device [n_nodes] FP64  standard errors sqrt(var/n_paths)
  *   exit_step      device [n_nodes][n_paths] int32 or NULL: step after which
@@ -209,7 +223,7 @@ size_t fk_interface_workspace_bytes(int64_t n_nodes, int64_t n_paths);
  *                  other work until the stream passes this call
  */
 int fk_interface_solve(const fk_density *w, const fk_data *d,
-                       const double *pts, int64_t n_nodes,
+                       const double *pts, const uint8_t *mask, int64_t n_nodes,
                        double t, double dt, int64_t n_paths, uint64_t seed, uint32_t level_id,
                        double *xi, double *eta, double *se_xi, double *se_eta,
                        int32_t *exit_step, float *scores, int64_t *steps, uint64_t *total_steps,
@@ -231,10 +245,11 @@ int fk_interface_solve(const fk_density *w, const fk_data *d,
  * call's contents.
  */
 size_t fk_interface_noalloc_max_bytes(void);
-int fk_interface_solve_noalloc(const fk_density *w, const fk_data *d, const double *pts, int64_t n_nodes, double t,
-                               double dt, int64_t n_paths, uint64_t seed, uint32_t level_id, double *xi,
-                               double *eta, double *se_xi, double *se_eta, int32_t *exit_step, float *scores,
-                               int64_t *steps, uint64_t *total_steps, const fk_plan *plan, hipStream_t stream);
+int fk_interface_solve_noalloc(const fk_density *w, const fk_data *d, const double *pts, const uint8_t *mask,
+                               int64_t n_nodes, double t, double dt, int64_t n_paths, uint64_t seed,
+                               uint32_t level_id, double *xi, double *eta, double *se_xi, double *se_eta,
+                               int32_t *exit_step, float *scores, int64_t *steps, uint64_t *total_steps,
+                               const fk_plan *plan, hipStream_t stream);
 
 /*
  * Batched interface solves: several time levels, each with its own density
@@ -257,8 +272,9 @@ typedef struct fk_level {
 
 typedef struct fk_batch *fk_batch_t;
 
-/* Builds the device tables (cost-ordered nodes, level constants) once;
- * pts is host [n_total][2]; the data's grid pointers must outlive the batch.
+/* Builds the device tables (cost-ordered nodes, level constants) once, on the
+ * host: pts is host [n_total][2] here (checked: FK_E_INVAL for a node outside
+ * the closed square); the data's grid pointers must outlive the batch.
  * Allocates device memory for the tables (freed by fk_batch_destroy). */
 int fk_batch_create(const fk_level *levels, int32_t n_levels, const double *pts, int64_t n_total,
                     const fk_data *d, double dt, int64_t n_paths, uint64_t seed, fk_batch_t *out);
@@ -389,6 +405,20 @@ int fk_interface_interpolate(int32_t px, int32_t m, const int32_t *slot, int64_t
                              double *iface_eta, hipStream_t stream);
 
 /*
+ * The same interpolant in place, for a solve restricted by a mask (the
+ * mask argument of fk_interface_solve): iface_xi / iface_eta (device
+ * [n_iface] FP64, canonical order) hold the key points' values at the nodes
+ * with mask[i] != 0 on entry; the other nodes are overwritten with the
+ * interpolant through those values and the line ends (edge_xi / edge_eta as
+ * above).  Key points are read only, so the call needs no second buffer
+ * and no host copy of the mask.
+ *
+ * FK_E_INVAL for px < 2, m < 2, px m > 65535, NULL arrays.
+ */
+int fk_interface_interpolate_mask(int32_t px, int32_t m, const uint8_t *mask, const double *edge_xi,
+                                  const double *edge_eta, double *iface_xi, double *iface_eta, hipStream_t stream);
+
+/*
  * Mesh quality of a nodal map (xi, eta) on an (n+1)^2 grid: out[0] = minimum
  * over cells of the Jacobian xi_x eta_y - xi_y eta_x, out[1] = maximum of the
  * skewness |grad xi . grad eta| / (|grad xi| |grad eta|), both from
@@ -463,7 +493,8 @@ int fk_cv_train(fk_cv_t cv, const float *txy, const float *target, int64_t n, in
 
 /*
  * Control-variate interface solve: the paths of fk_interface_solve (same
- * counters), each scored with a control variate built from the network u_hat.
+ * counters; pts and mask as there: device coordinates, optional mask), each
+ * scored with a control variate built from the network u_hat.
  * Two forms of one estimator (they agree in continuous time by Ito's formula
  * applied to u_hat along the path; u_hat's time argument runs backward from
  * t_init + t like the density's):
@@ -502,8 +533,9 @@ size_t fk_interface_cv_workspace_bytes(int64_t n_nodes, int64_t n_paths);
  * results.  A workspace of fk_interface_cv_workspace_bytes still works, reading the grids.
  * Returns 0 for n_paths < 2, negative n_nodes or grid_n outside 1..65535. */
 size_t fk_interface_cv_grid_workspace_bytes(int64_t n_nodes, int64_t n_paths, int32_t grid_n);
-int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *pts, int64_t n_nodes, double t,
-                          double dt, int64_t n_paths, uint64_t seed, uint32_t level_id, fk_cv_t cv, int32_t stride,
+int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *pts, const uint8_t *mask,
+                          int64_t n_nodes, double t, double dt, int64_t n_paths, uint64_t seed, uint32_t level_id,
+                          fk_cv_t cv, int32_t stride,
                           int32_t form, double *xi, double *eta, double *se_xi, double *se_eta, double *plain_xi,
                           double *plain_eta, double *plain_se_xi, double *plain_se_eta, int32_t *exit_step,
                           float *cv_scores, uint64_t *total_steps, const fk_plan *plan, void *workspace,

@@ -209,7 +209,8 @@ def fk_paths(dens, data, pts, node_ids, path_ids, t, dt, seed=0, level_id=0, str
 UHAT_MLP, UHAT_LINEAR, UHAT_SIN, UHAT_ZERO, UHAT_GRID, UHAT_MLP_BASE, UHAT_QUAD, UHAT_GRID_MLP = 0, 1, 2, 3, 4, 5, 6, 7
 # GRID: the grid initial data; MLP_BASE: the identity map plus the MLP;
 # QUAD: the test function (tau x^2, tau y^2); GRID_MLP: the grid initial data
-# (bilinear) plus the MLP (martingale form)
+# (bilinear) plus the MLP (martingale form: the mesh's gradient every 2 steps,
+# the network's every `stride` steps)
 CV_DYNKIN, CV_MARTINGALE = 0, 1   # forms of the control-variate estimator
 
 

@@ -853,7 +853,10 @@ static int64_t run_path_cv(const or_problem *pb, const or_uhat *u, int stride, d
  * steps in block j and G_j = grad u_hat at the block's first state, blocks
  * starting every `stride` steps from the path's start and the last one
  * closed at the path's end.  Each G_j is fixed before the increments it
- * multiplies, so the sum has mean zero for the discrete chain itself.
+ * multiplies, so the sum has mean zero for the discrete chain itself.  With
+ * the grid base (u_hat kind 7) blocks start every 2 steps, with G_j the
+ * mesh's gradient there plus the network's gradient taken every `stride`
+ * steps (stride even) and held.
  */
 static int64_t run_path_mg(const or_problem *pb, const or_uhat *u, int stride, double px, double py,
                            uint32_t path, uint32_t node, double plain[2], double cv[2])
@@ -861,6 +864,7 @@ static int64_t run_path_mg(const or_problem *pb, const or_uhat *u, int stride, d
     double x = px, y = py, s = 0.0;
     uint32_t r[4] = {0, 0, 0, 0};
     double G[2][2] = {{0.0, 0.0}, {0.0, 0.0}}, dB[2] = {0.0, 0.0}, M[2] = {0.0, 0.0};
+    double Gn[2][2] = {{0.0, 0.0}, {0.0, 0.0}};   /* grid base: the network's part of G */
     int64_t exit_k = -1;
     for (int64_t k = 0; k < pb->K; ++k) {
         if ((k & 1) == 0) {
@@ -874,7 +878,28 @@ static int64_t run_path_mg(const or_problem *pb, const or_uhat *u, int stride, d
         double tau = (pb->time_mode == 0) ? pb->t_init + pb->t - s : pb->par[6];
         double bx, by;
         drift(&pb->dens, tau, x, y, &bx, &by);
-        if (k % stride == 0) {
+        if (u->kind == 7) {
+            /* grid base: blocks every 2 steps with the mesh's gradient there,
+               plus the network's gradient taken every `stride` steps and held */
+            if (k % 2 == 0) {
+                for (int c = 0; c < 2; ++c) M[c] += G[c][0] * dB[0] + G[c][1] * dB[1];
+                dB[0] = dB[1] = 0.0;
+                if (k % stride == 0) {
+                    double e[2][5];
+                    mlp_forward_mode(&u->mlp, pb->t_init + pb->t - s, x, y, e);
+                    for (int c = 0; c < 2; ++c) {
+                        Gn[c][0] = e[c][1];
+                        Gn[c][1] = e[c][2];
+                    }
+                }
+                const double *g[2] = {u->grid_xi, u->grid_eta};
+                for (int c = 0; c < 2; ++c) {
+                    bilinear_grad(g[c], u->grid_n, x, y, &G[c][0], &G[c][1]);
+                    G[c][0] += Gn[c][0];
+                    G[c][1] += Gn[c][1];
+                }
+            }
+        } else if (k % stride == 0) {
             double e[2][5];
             for (int c = 0; c < 2; ++c) M[c] += G[c][0] * dB[0] + G[c][1] * dB[1];
             dB[0] = dB[1] = 0.0;

@@ -76,7 +76,7 @@ _lib.fk_interface_workspace_bytes.restype = ctypes.c_size_t
 _lib.fk_sync.argtypes = [_P]
 _lib.fk_sync.restype = ctypes.c_int
 _lib.fk_interface_solve.argtypes = [
-    ctypes.POINTER(fk_density), ctypes.POINTER(fk_data), _P, ctypes.c_int64,
+    ctypes.POINTER(fk_density), ctypes.POINTER(fk_data), _P, _P, ctypes.c_int64,
     ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
     _P, _P, _P, _P, _P, _P, _P, _P,
     ctypes.POINTER(fk_plan), _P, ctypes.c_size_t, _P]
@@ -84,7 +84,7 @@ _lib.fk_interface_solve.restype = ctypes.c_int
 _lib.fk_interface_noalloc_max_bytes.argtypes = []
 _lib.fk_interface_noalloc_max_bytes.restype = ctypes.c_size_t
 _lib.fk_interface_solve_noalloc.argtypes = [
-    ctypes.POINTER(fk_density), ctypes.POINTER(fk_data), _P, ctypes.c_int64,
+    ctypes.POINTER(fk_density), ctypes.POINTER(fk_data), _P, _P, ctypes.c_int64,
     ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32,
     _P, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(fk_plan), _P]
 _lib.fk_interface_solve_noalloc.restype = ctypes.c_int
@@ -131,6 +131,8 @@ _lib.fk_key_points.restype = ctypes.c_int
 _lib.fk_interface_interpolate.argtypes = [ctypes.c_int32, ctypes.c_int32, _P, ctypes.c_int64, _P, _P, _P, _P, _P, _P,
                                           _P]
 _lib.fk_interface_interpolate.restype = ctypes.c_int
+_lib.fk_interface_interpolate_mask.argtypes = [ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P]
+_lib.fk_interface_interpolate_mask.restype = ctypes.c_int
 _lib.fk_mesh_quality.argtypes = [_P, _P, ctypes.c_int32, _P, _P]
 _lib.fk_mesh_quality.restype = ctypes.c_int
 _lib.fk_cv_create.argtypes = [_P, ctypes.c_double, ctypes.POINTER(_P)]
@@ -159,7 +161,7 @@ _lib.fk_interface_cv_workspace_bytes.restype = ctypes.c_size_t
 _lib.fk_interface_cv_grid_workspace_bytes.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32]
 _lib.fk_interface_cv_grid_workspace_bytes.restype = ctypes.c_size_t
 _lib.fk_interface_solve_cv.argtypes = [
-    ctypes.POINTER(fk_density), ctypes.POINTER(fk_data), _P, ctypes.c_int64,
+    ctypes.POINTER(fk_density), ctypes.POINTER(fk_data), _P, _P, ctypes.c_int64,
     ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, ctypes.c_uint32, _P, ctypes.c_int32,
     ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, _P, ctypes.POINTER(fk_plan), _P, ctypes.c_size_t, _P]
 _lib.fk_interface_solve_cv.restype = ctypes.c_int
@@ -286,6 +288,23 @@ def fk_interface_interpolate(px, m, slot, key_xi, key_eta, edge_xi, edge_eta, ou
     return out
 
 
+def fk_interface_interpolate_mask(px, m, mask, edge_xi, edge_eta, iface_xi, iface_eta):
+    """In place: the interface nodes with ``mask`` (device uint8 [n_iface])
+    zero get the interpolant through the values at the nonzero ones (already
+    in ``iface_xi`` / ``iface_eta``) and the line ends in the edge nodes of
+    ``edge_xi`` / ``edge_eta``."""
+    import torch
+    n_if = n_interface_nodes(px, m)
+    for name, x, dt in (("mask", mask, torch.uint8), ("iface_xi", iface_xi, torch.float64),
+                        ("iface_eta", iface_eta, torch.float64)):
+        if x.dtype != dt or x.numel() != n_if or not x.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {dt} tensor with one entry per interface node")
+    _check(_lib.fk_interface_interpolate_mask(int(px), int(m), mask.data_ptr(), edge_xi.data_ptr(),
+                                              edge_eta.data_ptr(), iface_xi.data_ptr(), iface_eta.data_ptr(),
+                                              _stream(torch, mask.device)))
+    return iface_xi, iface_eta
+
+
 class GridDensity:
     """A density known only at grid nodes (Sect. 4): device FP64 samples
     ``grid_w`` [(n+1), (n+1)] and their drift table ``grid_b`` (computed here
@@ -309,6 +328,29 @@ def _data(d, grids=None) -> fk_data:
         n = int(round(gx.numel() ** 0.5)) - 1
     return fk_data(int(d.init_kind), int(d.bdry_kind), int(d.score_mode), n, float(d.t_init),
                    None if gx is None else gx.data_ptr(), None if gy is None else gy.data_ptr())
+
+
+def _device_pts(pts, dev):
+    """Node coordinates as a contiguous FP64 [n, 2] device tensor (a device
+    tensor is used as it is; host arrays are copied)."""
+    import torch
+    if isinstance(pts, torch.Tensor):
+        if pts.device.type != "cuda" or pts.dtype != torch.float64 or not pts.is_contiguous():
+            pts = pts.to(device=dev, dtype=torch.float64).contiguous()
+        return pts.reshape(-1, 2)
+    a = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 2)
+    return torch.from_numpy(a).to(dev)
+
+
+def _device_mask(mask, n, dev):
+    if mask is None:
+        return None
+    import torch
+    if not isinstance(mask, torch.Tensor):
+        mask = torch.from_numpy(np.ascontiguousarray(mask, dtype=np.uint8)).to(dev)
+    if mask.dtype != torch.uint8 or mask.numel() != n or not mask.is_contiguous():
+        raise ValueError("mask must be a contiguous uint8 tensor with one entry per node")
+    return mask
 
 
 def _stream(torch, device):
@@ -356,12 +398,15 @@ def fk_sync(stream=None):
 
 def fk_interface_solve(density, data, pts, t, dt, n_paths, seed=0, level_id=0, *,
                        exit_step=False, scores=False, steps=False, plan=None,
-                       device="cuda", workspace=None, grids=None, out=None):
+                       device="cuda", workspace=None, grids=None, out=None, mask=None):
     """Monte-Carlo interface solve (C: ``fk_interface_solve``).
 
     ``density`` / ``data`` are objects with the fields of ``fk_density`` /
     ``fk_data`` (e.g. ``workloads.Density`` / ``workloads.Data``); ``pts`` is
-    an [n, 2] array of node coordinates (host).  ``grids`` = (xi, eta) device
+    an [n, 2] array of node coordinates (a device tensor, or a host array that
+    is copied to the device); ``mask`` (uint8 [n], device or host) restricts
+    the solve to its nonzero nodes and leaves the others' outputs as they
+    were.  ``grids`` = (xi, eta) device
     FP64 tensors for grid initial data.  Returns a dict of device tensors:
     ``xi, eta, se_xi, se_eta`` (FP64 [n]), ``total_steps`` (uint64 [1] as
     int64), and on request ``exit_step`` (int32 [n, N]), ``scores`` (FP32
@@ -369,9 +414,10 @@ def fk_interface_solve(density, data, pts, t, dt, n_paths, seed=0, level_id=0, *
     current stream.
     """
     import torch
-    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 2)
-    n = pts.shape[0]
     dev = torch.device(device)
+    pts = _device_pts(pts, dev)
+    n = pts.shape[0]
+    mask = _device_mask(mask, n, dev)
     if out is None:
         out = {k: torch.empty(n, dtype=torch.float64, device=dev) for k in ("xi", "eta", "se_xi", "se_eta")}
         out["total_steps"] = torch.zeros(1, dtype=torch.int64, device=dev)
@@ -392,12 +438,14 @@ def fk_interface_solve(density, data, pts, t, dt, n_paths, seed=0, level_id=0, *
 
     rc = _lib.fk_interface_solve(
         ctypes.byref(_density(density)), ctypes.byref(_data(data, grids)),
-        pts.ctypes.data_as(ctypes.c_void_p), n, float(t), float(dt), int(n_paths), int(seed), int(level_id),
+        pts.data_ptr() if n else None, None if mask is None else mask.data_ptr(), n, float(t), float(dt),
+        int(n_paths), int(seed), int(level_id),
         ptr("xi"), ptr("eta"), ptr("se_xi"), ptr("se_eta"), ptr("exit_step"), ptr("scores"), ptr("steps"),
         ptr("total_steps"), None if pl is None else ctypes.byref(pl),
         workspace.data_ptr(), workspace.numel(), _stream(torch, dev))
     _check(rc)
     out["_workspace"] = workspace
+    out["_pts"] = pts
     return out
 
 
@@ -406,13 +454,15 @@ def fk_interface_noalloc_max_bytes() -> int:
 
 
 def fk_interface_solve_noalloc(density, data, pts, t, dt, n_paths, seed=0, level_id=0, *, out, plan=None,
-                               device="cuda", grids=None):
+                               device="cuda", grids=None, mask=None):
     """``fk_interface_solve_noalloc``: the interface solve on the library's
     static device scratch (no workspace).  ``out``: dict of caller-allocated
     device tensors -- xi, eta, se_xi, se_eta (FP64 [n]) and optionally
     exit_step, scores, steps, total_steps as in ``fk_interface_solve``."""
     import torch
-    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 2)
+    dev = torch.device(device)
+    pts = _device_pts(pts, dev)
+    mask = _device_mask(mask, pts.shape[0], dev)
     pl = _plan_struct(plan)
 
     def ptr(k):
@@ -421,9 +471,10 @@ def fk_interface_solve_noalloc(density, data, pts, t, dt, n_paths, seed=0, level
 
     rc = _lib.fk_interface_solve_noalloc(
         ctypes.byref(_density(density)), ctypes.byref(_data(data, grids)),
-        pts.ctypes.data_as(ctypes.c_void_p), pts.shape[0], float(t), float(dt), int(n_paths), int(seed),
-        int(level_id), ptr("xi"), ptr("eta"), ptr("se_xi"), ptr("se_eta"), ptr("exit_step"), ptr("scores"),
-        ptr("steps"), ptr("total_steps"), None if pl is None else ctypes.byref(pl), _stream(torch, torch.device(device)))
+        pts.data_ptr() if pts.shape[0] else None, None if mask is None else mask.data_ptr(), pts.shape[0], float(t),
+        float(dt), int(n_paths), int(seed), int(level_id), ptr("xi"), ptr("eta"), ptr("se_xi"), ptr("se_eta"),
+        ptr("exit_step"), ptr("scores"), ptr("steps"), ptr("total_steps"), None if pl is None else ctypes.byref(pl),
+        _stream(torch, dev))
     _check(rc)
     return out
 
@@ -649,7 +700,7 @@ FK_CV_DYNKIN, FK_CV_MARTINGALE, FK_CV_MARTINGALE_GRID = 0, 1, 2
 
 def fk_interface_solve_cv(density, data, pts, t, dt, n_paths, cv, stride=2, seed=0, level_id=0, *,
                           form=FK_CV_DYNKIN, plain=True, exit_step=False, cv_scores=False, plan=None, device="cuda",
-                          workspace=None, grids=None, out=None, grad_table=True):
+                          workspace=None, grids=None, out=None, grad_table=True, mask=None):
     """Control-variate interface solve (C: ``fk_interface_solve_cv``), Dynkin
     or martingale form; returns a dict of device tensors: xi, eta, se_xi,
     se_eta (CV), plain_* (same paths), total_steps, and on request exit_step,
@@ -659,9 +710,10 @@ def fk_interface_solve_cv(density, data, pts, t, dt, n_paths, cv, stride=2, seed
     for the per-cell gradient table (a smaller one is replaced); False keeps
     a given workspace of the plain size, and the kernel reads the grids."""
     import torch
-    pts = np.ascontiguousarray(pts, dtype=np.float64).reshape(-1, 2)
-    n = pts.shape[0]
     dev = torch.device(device)
+    pts = _device_pts(pts, dev)
+    n = pts.shape[0]
+    mask = _device_mask(mask, n, dev)
     keys = ["xi", "eta", "se_xi", "se_eta"] + (["plain_xi", "plain_eta", "plain_se_xi", "plain_se_eta"] if plain else [])
     out = dict(out or {})
     for k in keys:
@@ -670,12 +722,13 @@ def fk_interface_solve_cv(density, data, pts, t, dt, n_paths, cv, stride=2, seed
         elif out[k].numel() != n or out[k].dtype != torch.float64 or not out[k].is_contiguous():
             raise ValueError(f"out[{k!r}] must be a contiguous FP64 tensor of {n} elements")
     out.setdefault("total_steps", torch.zeros(1, dtype=torch.int64, device=dev))
-    if exit_step:
+    if exit_step and "exit_step" not in out:
         out["exit_step"] = torch.empty((n, n_paths), dtype=torch.int32, device=dev)
-    if cv_scores:
+    if cv_scores and "cv_scores" not in out:
         out["cv_scores"] = torch.empty((n, n_paths, 2), dtype=torch.float32, device=dev)
     need = _lib.fk_interface_cv_workspace_bytes(n, n_paths)
-    if form == FK_CV_MARTINGALE_GRID and grids is not None and grad_table:
+    mesh_gradient = form == FK_CV_MARTINGALE_GRID or (cv is not None and getattr(cv, "base", None) == "grid")
+    if mesh_gradient and grids is not None and grad_table:
         grid_n = int(round(grids[0].numel() ** 0.5)) - 1
         need = _lib.fk_interface_cv_grid_workspace_bytes(n, n_paths, grid_n)
     if workspace is None or workspace.numel() < need:
@@ -686,11 +739,13 @@ def fk_interface_solve_cv(density, data, pts, t, dt, n_paths, cv, stride=2, seed
         return None if v is None else v.data_ptr()
 
     _check(_lib.fk_interface_solve_cv(
-        ctypes.byref(_density(density)), ctypes.byref(_data(data, grids)), pts.ctypes.data_as(ctypes.c_void_p), n,
+        ctypes.byref(_density(density)), ctypes.byref(_data(data, grids)), pts.data_ptr() if n else None,
+        None if mask is None else mask.data_ptr(), n,
         float(t), float(dt), int(n_paths), int(seed), int(level_id), None if cv is None else cv.handle, int(stride),
         int(form),
         ptr("xi"), ptr("eta"), ptr("se_xi"), ptr("se_eta"), ptr("plain_xi"), ptr("plain_eta"), ptr("plain_se_xi"),
         ptr("plain_se_eta"), ptr("exit_step"), ptr("cv_scores"), ptr("total_steps"), _plan_struct(plan),
         workspace.data_ptr(), workspace.numel(), _stream(torch, dev)))
     out["_workspace"] = workspace
+    out["_pts"] = pts
     return out

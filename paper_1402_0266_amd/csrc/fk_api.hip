@@ -104,6 +104,14 @@ int validate_horizon(double t, double t_init, double dt, uint32_t level_id) {
     return FK_OK;
 }
 
+int validate_device_points(const double *pts, int64_t n) {
+    if (n < 0) return fail(FK_E_INVAL, "negative node count");
+    if (n > 0 && !pts) return fail(FK_E_INVAL, "pts is NULL");
+    if (n > 0xffffffffLL) return fail(FK_E_INVAL, "too many nodes");
+    if (((uintptr_t)pts & 7u) != 0) return fail(FK_E_INVAL, "pts must be 8-byte aligned");
+    return FK_OK;
+}
+
 int validate_points(const double *pts, int64_t n) {
     if (n < 0) return fail(FK_E_INVAL, "negative node count");
     if (n > 0 && !pts) return fail(FK_E_INVAL, "pts is NULL");
@@ -274,9 +282,18 @@ int enqueue_solve(const SolveLaunch &S, hipStream_t stream, bool allow_timing) {
     if ((rc = check_chunks(S.n_nodes, S.n_paths, S.plan)) != FK_OK) return rc;
     const bool timed = allow_timing && g_timing.enabled;
     hipError_t e;
-    if ((e = launch_zero_u32(S.counters, 64, stream)) != hipSuccess) return hip_fail(e, "zero counters");
+    const int64_t cpn = (S.n_paths + S.plan.chunk - 1) / S.plan.chunk;
+    if ((e = launch_counters_init(S.counters, (uint32_t)(S.n_nodes * cpn), stream)) != hipSuccess)
+        return hip_fail(e, "zero counters");
     if ((e = launch_zero_u32((uint32_t *)S.args.acc, (int)(acc_bytes(S.n_nodes) / 4), stream)) != hipSuccess)
         return hip_fail(e, "zero estimator sums");
+    if (S.tables) {
+        // node tables from the device coordinates (they also set the chunk count)
+        TableArgs t = *S.tables;
+        t.counters = S.counters;
+        t.cpn = (uint32_t)cpn;
+        if ((e = launch_tables(t, stream)) != hipSuccess) return hip_fail(e, "node table kernels");
+    }
     PathArgs a = S.args;
     if (S.total_steps) {
         if ((e = launch_zero_u32((uint32_t *)S.total_steps, 2, stream)) != hipSuccess)
@@ -287,7 +304,6 @@ int enqueue_solve(const SolveLaunch &S, hipStream_t stream, bool allow_timing) {
         a.total_steps = S.first_by_index ? nullptr : (unsigned long long *)(S.counters + 2);
     }
     a.queue = S.counters;
-    const int64_t cpn = (S.n_paths + S.plan.chunk - 1) / S.plan.chunk;
     a.n_paths = (uint32_t)S.n_paths;
     a.chunk = (uint32_t)S.plan.chunk;
     a.cpn = (uint32_t)cpn;
@@ -426,18 +442,18 @@ int fk_sync(hipStream_t stream) {
     return FK_OK;
 }
 
-int fk_interface_solve(const fk_density *w, const fk_data *d, const double *pts, int64_t n_nodes, double t,
-                       double dt, int64_t n_paths, uint64_t seed, uint32_t level_id, double *xi, double *eta,
-                       double *se_xi, double *se_eta, int32_t *exit_step, float *scores, int64_t *steps,
-                       uint64_t *total_steps, const fk_plan *plan, void *workspace, size_t workspace_bytes,
-                       hipStream_t stream) {
+int fk_interface_solve(const fk_density *w, const fk_data *d, const double *pts, const uint8_t *mask,
+                       int64_t n_nodes, double t, double dt, int64_t n_paths, uint64_t seed, uint32_t level_id,
+                       double *xi, double *eta, double *se_xi, double *se_eta, int32_t *exit_step, float *scores,
+                       int64_t *steps, uint64_t *total_steps, const fk_plan *plan, void *workspace,
+                       size_t workspace_bytes, hipStream_t stream) {
     g_last_error.clear();
     int rc;
     if ((rc = validate_density(w)) != FK_OK) return rc;
     if ((rc = validate_data(d)) != FK_OK) return rc;
     if ((rc = validate_common(n_paths, dt)) != FK_OK) return rc;
     if ((rc = validate_horizon(t, d->t_init, dt, level_id)) != FK_OK) return rc;
-    if ((rc = validate_points(pts, n_nodes)) != FK_OK) return rc;
+    if ((rc = validate_device_points(pts, n_nodes)) != FK_OK) return rc;
     if (n_nodes > 0 && (!xi || !eta || !se_xi || !se_eta)) return fail(FK_E_INVAL, "an output pointer is NULL");
     fk_plan pl;
     if ((rc = resolve_plan(plan, &pl)) != FK_OK) return rc;
@@ -448,58 +464,60 @@ int fk_interface_solve(const fk_density *w, const fk_data *d, const double *pts,
     if (((uintptr_t)workspace & 255u) != 0) return fail(FK_E_INVAL, "workspace must be 256-byte aligned");
     if (n_nodes == 0) return FK_OK;
 
-    LevelSpec spec{*w, t, d->t_init, 0, n_nodes, level_id};
-    Tables T;
-    if ((rc = build_tables(&spec, 1, pts, n_nodes, d, dt, T)) != FK_OK) return rc;
-
     char *ws = (char *)workspace;
-    hipError_t e;
-    if ((e = hipMemcpyAsync(ws + lay.levels, T.levels.data(), sizeof(LevelDev) * T.levels.size(),
-                            hipMemcpyHostToDevice, stream)) != hipSuccess)
-        return hip_fail(e, "upload level table");
-    if ((e = hipMemcpyAsync(ws + lay.nodes, T.nodes.data(), sizeof(NodeDev) * T.nodes.size(), hipMemcpyHostToDevice,
-                            stream)) != hipSuccess)
-        return hip_fail(e, "upload node table");
-    if ((e = hipMemcpyAsync(ws + lay.outs, T.outs.data(), sizeof(OutDev) * T.outs.size(), hipMemcpyHostToDevice,
-                            stream)) != hipSuccess)
-        return hip_fail(e, "upload output table");
-
+    const LevelDev level = make_level(w, d->t_init, t, dt, level_id, 0u);
+    const bool shift = (d->init_kind == FK_DATA_IDENTITY && d->bdry_kind == FK_DATA_IDENTITY);
     SolveLaunch S{};
-    S.kind = T.kind;
-    S.time_mode = T.time_mode;
-    S.uniform = T.uniform;
+    S.kind = w->kind;
+    S.time_mode = w->time_mode;
+    S.uniform = (level.dt_last == level.dt && level.cbm_last == level.cbm);
     S.plan = pl;
     // Short paths (a mesh step of a few tens of sub-steps): each wavefront's
     // first chunk by its grid index, and by default 256 paths per grab,
     // which halves the wavefronts' fixed costs per path; long ones 128, for
     // the balance of the tail.
-    S.first_by_index = T.levels[0].K <= 64;
+    S.first_by_index = level.K <= 64;
     if ((!plan || plan->chunk == 0) && S.first_by_index) S.plan.chunk = 256;
     S.n_nodes = n_nodes;
     S.n_paths = n_paths;
     S.counters = (uint32_t *)(ws + lay.counters);
     S.total_steps = total_steps;
-    fill_common_args(S, d, T.shift, seed);
+    fill_common_args(S, d, shift, seed);
     S.args.levels = (const LevelDev *)(ws + lay.levels);
     S.args.nodes = (const NodeDev *)(ws + lay.nodes);
     S.args.acc = (NodeAcc *)(ws + lay.acc);
     S.args.scores = (float2 *)scores;
     S.args.exit_step = exit_step;
+    TableArgs tab{};
+    tab.pts = pts;
+    tab.mask = mask;
+    tab.n = n_nodes;
+    tab.level = level;
+    tab.levels_out = (LevelDev *)(ws + lay.levels);
+    tab.nodes_out = (NodeDev *)(ws + lay.nodes);
+    tab.outs_out = (OutDev *)(ws + lay.outs);
+    tab.acc = S.args.acc;
+    tab.shift = shift ? 1 : 0;
+    tab.sort = S.first_by_index ? 0 : 1;   // every node of a short horizon costs about the same
+    tab.horizon = (float)t;
+    S.tables = &tab;
     S.fin.outs = (const OutDev *)(ws + lay.outs);
     S.fin.xi = xi;
     S.fin.eta = eta;
     S.fin.se_xi = se_xi;
     S.fin.se_eta = se_eta;
     S.fin.steps = steps;
+    S.fin.mask = mask;
     return enqueue_solve(S, stream, true);
 }
 
 size_t fk_interface_noalloc_max_bytes(void) { return kScratchBytes; }
 
-int fk_interface_solve_noalloc(const fk_density *w, const fk_data *d, const double *pts, int64_t n_nodes, double t,
-                               double dt, int64_t n_paths, uint64_t seed, uint32_t level_id, double *xi,
-                               double *eta, double *se_xi, double *se_eta, int32_t *exit_step, float *scores,
-                               int64_t *steps, uint64_t *total_steps, const fk_plan *plan, hipStream_t stream) {
+int fk_interface_solve_noalloc(const fk_density *w, const fk_data *d, const double *pts, const uint8_t *mask,
+                               int64_t n_nodes, double t, double dt, int64_t n_paths, uint64_t seed,
+                               uint32_t level_id, double *xi, double *eta, double *se_xi, double *se_eta,
+                               int32_t *exit_step, float *scores, int64_t *steps, uint64_t *total_steps,
+                               const fk_plan *plan, hipStream_t stream) {
     g_last_error.clear();
     const size_t need = fk_interface_workspace_bytes(n_nodes, n_paths);
     if (need > kScratchBytes)
@@ -509,8 +527,8 @@ int fk_interface_solve_noalloc(const fk_density *w, const fk_data *d, const doub
     void *ws = nullptr;
     int rc;
     if ((rc = scratch_address(&ws)) != FK_OK) return rc;
-    return fk_interface_solve(w, d, pts, n_nodes, t, dt, n_paths, seed, level_id, xi, eta, se_xi, se_eta, exit_step,
-                              scores, steps, total_steps, plan, ws, kScratchBytes, stream);
+    return fk_interface_solve(w, d, pts, mask, n_nodes, t, dt, n_paths, seed, level_id, xi, eta, se_xi, se_eta,
+                              exit_step, scores, steps, total_steps, plan, ws, kScratchBytes, stream);
 }
 
 }  // extern "C"

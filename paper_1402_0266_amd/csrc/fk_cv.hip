@@ -471,7 +471,8 @@ __global__ void __launch_bounds__(256, 2) fk_cv_path_kernel(const PathArgs a, co
     NodeAcc *const accs[1] = {c.acc_cv};
     slots_init<2>(slots, lane);
     uint32_t q_slot = 0, q_next = 0, q_end = 0, q_tag = 0, grabs = 0;
-    bool q_done = !grab_chunk<2>(a, first_chunk(), q_slot, q_next, q_end, slots, accs, q_tag, grabs, lane);
+    const uint32_t total_chunks = launch_chunks(a);
+    bool q_done = !grab_chunk<2>(a, total_chunks, first_chunk(), q_slot, q_next, q_end, slots, accs, q_tag, grabs, lane);
     const uint32_t key0 = a.key0, key1 = a.key1;
     Lane L;
     bool active = false, parked = false, out = false;
@@ -529,7 +530,7 @@ __global__ void __launch_bounds__(256, 2) fk_cv_path_kernel(const PathArgs a, co
             uint64_t need = __ballot(!active && !parked);
             while (need != 0ull && !q_done) {
                 if (q_next >= q_end) {
-                    if (!grab_chunk<2>(a, next_chunk(a), q_slot, q_next, q_end, slots, accs, q_tag, grabs, lane)) {
+                    if (!grab_chunk<2>(a, total_chunks, next_chunk(a), q_slot, q_next, q_end, slots, accs, q_tag, grabs, lane)) {
                         q_done = true;
                         break;
                     }
@@ -682,7 +683,8 @@ __global__ void __launch_bounds__(256, 4) fk_mg_path_kernel(const PathArgs a, co
     NodeAcc *const accs[1] = {c.acc_cv};
     slots_init<2>(slots, lane);
     uint32_t q_slot = 0, q_next = 0, q_end = 0, q_tag = 0, grabs = 0;
-    bool q_done = !grab_chunk<2>(a, first_chunk(), q_slot, q_next, q_end, slots, accs, q_tag, grabs, lane);
+    const uint32_t total_chunks = launch_chunks(a);
+    bool q_done = !grab_chunk<2>(a, total_chunks, first_chunk(), q_slot, q_next, q_end, slots, accs, q_tag, grabs, lane);
     const uint32_t key0 = a.key0, key1 = a.key1;
     Lane L;
     bool active = false;
@@ -729,7 +731,7 @@ __global__ void __launch_bounds__(256, 4) fk_mg_path_kernel(const PathArgs a, co
             uint64_t need = __ballot(!active);
             while (need != 0ull && !q_done) {
                 if (q_next >= q_end) {
-                    if (!grab_chunk<2>(a, next_chunk(a), q_slot, q_next, q_end, slots, accs, q_tag, grabs, lane)) {
+                    if (!grab_chunk<2>(a, total_chunks, next_chunk(a), q_slot, q_next, q_end, slots, accs, q_tag, grabs, lane)) {
                         q_done = true;
                         break;
                     }
@@ -856,7 +858,8 @@ __global__ void __launch_bounds__(256) fk_mgg_path_kernel(const PathArgs a, cons
     NodeAcc *const accs[1] = {c.acc_cv};
     slots_init<2>(slots, lane);
     uint32_t q_slot = 0, q_next = 0, q_end = 0, q_tag = 0, grabs = 0;
-    bool q_done = !grab_chunk<2>(a, first_chunk(), q_slot, q_next, q_end, slots, accs, q_tag, grabs, lane);
+    const uint32_t total_chunks = launch_chunks(a);
+    bool q_done = !grab_chunk<2>(a, total_chunks, first_chunk(), q_slot, q_next, q_end, slots, accs, q_tag, grabs, lane);
     const uint32_t key0 = a.key0, key1 = a.key1;
     Lane L;
     bool active = false;
@@ -875,7 +878,7 @@ __global__ void __launch_bounds__(256) fk_mgg_path_kernel(const PathArgs a, cons
         uint64_t need = __ballot(!active);
         while (need != 0ull && !q_done) {
             if (q_next >= q_end) {
-                if (!grab_chunk<2>(a, next_chunk(a), q_slot, q_next, q_end, slots, accs, q_tag, grabs, lane)) {
+                if (!grab_chunk<2>(a, total_chunks, next_chunk(a), q_slot, q_next, q_end, slots, accs, q_tag, grabs, lane)) {
                     q_done = true;
                     break;
                 }
@@ -977,7 +980,8 @@ __global__ void __launch_bounds__(256) fk_mgg_path_kernel(const PathArgs a, cons
 struct CvNodeArgs {
     const NodeDev *nodes;
     const LevelDev *levels;
-    int64_t n_nodes;
+    int64_t n_nodes;               // bound on the slots
+    const uint32_t *active;        // the slots in use (set by the node-table kernels)
     OutDev *outs_cv;   // shift_x/shift_y <- u_hat(t_init + t, P), or NULL
     float2 *r0;        // integrand at P, or NULL
     float4 *g0;        // gradient of both outputs at P, or NULL
@@ -991,7 +995,7 @@ __global__ void __launch_bounds__(256) cv_node_kernel(const CvNodeArgs na, const
     load_net(N, bf);
     __syncthreads();
     const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool ok = s < na.n_nodes;
+    const bool ok = s < na.n_nodes && s < (int64_t)*na.active;
     Lane L;
     float tend = 0.f;
     if (ok) {
@@ -1744,8 +1748,9 @@ size_t fk_interface_cv_grid_workspace_bytes(int64_t n_nodes, int64_t n_paths, in
     return align256(cv_ws_layout(n_nodes).total) + (size_t)grid_n * grid_n * 2 * sizeof(float4);
 }
 
-int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *pts, int64_t n_nodes, double t,
-                          double dt, int64_t n_paths, uint64_t seed, uint32_t level_id, fk_cv_t cv, int32_t stride,
+int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *pts, const uint8_t *mask,
+                          int64_t n_nodes, double t, double dt, int64_t n_paths, uint64_t seed, uint32_t level_id,
+                          fk_cv_t cv, int32_t stride,
                           int32_t form, double *xi, double *eta, double *se_xi, double *se_eta, double *plain_xi,
                           double *plain_eta, double *plain_se_xi, double *plain_se_eta, int32_t *exit_step,
                           float *cv_scores, uint64_t *total_steps, const fk_plan *plan, void *workspace,
@@ -1760,7 +1765,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         return fail(FK_E_UNSUPPORTED, "the Brownian-bridge exit test is for plain solves only");
     if ((rc = validate_common(n_paths, dt)) != FK_OK) return rc;
     if ((rc = validate_horizon(t, d->t_init, dt, level_id)) != FK_OK) return rc;
-    if ((rc = validate_points(pts, n_nodes)) != FK_OK) return rc;
+    if ((rc = validate_device_points(pts, n_nodes)) != FK_OK) return rc;
     if (stride < 2 || stride % 2 != 0 || stride > (1 << 20)) return fail(FK_E_INVAL, "stride must be even and >= 2");
     if (form != FK_CV_DYNKIN && form != FK_CV_MARTINGALE && form != FK_CV_MARTINGALE_GRID)
         return fail(FK_E_INVAL, "unknown control-variate form");
@@ -1783,37 +1788,50 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     int n_cu = 0;
     if ((rc = device_cus(&n_cu)) != FK_OK) return rc;
 
-    LevelSpec spec{*w, t, d->t_init, 0, n_nodes, level_id};
-    Tables T;
-    if ((rc = build_tables(&spec, 1, pts, n_nodes, d, dt, T)) != FK_OK) return rc;
     char *ws = (char *)workspace;
-    // CV records are absolute: the Dynkin form's shift is u_hat at the node
-    // (the node kernel writes it), the martingale form's is zero
-    std::vector<OutDev> outs_cv = T.outs;
-    for (OutDev &o : outs_cv) o.shift_x = o.shift_y = 0.0;
+    const LevelDev level = make_level(w, d->t_init, t, dt, level_id, 0u);
+    const bool shift = (d->init_kind == FK_DATA_IDENTITY && d->bdry_kind == FK_DATA_IDENTITY);
+    const bool uniform = (level.dt_last == level.dt && level.cbm_last == level.cbm);
     const bool mg = (form != FK_CV_DYNKIN);
+    // network forms on short paths (a mesh step's sub-steps): 256 per grab
+    // by default, as in the plain solve (the network-control mesh step goes
+    // from 29.9 to 22.6 ms on the 768-cell run; the grid control keeps 128)
+    if ((!plan || plan->chunk == 0) && !grid_ctl && level.K <= 64) pl.chunk = 256;
+    const int64_t cpn = (n_paths + pl.chunk - 1) / pl.chunk;
     hipError_t e;
-    if ((e = hipMemcpyAsync(ws + lay.levels, T.levels.data(), sizeof(LevelDev), hipMemcpyHostToDevice, stream)) !=
-            hipSuccess ||
-        (e = hipMemcpyAsync(ws + lay.nodes, T.nodes.data(), sizeof(NodeDev) * T.nodes.size(), hipMemcpyHostToDevice,
-                            stream)) != hipSuccess ||
-        (e = hipMemcpyAsync(ws + lay.outs, T.outs.data(), sizeof(OutDev) * T.outs.size(), hipMemcpyHostToDevice,
-                            stream)) != hipSuccess ||
-        (e = hipMemcpyAsync(ws + lay.outs_cv, outs_cv.data(), sizeof(OutDev) * outs_cv.size(), hipMemcpyHostToDevice,
-                            stream)) != hipSuccess)
-        return hip_fail(e, "upload tables");
     uint32_t *counters = (uint32_t *)(ws + lay.counters);
     if ((e = launch_zero_u32(counters, 64, stream)) != hipSuccess) return hip_fail(e, "zero counters");
-    if ((e = launch_zero_u32((uint32_t *)(ws + lay.acc_cv), (int)(acc_bytes(n_nodes) / 4), stream)) != hipSuccess)
+    // the plain and the CV sums lie back to back
+    if ((e = launch_zero_u32((uint32_t *)(ws + lay.acc), (int)((lay.total - lay.acc) / 4), stream)) != hipSuccess)
         return hip_fail(e, "zero estimator sums");
     if (total_steps && (e = launch_zero_u32((uint32_t *)total_steps, 2, stream)) != hipSuccess)
         return hip_fail(e, "zero total_steps");
+    // node tables from the device coordinates; the CV estimates have zero
+    // shift (the Dynkin form's, u_hat at the node, is written by the node kernel)
+    TableArgs tab{};
+    tab.pts = pts;
+    tab.mask = mask;
+    tab.n = n_nodes;
+    tab.level = level;
+    tab.levels_out = (LevelDev *)(ws + lay.levels);
+    tab.nodes_out = (NodeDev *)(ws + lay.nodes);
+    tab.outs_out = (OutDev *)(ws + lay.outs);
+    tab.outs_zero_out = (OutDev *)(ws + lay.outs_cv);
+    tab.acc = (NodeAcc *)(ws + lay.acc);
+    tab.acc2 = (NodeAcc *)(ws + lay.acc_cv);
+    tab.counters = counters;
+    tab.cpn = (uint32_t)cpn;
+    tab.shift = shift ? 1 : 0;
+    tab.sort = level.K > 64 ? 1 : 0;
+    tab.horizon = (float)t;
+    if ((e = launch_tables(tab, stream)) != hipSuccess) return hip_fail(e, "node table kernels");
 
     // per-node u_hat and integrand at the start
     CvNodeArgs na{};
     na.nodes = (const NodeDev *)(ws + lay.nodes);
     na.levels = (const LevelDev *)(ws + lay.levels);
     na.n_nodes = n_nodes;
+    na.active = counters + kCtrActive;
     na.outs_cv = mg ? nullptr : (OutDev *)(ws + lay.outs_cv);
     na.r0 = mg ? nullptr : (float2 *)(ws + lay.r0);
     na.g0 = mg ? (float4 *)(ws + lay.g0) : nullptr;
@@ -1822,19 +1840,19 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     const float ts2 = grid_ctl ? 0.f : 2.f / cv->t_scale;
     if ((e = timing_record(0, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     if (!grid_ctl &&
-        (e = cv_dispatch<CvNodeF>(T.kind, T.time_mode, true, na, (const uint16_t *)cv->s.bf, ts2, stream)) !=
+        (e = cv_dispatch<CvNodeF>(w->kind, w->time_mode, true, na, (const uint16_t *)cv->s.bf, ts2, stream)) !=
             hipSuccess)
         return hip_fail(e, "node kernel launch");
     // The grid base with a stride of at least the horizon takes the network
     // only at each path's start: that is the node kernel's gradient, and the
     // grid-control kernel adds it to the mesh's at every block (bitwise the
     // same arithmetic as the network kernel, without its evaluation points).
-    const bool base_at_start = grid_base && (int64_t)stride >= (int64_t)T.levels[0].K;
+    const bool base_at_start = grid_base && (int64_t)stride >= (int64_t)level.K;
 
     PathArgs a{};
     SolveLaunch S{};
     S.args = a;
-    fill_common_args(S, d, T.shift, seed);
+    fill_common_args(S, d, shift, seed);
     a = S.args;
     a.levels = (const LevelDev *)(ws + lay.levels);
     a.nodes = (const NodeDev *)(ws + lay.nodes);
@@ -1843,11 +1861,6 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     a.exit_step = exit_step;
     a.queue = counters;
     a.total_steps = total_steps ? (unsigned long long *)total_steps : (unsigned long long *)(counters + 2);
-    // network forms on short paths (a mesh step's sub-steps): 256 per grab
-    // by default, as in the plain solve (the network-control mesh step goes
-    // from 29.9 to 22.6 ms on the 768-cell run; the grid control keeps 128)
-    if ((!plan || plan->chunk == 0) && !grid_ctl && T.levels[0].K <= 64) pl.chunk = 256;
-    const int64_t cpn = (n_paths + pl.chunk - 1) / pl.chunk;
     a.n_paths = (uint32_t)n_paths;
     a.chunk = (uint32_t)pl.chunk;
     a.cpn = (uint32_t)cpn;
@@ -1864,9 +1877,9 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         c.r0 = (const float2 *)(ws + lay.r0);
         c.cv_scores = cv_rec;
         c.acc_cv = acc_cv;
-        const int occ = cv_dispatch<CvOccF>(T.kind, T.time_mode, T.uniform);
+        const int occ = cv_dispatch<CvOccF>(w->kind, w->time_mode, uniform);
         if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
-        if ((e = cv_dispatch<CvLaunchF>(T.kind, T.time_mode, T.uniform, a, c, cap_grid(n_cu * bpc, a.total_chunks, 256), stream)) != hipSuccess)
+        if ((e = cv_dispatch<CvLaunchF>(w->kind, w->time_mode, uniform, a, c, cap_grid(n_cu * bpc, a.total_chunks, 256), stream)) != hipSuccess)
             return hip_fail(e, "control-variate path kernel launch");
     } else if (grid_ctl || base_at_start) {
         MggArgs c{};
@@ -1876,9 +1889,9 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         c.acc_cv = acc_cv;
         c.gtab = grid_table(d, workspace, workspace_bytes, lay.total, stream, &e);
         if (e != hipSuccess) return hip_fail(e, "gradient table kernel launch");
-        const int occ = cv_dispatch<MggOccF>(T.kind, T.time_mode, T.uniform);
+        const int occ = cv_dispatch<MggOccF>(w->kind, w->time_mode, uniform);
         if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
-        if ((e = cv_dispatch<MggLaunchF>(T.kind, T.time_mode, T.uniform, a, c, cap_grid(n_cu * bpc, a.total_chunks, 256), stream)) != hipSuccess)
+        if ((e = cv_dispatch<MggLaunchF>(w->kind, w->time_mode, uniform, a, c, cap_grid(n_cu * bpc, a.total_chunks, 256), stream)) != hipSuccess)
             return hip_fail(e, "control-variate path kernel launch");
     } else {
         MgArgs c{};
@@ -1892,9 +1905,9 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         if (e != hipSuccess) return hip_fail(e, "gradient table kernel launch");
         c.cv_scores = cv_rec;
         c.acc_cv = acc_cv;
-        const int occ = cv_dispatch<MgOccF>(T.kind, T.time_mode, T.uniform);
+        const int occ = cv_dispatch<MgOccF>(w->kind, w->time_mode, uniform);
         if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
-        if ((e = cv_dispatch<MgLaunchF>(T.kind, T.time_mode, T.uniform, a, c, cap_grid(n_cu * bpc, a.total_chunks, 256), stream)) != hipSuccess)
+        if ((e = cv_dispatch<MgLaunchF>(w->kind, w->time_mode, uniform, a, c, cap_grid(n_cu * bpc, a.total_chunks, 256), stream)) != hipSuccess)
             return hip_fail(e, "control-variate path kernel launch");
     }
     if ((e = timing_record(1, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
@@ -1908,6 +1921,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     f.eta = eta;
     f.se_xi = se_xi;
     f.se_eta = se_eta;
+    f.mask = mask;
     if ((e = launch_finalize(f, stream)) != hipSuccess) return hip_fail(e, "finalize kernel launch");
     if ((e = timing_record(2, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     if (plain_xi && plain_eta && plain_se_xi && plain_se_eta) {
@@ -1918,10 +1932,10 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         P.args.acc = (NodeAcc *)(ws + lay.acc);
         P.args.scores = nullptr;
         P.args.exit_step = nullptr;
-        P.kind = T.kind;
-        P.time_mode = T.time_mode;
-        P.uniform = T.uniform;
-        P.first_by_index = T.levels[0].K <= 64;
+        P.kind = w->kind;
+        P.time_mode = w->time_mode;
+        P.uniform = uniform;
+        P.first_by_index = level.K <= 64;
         if ((rc = resolve_plan(nullptr, &P.plan)) != FK_OK) return rc;
         if (P.first_by_index) P.plan.chunk = 256;
         P.n_nodes = n_nodes;
@@ -1933,6 +1947,12 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         P.fin.eta = plain_eta;
         P.fin.se_xi = plain_se_xi;
         P.fin.se_eta = plain_se_eta;
+        P.fin.mask = mask;
+        TableArgs tp = tab;
+        tp.outs_zero_out = nullptr;
+        tp.acc2 = nullptr;
+        tp.sort = P.first_by_index ? 0 : 1;
+        P.tables = &tp;
         if ((rc = enqueue_solve(P, stream, false)) != FK_OK) return rc;
     }
     return FK_OK;

@@ -58,6 +58,14 @@ struct alignas(16) OutDev {
 
 struct NodeAcc;
 
+// The 64 32-bit words of a launch's counters (zeroed before it).
+constexpr int kCtrQueue = 0;     // work-chunk counter
+constexpr int kCtrSteps = 2;     // [2..3] 64-bit step count (when the caller gives no buffer)
+constexpr int kCtrActive = 4;    // nodes in the launch
+constexpr int kCtrTotal = 5;     // work chunks in the launch (the path kernels read it here)
+constexpr int kCtrHist = 16;     // [16..48) per cost bucket: node count, then the bucket's next slot
+constexpr int kCostBuckets = 32;
+
 struct PathArgs {
     const LevelDev *levels;
     const NodeDev *nodes;
@@ -75,7 +83,8 @@ struct PathArgs {
     uint32_t n_paths;                // paths per node
     uint32_t chunk;                  // paths per queue grab
     uint32_t cpn;                    // chunks per node
-    uint32_t total_chunks;
+    uint32_t total_chunks;           // host bound on the work chunks (grid size); the kernels
+                                     // read the launch's own count from queue[kCtrTotal]
 };
 
 // The estimator's last step: node sums -> means, standard errors, steps.
@@ -86,6 +95,28 @@ struct FinalArgs {
     int64_t n_paths;
     double *xi, *eta, *se_xi, *se_eta;
     int64_t *steps;                  // or nullptr
+    const uint8_t *mask;             // nodes solved (others' outputs untouched), or nullptr: all
+};
+
+// Node tables of a single-level solve built on the device from its node
+// coordinates (device memory): the level constants, one NodeDev per node in
+// the solve (in decreasing expected cost when `sort`), one OutDev per node.
+struct TableArgs {
+    const double *pts;       // [n][2] FP64
+    const uint8_t *mask;     // [n]: nodes to solve, or nullptr: all
+    int64_t n;
+    LevelDev level;
+    LevelDev *levels_out;    // [1]
+    NodeDev *nodes_out;      // [n] (the first counters[kCtrActive] used)
+    OutDev *outs_out;        // [n]: shift (FP32 rounding of the node when `shift`), K
+    OutDev *outs_zero_out;   // [n] or nullptr: the same with zero shift (control-variate estimates)
+    NodeAcc *acc;            // [n]: a node outside the closed square (or NaN) is flagged bad
+    NodeAcc *acc2;           // [n] or nullptr: flagged too
+    uint32_t *counters;
+    uint32_t cpn;            // work chunks per node
+    int shift;
+    int sort;
+    float horizon;           // t: caps the expected cost
 };
 
 // ---- host-side planning (fk_api.hip) ---------------------------------------
@@ -117,6 +148,7 @@ struct SolveLaunch {
     int kind, time_mode;
     bool uniform;
     bool first_by_index;  // short horizons: each wavefront's first chunk by its grid index
+    const TableArgs *tables;  // device-built tables (filled in by enqueue_solve), or nullptr: host tables
     fk_plan plan;
     int64_t n_nodes, n_paths;
     uint32_t *counters;  // 256 B of device scratch (queue, step count)
@@ -132,7 +164,9 @@ int validate_density(const fk_density *w);
 int validate_data(const fk_data *d);
 int validate_common(int64_t n_paths, double dt);
 int validate_horizon(double t, double t_init, double dt, uint32_t level_id);
-int validate_points(const double *pts, int64_t n);
+int validate_points(const double *pts, int64_t n);         // host coordinates
+int validate_device_points(const double *pts, int64_t n);  // device coordinates (checked in the kernels)
+LevelDev make_level(const fk_density *w, double t_init, double t, double dt, uint32_t level_id, uint32_t stream);
 int resolve_plan(const fk_plan *plan, fk_plan *out);
 int check_chunks(int64_t n_nodes, int64_t n_paths, const fk_plan &pl);
 // A persistent grid of `grid` blocks cut to no more wavefronts than there
@@ -159,6 +193,10 @@ hipError_t launch_zero_u32(uint32_t *p, int n_words, hipStream_t s);
 hipError_t launch_paths(int kind, int time_mode, bool uniform, bool first_by_index, const PathArgs &a, int grid,
                         int block, hipStream_t s);
 hipError_t launch_finalize(const FinalArgs &a, hipStream_t s);
+// Device node tables (three small kernels; after the counters and sums are zeroed).
+hipError_t launch_tables(const TableArgs &t, hipStream_t s);
+// Zeroes a launch's 64 counter words and sets counters[kCtrTotal] (host tables).
+hipError_t launch_counters_init(uint32_t *counters, uint32_t total_chunks, hipStream_t s);
 // Bytes of the per-node estimator sums of n_out rows.
 size_t acc_bytes(int64_t n_out);
 int path_kernel_max_blocks_per_cu(int kind, int time_mode, bool uniform, bool bridge, bool first_by_index, int block);

@@ -158,7 +158,8 @@ __global__ void __launch_bounds__(kKeyThreads) key_points_kernel(const KeyArgs a
 // ---------------------------------------------------------------------------
 struct InterpArgs {
     int px, m;
-    const int32_t *slot;  // [n_iface]: index into key_xi / key_eta, or -1
+    const int32_t *slot;  // [n_iface]: index into key_xi / key_eta, or -1 (slot form)
+    const uint8_t *mask;  // [n_iface]: key point where nonzero (mask form: values in out_xi / out_eta)
     int64_t n_keys;
     const double *key_xi, *key_eta;
     const double *edge_xi, *edge_eta;  // grids whose edge nodes hold the boundary data
@@ -168,13 +169,16 @@ struct InterpArgs {
 
 __device__ __forceinline__ bool is_knot(const InterpArgs &a, int line, int k) {
     const int N = a.px * a.m;
-    return k == 0 || k == N || a.slot[line_node(a.px, a.m, line, k)] >= 0;
+    if (k == 0 || k == N) return true;
+    const int64_t f = line_node(a.px, a.m, line, k);
+    return a.mask ? a.mask[f] != 0 : a.slot[f] >= 0;
 }
 
 // Value of component c at knot position k (a boundary end or a key point).
 __device__ __forceinline__ double knot_value(const InterpArgs &a, int line, int k, int c) {
     const int N = a.px * a.m;
     if (k == 0 || k == N) return (c == 0 ? a.edge_xi : a.edge_eta)[line_grid(a.px, a.m, line, k)];
+    if (a.mask) return (c == 0 ? a.out_xi : a.out_eta)[line_node(a.px, a.m, line, k)];
     const int32_t s = a.slot[line_node(a.px, a.m, line, k)];
     if (s >= a.n_keys) return NAN;
     return (c == 0 ? a.key_xi : a.key_eta)[s];
@@ -199,8 +203,10 @@ __device__ __forceinline__ double end_slope(double h0, double d0, double h1, dou
 __global__ void interpolate_kernel(const InterpArgs a) {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (f >= a.n_iface) return;
-    const int32_t s = a.slot[f];
-    if (s >= 0) {
+    if (a.mask) {
+        // in place: a key point keeps its value (and is only read by others)
+        if (a.mask[f] != 0) return;
+    } else if (const int32_t s = a.slot[f]; s >= 0) {
         const bool ok = s < a.n_keys;
         a.out_xi[f] = ok ? a.key_xi[s] : NAN;
         a.out_eta[f] = ok ? a.key_eta[s] : NAN;
@@ -286,6 +292,27 @@ int fk_interface_interpolate(int32_t px, int32_t m, const int32_t *slot, int64_t
     a.n_keys = n_keys;
     a.key_xi = key_xi;
     a.key_eta = key_eta;
+    a.edge_xi = edge_xi;
+    a.edge_eta = edge_eta;
+    a.out_xi = iface_xi;
+    a.out_eta = iface_eta;
+    a.n_iface = 2 * (px - 1) * (N - 1) - (int64_t)(px - 1) * (px - 1);
+    hipLaunchKernelGGL(interpolate_kernel, dim3((unsigned)((a.n_iface + 255) / 256)), dim3(256), 0, stream, a);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FK_OK : hip_fail(e, "interface interpolation kernel launch");
+}
+
+int fk_interface_interpolate_mask(int32_t px, int32_t m, const uint8_t *mask, const double *edge_xi,
+                                  const double *edge_eta, double *iface_xi, double *iface_eta, hipStream_t stream) {
+    g_last_error.clear();
+    if (px < 2 || m < 2) return fail(FK_E_INVAL, "need px >= 2 and m >= 2");
+    if ((int64_t)px * m > 65535) return fail(FK_E_INVAL, "grid too large (px m > 65535)");
+    if (!mask || !edge_xi || !edge_eta || !iface_xi || !iface_eta) return fail(FK_E_INVAL, "NULL array");
+    const int64_t N = (int64_t)px * m;
+    InterpArgs a{};
+    a.px = px;
+    a.m = m;
+    a.mask = mask;
     a.edge_xi = edge_xi;
     a.edge_eta = edge_eta;
     a.out_xi = iface_xi;

@@ -30,6 +30,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <utility>
 
 #include "fk_accum.hpp"
@@ -47,6 +48,107 @@ __global__ void zero_u32_kernel(uint32_t *p, int n) {
 hipError_t launch_zero_u32(uint32_t *p, int n_words, hipStream_t s) {
     const int blocks = (n_words + 255) / 256;
     hipLaunchKernelGGL(zero_u32_kernel, dim3(blocks), dim3(256), 0, s, p, n_words);
+    return hipGetLastError();
+}
+
+__global__ void counters_init_kernel(uint32_t *c, uint32_t total_chunks) {
+    const int i = threadIdx.x;
+    if (i < 64) c[i] = (i == kCtrTotal) ? total_chunks : 0u;
+}
+
+hipError_t launch_counters_init(uint32_t *counters, uint32_t total_chunks, hipStream_t s) {
+    hipLaunchKernelGGL(counters_init_kernel, dim3(1), dim3(64), 0, s, counters, total_chunks);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Node tables from device coordinates.  Nodes are queued in decreasing
+// expected cost -- a proxy of the mean exit time, capped by the horizon --
+// bucketed into kCostBuckets classes (the order within a class is that of
+// the atomics: it only changes the schedule, never a result, since every
+// path draws its numbers by its own counters).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ bool node_wanted(const TableArgs &t, int64_t i, double &x, double &y, bool &ok) {
+    x = t.pts[2 * i];
+    y = t.pts[2 * i + 1];
+    ok = (x >= 0.0 && x <= 1.0 && y >= 0.0 && y <= 1.0);   // false for NaN
+    return !t.mask || t.mask[i];
+}
+
+__device__ __forceinline__ int cost_bucket(const TableArgs &t, double x, double y) {
+    if (!t.sort) return 0;
+    const double ax = x * (1.0 - x), ay = y * (1.0 - y);
+    double c = 0.0;
+    if (ax > 0.0 && ay > 0.0) c = fmin((double)t.horizon, 1.0 / (2.0 / ax + 2.0 / ay));
+    const double f = t.horizon > 0.f ? c / (double)t.horizon : 0.0;     // in [0, 1]
+    return min(kCostBuckets - 1, max(0, (int)((1.0 - f) * kCostBuckets)));
+}
+
+__global__ void table_count_kernel(const TableArgs t) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i == 0) *t.levels_out = t.level;
+    if (i >= t.n) return;
+    double x, y;
+    bool ok;
+    const bool want = node_wanted(t, i, x, y, ok);
+    OutDev o{};
+    o.shift_x = t.shift ? (double)(float)x : 0.0;
+    o.shift_y = t.shift ? (double)(float)y : 0.0;
+    o.K = t.level.K;
+    t.outs_out[i] = o;
+    if (t.outs_zero_out) {
+        o.shift_x = o.shift_y = 0.0;
+        t.outs_zero_out[i] = o;
+    }
+    if (!want) return;
+    if (!ok) {
+        // not a node of the square: no paths, NaN results
+        t.acc[i].bad = 1u;
+        if (t.acc2) t.acc2[i].bad = 1u;
+        return;
+    }
+    atomicAdd(&t.counters[kCtrHist + cost_bucket(t, x, y)], 1u);
+}
+
+__global__ void table_scan_kernel(uint32_t *c, uint32_t cpn) {
+    if (threadIdx.x != 0) return;
+    uint32_t run = 0;
+    for (int b = 0; b < kCostBuckets; ++b) {
+        const uint32_t k = c[kCtrHist + b];
+        c[kCtrHist + b] = run;
+        run += k;
+    }
+    c[kCtrActive] = run;
+    c[kCtrTotal] = run * cpn;
+}
+
+__global__ void table_scatter_kernel(const TableArgs t) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= t.n) return;
+    double x, y;
+    bool ok;
+    if (!node_wanted(t, i, x, y, ok) || !ok) return;
+    const uint32_t slot = atomicAdd(&t.counters[kCtrHist + cost_bucket(t, x, y)], 1u);
+    NodeDev nd{};
+    // the start point as an FP32 (hi, lo) pair holding the FP64 node to ~2^-48
+    nd.x = (float)x;
+    nd.y = (float)y;
+    nd.xlo = (float)(x - (double)nd.x);
+    nd.ylo = (float)(y - (double)nd.y);
+    nd.nid = (uint32_t)i;
+    nd.level = 0;
+    nd.out = (uint64_t)i;
+    t.nodes_out[slot] = nd;
+}
+
+hipError_t launch_tables(const TableArgs &t, hipStream_t s) {
+    const unsigned blocks = (unsigned)std::max<int64_t>(1, (t.n + 255) / 256);
+    hipLaunchKernelGGL(table_count_kernel, dim3(blocks), dim3(256), 0, s, t);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(table_scan_kernel, dim3(1), dim3(64), 0, s, t.counters, t.cpn);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    hipLaunchKernelGGL(table_scatter_kernel, dim3(blocks), dim3(256), 0, s, t);
     return hipGetLastError();
 }
 
@@ -69,8 +171,9 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
     // the grab number of the chunk (its accumulation slot).
     uint32_t q_slot = 0, q_next = 0, q_end = 0, q_tag = 0, grabs = 0;
     bool q_done = false;
+    const uint32_t total_chunks = launch_chunks(a);
     if constexpr (FIRST_BY_INDEX) {
-        q_done = !chunk_cursor(a, first_chunk(), q_slot, q_next, q_end);
+        q_done = !chunk_cursor(a, total_chunks, first_chunk(), q_slot, q_next, q_end);
         if (!q_done) {
             q_tag = slot_open<2>(slots, accs, grabs++, (uint32_t)a.nodes[q_slot].out, q_end - q_next, lane);
         }
@@ -95,7 +198,7 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
                 if constexpr (FIRST_BY_INDEX) {
                     // a grid no larger than the chunk count hands out no more
                     // chunks: finish without touching the counter
-                    if (gridDim.x * (blockDim.x >> 6) >= a.total_chunks) {
+                    if (gridDim.x * (blockDim.x >> 6) >= total_chunks) {
                         q_done = true;
                         break;
                     }
@@ -104,7 +207,7 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
                 if (lane == 0) c = atomicAdd(a.queue, 1u);
                 c = __builtin_amdgcn_readfirstlane(c);
                 if constexpr (FIRST_BY_INDEX) c += gridDim.x * (blockDim.x >> 6);
-                if (c >= a.total_chunks) {
+                if (c >= total_chunks) {
                     q_done = true;
                     break;
                 }
@@ -281,6 +384,7 @@ size_t acc_bytes(int64_t n_out) { return sizeof(NodeAcc) * (size_t)(n_out > 0 ? 
 __global__ void __launch_bounds__(256) fk_finalize_kernel(const FinalArgs f) {
     const int64_t o = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (o >= f.n_out) return;
+    if (f.mask && !f.mask[o]) return;
     const NodeAcc &A = f.acc[o];
     const double N = (double)f.n_paths;
     double mean[2], se[2];

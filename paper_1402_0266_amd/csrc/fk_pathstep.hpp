@@ -145,10 +145,15 @@ __device__ __forceinline__ uint32_t next_chunk(const PathArgs &a) {
     if ((threadIdx.x & 63u) == 0) c = atomicAdd(a.queue, 1u);
     return __builtin_amdgcn_readfirstlane(c) + gridDim.x * (blockDim.x >> 6);
 }
+// The launch's work-chunk count (set by the node-table kernels or the host).
+__device__ __forceinline__ uint32_t launch_chunks(const PathArgs &a) {
+    return __builtin_amdgcn_readfirstlane(a.queue[kCtrTotal]);
+}
+
 // The cursor (node slot, path range) of chunk c; false past the last chunk.
-__device__ __forceinline__ bool chunk_cursor(const PathArgs &a, uint32_t c, uint32_t &slot, uint32_t &next,
-                                             uint32_t &end) {
-    if (c >= a.total_chunks) return false;
+__device__ __forceinline__ bool chunk_cursor(const PathArgs &a, uint32_t total, uint32_t c, uint32_t &slot,
+                                             uint32_t &next, uint32_t &end) {
+    if (c >= total) return false;
     slot = c / a.cpn;
     next = (c - slot * a.cpn) * a.chunk;
     end = min(next + a.chunk, a.n_paths);
@@ -158,10 +163,10 @@ __device__ __forceinline__ bool chunk_cursor(const PathArgs &a, uint32_t c, uint
 // chunk_cursor, and on success the chunk's accumulation slot: its tag
 // (wave-uniform; every lane calls this).
 template <int NV>
-__device__ __forceinline__ bool grab_chunk(const PathArgs &a, uint32_t c, uint32_t &slot, uint32_t &next,
-                                           uint32_t &end, AccSlot<NV> *slots, NodeAcc *const *accs, uint32_t &tag,
-                                           uint32_t &grabs, uint32_t lane) {
-    if (!chunk_cursor(a, c, slot, next, end)) return false;
+__device__ __forceinline__ bool grab_chunk(const PathArgs &a, uint32_t total, uint32_t c, uint32_t &slot,
+                                           uint32_t &next, uint32_t &end, AccSlot<NV> *slots, NodeAcc *const *accs,
+                                           uint32_t &tag, uint32_t &grabs, uint32_t lane) {
+    if (!chunk_cursor(a, total, c, slot, next, end)) return false;
     tag = slot_open<NV>(slots, accs, grabs++, (uint32_t)a.nodes[slot].out, end - next, lane);
     return true;
 }

@@ -48,7 +48,7 @@ from dataclasses import dataclass
 import numpy as np
 
 from . import (FK_CV_DYNKIN, FK_CV_MARTINGALE, FK_CV_MARTINGALE_GRID, FkCv, GridDensity, fk_boundary_data,
-               fk_density_sample, fk_interface_interpolate, fk_interface_solve, fk_interface_solve_cv, fk_key_points,
+               fk_density_sample, fk_interface_interpolate_mask, fk_interface_solve, fk_interface_solve_cv, fk_key_points,
                fk_mesh_quality, subdomain_solve, subdomain_workspace_bytes)
 
 DATA_GRID = 3
@@ -188,8 +188,9 @@ class MeshRun:
         self.dev = torch.device(device)
         self.density_fn = density_fn
         self.N = cfg.px * cfg.m
-        self.pts = interface_nodes(cfg.px, cfg.m)
-        self.n_nodes = self.pts.shape[0]
+        self.pts_host = interface_nodes(cfg.px, cfg.m)
+        self.n_nodes = self.pts_host.shape[0]
+        self.pts = torch.tensor(self.pts_host, dtype=torch.float64, device=self.dev)
         x = torch.arange(self.N + 1, dtype=torch.float64, device=self.dev) / self.N
         self.xi = x.repeat(self.N + 1, 1).contiguous()            # [j][i] = x_i
         self.eta = x[:, None].repeat(1, self.N + 1).contiguous()  # [j][i] = y_j
@@ -211,10 +212,9 @@ class MeshRun:
             self._wg = torch.empty((self.N + 1, self.N + 1), dtype=torch.float64, device=self.dev)
         if cfg.density_data == "grid":
             self._wb = torch.empty((self.N + 1, self.N + 1, 2), dtype=torch.float32, device=self.dev)
-        self.n_keys = []
         if cfg.key_points:
             self._mask = torch.empty(self.n_nodes, dtype=torch.uint8, device=self.dev)
-            self._slot = torch.empty(self.n_nodes, dtype=torch.int32, device=self.dev)
+            self._n_keys = torch.zeros(cfg.n_steps, dtype=torch.int64, device=self.dev)
             self._bdry_ws = None
         if cfg.refit_every > 0 and cfg.cv_form != "grid":
             if init_params is None:
@@ -226,9 +226,9 @@ class MeshRun:
             self._mesh_base = cfg.cv_base == "mesh"
             self.cv = FkCv(init_params, cfg.t_scale, base="grid" if self._mesh_base else "none")
             if cfg.labels == "interface":
-                lab_pts = self.pts
+                lab_pts = self.pts_host
                 self._band_idx = None
-                ij = np.rint(self.pts * self.N).astype(np.int64)
+                ij = np.rint(self.pts_host * self.N).astype(np.int64)
                 self._iface_idx = torch.tensor(ij[:, 1] * (self.N + 1) + ij[:, 0], dtype=torch.int64,
                                                device=self.dev)
             elif cfg.labels == "band":
@@ -249,6 +249,14 @@ class MeshRun:
                 self._add_labels(0.0, torch.zeros_like(p[:, 0]), torch.zeros_like(p[:, 1]))
             else:
                 self._add_labels(0.0, p[:, 0], p[:, 1])
+
+    @property
+    def n_keys(self):
+        """Key points simulated in each step taken (a host list; reading it
+        synchronises with the device)."""
+        if not self.cfg.key_points:
+            return []
+        return [int(v) for v in self._n_keys[:self.n].cpu()]
 
     # -- labels ----------------------------------------------------------------
     def _add_labels(self, t, xi, eta):
@@ -285,57 +293,47 @@ class MeshRun:
         if self.cv is not None and self.n % cfg.refit_every == 0:
             self.refit()
         dt = cfg.dt_mesh / cfg.substeps
-        pts, idx = self.pts, None
-        rows = None                 # all nodes simulated: the solve writes the history rows
-        if not cfg.key_points:
-            rows = {"xi": self._iface[self.n, 0], "eta": self._iface[self.n, 1],
-                    "se_xi": self._se[self.n, 0], "se_eta": self._se[self.n, 1]}
+        # the solve writes the history rows in place; with key points it
+        # simulates the masked nodes only (the mask stays on the device: no
+        # host synchronisation in the step)
+        rows = {"xi": self._iface[self.n, 0], "eta": self._iface[self.n, 1],
+                "se_xi": self._se[self.n, 0], "se_eta": self._se[self.n, 1]}
+        mask = None
         if cfg.key_points:
             fk_key_points(self._wg, cfg.px, cfg.m, cfg.key_tol, cfg.key_gap or None, out=self._mask)
-            idx = np.flatnonzero(self._mask.cpu().numpy())           # synchronises: the node list is host input
-            slot = np.full(self.n_nodes, -1, dtype=np.int32)
-            slot[idx] = np.arange(idx.size, dtype=np.int32)
-            self._slot.copy_(self.torch.from_numpy(slot))
-            pts = self.pts[idx]
-            self.n_keys.append(int(idx.size))
+            mask = self._mask
+            self._n_keys[self.n] = mask.sum()
+            # standard errors exist at the key points only
+            self._se[self.n].fill_(float("nan"))
         if cfg.cv_form == "grid":
-            out = fk_interface_solve_cv(dens, data, pts, cfg.dt_mesh, dt, cfg.n_paths, None,
+            out = fk_interface_solve_cv(dens, data, self.pts, cfg.dt_mesh, dt, cfg.n_paths, None,
                                         stride=cfg.cv_stride, seed=cfg.seed, level_id=self.n,
                                         form=FK_CV_MARTINGALE_GRID, plain=False, device=self.dev,
-                                        workspace=self.workspace, grids=grids, out=rows)
+                                        workspace=self.workspace, grids=grids, out=rows, mask=mask)
             self.used_cv[self.n] = True
         elif self.cv is not None:
             form = FK_CV_MARTINGALE if cfg.cv_form == "martingale" else FK_CV_DYNKIN
-            out = fk_interface_solve_cv(dens, data, pts, cfg.dt_mesh, dt, cfg.n_paths, self.cv,
+            out = fk_interface_solve_cv(dens, data, self.pts, cfg.dt_mesh, dt, cfg.n_paths, self.cv,
                                         stride=cfg.cv_stride, seed=cfg.seed, level_id=self.n, form=form,
                                         plain=False, device=self.dev, workspace=self.workspace, grids=grids,
-                                        out=rows)
+                                        out=rows, mask=mask)
             self.used_cv[self.n] = True
         else:
-            out = fk_interface_solve(dens, data, pts, cfg.dt_mesh, dt, cfg.n_paths, seed=cfg.seed,
+            out = fk_interface_solve(dens, data, self.pts, cfg.dt_mesh, dt, cfg.n_paths, seed=cfg.seed,
                                      level_id=self.n, device=self.dev, workspace=self.workspace, grids=grids,
-                                     out=rows)
+                                     out=rows, mask=mask)
         self.workspace = out["_workspace"]
+        iface_xi, iface_eta = out["xi"], out["eta"]
         if cfg.key_points:
             # the line ends: this step's outer boundary data, in the grids the
             # sub-domain solve then fills
             self._bdry_ws = fk_boundary_data(dens, tn, self.N, cfg.bdry, self.spare[0], self.spare[1],
                                              workspace=self._bdry_ws)
-            iface_xi, iface_eta = fk_interface_interpolate(cfg.px, cfg.m, self._slot, out["xi"], out["eta"],
-                                                           self.spare[0], self.spare[1],
-                                                           out=(self._iface[self.n, 0], self._iface[self.n, 1]))
-        else:
-            iface_xi, iface_eta = out["xi"], out["eta"]
+            fk_interface_interpolate_mask(cfg.px, cfg.m, mask, self.spare[0], self.spare[1], iface_xi, iface_eta)
         xi_new, eta_new = subdomain_solve(dens, tn, cfg.dt_mesh, cfg.px, cfg.m, self.xi, self.eta, iface_xi,
                                           iface_eta, bdry_kind=cfg.bdry, out=self.spare,
                                           workspace=self.sub_workspace)
         fk_mesh_quality(xi_new, eta_new, out=self._quality[self.n])
-        if idx is not None:
-            # standard errors exist at the key points only
-            self._se[self.n].fill_(float("nan"))
-            it = self.torch.from_numpy(idx).to(self.dev)
-            self._se[self.n, 0, it] = out["se_xi"]
-            self._se[self.n, 1, it] = out["se_eta"]
         if self.cv is not None:
             if self._band_idx is None:
                 lx, ly = iface_xi, iface_eta

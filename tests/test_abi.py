@@ -23,14 +23,14 @@ def test_version(fk):
 def _call(fk, dens=None, data=None, pts=None, t=0.05, dt=1e-4, n_paths=16, ws_bytes=None, out_ptr=8, plan=None):
     dens = dens or W.static_bump()
     data = data or W.Data()
-    pts = np.ascontiguousarray(pts if pts is not None else [[0.5, 0.5]], dtype=np.float64)
-    n = pts.shape[0]
-    need = fk.fk_interface_workspace_bytes(n, max(n_paths, 2))
+    n = 1 if pts is None else int(pts)
+    need = fk.fk_interface_workspace_bytes(max(n, 0), max(n_paths, 2))
     ws = ws_bytes if ws_bytes is not None else need
     lib = fk.library()
-    # Non-null dummies: every call here must fail validation before any use.
+    # Non-null dummies (the node coordinates are device memory, never read
+    # here): every call must fail validation before any use.
     return lib.fk_interface_solve(ctypes.byref(fk._density(dens)), ctypes.byref(fk._data(data)),
-                                  pts.ctypes.data_as(ctypes.c_void_p), n, t, dt, n_paths, 0, 0,
+                                  4096 if n else None, None, n, t, dt, n_paths, 0, 0,
                                   out_ptr, out_ptr, out_ptr, out_ptr, None, None, None, None,
                                   None if plan is None else ctypes.byref(fk._plan_struct(plan)),
                                   4096, ws, None)
@@ -41,8 +41,7 @@ def _call(fk, dens=None, data=None, pts=None, t=0.05, dt=1e-4, n_paths=16, ws_by
     (dict(dt=0.0), -1),
     (dict(dt=float("nan")), -1),
     (dict(t=-1.0), -1),
-    (dict(pts=[[1.5, 0.5]]), -1),
-    (dict(pts=[[0.5, float("nan")]]), -1),
+    (dict(pts=-1), -1),
     (dict(dens=W.Density(kind=9)), -1),
     (dict(dens=W.Density(kind=W.KIND_RING, amp=10.0, width2=50.0)), -1),   # ring needs beta <= 0
     (dict(dens=W.Density(kind=W.KIND_RING, amp=-1.0, width2=-50.0)), -1),  # and alpha >= 0
@@ -60,7 +59,7 @@ def test_validation_errors(fk, kw, code):
 
 
 def test_empty_solve_is_a_noop(fk):
-    assert _call(fk, pts=np.zeros((0, 2))) == 0
+    assert _call(fk, pts=0) == 0
 
 
 def test_workspace_size(fk):
@@ -179,9 +178,8 @@ def test_noalloc_rejects_sizes_beyond_its_scratch(fk):
     assert cap == 8 << 20
     n = 100_000
     assert fk.fk_interface_workspace_bytes(n, 16) > cap
-    pts = np.full((n, 2), 0.5)
     rc = lib.fk_interface_solve_noalloc(ctypes.byref(fk._density(W.static_bump())), ctypes.byref(fk._data(W.Data())),
-                                        pts.ctypes.data_as(ctypes.c_void_p), n, 0.05, 1e-4, 16, 0, 0,
+                                        4096, None, n, 0.05, 1e-4, 16, 0, 0,
                                         8, 8, 8, 8, None, None, None, None, None, None)
     assert rc == -3
     assert "scratch" in fk.fk_last_error()

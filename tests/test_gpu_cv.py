@@ -308,6 +308,21 @@ def test_cv_grid_control_against_oracle(fk, oracle_mod, stride):
     assert h["_workspace"] is small
     for k in ("xi", "eta", "se_xi", "se_eta", "exit_step"):
         assert np.array_equal(h[k].cpu().numpy(), g[k]), k
+    # a device mask: bitwise the full solve at its nodes, the rest untouched
+    mask = np.arange(len(pts)) % 3 == 1
+    sentinel = {k: torch.full(v.shape, 7, dtype=torch.float64 if v.dtype == np.float64 else
+                              (torch.int32 if v.dtype == np.int32 else torch.float32), device="cuda")
+                for k, v in g.items() if k != "total_steps"}
+    m = fk.fk_interface_solve_cv(dens, data, torch.tensor(pts, device="cuda"), t, dt, N, None, stride=stride,
+                                 seed=5, level_id=2, form=fk.FK_CV_MARTINGALE_GRID, exit_step=True, cv_scores=True,
+                                 grids=grids, out=sentinel, mask=torch.tensor(mask.astype(np.uint8), device="cuda"))
+    torch.cuda.synchronize()
+    for k, v in g.items():
+        if k == "total_steps":
+            continue
+        got = m[k].cpu().numpy()
+        assert np.array_equal(got[mask], v[mask]), k
+        assert np.all(got[~mask] == 7), k
 
 
 @pytest.mark.parametrize("stride", [2, 20])

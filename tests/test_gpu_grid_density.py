@@ -166,9 +166,9 @@ def test_paper_run_with_grid_density_against_oracle(fk, oracle_mod):
         assert np.array_equal(iface[n, :, 0], g["xi"]) and np.array_equal(iface[n, :, 1], g["eta"])
         dens = W.Density(W.KIND_GRID, w_grid=w)
         data = W.Data(init_kind=W.DATA_GRID, score_mode=W.SCORE_EXTEND, t_init=tn, grid_xi=xi_n, grid_eta=eta_n)
-        o = oracle_mod.fk_solve(dens, data, run.pts, D, D / cfg.substeps, cfg.n_paths, level_id=n, want_exit=True,
+        o = oracle_mod.fk_solve(dens, data, run.pts_host, D, D / cfg.substeps, cfg.n_paths, level_id=n, want_exit=True,
                                 want_scores=True, threads=THREADS)
-        assert_parity({k: v for k, v in g.items() if k != "steps"}, o, run.pts, shifted=False, label=f"step {n}:")
+        assert_parity({k: v for k, v in g.items() if k != "steps"}, o, run.pts_host, shifted=False, label=f"step {n}:")
         sx, sy = S.subdomain_be_step(dens, tn, D, cfg.px, cfg.m, xi_n, eta_n, iface[n, :, 0], iface[n, :, 1],
                                      bdry="equidistributed")
         gx, gy = run.mesh()

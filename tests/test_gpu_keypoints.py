@@ -69,6 +69,15 @@ def test_interpolation_against_oracle(fk, oracle_mod, dens, tau, px, m, tol, gap
     o = K.interpolate_interface(px, m, mask, keys, ex, ey)
     g = np.stack([gx.cpu().numpy(), gy.cpu().numpy()], 1)
     assert np.abs(g - o).max() < 1e-13
+    # the in-place form on the mask: key values in their nodes' rows, the
+    # rest garbage that must be overwritten; bitwise the slot form's result
+    ix = np.full(mask.size, 1e300)
+    iy = np.full(mask.size, -1e300)
+    ix[mask], iy[mask] = keys[:, 0], keys[:, 1]
+    ix, iy = cuda(ix), cuda(iy)
+    fk.fk_interface_interpolate_mask(px, m, cuda(mask, torch.uint8), cuda(ex), cuda(ey), ix, iy)
+    torch.cuda.synchronize()
+    assert np.array_equal(ix.cpu().numpy(), g[:, 0]) and np.array_equal(iy.cpu().numpy(), g[:, 1])
 
 
 @pytest.mark.parametrize("dens,t_w,n,bdry", [
@@ -120,8 +129,10 @@ def test_paper_run_with_key_points_against_oracle(fk, oracle_mod, density_data):
         ring = W.paper_ring(W.TIME_FROZEN, tn)
         dens = ring if density_data == "analytic" else W.Density(W.KIND_GRID, w_grid=w)
         data = W.Data(init_kind=W.DATA_GRID, score_mode=W.SCORE_EXTEND, t_init=tn, grid_xi=xi_n, grid_eta=eta_n)
-        pts = run.pts[mask]
-        o = oracle_mod.fk_solve(dens, data, pts, D, D / cfg.substeps, cfg.n_paths, level_id=n, threads=THREADS)
+        pts = run.pts_host[mask]
+        # a masked solve keeps each node's own random stream (its index)
+        o = oracle_mod.fk_solve(dens, data, pts, D, D / cfg.substeps, cfg.n_paths, level_id=n,
+                                node_ids=np.flatnonzero(mask), threads=THREADS)
         d = np.abs(iface[n][mask] - o["mean"])
         c = (0.5 + 0.25 * math.cos(2 * math.pi * tn), 0.5 + 0.25 * math.sin(2 * math.pi * tn))
         on_ring = np.abs((pts[:, 0] - c[0]) ** 2 + (pts[:, 1] - c[1]) ** 2 - 0.01) < 1e-6

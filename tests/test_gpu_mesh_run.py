@@ -53,7 +53,7 @@ def test_plain_mesh_run_against_oracle(fk, oracle_mod):
     n_paths = 1 << 16
     run = MeshRun(MeshRunConfig(px=PX, m=M, n_steps=3, n_paths=n_paths, refit_every=0))
     sub = np.arange(0, run.n_nodes, 9)
-    assert np.array_equal(run.pts, MS.interface_points(PX, M))
+    assert np.array_equal(run.pts_host, MS.interface_points(PX, M))
     for n in range(3):
         xi_n, eta_n = run.mesh()
         print(f"[gpu] mesh run plain step {n}, {run.n_nodes} nodes, N={n_paths}", flush=True)
@@ -93,7 +93,7 @@ def test_cv_mesh_run_against_oracle(fk, oracle_mod, form):
             ctl = dict(uhat=oracle_mod.UHAT_GRID_MLP if form == "martingale" else oracle_mod.UHAT_MLP, flat=bf,
                        t_scale=W.CV_T_SCALE,
                        form=oracle_mod.CV_MARTINGALE if form == "martingale" else oracle_mod.CV_DYNKIN)
-        o = oracle_mod.fk_solve_cv(W.two_bumps(W.TIME_FROZEN, n * D), data, run.pts[sub], D, D / 20, n_paths,
+        o = oracle_mod.fk_solve_cv(W.two_bumps(W.TIME_FROZEN, n * D), data, run.pts_host[sub], D, D / 20, n_paths,
                                    level_id=n, node_ids=sub, stride=stride, want_scores=True, threads=THREADS, **ctl)
         iface, se = run.interface_values()
         # Dynkin-form scores g - u_hat(end) + sum r ds carry the network's
@@ -140,7 +140,7 @@ def test_full_size_first_step_against_oracle(fk, oracle_mod):
     sub = np.arange(0, run.n_nodes, 97)
     dens = W.two_bumps(W.TIME_FROZEN, 0.0)
     data = W.Data(init_kind=W.DATA_GRID, score_mode=W.SCORE_EXTEND, t_init=0.0, grid_xi=xi0, grid_eta=eta0)
-    o = oracle_mod.fk_solve_cv(dens, data, run.pts[sub], cfg.dt_mesh, cfg.dt_mesh / cfg.substeps, cfg.n_paths,
+    o = oracle_mod.fk_solve_cv(dens, data, run.pts_host[sub], cfg.dt_mesh, cfg.dt_mesh / cfg.substeps, cfg.n_paths,
                                node_ids=sub, uhat=oracle_mod.UHAT_GRID_MLP, flat=bf, t_scale=cfg.t_scale,
                                stride=cfg.cv_stride, form=oracle_mod.CV_MARTINGALE, threads=THREADS)
     d = np.abs(iface[0, sub] - o["mean"])
@@ -198,7 +198,7 @@ def test_full_run_learned_control_against_oracle(fk, oracle_mod):
         data = W.Data(init_kind=W.DATA_GRID, score_mode=W.SCORE_EXTEND, t_init=tn, grid_xi=xi_n, grid_eta=eta_n)
         iface, se = run.interface_values()
         dt = cfg.dt_mesh / cfg.substeps
-        o = oracle_mod.fk_solve(dens, data, run.pts[sub], cfg.dt_mesh, dt, cfg.n_paths, level_id=n, node_ids=sub,
+        o = oracle_mod.fk_solve(dens, data, run.pts_host[sub], cfg.dt_mesh, dt, cfg.n_paths, level_id=n, node_ids=sub,
                                 threads=THREADS)
         d = np.abs(iface[n, sub] - o["mean"])
         z = d / (se[n, sub] + o["se"])
@@ -206,7 +206,7 @@ def test_full_run_learned_control_against_oracle(fk, oracle_mod):
               f"se cv/plain {np.median(se[n, sub] / o['se']):.4f}", flush=True)
         assert np.all(z <= 4.5)
         _, bf = run.cv.params()
-        oc = oracle_mod.fk_solve_cv(dens, data, run.pts[sub_cv], cfg.dt_mesh, dt, cfg.n_paths, level_id=n,
+        oc = oracle_mod.fk_solve_cv(dens, data, run.pts_host[sub_cv], cfg.dt_mesh, dt, cfg.n_paths, level_id=n,
                                     node_ids=sub_cv, uhat=oracle_mod.UHAT_GRID_MLP, flat=bf, t_scale=cfg.t_scale,
                                     stride=cfg.cv_stride, form=oracle_mod.CV_MARTINGALE, threads=THREADS)
         dc = np.abs(iface[n, sub_cv] - oc["mean"])
@@ -257,16 +257,16 @@ def test_paper_ring_run_against_oracle(fk, oracle_mod):
         assert np.array_equal(iface[n, :, 0], g["xi"]) and np.array_equal(iface[n, :, 1], g["eta"])
         dens = W.paper_ring(W.TIME_FROZEN, tn)
         data = W.Data(init_kind=W.DATA_GRID, score_mode=W.SCORE_EXTEND, t_init=tn, grid_xi=xi_n, grid_eta=eta_n)
-        o = oracle_mod.fk_solve(dens, data, run.pts, D, D / cfg.substeps, cfg.n_paths, level_id=n, want_exit=True,
+        o = oracle_mod.fk_solve(dens, data, run.pts_host, D, D / cfg.substeps, cfg.n_paths, level_id=n, want_exit=True,
                                 want_scores=True, threads=THREADS)
         c = (0.5 + 0.25 * math.cos(2 * math.pi * tn), 0.5 + 0.25 * math.sin(2 * math.pi * tn))
-        on_ring = np.abs((run.pts[:, 0] - c[0]) ** 2 + (run.pts[:, 1] - c[1]) ** 2 - 0.01) < 1e-6
+        on_ring = np.abs((run.pts_host[:, 0] - c[0]) ** 2 + (run.pts_host[:, 1] - c[1]) ** 2 - 0.01) < 1e-6
         d = np.abs(np.stack([g["xi"], g["eta"]], 1) - o["mean"])
         assert np.all(d[on_ring] <= 3 * o["se"][on_ring])
         keep = ~on_ring
         sub = {k: (v[keep] if k != "total_steps" else v) for k, v in g.items() if k != "steps"}
         assert_parity(sub, {k: v[keep] for k, v in o.items() if k in ("mean", "se", "exit_step", "scores")},
-                      run.pts[keep], shifted=False, label=f"step {n} ({int(on_ring.sum())} nodes on the ring):")
+                      run.pts_host[keep], shifted=False, label=f"step {n} ({int(on_ring.sum())} nodes on the ring):")
         sx, sy = S.subdomain_be_step(dens, tn, D, cfg.px, cfg.m, xi_n, eta_n, iface[n, :, 0], iface[n, :, 1],
                                      bdry="equidistributed")
         gx, gy = run.mesh()

@@ -213,6 +213,51 @@ def test_in_kernel_estimator_equals_two_pass_fp64(fk, torch_cuda):
             assert np.array_equal(only[k].cpu().numpy(), g[k]), k
 
 
+def test_device_nodes_and_mask(fk, torch_cuda, oracle_mod):
+    """Node coordinates on the device and a device mask: a masked solve gives
+    bitwise the full solve's results at its nodes (each node keeps its own
+    random stream) and leaves the other nodes' outputs alone; a node outside
+    the square or with a NaN coordinate gets NaN results without disturbing
+    the others."""
+    torch = torch_cuda
+    wl = W.MOVING_BUMP_1521
+    pts = wl.nodes()[::7]
+    n, N = pts.shape[0], 700
+    full = fk.fk_interface_solve(wl.density, wl.data, pts, 0.01, 1e-4, N, 3, 2, exit_step=True, scores=True,
+                                 steps=True)
+    dpts = torch.tensor(pts, device="cuda")
+    again = fk.fk_interface_solve(wl.density, wl.data, dpts, 0.01, 1e-4, N, 3, 2, exit_step=True, scores=True,
+                                  steps=True)
+    rng = np.random.default_rng(11)
+    mask = rng.random(n) < 0.3
+    mask[0] = True
+    sentinel = {k: torch.full_like(v, 7) for k, v in full.items() if not k.startswith("_") and k != "total_steps"}
+    sentinel["total_steps"] = torch.zeros(1, dtype=torch.int64, device="cuda")
+    print(f"[gpu] masked solve: {int(mask.sum())} of {n} nodes", flush=True)
+    part = fk.fk_interface_solve(wl.density, wl.data, dpts, 0.01, 1e-4, N, 3, 2, exit_step=True, scores=True,
+                                 steps=True, out=sentinel, mask=torch.tensor(mask.astype(np.uint8), device="cuda"))
+    torch.cuda.synchronize()
+    f = {k: v.cpu().numpy() for k, v in full.items() if not k.startswith("_")}
+    for k in ("xi", "eta", "se_xi", "se_eta", "exit_step", "scores", "steps"):
+        assert np.array_equal(again[k].cpu().numpy(), f[k]), k
+        got = part[k].cpu().numpy()
+        assert np.array_equal(got[mask], f[k][mask]), k
+        assert np.all(got[~mask] == 7), k
+    assert int(part["total_steps"][0]) == int(f["steps"][mask].sum())
+    # bad nodes appended: NaN there, the others bitwise as before
+    bad = np.vstack([pts, [[1.5, 0.5], [0.5, np.nan], [-1e-9, 0.2]]])
+    g = run_gpu(fk, torch, wl.density, wl.data, bad, 0.01, 1e-4, N, 3, 2)
+    for k in ("xi", "eta", "se_xi", "se_eta"):
+        assert np.all(np.isnan(g[k][n:])), k
+        assert np.array_equal(g[k][:n], f[k]), k
+    assert np.array_equal(g["steps"][n:], [0, 0, 0])
+    # the oracle on the masked nodes with their own ids
+    idx = np.flatnonzero(mask)
+    o = oracle_mod.fk_solve(wl.density, wl.data, pts[idx], 0.01, 1e-4, N, 3, 2, node_ids=idx, want_exit=True,
+                            want_scores=True, threads=THREADS)
+    assert_parity({k: v[mask] for k, v in f.items() if k != "total_steps"}, o, pts[idx])
+
+
 def oracle_steps(t, dt):
     return int(math.ceil(t / dt - 1e-9))
 

@@ -24,10 +24,10 @@ def _outputs(torch, n, n_paths):
 
 
 def _call_noalloc(fk, torch, dens, data, pts, t, dt, n_paths, seed, level_id, o):
-    pts = np.ascontiguousarray(pts, dtype=np.float64)
+    pts = torch.as_tensor(np.ascontiguousarray(pts, dtype=np.float64), device="cuda")
     stream = ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
     rc = fk.library().fk_interface_solve_noalloc(
-        ctypes.byref(fk._density(dens)), ctypes.byref(fk._data(data)), pts.ctypes.data_as(ctypes.c_void_p),
+        ctypes.byref(fk._density(dens)), ctypes.byref(fk._data(data)), pts.data_ptr(), None,
         pts.shape[0], t, dt, n_paths, seed, level_id, o["xi"].data_ptr(), o["eta"].data_ptr(),
         o["se_xi"].data_ptr(), o["se_eta"].data_ptr(), o["exit_step"].data_ptr(), o["scores"].data_ptr(),
         o["steps"].data_ptr(), o["total_steps"].data_ptr(), None, stream)
