@@ -174,9 +174,11 @@ def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=409
     t_train = time.perf_counter() - t0
     loss = loss.cpu().numpy()
 
-    def solve(n_paths, form, stride):
+    def solve(n_paths, form, stride, plain=True):
+        # plain=False: the control-variate estimates only (the plain estimate
+        # on the same paths is a diagnostic and costs a second pass)
         return fk.fk_interface_solve_cv(wl.density, wl.data, pts, wl.t, wl.dt, n_paths, cv, stride=stride,
-                                        seed=wl.seed, form=form)
+                                        seed=wl.seed, form=form, plain=plain)
 
     def pilot(form, stride):
         torch.cuda.synchronize()
@@ -201,13 +203,13 @@ def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=409
     form, stride, n_star = fk.FK_CV_MARTINGALE, best["stride"], max(2, best["n_star"])
     print(f"[bench] cv: martingale stride {stride}, N* = {n_star}", file=sys.stderr, flush=True)
     for _ in range(warmup):
-        solve(n_star, form, stride)
+        solve(n_star, form, stride, plain=False)
     torch.cuda.synchronize()
     fk.fk_timing_enable(True)
     kern = []
     t0 = time.perf_counter()
     for _ in range(steps):
-        r = solve(n_star, form, stride)
+        r = solve(n_star, form, stride, plain=False)
         kern.append(fk.fk_timing_last()[0])
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
@@ -242,7 +244,8 @@ def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=409
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         rl = fk.fk_interface_solve_cv(wl.density, gdata, pts, wl.t, wl.dt, max(2, n_lin), None, stride=1 << 20,
-                                      seed=wl.seed, form=fk.FK_CV_MARTINGALE_GRID, grids=(gx.view(-1), gy.view(-1)))
+                                      seed=wl.seed, form=fk.FK_CV_MARTINGALE_GRID, grids=(gx.view(-1), gy.view(-1)),
+                                      plain=False)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         linear.update({"paths_per_node": max(2, n_lin), "s_per_solve": el, "nodes_per_s": n_nodes / el,

@@ -536,7 +536,7 @@ __global__ void __launch_bounds__(256) subdomain_lu_kernel(const SubArgs a) {
     double2 pr2;
     double pcn;
     load_batch(0, pc4, pr2, pcn);
-    double cE_Rm1 = (P1 - 1 < n) ? cf[P1 - 1].x : 0.0;   // east coefficient of row R - 1
+    const double cE_first = (P1 - 1 < n) ? cf[P1 - 1].x : 0.0;   // east coefficient of row P1 - 1
 
     int owner = 0;
     for (int k = 0; k < steps; ++k) {
@@ -599,7 +599,11 @@ __global__ void __launch_bounds__(256) subdomain_lu_kernel(const SubArgs a) {
             } else if (is_col) {
                 if (slot == owner) {
                     col = R;
-                    v[H - 2] = live ? cE_Rm1 : 0.0;                        // row R - 1
+                    // row R - 1: the east coefficient of the row that entered
+                    // one step earlier (staged in the previous step's slot)
+                    const int kp = k - 1;
+                    const double cE = k == 0 ? cE_first : Cst[(kp / kB) & 1][kp % kB].x;
+                    v[H - 2] = live ? cE : 0.0;
                     v[H - 1] = live ? diag : 1.0;                          // row R
                 } else {
                     const double4 cR = Cst[bb][j];
@@ -609,7 +613,6 @@ __global__ void __launch_bounds__(256) subdomain_lu_kernel(const SubArgs a) {
                 v[H - 1] = rhs_c == 0 ? Rst[bb][j].x : Rst[bb][j].y;
             }
         }
-        cE_Rm1 = Cst[bb][j].x;
         owner = (owner + 1 == P1) ? 0 : owner + 1;
     }
     __syncthreads();
