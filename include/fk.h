@@ -305,33 +305,46 @@ int fk_batch_replay(fk_batch_t b, hipStream_t stream);
 void fk_batch_destroy(fk_batch_t b);
 
 /*
- * Deterministic sub-domain solves (Sect. 4): the unit square is split into
- * px x px sub-domains of m x m cells on the nodal grid x = i/N, y = j/N,
- * N = px m.  With the interface values as Dirichlet data, every sub-domain
- * takes one backward-Euler step of length dt_mesh of the relaxed Winslow
- * system (Sect. 2, eq. (3)), central differences, density frozen at t_w:
+ * Deterministic sub-domain solves (Sect. 4): the unit square's nodal grid
+ * x = i/N, y = j/N is split into px x py sub-domains of mx x my cells
+ * (mx = N/px, my = N/py; px and py divide N, mx, my >= 2).  With the
+ * interface values as Dirichlet data, every sub-domain takes one
+ * backward-Euler step of length dt_mesh of the relaxed Winslow system (Sect.
+ * 2, eq. (3)), central differences, density frozen at t_w:
  *   (u - u^n)/dt_mesh = Laplacian_h u + b . grad_h u,  b = -grad w / w.
  * dt_mesh = +INFINITY solves the steady (elliptic) system of eq. (2),
  * Laplacian_h u + b . grad_h u = 0; xi_n / eta_n are then not read (may be
  * NULL).
- * Each sub-domain system is solved by banded LU without pivoting, in FP64;
- * xi and eta share the factorisation.  Requires |b| h / 2 < 1 (checked from
- * the density's bound; FK_E_UNSUPPORTED otherwise) and m - 1 < 128.  A grid
- * density (FK_DENSITY_GRID) must be sampled on this mesh's grid
- * (grid_n == N, else FK_E_INVAL): its FP64 finite-difference drift is taken
- * at the nodes, the equidistributed edge data integrates w as linear between
- * the nodes, and |b| h / 2 = |w[i+1] - w[i-1]| / (4 w[i]) < 1 is the
- * caller's to ensure (the samples stay in device memory).
+ * Each sub-domain system is solved by banded LU without pivoting, in FP64
+ * (unknowns numbered along the shorter side first, so the half-bandwidth is
+ * min(mx, my) - 1); xi and eta share the factorisation.  Requires
+ * |b| h / 2 < 1 (checked from the density's bound; FK_E_UNSUPPORTED
+ * otherwise) and min(mx, my) <= 128 (FK_E_UNSUPPORTED).  A grid density
+ * (FK_DENSITY_GRID) must be sampled on this mesh's grid (grid_n == N, else
+ * FK_E_INVAL): its FP64 finite-difference drift is taken at the nodes, the
+ * equidistributed edge data integrates w as linear between the nodes, and
+ * |b| h / 2 = |w[i+1] - w[i-1]| / (4 w[i]) < 1 is the caller's to ensure (the
+ * samples stay in device memory).
  *   xi_n, eta_n        device [(N+1)^2] FP64, row-major [j][i]: the mesh at t^n
- *   iface_xi/eta       device FP64, interface nodes in canonical order
- *                      (vertical lines x = a/px with y = j/N ascending, then
- *                      horizontal lines without their crossings)
+ *   iface_xi/eta       device FP64 [(px-1)(N-1) + (py-1)(N-px)], interface
+ *                      nodes in canonical order (vertical lines x = a/px with
+ *                      y = j/N ascending, then horizontal lines y = c/py with
+ *                      x = i/N ascending, without their crossings)
  *   bdry_kind          FK_DATA_IDENTITY (xi = x, eta = y), FK_DATA_ZERO or
  *                      FK_DATA_EQUIDISTRIBUTED (at t_w) on the outer boundary
  *   xi_out, eta_out    device [(N+1)^2] FP64: the new mesh (boundary, interface
  *                      and sub-domain interiors); must not alias xi_n / eta_n
- *   workspace          device, subdomain_workspace_bytes(px, m) bytes, 256-B aligned
+ *   workspace          device, subdomain_workspace_bytes_rect(px, py, N)
+ *                      bytes, 256-B aligned (0 for an unsupported layout)
+ * FK_E_INVAL for px, py < 1, N outside [2, 65535], px or py not dividing N,
+ * sub-domains under 2 cells a side, NULL arrays.
  */
+size_t subdomain_workspace_bytes_rect(int32_t px, int32_t py, int32_t n_cells);
+int subdomain_solve_rect(const fk_density *w, double t_w, double dt_mesh, int32_t px, int32_t py, int32_t n_cells,
+                         int32_t bdry_kind, const double *xi_n, const double *eta_n, const double *iface_xi,
+                         const double *iface_eta, double *xi_out, double *eta_out, void *workspace,
+                         size_t workspace_bytes, hipStream_t stream);
+/* The square layout: px x px sub-domains of m x m cells, N = px m. */
 size_t subdomain_workspace_bytes(int32_t px, int32_t m);
 int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px, int32_t m, int32_t bdry_kind,
                     const double *xi_n, const double *eta_n, const double *iface_xi, const double *iface_eta,

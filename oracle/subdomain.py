@@ -15,8 +15,10 @@ with b = -grad w / w (eq. (6)) at the node, w held at one time t_w over the
 step (Sect. 4 freezes the density over a mesh step), on the uniform nodal
 grid x = i/N, y = j/N.  Outer boundary data: the identity (xi = x, eta = y),
 zero, or the paper's equidistributed edges (Sect. 3).  ``global_be_step`` solves the whole grid; ``subdomain_be_step``
-solves each of px x px sub-domains (m cells a side, N = px m) with the
-interface nodes as Dirichlet data.  Both use scipy.sparse LU (splu).
+solves each of px x px sub-domains (m cells a side, N = px m), and
+``subdomain_be_step_rect`` each of px x py sub-domains of (N/px) x (N/py)
+cells, with the interface nodes as Dirichlet data.  All use scipy.sparse
+LU (splu).
 
 Grids are [(N+1), (N+1)] arrays indexed [j, i].
 """
@@ -131,38 +133,52 @@ def global_be_step(dens, t_w, D, N, xi_n, eta_n, bdry="identity"):
     return xi, eta
 
 
-def interface_index(px, m):
-    """Grid indices (i, j) of the interface nodes in canonical order (vertical
-    lines, then horizontal lines without the crossings), for N = px m."""
-    N = px * m
+def interface_index_rect(px, py, N):
+    """Grid indices (i, j) of the interface nodes of a px x py split of the
+    N-cell grid in canonical order: vertical lines x = a/px (y ascending),
+    then horizontal lines y = c/py (x ascending) without the crossings."""
+    mx, my = N // px, N // py
     out = []
     for a in range(1, px):
         for j in range(1, N):
-            out.append((a * m, j))
-    for c in range(1, px):
+            out.append((a * mx, j))
+    for c in range(1, py):
         for i in range(1, N):
-            if i % m == 0:
+            if i % mx == 0:
                 continue
-            out.append((i, c * m))
+            out.append((i, c * my))
     return np.array(out, dtype=np.int64).reshape(-1, 2)
 
 
-def subdomain_be_step(dens, t_w, D, px, m, xi_n, eta_n, iface_xi, iface_eta, bdry="identity"):
-    """Backward-Euler step on each of px x px sub-domains with the interface
-    values (canonical order) as Dirichlet data; returns the assembled grids."""
-    N = px * m
+def interface_index(px, m):
+    """The same for px x px sub-domains of m cells a side (N = px m)."""
+    return interface_index_rect(px, px, px * m)
+
+
+def subdomain_be_step_rect(dens, t_w, D, px, py, N, xi_n, eta_n, iface_xi, iface_eta, bdry="identity"):
+    """Backward-Euler step on each of px x py sub-domains of (N/px) x (N/py)
+    cells with the interface values (canonical order) as Dirichlet data;
+    returns the assembled grids."""
+    assert N % px == 0 and N % py == 0
+    mx, my = N // px, N // py
     h = 1.0 / N
     bx, by = _drift_grid(dens, t_w, N)
     xi, eta = boundary_grid(N, bdry, dens, t_w)
-    ij = interface_index(px, m)
-    xi[ij[:, 1], ij[:, 0]] = iface_xi
-    eta[ij[:, 1], ij[:, 0]] = iface_eta
-    for sj in range(px):
+    ij = interface_index_rect(px, py, N)
+    if len(ij):
+        xi[ij[:, 1], ij[:, 0]] = iface_xi
+        eta[ij[:, 1], ij[:, 0]] = iface_eta
+    for sj in range(py):
         for si in range(px):
-            i0, i1, j0, j1 = si * m, (si + 1) * m, sj * m, (sj + 1) * m
+            i0, i1, j0, j1 = si * mx, (si + 1) * mx, sj * my, (sj + 1) * my
             sx, sy = _be_solve_region(bx, by, D, h, i0, i1, j0, j1, [xi_n, eta_n], [xi, eta])
             xi[j0 + 1:j1, i0 + 1:i1], eta[j0 + 1:j1, i0 + 1:i1] = sx, sy
     return xi, eta
+
+
+def subdomain_be_step(dens, t_w, D, px, m, xi_n, eta_n, iface_xi, iface_eta, bdry="identity"):
+    """Backward-Euler step on each of px x px sub-domains (m cells a side)."""
+    return subdomain_be_step_rect(dens, t_w, D, px, px, px * m, xi_n, eta_n, iface_xi, iface_eta, bdry)
 
 
 def mesh_quality(xi, eta):

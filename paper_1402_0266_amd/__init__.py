@@ -117,6 +117,12 @@ _lib.subdomain_workspace_bytes.restype = ctypes.c_size_t
 _lib.subdomain_solve.argtypes = [ctypes.POINTER(fk_density), ctypes.c_double, ctypes.c_double, ctypes.c_int32,
                                  ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]
 _lib.subdomain_solve.restype = ctypes.c_int
+_lib.subdomain_workspace_bytes_rect.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]
+_lib.subdomain_workspace_bytes_rect.restype = ctypes.c_size_t
+_lib.subdomain_solve_rect.argtypes = [ctypes.POINTER(fk_density), ctypes.c_double, ctypes.c_double, ctypes.c_int32,
+                                      ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _P, _P, _P, _P, _P, _P, _P,
+                                      ctypes.c_size_t, _P]
+_lib.subdomain_solve_rect.restype = ctypes.c_int
 _lib.fk_density_sample.argtypes = [ctypes.POINTER(fk_density), ctypes.c_double, ctypes.c_int32, _P, _P]
 _lib.fk_density_sample.restype = ctypes.c_int
 _lib.fk_density_grid_drift.argtypes = [_P, ctypes.c_int32, _P, _P]
@@ -600,6 +606,37 @@ def subdomain_solve(density, t_w, dt_mesh, px, m, xi_n, eta_n, iface_xi, iface_e
                                 None if eta_n is None else eta_n.data_ptr(), iface_xi.data_ptr(),
                                 iface_eta.data_ptr(), out[0].data_ptr(), out[1].data_ptr(), workspace.data_ptr(),
                                 workspace.numel(), _stream(torch, dev)))
+    return out
+
+
+def subdomain_workspace_bytes_rect(px: int, py: int, n_cells: int) -> int:
+    return int(_lib.subdomain_workspace_bytes_rect(px, py, n_cells))
+
+
+def n_interface_nodes_rect(px: int, py: int, n_cells: int) -> int:
+    """Interface nodes of a px x py split of an n-cell grid (canonical order:
+    vertical lines, then horizontal lines without the crossings)."""
+    return (px - 1) * (n_cells - 1) + (py - 1) * (n_cells - px)
+
+
+def subdomain_solve_rect(density, t_w, dt_mesh, px, py, n_cells, xi_n, eta_n, iface_xi, iface_eta, bdry_kind=0,
+                         out=None, workspace=None):
+    """``subdomain_solve_rect``: px x py sub-domains of (n/px) x (n/py) cells
+    of an n-cell grid; otherwise as ``subdomain_solve``."""
+    import torch
+    dev = iface_xi.device
+    N1 = int(n_cells) + 1
+    if out is None:
+        out = (torch.empty((N1, N1), dtype=torch.float64, device=dev),
+               torch.empty((N1, N1), dtype=torch.float64, device=dev))
+    need = _lib.subdomain_workspace_bytes_rect(px, py, n_cells)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    _check(_lib.subdomain_solve_rect(ctypes.byref(_density(density)), float(t_w), float(dt_mesh), int(px), int(py),
+                                     int(n_cells), int(bdry_kind), None if xi_n is None else xi_n.data_ptr(),
+                                     None if eta_n is None else eta_n.data_ptr(), iface_xi.data_ptr(),
+                                     iface_eta.data_ptr(), out[0].data_ptr(), out[1].data_ptr(), workspace.data_ptr(),
+                                     workspace.numel(), _stream(torch, dev)))
     return out
 
 

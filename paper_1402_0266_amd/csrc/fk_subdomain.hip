@@ -9,17 +9,17 @@
 // and the system is solved by LU factorisation without pivoting (strictly
 // diagonally dominant while |b| h / 2 < 1).  Plus the mesh-quality reduction.
 //
-// MI355X mapping: one workgroup per sub-domain.  With the q x q interior
-// unknowns in row-major order the matrix is banded with half-bandwidth
-// p = q, and the fill of the LU stays in the band; elimination step k only
-// touches rows and columns k..k+p, and the new row and column that enter
-// the (p+1)^2 window carry their original stencil values (at most five
-// non-zeros).  Both right-hand sides (xi and eta) are eliminated with the
-// same multipliers.  For the sub-domain sizes it is built for, the window
-// lives in registers, one column per thread (subdomain_lu_kernel); other
-// sizes keep it in LDS, indexed circularly (subdomain_be_kernel).  Finished U
-// rows go to the workspace; one wavefront then back-substitutes, prefetching
-// the next U row while it reduces the current one.
+// MI355X mapping: the unit square's N x N grid is split into px x py
+// sub-domains of mx x my cells.  A sub-domain's interior unknowns are
+// numbered along the shorter side first (the fast index), so its matrix is
+// banded with half-bandwidth q = the number of unknowns on that side, and
+// the fill of the LU stays in the band.  Large sub-domains are eliminated
+// from both ends at once (twisted: two workgroups meet at a separator line,
+// whose dense system one workgroup then solves).  The elimination window
+// lives in registers: one wavefront, a column per lane, for q < 32
+// (subdomain_lu_wave_kernel); otherwise 256 lanes as a 16 x 16 grid of
+// register tiles (subdomain_lu_tile_kernel).  Finished U rows go to the
+// workspace, and one wavefront per end back-substitutes.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -38,7 +38,10 @@ struct SubArgs {
     double *ybuf;                // per sub-domain: 2 n doubles
     double *cbuf;                // per sub-domain: 4 n doubles, (E, W, N, S) coefficients of each row
     double *rbuf;                // per sub-domain: 2 n doubles, right-hand sides (xi, eta) of each row
-    int N, m, px;
+    int N;                       // grid cells a side
+    int px, py, mx, my;          // px x py sub-domains of mx x my cells
+    int qf, qs;                  // interior unknowns along the fast / slow index of the ordering
+    int xfast;                   // 1: x is the fast index (row-major), 0: y is
     double c, half_d_over_h;     // D/h^2 and D/(2h); steady: 1/h^2 and 1/(2h)
     double diag0;                // 1 (backward Euler), 0 (steady: the rows divided by D, D -> inf)
     int steady;                  // no previous values in the right-hand side
@@ -59,6 +62,19 @@ struct SubArgs {
 // The separator system is then A_SS - (top part) - (bottom part) = S_top +
 // S_bot - A_SS (a dense q x q solve), and each side back-substitutes from it.
 __host__ __device__ inline size_t sep_stride(int q) { return (size_t)2 * ((size_t)q * q + 2 * q) + 2 * q; }
+
+// Lower-left grid node (i0, j0) of sub-domain sd (row-major over the layout).
+__device__ __forceinline__ void sub_origin(const SubArgs &a, int sd, int &i0, int &j0) {
+    i0 = (sd % a.px) * a.mx;
+    j0 = (sd / a.px) * a.my;
+}
+
+// Grid index of interior unknown r (natural order) of the sub-domain at (i0, j0).
+__device__ __forceinline__ int64_t unknown_node(const SubArgs &a, int r, int i0, int j0) {
+    const int f = r % a.qf, s = r / a.qf;
+    const int gi = i0 + 1 + (a.xfast ? f : s), gj = j0 + 1 + (a.xfast ? s : f);
+    return (int64_t)gj * (a.N + 1) + gi;
+}
 
 // ---------------------------------------------------------------------------
 // Grid densities (Sect. 4: w known at the grid points only; the derivatives
@@ -255,7 +271,6 @@ __device__ __forceinline__ double sum32_f64(double v) {
     return readlane_f64(v, 0) + readlane_f64(v, 16);
 }
 
-constexpr int kB = 32;   // steps per staging batch of the register-window kernel
 
 // Back substitution by one wavefront, kD rows at a time: x_k = (y_k -
 // sum_j U[k][k+j] x_{k+j}) / U[k][k] for k = n-1 .. 0.  Lane l holds
@@ -273,7 +288,6 @@ template <int P1>
 __device__ __forceinline__ void back_substitute_blocked(const SubArgs &a, const double *U, const double *Y, int n,
                                                         int top0, int i0, int j0, const double *xs, bool rev) {
     constexpr int p = P1 - 1, q = P1 - 1, kD = 8;
-    const int N1 = a.N + 1;
     const int lane = threadIdx.x & 63;
     // the ring: x_{top+lane+1}, x_{top+lane+65}; eta likewise
     auto sep_val = [&](int t, int comp) -> double {
@@ -354,9 +368,7 @@ __device__ __forceinline__ void back_substitute_blocked(const SubArgs &a, const 
         for (int j = 0; j < kD; ++j) {
             const int k = top - j;
             if (lane == j && k >= 0) {
-                const int r = rev ? n - 1 - k : k;
-                const int ii = r % q, jj = r / q;
-                const int64_t g = (int64_t)(j0 + 1 + jj) * N1 + (i0 + 1 + ii);
+                const int64_t g = unknown_node(a, rev ? n - 1 - k : k, i0, j0);
                 a.xi_out[g] = xb[j];
                 a.eta_out[g] = yb[j];
             }
@@ -389,76 +401,84 @@ __device__ __forceinline__ void back_substitute_blocked(const SubArgs &a, const 
 
 // Every row's coefficients of a sub-domain system (Dirichlet neighbours
 // moved to the right-hand side), in the natural or the reversed order (row
-// n-1-r, east <-> west, north <-> south), by the threads of the workgroup.
-__device__ void assemble_rows(const SubArgs &a, int n, int q, int i0, int j0, bool rev, double4 *cf, double2 *rh) {
-    const int N1 = a.N + 1;
+// n-1-r, fast+ <-> fast-, slow+ <-> slow-), by the threads of the
+// workgroup.  cf[r] = (fast+, fast-, slow+, slow-) neighbour coefficients:
+// (east, west, north, south) when x is the fast index, (north, south, east,
+// west) when y is.
+__device__ void assemble_rows(const SubArgs &a, int n, int i0, int j0, bool rev, double4 *cf, double2 *rh) {
+    const int N1 = a.N + 1, qf = a.qf, qs = a.qs;
+    const int64_t of = a.xfast ? 1 : N1, os = a.xfast ? N1 : 1;   // grid offsets of the fast / slow neighbours
     for (int r = threadIdx.x; r < n; r += blockDim.x) {
-        const int ii = r % q, jj = r / q;
-        const int gi = i0 + 1 + ii, gj = j0 + 1 + jj;
+        const int f = r % qf, s = r / qf;
+        const int gi = i0 + 1 + (a.xfast ? f : s), gj = j0 + 1 + (a.xfast ? s : f);
         double bx, by;
         node_drift_f64(a, gi, gj, bx, by);
         const double cxr = a.half_d_over_h * bx, cyr = a.half_d_over_h * by;
         const double cE = -a.c - cxr, cW = -a.c + cxr, cN = -a.c - cyr, cS = -a.c + cyr;
+        const double cFp = a.xfast ? cE : cN, cFm = a.xfast ? cW : cS;
+        const double cSp = a.xfast ? cN : cE, cSm = a.xfast ? cS : cW;
         const int64_t g = (int64_t)gj * N1 + gi;
         double fx = a.steady ? 0.0 : a.xi_n[g], fy = a.steady ? 0.0 : a.eta_n[g];
-        if (ii == q - 1) { fx -= cE * a.xi_out[g + 1]; fy -= cE * a.eta_out[g + 1]; }
-        if (ii == 0) { fx -= cW * a.xi_out[g - 1]; fy -= cW * a.eta_out[g - 1]; }
-        if (jj == q - 1) { fx -= cN * a.xi_out[g + N1]; fy -= cN * a.eta_out[g + N1]; }
-        if (jj == 0) { fx -= cS * a.xi_out[g - N1]; fy -= cS * a.eta_out[g - N1]; }
-        const double e = ii < q - 1 ? cE : 0.0, w = ii > 0 ? cW : 0.0;
-        const double nn = jj < q - 1 ? cN : 0.0, ss = jj > 0 ? cS : 0.0;
+        if (f == qf - 1) { fx -= cFp * a.xi_out[g + of]; fy -= cFp * a.eta_out[g + of]; }
+        if (f == 0) { fx -= cFm * a.xi_out[g - of]; fy -= cFm * a.eta_out[g - of]; }
+        if (s == qs - 1) { fx -= cSp * a.xi_out[g + os]; fy -= cSp * a.eta_out[g + os]; }
+        if (s == 0) { fx -= cSm * a.xi_out[g - os]; fy -= cSm * a.eta_out[g - os]; }
+        const double e = f < qf - 1 ? cFp : 0.0, w = f > 0 ? cFm : 0.0;
+        const double nn = s < qs - 1 ? cSp : 0.0, ss = s > 0 ? cSm : 0.0;
         cf[rev ? n - 1 - r : r] = rev ? make_double4(w, e, ss, nn) : make_double4(e, w, nn, ss);
         rh[rev ? n - 1 - r : r] = make_double2(fx, fy);
     }
 }
 
-// Original matrix entry (r, c) of an assembled system; identity beyond n.
+// Original matrix entry (r, c) of an assembled system with band width q;
+// identity beyond n.  (With q = 1 the fast and slow neighbours are the same
+// column: their coefficients add.)
 __device__ __forceinline__ double band_entry(const double4 *cf, int n, int q, double diag, int r, int c) {
     if (r >= n || c >= n) return r == c ? 1.0 : 0.0;
     const int d = c - r;
     if (d == 0) return diag;
     if (d != 1 && d != -1 && d != q && d != -q) return 0.0;
     const double4 f = cf[r];
+    if (q == 1) return d == 1 ? f.x + f.z : f.y + f.w;
     return d == 1 ? f.x : d == -1 ? f.y : d == q ? f.z : f.w;
 }
 
-// Banded LU with the window in registers.  For P1 = q + 1 the window of
-// elimination step k is rows and columns k .. k + q.  Column slot t < P1
-// holds the columns c = t (mod P1), split over two lanes: the upper lane
-// keeps window rows 0 .. H-1 (H = P1/2) in v[0 .. H-1], the lower lane rows
-// H .. P1-1; four more lanes hold the two right-hand sides the same way.
-// Step k: the two lanes of the pivot column's slot write it to LDS (1/pivot
-// in place of the pivot), every upper lane publishes its row-k entry u and
-// every lower lane its first row, then one barrier; each lane updates and
-// shifts its rows in one pass,
-//   v[i] = v[i + 1] - pivotcol[i + 1] * (u / pivot),
-// the upper lane's last row taking the lower lane's first, the lower lane's
-// last row taking the original entry of the row k + P1 that enters.  The
-// pivot column becomes exactly zero and its slot takes the entering column
-// k + P1: non-zero only in rows k + 1 (north neighbour), k + q (east
-// neighbour) and k + P1 (diagonal).  LDS buffers alternate between steps, so
-// one barrier per step suffices; every register index is a compile-time
-// constant.  Rows and columns beyond n are identity padding.
-template <int P1>
-__global__ void __launch_bounds__(256) subdomain_lu_kernel(const SubArgs a) {
-    constexpr int q = P1 - 1, H = P1 / 2;
-    static_assert(P1 % 2 == 0 && H >= 2, "even window of at least 4");
-    __shared__ __align__(16) double Vs[2][P1];   // pivot column, 1/pivot first
-    __shared__ double Us[2][P1 + 2];    // row-k entry of every column and rhs
-    __shared__ double Ls[2][P1 + 2];    // first lower row of every column and rhs
-    __shared__ double Ust[2][kB][P1];   // U rows of a batch
-    __shared__ double2 Yst[2][kB];      // y values (xi, eta) of a batch
-    __shared__ double4 Cst[2][kB];      // coefficients of the entering rows R
-    __shared__ double2 Rst[2][kB];      // right-hand sides of the entering rows R
-    __shared__ double Nst[2][kB];       // north coefficients of the rows k + 1
-    const int n = q * q;
-    const int sd = a.twisted ? blockIdx.x >> 1 : blockIdx.x;   // sub-domain
-    const bool rev = a.twisted && (blockIdx.x & 1);           // the reversed (bottom) end
-    const int si = sd % a.px, sj = sd / a.px;
-    const int i0 = si * a.m, j0 = sj * a.m;
-    const int N1 = a.N + 1;
-    // rows eliminated here, and where this end's U rows and y values go
-    const int steps = !a.twisted ? n : (rev ? n - a.sep - q : a.sep);
+// Banded LU with the window spread over a 16 x 16 grid of lanes.  The
+// window of elimination step k is rows and columns k .. k + W - 1, W = 16 T
+// >= q + 16 (rows and columns past the band of row k are zero where they
+// meet column / row k and are left unchanged), kept circularly: global
+// index g sits at physical index g mod W.  Lane (rg, cg) holds the T x T
+// entries of the rows rg + (16-blocks) and columns cg + (16-blocks), and the
+// lanes with cg < 2 the right-hand side cg (xi, eta) of their rows.
+// Register slot 0 always holds the 16-block of the current pivots; after 16
+// steps the slots rotate by one, so every register index is a compile-time
+// constant.  Step k:
+//  * the lanes holding the pivot column write it to LDS, the lanes holding
+//    the pivot row write it and its right-hand sides to LDS and out as U row
+//    k and y_k; one barrier;
+//  * every lane reads its T pivot-column and T pivot-row entries and updates
+//    its entries: T^2 FMAs (plus T for the right-hand sides).
+// The freed row and column of the pivot are refilled only after the block's
+// 16 steps, all at once: the 16 rows and columns k0 + W .. k0 + W + 15 that
+// enter are not touched by an elimination step before step k0 + W - q >=
+// k0 + 16 (their first entries in the band), so until then the freed slots
+// may hold anything -- they only ever meet each other.  Entering rows and
+// columns carry their original entries (west / south and east / north
+// neighbours, loaded a block ahead).  Twisted elimination stops at the
+// separator and writes its block of the trailing window; the U rows are
+// solved by back_block_kernel.
+template <int T>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+subdomain_lu_tile_kernel(const SubArgs a) {
+    constexpr int W = 16 * T;
+    __shared__ double colb[2][W];         // pivot column by physical row
+    __shared__ double rowb[2][W + 2];     // pivot row by physical column, then its two right-hand sides
+    const int qf = a.qf, P1 = qf + 1, n = qf * a.qs;
+    const int sd = a.twisted ? blockIdx.x >> 1 : blockIdx.x;
+    const bool rev = a.twisted && (blockIdx.x & 1);
+    int i0, j0;
+    sub_origin(a, sd, i0, j0);
+    const int steps = !a.twisted ? n : (rev ? n - a.sep - qf : a.sep);
     const int off = rev ? a.sep : 0;
     double *U = a.ubuf + (int64_t)sd * n * P1 + (int64_t)off * P1;
     double *Y = a.ybuf + (int64_t)sd * 2 * n + off;
@@ -467,185 +487,288 @@ __global__ void __launch_bounds__(256) subdomain_lu_kernel(const SubArgs a) {
     double2 *rh = reinterpret_cast<double2 *>(a.rbuf + cix * 2 * n);
     const int tid = threadIdx.x;
 
-    // ---- every row's coefficients (Dirichlet neighbours moved to the rhs) --
-    for (int r = tid; r < n; r += blockDim.x) {
-        const int ii = r % q, jj = r / q;
-        const int gi = i0 + 1 + ii, gj = j0 + 1 + jj;
-        double bx, by;
-        node_drift_f64(a, gi, gj, bx, by);
-        const double cxr = a.half_d_over_h * bx, cyr = a.half_d_over_h * by;
-        const double cE = -a.c - cxr, cW = -a.c + cxr, cN = -a.c - cyr, cS = -a.c + cyr;
-        const int64_t g = (int64_t)gj * N1 + gi;
-        double fx = a.steady ? 0.0 : a.xi_n[g], fy = a.steady ? 0.0 : a.eta_n[g];
-        if (ii == q - 1) { fx -= cE * a.xi_out[g + 1]; fy -= cE * a.eta_out[g + 1]; }
-        if (ii == 0) { fx -= cW * a.xi_out[g - 1]; fy -= cW * a.eta_out[g - 1]; }
-        if (jj == q - 1) { fx -= cN * a.xi_out[g + N1]; fy -= cN * a.eta_out[g + N1]; }
-        if (jj == 0) { fx -= cS * a.xi_out[g - N1]; fy -= cS * a.eta_out[g - N1]; }
-        const double e = ii < q - 1 ? cE : 0.0, w = ii > 0 ? cW : 0.0;
-        const double nn = jj < q - 1 ? cN : 0.0, ss = jj > 0 ? cS : 0.0;
-        // the reversed system: row n-1-r, east <-> west, north <-> south
-        cf[rev ? n - 1 - r : r] = rev ? make_double4(w, e, ss, nn) : make_double4(e, w, nn, ss);
-        rh[rev ? n - 1 - r : r] = make_double2(fx, fy);
-    }
+    assemble_rows(a, n, i0, j0, rev, cf, rh);
     __threadfence_block();
     __syncthreads();
 
     const double diag = a.diag0 + 4.0 * a.c;
-    // original matrix entry (r, c); identity beyond n
-    auto entry = [&](int r, int c) -> double {
-        if (r >= n || c >= n) return r == c ? 1.0 : 0.0;
-        const int d = c - r;
-        if (d == 0) return diag;
-        if (d != 1 && d != -1 && d != q && d != -q) return 0.0;
-        const double4 f = cf[r];
-        return d == 1 ? f.x : d == -1 ? f.y : d == q ? f.z : f.w;
-    };
-    // roles: column slot / right-hand side, and which half of the rows
-    const bool is_col = tid < 2 * P1;
-    const bool is_rhs = !is_col && tid < 2 * P1 + 4;
-    const int slot = is_col ? tid % P1 : 0;
-    const int rhs_c = is_rhs ? (tid - 2 * P1) & 1 : 0;            // 0: xi, 1: eta
-    const bool lower = is_col ? tid >= P1 : (is_rhs && tid - 2 * P1 >= 2);
-    const int pub = is_col ? slot : P1 + rhs_c;                    // index in Us / Ls
-    const int r0 = lower ? H : 0;                                  // first window row held
-    int col = slot;
-    double v[H];
+    const int rg = tid >> 4, cg = tid & 15;
+    const bool rhs = cg < 2;
+    double A[T][T], B[T];
 #pragma unroll
-    for (int i = 0; i < H; ++i) {
-        double e = 0.0;
-        if (is_col) e = entry(r0 + i, col);
-        else if (is_rhs && r0 + i < n) e = rhs_c == 0 ? rh[r0 + i].x : rh[r0 + i].y;
-        v[i] = e;
+    for (int t = 0; t < T; ++t) {
+#pragma unroll
+        for (int u = 0; u < T; ++u) A[t][u] = band_entry(cf, n, qf, diag, rg + 16 * t, cg + 16 * u);
+        const int r = rg + 16 * t;
+        B[t] = (rhs && r < n) ? (cg == 0 ? rh[r].x : rh[r].y) : 0.0;
     }
-
-    // Per-step memory traffic goes through LDS in batches of kB steps, so no
-    // step waits on global memory: the coefficients of the rows that enter
-    // (row R = k + P1: west, south, east and rhs; row k + 1: north) are
-    // loaded a batch ahead by the first kB lanes and staged in LDS; the U rows
-    // and y values a batch produces are staged in LDS and written out by the
-    // whole workgroup, coalesced, at the next batch boundary.
-    const int nb = (n + kB - 1) / kB;
-    auto load_batch = [&](int bt, double4 &c4, double2 &r2, double &cn) {
-        const int j = tid, kk = bt * kB + j, R = kk + P1;
-        const bool ok = tid < kB && bt < nb;
-        c4 = (ok && R < n) ? cf[R] : make_double4(0.0, 0.0, 0.0, 0.0);
-        r2 = (ok && R < n) ? rh[R] : make_double2(0.0, 0.0);
-        cn = (ok && kk + 1 < n) ? cf[kk + 1].z : 0.0;
+    // what the block of steps k0 .. k0 + 15 lets in: this lane's row
+    // k0 + W + rg (coefficients and right-hand side) and, for its column
+    // c = k0 + W + cg, the fast+ coefficient of row c - 1 and the slow+ one
+    // of row c - q; zero past the last row
+    double4 crow;
+    double2 rrow;
+    double fcol, scol;
+    auto load_enter = [&](int k0) {
+        const int Rr = k0 + W + rg, Rc = k0 + W + cg;
+        crow = Rr < n ? cf[Rr] : make_double4(0.0, 0.0, 0.0, 0.0);
+        rrow = (rhs && Rr < n) ? rh[Rr] : make_double2(0.0, 0.0);
+        fcol = Rc - 1 < n ? cf[Rc - 1].x : 0.0;
+        scol = Rc - qf < n ? cf[Rc - qf].z : 0.0;
     };
-    double4 pc4;
-    double2 pr2;
-    double pcn;
-    load_batch(0, pc4, pr2, pcn);
-    const double cE_first = (P1 - 1 < n) ? cf[P1 - 1].x : 0.0;   // east coefficient of row P1 - 1
 
-    int owner = 0;
-    for (int k = 0; k < steps; ++k) {
-        const int b = k & 1;
-        const int R = k + P1;
-        const int j = k % kB, bt = k / kB, bb = bt & 1;
-        if (j == 0) {
-            // batch boundary: stage this batch's coefficients, fetch the next
-            if (tid < kB) {
-                Cst[bb][tid] = pc4;
-                Rst[bb][tid] = pr2;
-                Nst[bb][tid] = pcn;
-            }
-            load_batch(bt + 1, pc4, pr2, pcn);
-        }
-        if (is_col || is_rhs) {
-            if (lower) Ls[b][pub] = v[0];
-            else Us[b][pub] = v[0];
-        }
-        if (is_col && slot == owner) {
-            double2 *dst = reinterpret_cast<double2 *>(&Vs[b][r0]);
-            dst[0] = make_double2(lower ? v[0] : 1.0 / v[0], v[1]);
+    int base = 0, k = 0;
+    double rnext = 1.0 / A[0][0];  // reciprocal of the next pivot (meaningful in its lane)
+    int po[T];                     // physical offset of slot t: 16 ((t + base) mod T)
+    auto set_offsets = [&]() {
 #pragma unroll
-            for (int i = 2; i < H; i += 2) dst[i / 2] = make_double2(v[i], (i + 1 < H) ? v[i + 1] : 0.0);
-        }
-        __syncthreads();
-        if (j == 0 && bt > 0) {
-            // write out the previous batch's U rows and y values
-            const int kp = (bt - 1) * kB;
-            const double *src = &Ust[bb ^ 1][0][0];
-            double *dstU = U + (int64_t)kp * P1;
-            for (int e = tid; e < kB * P1; e += blockDim.x) dstU[e] = src[e];
-            if (tid < kB) {
-                Y[kp + tid] = Yst[bb ^ 1][tid].x;
-                Y[n + kp + tid] = Yst[bb ^ 1][tid].y;
-            }
-        }
-        if (is_col || is_rhs) {
-            const double u = lower ? Us[b][pub] : v[0];
-            if (!lower) {
-                if (is_col) Ust[bb][j][col - k] = u;
-                else if (rhs_c == 0) Yst[bb][j].x = u;
-                else Yst[bb][j].y = u;
-            }
-            // the pivot column itself: scale exactly 1, so it becomes exactly zero
-            const double sc = (is_col && slot == owner) ? 1.0 : u * Vs[b][0];
-            const double nxt = lower ? 0.0 : Ls[b][pub];        // the row below the upper half
+        for (int t = 0; t < T; ++t) po[t] = 16 * ((t + base) % T);
+    };
+    set_offsets();
+    while (k < steps) {
+        const int k0 = k;
+        load_enter(k0);
+        for (int g = 0; g < 16 && k < steps; ++g, ++k) {
+            const int kp = 16 * base + g;     // physical index of the pivot
+            const int buf = k & 1;
+            if (cg == g) {
+                // the pivot column; at the pivot its reciprocal, formed at the
+                // end of the previous step
 #pragma unroll
-            for (int i = 0; i < H - 1; ++i) {
-                if (i % 16 == 0) asm volatile("" ::: "memory");
-                v[i] = fma(-Vs[b][r0 + i + 1], sc, v[i + 1]);
+                for (int t = 0; t < T; ++t) colb[buf][rg + po[t]] = (t == 0 && rg == g) ? rnext : A[t][0];
             }
-            const bool live = R < n;
-            if (!lower) {
-                v[H - 1] = fma(-Vs[b][H], sc, nxt);
-                if (is_col && slot == owner) {
-                    v[0] = live ? Nst[bb][j] : 0.0;                        // entering column, row k + 1
-                    col = R;
+            if (rg == g) {
+#pragma unroll
+                for (int u = 0; u < T; ++u) {
+                    const int pc = cg + po[u];
+                    rowb[buf][pc] = A[0][u];
+                    int d = pc - kp;                 // band offset of the column in U row k
+                    d += d < 0 ? W : 0;
+                    if (d <= qf) U[(int64_t)k * P1 + d] = A[0][u];
                 }
-            } else if (is_col) {
-                if (slot == owner) {
-                    col = R;
-                    // row R - 1: the east coefficient of the row that entered
-                    // one step earlier (staged in the previous step's slot)
-                    const int kp = k - 1;
-                    const double cE = k == 0 ? cE_first : Cst[(kp / kB) & 1][kp % kB].x;
-                    v[H - 2] = live ? cE : 0.0;
-                    v[H - 1] = live ? diag : 1.0;                          // row R
-                } else {
-                    const double4 cR = Cst[bb][j];
-                    v[H - 1] = (live && col < n) ? (col == R - 1 ? cR.y : (col == R - q ? cR.w : 0.0)) : 0.0;
+                if (rhs) {
+                    rowb[buf][W + cg] = B[0];
+                    Y[(int64_t)cg * n + k] = B[0];
                 }
+            }
+            __syncthreads();
+            // every LDS read of the step at once, then the update
+            double l[T], r[T];
+            const double inv = colb[buf][kp];
+#pragma unroll
+            for (int t = 0; t < T; ++t) l[t] = colb[buf][rg + po[t]];
+#pragma unroll
+            for (int u = 0; u < T; ++u) r[u] = rowb[buf][cg + po[u]];
+            const double bp = rowb[buf][W + cg];
+#pragma unroll
+            for (int t = 0; t < T; ++t) l[t] *= inv;
+            // the entry that is the next pivot first (slot 0's diagonal, or
+            // slot 1's after the last step of the block), and its reciprocal,
+            // whose latency the rest of the update hides
+            double np;
+            if (T > 1 && g == 15) {
+                A[1][1] = fma(-l[1], r[1], A[1][1]);
+                np = A[1][1];
             } else {
-                v[H - 1] = rhs_c == 0 ? Rst[bb][j].x : Rst[bb][j].y;
+                A[0][0] = fma(-l[0], r[0], A[0][0]);
+                np = A[0][0];
+            }
+            rnext = 1.0 / np;
+#pragma unroll
+            for (int t = 0; t < T; ++t) {
+#pragma unroll
+                for (int u = 0; u < T; ++u) {
+                    if (t == 0 && u == 0 && !(T > 1 && g == 15)) continue;
+                    if (T > 1 && t == 1 && u == 1 && g == 15) continue;
+                    A[t][u] = fma(-l[t], r[u], A[t][u]);
+                }
+            }
+            if (rhs) {
+#pragma unroll
+                for (int t = 0; t < T; ++t) B[t] = fma(-l[t], bp, B[t]);
             }
         }
-        owner = (owner + 1 == P1) ? 0 : owner + 1;
-    }
-    __syncthreads();
-    {
-        // the last batch
-        const int bt = (steps - 1) / kB, bb = bt & 1, kp = bt * kB, cnt = steps - kp;
-        const double *src = &Ust[bb][0][0];
-        double *dstU = U + (int64_t)kp * P1;
-        for (int e = tid; e < cnt * P1; e += blockDim.x) dstU[e] = src[e];
-        if (tid < cnt) {
-            Y[kp + tid] = Yst[bb][tid].x;
-            Y[n + kp + tid] = Yst[bb][tid].y;
+        if (k - k0 < 16 || k >= steps) break;
+        // the block is done: its rows and columns k0 + W + (0 .. 15) enter
+        // slot 0.  The window now starts at k0 + 16, at physical 16 (base + 1).
+        const int ws = k0 + 16, wp = 16 * (base + 1 == T ? 0 : base + 1);
+        const int Rr = k0 + W + rg, Rc = k0 + W + cg;
+        const double dR = Rr < n ? diag : 1.0;
+        // row Rr over every column of the window
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            int rel = cg + po[u] - wp;
+            rel += rel < 0 ? W : 0;
+            const int d = ws + rel - Rr;             // column minus row
+            double v = d == 0 ? dR : 0.0;
+            v += d == 1 ? crow.x : 0.0;
+            v += d == -1 ? crow.y : 0.0;
+            v += d == qf ? crow.z : 0.0;
+            v += d == -qf ? crow.w : 0.0;
+            A[0][u] = v;
         }
+        if (rhs) B[0] = cg == 0 ? rrow.x : rrow.y;
+        // column Rc in the rows that were already there (slots 1 .. T-1)
+#pragma unroll
+        for (int t = 1; t < T; ++t) {
+            int rel = rg + po[t] - wp;
+            rel += rel < 0 ? W : 0;
+            const int d = Rc - (ws + rel);            // column minus row, > 0
+            double v = d == 1 ? fcol : 0.0;
+            v += d == qf ? scol : 0.0;
+            A[t][0] = v;
+        }
+        // rotate the slots by one: slot 0 (the rows and columns that just
+        // entered, the last of the window) goes last
+        {
+            double a0[T], b0 = B[0];
+#pragma unroll
+            for (int u = 0; u < T; ++u) a0[u] = A[0][u];
+#pragma unroll
+            for (int t = 0; t + 1 < T; ++t) {
+                const double c0 = A[t + 1][0];
+#pragma unroll
+                for (int u = 0; u + 1 < T; ++u) A[t][u] = A[t + 1][u + 1];
+                A[t][T - 1] = c0;
+                B[t] = B[t + 1];
+            }
+#pragma unroll
+            for (int u = 0; u + 1 < T; ++u) A[T - 1][u] = a0[u + 1];
+            A[T - 1][T - 1] = a0[0];
+            B[T - 1] = b0;
+        }
+        base = base + 1 == T ? 0 : base + 1;
+        set_offsets();
     }
     if (a.twisted) {
-        // the separator block of the trailing window (window rows and columns
-        // 0 .. q-1 are this end's separator rows) and its right-hand sides
-        double *S = a.sbuf + (int64_t)sd * sep_stride(q) + (rev ? (size_t)q * q + 2 * q : 0);
-        if (is_col) {
-            const int c = col - steps;
+        // the separator block of the trailing window (its first q rows and
+        // columns, global steps .. steps + q - 1) and its right-hand sides;
+        // the rows and columns freed in the last block are past it
+        double *S = a.sbuf + (int64_t)sd * sep_stride(qf) + (rev ? (size_t)qf * qf + 2 * qf : 0);
+        const int kp0 = steps % W;
 #pragma unroll
-            for (int i = 0; i < H; ++i)
-                if (r0 + i < q && c < q) S[(r0 + i) * q + c] = v[i];
-        } else if (is_rhs) {
+        for (int t = 0; t < T; ++t) {
+            int dr = rg + po[t] - kp0;
+            dr += dr < 0 ? W : 0;
+            if (dr >= qf) continue;
 #pragma unroll
-            for (int i = 0; i < H; ++i)
-                if (r0 + i < q) S[(size_t)q * q + rhs_c * q + r0 + i] = v[i];
+            for (int u = 0; u < T; ++u) {
+                int dc = cg + po[u] - kp0;
+                dc += dc < 0 ? W : 0;
+                if (dc < qf) S[(size_t)dr * qf + dc] = A[t][u];
+            }
+            if (rhs) S[(size_t)qf * qf + (size_t)cg * qf + dr] = B[t];
         }
-        return;
     }
-    __threadfence_block();
+}
+
+// Back substitution after the tile kernel, one wavefront per elimination
+// (per end when twisted): x_k = (y_k - sum_d U[k][k+d] x_{k+d}) / U[k][k],
+// rows from the last one up, 64 at a time.  The block's U rows are copied to
+// LDS (coalesced); lane l takes row top - l and first sums its terms with
+// the columns already solved (beyond the block, from an LDS ring of
+// solutions), all lanes at once; the triangle inside the block is then
+// swept row by row: the lane of the row finishes it, its value is
+// broadcast (readlane), and every lane below adds its term.  The ring
+// starts with the separator's values (twisted) or zeros (past the last row).
+constexpr int kBackRows = 64;
+
+__global__ void __launch_bounds__(64) back_block_kernel(const SubArgs a) {
+    extern __shared__ double Ub[];               // kBackRows rows of stride P1 | 1, then the ring
+    const int qf = a.qf, P1 = qf + 1, n = qf * a.qs, S = P1 | 1;
+    double *xr = Ub + (size_t)kBackRows * S;     // [2][256]: solutions by row & 255
+    const int sd = a.twisted ? blockIdx.x >> 1 : blockIdx.x;
+    const bool rev = a.twisted && (blockIdx.x & 1);
+    int i0, j0;
+    sub_origin(a, sd, i0, j0);
+    const int steps = !a.twisted ? n : (rev ? n - a.sep - qf : a.sep);
+    const int off = rev ? a.sep : 0;
+    const double *U = a.ubuf + (int64_t)sd * n * P1 + (int64_t)off * P1;
+    const double *Y = a.ybuf + (int64_t)sd * 2 * n + off;
+    const int lane = threadIdx.x;
+    for (int t = lane; t < 512; t += 64) xr[t] = 0.0;
     __syncthreads();
-    if (tid < 64) back_substitute_blocked<P1>(a, U, Y, n, n - 1, i0, j0, nullptr, false);
+    if (a.twisted) {
+        const double *xs = a.sbuf + (int64_t)sd * sep_stride(qf) + 2 * ((size_t)qf * qf + 2 * qf);
+        for (int t = lane; t < qf; t += 64) {
+            const int row = (steps + t) & 255, src = rev ? qf - 1 - t : t;
+            xr[row] = xs[src];
+            xr[256 + row] = xs[qf + src];
+        }
+    }
+    __syncthreads();
+    for (int top = steps - 1; top >= 0; top -= kBackRows) {
+        const int nb = min(kBackRows, top + 1), base = top - nb + 1;
+        const double *src = U + (int64_t)base * P1;
+        // the block's U rows into LDS, 16 loads in flight per lane
+        const int tot = nb * P1;
+        for (int e0 = 0; e0 < tot; e0 += 16 * 64) {
+            double v[16];
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int e = e0 + i * 64 + lane;
+                v[i] = e < tot ? src[e] : 0.0;
+            }
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                const int e = e0 + i * 64 + lane;
+                if (e < tot) {
+                    const int rr = e / P1;
+                    Ub[rr * S + (e - rr * P1)] = v[i];
+                }
+            }
+        }
+        __syncthreads();
+        const bool has = lane < nb;
+        const int r = top - lane, lr = nb - 1 - lane;   // this lane's row and its place in the block
+        const double *ur = Ub + (has ? lr : 0) * S;
+        double sx = 0.0, sy = 0.0, yx = 0.0, yy = 0.0, d0 = 1.0;
+        if (has) {
+            d0 = ur[0];
+            yx = Y[r];
+            yy = Y[n + r];
+            // four terms per pass, so the LDS reads of a pass are in flight together
+            int d = lane + 1;
+            for (; d + 3 <= qf; d += 4) {
+                double u4[4], x4[4], y4[4];
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const int c = (r + d + i) & 255;
+                    u4[i] = ur[d + i];
+                    x4[i] = xr[c];
+                    y4[i] = xr[256 + c];
+                }
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    sx = fma(u4[i], x4[i], sx);
+                    sy = fma(u4[i], y4[i], sy);
+                }
+            }
+            for (; d <= qf; ++d) {
+                const int c = (r + d) & 255;
+                sx = fma(ur[d], xr[c], sx);
+                sy = fma(ur[d], xr[256 + c], sy);
+            }
+        }
+        const double inv = 1.0 / d0;
+        double ucur = (has && lane >= 1 && lane <= qf) ? ur[lane] : 0.0;   // term of row top at step 0
+        for (int s = 0; s < nb; ++s) {
+            const int dn = lane - s - 1;
+            const double unext = (has && dn >= 1 && dn <= qf) ? ur[dn] : 0.0;
+            const double xv = readlane_f64((yx - sx) * inv, s), yv = readlane_f64((yy - sy) * inv, s);
+            if (lane == s) {
+                xr[r & 255] = xv;
+                xr[256 + (r & 255)] = yv;
+                const int64_t gn = unknown_node(a, rev ? n - 1 - r : r, i0, j0);
+                a.xi_out[gn] = xv;
+                a.eta_out[gn] = yv;
+            }
+            sx = fma(ucur, xv, sx);
+            sy = fma(ucur, yv, sy);
+            ucur = unext;
+        }
+        __syncthreads();
+    }
 }
 
 // Banded LU of a small window (P1 <= 32) in one wavefront, one lane per
@@ -668,12 +791,12 @@ __global__ void __launch_bounds__(64) subdomain_lu_wave_kernel(const SubArgs a) 
     static_assert(P1 + 2 <= 64, "one lane per window column and right-hand side");
     __shared__ double4 Cst[2][kW];   // coefficients of the entering rows R = k + P1
     __shared__ double2 Rst[2][kW];   // their right-hand sides
-    __shared__ double Nst[2][kW];    // north coefficients of the rows k + 1
-    const int n = q * q;
+    __shared__ double Nst[2][kW];    // slow+ coefficients of the rows k + 1
+    const int n = q * a.qs;
     const int sd = TW ? blockIdx.x >> 1 : blockIdx.x;
     const bool rev = TW && (blockIdx.x & 1);
-    const int si = sd % a.px, sj = sd / a.px;
-    const int i0 = si * a.m, j0 = sj * a.m;
+    int i0, j0;
+    sub_origin(a, sd, i0, j0);
     const int steps = !TW ? n : (rev ? n - a.sep - q : a.sep);
     const int off = rev ? a.sep : 0;
     double *U = a.ubuf + (int64_t)sd * n * P1 + (int64_t)off * P1;
@@ -683,7 +806,7 @@ __global__ void __launch_bounds__(64) subdomain_lu_wave_kernel(const SubArgs a) 
     double2 *rh = reinterpret_cast<double2 *>(a.rbuf + cix * 2 * n);
     const int lane = threadIdx.x;
 
-    assemble_rows(a, n, q, i0, j0, rev, cf, rh);
+    assemble_rows(a, n, i0, j0, rev, cf, rh);
     __threadfence_block();
     __syncthreads();
 
@@ -775,9 +898,9 @@ __global__ void __launch_bounds__(64) subdomain_lu_wave_kernel(const SubArgs a) 
 // matrix is diagonally dominant), then x_S into the workspace and the grid.
 __global__ void __launch_bounds__(256) separator_kernel(const SubArgs a) {
     extern __shared__ double M[];   // [q][q] then the two right-hand sides [2][q]
-    const int q = a.m - 1, n = q * q, sd = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
-    const int si = sd % a.px, sj = sd / a.px;
-    const int i0 = si * a.m, j0 = sj * a.m, N1 = a.N + 1;
+    const int q = a.qf, n = q * a.qs, sd = blockIdx.x, tid = threadIdx.x, nt = blockDim.x;
+    int i0, j0;
+    sub_origin(a, sd, i0, j0);
     double *S = a.sbuf + (int64_t)sd * sep_stride(q);
     const double *St = S, *Sb = S + (size_t)q * q + 2 * q;
     double *xs = S + 2 * ((size_t)q * q + 2 * q);
@@ -822,31 +945,13 @@ __global__ void __launch_bounds__(256) separator_kernel(const SubArgs a) {
         }
         __syncthreads();
     }
-    const int jj = a.sep / q;
     for (int e = tid; e < 2 * q; e += nt) {
         const int comp = e / q, r = e % q;
         xs[e] = b[e];
-        const int64_t g = (int64_t)(j0 + 1 + jj) * N1 + (i0 + 1 + r);
+        const int64_t g = unknown_node(a, a.sep + r, i0, j0);
         (comp ? a.eta_out : a.xi_out)[g] = b[e];
     }
 }
-
-// Back substitution of each end of a twisted elimination, from the
-// separator's values: one wavefront per (sub-domain, end).
-template <int P1>
-__global__ void __launch_bounds__(64) twisted_back_kernel(const SubArgs a) {
-    constexpr int q = P1 - 1;
-    const int n = q * q;
-    const int sd = blockIdx.x >> 1;
-    const bool rev = (blockIdx.x & 1) != 0;
-    const int steps = rev ? n - a.sep - q : a.sep, off = rev ? a.sep : 0;
-    const int si = sd % a.px, sj = sd / a.px;
-    const double *U = a.ubuf + (int64_t)sd * n * P1 + (int64_t)off * P1;
-    const double *Y = a.ybuf + (int64_t)sd * 2 * n + off;
-    const double *xs = a.sbuf + (int64_t)sd * sep_stride(q) + 2 * ((size_t)q * q + 2 * q);
-    back_substitute_blocked<P1>(a, U, Y, n, steps - 1, si * a.m, sj * a.m, xs, rev);
-}
-
 
 // The same for windows up to 32, a row at a time: lane l < q holds
 // x_{k+l+1} (both components), each row's sum over them is a DPP reduction
@@ -856,12 +961,12 @@ template <int P1>
 __global__ void __launch_bounds__(64) twisted_back_wave_kernel(const SubArgs a) {
     constexpr int q = P1 - 1, kR = 8;
     static_assert(q <= 32, "the window fits the first 32 lanes");
-    const int n = q * q;
+    const int n = q * a.qs;
     const int sd = blockIdx.x >> 1;
     const bool rev = (blockIdx.x & 1) != 0;
     const int steps = rev ? n - a.sep - q : a.sep, off = rev ? a.sep : 0;
-    const int si = sd % a.px, sj = sd / a.px;
-    const int i0 = si * a.m, j0 = sj * a.m, N1 = a.N + 1;
+    int i0, j0;
+    sub_origin(a, sd, i0, j0);
     const double *U = a.ubuf + (int64_t)sd * n * P1 + (int64_t)off * P1;
     const double *Y = a.ybuf + (int64_t)sd * 2 * n + off;
     const double *xs = a.sbuf + (int64_t)sd * sep_stride(q) + 2 * ((size_t)q * q + 2 * q);
@@ -890,8 +995,7 @@ __global__ void __launch_bounds__(64) twisted_back_wave_kernel(const SubArgs a) 
             const double sx = sum32_f64(ur[r] * xw), sy = sum32_f64(ur[r] * yw);
             const double x = (fx[r] - sx) / ud[r], y = (fy[r] - sy) / ud[r];
             if (lane == 0 && k >= 0) {
-                const int rr = rev ? n - 1 - k : k;
-                const int64_t g = (int64_t)(j0 + 1 + rr / q) * N1 + (i0 + 1 + rr % q);
+                const int64_t g = unknown_node(a, rev ? n - 1 - k : k, i0, j0);
                 a.xi_out[g] = x;
                 a.eta_out[g] = y;
             }
@@ -903,163 +1007,10 @@ __global__ void __launch_bounds__(64) twisted_back_wave_kernel(const SubArgs a) 
     }
 }
 
-__global__ void __launch_bounds__(256) subdomain_be_kernel(const SubArgs a) {
-    extern __shared__ double lds[];
-    const int q = a.m - 1, p = q, P1 = p + 1, n = q * q;
-    const int si = blockIdx.x % a.px, sj = blockIdx.x / a.px;
-    const int i0 = si * a.m, j0 = sj * a.m;
-    const int N1 = a.N + 1;
-    double *W = lds;                     // P1 x P1 window
-    double *rx = W + P1 * P1;            // rhs ring, xi
-    double *ry = rx + P1;                // rhs ring, eta
-    double *kx = ry + P1;                // cx of the rows in the window
-    double *ky = kx + P1;                // cy of the rows in the window
-    double *U = a.ubuf + (int64_t)blockIdx.x * n * P1;
-    double *Y = a.ybuf + (int64_t)blockIdx.x * 2 * n;
-    const int tid = threadIdx.x, nth = blockDim.x;
-
-    // Row r enters the window: its drift coefficients, its right-hand side
-    // with the Dirichlet neighbours moved over, and its lower entries (W, S)
-    // in window column coordinates relative to step k.
-    auto row_enter = [&](int r, int k) {
-        const int ii = r % q, jj = r / q;
-        const int gi = i0 + 1 + ii, gj = j0 + 1 + jj;
-        double bx, by;
-        node_drift_f64(a, gi, gj, bx, by);
-        const double cxr = a.half_d_over_h * bx, cyr = a.half_d_over_h * by;
-        const int s = r % P1;
-        kx[s] = cxr;
-        ky[s] = cyr;
-        const int64_t g = (int64_t)gj * N1 + gi;
-        double fx = a.steady ? 0.0 : a.xi_n[g], fy = a.steady ? 0.0 : a.eta_n[g];
-        const double cE = -a.c - cxr, cW = -a.c + cxr, cN = -a.c - cyr, cS = -a.c + cyr;
-        if (ii == q - 1) { fx -= cE * a.xi_out[g + 1]; fy -= cE * a.eta_out[g + 1]; }
-        if (ii == 0) { fx -= cW * a.xi_out[g - 1]; fy -= cW * a.eta_out[g - 1]; }
-        if (jj == q - 1) { fx -= cN * a.xi_out[g + N1]; fy -= cN * a.eta_out[g + N1]; }
-        if (jj == 0) { fx -= cS * a.xi_out[g - N1]; fy -= cS * a.eta_out[g - N1]; }
-        rx[s] = fx;
-        ry[s] = fy;
-        double *row = W + s * P1;
-        row[r % P1] = a.diag0 + 4.0 * a.c;
-        if (ii > 0 && r - 1 >= k) row[(r - 1) % P1] = cW;
-        if (jj > 0 && r - q >= k) row[(r - q) % P1] = cS;
-    };
-
-    // ---- initial window: rows and columns 0..p ------------------------------
-    for (int e = tid; e < P1 * P1; e += nth) W[e] = 0.0;
-    __syncthreads();
-    for (int r = tid; r < P1 && r < n; r += nth) row_enter(r, 0);
-    __syncthreads();
-    // upper entries (E, N) of rows 0..p that fall inside the window
-    for (int r = tid; r < P1 && r < n; r += nth) {
-        const int ii = r % q, jj = r / q;
-        double *row = W + (r % P1) * P1;
-        if (ii < q - 1 && r + 1 <= p) row[(r + 1) % P1] = -a.c - kx[r % P1];
-        if (jj < q - 1 && r + q <= p) row[(r + q) % P1] = -a.c - ky[r % P1];
-    }
-    __syncthreads();
-
-    // ---- forward elimination ------------------------------------------------
-    for (int k = 0; k < n; ++k) {
-        const int s0 = k % P1;
-        const double *prow = W + s0 * P1;
-        const double inv = 1.0 / prow[s0];
-        const int span = min(p, n - 1 - k);  // rows/cols below and right of the pivot
-        // save the U row and the eliminated right-hand side of step k
-        for (int c = tid; c <= p; c += nth) U[(int64_t)k * P1 + c] = (c <= span) ? prow[(k + c) % P1] : 0.0;
-        if (tid == 0) {
-            Y[k] = rx[s0];
-            Y[n + k] = ry[s0];
-        }
-        // rank-1 update of the window, and the right-hand sides
-        const int tot = span * span;
-        for (int e = tid; e < tot; e += nth) {
-            const int r = 1 + e / span, c = 1 + e % span;
-            double *row = W + ((k + r) % P1) * P1;
-            const double l = row[s0] * inv;
-            row[(k + c) % P1] -= l * prow[(k + c) % P1];
-        }
-        for (int r = 1 + tid; r <= span; r += nth) {
-            const int s = (k + r) % P1;
-            const double l = W[s * P1 + s0] * inv;
-            rx[s] -= l * rx[s0];
-            ry[s] -= l * ry[s0];
-        }
-        __syncthreads();
-        // slide: slot s0 becomes row / column k + P1
-        const int R = k + P1;
-        if (R < n) {
-            for (int e = tid; e < P1; e += nth) {
-                W[s0 * P1 + e] = 0.0;   // the new row
-                W[e * P1 + s0] = 0.0;   // the new column
-            }
-            __syncthreads();
-            if (tid == 0) row_enter(R, k + 1);
-            if (tid == 1) {
-                // new column entries: E of row R-1, N of row R-q
-                const int r1 = R - 1, rq = R - q;
-                if (r1 % q < q - 1) W[(r1 % P1) * P1 + s0] = -a.c - kx[r1 % P1];
-                if (rq >= k + 1 && (rq / q) < q - 1) W[(rq % P1) * P1 + s0] = -a.c - ky[rq % P1];
-            }
-        }
-        __syncthreads();
-    }
-
-    // ---- back substitution (one wavefront) ----------------------------------
-    if (tid < 64) {
-        double *xw = W;            // x ring (xi), reuse of the window storage
-        double *yw = W + P1;       // x ring (eta)
-        const int lane = tid;
-        double u0 = 0.0, u1 = 0.0, ud = 1.0;
-        int k = n - 1;
-        // prefetch row n-1
-        if (k >= 0) {
-            u0 = (lane + 1 <= p) ? U[(int64_t)k * P1 + lane + 1] : 0.0;
-            u1 = (lane + 65 <= p) ? U[(int64_t)k * P1 + lane + 65] : 0.0;
-            ud = U[(int64_t)k * P1];
-        }
-        for (; k >= 0; --k) {
-            double n0 = 0.0, n1 = 0.0, nd = 1.0;
-            if (k > 0) {
-                n0 = (lane + 1 <= p) ? U[(int64_t)(k - 1) * P1 + lane + 1] : 0.0;
-                n1 = (lane + 65 <= p) ? U[(int64_t)(k - 1) * P1 + lane + 65] : 0.0;
-                nd = U[(int64_t)(k - 1) * P1];
-            }
-            double sx = 0.0, sy = 0.0;
-            if (lane + 1 <= p && k + lane + 1 < n) {
-                sx += u0 * xw[(k + lane + 1) % P1];
-                sy += u0 * yw[(k + lane + 1) % P1];
-            }
-            if (lane + 65 <= p && k + lane + 65 < n) {
-                sx += u1 * xw[(k + lane + 65) % P1];
-                sy += u1 * yw[(k + lane + 65) % P1];
-            }
-#pragma unroll
-            for (int off = 32; off > 0; off >>= 1) {
-                sx += __shfl_xor(sx, off, 64);
-                sy += __shfl_xor(sy, off, 64);
-            }
-            const double xk = (Y[k] - sx) / ud, yk = (Y[n + k] - sy) / ud;
-            if (lane == 0) {
-                xw[k % P1] = xk;
-                yw[k % P1] = yk;
-                const int ii = k % q, jj = k / q;
-                const int64_t g = (int64_t)(j0 + 1 + jj) * N1 + (i0 + 1 + ii);
-                a.xi_out[g] = xk;
-                a.eta_out[g] = yk;
-            }
-            __builtin_amdgcn_wave_barrier();
-            u0 = n0;
-            u1 = n1;
-            ud = nd;
-        }
-    }
-}
-
 // Dirichlet data of the output grids: outer boundary and interface nodes.
 __global__ void dirichlet_kernel(const SubArgs a, const double *iface_xi, const double *iface_eta, int64_t n_iface,
                                  int bdry_kind, const double *edge_cells, double *xi_out, double *eta_out) {
-    const int N = a.N, m = a.m, px = a.px;
+    const int N = a.N, px = a.px, mx = a.mx, my = a.my;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int N1 = N + 1;
     const int64_t n_bd = 4 * (int64_t)N;
@@ -1093,19 +1044,19 @@ __global__ void dirichlet_kernel(const SubArgs a, const double *iface_xi, const 
     const int64_t f = t - n_bd;
     if (f >= n_iface) return;
     // canonical order: vertical lines x = a/px (nodes y = j/N), then
-    // horizontal lines y = c/px without the crossings
+    // horizontal lines y = c/py without the crossings
     const int64_t nv = (int64_t)(px - 1) * (N - 1);
     int i, j;
     if (f < nv) {
-        i = (int)(f / (N - 1) + 1) * m;
+        i = (int)(f / (N - 1) + 1) * mx;
         j = (int)(f % (N - 1)) + 1;
     } else {
         const int64_t h = f - nv;
         const int per = N - px;  // non-crossing nodes per horizontal line
         const int c = (int)(h / per) + 1;
         const int r = (int)(h % per);
-        i = r + 1 + r / (m - 1);
-        j = c * m;
+        i = r + 1 + r / (mx - 1);
+        j = c * my;
     }
     const int64_t g = (int64_t)j * N1 + i;
     xi_out[g] = iface_xi[f];
@@ -1151,91 +1102,101 @@ __global__ void __launch_bounds__(1024) quality_kernel(const double *xi, const d
     }
 }
 
+// Layout of a px x py split of an N-cell grid: sub-domain sizes, the
+// ordering (the shorter side is the fast index) and the band.
+struct SubGeom {
+    int px, py, mx, my, qf, qs, xfast;
+    int64_t n;       // unknowns per sub-domain
+    int64_t n_iface;
+};
+static SubGeom sub_geom(int px, int py, int N) {
+    SubGeom g{};
+    g.px = px;
+    g.py = py;
+    g.mx = N / px;
+    g.my = N / py;
+    g.xfast = g.mx <= g.my ? 1 : 0;
+    g.qf = (g.xfast ? g.mx : g.my) - 1;
+    g.qs = (g.xfast ? g.my : g.mx) - 1;
+    g.n = (int64_t)g.qf * g.qs;
+    g.n_iface = (int64_t)(px - 1) * (N - 1) + (int64_t)(py - 1) * (N - px);
+    return g;
+}
+
 // Workspace: U rows, y values, row coefficients and right-hand sides (two
 // copies per sub-domain: natural and reversed order), the separator blocks,
 // and the edge integrals.
-static size_t sub_ws_bytes(int px, int m) {
-    const size_t q = (size_t)m - 1, n = q * q, P1 = q + 1;
-    const size_t blocks = (size_t)px * px, N = (size_t)px * m;
+static size_t sub_ws_bytes(const SubGeom &g, int N) {
+    const size_t n = (size_t)g.n, P1 = (size_t)g.qf + 1;
+    const size_t blocks = (size_t)g.px * g.py;
     return align256(blocks * n * P1 * sizeof(double)) + align256(blocks * 2 * n * sizeof(double)) +
            align256(2 * blocks * 4 * n * sizeof(double)) + align256(2 * blocks * 2 * n * sizeof(double)) +
-           align256(blocks * sep_stride((int)q) * sizeof(double)) + align256(4 * N * sizeof(double));
+           align256(blocks * sep_stride(g.qf) * sizeof(double)) + align256(4 * (size_t)N * sizeof(double));
 }
 
-// Sides from which the twisted elimination (two workgroups per sub-domain)
-// is used: below, one workgroup's sequential steps are cheap and three
+// Twisted elimination (two workgroups per sub-domain) from this many
+// unknowns: below, one workgroup's sequential steps are cheap and the extra
 // launches would cost more than they save.
-constexpr int kTwistedMinM = 16;
+constexpr int64_t kTwistedMinN = 225;
 
-// Launch of the register-window kernel for the window widths it is built
-// for; false if m is not one of them.
-static bool launch_lu(const SubArgs &a, int blocks, hipStream_t s, hipError_t *err) {
-    auto go = [&](auto kern, int P1) {
-        const int threads = ((2 * P1 + 4 + 63) / 64) * 64;
-        hipLaunchKernelGGL(kern, dim3((unsigned)(a.twisted ? 2 * blocks : blocks)), dim3(threads), 0, s, a);
-        *err = hipGetLastError();
-        return true;
-    };
-    auto wave = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3((unsigned)(a.twisted ? 2 * blocks : blocks)), dim3(64), 0, s, a);
-        *err = hipGetLastError();
-        return true;
-    };
-    // windows up to 32: one wavefront per elimination (both ends when twisted)
-    if (a.twisted) {
-        switch (a.m) {
-        case 16: return wave(subdomain_lu_wave_kernel<16, true>);
-        case 20: return wave(subdomain_lu_wave_kernel<20, true>);
-        case 24: return wave(subdomain_lu_wave_kernel<24, true>);
-        case 32: return wave(subdomain_lu_wave_kernel<32, true>);
-        default: break;
-        }
-    } else {
-        switch (a.m) {
-        case 8: return wave(subdomain_lu_wave_kernel<8, false>);
-        case 12: return wave(subdomain_lu_wave_kernel<12, false>);
-        default: break;
-        }
-    }
-    switch (a.m) {
-    case 8: return go(subdomain_lu_kernel<8>, 8);
-    case 12: return go(subdomain_lu_kernel<12>, 12);
-    case 16: return go(subdomain_lu_kernel<16>, 16);
-    case 20: return go(subdomain_lu_kernel<20>, 20);
-    case 24: return go(subdomain_lu_kernel<24>, 24);
-    case 32: return go(subdomain_lu_kernel<32>, 32);
-    case 40: return go(subdomain_lu_kernel<40>, 40);
-    case 48: return go(subdomain_lu_kernel<48>, 48);
-    case 64: return go(subdomain_lu_kernel<64>, 64);
-    case 96: return go(subdomain_lu_kernel<96>, 96);
-    default: return false;
-    }
-}
-
-// The separator solves and the back substitutions of a twisted elimination.
-static hipError_t launch_twisted_rest(const SubArgs &a, int blocks, hipStream_t s) {
-    const int q = a.m - 1;
-    const size_t lds = ((size_t)q * q + 2 * q) * sizeof(double);
-    hipError_t e = hipFuncSetAttribute((const void *)separator_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                       (int)lds);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(separator_kernel, dim3((unsigned)blocks), dim3(256), lds, s, a);
-    if ((e = hipGetLastError()) != hipSuccess) return e;
-    auto back = [&](auto kern) {
-        hipLaunchKernelGGL(kern, dim3((unsigned)(2 * blocks)), dim3(64), 0, s, a);
+// Elimination, separator and back substitution of every sub-domain.
+static hipError_t launch_elimination(const SubArgs &a, int blocks, hipStream_t s) {
+    const int P1 = a.qf + 1;
+    const unsigned nwg = (unsigned)(a.twisted ? 2 * blocks : blocks);
+    hipError_t e;
+    auto separator = [&]() -> hipError_t {
+        const size_t lds = ((size_t)a.qf * a.qf + 2 * a.qf) * sizeof(double);
+        hipError_t r = hipFuncSetAttribute((const void *)separator_kernel,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+        if (r != hipSuccess) return r;
+        hipLaunchKernelGGL(separator_kernel, dim3((unsigned)blocks), dim3(256), lds, s, a);
         return hipGetLastError();
     };
-    switch (a.m) {
-    case 16: return back(twisted_back_wave_kernel<16>);
-    case 20: return back(twisted_back_wave_kernel<20>);
-    case 24: return back(twisted_back_wave_kernel<24>);
-    case 32: return back(twisted_back_wave_kernel<32>);
-    case 40: return back(twisted_back_kernel<40>);
-    case 48: return back(twisted_back_kernel<48>);
-    case 64: return back(twisted_back_kernel<64>);
-    case 96: return back(twisted_back_kernel<96>);
+    // windows up to 32: one wavefront per elimination, the back
+    // substitution in the kernel or one wavefront per end
+    auto wave = [&](auto lu, auto back) -> hipError_t {
+        hipLaunchKernelGGL(lu, dim3(nwg), dim3(64), 0, s, a);
+        hipError_t r = hipGetLastError();
+        if (r != hipSuccess || !a.twisted) return r;
+        if ((r = separator()) != hipSuccess) return r;
+        hipLaunchKernelGGL(back, dim3(nwg), dim3(64), 0, s, a);
+        return hipGetLastError();
+    };
+#define FK_WAVE(P)                                                                                    \
+    case P:                                                                                           \
+        return a.twisted ? wave(subdomain_lu_wave_kernel<P, true>, twisted_back_wave_kernel<P>)       \
+                         : wave(subdomain_lu_wave_kernel<P, false>, twisted_back_wave_kernel<P>);
+    switch (P1) {
+        FK_WAVE(8)
+        FK_WAVE(12)
+        FK_WAVE(16)
+        FK_WAVE(20)
+        FK_WAVE(24)
+        FK_WAVE(32)
+    default: break;
+    }
+#undef FK_WAVE
+    // any other band: the tile kernel, its window at least q + 16 wide
+    const int T = (a.qf + 16 + 15) / 16;
+    switch (T) {
+    case 2: hipLaunchKernelGGL(subdomain_lu_tile_kernel<2>, dim3(nwg), dim3(256), 0, s, a); break;
+    case 3: hipLaunchKernelGGL(subdomain_lu_tile_kernel<3>, dim3(nwg), dim3(256), 0, s, a); break;
+    case 4: hipLaunchKernelGGL(subdomain_lu_tile_kernel<4>, dim3(nwg), dim3(256), 0, s, a); break;
+    case 5: hipLaunchKernelGGL(subdomain_lu_tile_kernel<5>, dim3(nwg), dim3(256), 0, s, a); break;
+    case 6: hipLaunchKernelGGL(subdomain_lu_tile_kernel<6>, dim3(nwg), dim3(256), 0, s, a); break;
+    case 7: hipLaunchKernelGGL(subdomain_lu_tile_kernel<7>, dim3(nwg), dim3(256), 0, s, a); break;
+    case 8: hipLaunchKernelGGL(subdomain_lu_tile_kernel<8>, dim3(nwg), dim3(256), 0, s, a); break;
+    case 9: hipLaunchKernelGGL(subdomain_lu_tile_kernel<9>, dim3(nwg), dim3(256), 0, s, a); break;
     default: return hipErrorInvalidValue;
     }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (a.twisted && (e = separator()) != hipSuccess) return e;
+    const size_t lds = ((size_t)kBackRows * (P1 | 1) + 512) * sizeof(double);
+    if ((e = hipFuncSetAttribute((const void *)back_block_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)lds)) != hipSuccess)
+        return e;
+    hipLaunchKernelGGL(back_block_kernel, dim3(nwg), dim3(64), lds, s, a);
+    return hipGetLastError();
 }
 
 }  // namespace fk
@@ -1244,29 +1205,42 @@ using namespace fk;
 
 extern "C" {
 
-size_t subdomain_workspace_bytes(int32_t px, int32_t m) {
-    if (px < 1 || m < 2 || m - 1 >= kMaxP1) return 0;
-    return sub_ws_bytes(px, m);
+size_t subdomain_workspace_bytes_rect(int32_t px, int32_t py, int32_t n_cells) {
+    if (px < 1 || py < 1 || n_cells < 2 || n_cells > 65535 || n_cells % px || n_cells % py) return 0;
+    const SubGeom g = sub_geom(px, py, n_cells);
+    if (g.mx < 2 || g.my < 2 || g.qf >= kMaxP1) return 0;
+    return sub_ws_bytes(g, n_cells);
 }
 
-int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px, int32_t m, int32_t bdry_kind,
-                    const double *xi_n, const double *eta_n, const double *iface_xi, const double *iface_eta,
-                    double *xi_out, double *eta_out, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+size_t subdomain_workspace_bytes(int32_t px, int32_t m) {
+    if (px < 1 || m < 2 || (int64_t)px * m > 65535) return 0;
+    return subdomain_workspace_bytes_rect(px, px, px * m);
+}
+
+int subdomain_solve_rect(const fk_density *w, double t_w, double dt_mesh, int32_t px, int32_t py, int32_t n_cells,
+                         int32_t bdry_kind, const double *xi_n, const double *eta_n, const double *iface_xi,
+                         const double *iface_eta, double *xi_out, double *eta_out, void *workspace,
+                         size_t workspace_bytes, hipStream_t stream) {
     g_last_error.clear();
     int rc;
     if ((rc = validate_density(w)) != FK_OK) return rc;
-    if (px < 1 || m < 2) return fail(FK_E_INVAL, "need px >= 1 and m >= 2");
-    if (m - 1 >= kMaxP1) return fail(FK_E_UNSUPPORTED, "sub-domain side m must be <= %d", kMaxP1);
+    if (px < 1 || py < 1 || n_cells < 2 || n_cells > 65535)
+        return fail(FK_E_INVAL, "need px >= 1, py >= 1 and 2 <= n_cells <= 65535");
+    if (n_cells % px || n_cells % py) return fail(FK_E_INVAL, "px and py must divide n_cells");
+    const SubGeom geo = sub_geom(px, py, n_cells);
+    if (geo.mx < 2 || geo.my < 2) return fail(FK_E_INVAL, "sub-domains need at least 2 cells a side");
+    if (geo.qf >= kMaxP1)
+        return fail(FK_E_UNSUPPORTED, "the shorter sub-domain side must be <= %d cells", kMaxP1);
     const bool steady = std::isinf(dt_mesh) && dt_mesh > 0.0;
     if (!std::isfinite(t_w) || std::isnan(dt_mesh) || !(dt_mesh > 0.0))
         return fail(FK_E_INVAL, "t_w must be finite and dt_mesh > 0 (or +inf: the steady solve)");
     if (bdry_kind != FK_DATA_IDENTITY && bdry_kind != FK_DATA_ZERO && bdry_kind != FK_DATA_EQUIDISTRIBUTED)
         return fail(FK_E_INVAL, "outer boundary data must be FK_DATA_IDENTITY, _ZERO or _EQUIDISTRIBUTED");
-    const int N = px * m;
-    const int64_t n_iface = 2 * (int64_t)(px - 1) * (N - 1) - (int64_t)(px - 1) * (px - 1);
+    const int N = n_cells;
+    const int64_t n_iface = geo.n_iface;
     if ((!steady && (!xi_n || !eta_n)) || !xi_out || !eta_out || (n_iface > 0 && (!iface_xi || !iface_eta)))
         return fail(FK_E_INVAL, "NULL array");
-    const size_t need = sub_ws_bytes(px, m);
+    const size_t need = sub_ws_bytes(geo, N);
     if (!workspace || workspace_bytes < need) return fail(FK_E_NOMEM, "workspace too small: need %zu bytes", need);
     if (((uintptr_t)workspace & 255u) != 0) return fail(FK_E_INVAL, "workspace must be 256-byte aligned");
     const double h = 1.0 / N;
@@ -1304,8 +1278,8 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
     a.eta_n = eta_n;
     a.xi_out = xi_out;
     a.eta_out = eta_out;
-    const size_t q = (size_t)m - 1, n = q * q, P1 = q + 1;
-    const size_t blocks = (size_t)px * px;
+    const size_t n = (size_t)geo.n, P1 = (size_t)geo.qf + 1;
+    const size_t blocks = (size_t)px * py;
     char *ws = (char *)workspace;
     a.ubuf = (double *)ws;
     ws += align256(blocks * n * P1 * sizeof(double));
@@ -1316,11 +1290,16 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
     a.rbuf = (double *)ws;
     ws += align256(2 * blocks * 2 * n * sizeof(double));
     a.sbuf = (double *)ws;
-    ws += align256(blocks * sep_stride((int)q) * sizeof(double));
+    ws += align256(blocks * sep_stride(geo.qf) * sizeof(double));
     double *edge_cells = (double *)ws;
     a.N = N;
-    a.m = m;
     a.px = px;
+    a.py = py;
+    a.mx = geo.mx;
+    a.my = geo.my;
+    a.qf = geo.qf;
+    a.qs = geo.qs;
+    a.xfast = geo.xfast;
     // steady: the rows divided by D (D -> inf) -- no identity term, no
     // previous values -- and scaled by h^2
     a.steady = steady ? 1 : 0;
@@ -1345,24 +1324,21 @@ int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px,
     hipLaunchKernelGGL(dirichlet_kernel, dim3((unsigned)((nthr + 255) / 256)), dim3(256), 0, stream, a, iface_xi,
                        iface_eta, n_iface, (int)bdry_kind, (const double *)edge_cells, xi_out, eta_out);
     if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "dirichlet kernel launch");
-    // two workgroups per sub-domain from the separator grid row q/2
-    a.twisted = (m >= kTwistedMinM) ? 1 : 0;
-    a.sep = (int)((q / 2) * q);
-    if (launch_lu(a, px * px, stream, &e)) {
-        if (e != hipSuccess) return hip_fail(e, "sub-domain kernel launch");
-        if (a.twisted && (e = launch_twisted_rest(a, px * px, stream)) != hipSuccess)
-            return hip_fail(e, "separator / back substitution launch");
-        return FK_OK;
-    }
-    a.twisted = 0;
-    // other sub-domain sizes: the window in LDS
-    const size_t lds = (P1 * P1 + 4 * P1) * sizeof(double);
-    if ((e = hipFuncSetAttribute((const void *)subdomain_be_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lds)) != hipSuccess)
-        return hip_fail(e, "hipFuncSetAttribute (LDS)");
-    hipLaunchKernelGGL(subdomain_be_kernel, dim3((unsigned)(px * px)), dim3(256), lds, stream, a);
-    if ((e = hipGetLastError()) != hipSuccess) return hip_fail(e, "sub-domain kernel launch");
+    // two workgroups per sub-domain, meeting at the slow line qs/2
+    a.twisted = (geo.n >= kTwistedMinN && geo.qs >= 3) ? 1 : 0;
+    a.sep = (geo.qs / 2) * geo.qf;
+    if ((e = launch_elimination(a, (int)blocks, stream)) != hipSuccess) return hip_fail(e, "sub-domain kernel launch");
     return FK_OK;
+}
+
+int subdomain_solve(const fk_density *w, double t_w, double dt_mesh, int32_t px, int32_t m, int32_t bdry_kind,
+                    const double *xi_n, const double *eta_n, const double *iface_xi, const double *iface_eta,
+                    double *xi_out, double *eta_out, void *workspace, size_t workspace_bytes, hipStream_t stream) {
+    g_last_error.clear();
+    if (px < 1 || m < 2) return fail(FK_E_INVAL, "need px >= 1 and m >= 2");
+    if ((int64_t)px * m > 65535) return fail(FK_E_INVAL, "grid too large (px m > 65535)");
+    return subdomain_solve_rect(w, t_w, dt_mesh, px, px, px * m, bdry_kind, xi_n, eta_n, iface_xi, iface_eta, xi_out,
+                                eta_out, workspace, workspace_bytes, stream);
 }
 
 size_t fk_boundary_workspace_bytes(int32_t n) {
@@ -1391,8 +1367,8 @@ int fk_boundary_data(const fk_density *w, double t_w, int32_t n, int32_t bdry_ki
     a.xi_out = xi_out;
     a.eta_out = eta_out;
     a.N = n;
-    a.m = n;
-    a.px = 1;
+    a.px = a.py = 1;
+    a.mx = a.my = n;
     a.kind = w->kind;
     a.amp = w->amp;
     a.width2 = w->width2;

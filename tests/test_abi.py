@@ -183,3 +183,20 @@ def test_noalloc_rejects_sizes_beyond_its_scratch(fk):
                                         8, 8, 8, 8, None, None, None, None, None, None)
     assert rc == -3
     assert "scratch" in fk.fk_last_error()
+
+
+def test_subdomain_layout_validation(fk):
+    """px x py splits: px and py must divide N, sub-domains need 2 cells a
+    side and at most 128 on the shorter one; checked before any device use."""
+    lib = fk.library()
+    assert fk.subdomain_workspace_bytes_rect(2, 3, 48) > 0
+    assert fk.subdomain_workspace_bytes_rect(2, 3, 50) == 0          # 3 does not divide 50
+    assert fk.subdomain_workspace_bytes_rect(1, 1, 129) == 0         # 129 cells on the shorter side
+    assert fk.subdomain_workspace_bytes_rect(1, 2, 256) > 0          # 256 x 128: the shorter side is 128
+    assert fk.subdomain_workspace_bytes_rect(4, 1, 4) == 0           # 1-cell-wide sub-domains
+    assert fk.subdomain_workspace_bytes(8, 96) == fk.subdomain_workspace_bytes_rect(8, 8, 768)
+    dens = ctypes.byref(fk._density(W.static_bump()))
+    for px, py, n, code in ((2, 3, 50, -1), (0, 1, 8, -1), (1, 1, 258, -5), (4, 4, 4, -1)):
+        rc = lib.subdomain_solve_rect(dens, 0.0, 0.01, px, py, n, 0, 8, 8, 8, 8, 8, 8, 8, 1 << 30, None)
+        assert rc == code, (px, py, n, rc)
+        assert fk.fk_last_error() != ""

@@ -34,7 +34,8 @@ def cuda(a):
     (4, 64, W.moving_bump(), 0.0, 0.1),          # 4x4 layout on 64x64 grids
     (8, 96, W.two_bumps(W.TIME_FROZEN, 0.05), 0.05, 5e-4),  # 8x8 layout on 96x96 grids
     # every side of the one-wavefront eliminations: 12 (whole system), 16
-    # and 24 (both ends, separator), 48 and 40 (lane-pair kernel)
+    # and 24 (both ends, separator); 48 and 40 on the tile kernel (40: a
+    # window narrower than its 48 lanes)
     (3, 12, W.moving_bump(), 0.07, 0.01),
     (2, 16, W.paper_ring(W.TIME_FROZEN, 0.6), 0.6, 1e-3),
     (3, 24, W.two_bumps(W.TIME_FROZEN, 0.01), 0.01, 2e-3),
@@ -57,6 +58,44 @@ def test_subdomain_against_oracle(fk, px, m, dens, t_w, D):
     err = max(np.abs(gx.cpu().numpy() - ox).max(), np.abs(gy.cpu().numpy() - oy).max())
     print(f"max |gpu - oracle| = {err:.3e}", flush=True)
     assert err < 1e-12
+
+
+@pytest.mark.parametrize("px,py,N,dens,t_w,D", [
+    (2, 3, 48, W.moving_bump(), 0.04, 0.02),             # 24 x 16 cells: y is the fast index, 16-wide window
+    (4, 1, 64, W.static_bump(), 0.0, 0.05),              # 16 x 64: x fast, one row of sub-domains
+    (1, 2, 96, W.two_bumps(W.TIME_FROZEN, 0.03), 0.03, 5e-4),   # 96 x 48: tile kernel, 48-wide window
+    (3, 2, 150, W.moving_bump(), 0.02, 0.01),            # 50 x 75: window 50 in a 64-lane-row tile
+    (8, 6, 768, W.two_bumps(W.TIME_FROZEN, 0.05), 0.05, 5e-4),  # 96 x 128: the 768-cell grid, 48 sub-domains
+    (1, 1, 120, W.ridge(), 0.0, 0.02),                   # one 120 x 120 domain: the widest window
+    (3, 5, 30, W.static_bump(), 0.0, 0.05),              # 10 x 6: one end, no separator
+    # 2 x 8 cells: one unknown across, a column of 7 (the fast and slow neighbours share a band offset)
+    (4, 1, 8, W.Density(W.KIND_BUMP, W.TIME_FROZEN, amp=0.5, width2=0.05, cx=0.4, cy=0.6), 0.0, 0.05),
+])
+def test_subdomain_rect_against_oracle(fk, px, py, N, dens, t_w, D):
+    """px x py splits (sub-domains wider than tall and taller than wide)."""
+    import torch
+    xi0, eta0 = prev_mesh(N)
+    rng = np.random.default_rng(px * 1000 + py * 10 + N)
+    ij = S.interface_index_rect(px, py, N)
+    assert len(ij) == fk.n_interface_nodes_rect(px, py, N)
+    ix = xi0[ij[:, 1], ij[:, 0]] + 1e-3 * rng.standard_normal(len(ij))
+    iy = eta0[ij[:, 1], ij[:, 0]] + 1e-3 * rng.standard_normal(len(ij))
+    print(f"[gpu] subdomain rect px={px} py={py} N={N} kind={dens.kind}", flush=True)
+    e = torch.empty(0, dtype=torch.float64, device="cuda")
+    gx, gy = fk.subdomain_solve_rect(dens, t_w, D, px, py, N, cuda(xi0), cuda(eta0), cuda(ix) if len(ij) else e,
+                                     cuda(iy) if len(ij) else e)
+    torch.cuda.synchronize()
+    ox, oy = S.subdomain_be_step_rect(dens, t_w, D, px, py, N, xi0, eta0, ix, iy)
+    err = max(np.abs(gx.cpu().numpy() - ox).max(), np.abs(gy.cpu().numpy() - oy).max())
+    print(f"max |gpu - oracle| = {err:.3e}", flush=True)
+    assert err < 1e-12
+    if (px, py) == (8, 6):
+        # the exact domain-decomposition identity at full size
+        gxi, geta = S.global_be_step(dens, t_w, D, N, xi0, eta0)
+        sx, sy = fk.subdomain_solve_rect(dens, t_w, D, px, py, N, cuda(xi0), cuda(eta0),
+                                         cuda(gxi[ij[:, 1], ij[:, 0]]), cuda(geta[ij[:, 1], ij[:, 0]]))
+        torch.cuda.synchronize()
+        assert np.abs(sx.cpu().numpy() - gxi).max() < 1e-12 and np.abs(sy.cpu().numpy() - geta).max() < 1e-12
 
 
 @pytest.mark.parametrize("px,m,dens,t_w,D", [

@@ -67,11 +67,32 @@ def test_exact_domain_decomposition_identity(px, m, dens):
     assert np.abs(gxi - xi0).max() > 1e-4
 
 
+@pytest.mark.parametrize("px,py,N,dens", [(2, 3, 24, W.moving_bump()), (4, 1, 24, W.static_bump()),
+                                          (1, 3, 18, W.two_bumps(W.TIME_FROZEN, 0.03)),
+                                          (3, 2, 30, W.paper_ring(W.TIME_FROZEN, 0.1))])
+def test_exact_domain_decomposition_identity_rect(px, py, N, dens):
+    """The same identity for px x py splits (sub-domains wider than tall and
+    taller than wide, a single row or column of them)."""
+    X, Y = grid(N)
+    xi0 = X + 0.02 * np.sin(math.pi * X) * np.sin(2 * math.pi * Y)
+    eta0 = Y + 0.015 * np.sin(2 * math.pi * X) * np.sin(math.pi * Y)
+    gxi, geta = S.global_be_step(dens, 0.04, 0.02, N, xi0, eta0)
+    ij = S.interface_index_rect(px, py, N)
+    assert len(ij) == (px - 1) * (N - 1) + (py - 1) * (N - px)
+    sxi, seta = S.subdomain_be_step_rect(dens, 0.04, 0.02, px, py, N, xi0, eta0, gxi[ij[:, 1], ij[:, 0]],
+                                         geta[ij[:, 1], ij[:, 0]])
+    assert np.abs(sxi - gxi).max() < 1e-12 and np.abs(seta - geta).max() < 1e-12
+    assert np.abs(gxi - xi0).max() > 1e-4
+
+
 def test_interface_index_matches_canonical_nodes():
     for px, m in ((2, 16), (4, 64), (8, 96)):
         ij = S.interface_index(px, m)
         pts = W.interface_nodes(px, px, px * m)
         assert np.array_equal(ij / (px * m), pts)
+    for px, py, N in ((2, 4, 128), (8, 3, 96), (5, 7, 140)):
+        ij = S.interface_index_rect(px, py, N)
+        assert np.array_equal(ij / N, W.interface_nodes(px, py, N))
 
 
 def test_mesh_quality_closed_forms():
