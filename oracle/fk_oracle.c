@@ -45,6 +45,9 @@
  *    u1 = ((r >> 8) + 1) 2^-24 in (0,1], u2 = (r >> 8) 2^-24 in [0,1).
  *  - step sizes: K = ceil(t/dt), every step dt except the last, which is
  *    t - (K-1) dt.
+ *  - exponential time-stepping (score mode 4; Sect. 4 names it as the
+ *    alternative to the fixed steps, after Jansons & Lythe 2003): see
+ *    run_path_expo.
  */
 #include <math.h>
 #include <stdint.h>
@@ -352,7 +355,7 @@ static void boundary_value(const or_data *d, double elapsed, double x, double y,
         *eta = bilinear(d->grid_eta, d->grid_n, x, y);
         return;
     }
-    if (d->score_mode == 1 || d->score_mode == 3) {
+    if (d->score_mode == 1 || d->score_mode == 3 || d->score_mode == 4) {
         x = x < 0.0 ? 0.0 : (x > 1.0 ? 1.0 : x);
         y = y < 0.0 ? 0.0 : (y > 1.0 ? 1.0 : y);
     }
@@ -406,7 +409,7 @@ static int bridge_exit(const or_problem *pb, int64_t k, uint32_t path, uint32_t 
     int side = -1;
     for (int i = 0; i < 4; ++i) {
         const double e = d0[i] * d1[i] / D;
-        if (e > 17.0) continue;
+        if (!(e <= 17.0)) continue;   /* also a zero-length step on a side: 0/0 */
         const double ps = exp(-e);
         surv *= 1.0 - ps;
         if (ps > pmax) { pmax = ps; side = i; }
@@ -455,6 +458,75 @@ static int64_t run_path(const or_problem *pb, double px, double py, uint32_t pat
     return -1;
 }
 
+/* ---------------------------------------------------------------------------
+ * Exponential time-stepping (score mode 4).  Reading of the method of
+ * Jansons & Lythe (2003) for this problem: the steps have independent
+ * exponentially distributed lengths D_k with mean dt, and the step that
+ * would pass the horizon t is cut at it (so a path that never exits takes
+ * 1 + Poisson(t / dt) steps).  Given D_k, the step is the Euler-Maruyama
+ * step of that length with the drift frozen at its start, and the exit test
+ * within the step is the Brownian-bridge test of mode 3 for a step of
+ * length D_k.  For Brownian motion with constant drift this gives the end
+ * point and the crossing event of a step over an exponential time exactly
+ * (the Gaussian-bridge test given D_k averages to the exponential law of
+ * the running maximum given the end point); it leaves the drift's variation
+ * within a step as the only time-step error.  Exits are scored at the end
+ * point projected onto the square.  Random numbers of step k: the normals
+ * of the fixed-step scheme (stream word 3 = ctr3), and from
+ * Philox(k/2, path, node, ctr3 | 4) word (k & 1) the bridge uniform (as in
+ * mode 3) and word 2 + (k & 1), u = ((r >> 8) + 1) 2^-24 in (0, 1], the
+ * step length D_k = -dt ln u.  *steps receives the number of steps taken.
+ * ------------------------------------------------------------------------- */
+static int64_t run_path_expo(const or_problem *pb, double px, double py, uint32_t path, uint32_t node,
+                             double *score_xi, double *score_eta, int64_t *steps)
+{
+    double x = px, y = py, s = 0.0;
+    *steps = 0;
+    if (!(pb->t > 0.0)) {
+        initial_value(&pb->data, x, y, score_xi, score_eta);
+        return -1;
+    }
+    for (int64_t k = 0;; ++k) {
+        uint32_t ctr[4] = {(uint32_t)(k >> 1), path, node, pb->ctr3}, r[4];
+        or_philox4x32_10(ctr, pb->key, r);
+        uint32_t ctr_u[4] = {(uint32_t)(k >> 1), path, node, pb->ctr3 | 4u}, q[4];
+        or_philox4x32_10(ctr_u, pb->key, q);
+        double z0, z1;
+        if ((k & 1) == 0) box_muller(r[0], r[1], &z0, &z1);
+        else box_muller(r[2], r[3], &z0, &z1);
+        const double u = ((double)(q[2 + (k & 1)] >> 8) + 1.0) * 0x1p-24;
+        double D = -pb->dt * log(u);
+        const int last = s + D >= pb->t;
+        if (last) D = pb->t - s;
+        const double tau = (pb->time_mode == 0) ? pb->t_init + pb->t - s : pb->par[6];
+        double bx, by;
+        drift(&pb->dens, tau, x, y, &bx, &by);
+        const double sd = sqrt(2.0 * D);
+        const double x0 = x, y0 = y;
+        x = x + bx * D + sd * z0;
+        y = y + by * D + sd * z1;
+        s = last ? pb->t : s + D;
+        *steps = k + 1;
+        if (x < 0.0 || x > 1.0 || y < 0.0 || y > 1.0 || bridge_exit(pb, k, path, node, D, x0, y0, &x, &y)) {
+            boundary_value(&pb->data, pb->t - s, x, y, score_xi, score_eta);
+            return k + 1;
+        }
+        if (last) break;
+    }
+    initial_value(&pb->data, x, y, score_xi, score_eta);
+    return -1;
+}
+
+/* One path of the problem's scheme; *steps receives the steps it took. */
+static int64_t run_path_any(const or_problem *pb, double px, double py, uint32_t path, uint32_t node,
+                            double *score_xi, double *score_eta, int64_t *steps)
+{
+    if (pb->data.score_mode == 4) return run_path_expo(pb, px, py, path, node, score_xi, score_eta, steps);
+    const int64_t e = run_path(pb, px, py, path, node, score_xi, score_eta);
+    *steps = e < 0 ? pb->K : e;
+    return e;
+}
+
 static int64_t n_steps(double t, double dt)
 {
     if (t <= 0.0) return 0;
@@ -490,8 +562,8 @@ int or_fk_solve(int kind, int time_mode, const double *par, const double *w_grid
     pb.data.init_kind = init_kind;
     pb.data.bdry_kind = bdry_kind;
     pb.data.score_mode = score_mode;
-    if (score_mode < 0 || score_mode > 3 || (score_mode == 2 && (init_kind != D_GRID || !grid_xi || !grid_eta)) ||
-        (bdry_kind == D_GRID && (init_kind != D_GRID || (score_mode != 1 && score_mode != 3))))
+    if (score_mode < 0 || score_mode > 4 || (score_mode == 2 && (init_kind != D_GRID || !grid_xi || !grid_eta)) ||
+        (bdry_kind == D_GRID && (init_kind != D_GRID || (score_mode != 1 && score_mode != 3 && score_mode != 4))))
         return -1;
     pb.data.grid_xi = grid_xi;
     pb.data.grid_eta = grid_eta;
@@ -519,10 +591,11 @@ int or_fk_solve(int kind, int time_mode, const double *par, const double *w_grid
         int64_t i = g / n_paths, p = g % n_paths;
         uint32_t nid = (uint32_t)(node_ids ? node_ids[i] : i);
         double a, b;
-        int64_t e = run_path(&pb, pts[2 * i], pts[2 * i + 1], (uint32_t)p, nid, &a, &b);
+        int64_t ns;
+        int64_t e = run_path_any(&pb, pts[2 * i], pts[2 * i + 1], (uint32_t)p, nid, &a, &b, &ns);
         sc[2 * g] = a;
         sc[2 * g + 1] = b;
-        st[g] = (e < 0) ? pb.K : e;
+        st[g] = ns;
         if (exit_step) exit_step[g] = (int32_t)e;
     }
     /* Two-pass sample mean and variance per node and component. */
@@ -572,8 +645,8 @@ int or_fk_paths(int kind, int time_mode, const double *par, const double *w_grid
     pb.data.init_kind = init_kind;
     pb.data.bdry_kind = bdry_kind;
     pb.data.score_mode = score_mode;
-    if (score_mode < 0 || score_mode > 3 || (score_mode == 2 && (init_kind != D_GRID || !grid_xi || !grid_eta)) ||
-        (bdry_kind == D_GRID && (init_kind != D_GRID || (score_mode != 1 && score_mode != 3))))
+    if (score_mode < 0 || score_mode > 4 || (score_mode == 2 && (init_kind != D_GRID || !grid_xi || !grid_eta)) ||
+        (bdry_kind == D_GRID && (init_kind != D_GRID || (score_mode != 1 && score_mode != 3 && score_mode != 4))))
         return -1;
     pb.data.grid_xi = grid_xi;
     pb.data.grid_eta = grid_eta;
@@ -591,7 +664,9 @@ int or_fk_paths(int kind, int time_mode, const double *par, const double *w_grid
 #endif
     for (int64_t j = 0; j < m; ++j) {
         double a, b;
-        int64_t e = run_path(&pb, pts[2 * j], pts[2 * j + 1], (uint32_t)path_ids[j], (uint32_t)node_ids[j], &a, &b);
+        int64_t ns;
+        int64_t e = run_path_any(&pb, pts[2 * j], pts[2 * j + 1], (uint32_t)path_ids[j], (uint32_t)node_ids[j], &a, &b,
+                                 &ns);
         scores[2 * j] = a;
         scores[2 * j + 1] = b;
         exit_step[j] = (int32_t)e;

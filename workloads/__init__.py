@@ -50,6 +50,7 @@ SCORE_UNCLAMPED = 0   # evaluate the boundary data at the (unclamped) first outs
 SCORE_PROJECT = 1     # clamp that point onto the closed square first
 SCORE_EXTEND = 2      # the grid initial data continued bilinearly to that point
 SCORE_BRIDGE = 3      # Brownian-bridge exit test within each step; exits scored at the projected point
+SCORE_EXPONENTIAL = 4  # exponentially distributed step lengths (mean dt) with the bridge test; exits projected
 
 # Philox stream tags (low 4 bits of the last counter word).
 STREAM_PATHS = 0
