@@ -337,23 +337,27 @@ def measure_paper_run():
 
 
 def measure_bridge(fk, wl, pts, fd, pilot_paths=100000):
-    """The headline workload with the Brownian-bridge exit test, at the
-    configured dt and at coarser steps (plain discrete test beside it): a
-    pilot gives the variance and the bias against the FD reference, N* the
-    paths for RMS 1e-3, and one timed solve at N* the rate."""
+    """The headline workload with the Brownian-bridge exit test and with
+    exponential time-stepping, at the configured dt and at coarser steps
+    (plain discrete test beside them): a pilot gives the variance and the
+    bias against the FD reference, N* the paths for RMS 1e-3, and one timed
+    solve at N* the rate."""
     import dataclasses
 
     import torch
     pts = torch.tensor(pts, dtype=torch.float64, device="cuda")     # resident coordinates
     res = []
-    for dt, bridge in ((1e-5, True), (4e-5, False), (4e-5, True), (1e-4, False), (1e-4, True)):
-        data = dataclasses.replace(wl.data, score_mode=W.SCORE_BRIDGE if bridge else wl.data.score_mode)
-        print(f"[bench] bridge leg: dt {dt:g}, bridge {bridge}", file=sys.stderr, flush=True)
+    modes = {"discrete": wl.data.score_mode, "bridge": W.SCORE_BRIDGE, "exponential": W.SCORE_EXPONENTIAL}
+    for dt, mode in ((1e-5, "bridge"), (4e-5, "discrete"), (4e-5, "bridge"), (4e-5, "exponential"),
+                     (1e-4, "discrete"), (1e-4, "bridge"), (1e-4, "exponential"), (2.5e-4, "exponential")):
+        bridge = mode == "bridge"
+        data = dataclasses.replace(wl.data, score_mode=modes[mode])
+        print(f"[bench] bridge leg: dt {dt:g}, {mode}", file=sys.stderr, flush=True)
         r = fk.fk_interface_solve(wl.density, data, pts, wl.t, dt, pilot_paths, wl.seed)
         est, se = _stack(r, ("xi", "eta")), _stack(r, ("se_xi", "se_eta"))
         var = float(np.mean(se ** 2) * pilot_paths)
         b2 = max(0.0, float(np.mean((est - fd[:, 2:4]) ** 2)) - var / pilot_paths)
-        row = {"dt": dt, "bridge": bridge, "var": var, "bias": math.sqrt(b2)}
+        row = {"dt": dt, "mode": mode, "bridge": bridge, "var": var, "bias": math.sqrt(b2)}
         if b2 < 0.9e-6:
             n_star = int(math.ceil(var / (1e-6 - b2)))
             fk.fk_timing_enable(True)
@@ -372,7 +376,8 @@ def measure_bridge(fk, wl, pts, fd, pilot_paths=100000):
             row["note"] = "bias above 0.95e-3: RMS 1e-3 out of reach at this dt"
         res.append(row)
     return {"workload": "moving_bump_1521 (t = 0.1), identity data; bridge: Brownian-bridge exit test, "
-                        "exits projected; pilot 1e5 paths", "runs": res}
+                        "exits projected; exponential: exponential step lengths of mean dt with the bridge test; "
+                        "pilot 1e5 paths", "runs": res}
 
 
 def measure_steady():

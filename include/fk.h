@@ -96,6 +96,15 @@ extern "C" {
                                  Every exit is scored at the point clamped onto the square.  For w = 1
                                  the killed chain then has the law of the killed diffusion at any step
                                  size.  Plain solves only (fk_interface_solve, batches) */
+#define FK_SCORE_EXPONENTIAL 4  /* exponential time-stepping (Sect. 4's alternative to the fixed steps,
+                                 after Jansons & Lythe 2003): step lengths D_k exponentially distributed
+                                 with mean dt, D_k = -dt ln u with u = ((r >> 8) + 1) 2^-24 from word
+                                 2 + (k & 1) of Philox(k/2, path, node, ctr3 | 4), the step that would
+                                 pass the horizon cut at it (a path that stays inside takes
+                                 1 + Poisson(t/dt) steps); given D_k the Euler-Maruyama step of that
+                                 length and the bridge test of FK_SCORE_BRIDGE with D_k for dt; exits
+                                 scored at the projected point.  Single solves only (the batched and
+                                 control-variate solves return FK_E_UNSUPPORTED) */
 
 /* Density parameters (plain values; for FK_DENSITY_GRID also two device arrays). */
 typedef struct fk_density {

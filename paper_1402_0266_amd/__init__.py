@@ -360,6 +360,10 @@ def _device_mask(mask, n, dev):
 
 
 def _stream(torch, device):
+    # torch's current stream on a GPU device; no stream for host tensors (the
+    # library then fails its argument checks or finds no device, and says so)
+    if torch.device(device).type != "cuda":
+        return None
     return ctypes.c_void_p(torch.cuda.current_stream(device).cuda_stream)
 
 

@@ -75,10 +75,11 @@ int validate_data(const fk_data *d) {
     if (d->bdry_kind < 0 || d->bdry_kind > FK_DATA_GRID)
         return fail(FK_E_INVAL, "unknown boundary kind %d", d->bdry_kind);
     if (d->score_mode != FK_SCORE_UNCLAMPED && d->score_mode != FK_SCORE_PROJECT && d->score_mode != FK_SCORE_EXTEND &&
-        d->score_mode != FK_SCORE_BRIDGE)
+        d->score_mode != FK_SCORE_BRIDGE && d->score_mode != FK_SCORE_EXPONENTIAL)
         return fail(FK_E_INVAL, "unknown score mode %d", d->score_mode);
     if (d->bdry_kind == FK_DATA_GRID &&
-        (d->init_kind != FK_DATA_GRID || (d->score_mode != FK_SCORE_PROJECT && d->score_mode != FK_SCORE_BRIDGE)))
+        (d->init_kind != FK_DATA_GRID || (d->score_mode != FK_SCORE_PROJECT && d->score_mode != FK_SCORE_BRIDGE &&
+                                          d->score_mode != FK_SCORE_EXPONENTIAL)))
         return fail(FK_E_INVAL, "grid boundary data needs grid initial data and a projecting score mode");
     if (d->score_mode == FK_SCORE_EXTEND && d->init_kind != FK_DATA_GRID)
         return fail(FK_E_INVAL, "score mode EXTEND needs grid initial data");
@@ -309,14 +310,17 @@ int enqueue_solve(const SolveLaunch &S, hipStream_t stream, bool allow_timing) {
     a.cpn = (uint32_t)cpn;
     a.total_chunks = (uint32_t)(S.n_nodes * cpn);
     int bpc = S.plan.blocks_per_cu;
-    const int occ = path_kernel_max_blocks_per_cu(S.kind, S.time_mode, S.uniform, a.score_mode == FK_SCORE_BRIDGE,
-                                                  S.first_by_index, S.plan.block);
+    const bool expo = a.score_mode == FK_SCORE_EXPONENTIAL;
+    const int occ = expo ? expo_kernel_max_blocks_per_cu(S.kind, S.time_mode, S.plan.block)
+                         : path_kernel_max_blocks_per_cu(S.kind, S.time_mode, S.uniform,
+                                                         a.score_mode == FK_SCORE_BRIDGE, S.first_by_index,
+                                                         S.plan.block);
     if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
     const int grid = cap_grid(n_cu * bpc, a.total_chunks, S.plan.block);
     if ((e = timing_mark(timed, 0, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
-    if ((e = launch_paths(S.kind, S.time_mode, S.uniform, S.first_by_index, a, grid, S.plan.block, stream)) !=
-        hipSuccess)
-        return hip_fail(e, "path kernel launch");
+    e = expo ? launch_expo_paths(S.kind, S.time_mode, a, grid, S.plan.block, stream)
+             : launch_paths(S.kind, S.time_mode, S.uniform, S.first_by_index, a, grid, S.plan.block, stream);
+    if (e != hipSuccess) return hip_fail(e, "path kernel launch");
     if ((e = timing_mark(timed, 1, stream)) != hipSuccess) return hip_fail(e, "hipEventRecord");
     FinalArgs f = S.fin;
     f.acc = a.acc;
@@ -476,7 +480,7 @@ int fk_interface_solve(const fk_density *w, const fk_data *d, const double *pts,
     // first chunk by its grid index, and by default 256 paths per grab,
     // which halves the wavefronts' fixed costs per path; long ones 128, for
     // the balance of the tail.
-    S.first_by_index = level.K <= 64;
+    S.first_by_index = level.K <= 64 && d->score_mode != FK_SCORE_EXPONENTIAL;
     if ((!plan || plan->chunk == 0) && S.first_by_index) S.plan.chunk = 256;
     S.n_nodes = n_nodes;
     S.n_paths = n_paths;

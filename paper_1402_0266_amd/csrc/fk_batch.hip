@@ -94,6 +94,8 @@ int fk_batch_create(const fk_level *levels, int32_t n_levels, const double *pts,
     int rc;
     if (n_levels < 1 || !levels) return fail(FK_E_INVAL, "need at least one level");
     if ((rc = validate_data(d)) != FK_OK) return rc;
+    if (d->score_mode == FK_SCORE_EXPONENTIAL)
+        return fail(FK_E_UNSUPPORTED, "exponential time-stepping is for single plain solves only");
     if ((rc = validate_common(n_paths, dt)) != FK_OK) return rc;
     if ((rc = validate_points(pts, n_total)) != FK_OK) return rc;
     std::vector<LevelSpec> spec((size_t)n_levels);

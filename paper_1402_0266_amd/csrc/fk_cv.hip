@@ -1763,6 +1763,8 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     if ((rc = validate_data(d)) != FK_OK) return rc;
     if (d->score_mode == FK_SCORE_BRIDGE)
         return fail(FK_E_UNSUPPORTED, "the Brownian-bridge exit test is for plain solves only");
+    if (d->score_mode == FK_SCORE_EXPONENTIAL)
+        return fail(FK_E_UNSUPPORTED, "exponential time-stepping is for single plain solves only");
     if ((rc = validate_common(n_paths, dt)) != FK_OK) return rc;
     if ((rc = validate_horizon(t, d->t_init, dt, level_id)) != FK_OK) return rc;
     if ((rc = validate_device_points(pts, n_nodes)) != FK_OK) return rc;

@@ -200,5 +200,8 @@ hipError_t launch_counters_init(uint32_t *counters, uint32_t total_chunks, hipSt
 // Bytes of the per-node estimator sums of n_out rows.
 size_t acc_bytes(int64_t n_out);
 int path_kernel_max_blocks_per_cu(int kind, int time_mode, bool uniform, bool bridge, bool first_by_index, int block);
+// Exponential time-stepping (FK_SCORE_EXPONENTIAL): its own path kernel.
+hipError_t launch_expo_paths(int kind, int time_mode, const PathArgs &a, int grid, int block, hipStream_t s);
+int expo_kernel_max_blocks_per_cu(int kind, int time_mode, int block);
 
 }  // namespace fk

@@ -297,6 +297,128 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
     if (lane == 0 && st != 0ull) atomicAdd(a.total_steps, st);
 }
 
+// Exponential time-stepping (FK_SCORE_EXPONENTIAL): the same persistent
+// queue and in-kernel estimator as fk_path_kernel; each step has its own
+// length D = -dt ln u (u from word 2 + (k & 1) of Philox(k/2, path, node,
+// ctr3 | 4)), cut at the horizon, then the Euler-Maruyama step of length D
+// and the bridge test for D with that Philox call's word k & 1.  The elapsed
+// time is kept as a hi + lo pair; the orbit angle of a moving density at
+// PDE time t_init + t - s follows it.  A path ends when it exits or when
+// the cut step has been taken (L.K is set to the step count then).
+template <int KIND, int TMODE>
+__global__ void __launch_bounds__(256) fk_expo_path_kernel(const PathArgs a) {
+    constexpr bool kMovingBackward = moving_kind(KIND) && TMODE == TIME_BACKWARD;
+    const uint32_t lane = threadIdx.x & 63u;
+    __shared__ AccSlot<2> slot_tab[4][kAccSlots];
+    AccSlot<2> *slots = slot_tab[threadIdx.x >> 6];
+    NodeAcc *const accs[1] = {a.acc};
+    slots_init<2>(slots, lane);
+    uint32_t q_slot = 0, q_next = 0, q_end = 0, q_tag = 0, grabs = 0;
+    bool q_done = false;
+    const uint32_t total_chunks = launch_chunks(a);
+    const uint32_t key0 = a.key0, key1 = a.key1;
+    Lane L;
+    bool active = false;
+    uint32_t my_tag = 0, my_steps = 0;
+    bool closed = false;
+    for (;;) {
+        if (__ballot(closed) != 0ull) {
+            slots_collect<2>(slots, accs, lane);
+            closed = false;
+        }
+        uint64_t need = __ballot(!active);
+        while (need != 0ull && !q_done) {
+            if (q_next >= q_end) {
+                uint32_t c = 0;
+                if (lane == 0) c = atomicAdd(a.queue, 1u);
+                c = __builtin_amdgcn_readfirstlane(c);
+                if (!grab_chunk<2>(a, total_chunks, c, q_slot, q_next, q_end, slots, accs, q_tag, grabs, lane)) {
+                    q_done = true;
+                    break;
+                }
+                continue;
+            }
+            const uint32_t avail = q_end - q_next;
+            const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(need >> 32),
+                                                            __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
+            if (!active && rank < avail) {
+                lane_start<KIND, TMODE>(L, a.nodes[q_slot], a.levels, q_next + rank);
+                L.K = L.K > 0 ? 0x7fffffff : 0;      // open-ended; 0 for a zero horizon
+                L.s_hi = 0.f;
+                L.s_lo = 0.f;
+                my_tag = q_tag;
+                active = true;
+            }
+            q_next += min((uint32_t)__popcll(need), avail);
+            need = __ballot(!active);
+        }
+        if (__ballot(active) == 0ull) break;
+
+        if (active) {
+            bool out = false;
+            if (L.k < L.K) {
+                const PhiloxOut r = philox4x32_10((uint32_t)L.k >> 1, L.path, L.nid, L.ctr3, key0, key1);
+                const PhiloxOut q = philox4x32_10((uint32_t)L.k >> 1, L.path, L.nid, L.ctr3 | 4u, key0, key1);
+                const bool odd = (L.k & 1) != 0;
+                const float u = fmaf((float)((odd ? q.r3 : q.r2) >> 8), 0x1p-24f, 0x1p-24f);
+                float D = -0.69314718f * L.dt * hw_log2(u);
+                const float rem = (L.horizon - L.s_hi) - L.s_lo;
+                const bool last = D >= rem;
+                D = last ? rem : D;
+                float ox = L.ox, oy = L.oy;
+                if constexpr (kMovingBackward) {
+                    const float rev = fmaf(-L.s_hi, L.dens.omega_rev, L.rev0);
+                    ox = L.dens.orbit_r * hw_cos_rev(rev);
+                    oy = L.dens.orbit_r * hw_sin_rev(rev);
+                }
+                float dwx, dwy;
+                brownian_increment(odd ? r.r2 : r.r0, odd ? r.r3 : r.r1, -2.77258872f * D, dwx, dwy);
+                float bx, by;
+                drift<KIND>(L.dens, ox, oy, L.xh, L.yh, bx, by);
+                const float x0h = L.xh, x0l = L.xl, y0h = L.yh, y0l = L.yl;
+                comp_add(L.xh, L.xl, fmaf(bx, D, dwx));
+                comp_add(L.yh, L.yl, fmaf(by, D, dwy));
+                if (last) {
+                    L.s_hi = L.horizon;
+                    L.s_lo = 0.f;
+                } else {
+                    comp_add(L.s_hi, L.s_lo, D);
+                }
+                L.k += 1;
+                my_steps += 1;
+                const float lo = fminf(L.xh, L.yh);
+                const float hi = fmaxf((L.xh - 1.f) + L.xl, (L.yh - 1.f) + L.yl);
+                out = (lo < 0.f) | (hi > 0.f);
+                if (!out) {
+                    int side;
+                    const float p = bridge_prob(L, x0h, x0l, y0h, y0l, 1.f / D, side);
+                    if (side >= 0) {
+                        const float ub = fmaf((float)((odd ? q.r1 : q.r0) >> 8), 0x1p-24f, 0x1p-24f);
+                        if (ub < p) {
+                            move_to_side(L, side);
+                            out = true;
+                        }
+                    }
+                }
+                if (last) L.K = L.k;
+            }
+            if (out || L.k >= L.K) {
+                float v[2];
+                score_path(a, L, out, v[0], v[1]);
+                closed = acc_path<2>(slots, accs, my_tag, L.out, v, (uint32_t)L.k);
+                if (a.scores) a.scores[path_rec(L, a.n_paths)] = make_float2(v[0], v[1]);
+                if (a.exit_step) a.exit_step[path_rec(L, a.n_paths)] = out ? L.k : -1;
+                active = false;
+            }
+        }
+    }
+    slots_collect<2>(slots, accs, lane);
+    unsigned long long st = my_steps;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) st += __shfl_xor(st, off, 64);
+    if (lane == 0 && st != 0ull) atomicAdd(a.total_steps, st);
+}
+
 namespace {
 template <int KIND, int TMODE, bool UNIFORM, bool BRIDGE, bool FIRST>
 hipError_t launch_one(const PathArgs &a, int grid, int block, hipStream_t s) {
@@ -372,6 +494,37 @@ int path_kernel_max_blocks_per_cu(int kind, int time_mode, bool uniform, bool br
                                   int block) {
     if (!kind_known(kind)) return 0;
     return dispatch<OccF>(kind, time_mode, uniform, bridge, first_by_index, block);
+}
+
+namespace {
+template <int K, int T, bool U, bool B, bool F>
+struct ExpoLaunchF {
+    static hipError_t run(const PathArgs &a, int grid, int block, hipStream_t s) {
+        hipLaunchKernelGGL((fk_expo_path_kernel<K, T>), dim3(grid), dim3(block), 0, s, a);
+        return hipGetLastError();
+    }
+};
+template <int K, int T, bool U, bool B, bool F>
+struct ExpoOccF {
+    static int run(int block) {
+        int nb = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk_expo_path_kernel<K, T>, block, 0) != hipSuccess)
+            return 0;
+        return nb;
+    }
+};
+}  // namespace
+
+// The kind / time-mode dispatch of the fixed-step kernels, with one
+// instantiation per pair (uniform, bridge and first-chunk flags unused).
+hipError_t launch_expo_paths(int kind, int time_mode, const PathArgs &a, int grid, int block, hipStream_t s) {
+    if (!kind_known(kind)) return hipErrorInvalidValue;
+    return dispatch<ExpoLaunchF>(kind, time_mode, false, false, false, a, grid, block, s);
+}
+
+int expo_kernel_max_blocks_per_cu(int kind, int time_mode, int block) {
+    if (!kind_known(kind)) return 0;
+    return dispatch<ExpoOccF>(kind, time_mode, false, false, false, block);
 }
 
 // ---------------------------------------------------------------------------

@@ -23,6 +23,7 @@ struct Lane {
     float horizon, dt, dt_last, cbm, cbm_last;
     float ox, oy;          // frozen / static centre offset
     float rev0, drev, cos_d, sin_d;  // orbit angle at path start, step, rotation
+    float s_hi, s_lo;      // exponential time-stepping: elapsed time as a hi + lo pair
     DensityRegs dens;
 };
 
@@ -73,25 +74,19 @@ __device__ __forceinline__ bool em_step(Lane &L, uint32_t ra, uint32_t rb, float
 }
 
 // Brownian-bridge exit test of the step just taken (from (x0h + x0l,
-// y0h + y0l) to the lane's position, both inside).  The diffusion sqrt(2) W
-// pinned at both ends crosses a side at distances d0, d1 with probability
-// exp(-d0 d1 / D); the four sides combine as independent events.  A side
-// whose exponent d0 d1 / D exceeds 17 counts as 0 (below the uniforms'
-// resolution 2^-24), so lanes away from the boundary skip the uniform.  The
-// uniform of step k is word (k & 1) of Philox(k/2, path, node, ctr3 | 4),
-// u = ((r >> 8) + 1) 2^-24; on u < p the path has left within the step and
-// is moved onto the side it most likely crossed (its end point projected).
-template <bool UNIFORM>
-__device__ __forceinline__ bool bridge_exit(Lane &L, float x0h, float x0l, float y0h, float y0l, uint32_t key0,
-                                            uint32_t key1) {
-    const int32_t k = L.k - 1;
-    float D = L.dt;
-    if constexpr (!UNIFORM) D = (k == L.K - 1) ? L.dt_last : D;
-    const float iD = 1.f / D;
+// y0h + y0l) to the lane's position, both inside), for a step of length D
+// (iD = 1/D).  The diffusion sqrt(2) W pinned at both ends crosses a side at
+// distances d0, d1 with probability exp(-d0 d1 / D); the four sides combine
+// as independent events.  A side whose exponent d0 d1 / D exceeds 17 counts
+// as 0 (below the uniforms' resolution 2^-24; a zero-length step on a side,
+// 0/0, too).  Returns the crossing probability and the side most likely
+// crossed (-1: none within reach, and the caller needs no uniform).
+__device__ __forceinline__ float bridge_prob(const Lane &L, float x0h, float x0l, float y0h, float y0l, float iD,
+                                             int &side) {
     const float d0[4] = {x0h + x0l, (1.f - x0h) - x0l, y0h + y0l, (1.f - y0h) - y0l};
     const float d1[4] = {L.xh + L.xl, (1.f - L.xh) - L.xl, L.yh + L.yl, (1.f - L.yh) - L.yl};
     float p = 0.f, pmax = 0.f;
-    int side = -1;
+    side = -1;
 #pragma unroll
     for (int i = 0; i < 4; ++i) {
         const float e = d0[i] * d1[i] * iD;
@@ -104,15 +99,35 @@ __device__ __forceinline__ bool bridge_exit(Lane &L, float x0h, float x0l, float
             }
         }
     }
+    return p;
+}
+
+// The lane's end point projected onto side 0 (x = 0), 1 (x = 1), 2 (y = 0) or 3 (y = 1).
+__device__ __forceinline__ void move_to_side(Lane &L, int side) {
+    if (side == 0) { L.xh = 0.f; L.xl = 0.f; }
+    else if (side == 1) { L.xh = 1.f; L.xl = 0.f; }
+    else if (side == 2) { L.yh = 0.f; L.yl = 0.f; }
+    else { L.yh = 1.f; L.yl = 0.f; }
+}
+
+// The bridge test of fixed step k (FK_SCORE_BRIDGE).  The uniform of step k
+// is word (k & 1) of Philox(k/2, path, node, ctr3 | 4), u = ((r >> 8) + 1)
+// 2^-24; on u < p the path has left within the step and is moved onto the
+// side it most likely crossed (its end point projected).
+template <bool UNIFORM>
+__device__ __forceinline__ bool bridge_exit(Lane &L, float x0h, float x0l, float y0h, float y0l, uint32_t key0,
+                                            uint32_t key1) {
+    const int32_t k = L.k - 1;
+    float D = L.dt;
+    if constexpr (!UNIFORM) D = (k == L.K - 1) ? L.dt_last : D;
+    int side;
+    const float p = bridge_prob(L, x0h, x0l, y0h, y0l, 1.f / D, side);
     if (side < 0) return false;
     const PhiloxOut r = philox4x32_10((uint32_t)k >> 1, L.path, L.nid, L.ctr3 | 4u, key0, key1);
     const uint32_t word = (k & 1) ? r.r1 : r.r0;
     const float u = fmaf((float)(word >> 8), 0x1p-24f, 0x1p-24f);
     if (!(u < p)) return false;
-    if (side == 0) { L.xh = 0.f; L.xl = 0.f; }
-    else if (side == 1) { L.xh = 1.f; L.xl = 0.f; }
-    else if (side == 2) { L.yh = 0.f; L.yl = 0.f; }
-    else { L.yh = 1.f; L.yl = 0.f; }
+    move_to_side(L, side);
     return true;
 }
 
@@ -230,13 +245,15 @@ __device__ __forceinline__ void lane_start(Lane &L, const NodeDev &nd, const Lev
 // a.shift the identity scores are stored relative to the start point.
 // FK_SCORE_EXTEND scores an exit with the grid initial data extrapolated
 // bilinearly to the exit point (grid_bilinear extrapolates off the grid);
-// FK_SCORE_PROJECT and FK_SCORE_BRIDGE score it at the point clamped onto
-// the square (boundary data FK_DATA_GRID: the grid's edge there).
+// FK_SCORE_PROJECT, FK_SCORE_BRIDGE and FK_SCORE_EXPONENTIAL score it at
+// the point clamped onto the square (boundary data FK_DATA_GRID: the grid's
+// edge there).
 __device__ __forceinline__ void score_path(const PathArgs &a, const Lane &L, bool out, float &sx, float &sy) {
     const int kind = out ? (a.score_mode == FK_SCORE_EXTEND ? FK_DATA_GRID : a.bdry_kind) : a.init_kind;
     float x = L.xh, y = L.yh;
     float lx = L.xl, ly = L.yl;
-    if (out && (a.score_mode == FK_SCORE_PROJECT || a.score_mode == FK_SCORE_BRIDGE)) {
+    if (out && (a.score_mode == FK_SCORE_PROJECT || a.score_mode == FK_SCORE_BRIDGE ||
+                a.score_mode == FK_SCORE_EXPONENTIAL)) {
         if (x < 0.f || x > 1.f) { x = fminf(fmaxf(x, 0.f), 1.f); lx = 0.f; }
         if (y < 0.f || y > 1.f) { y = fminf(fmaxf(y, 0.f), 1.f); ly = 0.f; }
     }
@@ -248,7 +265,8 @@ __device__ __forceinline__ void score_path(const PathArgs &a, const Lane &L, boo
         float v = sin_mode(x, y);
         if (out) {
             // elapsed time since the initial data: t - s_kappa
-            const float s = (L.k >= L.K) ? L.horizon : (float)L.k * L.dt;
+            float s = (L.k >= L.K) ? L.horizon : (float)L.k * L.dt;
+            if (a.score_mode == FK_SCORE_EXPONENTIAL) s = L.s_hi + L.s_lo;
             v *= hw_exp2(-2.f * 9.8696044f * 1.44269504f * (L.horizon - s));
         }
         sx = v;

@@ -200,3 +200,18 @@ def test_subdomain_layout_validation(fk):
         rc = lib.subdomain_solve_rect(dens, 0.0, 0.01, px, py, n, 0, 8, 8, 8, 8, 8, 8, 8, 1 << 30, None)
         assert rc == code, (px, py, n, rc)
         assert fk.fk_last_error() != ""
+
+
+def test_exponential_steps_only_in_single_solves(fk):
+    """Exponential time-stepping is a single-solve mode: the control-variate
+    and batched solves reject it before any device use; an unknown mode is
+    invalid everywhere."""
+    data = W.Data(score_mode=W.SCORE_EXPONENTIAL)
+    with pytest.raises(fk.FkError) as e:
+        fk.fk_interface_solve_cv(W.CONST, data, np.array([[0.5, 0.5]]), 0.01, 1e-3, 64, None,
+                                 form=fk.FK_CV_MARTINGALE_GRID, device="cpu")
+    assert e.value.code == -5
+    with pytest.raises(fk.FkError) as e:
+        fk.FkBatch([(W.CONST, 0.01, 0.0, np.array([[0.5, 0.5]]), 1)], data, 1e-3, 64, device="cpu")
+    assert e.value.code == -5
+    assert _call(fk, data=W.Data(score_mode=5)) == -1
