@@ -986,12 +986,17 @@ static int64_t run_path_mg(const or_problem *pb, const or_uhat *u, int stride, d
         }
         double sd = sqrt(2.0 * D);
         double w0 = sd * z0, w1 = sd * z1;
+        const double x0 = x, y0 = y;
         x = x + bx * D + w0;
         y = y + by * D + w1;
         s = s + D;
         dB[0] += w0;
         dB[1] += w1;
-        if (x < 0.0 || x > 1.0 || y < 0.0 || y > 1.0) {
+        /* score mode 3: the bridge test of the step too (the last block then
+           ends with this step; the stopping rule sees only this step's
+           increments and its own uniform, so the sum keeps mean zero) */
+        if (x < 0.0 || x > 1.0 || y < 0.0 || y > 1.0 ||
+            (pb->data.score_mode == 3 && bridge_exit(pb, k, path, node, D, x0, y0, &x, &y))) {
             boundary_value(&pb->data, pb->t - s, x, y, &plain[0], &plain[1]);
             exit_k = k + 1;
             break;
@@ -1047,7 +1052,9 @@ int or_fk_solve_cv(int kind, int time_mode, const double *par, const double *w_g
     pb.data.init_kind = init_kind;
     pb.data.bdry_kind = bdry_kind;
     pb.data.score_mode = score_mode;
-    if (score_mode < 0 || score_mode > 2 || (score_mode == 2 && (init_kind != D_GRID || !grid_xi || !grid_eta)))
+    /* the bridge test (mode 3) in the martingale form only */
+    if (score_mode < 0 || score_mode > 3 || (score_mode == 3 && form != 1) ||
+        (score_mode == 2 && (init_kind != D_GRID || !grid_xi || !grid_eta)))
         return -1;
     pb.data.grid_xi = grid_xi;
     pb.data.grid_eta = grid_eta;

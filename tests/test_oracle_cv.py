@@ -307,3 +307,43 @@ def test_grid_base_control_is_unbiased(oracle_mod):
         z.append(diff.mean(1) / (diff.std(1, ddof=1) / math.sqrt(diff.shape[1])))
     z = np.concatenate(z).ravel()
     assert np.abs(z).max() < 4.0 and abs(z.mean()) < 4 / math.sqrt(z.size)
+
+
+def test_martingale_form_with_the_bridge_test(oracle_mod):
+    """The bridge test in the martingale form: the plain part is the plain
+    bridge solve on the same counters (identical exits, identical scores);
+    with w = 1 and the linear control the CV score differs from the start
+    point only by the projection of the last end point onto the square, so
+    its mean is the start point (the bridge identity pin), exactly so along
+    the near side; with a curved network over a moving density cv - plain
+    has mean zero."""
+    pts = np.array([[0.03, 0.5], [0.5, 0.04], [0.96, 0.45], [0.55, 0.97], [0.08, 0.3]])
+    t = 4e-3
+    data = W.Data(score_mode=W.SCORE_BRIDGE)
+    pl = oracle_mod.fk_solve(W.CONST, data, pts, t, t / 2, 20000, seed=3, want_exit=True, want_scores=True)
+    r = oracle_mod.fk_solve_cv(W.CONST, data, pts, t, t / 2, 20000, seed=3, uhat=oracle_mod.UHAT_LINEAR, stride=2,
+                               form=oracle_mod.CV_MARTINGALE, want_scores=True, want_exit=True)
+    assert np.array_equal(r["exit_step"], pl["exit_step"])
+    assert np.array_equal(r["plain_mean"], pl["mean"]) and np.array_equal(r["plain_se"], pl["se"])
+    assert np.all(np.abs(r["mean"] - pts) < 4.5 * r["se"] + 1e-12)   # tangential: x0 to round-off
+    assert np.all(r["se"] < pl["se"])
+    tangential = np.array([[0, 1], [1, 0], [2, 1], [3, 0]])   # the coordinate along the near side
+    assert np.all(r["se"][tangential[:, 0], tangential[:, 1]] < 1e-12)
+    # a curved network, a moving density, strides 2 and 10
+    dens = W.moving_bump()
+    nodes = W.MOVING_BUMP_1521.nodes()[::97]
+    flat = M.bf16_round(W.mlp_init(2) * 2.0)
+    base = oracle_mod.fk_solve(dens, data, nodes, 0.01, 1e-4, 2000, seed=5, want_scores=True)
+    z = []
+    for stride in (2, 10):
+        c = oracle_mod.fk_solve_cv(dens, data, nodes, 0.01, 1e-4, 2000, seed=5, uhat=oracle_mod.UHAT_MLP, flat=flat,
+                                   t_scale=W.CV_T_SCALE, stride=stride, form=oracle_mod.CV_MARTINGALE,
+                                   want_scores=True)
+        diff = c["cv_scores"] - base["scores"]
+        z.append(diff.mean(1) / (diff.std(1, ddof=1) / math.sqrt(diff.shape[1])))
+    z = np.concatenate(z).ravel()
+    assert np.abs(z).max() < 4.0 and abs(z.mean()) < 4 / math.sqrt(z.size)
+    # the Dynkin form does not take the bridge test
+    with pytest.raises(Exception):
+        oracle_mod.fk_solve_cv(W.CONST, data, pts, t, t / 2, 64, uhat=oracle_mod.UHAT_LINEAR, stride=2,
+                               form=oracle_mod.CV_DYNKIN)
