@@ -95,7 +95,8 @@ extern "C" {
                                  step at its end point projected onto the side of largest probability.
                                  Every exit is scored at the point clamped onto the square.  For w = 1
                                  the killed chain then has the law of the killed diffusion at any step
-                                 size.  Plain solves only (fk_interface_solve, batches) */
+                                 size.  Plain solves (fk_interface_solve, batches) and the martingale
+                                 forms of fk_interface_solve_cv (the Dynkin form: FK_E_UNSUPPORTED) */
 #define FK_SCORE_EXPONENTIAL 4  /* exponential time-stepping (Sect. 4's alternative to the fixed steps,
                                  after Jansons & Lythe 2003): step lengths D_k exponentially distributed
                                  with mean dt, D_k = -dt ln u with u = ((r >> 8) + 1) 2^-24 from word

@@ -301,7 +301,8 @@ int enqueue_solve(const SolveLaunch &S, hipStream_t stream, bool allow_timing) {
             return hip_fail(e, "zero total_steps");
         a.total_steps = (unsigned long long *)S.total_steps;
     } else {
-        // the short-horizon kernel skips the count when nobody asked for it
+        // nobody asked for the count: short horizons skip it (the kernels
+        // skip a null count), others keep it in the counters block
         a.total_steps = S.first_by_index ? nullptr : (unsigned long long *)(S.counters + 2);
     }
     a.queue = S.counters;

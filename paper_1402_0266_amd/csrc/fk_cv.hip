@@ -595,7 +595,7 @@ __global__ void __launch_bounds__(256, 2) fk_cv_path_kernel(const PathArgs a, co
     unsigned long long st = my_steps;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) st += __shfl_xor(st, off, 64);
-    if (lane == 0 && st != 0ull) atomicAdd(a.total_steps, st);
+    if (lane == 0 && st != 0ull && a.total_steps) atomicAdd(a.total_steps, st);
 }
 
 // Gradient of the bilinear interpolant of a nodal grid at (x, y) (the cell
@@ -645,6 +645,27 @@ __device__ __forceinline__ void table_gradient(const float4 *tab, int n, int com
     gy = (float)n * fmaf(ax, t.w, t.z);
 }
 
+// One Euler-Maruyama step with its Brownian part (wx, wy); with BRIDGE the
+// Brownian-bridge exit test of the step follows (FK_SCORE_BRIDGE), on the
+// same counters as in the plain kernel.  The step's Brownian part counts in
+// full toward the block it ends: the test sees only this step.
+template <int KIND, bool UNIFORM, bool BRIDGE>
+__device__ __forceinline__ bool cv_step(Lane &L, uint32_t ra, uint32_t rb, float ox, float oy, float &wx, float &wy,
+                                        uint32_t key0, uint32_t key1) {
+    float x0h = 0.f, x0l = 0.f, y0h = 0.f, y0l = 0.f;
+    if constexpr (BRIDGE) {
+        x0h = L.xh;
+        x0l = L.xl;
+        y0h = L.yh;
+        y0l = L.yl;
+    }
+    bool out = em_step_w<KIND, UNIFORM>(L, ra, rb, ox, oy, wx, wy);
+    if constexpr (BRIDGE) {
+        if (!out) out = bridge_exit<UNIFORM>(L, x0h, x0l, y0h, y0l, key0, key1);
+    }
+    return out;
+}
+
 // Martingale-form path kernel.  The score is g - sum_j G_j . dB_j: dB_j is the
 // Brownian part of the path's steps in block j, G_j the gradient of u_hat at
 // the block's first state.  Blocks start at the path's start (G_0 from the
@@ -671,7 +692,7 @@ struct MgArgs {
 // gains the latency hiding of the extra waves (about 14% faster per path
 // than two waves on the moving bump; the Dynkin kernel, whose evaluation
 // points are ten times as frequent, stays at two).
-template <int KIND, int TMODE, bool UNIFORM>
+template <int KIND, int TMODE, bool UNIFORM, bool BRIDGE>
 __global__ void __launch_bounds__(256, 4) fk_mg_path_kernel(const PathArgs a, const MgArgs c) {
     constexpr bool kMovingBackward = moving_kind(KIND) && TMODE == TIME_BACKWARD;
     __shared__ NetLds N;
@@ -793,7 +814,7 @@ __global__ void __launch_bounds__(256, 4) fk_mg_path_kernel(const PathArgs a, co
                     oy = L.dens.orbit_r * sr;
                 }
                 float wx, wy;
-                out = em_step_w<KIND, UNIFORM>(L, r.r0, r.r1, ox, oy, wx, wy);
+                out = cv_step<KIND, UNIFORM, BRIDGE>(L, r.r0, r.r1, ox, oy, wx, wy, key0, key1);
                 dbx += wx;
                 dby += wy;
                 my_steps += 1;
@@ -804,7 +825,7 @@ __global__ void __launch_bounds__(256, 4) fk_mg_path_kernel(const PathArgs a, co
                         ox = L.dens.orbit_r * c2;
                         oy = L.dens.orbit_r * s2;
                     }
-                    out = em_step_w<KIND, UNIFORM>(L, r.r2, r.r3, ox, oy, wx, wy);
+                    out = cv_step<KIND, UNIFORM, BRIDGE>(L, r.r2, r.r3, ox, oy, wx, wy, key0, key1);
                     dbx += wx;
                     dby += wy;
                     my_steps += 1;
@@ -830,7 +851,7 @@ __global__ void __launch_bounds__(256, 4) fk_mg_path_kernel(const PathArgs a, co
     unsigned long long st = my_steps;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) st += __shfl_xor(st, off, 64);
-    if (lane == 0 && st != 0ull) atomicAdd(a.total_steps, st);
+    if (lane == 0 && st != 0ull && a.total_steps) atomicAdd(a.total_steps, st);
 }
 
 // Martingale form with the grid initial data as the control: every `stride`
@@ -849,7 +870,7 @@ struct MggArgs {
                                  // taken only at the path's start), or NULL
 };
 
-template <int KIND, int TMODE, bool UNIFORM>
+template <int KIND, int TMODE, bool UNIFORM, bool BRIDGE>
 __global__ void __launch_bounds__(256) fk_mgg_path_kernel(const PathArgs a, const MggArgs c) {
     constexpr bool kMovingBackward = moving_kind(KIND) && TMODE == TIME_BACKWARD;
     const uint32_t lane = threadIdx.x & 63u;
@@ -935,7 +956,7 @@ __global__ void __launch_bounds__(256) fk_mgg_path_kernel(const PathArgs a, cons
                     oy = L.dens.orbit_r * sr;
                 }
                 float wx, wy;
-                out = em_step_w<KIND, UNIFORM>(L, r.r0, r.r1, ox, oy, wx, wy);
+                out = cv_step<KIND, UNIFORM, BRIDGE>(L, r.r0, r.r1, ox, oy, wx, wy, key0, key1);
                 dbx += wx;
                 dby += wy;
                 my_steps += 1;
@@ -946,7 +967,7 @@ __global__ void __launch_bounds__(256) fk_mgg_path_kernel(const PathArgs a, cons
                         ox = L.dens.orbit_r * c2;
                         oy = L.dens.orbit_r * s2;
                     }
-                    out = em_step_w<KIND, UNIFORM>(L, r.r2, r.r3, ox, oy, wx, wy);
+                    out = cv_step<KIND, UNIFORM, BRIDGE>(L, r.r2, r.r3, ox, oy, wx, wy, key0, key1);
                     dbx += wx;
                     dby += wy;
                     my_steps += 1;
@@ -972,7 +993,7 @@ __global__ void __launch_bounds__(256) fk_mgg_path_kernel(const PathArgs a, cons
     unsigned long long st = my_steps;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) st += __shfl_xor(st, off, 64);
-    if (lane == 0 && st != 0ull) atomicAdd(a.total_steps, st);
+    if (lane == 0 && st != 0ull && a.total_steps) atomicAdd(a.total_steps, st);
 }
 
 // Per node: u_hat at the start (the shift of the CV estimate) and the
@@ -1415,36 +1436,45 @@ struct CvOccF {
         return nb;
     }
 };
+// The martingale kernels with and without the bridge test (a.score_mode).
 template <int K, int T, bool U>
 struct MgLaunchF {
     static hipError_t run(const PathArgs &a, const MgArgs &c, int grid, hipStream_t s) {
-        hipLaunchKernelGGL((fk_mg_path_kernel<K, T, U>), dim3(grid), dim3(256), 0, s, a, c);
+        if (a.score_mode == FK_SCORE_BRIDGE)
+            hipLaunchKernelGGL((fk_mg_path_kernel<K, T, U, true>), dim3(grid), dim3(256), 0, s, a, c);
+        else
+            hipLaunchKernelGGL((fk_mg_path_kernel<K, T, U, false>), dim3(grid), dim3(256), 0, s, a, c);
         return hipGetLastError();
     }
 };
 template <int K, int T, bool U>
 struct MgOccF {
-    static int run() {
+    static int run(bool bridge) {
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk_mg_path_kernel<K, T, U>, 256, 0) != hipSuccess)
-            return 0;
-        return nb;
+        const hipError_t e =
+            bridge ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk_mg_path_kernel<K, T, U, true>, 256, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk_mg_path_kernel<K, T, U, false>, 256, 0);
+        return e == hipSuccess ? nb : 0;
     }
 };
 template <int K, int T, bool U>
 struct MggLaunchF {
     static hipError_t run(const PathArgs &a, const MggArgs &c, int grid, hipStream_t s) {
-        hipLaunchKernelGGL((fk_mgg_path_kernel<K, T, U>), dim3(grid), dim3(256), 0, s, a, c);
+        if (a.score_mode == FK_SCORE_BRIDGE)
+            hipLaunchKernelGGL((fk_mgg_path_kernel<K, T, U, true>), dim3(grid), dim3(256), 0, s, a, c);
+        else
+            hipLaunchKernelGGL((fk_mgg_path_kernel<K, T, U, false>), dim3(grid), dim3(256), 0, s, a, c);
         return hipGetLastError();
     }
 };
 template <int K, int T, bool U>
 struct MggOccF {
-    static int run() {
+    static int run(bool bridge) {
         int nb = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk_mgg_path_kernel<K, T, U>, 256, 0) != hipSuccess)
-            return 0;
-        return nb;
+        const hipError_t e =
+            bridge ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk_mgg_path_kernel<K, T, U, true>, 256, 0)
+                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk_mgg_path_kernel<K, T, U, false>, 256, 0);
+        return e == hipSuccess ? nb : 0;
     }
 };
 template <int K, int T, bool U>
@@ -1761,8 +1791,8 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     if (!cv && !grid_ctl) return fail(FK_E_INVAL, "network is NULL");
     if ((rc = validate_density(w)) != FK_OK) return rc;
     if ((rc = validate_data(d)) != FK_OK) return rc;
-    if (d->score_mode == FK_SCORE_BRIDGE)
-        return fail(FK_E_UNSUPPORTED, "the Brownian-bridge exit test is for plain solves only");
+    if (d->score_mode == FK_SCORE_BRIDGE && form == FK_CV_DYNKIN)
+        return fail(FK_E_UNSUPPORTED, "the Brownian-bridge exit test is for the plain and martingale forms only");
     if (d->score_mode == FK_SCORE_EXPONENTIAL)
         return fail(FK_E_UNSUPPORTED, "exponential time-stepping is for single plain solves only");
     if ((rc = validate_common(n_paths, dt)) != FK_OK) return rc;
@@ -1891,7 +1921,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         c.acc_cv = acc_cv;
         c.gtab = grid_table(d, workspace, workspace_bytes, lay.total, stream, &e);
         if (e != hipSuccess) return hip_fail(e, "gradient table kernel launch");
-        const int occ = cv_dispatch<MggOccF>(w->kind, w->time_mode, uniform);
+        const int occ = cv_dispatch<MggOccF>(w->kind, w->time_mode, uniform, d->score_mode == FK_SCORE_BRIDGE);
         if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
         if ((e = cv_dispatch<MggLaunchF>(w->kind, w->time_mode, uniform, a, c, cap_grid(n_cu * bpc, a.total_chunks, 256), stream)) != hipSuccess)
             return hip_fail(e, "control-variate path kernel launch");
@@ -1907,7 +1937,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         if (e != hipSuccess) return hip_fail(e, "gradient table kernel launch");
         c.cv_scores = cv_rec;
         c.acc_cv = acc_cv;
-        const int occ = cv_dispatch<MgOccF>(w->kind, w->time_mode, uniform);
+        const int occ = cv_dispatch<MgOccF>(w->kind, w->time_mode, uniform, d->score_mode == FK_SCORE_BRIDGE);
         if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
         if ((e = cv_dispatch<MgLaunchF>(w->kind, w->time_mode, uniform, a, c, cap_grid(n_cu * bpc, a.total_chunks, 256), stream)) != hipSuccess)
             return hip_fail(e, "control-variate path kernel launch");

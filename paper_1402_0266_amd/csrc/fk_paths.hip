@@ -291,10 +291,8 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
     unsigned long long st = my_steps;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) st += __shfl_xor(st, off, 64);
-    if constexpr (FIRST_BY_INDEX) {
-        if (!a.total_steps) return;              // the caller did not ask for the count
-    }
-    if (lane == 0 && st != 0ull) atomicAdd(a.total_steps, st);
+    // a null count: the caller did not ask for it (every kernel skips it)
+    if (lane == 0 && st != 0ull && a.total_steps) atomicAdd(a.total_steps, st);
 }
 
 // Exponential time-stepping (FK_SCORE_EXPONENTIAL): the same persistent
@@ -416,7 +414,7 @@ __global__ void __launch_bounds__(256) fk_expo_path_kernel(const PathArgs a) {
     unsigned long long st = my_steps;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) st += __shfl_xor(st, off, 64);
-    if (lane == 0 && st != 0ull) atomicAdd(a.total_steps, st);
+    if (lane == 0 && st != 0ull && a.total_steps) atomicAdd(a.total_steps, st);
 }
 
 namespace {
