@@ -137,14 +137,53 @@ typedef struct fk_data {
  * block 256; blocks_per_cu the kernel's occupancy (the grid is cut to no more
  * wavefronts than there are chunks); chunk 128, or 256 for horizons of at most 64
  * steps in fk_interface_solve and in the network forms of fk_interface_solve_cv;
- * chunk at most 2048 (FK_E_INVAL beyond).  The plan changes speed only: results
- * depend on the counters alone. */
+ * chunk at most 2048 (FK_E_INVAL beyond); node_tile 1.  The plan changes speed
+ * only: results depend on the counters alone. */
 typedef struct fk_plan {
     int32_t block;          /* threads per workgroup: 64, 128, 192 or 256 */
     int32_t blocks_per_cu;  /* resident workgroups per compute unit for the persistent grid */
     int32_t chunk;          /* paths handed to a wavefront per queue grab (>= 1) */
-    int32_t reserved;
+    int32_t node_tile;      /* work order: the chunks of this many consecutive nodes (in the queue's
+                               cost order) interleaved, 1..256; 1 = node by node */
 } fk_plan;
+
+/*
+ * Plan handle (launch plan + captured graph).  fk_plan_autotune times
+ * fk_interface_solve on the caller's problem (with probe_paths paths per node)
+ * for each candidate shape -- block 64 / 128 / 256 x chunk 32 / 128 / 512 x
+ * full / half occupancy x node tile 1 / 8 -- and keeps the fastest in the
+ * handle.  Results are cached per process by the device's signature and a
+ * hash of the problem's shape (kinds, modes, node count, paths, steps); with
+ * the environment variable FK_TUNE_CACHE naming a file they also persist
+ * there.  Synchronous; allocates and frees a probe output buffer.  Every
+ * candidate gives the same result: the plan changes the schedule only.
+ * Pass the tuned plan to the solves with fk_plan_get.
+ *
+ * fk_plan_capture_begin / _end bracket any sequence of library calls on a
+ * non-default stream (e.g. a whole mesh step: density samples, key points,
+ * the interface solve, interpolation, the sub-domain solves, quality) and
+ * keep it as the handle's executable HIP graph; nothing runs during capture.
+ * A later capture of the same sequence with other arguments (another time
+ * level, the other ping-pong buffers) updates the executable graph in place
+ * when its topology allows (fk_plan_graph_updates counts those), else
+ * replaces it.  fk_plan_replay launches it.  The captured calls must not
+ * allocate (pass workspaces and outputs) and must not synchronise with the
+ * host; the library records no memset into a graph.  create / set / get /
+ * autotune check their arguments (FK_E_INVAL); destroy synchronises the
+ * device first when a graph is held.
+ */
+typedef struct fk_plan_handle *fk_plan_t;
+int fk_plan_create(const fk_plan *initial, fk_plan_t *out);
+int fk_plan_set(fk_plan_t p, const fk_plan *plan);
+int fk_plan_get(fk_plan_t p, fk_plan *out);
+int fk_plan_autotune(fk_plan_t p, const fk_density *w, const fk_data *d, const double *pts, const uint8_t *mask,
+                     int64_t n_nodes, double t, double dt, int64_t probe_paths, uint64_t seed, void *workspace,
+                     size_t workspace_bytes, hipStream_t stream);
+int fk_plan_capture_begin(fk_plan_t p, hipStream_t stream);
+int fk_plan_capture_end(fk_plan_t p, hipStream_t stream);
+int fk_plan_replay(fk_plan_t p, hipStream_t stream);
+int fk_plan_graph_updates(fk_plan_t p);
+void fk_plan_destroy(fk_plan_t p);
 
 /*
  * Samples of an analytic density at the nodes of an n-cell grid (for the
@@ -293,11 +332,12 @@ size_t fk_batch_workspace_bytes(fk_batch_t b);
 int fk_batch_set_plan(fk_batch_t b, const fk_plan *plan);
 int fk_batch_get_plan(fk_batch_t b, fk_plan *plan);
 /* Times the launch with probe_paths paths per node for each candidate shape
- * (block 64/128/256 x chunk 32/128/512 x full/half occupancy), keeps the
+ * (as fk_plan_autotune: block x chunk x occupancy x node tile), keeps the
  * fastest as the batch's plan and returns it in *chosen (may be NULL).
- * Results are cached per process by device and problem shape.  Synchronous;
- * allocates and frees a small probe output buffer.  Every candidate computes
- * the same result: the plan only changes the schedule. */
+ * Results are cached like fk_plan_autotune's (device signature + shape hash;
+ * FK_TUNE_CACHE).  Synchronous; allocates and frees a small probe output
+ * buffer.  Every candidate computes the same result: the plan only changes
+ * the schedule. */
 int fk_batch_autotune(fk_batch_t b, int64_t probe_paths, void *workspace, size_t workspace_bytes,
                       hipStream_t stream, fk_plan *chosen);
 /* Outputs as in fk_interface_solve, over n_total nodes in node-list order. */

@@ -59,7 +59,7 @@ class fk_data(ctypes.Structure):
 
 class fk_plan(ctypes.Structure):
     _fields_ = [("block", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("chunk", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("chunk", ctypes.c_int32), ("node_tile", ctypes.c_int32)]
 
 
 class fk_level(ctypes.Structure):
@@ -371,6 +371,15 @@ def fk_interface_workspace_bytes(n_nodes: int, n_paths: int) -> int:
     return int(_lib.fk_interface_workspace_bytes(n_nodes, n_paths))
 
 
+def fk_interface_cv_grid_workspace_bytes(n_nodes: int, n_paths: int, grid_n: int) -> int:
+    """Workspace of a control-variate solve with the mesh-gradient table."""
+    return int(_lib.fk_interface_cv_grid_workspace_bytes(n_nodes, n_paths, grid_n))
+
+
+def fk_boundary_workspace_bytes(n: int) -> int:
+    return int(_lib.fk_boundary_workspace_bytes(int(n)))
+
+
 def fk_philox_words(ctr, seed: int):
     """Philox4x32-10 words of device counters ctr (int32/uint32 tensor [n, 4])."""
     import torch
@@ -492,11 +501,111 @@ def fk_interface_solve_noalloc(density, data, pts, t, dt, n_paths, seed=0, level
 def _plan_struct(plan):
     if plan is None:
         return None
-    return fk_plan(int(plan.get("block", 0)), int(plan.get("blocks_per_cu", 0)), int(plan.get("chunk", 0)), 0)
+    if isinstance(plan, FkPlan):
+        plan = plan.get()
+    return fk_plan(int(plan.get("block", 0)), int(plan.get("blocks_per_cu", 0)), int(plan.get("chunk", 0)),
+                   int(plan.get("node_tile", 0)))
 
 
 def _plan_dict(p: fk_plan) -> dict:
-    return {"block": p.block, "blocks_per_cu": p.blocks_per_cu, "chunk": p.chunk}
+    return {"block": p.block, "blocks_per_cu": p.blocks_per_cu, "chunk": p.chunk, "node_tile": p.node_tile}
+
+
+_lib.fk_plan_create.argtypes = [ctypes.POINTER(fk_plan), ctypes.POINTER(_P)]
+_lib.fk_plan_create.restype = ctypes.c_int
+_lib.fk_plan_set.argtypes = [_P, ctypes.POINTER(fk_plan)]
+_lib.fk_plan_set.restype = ctypes.c_int
+_lib.fk_plan_get.argtypes = [_P, ctypes.POINTER(fk_plan)]
+_lib.fk_plan_get.restype = ctypes.c_int
+_lib.fk_plan_autotune.argtypes = [_P, ctypes.POINTER(fk_density), ctypes.POINTER(fk_data), _P, _P, ctypes.c_int64,
+                                  ctypes.c_double, ctypes.c_double, ctypes.c_int64, ctypes.c_uint64, _P,
+                                  ctypes.c_size_t, _P]
+_lib.fk_plan_autotune.restype = ctypes.c_int
+for _name in ("fk_plan_capture_begin", "fk_plan_capture_end", "fk_plan_replay"):
+    getattr(_lib, _name).argtypes = [_P, _P]
+    getattr(_lib, _name).restype = ctypes.c_int
+_lib.fk_plan_graph_updates.argtypes = [_P]
+_lib.fk_plan_graph_updates.restype = ctypes.c_int
+_lib.fk_plan_destroy.argtypes = [_P]
+_lib.fk_plan_destroy.restype = None
+
+
+class FkPlan:
+    """A launch plan with its autotune record and a captured HIP graph
+    (C: ``fk_plan_*``).  Pass it as ``plan=`` to the solves.  ``capture()``
+    is a context manager: the library calls made inside it on torch's
+    current stream (a non-default one) are recorded, not run; ``replay()``
+    runs them.  Capturing the same sequence again with other arguments
+    updates the graph in place (``updates`` counts those)."""
+
+    def __init__(self, plan=None):
+        h = _P()
+        p = _plan_struct(plan) if plan is not None else None
+        _check(_lib.fk_plan_create(None if p is None else ctypes.byref(p), ctypes.byref(h)))
+        self.handle = h
+
+    def get(self) -> dict:
+        p = fk_plan()
+        _check(_lib.fk_plan_get(self.handle, ctypes.byref(p)))
+        return _plan_dict(p)
+
+    def set(self, plan):
+        _check(_lib.fk_plan_set(self.handle, ctypes.byref(_plan_struct(plan))))
+
+    def autotune(self, density, data, pts, t, dt, probe_paths, seed=0, mask=None, device="cuda", grids=None,
+                 workspace=None) -> dict:
+        import torch
+        dev = torch.device(device)
+        pts = _device_pts(pts, dev)
+        n = pts.shape[0]
+        mask = _device_mask(mask, n, dev)
+        need = _lib.fk_interface_workspace_bytes(n, probe_paths)
+        if workspace is None or workspace.numel() < need:
+            workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+        _check(_lib.fk_plan_autotune(self.handle, ctypes.byref(_density(density)), ctypes.byref(_data(data, grids)),
+                                     pts.data_ptr() if n else None, None if mask is None else mask.data_ptr(), n,
+                                     float(t), float(dt), int(probe_paths), int(seed), workspace.data_ptr(),
+                                     workspace.numel(), _stream(torch, dev)))
+        return self.get()
+
+    class _Capture:
+        def __init__(self, plan, device):
+            self.plan, self.device = plan, device
+
+        def __enter__(self):
+            import torch
+            _check(_lib.fk_plan_capture_begin(self.plan.handle, _stream(torch, self.device)))
+            return self.plan
+
+        def __exit__(self, exc_type, exc, tb):
+            import torch
+            rc = _lib.fk_plan_capture_end(self.plan.handle, _stream(torch, self.device))
+            if exc_type is None:
+                _check(rc)
+            return False
+
+    def capture(self, device="cuda"):
+        import torch
+        return FkPlan._Capture(self, torch.device(device))
+
+    def replay(self, device="cuda"):
+        import torch
+        _check(_lib.fk_plan_replay(self.handle, _stream(torch, torch.device(device))))
+
+    @property
+    def updates(self) -> int:
+        return int(_lib.fk_plan_graph_updates(self.handle))
+
+    def close(self):
+        if self.handle:
+            _lib.fk_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 class FkBatch:

@@ -125,12 +125,14 @@ int validate_points(const double *pts, int64_t n) {
 }
 
 int resolve_plan(const fk_plan *plan, fk_plan *out) {
-    fk_plan pl{256, 0, 128, 0};
+    fk_plan pl{256, 0, 128, 1};
     if (plan) {
         if (plan->block) pl.block = plan->block;
         if (plan->blocks_per_cu) pl.blocks_per_cu = plan->blocks_per_cu;
         if (plan->chunk) pl.chunk = plan->chunk;
+        if (plan->node_tile) pl.node_tile = plan->node_tile;
     }
+    if (pl.node_tile < 1 || pl.node_tile > 256) return fail(FK_E_INVAL, "plan node_tile must be in [1, 256]");
     if (pl.block < 64 || pl.block > 256 || pl.block % 64)
         return fail(FK_E_INVAL, "plan block must be 64, 128, 192 or 256");
     if (pl.chunk < 1 || pl.chunk > (int)kMaxChunk) return fail(FK_E_INVAL, "plan chunk must be in [1, %u]", kMaxChunk);
@@ -310,6 +312,7 @@ int enqueue_solve(const SolveLaunch &S, hipStream_t stream, bool allow_timing) {
     a.chunk = (uint32_t)S.plan.chunk;
     a.cpn = (uint32_t)cpn;
     a.total_chunks = (uint32_t)(S.n_nodes * cpn);
+    a.node_tile = (uint32_t)S.plan.node_tile;
     int bpc = S.plan.blocks_per_cu;
     const bool expo = a.score_mode == FK_SCORE_EXPONENTIAL;
     const int occ = expo ? expo_kernel_max_blocks_per_cu(S.kind, S.time_mode, S.plan.block)

@@ -69,15 +69,17 @@ static int batch_launch(fk_batch *b, int64_t n_paths, const fk_plan &pl, double 
     return enqueue_solve(S, stream, allow_timing);
 }
 
-// Autotune results of this process, keyed by device and problem shape.
-static std::mutex g_tune_mu;
-static std::map<std::string, fk_plan> g_tune_cache;
-
+// The batch's shape for the tuned-plan cache: the device and a hash of the
+// kinds, modes, level count, nodes, paths and probe size.
 static std::string tune_key(const fk_batch *b, int64_t probe) {
-    char buf[256];
-    snprintf(buf, sizeof buf, "dev%d k%d m%d u%d L%zu n%lld N%lld p%lld", b->device, b->T.kind, b->T.time_mode,
-             (int)b->T.uniform, b->T.levels.size(), (long long)b->n_total, (long long)b->n_paths, (long long)probe);
-    return buf;
+    struct {
+        int32_t kind, time_mode, uniform, score_mode;
+        int64_t levels, n_total, n_paths, probe;
+    } shape{b->T.kind, b->T.time_mode, (int32_t)b->T.uniform, b->data.score_mode, (int64_t)b->T.levels.size(),
+            b->n_total, b->n_paths, probe};
+    char hex[32];
+    std::snprintf(hex, sizeof hex, "%016llx", (unsigned long long)fnv1a(&shape, sizeof shape, 0xcbf29ce484222325ull));
+    return "batch/" + device_signature(b->device) + "/" + hex;
 }
 
 }  // namespace fk
@@ -180,14 +182,11 @@ int fk_batch_autotune(fk_batch_t b, int64_t probe_paths, void *workspace, size_t
     if (!b) return fail(FK_E_INVAL, "batch is NULL");
     if (probe_paths < 2 || probe_paths > b->n_paths) return fail(FK_E_INVAL, "probe_paths must be in [2, n_paths]");
     const std::string key = tune_key(b, probe_paths);
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune_cache.find(key);
-        if (it != g_tune_cache.end()) {
-            b->plan = it->second;
-            if (chosen) *chosen = b->plan;
-            return FK_OK;
-        }
+    fk_plan cached;
+    if (tune_cache_get(key, &cached)) {
+        b->plan = cached;
+        if (chosen) *chosen = b->plan;
+        return FK_OK;
     }
     if (b->n_total == 0) {
         if (chosen) *chosen = b->plan;
@@ -196,54 +195,21 @@ int fk_batch_autotune(fk_batch_t b, int64_t probe_paths, void *workspace, size_t
     double *out = nullptr;
     hipError_t e = hipMalloc(&out, sizeof(double) * 4 * (size_t)b->n_total);
     if (e != hipSuccess) return fail(FK_E_NOMEM, "hipMalloc of probe outputs: %s", hipGetErrorString(e));
-    hipEvent_t e0, e1;
-    hipEventCreate(&e0);
-    hipEventCreate(&e1);
-    const int blocks[] = {64, 128, 256};
-    const int chunks[] = {32, 128, 512};
-    const int bpc_div[] = {1, 2};
+    const int occ = path_kernel_max_blocks_per_cu(b->T.kind, b->T.time_mode, b->T.uniform,
+                                                  b->data.score_mode == FK_SCORE_BRIDGE, false, 256);
     fk_plan best = b->plan;
-    float best_ms = 1e30f;
-    int rc = FK_OK;
-    // one untimed launch loads the code object and warms the caches
-    rc = batch_launch(b, probe_paths, b->plan, out, out + b->n_total, out + 2 * b->n_total, out + 3 * b->n_total,
-                      nullptr, nullptr, nullptr, workspace, workspace_bytes, stream, false);
-    for (int bl : blocks) {
-        for (int ch : chunks) {
-            for (int dv : bpc_div) {
-                if (rc != FK_OK) break;
-                const int occ = path_kernel_max_blocks_per_cu(b->T.kind, b->T.time_mode, b->T.uniform,
-                                                              b->data.score_mode == FK_SCORE_BRIDGE, false, bl);
-                fk_plan pl{bl, occ > 0 ? (occ + dv - 1) / dv : 0, ch, 0};
-                if (check_chunks(b->n_total, probe_paths, pl) != FK_OK) continue;
-                hipEventRecord(e0, stream);
-                rc = batch_launch(b, probe_paths, pl, out, out + b->n_total, out + 2 * b->n_total,
-                                  out + 3 * b->n_total, nullptr, nullptr, nullptr, workspace, workspace_bytes, stream,
-                                  false);
-                hipEventRecord(e1, stream);
-                if (rc != FK_OK) break;
-                if ((e = hipEventSynchronize(e1)) != hipSuccess) {
-                    rc = hip_fail(e, "autotune probe");
-                    break;
-                }
-                float ms = 0.f;
-                hipEventElapsedTime(&ms, e0, e1);
-                if (ms < best_ms) {
-                    best_ms = ms;
-                    best = pl;
-                }
-            }
-        }
-    }
-    hipEventDestroy(e0);
-    hipEventDestroy(e1);
+    const int rc = tune_sweep(
+        occ,
+        [&](const fk_plan &pl) {
+            return batch_launch(b, probe_paths, pl, out, out + b->n_total, out + 2 * b->n_total,
+                                out + 3 * b->n_total, nullptr, nullptr, nullptr, workspace, workspace_bytes, stream,
+                                false);
+        },
+        [&](const fk_plan &pl) { return check_chunks(b->n_total, probe_paths, pl) == FK_OK; }, stream, &best);
     hipFree(out);
     if (rc != FK_OK) return rc;
     b->plan = best;
-    {
-        std::lock_guard<std::mutex> lk(g_tune_mu);
-        g_tune_cache[key] = best;
-    }
+    tune_cache_put(key, best);
     if (chosen) *chosen = best;
     return FK_OK;
 }

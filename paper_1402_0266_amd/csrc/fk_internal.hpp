@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <algorithm>
+#include <functional>
 
 #include <string>
 #include <vector>
@@ -85,6 +86,7 @@ struct PathArgs {
     uint32_t cpn;                    // chunks per node
     uint32_t total_chunks;           // host bound on the work chunks (grid size); the kernels
                                      // read the launch's own count from queue[kCtrTotal]
+    uint32_t node_tile;              // chunk order: interleave the chunks of this many nodes (<= 1: node by node)
 };
 
 // The estimator's last step: node sums -> means, standard errors, steps.
@@ -169,6 +171,19 @@ int validate_device_points(const double *pts, int64_t n);  // device coordinates
 LevelDev make_level(const fk_density *w, double t_init, double t, double dt, uint32_t level_id, uint32_t stream);
 int resolve_plan(const fk_plan *plan, fk_plan *out);
 int check_chunks(int64_t n_nodes, int64_t n_paths, const fk_plan &pl);
+
+// Launch-plan tuning (fk_plan.hip): a 64-bit FNV-1a hash, the device's
+// signature, the tuned-plan cache (per process; FK_TUNE_CACHE names a file
+// that persists it), and the sweep over candidate plans: `launch` enqueues
+// one run with a plan, `admissible` filters the candidates, occ_full is the
+// kernel's occupancy at 256 threads; best_out holds the starting plan and
+// receives the fastest.
+uint64_t fnv1a(const void *data, size_t n, uint64_t h);
+std::string device_signature(int dev);
+bool tune_cache_get(const std::string &key, fk_plan *out);
+void tune_cache_put(const std::string &key, const fk_plan &p);
+int tune_sweep(int occ_full, const std::function<int(const fk_plan &)> &launch,
+               const std::function<bool(const fk_plan &)> &admissible, hipStream_t stream, fk_plan *best_out);
 // A persistent grid of `grid` blocks cut to no more wavefronts than there
 // are work chunks (small solves: a wavefront with no chunk only costs its
 // launch).

@@ -211,8 +211,9 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
                     q_done = true;
                     break;
                 }
-                q_slot = c / a.cpn;
-                q_next = (c - q_slot * a.cpn) * a.chunk;
+                uint32_t pc;
+                chunk_slot(a, total_chunks, c, q_slot, pc);
+                q_next = pc * a.chunk;
                 q_end = min(q_next + a.chunk, a.n_paths);
                 q_tag = slot_open<2>(slots, accs, grabs++, (uint32_t)a.nodes[q_slot].out, q_end - q_next, lane);
                 continue;

@@ -165,12 +165,39 @@ __device__ __forceinline__ uint32_t launch_chunks(const PathArgs &a) {
     return __builtin_amdgcn_readfirstlane(a.queue[kCtrTotal]);
 }
 
+// Node slot and path chunk of work chunk c (c < total).  Node by node, or
+// (node_tile > 1) with the chunks of node_tile consecutive slots interleaved,
+// the last, partial tile likewise over its remaining slots.  The order only
+// changes the schedule: every path draws from its own counters and every
+// sum is exact.
+__device__ __forceinline__ void chunk_slot(const PathArgs &a, uint32_t total, uint32_t c, uint32_t &slot,
+                                           uint32_t &pc) {
+    const uint32_t nt = a.node_tile;
+    if (nt <= 1u) {
+        slot = c / a.cpn;
+        pc = c - slot * a.cpn;
+        return;
+    }
+    const uint32_t n_act = total / a.cpn, span = nt * a.cpn, full = n_act / nt;
+    const uint32_t tile = c / span;
+    if (tile < full) {
+        const uint32_t r = c - tile * span;
+        slot = tile * nt + r % nt;
+        pc = r / nt;
+    } else {
+        const uint32_t rem = n_act - full * nt, r = c - full * span;
+        slot = full * nt + r % rem;
+        pc = r / rem;
+    }
+}
+
 // The cursor (node slot, path range) of chunk c; false past the last chunk.
 __device__ __forceinline__ bool chunk_cursor(const PathArgs &a, uint32_t total, uint32_t c, uint32_t &slot,
                                              uint32_t &next, uint32_t &end) {
     if (c >= total) return false;
-    slot = c / a.cpn;
-    next = (c - slot * a.cpn) * a.chunk;
+    uint32_t pc;
+    chunk_slot(a, total, c, slot, pc);
+    next = pc * a.chunk;
     end = min(next + a.chunk, a.n_paths);
     return true;
 }

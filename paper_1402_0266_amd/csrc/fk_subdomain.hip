@@ -25,6 +25,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <mutex>
 
 #include "fk.h"
 #include "fk_internal.hpp"
@@ -1139,16 +1140,38 @@ static size_t sub_ws_bytes(const SubGeom &g, int N) {
 // launches would cost more than they save.
 constexpr int64_t kTwistedMinN = 225;
 
+// The dynamic LDS limits of the separator and back-substitution kernels,
+// raised once per device to what the largest band needs (not at every
+// launch: launches may be recorded into a graph).
+static hipError_t lds_limits_once() {
+    static std::mutex mu;
+    static bool done[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    std::lock_guard<std::mutex> lk(mu);
+    if (dev >= 0 && dev < 64 && done[dev]) return hipSuccess;
+    const int qmax = kMaxP1 - 1;
+    const size_t sep = ((size_t)qmax * qmax + 2 * qmax) * sizeof(double);
+    const size_t back = ((size_t)kBackRows * (kMaxP1 | 1) + 512) * sizeof(double);
+    if ((e = hipFuncSetAttribute((const void *)separator_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)sep)) != hipSuccess)
+        return e;
+    if ((e = hipFuncSetAttribute((const void *)back_block_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                 (int)back)) != hipSuccess)
+        return e;
+    if (dev >= 0 && dev < 64) done[dev] = true;
+    return hipSuccess;
+}
+
 // Elimination, separator and back substitution of every sub-domain.
 static hipError_t launch_elimination(const SubArgs &a, int blocks, hipStream_t s) {
     const int P1 = a.qf + 1;
     const unsigned nwg = (unsigned)(a.twisted ? 2 * blocks : blocks);
-    hipError_t e;
+    hipError_t e = lds_limits_once();
+    if (e != hipSuccess) return e;
     auto separator = [&]() -> hipError_t {
         const size_t lds = ((size_t)a.qf * a.qf + 2 * a.qf) * sizeof(double);
-        hipError_t r = hipFuncSetAttribute((const void *)separator_kernel,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
-        if (r != hipSuccess) return r;
         hipLaunchKernelGGL(separator_kernel, dim3((unsigned)blocks), dim3(256), lds, s, a);
         return hipGetLastError();
     };
@@ -1192,9 +1215,6 @@ static hipError_t launch_elimination(const SubArgs &a, int blocks, hipStream_t s
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (a.twisted && (e = separator()) != hipSuccess) return e;
     const size_t lds = ((size_t)kBackRows * (P1 | 1) + 512) * sizeof(double);
-    if ((e = hipFuncSetAttribute((const void *)back_block_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                 (int)lds)) != hipSuccess)
-        return e;
     hipLaunchKernelGGL(back_block_kernel, dim3(nwg), dim3(64), lds, s, a);
     return hipGetLastError();
 }

@@ -90,6 +90,8 @@ class MeshRunConfig:
     key_points: bool = False    # simulate only the key points; interpolate the other interface nodes
     key_tol: float = 1e-2       # significance of a derivative extremum, relative to the line's largest
     key_gap: int = 0            # largest gap between knots along a line (0: m // 2)
+    graph: bool = False         # record each step's device work as a HIP graph (an FkPlan) and replay it;
+                                # plain or mesh-gradient runs (no network), on a stream of the run's own
     seed: int = 0
 
 
@@ -205,6 +207,19 @@ class MeshRun:
         self.workspace = None
         self.sub_workspace = torch.empty(max(subdomain_workspace_bytes(cfg.px, cfg.m), 256), dtype=torch.uint8,
                                          device=self.dev)
+        # step counts of the interface solves (device; keeps the solves from allocating one)
+        self._total_steps = torch.zeros((cfg.n_steps, 1), dtype=torch.int64, device=self.dev)
+        self.plan = None
+        if cfg.graph:
+            if cfg.refit_every > 0 and cfg.cv_form != "grid":
+                raise ValueError("graph mode records plain or mesh-gradient steps (no network)")
+            from . import FkPlan, fk_interface_cv_grid_workspace_bytes, fk_interface_workspace_bytes
+            self.plan = FkPlan()
+            self.stream = torch.cuda.Stream(device=self.dev)
+            # every buffer a step uses exists before its capture
+            need = (fk_interface_cv_grid_workspace_bytes(self.n_nodes, cfg.n_paths, self.N)
+                    if cfg.cv_form == "grid" else fk_interface_workspace_bytes(self.n_nodes, cfg.n_paths))
+            self.workspace = torch.empty(max(need, 256), dtype=torch.uint8, device=self.dev)
         self.losses = []
         if cfg.density_data not in ("analytic", "grid"):
             raise ValueError("density_data must be 'analytic' or 'grid'")
@@ -213,9 +228,12 @@ class MeshRun:
         if cfg.density_data == "grid":
             self._wb = torch.empty((self.N + 1, self.N + 1, 2), dtype=torch.float32, device=self.dev)
         if cfg.key_points:
-            self._mask = torch.empty(self.n_nodes, dtype=torch.uint8, device=self.dev)
-            self._n_keys = torch.zeros(cfg.n_steps, dtype=torch.int64, device=self.dev)
-            self._bdry_ws = None
+            # each step's key-point mask; standard errors exist at the key points only
+            self._masks = torch.zeros((cfg.n_steps, self.n_nodes), dtype=torch.uint8, device=self.dev)
+            self._se.fill_(float("nan"))
+            from . import fk_boundary_workspace_bytes
+            self._bdry_ws = torch.empty(max(fk_boundary_workspace_bytes(self.N), 256), dtype=torch.uint8,
+                                        device=self.dev)
         if cfg.refit_every > 0 and cfg.cv_form != "grid":
             if init_params is None:
                 raise ValueError("refit_every > 0 needs initial network parameters")
@@ -256,7 +274,12 @@ class MeshRun:
         synchronises with the device)."""
         if not self.cfg.key_points:
             return []
-        return [int(v) for v in self._n_keys[:self.n].cpu()]
+        return [int(v) for v in self._masks[:self.n].sum(1, dtype=self.torch.int64).cpu()]
+
+    @property
+    def _mask(self):
+        """The last step's key-point mask."""
+        return self._masks[max(self.n - 1, 0)]
 
     # -- labels ----------------------------------------------------------------
     def _add_labels(self, t, xi, eta):
@@ -282,6 +305,23 @@ class MeshRun:
         cfg = self.cfg
         if self.n >= cfg.n_steps:
             raise RuntimeError("the run has taken all its steps")
+        if self.plan is None:
+            self._step_body()
+        else:
+            # record the step's device work (its time level and buffers), run
+            # it as a graph, and hand its results to the caller's stream
+            torch = self.torch
+            caller = torch.cuda.current_stream(self.dev)
+            self.stream.wait_stream(caller)
+            with torch.cuda.stream(self.stream):
+                with self.plan.capture(self.dev):
+                    self._step_body(advance=False)
+                self.plan.replay(self.dev)
+            caller.wait_stream(self.stream)
+            self._advance()
+
+    def _step_body(self, advance=True):
+        cfg = self.cfg
         tn = self.n * cfg.dt_mesh
         dens = self.density_fn(tn)
         if cfg.density_data == "grid" or cfg.key_points:
@@ -297,14 +337,12 @@ class MeshRun:
         # simulates the masked nodes only (the mask stays on the device: no
         # host synchronisation in the step)
         rows = {"xi": self._iface[self.n, 0], "eta": self._iface[self.n, 1],
-                "se_xi": self._se[self.n, 0], "se_eta": self._se[self.n, 1]}
+                "se_xi": self._se[self.n, 0], "se_eta": self._se[self.n, 1],
+                "total_steps": self._total_steps[self.n]}
         mask = None
         if cfg.key_points:
-            fk_key_points(self._wg, cfg.px, cfg.m, cfg.key_tol, cfg.key_gap or None, out=self._mask)
-            mask = self._mask
-            self._n_keys[self.n] = mask.sum()
-            # standard errors exist at the key points only
-            self._se[self.n].fill_(float("nan"))
+            mask = self._masks[self.n]
+            fk_key_points(self._wg, cfg.px, cfg.m, cfg.key_tol, cfg.key_gap or None, out=mask)
         if cfg.cv_form == "grid":
             out = fk_interface_solve_cv(dens, data, self.pts, cfg.dt_mesh, dt, cfg.n_paths, None,
                                         stride=cfg.cv_stride, seed=cfg.seed, level_id=self.n,
@@ -348,8 +386,12 @@ class MeshRun:
                     lx = lx - self.xi.view(-1)[self._band_idx]
                     ly = ly - self.eta.view(-1)[self._band_idx]
                 self._add_labels(tn + cfg.dt_mesh, lx, ly)
-        self.spare = (self.xi, self.eta)
-        self.xi, self.eta = xi_new, eta_new
+        if advance:
+            self._advance()
+
+    def _advance(self):
+        # the new mesh becomes the current one; the old one the next output
+        self.spare, (self.xi, self.eta) = (self.xi, self.eta), self.spare
         self.n += 1
 
     def run(self, n_steps=None):
