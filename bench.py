@@ -76,6 +76,8 @@ FP32_PEAK_TFLOPS = 157.3
 #                  2A/s2 e, reciprocal, product, 2 components)
 #   Euler-Maruyama update 4 (2 fma)
 FLOP_PER_STEP = 36
+# Paths per node of the control-variate kernels' profile (the timed solve's N*).
+CV_PROFILE_PATHS = 2952
 
 # HBM traffic of the path kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
 # (scaled by a plain 1 GiB copy: fetch x2.0, write x1.0), per path, valid only
@@ -336,6 +338,45 @@ def measure_paper_run():
     return res
 
 
+def cv_kernels_only(fk, n_paths=CV_PROFILE_PATHS):
+    """The control-variate kernels of the timed solve at its size, for the
+    profiler: the martingale kernel with the network at strides 500 and 20
+    (weights do not change the work: an untrained identity-base network)
+    and the linear control, two launches each."""
+    import dataclasses
+
+    import torch
+    wl = W.MOVING_BUMP_1521
+    pts = torch.tensor(wl.nodes(), dtype=torch.float64, device="cuda")
+    cv = fk.FkCv(W.mlp_init(0), W.CV_T_SCALE, identity_base=True)
+    G = 256
+    x = torch.arange(G + 1, dtype=torch.float64, device="cuda") / G
+    grids = (x.repeat(G + 1, 1).contiguous().view(-1), x[:, None].repeat(1, G + 1).contiguous().view(-1))
+    gdata = dataclasses.replace(wl.data, init_kind=W.DATA_GRID, score_mode=W.SCORE_EXTEND)
+    res = {}
+    fk.fk_timing_enable(True)
+    for name, call in (
+            ("martingale_stride500", lambda: fk.fk_interface_solve_cv(wl.density, wl.data, pts, wl.t, wl.dt, n_paths,
+                                                                      cv, stride=500, seed=wl.seed,
+                                                                      form=fk.FK_CV_MARTINGALE, plain=False)),
+            ("martingale_stride20", lambda: fk.fk_interface_solve_cv(wl.density, wl.data, pts, wl.t, wl.dt, n_paths,
+                                                                     cv, stride=20, seed=wl.seed,
+                                                                     form=fk.FK_CV_MARTINGALE, plain=False)),
+            ("linear", lambda: fk.fk_interface_solve_cv(wl.density, gdata, pts, wl.t, wl.dt, n_paths, None,
+                                                        stride=1 << 20, seed=wl.seed, form=fk.FK_CV_MARTINGALE_GRID,
+                                                        plain=False, grids=grids))):
+        ms, steps = [], []
+        for _ in range(2):
+            r = call()
+            torch.cuda.synchronize()
+            ms.append(fk.fk_timing_last()[0])
+            steps.append(int(r["total_steps"].item()))
+        res[name] = {"path_kernel_ms": ms, "path_steps": steps}
+    fk.fk_timing_enable(False)
+    cv.close()
+    return {"cv_kernels": res, "n_paths": n_paths, "nodes": int(pts.shape[0])}
+
+
 def measure_bridge(fk, wl, pts, fd, pilot_paths=100000):
     """The headline workload with the Brownian-bridge exit test and with
     exponential time-stepping, at the configured dt and at coarser steps
@@ -469,6 +510,8 @@ def main():
     ap.add_argument("--no-bridge", action="store_true", help="skip the Brownian-bridge exit-test leg")
     ap.add_argument("--no-steady", action="store_true", help="skip the elliptic (steady) meshes")
     ap.add_argument("--paths", type=int, default=0, help="fix paths/node and skip the N* pilot (profiling)")
+    ap.add_argument("--cv-kernels-only", action="store_true",
+                    help="run only the control-variate kernels at the timed solve's size (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scales HBM counters) and exit")
     args = ap.parse_args()
@@ -486,6 +529,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes": n}))
+        return
+
+    if args.cv_kernels_only:
+        print(json.dumps(cv_kernels_only(fk)))
         return
 
     wl = W.MOVING_BUMP_1521
@@ -539,7 +586,7 @@ def main():
         kern_ms.append(a)
         red_ms.append(b)
         steps_total.append(int(r["total_steps"].item()))
-        print(f"[bench] step: path kernel {a:.1f} ms, reduce {b:.2f} ms", file=sys.stderr, flush=True)
+        print(f"[bench] step: path kernel {a:.1f} ms, finalize {b:.2f} ms", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     fk.fk_timing_enable(False)
@@ -570,7 +617,7 @@ def main():
             "n_nodes": n_nodes, "paths_per_node": n_star, "rms_err": rms, "pilot": pilot,
             "path_steps_per_launch": path_steps,
             "path_steps_per_s": path_steps / (kms * 1e-3),
-            "path_kernel_ms": kms, "reduce_kernel_ms": float(np.mean(red_ms)),
+            "path_kernel_ms": kms, "finalize_kernel_ms": float(np.mean(red_ms)),
         },
         "roofline": {
             "bound": "alu", "achieved": achieved, "peak": FP32_PEAK_TFLOPS, "unit": "TFLOP/s",

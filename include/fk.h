@@ -144,7 +144,8 @@ typedef struct fk_plan {
     int32_t blocks_per_cu;  /* resident workgroups per compute unit for the persistent grid */
     int32_t chunk;          /* paths handed to a wavefront per queue grab (>= 1) */
     int32_t node_tile;      /* work order: the chunks of this many consecutive nodes (in the queue's
-                               cost order) interleaved, 1..256; 1 = node by node */
+                               cost order) interleaved, a power of two 1..256 (FK_E_INVAL otherwise);
+                               1 = node by node; a last, partial tile runs node by node */
 } fk_plan;
 
 /*

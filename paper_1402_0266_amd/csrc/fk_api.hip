@@ -132,7 +132,8 @@ int resolve_plan(const fk_plan *plan, fk_plan *out) {
         if (plan->chunk) pl.chunk = plan->chunk;
         if (plan->node_tile) pl.node_tile = plan->node_tile;
     }
-    if (pl.node_tile < 1 || pl.node_tile > 256) return fail(FK_E_INVAL, "plan node_tile must be in [1, 256]");
+    if (pl.node_tile < 1 || pl.node_tile > 256 || (pl.node_tile & (pl.node_tile - 1)))
+        return fail(FK_E_INVAL, "plan node_tile must be a power of two in [1, 256]");
     if (pl.block < 64 || pl.block > 256 || pl.block % 64)
         return fail(FK_E_INVAL, "plan block must be 64, 128, 192 or 256");
     if (pl.chunk < 1 || pl.chunk > (int)kMaxChunk) return fail(FK_E_INVAL, "plan chunk must be in [1, %u]", kMaxChunk);
@@ -312,7 +313,7 @@ int enqueue_solve(const SolveLaunch &S, hipStream_t stream, bool allow_timing) {
     a.chunk = (uint32_t)S.plan.chunk;
     a.cpn = (uint32_t)cpn;
     a.total_chunks = (uint32_t)(S.n_nodes * cpn);
-    a.node_tile = (uint32_t)S.plan.node_tile;
+    a.tile_shift = (uint32_t)__builtin_ctz((unsigned)S.plan.node_tile);
     int bpc = S.plan.blocks_per_cu;
     const bool expo = a.score_mode == FK_SCORE_EXPONENTIAL;
     const int occ = expo ? expo_kernel_max_blocks_per_cu(S.kind, S.time_mode, S.plan.block)

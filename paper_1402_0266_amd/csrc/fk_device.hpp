@@ -28,6 +28,10 @@ __device__ __forceinline__ uint32_t xor3_uniform(uint32_t a, uint32_t b, uint32_
 
 __device__ __forceinline__ PhiloxOut philox4x32_10(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                                    uint32_t k0, uint32_t k1) {
+    // The round keys are re-derived per call (two scalar adds a round, off
+    // the VALU) instead of being hoisted out of the path loop, where twenty
+    // live key words would push loop values out of the scalar file.
+    asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
         const uint64_t p0 = (uint64_t)0xD2511F53u * c0;

@@ -86,7 +86,7 @@ struct PathArgs {
     uint32_t cpn;                    // chunks per node
     uint32_t total_chunks;           // host bound on the work chunks (grid size); the kernels
                                      // read the launch's own count from queue[kCtrTotal]
-    uint32_t node_tile;              // chunk order: interleave the chunks of this many nodes (<= 1: node by node)
+    uint32_t tile_shift;             // chunk order: interleave the chunks of 2^tile_shift nodes (0: node by node)
 };
 
 // The estimator's last step: node sums -> means, standard errors, steps.

@@ -166,29 +166,23 @@ __device__ __forceinline__ uint32_t launch_chunks(const PathArgs &a) {
 }
 
 // Node slot and path chunk of work chunk c (c < total).  Node by node, or
-// (node_tile > 1) with the chunks of node_tile consecutive slots interleaved,
-// the last, partial tile likewise over its remaining slots.  The order only
-// changes the schedule: every path draws from its own counters and every
-// sum is exact.
+// (tile_shift > 0) with the chunks of 2^tile_shift consecutive slots
+// interleaved; a last, partial tile runs node by node.  Only the division by
+// cpn of the node-by-node order is needed: the tile is a power of two, so the
+// rest is masks and shifts.  The order only changes the schedule: every path
+// draws from its own counters and every sum is exact.
 __device__ __forceinline__ void chunk_slot(const PathArgs &a, uint32_t total, uint32_t c, uint32_t &slot,
                                            uint32_t &pc) {
-    const uint32_t nt = a.node_tile;
-    if (nt <= 1u) {
-        slot = c / a.cpn;
-        pc = c - slot * a.cpn;
-        return;
-    }
-    const uint32_t n_act = total / a.cpn, span = nt * a.cpn, full = n_act / nt;
-    const uint32_t tile = c / span;
-    if (tile < full) {
-        const uint32_t r = c - tile * span;
-        slot = tile * nt + r % nt;
-        pc = r / nt;
-    } else {
-        const uint32_t rem = n_act - full * nt, r = c - full * span;
-        slot = full * nt + r % rem;
-        pc = r / rem;
-    }
+    const uint32_t q = c / a.cpn;
+    slot = q;
+    pc = c - q * a.cpn;
+    const uint32_t sh = a.tile_shift;
+    if (sh == 0u) return;
+    const uint32_t m = (1u << sh) - 1u;
+    if ((uint64_t)((q | m) + 1u) * a.cpn > total) return;   // in the partial last tile
+    const uint32_t r = (q & m) * a.cpn + pc;                 // rank of the chunk within its tile
+    slot = (q & ~m) | (r & m);
+    pc = r >> sh;
 }
 
 // The cursor (node slot, path range) of chunk c; false past the last chunk.

@@ -50,6 +50,8 @@ def _call(fk, dens=None, data=None, pts=None, t=0.05, dt=1e-4, n_paths=16, ws_by
     (dict(ws_bytes=16), -3),
     (dict(plan={"chunk": 4096}), -1),      # a chunk's sums must fit the 64-bit LDS slots
     (dict(plan={"block": 96}), -1),
+    (dict(plan={"node_tile": 3}), -1),     # node tiles are powers of two
+    (dict(plan={"node_tile": 512}), -1),
     (dict(out_ptr=None), -1),
 ])
 def test_validation_errors(fk, kw, code):
