@@ -76,6 +76,11 @@ FP32_PEAK_TFLOPS = 157.3
 #                  2A/s2 e, reciprocal, product, 2 components)
 #   Euler-Maruyama update 4 (2 fma)
 FLOP_PER_STEP = 36
+# The martingale form's network gradient on MFMA: value, d/dx and d/dy
+# channels through the two 64 x 64 hidden products, 2 FLOP per
+# multiply-add: 3 x 2 x 2 x 64 x 64 per evaluation point.
+NET_GRAD_FLOP = 3 * 2 * 2 * 64 * 64
+BF16_PEAK_TFLOPS = 2500.0
 # Paths per node of the control-variate kernels' profile (the timed solve's N*).
 CV_PROFILE_PATHS = 2952
 
@@ -182,7 +187,8 @@ def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=409
         return fk.fk_interface_solve_cv(wl.density, wl.data, pts, wl.t, wl.dt, n_paths, cv, stride=stride,
                                         seed=wl.seed, form=form, plain=plain)
 
-    def pilot(form, stride):
+    def pilot(form, stride, grad="split"):
+        cv.set_grad_precision(grad)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         r = solve(pilot_paths, form, stride)
@@ -194,16 +200,19 @@ def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=409
         b2 = max(0.0, float(np.mean((est - ref) ** 2)) - var / pilot_paths)
         n_star = int(math.ceil(var / (1e-6 - b2))) if b2 < 1e-6 else None
         return {"form": "martingale" if form == fk.FK_CV_MARTINGALE else "dynkin", "stride": stride,
-                "pilot_s": el, "var": var, "var_ratio": float(np.mean(pse ** 2) / np.mean(se ** 2)),
+                "grad": grad if form == fk.FK_CV_MARTINGALE else "split", "pilot_s": el, "var": var, "var_ratio": float(np.mean(pse ** 2) / np.mean(se ** 2)),
                 "bias": math.sqrt(b2), "n_star": n_star,
                 "predicted_s": None if n_star is None else el * n_star / pilot_paths}
 
     solve(256, fk.FK_CV_MARTINGALE, 20)         # first-launch costs out of the pilots
-    pilots = [pilot(fk.FK_CV_MARTINGALE, s) for s in (20, 100, 500, 2000)] + [pilot(fk.FK_CV_DYNKIN, 50)]
+    pilots = ([pilot(fk.FK_CV_MARTINGALE, s) for s in (20, 100, 500, 2000)] +
+              [pilot(fk.FK_CV_MARTINGALE, s, "bf16") for s in (20, 100, 500)] + [pilot(fk.FK_CV_DYNKIN, 50)])
     best = min((p for p in pilots if p["form"] == "martingale" and p["n_star"]),
                key=lambda p: p["predicted_s"])
     form, stride, n_star = fk.FK_CV_MARTINGALE, best["stride"], max(2, best["n_star"])
-    print(f"[bench] cv: martingale stride {stride}, N* = {n_star}", file=sys.stderr, flush=True)
+    cv.set_grad_precision(best["grad"])
+    print(f"[bench] cv: martingale stride {stride} ({best['grad']} gradient), N* = {n_star}", file=sys.stderr,
+          flush=True)
     for _ in range(warmup):
         solve(n_star, form, stride, plain=False)
     torch.cuda.synchronize()
@@ -217,6 +226,7 @@ def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=409
     wall = (time.perf_counter() - t0) / steps
     fk.fk_timing_enable(False)
     rms = float(np.sqrt(np.mean((_stack(r, ("xi", "eta")) - ref) ** 2)))
+    steps_cv = int(r["total_steps"].item())
     cv.close()
     # Beside the network: the same martingale estimator with the identity
     # map's gradient (the linear control, no training).  The identity data
@@ -252,9 +262,11 @@ def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=409
         el = time.perf_counter() - t0
         linear.update({"paths_per_node": max(2, n_lin), "s_per_solve": el, "nodes_per_s": n_nodes / el,
                        "rms_err": float(np.sqrt(np.mean((_stack(rl, ("xi", "eta")) - ref) ** 2)))})
+    kms = float(np.mean(kern))
     return {
-        "form": "martingale", "stride": stride, "paths_per_node": n_star, "rms_err": rms,
-        "s_per_solve": wall, "path_kernel_ms": float(np.mean(kern)),
+        "form": "martingale", "stride": stride, "grad": best["grad"], "paths_per_node": n_star, "rms_err": rms,
+        "s_per_solve": wall, "path_kernel_ms": kms,
+        "roofline": cv_roofline(steps_cv, stride, kms, best["grad"]),
         "nodes_per_s": n_nodes / wall,
         "nodes_per_s_incl_labels_and_training": n_nodes / (wall + t_labels + t_train),
         "labels": {"levels": 132, "paths": label_paths, "n": int(txy.shape[0]), "s": t_labels},
@@ -263,6 +275,23 @@ def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=409
         "pilots": pilots,
         "linear_control": linear,
     }
+
+
+def cv_roofline(path_steps, stride, kernel_ms, grad):
+    """Roofline of the martingale path kernel: FP32 VALU on the path steps
+    (FLOP_PER_STEP each) against the FP32 vector peak, and the network's
+    products on MFMA against the dense BF16 peak.  The network's algorithmic
+    work is NET_GRAD_FLOP per evaluation point, one evaluation per `stride`
+    steps of a path (path_steps / stride); the hi + lo split issues each
+    product twice, which counts as work done but not as algorithmic work."""
+    fp32 = FLOP_PER_STEP * path_steps / (kernel_ms * 1e-3) / 1e12
+    evals = path_steps / stride
+    mf = NET_GRAD_FLOP * evals / (kernel_ms * 1e-3) / 1e12
+    return {"kernel": "fk_mg_path_kernel", "bound": "alu", "achieved": fp32, "peak": FP32_PEAK_TFLOPS,
+            "unit": "TFLOP/s", "frac": fp32 / FP32_PEAK_TFLOPS, "flop_per_path_step": FLOP_PER_STEP,
+            "mfma": {"achieved": mf, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": mf / BF16_PEAK_TFLOPS,
+                     "flop_per_eval": NET_GRAD_FLOP, "evals_per_launch": evals,
+                     "issued_per_algorithmic": 2 if grad == "split" else 1}}
 
 
 def measure_batched(fk, probe_paths=512):
@@ -340,15 +369,17 @@ def measure_paper_run():
 
 def cv_kernels_only(fk, n_paths=CV_PROFILE_PATHS):
     """The control-variate kernels of the timed solve at its size, for the
-    profiler: the martingale kernel with the network at strides 500 and 20
-    (weights do not change the work: an untrained identity-base network)
-    and the linear control, two launches each."""
+    profiler: the martingale kernel with the network at strides 500 and 20,
+    with the hi + lo and the BF16 gradient (weights do not change the work:
+    an untrained identity-base network), and the linear control, two
+    launches each."""
     import dataclasses
 
     import torch
     wl = W.MOVING_BUMP_1521
     pts = torch.tensor(wl.nodes(), dtype=torch.float64, device="cuda")
     cv = fk.FkCv(W.mlp_init(0), W.CV_T_SCALE, identity_base=True)
+    cvb = fk.FkCv(W.mlp_init(0), W.CV_T_SCALE, identity_base=True, grad_precision="bf16")
     G = 256
     x = torch.arange(G + 1, dtype=torch.float64, device="cuda") / G
     grids = (x.repeat(G + 1, 1).contiguous().view(-1), x[:, None].repeat(1, G + 1).contiguous().view(-1))
@@ -362,6 +393,12 @@ def cv_kernels_only(fk, n_paths=CV_PROFILE_PATHS):
             ("martingale_stride20", lambda: fk.fk_interface_solve_cv(wl.density, wl.data, pts, wl.t, wl.dt, n_paths,
                                                                      cv, stride=20, seed=wl.seed,
                                                                      form=fk.FK_CV_MARTINGALE, plain=False)),
+            ("martingale_bf16_stride500", lambda: fk.fk_interface_solve_cv(wl.density, wl.data, pts, wl.t, wl.dt,
+                                                                           n_paths, cvb, stride=500, seed=wl.seed,
+                                                                           form=fk.FK_CV_MARTINGALE, plain=False)),
+            ("martingale_bf16_stride20", lambda: fk.fk_interface_solve_cv(wl.density, wl.data, pts, wl.t, wl.dt,
+                                                                          n_paths, cvb, stride=20, seed=wl.seed,
+                                                                          form=fk.FK_CV_MARTINGALE, plain=False)),
             ("linear", lambda: fk.fk_interface_solve_cv(wl.density, gdata, pts, wl.t, wl.dt, n_paths, None,
                                                         stride=1 << 20, seed=wl.seed, form=fk.FK_CV_MARTINGALE_GRID,
                                                         plain=False, grids=grids))):
@@ -374,6 +411,7 @@ def cv_kernels_only(fk, n_paths=CV_PROFILE_PATHS):
         res[name] = {"path_kernel_ms": ms, "path_steps": steps}
     fk.fk_timing_enable(False)
     cv.close()
+    cvb.close()
     return {"cv_kernels": res, "n_paths": n_paths, "nodes": int(pts.shape[0])}
 
 
@@ -636,8 +674,8 @@ def main():
         out["cv"]["identity_base"] = True
         pn = measure_cv(fk, wl, pts, fd, args.steps, args.warmup, identity_base=False)
         out["cv"]["plain_output_network"] = {k: pn[k] for k in ("stride", "paths_per_node", "rms_err", "nodes_per_s")}
-        out["cv"]["plain_output_network"]["pilots"] = [{k: p[k] for k in ("form", "stride", "var_ratio", "n_star")}
-                                                       for p in pn["pilots"]]
+        out["cv"]["plain_output_network"]["pilots"] = [
+            {k: p[k] for k in ("form", "stride", "grad", "var_ratio", "n_star")} for p in pn["pilots"]]
     if not args.no_bridge and fd is not None:
         out["bridge"] = measure_bridge(fk, wl, pts, fd)
     if not args.no_mesh_run:

@@ -536,6 +536,25 @@ int fk_cv_set_params(fk_cv_t cv, const float *params /* host [8706] */);
  * out (device [n][2][5]) = for each output: value, d/dx, d/dy, d/dt,
  * Laplacian in (x, y). */
 int fk_cv_eval(fk_cv_t cv, const float *txy, int64_t n, float *out, hipStream_t stream);
+/* Precision of the network's (x, y) gradient in the martingale forms of
+ * fk_interface_solve_cv (FK_CV_MARTINGALE, and the network part under
+ * FK_CV_BASE_GRID).  FK_CV_GRAD_SPLIT (the default): every activation enters
+ * the BF16 products as a hi + lo pair, two products each, and the gradient
+ * matches the FP64 evaluation of the same BF16 weights to ~1e-5 relative.
+ * FK_CV_GRAD_BF16: activations are rounded to BF16 once (half the products
+ * and conversions), ~1e-2 relative.  The martingale estimator is unbiased
+ * for any gradient fixed before the increments it multiplies, so both give
+ * the same expectation; the rounding only moves each path's score a little
+ * (and the variance with it).  The Dynkin form and fk_cv_eval always use
+ * the split form.  Applies to later calls; FK_E_INVAL for other modes. */
+#define FK_CV_GRAD_SPLIT 0
+#define FK_CV_GRAD_BF16 1
+int fk_cv_set_grad_precision(fk_cv_t cv, int32_t mode);
+/* The network's (x, y) gradient at n points txy (device [n][3]: t, x, y) as
+ * the martingale path kernels take it (the handle's gradient precision and
+ * base): out (device [n][2][2]) = (dxi/dx, dxi/dy, deta/dx, deta/dy).
+ * Parity hook. */
+int fk_cv_eval_grad(fk_cv_t cv, const float *txy, int64_t n, float *out, hipStream_t stream);
 /* Gradient of the mean-squared error over all n samples (device txy [n][3],
  * target [n][2]) at the current network: grad device [8706], loss device [1]
  * (mean over samples and both outputs) or NULL.  Parity hook. */

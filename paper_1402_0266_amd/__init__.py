@@ -155,6 +155,10 @@ _lib.fk_cv_set_params.argtypes = [_P, _P]
 _lib.fk_cv_set_params.restype = ctypes.c_int
 _lib.fk_cv_eval.argtypes = [_P, _P, ctypes.c_int64, _P, _P]
 _lib.fk_cv_eval.restype = ctypes.c_int
+_lib.fk_cv_set_grad_precision.argtypes = [_P, ctypes.c_int32]
+_lib.fk_cv_set_grad_precision.restype = ctypes.c_int
+_lib.fk_cv_eval_grad.argtypes = [_P, _P, ctypes.c_int64, _P, _P]
+_lib.fk_cv_eval_grad.restype = ctypes.c_int
 _lib.fk_cv_grad.argtypes = [_P, _P, _P, ctypes.c_int64, _P, _P, _P]
 _lib.fk_cv_grad.restype = ctypes.c_int
 _lib.fk_cv_adam_apply.argtypes = [_P, _P, ctypes.c_float, _P]
@@ -770,15 +774,18 @@ FK_CV_N_PARAMS = 8706
 
 
 FK_CV_BASES = {"none": 0, "identity": 1, "grid": 2}
+FK_CV_GRAD_PRECISIONS = {"split": 0, "bf16": 1}
 
 
 class FkCv:
     """The control-variate network (C: ``fk_cv_*``)."""
 
-    def __init__(self, params, t_scale=0.1, identity_base=False, base=None):
+    def __init__(self, params, t_scale=0.1, identity_base=False, base=None, grad_precision="split"):
         """``base``: None / "none" (the network itself), "identity" (u_hat =
         (x, y) + network; also ``identity_base=True``) or "grid" (u_hat = the
-        solve's grid initial data, bilinear, + network; martingale solves)."""
+        solve's grid initial data, bilinear, + network; martingale solves).
+        ``grad_precision``: "split" (BF16 hi + lo operands) or "bf16"
+        (activations rounded to BF16 once) for the martingale forms' gradient."""
         p = np.ascontiguousarray(params, dtype=np.float32).ravel()
         if p.size != FK_CV_N_PARAMS:
             raise ValueError("need 8706 parameters")
@@ -792,6 +799,13 @@ class FkCv:
         self.base = base
         self.identity_base = base == "identity"
         _check(_lib.fk_cv_set_base(h, FK_CV_BASES[base]))
+        self.set_grad_precision(grad_precision)
+
+    def set_grad_precision(self, mode):
+        if mode not in FK_CV_GRAD_PRECISIONS:
+            raise ValueError(f"grad_precision must be one of {sorted(FK_CV_GRAD_PRECISIONS)}")
+        _check(_lib.fk_cv_set_grad_precision(self._h, FK_CV_GRAD_PRECISIONS[mode]))
+        self.grad_precision = mode
 
     def close(self):
         if getattr(self, "_h", None) and _lib is not None:
@@ -822,6 +836,14 @@ class FkCv:
         import torch
         out = torch.empty((txy.shape[0], 2, 5), dtype=torch.float32, device=txy.device)
         _check(_lib.fk_cv_eval(self._h, txy.data_ptr(), txy.shape[0], out.data_ptr(), _stream(torch, txy.device)))
+        return out
+
+    def eval_grad(self, txy):
+        """(x, y) gradient [n, 2, 2] as the martingale path kernels take it, at device points txy [n, 3]."""
+        import torch
+        out = torch.empty((txy.shape[0], 2, 2), dtype=torch.float32, device=txy.device)
+        _check(_lib.fk_cv_eval_grad(self._h, txy.data_ptr(), txy.shape[0], out.data_ptr(),
+                                    _stream(torch, txy.device)))
         return out
 
     def grad(self, txy, target):

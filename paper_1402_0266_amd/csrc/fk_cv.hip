@@ -4,17 +4,22 @@
 //
 //  * Training: mean-squared error on (t, x, y) -> Monte-Carlo interface
 //    estimates, Adam (FP32 master weights and moments).  Forward and
-//    backward run on BF16 MFMA (v_mfma_f32_16x16x16_bf16, FP32 accumulate)
+//    backward run on BF16 MFMA (v_mfma_f32_16x16x32_bf16, FP32 accumulate)
 //    over LDS-resident 64-sample tiles; the per-tile weight gradients are
 //    summed in a fixed order by the Adam kernel.
 //  * Evaluation: forward-mode value, d/dx, d/dy, d/dt and Laplacian of both
-//    outputs, wavefront-wide: 16 points per round, the 5 derivative channels
-//    as 5 MFMA column blocks.  The MFMA output layout (lane = point column,
-//    4 consecutive units per lane group) is the B-operand layout of the next
-//    layer, so layers chain in registers.  Activations are split into BF16
-//    hi + lo parts (two MFMAs per product) so that the evaluation carries
-//    ~16 mantissa bits: the Dynkin-form estimator is only unbiased if value
-//    and derivative channels describe one function consistently.
+//    outputs, wavefront-wide: 16 points per round, the derivative channels
+//    as MFMA column blocks.  A 16x16x32 product's output (lane = point
+//    column, 4 consecutive units per lane group) of two adjacent 16-unit
+//    tiles is the B operand of one 32-unit K block of the next layer, once
+//    the K order inside the block is permuted alike in the weights, so
+//    layers chain in registers.  Activations are split into BF16 hi + lo
+//    parts (two MFMAs per product) so that the evaluation carries ~16
+//    mantissa bits: the Dynkin-form estimator is only unbiased if value and
+//    derivative channels describe one function consistently.  The martingale
+//    form's gradient may instead round activations to BF16 once (one MFMA
+//    per product): its estimator stays unbiased for any gradient fixed
+//    before the block's increments.
 //  * The control-variate path kernel: plain Euler-Maruyama paths (same
 //    counters as fk_interface_solve) plus, every `stride` steps and at the
 //    path's end, the integrand r = Laplacian u_hat + b . grad u_hat - d_t u_hat
@@ -35,14 +40,14 @@
 #include "fk_internal.hpp"
 #include "fk_pathstep.hpp"
 
-typedef short fk_s4 __attribute__((ext_vector_type(4)));
+typedef __bf16 fk_b8 __attribute__((ext_vector_type(8)));
 typedef float fk_f4 __attribute__((ext_vector_type(4)));
 
 namespace fk {
 
 constexpr int kNP = 8706;
 constexpr int OW1 = 0, OB1 = 192, OW2 = 256, OB2 = 4352, OW3 = 4416, OB3 = 8512, OW4 = 8576, OB4 = 8704;
-constexpr int kWS = 68;  // padded LDS row stride (bf16 elements) of W2 / W3
+constexpr int kWS = 72;  // padded LDS row stride (bf16 elements) of W2 / W3: rows on 16-byte boundaries
 
 struct TrainDesc;
 
@@ -74,6 +79,8 @@ struct fk_cv {
     float t_scale = 0.1f;
     float base = 0.f;    // 1: u_hat = (x, y) + network (the identity base)
     int grid_base = 0;   // 1: u_hat = bilinear(grid initial data) + network (martingale solves)
+    int grad_bf16 = 0;   // 1: the martingale forms take the network's gradient with BF16-rounded
+                         // activations (FK_CV_GRAD_BF16), else with hi + lo operands
     int64_t steps_done = 0;
     fk::CvState s;
 };
@@ -86,6 +93,9 @@ __device__ __forceinline__ uint16_t f2bf(float f) { return __builtin_bit_cast(ui
 // ---------------------------------------------------------------------------
 // The network in LDS.
 // ---------------------------------------------------------------------------
+// 2 log2(e): tanh(a) = 1 - 2 / (1 + 2^(a K2)).
+constexpr float K2 = 2.8853900817779268f;
+
 struct NetLds {
     float w1[64 * 3];
     float b1[64], b2[64], b3[64];
@@ -93,7 +103,21 @@ struct NetLds {
     float b4[2];
     uint16_t w2[64 * kWS];
     uint16_t w3[64 * kWS];
+    // for the gradient evaluation: per unit u (K2 w0, K2 w1, K2 w2, K2 b1);
+    // per group of four units 4 q .. 4 q + 3 (the four a lane takes from one
+    // 16x16 output tile) K2 b2, K2 b3, W4[0] and W4[1]
+    float4 g1[64];
+    float4 q2[16], q3[16], q40[16], q41[16];
 };
+
+// Column position of unit k of a W2 / W3 row in LDS: inside each 32-unit
+// block, the units lane group g takes as MFMA operand elements 0-7 (ku: 4 g
+// .. 4 g + 3 and 16 + 4 g .. 16 + 4 g + 3) sit next to each other at 8 g, so
+// an operand is one 16-byte read.
+__device__ __forceinline__ int wcol(int k) {
+    const int b = k & 31;
+    return (k & ~31) | (8 * ((b & 15) >> 2) + 4 * (b >> 4) + (b & 3));
+}
 
 __device__ void load_net(NetLds &N, const uint16_t *bf) {
     for (int i = threadIdx.x; i < 192; i += blockDim.x) N.w1[i] = bf2f(bf[OW1 + i]);
@@ -106,8 +130,16 @@ __device__ void load_net(NetLds &N, const uint16_t *bf) {
     if (threadIdx.x < 2) N.b4[threadIdx.x] = bf2f(bf[OB4 + threadIdx.x]);
     for (int i = threadIdx.x; i < 4096; i += blockDim.x) {
         const int r = i >> 6, c = i & 63;
-        N.w2[r * kWS + c] = bf[OW2 + i];
-        N.w3[r * kWS + c] = bf[OW3 + i];
+        N.w2[r * kWS + wcol(c)] = bf[OW2 + i];
+        N.w3[r * kWS + wcol(c)] = bf[OW3 + i];
+    }
+    for (int u = threadIdx.x; u < 64; u += blockDim.x) {
+        const float w0 = bf2f(bf[OW1 + 3 * u]), w1 = bf2f(bf[OW1 + 3 * u + 1]), w2 = bf2f(bf[OW1 + 3 * u + 2]);
+        N.g1[u] = make_float4(K2 * w0, K2 * w1, K2 * w2, K2 * bf2f(bf[OB1 + u]));
+        reinterpret_cast<float *>(N.q2)[u] = K2 * bf2f(bf[OB2 + u]);
+        reinterpret_cast<float *>(N.q3)[u] = K2 * bf2f(bf[OB3 + u]);
+        reinterpret_cast<float *>(N.q40)[u] = bf2f(bf[OW4 + u]);
+        reinterpret_cast<float *>(N.q41)[u] = bf2f(bf[OW4 + 64 + u]);
     }
 }
 
@@ -116,7 +148,7 @@ __device__ void load_net(NetLds &N, const uint16_t *bf) {
 __device__ __forceinline__ void act5(float a, float ax, float ay, float at, float al, float &h, float &hx,
                                      float &hy, float &ht, float &hl) {
     const float ac = fminf(fmaxf(a, -15.f), 15.f);
-    const float e = hw_exp2(ac * 2.8853900817779268f);
+    const float e = hw_exp2(ac * K2);
     const float r = hw_rcp(1.f + e);
     h = fmaf(-2.f, r, 1.f);
     const float s = 4.f * e * r * r;
@@ -124,13 +156,6 @@ __device__ __forceinline__ void act5(float a, float ax, float ay, float at, floa
     hy = s * ay;
     ht = s * at;
     hl = s * fmaf(-2.f * h, fmaf(ax, ax, ay * ay), al);
-}
-
-// BF16 hi + lo split of an FP32 value.
-__device__ __forceinline__ void split_bf16(float v, short &hi, short &lo) {
-    const __bf16 h = (__bf16)v;
-    hi = __builtin_bit_cast(short, h);
-    lo = __builtin_bit_cast(short, (__bf16)(v - (float)h));
 }
 
 // The identity base (base = 1): u_hat = (x, y) + network, so the value of
@@ -147,30 +172,40 @@ __device__ __forceinline__ void add_base_grad(float base, float o[2][2]) {
     o[1][1] += base;
 }
 
-__device__ __forceinline__ fk_f4 mfma16(fk_s4 a, fk_s4 b, fk_f4 c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+__device__ __forceinline__ fk_f4 mfma32(fk_b8 a, fk_b8 b, fk_f4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
 }
 
-// A operand (16x16 tile) of a padded BF16 weight matrix: lane holds
-// W[16 mt + (lane % 16)][16 kt + 4 (lane / 16) + 0..3].
-__device__ __forceinline__ fk_s4 load_a(const uint16_t *W, int mt, int kt, int n, int g) {
-    const uint16_t *p = W + (16 * mt + n) * kWS + 16 * kt + 4 * g;
-    fk_s4 a;
-    a[0] = (short)p[0];
-    a[1] = (short)p[1];
-    a[2] = (short)p[2];
-    a[3] = (short)p[3];
-    return a;
+// K order of the 32-unit block kb inside a product: lane group g's operand
+// element j is unit ku(kb, g, j) = 32 kb + 16 (j / 4) + 4 g + j % 4, i.e.
+// elements 0-3 are the 16x16 output rows 4 g .. 4 g + 3 of tile 2 kb and
+// elements 4-7 those of tile 2 kb + 1.  A and B use the same order, so the
+// product sums every unit of the block once.
+__device__ __forceinline__ int ku(int kb, int g, int j) { return 32 * kb + 16 * (j >> 2) + 4 * g + (j & 3); }
+
+// A operand of a padded BF16 weight matrix: lane (g, n) holds
+// W[16 mt + n][ku(kb, g, 0..7)], 16 bytes at column 32 kb + 8 g (wcol).
+__device__ __forceinline__ fk_b8 load_a(const uint16_t *W, int mt, int kb, int n, int g) {
+    return __builtin_bit_cast(fk_b8, *reinterpret_cast<const uint4 *>(W + (16 * mt + n) * kWS + 32 * kb + 8 * g));
+}
+
+// BF16 hi (+ lo with SPLIT) operand element of an FP32 value.
+template <bool SPLIT>
+__device__ __forceinline__ void put_bf16(float v, fk_b8 &hi, fk_b8 &lo, int j) {
+    const __bf16 h = (__bf16)v;
+    hi[j] = h;
+    if constexpr (SPLIT) lo[j] = (__bf16)(v - (float)h);
 }
 
 // Wavefront-wide forward-mode evaluation.  Every lane of the wavefront must
 // call it.  Lane l's point is (tau, x, y); on return out[o][c] holds, for
 // output o, channel c = value, d/dx, d/dy, d/dtau, Laplacian (x, y).
+// Activations enter the products as BF16 hi + lo pairs.
 //
 // Register budget: per round (16 points) at most the layer-2 accumulators
 // (4 output tiles x 5 channels x 4) plus one operand block are live; layer 1
 // is computed per K block as it is consumed, and layer 3 per output tile from
-// the BF16 hi/lo operands of all four K blocks.
+// the hi/lo operands of both K blocks.
 __device__ void net_eval_wave(const NetLds &N, float tscale2, float tau, float x, float y, float out[2][5]) {
     const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
 #pragma unroll 1
@@ -191,51 +226,41 @@ __device__ void net_eval_wave(const NetLds &N, float tscale2, float tau, float x
 #pragma unroll
             for (int c = 0; c < 5; ++c) acc[mt][c] = fk_f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kt = 0; kt < 4; ++kt) {
-            // layer 1 (VALU) for units 16 kt + 4 g + i of point n
-            fk_s4 Bh[5], Bl[5];
+        for (int kb = 0; kb < 2; ++kb) {
+            // layer 1 (VALU) for units ku(kb, g, j) of point n
+            fk_b8 Bh[5], Bl[5];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int u = 16 * kt + 4 * g + i;
+            for (int j = 0; j < 8; ++j) {
+                const int u = ku(kb, g, j);
                 const float w0 = M.w1[3 * u], w1 = M.w1[3 * u + 1], w2 = M.w1[3 * u + 2];
                 const float a = fmaf(w0, z0, fmaf(w1, z1, fmaf(w2, z2, M.b1[u])));
                 float ch[5];
                 act5(a, 2.f * w1, 2.f * w2, tscale2 * w0, 0.f, ch[0], ch[1], ch[2], ch[3], ch[4]);
 #pragma unroll
-                for (int c = 0; c < 5; ++c) {
-                    short hi, lo;
-                    split_bf16(ch[c], hi, lo);
-                    Bh[c][i] = hi;
-                    Bl[c][i] = lo;
-                }
+                for (int c = 0; c < 5; ++c) put_bf16<true>(ch[c], Bh[c], Bl[c], j);
             }
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
-                const fk_s4 A = load_a(M.w2, mt, kt, n, g);
+                const fk_b8 A = load_a(M.w2, mt, kb, n, g);
 #pragma unroll
                 for (int c = 0; c < 5; ++c) {
-                    acc[mt][c] = mfma16(A, Bh[c], acc[mt][c]);
-                    acc[mt][c] = mfma16(A, Bl[c], acc[mt][c]);
+                    acc[mt][c] = mfma32(A, Bh[c], acc[mt][c]);
+                    acc[mt][c] = mfma32(A, Bl[c], acc[mt][c]);
                 }
             }
         }
         // ---- layer 2 activations -> layer 3 operands -------------------------
-        fk_s4 Ch[4][5], Cl[4][5];
+        fk_b8 Ch[2][5], Cl[2][5];
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
+        for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int u = 16 * mt + 4 * g + i;
+            for (int j = 0; j < 8; ++j) {
+                const int mt = 2 * kb + (j >> 2), i = j & 3, u = ku(kb, g, j);
                 float ch[5];
                 act5(acc[mt][0][i] + M.b2[u], acc[mt][1][i], acc[mt][2][i], acc[mt][3][i], acc[mt][4][i], ch[0], ch[1],
                      ch[2], ch[3], ch[4]);
 #pragma unroll
-                for (int c = 0; c < 5; ++c) {
-                    short hi, lo;
-                    split_bf16(ch[c], hi, lo);
-                    Ch[mt][c][i] = hi;
-                    Cl[mt][c][i] = lo;
-                }
+                for (int c = 0; c < 5; ++c) put_bf16<true>(ch[c], Ch[kb][c], Cl[kb][c], j);
             }
         // ---- layer 3, one output tile at a time, into the output layer -------
         float po[2][5];
@@ -249,12 +274,12 @@ __device__ void net_eval_wave(const NetLds &N, float tscale2, float tau, float x
 #pragma unroll
             for (int c = 0; c < 5; ++c) a3[c] = fk_f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int kt = 0; kt < 4; ++kt) {
-                const fk_s4 A = load_a(M.w3, mt, kt, n, g);
+            for (int kb = 0; kb < 2; ++kb) {
+                const fk_b8 A = load_a(M.w3, mt, kb, n, g);
 #pragma unroll
                 for (int c = 0; c < 5; ++c) {
-                    a3[c] = mfma16(A, Ch[kt][c], a3[c]);
-                    a3[c] = mfma16(A, Cl[kt][c], a3[c]);
+                    a3[c] = mfma32(A, Ch[kb][c], a3[c]);
+                    a3[c] = mfma32(A, Cl[kb][c], a3[c]);
                 }
             }
 #pragma unroll
@@ -284,85 +309,128 @@ __device__ void net_eval_wave(const NetLds &N, float tscale2, float tau, float x
     }
 }
 
-// tanh with its first derivatives: h = tanh(a), dh = (1 - h^2) da.
-__device__ __forceinline__ void act3(float a, float ax, float ay, float &h, float &hx, float &hy) {
-    const float ac = fminf(fmaxf(a, -15.f), 15.f);
-    const float e = hw_exp2(ac * 2.8853900817779268f);
-    const float r = hw_rcp(1.f + e);
+// tanh with its first derivatives from the pre-activation scaled by K2
+// (as = K2 a): h = tanh(a) = 1 - 2 / (1 + 2^as), s = 1 - h^2, dh = s da.
+// Saturated units need no clamp: 2^as = inf gives h = 1, s = 0, and 2^as = 0
+// gives h = -1, s = 0.  s is formed as 1 - h^2 (one FMA; its absolute error
+// ~1e-7 is far below the operands' BF16 rounding).
+__device__ __forceinline__ void act3(float as, float ax, float ay, float &h, float &hx, float &hy) {
+    const float r = hw_rcp(1.f + hw_exp2(as));
     h = fmaf(-2.f, r, 1.f);
-    const float s = 4.f * e * r * r;
+    const float s = fmaf(-h, h, 1.f);
     hx = s * ax;
     hy = s * ay;
 }
 
+// A 16-byte LDS value at a compile-time field address plus a per-lane byte
+// offset (one ds_read_b128 with the field address as its immediate offset;
+// every read of the gradient evaluation is such a full 16-byte read, so none
+// is merged into a two-address read, whose 8-bit offsets could not hold it).
+template <typename T>
+__device__ __forceinline__ T lds_at(const T *field, int byte_off) {
+    static_assert(sizeof(T) == 16, "16-byte reads only");
+    return *reinterpret_cast<const T *>(reinterpret_cast<const char *>(field) + byte_off);
+}
+
+// A operand of W2 / W3 (as load_a) from the lane's byte offset 2 (n kWS + 8 g).
+__device__ __forceinline__ fk_b8 load_a_at(const uint16_t *W, int mt, int kb, int off_w) {
+    return __builtin_bit_cast(fk_b8, lds_at(reinterpret_cast<const uint4 *>(W + 16 * mt * kWS + 32 * kb), off_w));
+}
+
 // Wavefront-wide gradient of both outputs in (x, y) at lane l's point, for
 // the martingale form: out[o] = (d/dx, d/dy) of output o.  Three channels
-// (value, d/dx, d/dy); the operands are split into BF16 hi + lo parts as in
-// net_eval_wave, so the gradient matches the FP64 evaluation of the network
-// to ~1e-5 relative (plain BF16 operands would leave ~1e-2 absolute).
+// (value, d/dx, d/dy).  SPLIT: the operands are BF16 hi + lo pairs as in
+// net_eval_wave, and the gradient matches the FP64 evaluation of the network
+// to ~1e-5 relative; otherwise activations are rounded to BF16 once (half
+// the products and operand conversions; ~1e-2 relative).
+//
+// Every LDS read is a field address known at compile time plus one of four
+// per-lane byte offsets (lane group g's units sit 4 g on, lane n's weight
+// row n kWS on).  The offsets pass through an empty asm each round, so the
+// reads stay inside the round (the weights are not hoisted into registers)
+// and fold into the reads' immediate offsets.
+template <bool SPLIT>
 __device__ void net_grad_wave(const NetLds &N, float tscale2, float tau, float x, float y, float out[2][2]) {
     const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15;
 #pragma unroll 1
     for (int r = 0; r < 4; ++r) {
-        // an index offset the compiler cannot see through: keeps the weight
-        // reads inside the loop instead of hoisting ~200 registers of them
-        int lz = 0;
-        asm volatile("" : "+s"(lz));
-        const NetLds &M = *reinterpret_cast<const NetLds *>(reinterpret_cast<const char *>(&N) + lz);
+        int off_g = 64 * g, off_q = 16 * g, off_w = 2 * (n * kWS + 8 * g);
+        asm volatile("" : "+v"(off_g), "+v"(off_q), "+v"(off_w));
         const int src = 16 * r + n;
         const float z0 = __shfl(tau, src, 64) * tscale2 - 1.f;
         const float z1 = 2.f * __shfl(x, src, 64) - 1.f;
         const float z2 = 2.f * __shfl(y, src, 64) - 1.f;
-        fk_f4 acc[4][3];
+        // Layer 1 (VALU) for units ku(kb, g, j) of point n.  The derivative
+        // channels start from K2 w (not 2 w): they are linear through the
+        // network, so the outputs are scaled back by 2 / K2 at the end.
+        auto layer1 = [&](int kb, fk_b8 (&Bh)[3], fk_b8 (&Bl)[3]) {
 #pragma unroll
-        for (int mt = 0; mt < 4; ++mt)
+            for (int j = 0; j < 8; ++j) {
+                const float4 gw = lds_at(N.g1 + ku(kb, 0, j), off_g);   // lane group g's unit is 4 g on
+                const float as = fmaf(gw.x, z0, fmaf(gw.y, z1, fmaf(gw.z, z2, gw.w)));
+                float ch[3];
+                act3(as, gw.y, gw.z, ch[0], ch[1], ch[2]);
 #pragma unroll
-            for (int c = 0; c < 3; ++c) acc[mt][c] = fk_f4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int kt = 0; kt < 4; ++kt) {
-            fk_s4 Bh[3], Bl[3];
+                for (int c = 0; c < 3; ++c) put_bf16<SPLIT>(ch[c], Bh[c], Bl[c], j);
+            }
+        };
+        // Layer-2 tile mt's activations into the layer-3 operands: tile mt is
+        // elements 4 (mt % 2) .. + 3 of K block mt / 2.
+        fk_b8 Ch[2][3], Cl[2][3];
+        auto act2 = [&](int mt, const fk_f4 (&a2)[3]) {
+            const float4 b2 = lds_at(N.q2 + 4 * mt, off_q);   // units 16 mt + 4 g + 0..3
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int u = 16 * kt + 4 * g + i;
-                const float a = fmaf(M.w1[3 * u], z0, fmaf(M.w1[3 * u + 1], z1, fmaf(M.w1[3 * u + 2], z2, M.b1[u])));
                 float ch[3];
-                act3(a, 2.f * M.w1[3 * u + 1], 2.f * M.w1[3 * u + 2], ch[0], ch[1], ch[2]);
+                act3(fmaf(a2[0][i], K2, b2[i]), a2[1][i], a2[2][i], ch[0], ch[1], ch[2]);
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    short hi, lo;
-                    split_bf16(ch[c], hi, lo);
-                    Bh[c][i] = hi;
-                    Bl[c][i] = lo;
+                for (int c = 0; c < 3; ++c) put_bf16<SPLIT>(ch[c], Ch[mt >> 1][c], Cl[mt >> 1][c], 4 * (mt & 1) + i);
+            }
+        };
+        if constexpr (SPLIT) {
+            // K block by K block: one block's hi + lo operands and all four
+            // tiles' accumulators live
+            fk_f4 acc[4][3];
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt)
+#pragma unroll
+                for (int c = 0; c < 3; ++c) acc[mt][c] = fk_f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int kb = 0; kb < 2; ++kb) {
+                fk_b8 Bh[3], Bl[3];
+                layer1(kb, Bh, Bl);
+#pragma unroll
+                for (int mt = 0; mt < 4; ++mt) {
+                    const fk_b8 A = load_a_at(N.w2, mt, kb, off_w);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) {
+                        acc[mt][c] = mfma32(A, Bh[c], acc[mt][c]);
+                        acc[mt][c] = mfma32(A, Bl[c], acc[mt][c]);
+                    }
                 }
             }
+#pragma unroll
+            for (int mt = 0; mt < 4; ++mt) act2(mt, acc[mt]);
+        } else {
+            // both K blocks' operands (half the registers of a hi + lo pair),
+            // then tile by tile: one tile's accumulators live
+            fk_b8 B[2][3], unused[3];
+            layer1(0, B[0], unused);
+            layer1(1, B[1], unused);
 #pragma unroll
             for (int mt = 0; mt < 4; ++mt) {
-                const fk_s4 A = load_a(M.w2, mt, kt, n, g);
+                fk_f4 a2[3];
 #pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    acc[mt][c] = mfma16(A, Bh[c], acc[mt][c]);
-                    acc[mt][c] = mfma16(A, Bl[c], acc[mt][c]);
+                for (int c = 0; c < 3; ++c) a2[c] = fk_f4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+                for (int kb = 0; kb < 2; ++kb) {
+                    const fk_b8 A = load_a_at(N.w2, mt, kb, off_w);
+#pragma unroll
+                    for (int c = 0; c < 3; ++c) a2[c] = mfma32(A, B[kb][c], a2[c]);
                 }
+                act2(mt, a2);
             }
         }
-        // ---- layer 2 activations -> layer 3 operands (the layer-2
-        //      accumulators die as their operands are formed) --------------
-        fk_s4 Ch[4][3], Cl[4][3];
-#pragma unroll
-        for (int kt = 0; kt < 4; ++kt)
-#pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const int u = 16 * kt + 4 * g + i;
-                float ch[3];
-                act3(acc[kt][0][i] + M.b2[u], acc[kt][1][i], acc[kt][2][i], ch[0], ch[1], ch[2]);
-#pragma unroll
-                for (int c = 0; c < 3; ++c) {
-                    short hi, lo;
-                    split_bf16(ch[c], hi, lo);
-                    Ch[kt][c][i] = hi;
-                    Cl[kt][c][i] = lo;
-                }
-            }
         // ---- layer 3, one output tile at a time, into the output layer -------
         float po[2][2] = {{0.f, 0.f}, {0.f, 0.f}};
 #pragma unroll
@@ -371,25 +439,24 @@ __device__ void net_grad_wave(const NetLds &N, float tscale2, float tau, float x
 #pragma unroll
             for (int c = 0; c < 3; ++c) a3[c] = fk_f4{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-            for (int kt = 0; kt < 4; ++kt) {
-                const fk_s4 A = load_a(M.w3, mt, kt, n, g);
+            for (int kb = 0; kb < 2; ++kb) {
+                const fk_b8 A = load_a_at(N.w3, mt, kb, off_w);
 #pragma unroll
                 for (int c = 0; c < 3; ++c) {
-                    a3[c] = mfma16(A, Ch[kt][c], a3[c]);
-                    a3[c] = mfma16(A, Cl[kt][c], a3[c]);
+                    a3[c] = mfma32(A, Ch[kb][c], a3[c]);
+                    if constexpr (SPLIT) a3[c] = mfma32(A, Cl[kb][c], a3[c]);
                 }
             }
+            const float4 b3 = lds_at(N.q3 + 4 * mt, off_q), v0 = lds_at(N.q40 + 4 * mt, off_q),
+                         v1 = lds_at(N.q41 + 4 * mt, off_q);
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                const int u = 16 * mt + 4 * g + i;
                 float h, hx, hy;
-                act3(a3[0][i] + M.b3[u], a3[1][i], a3[2][i], h, hx, hy);
-#pragma unroll
-                for (int o = 0; o < 2; ++o) {
-                    const float w = M.w4[64 * o + u];
-                    po[o][0] = fmaf(w, hx, po[o][0]);
-                    po[o][1] = fmaf(w, hy, po[o][1]);
-                }
+                act3(fmaf(a3[0][i], K2, b3[i]), a3[1][i], a3[2][i], h, hx, hy);
+                po[0][0] = fmaf(v0[i], hx, po[0][0]);
+                po[0][1] = fmaf(v0[i], hy, po[0][1]);
+                po[1][0] = fmaf(v1[i], hx, po[1][0]);
+                po[1][1] = fmaf(v1[i], hy, po[1][1]);
             }
         }
 #pragma unroll
@@ -399,7 +466,7 @@ __device__ void net_grad_wave(const NetLds &N, float tscale2, float tau, float x
                 float v = po[o][c];
                 v += __shfl_xor(v, 16, 64);
                 v += __shfl_xor(v, 32, 64);
-                if (g == r) out[o][c] = v;
+                if (g == r) out[o][c] = v * (2.f / K2);
             }
     }
 }
@@ -421,6 +488,25 @@ __global__ void __launch_bounds__(256) cv_eval_kernel(const uint16_t *bf, float 
     if (ok)
         for (int c = 0; c < 2; ++c)
             for (int k = 0; k < 5; ++k) out[10 * i + 5 * c + k] = o[c][k];
+}
+
+// The network's (x, y) gradient at given points, as the martingale path
+// kernels take it (the parity hook of their evaluation).
+template <bool SPLIT>
+__global__ void __launch_bounds__(256) cv_eval_grad_kernel(const uint16_t *bf, float tscale2, float base,
+                                                           const float *txy, int64_t n, float *out) {
+    __shared__ NetLds N;
+    load_net(N, bf);
+    __syncthreads();
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool ok = i < n;
+    const float t = ok ? txy[3 * i] : 0.f, x = ok ? txy[3 * i + 1] : 0.5f, y = ok ? txy[3 * i + 2] : 0.5f;
+    float o[2][2];
+    net_grad_wave<SPLIT>(N, tscale2, t, x, y, o);
+    add_base_grad(base, o);
+    if (ok)
+        for (int c = 0; c < 2; ++c)
+            for (int k = 0; k < 2; ++k) out[4 * i + 2 * c + k] = o[c][k];
 }
 
 // ---------------------------------------------------------------------------
@@ -685,15 +771,20 @@ struct MgArgs {
     const float4 *gtab;          // grid base: per-cell gradient table, or NULL (read the grids)
     NodeAcc *acc_cv;             // [n_out] sums of the CV scores
     float2 *cv_scores;           // [n_out * n_paths], absolute, or nullptr
+    int32_t split;               // host side: the network's gradient with BF16 hi + lo operands (1) or
+                                 // BF16-rounded activations (0); selects the instantiation
 };
 
-// Four waves per SIMD (128 VGPRs): the few values the compiler moves to
-// scratch are touched at block boundaries, and the path loop between them
-// gains the latency hiding of the extra waves (about 14% faster per path
-// than two waves on the moving bump; the Dynkin kernel, whose evaluation
-// points are ten times as frequent, stays at two).
-template <int KIND, int TMODE, bool UNIFORM, bool BRIDGE>
-__global__ void __launch_bounds__(256, 4) fk_mg_path_kernel(const PathArgs a, const MgArgs c) {
+// Four waves per SIMD (128 VGPRs) with the BF16 gradient, three (168) with
+// the hi + lo split: the few values the compiler moves to scratch are
+// touched at block boundaries, and the path loop between them gains the
+// latency hiding of the extra waves (four waves were about 14% faster per
+// path than two on the moving bump; at four the split form spills ~57
+// registers around each evaluation and runs 5% slower at stride 20 than at
+// three).  The Dynkin kernel, whose evaluation points are ten times as
+// frequent, stays at two.
+template <int KIND, int TMODE, bool UNIFORM, bool BRIDGE, bool SPLIT>
+__global__ void __launch_bounds__(256, SPLIT ? 3 : 4) fk_mg_path_kernel(const PathArgs a, const MgArgs c) {
     constexpr bool kMovingBackward = moving_kind(KIND) && TMODE == TIME_BACKWARD;
     __shared__ NetLds N;
     load_net(N, c.bf);
@@ -729,7 +820,7 @@ __global__ void __launch_bounds__(256, 4) fk_mg_path_kernel(const PathArgs a, co
             if (__ballot(active) != 0ull) {
                 const float tau = active ? tend - (float)L.k * L.dt : 0.f;
                 float o[2][2];
-                net_grad_wave(N, c.tscale2, tau, active ? L.xh : 0.5f, active ? L.yh : 0.5f, o);
+                net_grad_wave<SPLIT>(N, c.tscale2, tau, active ? L.xh : 0.5f, active ? L.yh : 0.5f, o);
                 add_base_grad(c.base, o);
                 if (c.grid_base) {
                     // grid base: the network's part, held until the next
@@ -1097,8 +1188,8 @@ struct TrainArgs {
 };
 
 // C[M = 64][N = 64] = A[64 x K] B[K x 64] with K = 64, A and B given by
-// element accessors, on MFMA; each wavefront computes four 16 x 16 tiles
-// and hands each result fragment to `sink(row, col, value)`.
+// element accessors, on MFMA (two 32-deep K blocks); each wavefront computes
+// four 16 x 16 tiles and hands each result fragment to `sink(row, col, value)`.
 template <typename FA, typename FB, typename FS>
 __device__ __forceinline__ void wave_gemm64(FA A, FB B, FS sink) {
     const int lane = threadIdx.x & 63, g = lane >> 4, n = lane & 15, w = threadIdx.x >> 6;
@@ -1107,14 +1198,15 @@ __device__ __forceinline__ void wave_gemm64(FA A, FB B, FS sink) {
         const int tile = 4 * w + t, mt = tile >> 2, nt = tile & 3;
         fk_f4 acc = {0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int kt = 0; kt < 4; ++kt) {
-            fk_s4 a, b;
+        for (int kb = 0; kb < 2; ++kb) {
+            fk_b8 a, b;
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                a[i] = (short)f2bf(A(16 * mt + n, 16 * kt + 4 * g + i));
-                b[i] = (short)f2bf(B(16 * kt + 4 * g + i, 16 * nt + n));
+            for (int j = 0; j < 8; ++j) {
+                const int k = ku(kb, g, j);
+                a[j] = (__bf16)A(16 * mt + n, k);
+                b[j] = (__bf16)B(k, 16 * nt + n);
             }
-            acc = mfma16(a, b, acc);
+            acc = mfma32(a, b, acc);
         }
 #pragma unroll
         for (int i = 0; i < 4; ++i) sink(16 * mt + 4 * g + i, 16 * nt + n, acc[i]);
@@ -1168,10 +1260,10 @@ __global__ void __launch_bounds__(256) cv_grad_kernel(TrainArgs ta) {
         S.H1[u * kTS + s] = tanhf(a);
     }
     __syncthreads();
-    wave_gemm64([&](int m, int k) { return bf2f(S.net.w2[m * kWS + k]); }, [&](int k, int n) { return S.H1[k * kTS + n]; },
+    wave_gemm64([&](int m, int k) { return bf2f(S.net.w2[m * kWS + wcol(k)]); }, [&](int k, int n) { return S.H1[k * kTS + n]; },
                 [&](int m, int n, float v) { S.H2[m * kTS + n] = tanhf(v + S.net.b2[m]); });
     __syncthreads();
-    wave_gemm64([&](int m, int k) { return bf2f(S.net.w3[m * kWS + k]); }, [&](int k, int n) { return S.H2[k * kTS + n]; },
+    wave_gemm64([&](int m, int k) { return bf2f(S.net.w3[m * kWS + wcol(k)]); }, [&](int k, int n) { return S.H2[k * kTS + n]; },
                 [&](int m, int n, float v) { S.H3[m * kTS + n] = tanhf(v + S.net.b3[m]); });
     __syncthreads();
     // outputs, residuals and d loss / d out (mean over batch and both outputs)
@@ -1227,7 +1319,7 @@ __global__ void __launch_bounds__(256) cv_grad_kernel(TrainArgs ta) {
         P[OB3 + tid] = acc;
     }
     // dA2 = (W3^T dA3) (1 - H2^2)
-    wave_gemm64([&](int m, int k) { return bf2f(S.net.w3[k * kWS + m]); }, [&](int k, int n) { return S.D[k * kTS + n]; },
+    wave_gemm64([&](int m, int k) { return bf2f(S.net.w3[k * kWS + wcol(m)]); }, [&](int k, int n) { return S.D[k * kTS + n]; },
                 [&](int m, int n, float v) {
                     const float h = S.H2[m * kTS + n];
                     S.E[m * kTS + n] = v * (1.f - h * h);
@@ -1242,7 +1334,7 @@ __global__ void __launch_bounds__(256) cv_grad_kernel(TrainArgs ta) {
         P[OB2 + tid] = acc;
     }
     // dA1 = (W2^T dA2) (1 - H1^2)
-    wave_gemm64([&](int m, int k) { return bf2f(S.net.w2[k * kWS + m]); }, [&](int k, int n) { return S.E[k * kTS + n]; },
+    wave_gemm64([&](int m, int k) { return bf2f(S.net.w2[k * kWS + wcol(m)]); }, [&](int k, int n) { return S.E[k * kTS + n]; },
                 [&](int m, int n, float v) {
                     const float h = S.H1[m * kTS + n];
                     S.D[m * kTS + n] = v * (1.f - h * h);
@@ -1439,22 +1531,30 @@ struct CvOccF {
 // The martingale kernels with and without the bridge test (a.score_mode).
 template <int K, int T, bool U>
 struct MgLaunchF {
-    static hipError_t run(const PathArgs &a, const MgArgs &c, int grid, hipStream_t s) {
-        if (a.score_mode == FK_SCORE_BRIDGE)
-            hipLaunchKernelGGL((fk_mg_path_kernel<K, T, U, true>), dim3(grid), dim3(256), 0, s, a, c);
-        else
-            hipLaunchKernelGGL((fk_mg_path_kernel<K, T, U, false>), dim3(grid), dim3(256), 0, s, a, c);
+    template <bool B, bool S>
+    static hipError_t go(const PathArgs &a, const MgArgs &c, int grid, hipStream_t s) {
+        hipLaunchKernelGGL((fk_mg_path_kernel<K, T, U, B, S>), dim3(grid), dim3(256), 0, s, a, c);
         return hipGetLastError();
+    }
+    static hipError_t run(const PathArgs &a, const MgArgs &c, int grid, hipStream_t s) {
+        const bool b = a.score_mode == FK_SCORE_BRIDGE;
+        if (c.split) return b ? go<true, true>(a, c, grid, s) : go<false, true>(a, c, grid, s);
+        return b ? go<true, false>(a, c, grid, s) : go<false, false>(a, c, grid, s);
     }
 };
 template <int K, int T, bool U>
 struct MgOccF {
-    static int run(bool bridge) {
+    template <bool B, bool S>
+    static int occ() {
         int nb = 0;
-        const hipError_t e =
-            bridge ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk_mg_path_kernel<K, T, U, true>, 256, 0)
-                   : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk_mg_path_kernel<K, T, U, false>, 256, 0);
-        return e == hipSuccess ? nb : 0;
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fk_mg_path_kernel<K, T, U, B, S>, 256, 0) ==
+                       hipSuccess
+                   ? nb
+                   : 0;
+    }
+    static int run(bool bridge, bool split) {
+        if (split) return bridge ? occ<true, true>() : occ<false, true>();
+        return bridge ? occ<true, false>() : occ<false, false>();
     }
 };
 template <int K, int T, bool U>
@@ -1678,6 +1778,31 @@ int fk_cv_eval(fk_cv_t cv, const float *txy, int64_t n, float *out, hipStream_t 
                        cv->base, txy, n, out);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? FK_OK : hip_fail(e, "eval kernel launch");
+}
+
+int fk_cv_set_grad_precision(fk_cv_t cv, int32_t mode) {
+    g_last_error.clear();
+    if (!cv) return fail(FK_E_INVAL, "network is NULL");
+    if (mode != FK_CV_GRAD_SPLIT && mode != FK_CV_GRAD_BF16) return fail(FK_E_INVAL, "unknown gradient precision %d", mode);
+    cv->grad_bf16 = mode == FK_CV_GRAD_BF16 ? 1 : 0;
+    return FK_OK;
+}
+
+int fk_cv_eval_grad(fk_cv_t cv, const float *txy, int64_t n, float *out, hipStream_t stream) {
+    g_last_error.clear();
+    if (!cv) return fail(FK_E_INVAL, "network is NULL");
+    if (n < 0) return fail(FK_E_INVAL, "n < 0");
+    if (n == 0) return FK_OK;
+    if (!txy || !out) return fail(FK_E_INVAL, "NULL array");
+    const int64_t blocks = (n + 255) / 256;
+    if (cv->grad_bf16)
+        hipLaunchKernelGGL(cv_eval_grad_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, stream, cv->s.bf,
+                           2.f / cv->t_scale, cv->base, txy, n, out);
+    else
+        hipLaunchKernelGGL(cv_eval_grad_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, stream, cv->s.bf,
+                           2.f / cv->t_scale, cv->base, txy, n, out);
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? FK_OK : hip_fail(e, "gradient eval kernel launch");
 }
 
 int fk_cv_grad(fk_cv_t cv, const float *txy, const float *target, int64_t n, float *grad, float *loss,
@@ -1937,7 +2062,9 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         if (e != hipSuccess) return hip_fail(e, "gradient table kernel launch");
         c.cv_scores = cv_rec;
         c.acc_cv = acc_cv;
-        const int occ = cv_dispatch<MgOccF>(w->kind, w->time_mode, uniform, d->score_mode == FK_SCORE_BRIDGE);
+        c.split = cv->grad_bf16 ? 0 : 1;
+        const int occ = cv_dispatch<MgOccF>(w->kind, w->time_mode, uniform, d->score_mode == FK_SCORE_BRIDGE,
+                                            c.split != 0);
         if (bpc == 0 || (occ > 0 && bpc > occ)) bpc = occ > 0 ? occ : 1;
         if ((e = cv_dispatch<MgLaunchF>(w->kind, w->time_mode, uniform, a, c, cap_grid(n_cu * bpc, a.total_chunks, 256), stream)) != hipSuccess)
             return hip_fail(e, "control-variate path kernel launch");

@@ -217,3 +217,12 @@ def test_exponential_steps_only_in_single_solves(fk):
         fk.FkBatch([(W.CONST, 0.01, 0.0, np.array([[0.5, 0.5]]), 1)], data, 1e-3, 64, device="cpu")
     assert e.value.code == -5
     assert _call(fk, data=W.Data(score_mode=5)) == -1
+
+
+def test_network_handle_calls_reject_a_null_handle(fk):
+    lib = fk.library()
+    assert lib.fk_cv_set_grad_precision(None, 0) == -1
+    assert lib.fk_cv_set_base(None, 0) == -1
+    assert lib.fk_cv_eval_grad(None, None, 4, None, None) == -1
+    assert lib.fk_cv_eval(None, None, 4, None, None) == -1
+    assert fk.fk_last_error() != ""

@@ -47,6 +47,34 @@ def test_eval_matches_oracle(fk):
     cv.close()
 
 
+@pytest.mark.parametrize("mode,bar", [("split", 2e-4), ("bf16", 2e-2)])
+def test_eval_grad_matches_oracle(fk, mode, bar):
+    """The martingale kernels' (x, y) gradient against the FP64 forward mode
+    of the same BF16 weights (channel-wise max-norm relative error): hi + lo
+    operands near FP32, BF16-rounded activations within the network bar."""
+    import torch
+    cv = fk.FkCv(curved_params(3), T, grad_precision=mode)
+    _, bf = cv.params()
+    rng = np.random.default_rng(5)
+    n = 1000                                   # ragged: 15 full wavefronts and a partial one
+    txy = np.stack([rng.uniform(0, T, n), rng.uniform(0, 1, n), rng.uniform(0, 1, n)], 1).astype(np.float32)
+    print(f"[gpu] cv eval_grad {mode} n={n}", flush=True)
+    g = cv.eval_grad(cuda32(txy))
+    torch.cuda.synchronize()
+    g = g.cpu().numpy().astype(np.float64)
+    t64 = txy.astype(np.float64)
+    fm = M.forward_mode(bf, t64[:, 0], t64[:, 1], t64[:, 2], T)
+    errs = []
+    for k, key in enumerate(("dx", "dy")):
+        scale = np.abs(fm[key]).max()
+        errs.append(np.abs(g[:, :, k] - fm[key]).max() / scale)
+        print(f"{mode} channel {key}: max rel err {errs[-1]:.2e} (scale {scale:.3g})", flush=True)
+    assert max(errs) < bar
+    if mode == "bf16":
+        assert max(errs) > 1e-4             # the rounding is really taken once
+    cv.close()
+
+
 def test_grad_matches_oracle(fk):
     import torch
     cv = fk.FkCv(curved_params(2), T)
@@ -250,6 +278,49 @@ def test_cv_martingale_against_oracle(fk, oracle_mod, stride):
     assert rel.max() < 0.05
     assert np.all(d <= 3 * o["se"]) and np.all(d <= 1e-5)
     assert np.all(np.abs(np.stack([g["se_xi"], g["se_eta"]], 1) - o["se"]) <= 0.05 * o["se"])
+    cv.close()
+
+
+@pytest.mark.parametrize("stride", [2, 20])
+def test_cv_martingale_bf16_gradient_against_oracle(fk, oracle_mod, stride):
+    """Martingale form with the gradient from BF16-rounded activations: the
+    estimator stays unbiased for any gradient fixed before the block's
+    increments, so per-node means agree with the oracle's FP64-gradient
+    estimate on the same paths within 3 SE; the plain part is unchanged and
+    each path's martingale sum moves by at most the gradient's error."""
+    import torch
+    cv = fk.FkCv(W.mlp_init(7), T, grad_precision="bf16")
+    _, bf = cv.params()
+    dens = W.moving_bump()
+    pts = W.interface_nodes(4, 4, 16)[::3]
+    t, dt, N = 0.01, 1e-4, 512
+    print(f"[gpu] cv martingale bf16 stride={stride} nodes={len(pts)} N={N}", flush=True)
+    g = fk.fk_interface_solve_cv(dens, W.Data(), pts, t, dt, N, cv, stride=stride, seed=3, form=fk.FK_CV_MARTINGALE,
+                                 exit_step=True, cv_scores=True)
+    torch.cuda.synchronize()
+    g = {k: v.cpu().numpy() for k, v in g.items() if not k.startswith("_")}
+    o = oracle_mod.fk_solve_cv(dens, W.Data(), pts, t, dt, N, seed=3, uhat=oracle_mod.UHAT_MLP, flat=bf, t_scale=T,
+                               stride=stride, form=oracle_mod.CV_MARTINGALE, want_scores=True, want_exit=True,
+                               threads=THREADS)
+    plain = {"xi": g["plain_xi"], "eta": g["plain_eta"], "se_xi": g["plain_se_xi"], "se_eta": g["plain_se_eta"],
+             "exit_step": g["exit_step"]}
+    assert_parity(plain, {"mean": o["plain_mean"], "se": o["plain_se"], "exit_step": o["exit_step"]}, pts,
+                  label="plain part:")
+    same = g["exit_step"] == o["exit_step"]
+    po = oracle_mod.fk_solve(dens, W.Data(), pts, t, dt, N, seed=3, want_scores=True, threads=THREADS)["scores"]
+    msum = np.abs(po - o["cv_scores"])[same]
+    ds = np.abs(g["cv_scores"].astype(np.float64) - o["cv_scores"])[same]
+    mean_g = np.stack([g["xi"], g["eta"]], 1)
+    se_g = np.stack([g["se_xi"], g["se_eta"]], 1)
+    d = np.abs(mean_g - o["mean"])
+    print(f"martingale bf16: max |score diff| {ds.max():.2e} (largest |martingale sum| {msum.max():.3g}), "
+          f"max |mean diff| {d.max():.2e} = {np.max(d / o['se']):.2f} se, se ratio gpu/oracle "
+          f"{np.median(se_g / o['se']):.3f}", flush=True)
+    # a 2e-2 relative gradient error moves a path's sum by at most that
+    # fraction of the sums' scale (sums that cancel to ~0 have no scale of their own)
+    assert ds.max() <= 2e-2 * msum.max()
+    assert np.all(d <= 3 * o["se"])
+    assert np.all(np.abs(se_g - o["se"]) <= 0.1 * o["se"])
     cv.close()
 
 
