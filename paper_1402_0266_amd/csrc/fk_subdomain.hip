@@ -472,8 +472,8 @@ template <int T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 subdomain_lu_tile_kernel(const SubArgs a) {
     constexpr int W = 16 * T;
-    __shared__ double colb[2][W];         // pivot column by physical row
-    __shared__ double rowb[2][W + 2];     // pivot row by physical column, then its two right-hand sides
+    __shared__ double colb[2][2][W];      // [buffer][pivot 0 / 1] pivot column by physical row
+    __shared__ double rowb[2][2][W + 2];  // ... pivot row by physical column, then its two right-hand sides
     const int qf = a.qf, P1 = qf + 1, n = qf * a.qs;
     const int sd = a.twisted ? blockIdx.x >> 1 : blockIdx.x;
     const bool rev = a.twisted && (blockIdx.x & 1);
@@ -518,7 +518,7 @@ subdomain_lu_tile_kernel(const SubArgs a) {
         scol = Rc - qf < n ? cf[Rc - qf].z : 0.0;
     };
 
-    int base = 0, k = 0;
+    int base = 0, k = 0, it = 0;
     double rnext = 1.0 / A[0][0];  // reciprocal of the next pivot (meaningful in its lane)
     int po[T];                     // physical offset of slot t: 16 ((t + base) mod T)
     auto set_offsets = [&]() {
@@ -526,41 +526,147 @@ subdomain_lu_tile_kernel(const SubArgs a) {
         for (int t = 0; t < T; ++t) po[t] = 16 * ((t + base) % T);
     };
     set_offsets();
+    // U row k (global) from this lane's entries v of the row whose pivot sits
+    // at physical index kp
+    auto put_u = [&](int kk, int kp, const double (&v)[T]) {
+#pragma unroll
+        for (int u = 0; u < T; ++u) {
+            int d = cg + po[u] - kp;                 // band offset of the column in U row kk
+            d += d < 0 ? W : 0;
+            if (d <= qf) U[(int64_t)kk * P1 + d] = v[u];
+        }
+    };
     while (k < steps) {
         const int k0 = k;
         load_enter(k0);
-        for (int g = 0; g < 16 && k < steps; ++g, ++k) {
+        for (int g = 0; g < 16 && k < steps;) {
             const int kp = 16 * base + g;     // physical index of the pivot
-            const int buf = k & 1;
+            const int buf = it++ & 1;
+            if (g < 15 && k + 1 < steps) {
+                // ---- steps k and k + 1 behind one barrier -------------------
+                // The lanes of columns g and g + 1 publish them (the pivot's
+                // reciprocal, formed at the end of the previous step, at the
+                // pivot), the lanes of rows g and g + 1 theirs and their
+                // right-hand sides, all as they stand before step k.
+                if (cg == g) {
+#pragma unroll
+                    for (int t = 0; t < T; ++t) colb[buf][0][rg + po[t]] = (t == 0 && rg == g) ? rnext : A[t][0];
+                } else if (cg == g + 1) {
+#pragma unroll
+                    for (int t = 0; t < T; ++t) colb[buf][1][rg + po[t]] = A[t][0];
+                }
+                if (rg == g || rg == g + 1) {
+                    const int h = rg - g;
+                    double v[T];
+#pragma unroll
+                    for (int u = 0; u < T; ++u) {
+                        v[u] = A[0][u];
+                        rowb[buf][h][cg + po[u]] = v[u];
+                    }
+                    if (rhs) rowb[buf][h][W + cg] = B[0];
+                    if (h == 0) {
+                        put_u(k, kp, v);
+                        if (rhs) Y[(int64_t)cg * n + k] = B[0];
+                    }
+                }
+                __syncthreads();
+                double l0[T], c1[T], r0[T], r1[T];
+                const double inv0 = colb[buf][0][kp];
+                const double a1k = colb[buf][0][kp + 1], ak1 = rowb[buf][0][kp + 1], a11 = rowb[buf][1][kp + 1];
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+                    l0[t] = colb[buf][0][rg + po[t]];
+                    c1[t] = colb[buf][1][rg + po[t]];
+                }
+#pragma unroll
+                for (int u = 0; u < T; ++u) {
+                    r0[u] = rowb[buf][0][cg + po[u]];
+                    r1[u] = rowb[buf][1][cg + po[u]];
+                }
+                const double b0 = rowb[buf][0][W + cg], b1 = rowb[buf][1][W + cg];
+                // step k's multipliers; row k + 1, its right-hand side and its
+                // pivot as step k leaves them (the operations step k would
+                // apply to them, in the same order)
+                const double l01 = a1k * inv0;
+                const double inv1 = 1.0 / fma(-l01, ak1, a11);
+#pragma unroll
+                for (int t = 0; t < T; ++t) l0[t] *= inv0;
+#pragma unroll
+                for (int u = 0; u < T; ++u) r1[u] = fma(-l01, r0[u], r1[u]);
+                const double b1p = fma(-l01, b0, b1);
+                if (rg == g + 1) {
+                    put_u(k + 1, kp + 1, r1);
+                    if (rhs) Y[(int64_t)cg * n + k + 1] = b1p;
+                }
+                // step k on every entry (the reciprocal's latency hides behind it)
+#pragma unroll
+                for (int t = 0; t < T; ++t)
+#pragma unroll
+                    for (int u = 0; u < T; ++u) A[t][u] = fma(-l0[t], r0[u], A[t][u]);
+                if (rhs) {
+#pragma unroll
+                    for (int t = 0; t < T; ++t) B[t] = fma(-l0[t], b0, B[t]);
+                }
+                // step k + 1: column k + 1 as step k leaves it, its multipliers
+                double l1[T];
+#pragma unroll
+                for (int t = 0; t < T; ++t) l1[t] = fma(-l0[t], ak1, c1[t]) * inv1;
+                // the entry that is the next pivot first, and its reciprocal
+                double np;
+                if (T > 1 && g == 14) {
+                    A[1][1] = fma(-l1[1], r1[1], A[1][1]);
+                    np = A[1][1];
+                } else {
+                    A[0][0] = fma(-l1[0], r1[0], A[0][0]);
+                    np = A[0][0];
+                }
+                rnext = 1.0 / np;
+#pragma unroll
+                for (int t = 0; t < T; ++t) {
+#pragma unroll
+                    for (int u = 0; u < T; ++u) {
+                        if (t == 0 && u == 0 && !(T > 1 && g == 14)) continue;
+                        if (T > 1 && t == 1 && u == 1 && g == 14) continue;
+                        A[t][u] = fma(-l1[t], r1[u], A[t][u]);
+                    }
+                }
+                if (rhs) {
+#pragma unroll
+                    for (int t = 0; t < T; ++t) B[t] = fma(-l1[t], b1p, B[t]);
+                }
+                g += 2;
+                k += 2;
+                continue;
+            }
+            // ---- one step (the last one of an odd count) --------------------
             if (cg == g) {
                 // the pivot column; at the pivot its reciprocal, formed at the
                 // end of the previous step
 #pragma unroll
-                for (int t = 0; t < T; ++t) colb[buf][rg + po[t]] = (t == 0 && rg == g) ? rnext : A[t][0];
+                for (int t = 0; t < T; ++t) colb[buf][0][rg + po[t]] = (t == 0 && rg == g) ? rnext : A[t][0];
             }
             if (rg == g) {
+                double v[T];
 #pragma unroll
                 for (int u = 0; u < T; ++u) {
-                    const int pc = cg + po[u];
-                    rowb[buf][pc] = A[0][u];
-                    int d = pc - kp;                 // band offset of the column in U row k
-                    d += d < 0 ? W : 0;
-                    if (d <= qf) U[(int64_t)k * P1 + d] = A[0][u];
+                    v[u] = A[0][u];
+                    rowb[buf][0][cg + po[u]] = v[u];
                 }
+                put_u(k, kp, v);
                 if (rhs) {
-                    rowb[buf][W + cg] = B[0];
+                    rowb[buf][0][W + cg] = B[0];
                     Y[(int64_t)cg * n + k] = B[0];
                 }
             }
             __syncthreads();
             // every LDS read of the step at once, then the update
             double l[T], r[T];
-            const double inv = colb[buf][kp];
+            const double inv = colb[buf][0][kp];
 #pragma unroll
-            for (int t = 0; t < T; ++t) l[t] = colb[buf][rg + po[t]];
+            for (int t = 0; t < T; ++t) l[t] = colb[buf][0][rg + po[t]];
 #pragma unroll
-            for (int u = 0; u < T; ++u) r[u] = rowb[buf][cg + po[u]];
-            const double bp = rowb[buf][W + cg];
+            for (int u = 0; u < T; ++u) r[u] = rowb[buf][0][cg + po[u]];
+            const double bp = rowb[buf][0][W + cg];
 #pragma unroll
             for (int t = 0; t < T; ++t) l[t] *= inv;
             // the entry that is the next pivot first (slot 0's diagonal, or
@@ -588,6 +694,8 @@ subdomain_lu_tile_kernel(const SubArgs a) {
 #pragma unroll
                 for (int t = 0; t < T; ++t) B[t] = fma(-l[t], bp, B[t]);
             }
+            g += 1;
+            k += 1;
         }
         if (k - k0 < 16 || k >= steps) break;
         // the block is done: its rows and columns k0 + W + (0 .. 15) enter
