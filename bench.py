@@ -85,12 +85,14 @@ BF16_PEAK_TFLOPS = 2500.0
 CV_PROFILE_PATHS = 2952
 
 # HBM traffic of the path kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
-# (scaled by a plain 1 GiB copy: fetch x2.0, write x1.0), per path, valid only
+# (scaled by a plain 1 GiB copy: fetch x2.0, write x1.0) on the moving-bump
+# solve at N* = 73858 (1521 x 578 chunks of 128 paths), per path, valid only
 # for the kernel sources it was measured on (hash below); otherwise null.
-TRAFFIC_BYTES_PER_PATH = (2.0 * 237.6875 + 1.0 * 1056887.71875) * 1024 / (1521 * 73858)
-TRAFFIC_SOURCE_HASH = "58f7fd54ff597d97"
+TRAFFIC_BYTES_PER_PATH = (2.0 * 244.5625 + 1.0 * 494984.0) * 1024 / (1521 * 73858)
+TRAFFIC_SOURCE_HASH = "3f3de98ef7bc6deb"
 KERNEL_SOURCES = ["paper_1402_0266_amd/csrc/fk_paths.hip", "paper_1402_0266_amd/csrc/fk_device.hpp",
-                  "paper_1402_0266_amd/csrc/fk_internal.hpp", "paper_1402_0266_amd/csrc/fk_pathstep.hpp"]
+                  "paper_1402_0266_amd/csrc/fk_internal.hpp", "paper_1402_0266_amd/csrc/fk_pathstep.hpp",
+                  "paper_1402_0266_amd/csrc/fk_accum.hpp"]
 
 
 def kernel_source_hash() -> str:
