@@ -210,7 +210,11 @@ def test_trained_network_gain(fk):
     """What the trained network buys on the moving-bump workload: labels from
     plain Monte Carlo, training on the GPU, then the control-variate solve at
     t = 0.1 on every 8th node, judged against the finite-difference
-    reference and against plain Monte Carlo on the same paths."""
+    reference, against plain Monte Carlo on the same paths, and against the
+    linear control (the identity map's gradient, no network) on the same
+    paths.  Away from the bump the solution's gradient is close to the
+    identity, so the linear control is already strong here: the network's
+    variance is reported beside it and held within a factor 2 of it."""
     import torch
     from paper_1402_0266_amd import cv_pipeline as P
     wl = W.MOVING_BUMP_1521
@@ -241,6 +245,24 @@ def test_trained_network_gain(fk):
     z = (cvm - ref) / np.sqrt(cvs ** 2 + fd[:, 4:6] ** 2)
     assert abs(float(z.mean())) < 0.5 and float(np.sqrt(np.mean(z ** 2))) < 1.5
     cv.close()
+    # the linear control on the same paths: the identity data posed as a
+    # 256-cell identity grid scored past the edge (the same scores), whose
+    # bilinear gradient is exactly I
+    import dataclasses
+    G = 256
+    x = torch.arange(G + 1, dtype=torch.float64, device="cuda") / G
+    grids = (x.repeat(G + 1, 1).contiguous().view(-1), x[:, None].repeat(1, G + 1).contiguous().view(-1))
+    gdata = dataclasses.replace(wl.data, init_kind=W.DATA_GRID, score_mode=W.SCORE_EXTEND)
+    lin = fk.fk_interface_solve_cv(wl.density, gdata, nodes[sub], wl.t, wl.dt, 2048, None, stride=1 << 20, seed=3,
+                                   form=fk.FK_CV_MARTINGALE_GRID, grids=grids)
+    torch.cuda.synchronize()
+    lps = np.stack([lin["plain_se_xi"].cpu().numpy(), lin["plain_se_eta"].cpu().numpy()], 1)
+    assert np.array_equal(lps, pls)           # the same paths
+    lcs = np.stack([lin["se_xi"].cpu().numpy(), lin["se_eta"].cpu().numpy()], 1)
+    ratio_lin = float(np.mean(lcs ** 2) / np.mean(pls ** 2))
+    print(f"variance ratio to plain: network {ratio:.4f}, linear control {ratio_lin:.4f}; network / linear "
+          f"{ratio / ratio_lin:.3f}", flush=True)
+    assert ratio < 2.0 * ratio_lin
 
 
 @pytest.mark.parametrize("stride", [2, 20])
