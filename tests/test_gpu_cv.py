@@ -214,7 +214,8 @@ def test_trained_network_gain(fk):
     linear control (the identity map's gradient, no network) on the same
     paths.  Away from the bump the solution's gradient is close to the
     identity, so the linear control is already strong here: the network's
-    variance is reported beside it and held within a factor 2 of it."""
+    variance is reported beside it and held within a factor 2 of it
+    (measured: 0.0417 of plain against the linear control's 0.0386)."""
     import torch
     from paper_1402_0266_amd import cv_pipeline as P
     wl = W.MOVING_BUMP_1521
@@ -257,7 +258,9 @@ def test_trained_network_gain(fk):
                                    form=fk.FK_CV_MARTINGALE_GRID, grids=grids)
     torch.cuda.synchronize()
     lps = np.stack([lin["plain_se_xi"].cpu().numpy(), lin["plain_se_eta"].cpu().numpy()], 1)
-    assert np.array_equal(lps, pls)           # the same paths
+    # the same paths (the grid's bilinear identity equals x to rounding)
+    print(f"plain se, identity data vs identity grid: max rel diff {np.max(np.abs(lps / pls - 1)):.2e}", flush=True)
+    assert np.allclose(lps, pls, rtol=1e-5, atol=0)
     lcs = np.stack([lin["se_xi"].cpu().numpy(), lin["se_eta"].cpu().numpy()], 1)
     ratio_lin = float(np.mean(lcs ** 2) / np.mean(pls ** 2))
     print(f"variance ratio to plain: network {ratio:.4f}, linear control {ratio_lin:.4f}; network / linear "
