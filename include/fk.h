@@ -135,9 +135,12 @@ typedef struct fk_data {
 
 /* Launch plan of the path kernel (see fk_plan_autotune).  Zero fields take defaults:
  * block 256; blocks_per_cu the kernel's occupancy (the grid is cut to no more
- * wavefronts than there are chunks); chunk 128, or 256 for horizons of at most 64
- * steps in fk_interface_solve and in the network forms of fk_interface_solve_cv;
- * chunk at most 2048 (FK_E_INVAL beyond); node_tile 1.  The plan changes speed
+ * wavefronts than there are chunks); chunk 128, or for horizons of at most 64
+ * steps: in fk_interface_solve (and the plain pass of fk_interface_solve_cv)
+ * the largest of 256, 512, 1024, 2048 that leaves at least 8 chunks per
+ * resident wavefront (28 per CU), 256 with a node mask, and 256 in the network
+ * forms of fk_interface_solve_cv; chunk at most 2048 (FK_E_INVAL beyond);
+ * node_tile 1.  The plan changes speed
  * only: results depend on the counters alone. */
 typedef struct fk_plan {
     int32_t block;          /* threads per workgroup: 64, 128, 192 or 256 */

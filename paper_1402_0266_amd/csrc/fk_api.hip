@@ -271,6 +271,14 @@ hipError_t timing_record(int i, hipStream_t s) {
     return e;
 }
 
+int short_chunk(int64_t n_nodes, int64_t n_paths, int n_cu, bool masked) {
+    if (masked) return 256;   // the active count is known on the device only
+    const int64_t want = 8LL * 28 * n_cu;
+    for (int c = 2048; c > 256; c >>= 1)
+        if (n_nodes * ((n_paths + c - 1) / c) >= want) return c;
+    return 256;
+}
+
 int check_chunks(int64_t n_nodes, int64_t n_paths, const fk_plan &pl) {
     const int64_t cpn = (n_paths + pl.chunk - 1) / pl.chunk;
     // chunk indices run past the last chunk by up to two grid-fulls of
@@ -482,11 +490,15 @@ int fk_interface_solve(const fk_density *w, const fk_data *d, const double *pts,
     S.uniform = (level.dt_last == level.dt && level.cbm_last == level.cbm);
     S.plan = pl;
     // Short paths (a mesh step of a few tens of sub-steps): each wavefront's
-    // first chunk by its grid index, and by default 256 paths per grab,
-    // which halves the wavefronts' fixed costs per path; long ones 128, for
-    // the balance of the tail.
+    // first chunk by its grid index, and by default short_chunk paths per
+    // grab, which cuts the wavefronts' fixed costs per path; long ones 128,
+    // for the balance of the tail.
     S.first_by_index = level.K <= 64 && d->score_mode != FK_SCORE_EXPONENTIAL;
-    if ((!plan || plan->chunk == 0) && S.first_by_index) S.plan.chunk = 256;
+    if ((!plan || plan->chunk == 0) && S.first_by_index) {
+        int n_cu = 0;
+        if ((rc = device_cus(&n_cu)) != FK_OK) return rc;
+        S.plan.chunk = short_chunk(n_nodes, n_paths, n_cu, mask != nullptr);
+    }
     S.n_nodes = n_nodes;
     S.n_paths = n_paths;
     S.counters = (uint32_t *)(ws + lay.counters);

@@ -1951,8 +1951,9 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     const bool uniform = (level.dt_last == level.dt && level.cbm_last == level.cbm);
     const bool mg = (form != FK_CV_DYNKIN);
     // network forms on short paths (a mesh step's sub-steps): 256 per grab
-    // by default, as in the plain solve (the network-control mesh step goes
-    // from 29.9 to 22.6 ms on the 768-cell run; the grid control keeps 128)
+    // by default (the network-control mesh step went from 29.9 to 22.6 ms on
+    // the 768-cell run against 128); the grid control keeps 128.  Larger
+    // grabs, which the plain kernel prefers there, cost these kernels 5%.
     if ((!plan || plan->chunk == 0) && !grid_ctl && level.K <= 64) pl.chunk = 256;
     const int64_t cpn = (n_paths + pl.chunk - 1) / pl.chunk;
     hipError_t e;
@@ -2096,7 +2097,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
         P.uniform = uniform;
         P.first_by_index = level.K <= 64;
         if ((rc = resolve_plan(nullptr, &P.plan)) != FK_OK) return rc;
-        if (P.first_by_index) P.plan.chunk = 256;
+        if (P.first_by_index) P.plan.chunk = short_chunk(n_nodes, n_paths, n_cu, mask != nullptr);
         P.n_nodes = n_nodes;
         P.n_paths = n_paths;
         P.counters = counters;

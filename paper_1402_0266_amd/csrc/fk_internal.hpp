@@ -171,6 +171,10 @@ int validate_device_points(const double *pts, int64_t n);  // device coordinates
 LevelDev make_level(const fk_density *w, double t_init, double t, double dt, uint32_t level_id, uint32_t stream);
 int resolve_plan(const fk_plan *plan, fk_plan *out);
 int check_chunks(int64_t n_nodes, int64_t n_paths, const fk_plan &pl);
+// Default paths per grab for short horizons: 256, or the largest of 512 ..
+// 2048 that still leaves 8 chunks per resident wavefront (28 per CU); 256
+// for masked solves.  The chunk only changes the schedule, never a result.
+int short_chunk(int64_t n_nodes, int64_t n_paths, int n_cu, bool masked);
 
 // Launch-plan tuning (fk_plan.hip): a 64-bit FNV-1a hash, the device's
 // signature, the tuned-plan cache (per process; FK_TUNE_CACHE names a file
