@@ -771,21 +771,26 @@ subdomain_lu_tile_kernel(const SubArgs a) {
     }
 }
 
-// Back substitution after the tile kernel, one wavefront per elimination
+// Back substitution after the tile kernel, one workgroup per elimination
 // (per end when twisted): x_k = (y_k - sum_d U[k][k+d] x_{k+d}) / U[k][k],
-// rows from the last one up, 64 at a time.  The block's U rows are copied to
-// LDS (coalesced); lane l takes row top - l and first sums its terms with
-// the columns already solved (beyond the block, from an LDS ring of
-// solutions), all lanes at once; the triangle inside the block is then
-// swept row by row: the lane of the row finishes it, its value is
-// broadcast (readlane), and every lane below adds its term.  The ring
-// starts with the separator's values (twisted) or zeros (past the last row).
+// rows from the last one up, 64 at a time.  Wavefront 0 solves a block
+// while wavefronts 1-3 copy the next block's U rows and right-hand sides to
+// the other of two LDS buffers (coalesced, 16 loads in flight per lane), so
+// the copy's latency hides behind the solve; one barrier per block.  The
+// solve: lane l takes row top - l and first sums its terms with the columns
+// already solved (beyond the block, from an LDS ring of solutions), all
+// lanes at once; the triangle inside the block is then swept row by row: the
+// value of each row is broadcast from its lane (readlane) and every lane
+// below adds its term; then every lane stores its own row's solution.  The
+// ring starts with the separator's values (twisted) or zeros (past the last
+// row).
 constexpr int kBackRows = 64;
 
-__global__ void __launch_bounds__(64) back_block_kernel(const SubArgs a) {
-    extern __shared__ double Ub[];               // kBackRows rows of stride P1 | 1, then the ring
+__global__ void __launch_bounds__(256) back_block_kernel(const SubArgs a) {
+    extern __shared__ double Ub[];               // 2 x kBackRows rows of stride P1 | 1, the ring, the y blocks
     const int qf = a.qf, P1 = qf + 1, n = qf * a.qs, S = P1 | 1;
-    double *xr = Ub + (size_t)kBackRows * S;     // [2][256]: solutions by row & 255
+    double *xr = Ub + (size_t)2 * kBackRows * S; // [2][256]: solutions by row & 255
+    double *yb = xr + 512;                       // [2 buffers][2 components][kBackRows]
     const int sd = a.twisted ? blockIdx.x >> 1 : blockIdx.x;
     const bool rev = a.twisted && (blockIdx.x & 1);
     int i0, j0;
@@ -794,87 +799,107 @@ __global__ void __launch_bounds__(64) back_block_kernel(const SubArgs a) {
     const int off = rev ? a.sep : 0;
     const double *U = a.ubuf + (int64_t)sd * n * P1 + (int64_t)off * P1;
     const double *Y = a.ybuf + (int64_t)sd * 2 * n + off;
-    const int lane = threadIdx.x;
-    for (int t = lane; t < 512; t += 64) xr[t] = 0.0;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int t = tid; t < 512; t += 256) xr[t] = 0.0;
     __syncthreads();
     if (a.twisted) {
         const double *xs = a.sbuf + (int64_t)sd * sep_stride(qf) + 2 * ((size_t)qf * qf + 2 * qf);
-        for (int t = lane; t < qf; t += 64) {
+        for (int t = tid; t < qf; t += 256) {
             const int row = (steps + t) & 255, src = rev ? qf - 1 - t : t;
             xr[row] = xs[src];
             xr[256 + row] = xs[qf + src];
         }
     }
-    __syncthreads();
-    for (int top = steps - 1; top >= 0; top -= kBackRows) {
+    // the U rows and y values of the block ending at row `top` into buffer
+    // `buf`, by threads t of nt
+    auto load_block = [&](int top, int buf, int t, int nt) {
         const int nb = min(kBackRows, top + 1), base = top - nb + 1;
         const double *src = U + (int64_t)base * P1;
-        // the block's U rows into LDS, 16 loads in flight per lane
+        double *dst = Ub + (size_t)buf * kBackRows * S;
         const int tot = nb * P1;
-        for (int e0 = 0; e0 < tot; e0 += 16 * 64) {
+        if (t < nb) {
+            yb[(2 * buf) * kBackRows + t] = Y[base + t];
+            yb[(2 * buf + 1) * kBackRows + t] = Y[n + base + t];
+        }
+        for (int e0 = 0; e0 < tot; e0 += 16 * nt) {
             double v[16];
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                const int e = e0 + i * 64 + lane;
+                const int e = e0 + i * nt + t;
                 v[i] = e < tot ? src[e] : 0.0;
             }
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                const int e = e0 + i * 64 + lane;
+                const int e = e0 + i * nt + t;
                 if (e < tot) {
                     const int rr = e / P1;
-                    Ub[rr * S + (e - rr * P1)] = v[i];
+                    dst[rr * S + (e - rr * P1)] = v[i];
                 }
             }
         }
-        __syncthreads();
-        const bool has = lane < nb;
-        const int r = top - lane, lr = nb - 1 - lane;   // this lane's row and its place in the block
-        const double *ur = Ub + (has ? lr : 0) * S;
-        double sx = 0.0, sy = 0.0, yx = 0.0, yy = 0.0, d0 = 1.0;
-        if (has) {
-            d0 = ur[0];
-            yx = Y[r];
-            yy = Y[n + r];
-            // four terms per pass, so the LDS reads of a pass are in flight together
-            int d = lane + 1;
-            for (; d + 3 <= qf; d += 4) {
-                double u4[4], x4[4], y4[4];
+    };
+    if (steps > 0) load_block(steps - 1, 0, tid, 256);
+    __syncthreads();
+    int buf = 0;
+    for (int top = steps - 1; top >= 0; top -= kBackRows, buf ^= 1) {
+        if (wave != 0) {
+            if (top >= kBackRows) load_block(top - kBackRows, buf ^ 1, tid - 64, 192);
+        } else {
+            const int nb = min(kBackRows, top + 1);
+            const bool has = lane < nb;
+            const int r = top - lane, lr = nb - 1 - lane;   // this lane's row and its place in the block
+            const double *ur = Ub + (size_t)buf * kBackRows * S + (has ? lr : 0) * S;
+            double sx = 0.0, sy = 0.0, yx = 0.0, yy = 0.0, d0 = 1.0;
+            if (has) {
+                d0 = ur[0];
+                yx = yb[(2 * buf) * kBackRows + lr];
+                yy = yb[(2 * buf + 1) * kBackRows + lr];
+                // four terms per pass, so the LDS reads of a pass are in flight together
+                int d = lane + 1;
+                for (; d + 3 <= qf; d += 4) {
+                    double u4[4], x4[4], y4[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    const int c = (r + d + i) & 255;
-                    u4[i] = ur[d + i];
-                    x4[i] = xr[c];
-                    y4[i] = xr[256 + c];
+                    for (int i = 0; i < 4; ++i) {
+                        const int c = (r + d + i) & 255;
+                        u4[i] = ur[d + i];
+                        x4[i] = xr[c];
+                        y4[i] = xr[256 + c];
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        sx = fma(u4[i], x4[i], sx);
+                        sy = fma(u4[i], y4[i], sy);
+                    }
                 }
-#pragma unroll
-                for (int i = 0; i < 4; ++i) {
-                    sx = fma(u4[i], x4[i], sx);
-                    sy = fma(u4[i], y4[i], sy);
+                for (; d <= qf; ++d) {
+                    const int c = (r + d) & 255;
+                    sx = fma(ur[d], xr[c], sx);
+                    sy = fma(ur[d], xr[256 + c], sy);
                 }
             }
-            for (; d <= qf; ++d) {
-                const int c = (r + d) & 255;
-                sx = fma(ur[d], xr[c], sx);
-                sy = fma(ur[d], xr[256 + c], sy);
+            const double inv = 1.0 / d0;
+            double ucur = (has && lane >= 1 && lane <= qf) ? ur[lane] : 0.0;   // term of row top at step 0
+            double mx = 0.0, my = 0.0;                   // this lane's own row's solution
+            for (int s = 0; s < nb; ++s) {
+                const int dn = lane - s - 1;
+                const double unext = (has && dn >= 1 && dn <= qf) ? ur[dn] : 0.0;
+                const double ox = (yx - sx) * inv, oy = (yy - sy) * inv;
+                const double xv = readlane_f64(ox, s), yv = readlane_f64(oy, s);
+                if (lane == s) {
+                    mx = ox;
+                    my = oy;
+                }
+                sx = fma(ucur, xv, sx);
+                sy = fma(ucur, yv, sy);
+                ucur = unext;
             }
-        }
-        const double inv = 1.0 / d0;
-        double ucur = (has && lane >= 1 && lane <= qf) ? ur[lane] : 0.0;   // term of row top at step 0
-        for (int s = 0; s < nb; ++s) {
-            const int dn = lane - s - 1;
-            const double unext = (has && dn >= 1 && dn <= qf) ? ur[dn] : 0.0;
-            const double xv = readlane_f64((yx - sx) * inv, s), yv = readlane_f64((yy - sy) * inv, s);
-            if (lane == s) {
-                xr[r & 255] = xv;
-                xr[256 + (r & 255)] = yv;
+            if (has) {
+                xr[r & 255] = mx;
+                xr[256 + (r & 255)] = my;
                 const int64_t gn = unknown_node(a, rev ? n - 1 - r : r, i0, j0);
-                a.xi_out[gn] = xv;
-                a.eta_out[gn] = yv;
+                a.xi_out[gn] = mx;
+                a.eta_out[gn] = my;
             }
-            sx = fma(ucur, xv, sx);
-            sy = fma(ucur, yv, sy);
-            ucur = unext;
         }
         __syncthreads();
     }
@@ -1261,7 +1286,7 @@ static hipError_t lds_limits_once() {
     if (dev >= 0 && dev < 64 && done[dev]) return hipSuccess;
     const int qmax = kMaxP1 - 1;
     const size_t sep = ((size_t)qmax * qmax + 2 * qmax) * sizeof(double);
-    const size_t back = ((size_t)kBackRows * (kMaxP1 | 1) + 512) * sizeof(double);
+    const size_t back = ((size_t)2 * kBackRows * (kMaxP1 | 1) + 512 + 4 * kBackRows) * sizeof(double);
     if ((e = hipFuncSetAttribute((const void *)separator_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
                                  (int)sep)) != hipSuccess)
         return e;
@@ -1322,8 +1347,8 @@ static hipError_t launch_elimination(const SubArgs &a, int blocks, hipStream_t s
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (a.twisted && (e = separator()) != hipSuccess) return e;
-    const size_t lds = ((size_t)kBackRows * (P1 | 1) + 512) * sizeof(double);
-    hipLaunchKernelGGL(back_block_kernel, dim3(nwg), dim3(64), lds, s, a);
+    const size_t lds = ((size_t)2 * kBackRows * (P1 | 1) + 512 + 4 * kBackRows) * sizeof(double);
+    hipLaunchKernelGGL(back_block_kernel, dim3(nwg), dim3(256), lds, s, a);
     return hipGetLastError();
 }
 
