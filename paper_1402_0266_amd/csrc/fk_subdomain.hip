@@ -35,7 +35,8 @@ namespace fk {
 struct SubArgs {
     const double *xi_n, *eta_n;  // previous mesh, (N+1)^2
     double *xi_out, *eta_out;    // Dirichlet data pre-filled; interior written
-    double *ubuf;                // per sub-domain: n * (p+1) doubles
+    double *ubuf;                // per sub-domain: n rows of ustride doubles (U row k: entries k .. k+q)
+    int ustride;                 // U row stride: q + 1 (one-wavefront kernels), or the tile kernel's window
     double *ybuf;                // per sub-domain: 2 n doubles
     double *cbuf;                // per sub-domain: 4 n doubles, (E, W, N, S) coefficients of each row
     double *rbuf;                // per sub-domain: 2 n doubles, right-hand sides (xi, eta) of each row
@@ -481,7 +482,8 @@ subdomain_lu_tile_kernel(const SubArgs a) {
     sub_origin(a, sd, i0, j0);
     const int steps = !a.twisted ? n : (rev ? n - a.sep - qf : a.sep);
     const int off = rev ? a.sep : 0;
-    double *U = a.ubuf + (int64_t)sd * n * P1 + (int64_t)off * P1;
+    const int us = a.ustride;                    // = W: every window column has a slot in U's rows
+    double *U = a.ubuf + (int64_t)sd * n * us + (int64_t)off * us;
     double *Y = a.ybuf + (int64_t)sd * 2 * n + off;
     const int64_t cix = a.twisted ? 2 * (int64_t)sd + (rev ? 1 : 0) : sd;
     double4 *cf = reinterpret_cast<double4 *>(a.cbuf + cix * 4 * n);
@@ -503,6 +505,10 @@ subdomain_lu_tile_kernel(const SubArgs a) {
         const int r = rg + 16 * t;
         B[t] = (rhs && r < n) ? (cg == 0 ? rh[r].x : rh[r].y) : 0.0;
     }
+    // Wait for the window's loads here, once: the waits the compiler places
+    // for registers loaded before the step loop would otherwise sit inside
+    // it (vmcnt 0 on every step, behind the U-row stores of the step).
+    __builtin_amdgcn_s_waitcnt(0x0F70);   // vmcnt(0), expcnt and lgkmcnt unconstrained
     // what the block of steps k0 .. k0 + 15 lets in: this lane's row
     // k0 + W + rg (coefficients and right-hand side) and, for its column
     // c = k0 + W + cg, the fast+ coefficient of row c - 1 and the slow+ one
@@ -526,15 +532,18 @@ subdomain_lu_tile_kernel(const SubArgs a) {
         for (int t = 0; t < T; ++t) po[t] = 16 * ((t + base) % T);
     };
     set_offsets();
-    // U row k (global) from this lane's entries v of the row whose pivot sits
-    // at physical index kp
-    auto put_u = [&](int kk, int kp, const double (&v)[T]) {
+    // U row k (global) from this lane's entries v of the row whose pivot is
+    // lane column gg of slot 0: the window column at band offset d goes to
+    // slot d of the row (d in 0 .. W-1; the slots past q receive columns
+    // outside the band and are never read), so the stores need no test.  The
+    // band offset of slot u is cg - gg + 16 u modulo W whatever the rotation
+    // (slot u sits 16 u physical columns after slot 0, circularly), which is
+    // cg - gg + 16 u itself for u >= 1.
+    auto put_u = [&](int kk, int gg, const double (&v)[T]) {
+        const int64_t rb = (int64_t)kk * us + (cg - gg);
+        U[rb + (cg < gg ? W : 0)] = v[0];
 #pragma unroll
-        for (int u = 0; u < T; ++u) {
-            int d = cg + po[u] - kp;                 // band offset of the column in U row kk
-            d += d < 0 ? W : 0;
-            if (d <= qf) U[(int64_t)kk * P1 + d] = v[u];
-        }
+        for (int u = 1; u < T; ++u) U[rb + 16 * u] = v[u];
     };
     while (k < steps) {
         const int k0 = k;
@@ -565,7 +574,7 @@ subdomain_lu_tile_kernel(const SubArgs a) {
                     }
                     if (rhs) rowb[buf][h][W + cg] = B[0];
                     if (h == 0) {
-                        put_u(k, kp, v);
+                        put_u(k, g, v);
                         if (rhs) Y[(int64_t)cg * n + k] = B[0];
                     }
                 }
@@ -595,7 +604,7 @@ subdomain_lu_tile_kernel(const SubArgs a) {
                 for (int u = 0; u < T; ++u) r1[u] = fma(-l01, r0[u], r1[u]);
                 const double b1p = fma(-l01, b0, b1);
                 if (rg == g + 1) {
-                    put_u(k + 1, kp + 1, r1);
+                    put_u(k + 1, g + 1, r1);
                     if (rhs) Y[(int64_t)cg * n + k + 1] = b1p;
                 }
                 // step k on every entry (the reciprocal's latency hides behind it)
@@ -652,7 +661,7 @@ subdomain_lu_tile_kernel(const SubArgs a) {
                     v[u] = A[0][u];
                     rowb[buf][0][cg + po[u]] = v[u];
                 }
-                put_u(k, kp, v);
+                put_u(k, g, v);
                 if (rhs) {
                     rowb[buf][0][W + cg] = B[0];
                     Y[(int64_t)cg * n + k] = B[0];
@@ -797,7 +806,8 @@ __global__ void __launch_bounds__(256) back_block_kernel(const SubArgs a) {
     sub_origin(a, sd, i0, j0);
     const int steps = !a.twisted ? n : (rev ? n - a.sep - qf : a.sep);
     const int off = rev ? a.sep : 0;
-    const double *U = a.ubuf + (int64_t)sd * n * P1 + (int64_t)off * P1;
+    const int us = a.ustride;
+    const double *U = a.ubuf + (int64_t)sd * n * us + (int64_t)off * us;
     const double *Y = a.ybuf + (int64_t)sd * 2 * n + off;
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     for (int t = tid; t < 512; t += 256) xr[t] = 0.0;
@@ -814,9 +824,9 @@ __global__ void __launch_bounds__(256) back_block_kernel(const SubArgs a) {
     // `buf`, by threads t of nt
     auto load_block = [&](int top, int buf, int t, int nt) {
         const int nb = min(kBackRows, top + 1), base = top - nb + 1;
-        const double *src = U + (int64_t)base * P1;
+        const double *src = U + (int64_t)base * us;
         double *dst = Ub + (size_t)buf * kBackRows * S;
-        const int tot = nb * P1;
+        const int tot = nb * P1;                 // the first P1 slots of each row
         if (t < nb) {
             yb[(2 * buf) * kBackRows + t] = Y[base + t];
             yb[(2 * buf + 1) * kBackRows + t] = Y[n + base + t];
@@ -825,8 +835,8 @@ __global__ void __launch_bounds__(256) back_block_kernel(const SubArgs a) {
             double v[16];
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
-                const int e = e0 + i * nt + t;
-                v[i] = e < tot ? src[e] : 0.0;
+                const int e = e0 + i * nt + t, rr = e / P1;
+                v[i] = e < tot ? src[(int64_t)rr * us + (e - rr * P1)] : 0.0;
             }
 #pragma unroll
             for (int i = 0; i < 16; ++i) {
@@ -1257,13 +1267,21 @@ static SubGeom sub_geom(int px, int py, int N) {
     return g;
 }
 
+// U row stride of a band of q = qf unknowns: q + 1 for the one-wavefront
+// kernels (the bands they take), otherwise the tile kernel's window 16 T.
+static int u_stride(int qf) {
+    const int P1 = qf + 1;
+    if (P1 == 8 || P1 == 12 || P1 == 16 || P1 == 20 || P1 == 24 || P1 == 32) return P1;
+    return 16 * ((qf + 16 + 15) / 16);
+}
+
 // Workspace: U rows, y values, row coefficients and right-hand sides (two
 // copies per sub-domain: natural and reversed order), the separator blocks,
 // and the edge integrals.
 static size_t sub_ws_bytes(const SubGeom &g, int N) {
-    const size_t n = (size_t)g.n, P1 = (size_t)g.qf + 1;
+    const size_t n = (size_t)g.n, us = (size_t)u_stride(g.qf);
     const size_t blocks = (size_t)g.px * g.py;
-    return align256(blocks * n * P1 * sizeof(double)) + align256(blocks * 2 * n * sizeof(double)) +
+    return align256(blocks * n * us * sizeof(double)) + align256(blocks * 2 * n * sizeof(double)) +
            align256(2 * blocks * 4 * n * sizeof(double)) + align256(2 * blocks * 2 * n * sizeof(double)) +
            align256(blocks * sep_stride(g.qf) * sizeof(double)) + align256(4 * (size_t)N * sizeof(double));
 }
@@ -1431,11 +1449,12 @@ int subdomain_solve_rect(const fk_density *w, double t_w, double dt_mesh, int32_
     a.eta_n = eta_n;
     a.xi_out = xi_out;
     a.eta_out = eta_out;
-    const size_t n = (size_t)geo.n, P1 = (size_t)geo.qf + 1;
+    const size_t n = (size_t)geo.n;
     const size_t blocks = (size_t)px * py;
     char *ws = (char *)workspace;
+    a.ustride = u_stride(geo.qf);
     a.ubuf = (double *)ws;
-    ws += align256(blocks * n * P1 * sizeof(double));
+    ws += align256(blocks * n * (size_t)a.ustride * sizeof(double));
     a.ybuf = (double *)ws;
     ws += align256(blocks * 2 * n * sizeof(double));
     a.cbuf = (double *)ws;
