@@ -26,6 +26,7 @@
 #include <algorithm>
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 
 #include "fk.h"
 #include "fk_internal.hpp"
@@ -524,7 +525,7 @@ subdomain_lu_tile_kernel(const SubArgs a) {
         scol = Rc - qf < n ? cf[Rc - qf].z : 0.0;
     };
 
-    int base = 0, k = 0, it = 0;
+    int base = 0, k = 0;
     double rnext = 1.0 / A[0][0];  // reciprocal of the next pivot (meaningful in its lane)
     int po[T];                     // physical offset of slot t: 16 ((t + base) mod T)
     auto set_offsets = [&]() {
@@ -545,166 +546,120 @@ subdomain_lu_tile_kernel(const SubArgs a) {
 #pragma unroll
         for (int u = 1; u < T; ++u) U[rb + 16 * u] = v[u];
     };
-    while (k < steps) {
-        const int k0 = k;
-        load_enter(k0);
-        for (int g = 0; g < 16 && k < steps;) {
-            const int kp = 16 * base + g;     // physical index of the pivot
-            const int buf = it++ & 1;
-            if (g < 15 && k + 1 < steps) {
-                // ---- steps k and k + 1 behind one barrier -------------------
-                // The lanes of columns g and g + 1 publish them (the pivot's
-                // reciprocal, formed at the end of the previous step, at the
-                // pivot), the lanes of rows g and g + 1 theirs and their
-                // right-hand sides, all as they stand before step k.
-                if (cg == g) {
+    // Steps k and k + 1 (block-relative pivots g and g + 1) behind one
+    // barrier, with LDS buffer BUF (the buffers alternate from barrier to
+    // barrier; a block's 16 steps are 8 pairs, so its first pair takes buffer
+    // 0 and the buffer index is a compile-time constant).
+    auto pair = [&](int g, auto bufc) {
+        constexpr int buf = decltype(bufc)::value;
+        const int kp = 16 * base + g;     // physical index of the pivot
+        // ---- steps k and k + 1 behind one barrier -------------------
+        // The lanes of columns g and g + 1 publish them (the pivot's
+        // reciprocal, formed at the end of the previous step, at the
+        // pivot), the lanes of rows g and g + 1 theirs and their
+        // right-hand sides, all as they stand before step k.
+        if (cg == g) {
 #pragma unroll
-                    for (int t = 0; t < T; ++t) colb[buf][0][rg + po[t]] = (t == 0 && rg == g) ? rnext : A[t][0];
-                } else if (cg == g + 1) {
+            for (int t = 0; t < T; ++t) colb[buf][0][rg + po[t]] = (t == 0 && rg == g) ? rnext : A[t][0];
+        } else if (cg == g + 1) {
 #pragma unroll
-                    for (int t = 0; t < T; ++t) colb[buf][1][rg + po[t]] = A[t][0];
-                }
-                if (rg == g || rg == g + 1) {
-                    const int h = rg - g;
-                    double v[T];
+            for (int t = 0; t < T; ++t) colb[buf][1][rg + po[t]] = A[t][0];
+        }
+        if (rg == g || rg == g + 1) {
+            const int h = rg - g;
+            double v[T];
 #pragma unroll
-                    for (int u = 0; u < T; ++u) {
-                        v[u] = A[0][u];
-                        rowb[buf][h][cg + po[u]] = v[u];
-                    }
-                    if (rhs) rowb[buf][h][W + cg] = B[0];
-                    if (h == 0) {
-                        put_u(k, g, v);
-                        if (rhs) Y[(int64_t)cg * n + k] = B[0];
-                    }
-                }
-                __syncthreads();
-                double l0[T], c1[T], r0[T], r1[T];
-                const double inv0 = colb[buf][0][kp];
-                const double a1k = colb[buf][0][kp + 1], ak1 = rowb[buf][0][kp + 1], a11 = rowb[buf][1][kp + 1];
-#pragma unroll
-                for (int t = 0; t < T; ++t) {
-                    l0[t] = colb[buf][0][rg + po[t]];
-                    c1[t] = colb[buf][1][rg + po[t]];
-                }
-#pragma unroll
-                for (int u = 0; u < T; ++u) {
-                    r0[u] = rowb[buf][0][cg + po[u]];
-                    r1[u] = rowb[buf][1][cg + po[u]];
-                }
-                const double b0 = rowb[buf][0][W + cg], b1 = rowb[buf][1][W + cg];
-                // step k's multipliers; row k + 1, its right-hand side and its
-                // pivot as step k leaves them (the operations step k would
-                // apply to them, in the same order)
-                const double l01 = a1k * inv0;
-                const double inv1 = 1.0 / fma(-l01, ak1, a11);
-#pragma unroll
-                for (int t = 0; t < T; ++t) l0[t] *= inv0;
-#pragma unroll
-                for (int u = 0; u < T; ++u) r1[u] = fma(-l01, r0[u], r1[u]);
-                const double b1p = fma(-l01, b0, b1);
-                if (rg == g + 1) {
-                    put_u(k + 1, g + 1, r1);
-                    if (rhs) Y[(int64_t)cg * n + k + 1] = b1p;
-                }
-                // step k on every entry (the reciprocal's latency hides behind it)
-#pragma unroll
-                for (int t = 0; t < T; ++t)
-#pragma unroll
-                    for (int u = 0; u < T; ++u) A[t][u] = fma(-l0[t], r0[u], A[t][u]);
-                if (rhs) {
-#pragma unroll
-                    for (int t = 0; t < T; ++t) B[t] = fma(-l0[t], b0, B[t]);
-                }
-                // step k + 1: column k + 1 as step k leaves it, its multipliers
-                double l1[T];
-#pragma unroll
-                for (int t = 0; t < T; ++t) l1[t] = fma(-l0[t], ak1, c1[t]) * inv1;
-                // the entry that is the next pivot first, and its reciprocal
-                double np;
-                if (T > 1 && g == 14) {
-                    A[1][1] = fma(-l1[1], r1[1], A[1][1]);
-                    np = A[1][1];
-                } else {
-                    A[0][0] = fma(-l1[0], r1[0], A[0][0]);
-                    np = A[0][0];
-                }
-                rnext = 1.0 / np;
-#pragma unroll
-                for (int t = 0; t < T; ++t) {
-#pragma unroll
-                    for (int u = 0; u < T; ++u) {
-                        if (t == 0 && u == 0 && !(T > 1 && g == 14)) continue;
-                        if (T > 1 && t == 1 && u == 1 && g == 14) continue;
-                        A[t][u] = fma(-l1[t], r1[u], A[t][u]);
-                    }
-                }
-                if (rhs) {
-#pragma unroll
-                    for (int t = 0; t < T; ++t) B[t] = fma(-l1[t], b1p, B[t]);
-                }
-                g += 2;
-                k += 2;
-                continue;
+            for (int u = 0; u < T; ++u) {
+                v[u] = A[0][u];
+                rowb[buf][h][cg + po[u]] = v[u];
             }
-            // ---- one step (the last one of an odd count) --------------------
-            if (cg == g) {
-                // the pivot column; at the pivot its reciprocal, formed at the
-                // end of the previous step
-#pragma unroll
-                for (int t = 0; t < T; ++t) colb[buf][0][rg + po[t]] = (t == 0 && rg == g) ? rnext : A[t][0];
-            }
-            if (rg == g) {
-                double v[T];
-#pragma unroll
-                for (int u = 0; u < T; ++u) {
-                    v[u] = A[0][u];
-                    rowb[buf][0][cg + po[u]] = v[u];
-                }
+            if (rhs) rowb[buf][h][W + cg] = B[0];
+            if (h == 0) {
                 put_u(k, g, v);
-                if (rhs) {
-                    rowb[buf][0][W + cg] = B[0];
-                    Y[(int64_t)cg * n + k] = B[0];
-                }
+                if (rhs) Y[(int64_t)cg * n + k] = B[0];
             }
-            __syncthreads();
-            // every LDS read of the step at once, then the update
-            double l[T], r[T];
-            const double inv = colb[buf][0][kp];
+        }
+        __syncthreads();
+        double l0[T], c1[T], r0[T], r1[T];
+        const double inv0 = colb[buf][0][kp];
+        const double a1k = colb[buf][0][kp + 1], ak1 = rowb[buf][0][kp + 1], a11 = rowb[buf][1][kp + 1];
 #pragma unroll
-            for (int t = 0; t < T; ++t) l[t] = colb[buf][0][rg + po[t]];
+        for (int t = 0; t < T; ++t) {
+            l0[t] = colb[buf][0][rg + po[t]];
+            c1[t] = colb[buf][1][rg + po[t]];
+        }
 #pragma unroll
-            for (int u = 0; u < T; ++u) r[u] = rowb[buf][0][cg + po[u]];
-            const double bp = rowb[buf][0][W + cg];
+        for (int u = 0; u < T; ++u) {
+            r0[u] = rowb[buf][0][cg + po[u]];
+            r1[u] = rowb[buf][1][cg + po[u]];
+        }
+        const double b0 = rowb[buf][0][W + cg], b1 = rowb[buf][1][W + cg];
+        // step k's multipliers; row k + 1, its right-hand side and its
+        // pivot as step k leaves them (the operations step k would
+        // apply to them, in the same order)
+        const double l01 = a1k * inv0;
+        const double inv1 = 1.0 / fma(-l01, ak1, a11);
 #pragma unroll
-            for (int t = 0; t < T; ++t) l[t] *= inv;
-            // the entry that is the next pivot first (slot 0's diagonal, or
-            // slot 1's after the last step of the block), and its reciprocal,
-            // whose latency the rest of the update hides
-            double np;
-            if (T > 1 && g == 15) {
-                A[1][1] = fma(-l[1], r[1], A[1][1]);
-                np = A[1][1];
-            } else {
-                A[0][0] = fma(-l[0], r[0], A[0][0]);
-                np = A[0][0];
+        for (int t = 0; t < T; ++t) l0[t] *= inv0;
+#pragma unroll
+        for (int u = 0; u < T; ++u) r1[u] = fma(-l01, r0[u], r1[u]);
+        const double b1p = fma(-l01, b0, b1);
+        if (rg == g + 1) {
+            put_u(k + 1, g + 1, r1);
+            if (rhs) Y[(int64_t)cg * n + k + 1] = b1p;
+        }
+        // step k on every entry (the reciprocal's latency hides behind it)
+#pragma unroll
+        for (int t = 0; t < T; ++t)
+#pragma unroll
+            for (int u = 0; u < T; ++u) A[t][u] = fma(-l0[t], r0[u], A[t][u]);
+        if (rhs) {
+#pragma unroll
+            for (int t = 0; t < T; ++t) B[t] = fma(-l0[t], b0, B[t]);
+        }
+        // step k + 1: column k + 1 as step k leaves it, its multipliers
+        double l1[T];
+#pragma unroll
+        for (int t = 0; t < T; ++t) l1[t] = fma(-l0[t], ak1, c1[t]) * inv1;
+        // the entry that is the next pivot first, and its reciprocal
+        double np;
+        if (T > 1 && g == 14) {
+            A[1][1] = fma(-l1[1], r1[1], A[1][1]);
+            np = A[1][1];
+        } else {
+            A[0][0] = fma(-l1[0], r1[0], A[0][0]);
+            np = A[0][0];
+        }
+        rnext = 1.0 / np;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+#pragma unroll
+            for (int u = 0; u < T; ++u) {
+                if (t == 0 && u == 0 && !(T > 1 && g == 14)) continue;
+                if (T > 1 && t == 1 && u == 1 && g == 14) continue;
+                A[t][u] = fma(-l1[t], r1[u], A[t][u]);
             }
-            rnext = 1.0 / np;
+        }
+        if (rhs) {
 #pragma unroll
-            for (int t = 0; t < T; ++t) {
-#pragma unroll
-                for (int u = 0; u < T; ++u) {
-                    if (t == 0 && u == 0 && !(T > 1 && g == 15)) continue;
-                    if (T > 1 && t == 1 && u == 1 && g == 15) continue;
-                    A[t][u] = fma(-l[t], r[u], A[t][u]);
-                }
-            }
-            if (rhs) {
-#pragma unroll
-                for (int t = 0; t < T; ++t) B[t] = fma(-l[t], bp, B[t]);
-            }
-            g += 1;
-            k += 1;
+            for (int t = 0; t < T; ++t) B[t] = fma(-l1[t], b1p, B[t]);
+        }
+    };
+    int k0 = 0, npair = 0;
+    while (k < steps) {
+        k0 = k;
+        load_enter(k0);
+        npair = 0;
+        for (int g = 0; g < 16 && k + 1 < steps;) {
+            pair(g, std::integral_constant<int, 0>{});
+            g += 2;
+            k += 2;
+            ++npair;
+            if (g >= 16 || k + 1 >= steps) break;
+            pair(g, std::integral_constant<int, 1>{});
+            g += 2;
+            k += 2;
+            ++npair;
         }
         if (k - k0 < 16 || k >= steps) break;
         // the block is done: its rows and columns k0 + W + (0 .. 15) enter
@@ -757,6 +712,66 @@ subdomain_lu_tile_kernel(const SubArgs a) {
         }
         base = base + 1 == T ? 0 : base + 1;
         set_offsets();
+    }
+    if (k < steps) {
+        // ---- the last step of an odd count, alone --------------------------
+        const int g = k - k0, kp = 16 * base + g, buf = npair & 1;
+        if (cg == g) {
+            // the pivot column; at the pivot its reciprocal, formed at the
+            // end of the previous step
+#pragma unroll
+            for (int t = 0; t < T; ++t) colb[buf][0][rg + po[t]] = (t == 0 && rg == g) ? rnext : A[t][0];
+        }
+        if (rg == g) {
+            double v[T];
+#pragma unroll
+            for (int u = 0; u < T; ++u) {
+                v[u] = A[0][u];
+                rowb[buf][0][cg + po[u]] = v[u];
+            }
+            put_u(k, g, v);
+            if (rhs) {
+                rowb[buf][0][W + cg] = B[0];
+                Y[(int64_t)cg * n + k] = B[0];
+            }
+        }
+        __syncthreads();
+        // every LDS read of the step at once, then the update
+        double l[T], r[T];
+        const double inv = colb[buf][0][kp];
+#pragma unroll
+        for (int t = 0; t < T; ++t) l[t] = colb[buf][0][rg + po[t]];
+#pragma unroll
+        for (int u = 0; u < T; ++u) r[u] = rowb[buf][0][cg + po[u]];
+        const double bp = rowb[buf][0][W + cg];
+#pragma unroll
+        for (int t = 0; t < T; ++t) l[t] *= inv;
+        // the entry that is the next pivot first (slot 0's diagonal, or
+        // slot 1's after the last step of the block), and its reciprocal,
+        // whose latency the rest of the update hides
+        double np;
+        if (T > 1 && g == 15) {
+            A[1][1] = fma(-l[1], r[1], A[1][1]);
+            np = A[1][1];
+        } else {
+            A[0][0] = fma(-l[0], r[0], A[0][0]);
+            np = A[0][0];
+        }
+        rnext = 1.0 / np;
+#pragma unroll
+        for (int t = 0; t < T; ++t) {
+#pragma unroll
+            for (int u = 0; u < T; ++u) {
+                if (t == 0 && u == 0 && !(T > 1 && g == 15)) continue;
+                if (T > 1 && t == 1 && u == 1 && g == 15) continue;
+                A[t][u] = fma(-l[t], r[u], A[t][u]);
+            }
+        }
+        if (rhs) {
+#pragma unroll
+            for (int t = 0; t < T; ++t) B[t] = fma(-l[t], bp, B[t]);
+        }
+        ++k;
     }
     if (a.twisted) {
         // the separator block of the trailing window (its first q rows and
