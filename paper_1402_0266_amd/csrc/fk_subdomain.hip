@@ -474,8 +474,11 @@ template <int T>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 subdomain_lu_tile_kernel(const SubArgs a) {
     constexpr int W = 16 * T;
-    __shared__ double colb[2][2][W];      // [buffer][pivot 0 / 1] pivot column by physical row
-    __shared__ double rowb[2][2][W + 2];  // ... pivot row by physical column, then its two right-hand sides
+    // [buffer][pivot 0 / 1] the pivot column by row and the pivot row by
+    // column, indexed by register slot and lane (16 t + lane: slot 0 holds the
+    // pivots' block), then the row's two right-hand sides
+    __shared__ double colb[2][2][W];
+    __shared__ double rowb[2][2][W + 2];
     const int qf = a.qf, P1 = qf + 1, n = qf * a.qs;
     const int sd = a.twisted ? blockIdx.x >> 1 : blockIdx.x;
     const bool rev = a.twisted && (blockIdx.x & 1);
@@ -552,7 +555,6 @@ subdomain_lu_tile_kernel(const SubArgs a) {
     // 0 and the buffer index is a compile-time constant).
     auto pair = [&](int g, auto bufc) {
         constexpr int buf = decltype(bufc)::value;
-        const int kp = 16 * base + g;     // physical index of the pivot
         // ---- steps k and k + 1 behind one barrier -------------------
         // The lanes of columns g and g + 1 publish them (the pivot's
         // reciprocal, formed at the end of the previous step, at the
@@ -560,10 +562,10 @@ subdomain_lu_tile_kernel(const SubArgs a) {
         // right-hand sides, all as they stand before step k.
         if (cg == g) {
 #pragma unroll
-            for (int t = 0; t < T; ++t) colb[buf][0][rg + po[t]] = (t == 0 && rg == g) ? rnext : A[t][0];
+            for (int t = 0; t < T; ++t) colb[buf][0][16 * t + rg] = (t == 0 && rg == g) ? rnext : A[t][0];
         } else if (cg == g + 1) {
 #pragma unroll
-            for (int t = 0; t < T; ++t) colb[buf][1][rg + po[t]] = A[t][0];
+            for (int t = 0; t < T; ++t) colb[buf][1][16 * t + rg] = A[t][0];
         }
         if (rg == g || rg == g + 1) {
             const int h = rg - g;
@@ -571,7 +573,7 @@ subdomain_lu_tile_kernel(const SubArgs a) {
 #pragma unroll
             for (int u = 0; u < T; ++u) {
                 v[u] = A[0][u];
-                rowb[buf][h][cg + po[u]] = v[u];
+                rowb[buf][h][16 * u + cg] = v[u];
             }
             if (rhs) rowb[buf][h][W + cg] = B[0];
             if (h == 0) {
@@ -581,17 +583,17 @@ subdomain_lu_tile_kernel(const SubArgs a) {
         }
         __syncthreads();
         double l0[T], c1[T], r0[T], r1[T];
-        const double inv0 = colb[buf][0][kp];
-        const double a1k = colb[buf][0][kp + 1], ak1 = rowb[buf][0][kp + 1], a11 = rowb[buf][1][kp + 1];
+        const double inv0 = colb[buf][0][g];
+        const double a1k = colb[buf][0][g + 1], ak1 = rowb[buf][0][g + 1], a11 = rowb[buf][1][g + 1];
 #pragma unroll
         for (int t = 0; t < T; ++t) {
-            l0[t] = colb[buf][0][rg + po[t]];
-            c1[t] = colb[buf][1][rg + po[t]];
+            l0[t] = colb[buf][0][16 * t + rg];
+            c1[t] = colb[buf][1][16 * t + rg];
         }
 #pragma unroll
         for (int u = 0; u < T; ++u) {
-            r0[u] = rowb[buf][0][cg + po[u]];
-            r1[u] = rowb[buf][1][cg + po[u]];
+            r0[u] = rowb[buf][0][16 * u + cg];
+            r1[u] = rowb[buf][1][16 * u + cg];
         }
         const double b0 = rowb[buf][0][W + cg], b1 = rowb[buf][1][W + cg];
         // step k's multipliers; row k + 1, its right-hand side and its
@@ -715,19 +717,19 @@ subdomain_lu_tile_kernel(const SubArgs a) {
     }
     if (k < steps) {
         // ---- the last step of an odd count, alone --------------------------
-        const int g = k - k0, kp = 16 * base + g, buf = npair & 1;
+        const int g = k - k0, buf = npair & 1;
         if (cg == g) {
             // the pivot column; at the pivot its reciprocal, formed at the
             // end of the previous step
 #pragma unroll
-            for (int t = 0; t < T; ++t) colb[buf][0][rg + po[t]] = (t == 0 && rg == g) ? rnext : A[t][0];
+            for (int t = 0; t < T; ++t) colb[buf][0][16 * t + rg] = (t == 0 && rg == g) ? rnext : A[t][0];
         }
         if (rg == g) {
             double v[T];
 #pragma unroll
             for (int u = 0; u < T; ++u) {
                 v[u] = A[0][u];
-                rowb[buf][0][cg + po[u]] = v[u];
+                rowb[buf][0][16 * u + cg] = v[u];
             }
             put_u(k, g, v);
             if (rhs) {
@@ -738,11 +740,11 @@ subdomain_lu_tile_kernel(const SubArgs a) {
         __syncthreads();
         // every LDS read of the step at once, then the update
         double l[T], r[T];
-        const double inv = colb[buf][0][kp];
+        const double inv = colb[buf][0][g];
 #pragma unroll
-        for (int t = 0; t < T; ++t) l[t] = colb[buf][0][rg + po[t]];
+        for (int t = 0; t < T; ++t) l[t] = colb[buf][0][16 * t + rg];
 #pragma unroll
-        for (int u = 0; u < T; ++u) r[u] = rowb[buf][0][cg + po[u]];
+        for (int u = 0; u < T; ++u) r[u] = rowb[buf][0][16 * u + cg];
         const double bp = rowb[buf][0][W + cg];
 #pragma unroll
         for (int t = 0; t < T; ++t) l[t] *= inv;
@@ -1079,18 +1081,22 @@ __global__ void __launch_bounds__(256) separator_kernel(const SubArgs a) {
         b[e] = St[(size_t)q * q + e] + Sb[(size_t)q * q + comp * q + (q - 1 - r)] - (comp ? f.y : f.x);
     }
     __syncthreads();
+    // rows by groups of 32 lanes, columns by the lanes of a group (no index
+    // division per entry)
+    const int tj = tid & 31, ti = tid >> 5, ng = nt >> 5;
     for (int k = 0; k < q; ++k) {
         const double inv = 1.0 / M[k * q + k];
         const int w = q - 1 - k + 2;   // columns k+1 .. q-1, then the two right-hand sides
-        for (int e = tid; e < (q - 1 - k) * w; e += nt) {
-            const int i = k + 1 + e / w, jj = e % w;
+        for (int i = k + 1 + ti; i < q; i += ng) {
             const double l = M[i * q + k] * inv;
-            if (jj < q - 1 - k) {
-                const int j = k + 1 + jj;
-                M[i * q + j] = fma(-l, M[k * q + j], M[i * q + j]);
-            } else {
-                const int comp = jj - (q - 1 - k);
-                b[comp * q + i] = fma(-l, b[comp * q + k], b[comp * q + i]);
+            for (int jj = tj; jj < w; jj += 32) {
+                if (jj < q - 1 - k) {
+                    const int j = k + 1 + jj;
+                    M[i * q + j] = fma(-l, M[k * q + j], M[i * q + j]);
+                } else {
+                    const int comp = jj - (q - 1 - k);
+                    b[comp * q + i] = fma(-l, b[comp * q + k], b[comp * q + i]);
+                }
             }
         }
         __syncthreads();
@@ -1099,7 +1105,7 @@ __global__ void __launch_bounds__(256) separator_kernel(const SubArgs a) {
         if (tid < 2) b[tid * q + k] = b[tid * q + k] / M[k * q + k];
         __syncthreads();
         for (int e = tid; e < 2 * k; e += nt) {
-            const int comp = e / k, i = e % k;
+            const int comp = e >= k ? 1 : 0, i = e - comp * k;
             b[comp * q + i] = fma(-M[i * q + k], b[comp * q + k], b[comp * q + i]);
         }
         __syncthreads();
