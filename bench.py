@@ -16,9 +16,11 @@ The same line reports, as extra objects:
 
 * "cv": the learned control variate on the same workload -- training labels
   from batched plain solves (132 time levels in [0, 0.1] x 1521 nodes x 1024
-  paths), 2000 Adam steps on the GPU, then the control-variate solve in its
-  martingale form at the stride that reaches RMS 1e-3 fastest (pilot at 4096
-  paths), timed at its own N*; the Dynkin form at stride 50 beside it.  The
+  paths), 16000 Adam steps on the GPU (a constant learning rate, then two
+  decays), then the control-variate solve in the form (martingale with the
+  hi + lo or the BF16 gradient, or Dynkin) and at the stride that reach RMS
+  1e-3 fastest: pilots at 4096 paths give each candidate's N*, each
+  candidate is timed once at its N*, and the fastest is timed.  The
   network fits the deviation from the identity map (u_hat = (x, y) + MLP);
   the same pipeline with the plain-output network, and the identity's
   gradient alone as the control, are reported beside it.  Throughput is
@@ -80,6 +82,9 @@ FLOP_PER_STEP = 36
 # channels through the two 64 x 64 hidden products, 2 FLOP per
 # multiply-add: 3 x 2 x 2 x 64 x 64 per evaluation point.
 NET_GRAD_FLOP = 3 * 2 * 2 * 64 * 64
+# The Dynkin form's five channels (value, d/dt, d/dx, d/dy, Laplacian)
+# through the same two products.
+NET_DYNKIN_FLOP = 5 * 2 * 2 * 64 * 64
 BF16_PEAK_TFLOPS = 2500.0
 # Paths per node of the control-variate kernels' profile (the timed solve's N*).
 CV_PROFILE_PATHS = 2952
@@ -178,7 +183,7 @@ def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=409
     cv = fk.FkCv(W.mlp_init(0), W.CV_T_SCALE, identity_base=identity_base)
     pts = torch.tensor(pts, dtype=torch.float64, device="cuda")     # resident coordinates
     t0 = time.perf_counter()
-    loss = P.train(cv, txy, target, steps=2000, batch=8192, lr=1e-3, seed=2)
+    loss = P.train_schedule(cv, txy, target, P.TRAIN_SCHEDULE, batch=8192, seed=2)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     loss = loss.cpu().numpy()
@@ -207,13 +212,27 @@ def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=409
                 "predicted_s": None if n_star is None else el * n_star / pilot_paths}
 
     solve(256, fk.FK_CV_MARTINGALE, 20)         # first-launch costs out of the pilots
+    solve(256, fk.FK_CV_DYNKIN, 20)
     pilots = ([pilot(fk.FK_CV_MARTINGALE, s) for s in (20, 100, 500, 2000)] +
-              [pilot(fk.FK_CV_MARTINGALE, s, "bf16") for s in (20, 100, 500)] + [pilot(fk.FK_CV_DYNKIN, 50)])
-    best = min((p for p in pilots if p["form"] == "martingale" and p["n_star"]),
-               key=lambda p: p["predicted_s"])
-    form, stride, n_star = fk.FK_CV_MARTINGALE, best["stride"], max(2, best["n_star"])
+              [pilot(fk.FK_CV_MARTINGALE, s, "bf16") for s in (20, 50, 100, 500)] +
+              [pilot(fk.FK_CV_DYNKIN, s) for s in (20, 50, 100, 200, 500)])
+    # Every candidate timed once at its own N*: below a few thousand paths
+    # per node the grid is no longer full and the pilots' time does not
+    # scale to N*.
+    forms = {"martingale": fk.FK_CV_MARTINGALE, "dynkin": fk.FK_CV_DYNKIN}
+    for p in pilots:
+        if not p["n_star"]:
+            continue
+        cv.set_grad_precision(p["grad"])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        solve(max(2, p["n_star"]), forms[p["form"]], p["stride"], plain=False)
+        torch.cuda.synchronize()
+        p["s_at_n_star"] = time.perf_counter() - t0
+    best = min((p for p in pilots if p["n_star"]), key=lambda p: p["s_at_n_star"])
+    form, stride, n_star = forms[best["form"]], best["stride"], max(2, best["n_star"])
     cv.set_grad_precision(best["grad"])
-    print(f"[bench] cv: martingale stride {stride} ({best['grad']} gradient), N* = {n_star}", file=sys.stderr,
+    print(f"[bench] cv: {best['form']} stride {stride} ({best['grad']} gradient), N* = {n_star}", file=sys.stderr,
           flush=True)
     for _ in range(warmup):
         solve(n_star, form, stride, plain=False)
@@ -266,33 +285,37 @@ def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=409
                        "rms_err": float(np.sqrt(np.mean((_stack(rl, ("xi", "eta")) - ref) ** 2)))})
     kms = float(np.mean(kern))
     return {
-        "form": "martingale", "stride": stride, "grad": best["grad"], "paths_per_node": n_star, "rms_err": rms,
+        "form": best["form"], "stride": stride, "grad": best["grad"], "paths_per_node": n_star, "rms_err": rms,
         "s_per_solve": wall, "path_kernel_ms": kms,
-        "roofline": cv_roofline(steps_cv, stride, kms, best["grad"]),
+        "roofline": cv_roofline(steps_cv, stride, kms, best["form"], best["grad"]),
         "nodes_per_s": n_nodes / wall,
         "nodes_per_s_incl_labels_and_training": n_nodes / (wall + t_labels + t_train),
         "labels": {"levels": 132, "paths": label_paths, "n": int(txy.shape[0]), "s": t_labels},
-        "training": {"steps": 2000, "batch": 8192, "lr": 1e-3, "s": t_train, "loss_first": float(loss[0]),
+        "training": {"schedule": [list(x) for x in P.TRAIN_SCHEDULE], "batch": 8192, "s": t_train,
+                     "loss_first": float(loss[0]),
                      "loss_last50": float(loss[-50:].mean())},
         "pilots": pilots,
         "linear_control": linear,
     }
 
 
-def cv_roofline(path_steps, stride, kernel_ms, grad):
-    """Roofline of the martingale path kernel: FP32 VALU on the path steps
-    (FLOP_PER_STEP each) against the FP32 vector peak, and the network's
-    products on MFMA against the dense BF16 peak.  The network's algorithmic
-    work is NET_GRAD_FLOP per evaluation point, one evaluation per `stride`
-    steps of a path (path_steps / stride); the hi + lo split issues each
-    product twice, which counts as work done but not as algorithmic work."""
+def cv_roofline(path_steps, stride, kernel_ms, form, grad):
+    """Roofline of the control-variate path kernel: FP32 VALU on the path
+    steps (FLOP_PER_STEP each) against the FP32 vector peak, and the
+    network's products on MFMA against the dense BF16 peak.  The network's
+    algorithmic work is NET_GRAD_FLOP (martingale form) or NET_DYNKIN_FLOP
+    (Dynkin form) per evaluation point, one evaluation per `stride` steps of
+    a path (path_steps / stride); the hi + lo split issues each product
+    twice, which counts as work done but not as algorithmic work."""
     fp32 = FLOP_PER_STEP * path_steps / (kernel_ms * 1e-3) / 1e12
     evals = path_steps / stride
-    mf = NET_GRAD_FLOP * evals / (kernel_ms * 1e-3) / 1e12
-    return {"kernel": "fk_mg_path_kernel", "bound": "alu", "achieved": fp32, "peak": FP32_PEAK_TFLOPS,
+    per_eval = NET_GRAD_FLOP if form == "martingale" else NET_DYNKIN_FLOP
+    mf = per_eval * evals / (kernel_ms * 1e-3) / 1e12
+    return {"kernel": "fk_mg_path_kernel" if form == "martingale" else "fk_cv_path_kernel", "bound": "alu",
+            "achieved": fp32, "peak": FP32_PEAK_TFLOPS,
             "unit": "TFLOP/s", "frac": fp32 / FP32_PEAK_TFLOPS, "flop_per_path_step": FLOP_PER_STEP,
             "mfma": {"achieved": mf, "peak": BF16_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": mf / BF16_PEAK_TFLOPS,
-                     "flop_per_eval": NET_GRAD_FLOP, "evals_per_launch": evals,
+                     "flop_per_eval": per_eval, "evals_per_launch": evals,
                      "issued_per_algorithmic": 2 if grad == "split" else 1}}
 
 
@@ -370,11 +393,12 @@ def measure_paper_run():
 
 
 def cv_kernels_only(fk, n_paths=CV_PROFILE_PATHS):
-    """The control-variate kernels of the timed solve at its size, for the
-    profiler: the martingale kernel with the network at strides 500 and 20,
-    with the hi + lo and the BF16 gradient (weights do not change the work:
-    an untrained identity-base network), and the linear control, two
-    launches each."""
+    """The control-variate kernels, for the profiler: the Dynkin kernel at
+    strides 100 and 200 at the timed solve's N* (163 and 289 paths per node)
+    and at n_paths; the martingale kernel with the network at strides 500
+    and 20, with the hi + lo and the BF16 gradient, and the linear control,
+    at n_paths; two launches each.  The weights do not change the work: an
+    untrained identity-base network."""
     import dataclasses
 
     import torch
@@ -388,7 +412,14 @@ def cv_kernels_only(fk, n_paths=CV_PROFILE_PATHS):
     gdata = dataclasses.replace(wl.data, init_kind=W.DATA_GRID, score_mode=W.SCORE_EXTEND)
     res = {}
     fk.fk_timing_enable(True)
+    def dynkin(n, stride):
+        return lambda: fk.fk_interface_solve_cv(wl.density, wl.data, pts, wl.t, wl.dt, n, cv, stride=stride,
+                                                seed=wl.seed, form=fk.FK_CV_DYNKIN, plain=False)
+
     for name, call in (
+            ("dynkin_stride100_n163", dynkin(163, 100)),
+            ("dynkin_stride200_n289", dynkin(289, 200)),
+            ("dynkin_stride100", dynkin(n_paths, 100)),
             ("martingale_stride500", lambda: fk.fk_interface_solve_cv(wl.density, wl.data, pts, wl.t, wl.dt, n_paths,
                                                                       cv, stride=500, seed=wl.seed,
                                                                       form=fk.FK_CV_MARTINGALE, plain=False)),
@@ -675,9 +706,11 @@ def main():
         out["cv"] = measure_cv(fk, wl, pts, fd, args.steps, args.warmup, identity_base=True)
         out["cv"]["identity_base"] = True
         pn = measure_cv(fk, wl, pts, fd, args.steps, args.warmup, identity_base=False)
-        out["cv"]["plain_output_network"] = {k: pn[k] for k in ("stride", "paths_per_node", "rms_err", "nodes_per_s")}
+        out["cv"]["plain_output_network"] = {k: pn[k] for k in ("form", "stride", "grad", "paths_per_node", "rms_err",
+                                                                "nodes_per_s")}
         out["cv"]["plain_output_network"]["pilots"] = [
-            {k: p[k] for k in ("form", "stride", "grad", "var_ratio", "n_star")} for p in pn["pilots"]]
+            {k: p.get(k) for k in ("form", "stride", "grad", "var_ratio", "n_star", "s_at_n_star")}
+            for p in pn["pilots"]]
     if not args.no_bridge and fd is not None:
         out["bridge"] = measure_bridge(fk, wl, pts, fd)
     if not args.no_mesh_run:

@@ -139,7 +139,9 @@ typedef struct fk_data {
  * steps: in fk_interface_solve (and the plain pass of fk_interface_solve_cv)
  * the largest of 256, 512, 1024, 2048 that leaves at least 8 chunks per
  * resident wavefront (28 per CU), 256 with a node mask, and 256 in the network
- * forms of fk_interface_solve_cv; chunk at most 2048 (FK_E_INVAL beyond);
+ * forms of fk_interface_solve_cv; for longer horizons in the control-variate
+ * passes of fk_interface_solve_cv, the largest of 128, 64, 32 that leaves at
+ * least 64 chunks per CU; chunk at most 2048 (FK_E_INVAL beyond);
  * node_tile 1.  The plan changes speed
  * only: results depend on the counters alone. */
 typedef struct fk_plan {

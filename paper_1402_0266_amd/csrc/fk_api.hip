@@ -279,6 +279,15 @@ int short_chunk(int64_t n_nodes, int64_t n_paths, int n_cu, bool masked) {
     return 256;
 }
 
+int few_paths_chunk(int64_t n_nodes, int64_t n_paths, int n_cu) {
+    // 64 chunks per CU: at least eight per resident wavefront of the
+    // network kernels (two waves per SIMD)
+    const int64_t want = 64LL * n_cu;
+    for (int c = 128; c > 32; c >>= 1)
+        if (n_nodes * ((n_paths + c - 1) / c) >= want) return c;
+    return 32;
+}
+
 int check_chunks(int64_t n_nodes, int64_t n_paths, const fk_plan &pl) {
     const int64_t cpn = (n_paths + pl.chunk - 1) / pl.chunk;
     // chunk indices run past the last chunk by up to two grid-fulls of

@@ -1955,6 +1955,7 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     // the 768-cell run against 128); the grid control keeps 128.  Larger
     // grabs, which the plain kernel prefers there, cost these kernels 5%.
     if ((!plan || plan->chunk == 0) && !grid_ctl && level.K <= 64) pl.chunk = 256;
+    else if ((!plan || plan->chunk == 0) && level.K > 64) pl.chunk = few_paths_chunk(n_nodes, n_paths, n_cu);
     const int64_t cpn = (n_paths + pl.chunk - 1) / pl.chunk;
     hipError_t e;
     uint32_t *counters = (uint32_t *)(ws + lay.counters);

@@ -175,6 +175,10 @@ int check_chunks(int64_t n_nodes, int64_t n_paths, const fk_plan &pl);
 // 2048 that still leaves 8 chunks per resident wavefront (28 per CU); 256
 // for masked solves.  The chunk only changes the schedule, never a result.
 int short_chunk(int64_t n_nodes, int64_t n_paths, int n_cu, bool masked);
+// Default grab of the network and gradient-table forms on long horizons:
+// the largest of 128, 64, 32 paths that leaves at least 64 chunks per CU
+// (few paths per node leave the grid part-empty with larger grabs).
+int few_paths_chunk(int64_t n_nodes, int64_t n_paths, int n_cu);
 
 // Launch-plan tuning (fk_plan.hip): a 64-bit FNV-1a hash, the device's
 // signature, the tuned-plan cache (per process; FK_TUNE_CACHE names a file

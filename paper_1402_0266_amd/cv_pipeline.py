@@ -32,3 +32,16 @@ def make_labels(density, data, nodes, t_levels, dt, n_paths, seed=0, device="cud
 def train(cv: FkCv, txy, target, steps=2000, batch=8192, lr=1e-3, seed=0):
     """Adam on minibatches; returns the per-step minibatch losses (device)."""
     return cv.train(txy, target, steps=steps, batch=batch, lr=lr, seed=seed)
+
+
+# The default fit: Adam stages of (steps, learning rate), a constant rate and
+# two decays; the moments and the step count carry over from stage to stage.
+TRAIN_SCHEDULE = ((8000, 2e-3), (4000, 5e-4), (4000, 1e-4))
+
+
+def train_schedule(cv: FkCv, txy, target, schedule=TRAIN_SCHEDULE, batch=8192, seed=0):
+    """Adam through the stages of ``schedule``; returns the per-step
+    minibatch losses of all stages (device), in order."""
+    import torch
+    losses = [cv.train(txy, target, steps=n, batch=batch, lr=lr, seed=seed + i) for i, (n, lr) in enumerate(schedule)]
+    return torch.cat(losses)

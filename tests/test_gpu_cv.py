@@ -208,44 +208,47 @@ def test_cv_solve_against_oracle(fk, oracle_mod, stride):
 
 def test_trained_network_gain(fk):
     """What the trained network buys on the moving-bump workload: labels from
-    plain Monte Carlo, training on the GPU, then the control-variate solve at
-    t = 0.1 on every 8th node, judged against the finite-difference
-    reference, against plain Monte Carlo on the same paths, and against the
-    linear control (the identity map's gradient, no network) on the same
-    paths.  Away from the bump the solution's gradient is close to the
-    identity, so the linear control is already strong here: the network's
-    variance is reported beside it and held within a factor 2 of it
-    (measured: 0.0417 of plain against the linear control's 0.0386)."""
+    plain Monte Carlo (132 time levels in [0, 0.1] x 1521 nodes x 1024
+    paths), the default training schedule on the GPU (an identity-base
+    network: u_hat = (x, y) + MLP), then control-variate solves at t = 0.1 on
+    every 8th node, judged against the finite-difference reference, against
+    plain Monte Carlo on the same paths, and against the linear control (the
+    identity map's gradient, no network) on the same paths.  Away from the
+    bump the solution's gradient is close to the identity, so the linear
+    control alone already removes ~96% of the variance; the trained network
+    must remove most of what is left: in the martingale form with the BF16
+    gradient its variance is held below 0.3 of the linear control's at
+    stride 20 and below 0.6 at stride 100 (measured: 0.10 and 0.28), and in
+    the Dynkin form, whose integrand vanishes where u_hat solves the PDE,
+    below 0.2 at stride 20 (measured: 0.052)."""
     import torch
     from paper_1402_0266_amd import cv_pipeline as P
     wl = W.MOVING_BUMP_1521
     nodes = wl.nodes()
-    print("[gpu] cv gain: labels, training, solve", flush=True)
-    txy, target = P.make_labels(wl.density, wl.data, nodes, W.cv_label_levels(33, W.CV_T_SCALE), wl.dt, 256, seed=1)
-    cv = fk.FkCv(W.mlp_init(0), T)
-    loss = P.train(cv, txy, target, steps=1000, batch=8192, lr=1e-3, seed=2)
+    print("[gpu] cv gain: labels, training, solves", flush=True)
+    txy, target = P.make_labels(wl.density, wl.data, nodes, W.cv_label_levels(132, W.CV_T_SCALE), wl.dt, 1024,
+                                seed=1)
+    cv = fk.FkCv(W.mlp_init(0), T, identity_base=True, grad_precision="bf16")
+    loss = P.train_schedule(cv, txy, target, P.TRAIN_SCHEDULE, batch=8192, seed=2)
+    assert loss.shape[0] == sum(n for n, _ in P.TRAIN_SCHEDULE)
     sub = np.arange(0, len(nodes), 8)
-    g = fk.fk_interface_solve_cv(wl.density, wl.data, nodes[sub], wl.t, wl.dt, 2048, cv, stride=20, seed=3)
-    torch.cuda.synchronize()
-    loss = loss.cpu().numpy()
     fd = np.loadtxt(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", f"{wl.name}_fd.txt"))[sub]
     ref = fd[:, 2:4]
     assert np.abs(fd[:, :2] - nodes[sub]).max() < 1e-12
-    cvm = np.stack([g["xi"].cpu().numpy(), g["eta"].cpu().numpy()], 1)
-    plm = np.stack([g["plain_xi"].cpu().numpy(), g["plain_eta"].cpu().numpy()], 1)
-    cvs = np.stack([g["se_xi"].cpu().numpy(), g["se_eta"].cpu().numpy()], 1)
-    pls = np.stack([g["plain_se_xi"].cpu().numpy(), g["plain_se_eta"].cpu().numpy()], 1)
-    rms_cv = float(np.sqrt(np.mean((cvm - ref) ** 2)))
-    rms_pl = float(np.sqrt(np.mean((plm - ref) ** 2)))
-    ratio = float(np.mean(cvs ** 2) / np.mean(pls ** 2))
-    print(f"loss {loss[0]:.3e} -> {loss[-50:].mean():.3e}; variance ratio cv/plain {ratio:.4f}; "
-          f"RMS vs FD: cv {rms_cv:.2e}, plain {rms_pl:.2e}", flush=True)
-    assert ratio < 0.25                       # at least 4x fewer paths for the same error
-    assert rms_cv < 0.6 * rms_pl
-    # the control-variate estimate is unbiased: within its error of the FD reference
-    z = (cvm - ref) / np.sqrt(cvs ** 2 + fd[:, 4:6] ** 2)
-    assert abs(float(z.mean())) < 0.5 and float(np.sqrt(np.mean(z ** 2))) < 1.5
+
+    def pair(r, a, b):
+        return np.stack([r[a].cpu().numpy(), r[b].cpu().numpy()], 1)
+
+    runs = {}
+    for name, form, stride in (("martingale 20", fk.FK_CV_MARTINGALE, 20), ("martingale 100", fk.FK_CV_MARTINGALE, 100),
+                               ("dynkin 20", fk.FK_CV_DYNKIN, 20)):
+        g = fk.fk_interface_solve_cv(wl.density, wl.data, nodes[sub], wl.t, wl.dt, 2048, cv, stride=stride, seed=3,
+                                     form=form)
+        torch.cuda.synchronize()
+        runs[name] = (pair(g, "xi", "eta"), pair(g, "se_xi", "se_eta"), pair(g, "plain_xi", "plain_eta"),
+                      pair(g, "plain_se_xi", "plain_se_eta"))
     cv.close()
+    loss = loss.cpu().numpy()
     # the linear control on the same paths: the identity data posed as a
     # 256-cell identity grid scored past the edge (the same scores), whose
     # bilinear gradient is exactly I
@@ -257,15 +260,24 @@ def test_trained_network_gain(fk):
     lin = fk.fk_interface_solve_cv(wl.density, gdata, nodes[sub], wl.t, wl.dt, 2048, None, stride=1 << 20, seed=3,
                                    form=fk.FK_CV_MARTINGALE_GRID, grids=grids)
     torch.cuda.synchronize()
-    lps = np.stack([lin["plain_se_xi"].cpu().numpy(), lin["plain_se_eta"].cpu().numpy()], 1)
-    # the same paths (the grid's bilinear identity equals x to rounding)
-    print(f"plain se, identity data vs identity grid: max rel diff {np.max(np.abs(lps / pls - 1)):.2e}", flush=True)
-    assert np.allclose(lps, pls, rtol=1e-5, atol=0)
-    lcs = np.stack([lin["se_xi"].cpu().numpy(), lin["se_eta"].cpu().numpy()], 1)
-    ratio_lin = float(np.mean(lcs ** 2) / np.mean(pls ** 2))
-    print(f"variance ratio to plain: network {ratio:.4f}, linear control {ratio_lin:.4f}; network / linear "
-          f"{ratio / ratio_lin:.3f}", flush=True)
-    assert ratio < 2.0 * ratio_lin
+    lps, lcs = pair(lin, "plain_se_xi", "plain_se_eta"), pair(lin, "se_xi", "se_eta")
+    ratio_lin = float(np.mean(lcs ** 2) / np.mean(lps ** 2))
+    print(f"loss {loss[0]:.3e} -> {loss[-200:].mean():.3e}; linear control: variance ratio to plain "
+          f"{ratio_lin:.4f}", flush=True)
+    bound = {"martingale 20": 0.3, "martingale 100": 0.6, "dynkin 20": 0.2}
+    for name, (cvm, cvs, plm, pls) in runs.items():
+        # the same paths as the linear control's (its bilinear identity equals x to rounding)
+        assert np.allclose(lps, pls, rtol=1e-5, atol=0)
+        rms_cv = float(np.sqrt(np.mean((cvm - ref) ** 2)))
+        rms_pl = float(np.sqrt(np.mean((plm - ref) ** 2)))
+        ratio = float(np.mean(cvs ** 2) / np.mean(pls ** 2))
+        print(f"{name}: variance ratio to plain {ratio:.4f}, network / linear {ratio / ratio_lin:.3f}; "
+              f"RMS vs FD: cv {rms_cv:.2e}, plain {rms_pl:.2e}", flush=True)
+        assert ratio < bound[name] * ratio_lin
+        assert rms_cv < 0.6 * rms_pl
+        # the control-variate estimate is unbiased: within its error of the FD reference
+        z = (cvm - ref) / np.sqrt(cvs ** 2 + fd[:, 4:6] ** 2)
+        assert abs(float(z.mean())) < 0.5 and float(np.sqrt(np.mean(z ** 2))) < 1.5
 
 
 @pytest.mark.parametrize("stride", [2, 20])
