@@ -22,7 +22,8 @@ The same line reports, as extra objects:
   1e-3 fastest: pilots at 4096 paths give each candidate's N*, each
   candidate is timed once at its N*, and the fastest is timed.  The
   network fits the deviation from the identity map (u_hat = (x, y) + MLP);
-  the same pipeline with the plain-output network, and the identity's
+  the same pipeline with the plain-output network, with the identity-base
+  network fitted by 2000 Adam steps at lr 1e-3 only, and the identity's
   gradient alone as the control, are reported beside it.  Throughput is
   quoted for the solve alone and with the labels and training counted once.
 * "bridge": the same workload with the Brownian-bridge exit test (bias and
@@ -167,8 +168,10 @@ def _stack(r, keys):
     return np.stack([r[keys[0]].cpu().numpy(), r[keys[1]].cpu().numpy()], 1)
 
 
-def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=4096, identity_base=False):
-    """Labels, training and the control-variate solve; nodes/s at RMS 1e-3."""
+def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=4096, identity_base=False,
+               schedule=None):
+    """Labels, training (Adam stages of (steps, lr); the pipeline's default
+    schedule if None) and the control-variate solve; nodes/s at RMS 1e-3."""
     import torch
     from paper_1402_0266_amd import cv_pipeline as P
     n_nodes = len(pts)
@@ -183,7 +186,8 @@ def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=409
     cv = fk.FkCv(W.mlp_init(0), W.CV_T_SCALE, identity_base=identity_base)
     pts = torch.tensor(pts, dtype=torch.float64, device="cuda")     # resident coordinates
     t0 = time.perf_counter()
-    loss = P.train_schedule(cv, txy, target, P.TRAIN_SCHEDULE, batch=8192, seed=2)
+    schedule = P.TRAIN_SCHEDULE if schedule is None else schedule
+    loss = P.train_schedule(cv, txy, target, schedule, batch=8192, seed=2)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t0
     loss = loss.cpu().numpy()
@@ -291,7 +295,7 @@ def measure_cv(fk, wl, pts, fd, steps, warmup, label_paths=1024, pilot_paths=409
         "nodes_per_s": n_nodes / wall,
         "nodes_per_s_incl_labels_and_training": n_nodes / (wall + t_labels + t_train),
         "labels": {"levels": 132, "paths": label_paths, "n": int(txy.shape[0]), "s": t_labels},
-        "training": {"schedule": [list(x) for x in P.TRAIN_SCHEDULE], "batch": 8192, "s": t_train,
+        "training": {"schedule": [list(x) for x in schedule], "batch": 8192, "s": t_train,
                      "loss_first": float(loss[0]),
                      "loss_last50": float(loss[-50:].mean())},
         "pilots": pilots,
@@ -711,6 +715,13 @@ def main():
         out["cv"]["plain_output_network"]["pilots"] = [
             {k: p.get(k) for k in ("form", "stride", "grad", "var_ratio", "n_star", "s_at_n_star")}
             for p in pn["pilots"]]
+        # the fit the learned-control configuration names: 2000 Adam steps at lr 1e-3
+        cf = measure_cv(fk, wl, pts, fd, args.steps, args.warmup, identity_base=True, schedule=((2000, 1e-3),))
+        out["cv"]["fit_2000_steps"] = {k: cf[k] for k in ("form", "stride", "grad", "paths_per_node", "rms_err",
+                                                          "nodes_per_s", "training")}
+        out["cv"]["fit_2000_steps"]["pilots"] = [
+            {k: p.get(k) for k in ("form", "stride", "grad", "var_ratio", "n_star", "s_at_n_star")}
+            for p in cf["pilots"]]
     if not args.no_bridge and fd is not None:
         out["bridge"] = measure_bridge(fk, wl, pts, fd)
     if not args.no_mesh_run:
