@@ -206,6 +206,33 @@ def test_cv_solve_against_oracle(fk, oracle_mod, stride):
     cv.close()
 
 
+@pytest.mark.parametrize("form", ["dynkin", "martingale"])
+def test_cv_plans_change_only_the_schedule(fk, form):
+    """Few paths per node on a long horizon: the default plan of the
+    control-variate forms takes grabs of 32 to 128 paths by the node and
+    path counts; every grab size, block size and node tile gives bitwise the
+    same estimates, per-path scores and exit steps (each path draws from its
+    own counters, and the estimator's sums are exact integers)."""
+    import torch
+    cv = fk.FkCv(W.mlp_init(7), T, identity_base=True)
+    dens = W.moving_bump()
+    pts = W.interface_nodes(4, 4, 16)[::2]
+    t, dt, N = 0.01, 1e-4, 163                 # 100 steps: the long-horizon default
+    fm = fk.FK_CV_DYNKIN if form == "dynkin" else fk.FK_CV_MARTINGALE
+    print(f"[gpu] cv plans form={form} nodes={len(pts)} N={N}", flush=True)
+    runs = []
+    for plan in (None, {"chunk": 128}, {"chunk": 64}, {"chunk": 32}, {"chunk": 7, "block": 64},
+                 {"chunk": 32, "node_tile": 4}):
+        g = fk.fk_interface_solve_cv(dens, W.Data(), pts, t, dt, N, cv, stride=10, seed=3, form=fm, exit_step=True,
+                                     cv_scores=True, plan=plan)
+        torch.cuda.synchronize()
+        runs.append({k: v.cpu().numpy() for k, v in g.items() if not k.startswith("_")})
+    cv.close()
+    for r in runs[1:]:
+        for k in ("xi", "eta", "se_xi", "se_eta", "plain_xi", "plain_eta", "exit_step", "cv_scores", "total_steps"):
+            assert np.array_equal(r[k], runs[0][k]), k
+
+
 def test_trained_network_gain(fk):
     """What the trained network buys on the moving-bump workload: labels from
     plain Monte Carlo (132 time levels in [0, 0.1] x 1521 nodes x 1024
