@@ -491,7 +491,10 @@ int fk_interface_interpolate_mask(int32_t px, int32_t m, const uint8_t *mask, co
  * Mesh quality of a nodal map (xi, eta) on an (n+1)^2 grid: out[0] = minimum
  * over cells of the Jacobian xi_x eta_y - xi_y eta_x, out[1] = maximum of the
  * skewness |grad xi . grad eta| / (|grad xi| |grad eta|), both from
- * cell-centred differences.  out is device FP64 [2].
+ * cell-centred differences.  out is device FP64 [2], 8-byte aligned
+ * (FK_E_INVAL otherwise); it also holds the reduction's 64-bit keys between
+ * the call's three kernels, so it must not be read on another stream before
+ * they finish.  Cells whose skewness is 0/0 (a zero gradient) are passed over.
  */
 int fk_mesh_quality(const double *xi, const double *eta, int32_t n, double *out, hipStream_t stream);
 

@@ -1246,15 +1246,41 @@ __global__ void dirichlet_kernel(const SubArgs a, const double *iface_xi, const 
     eta_out[g] = iface_eta[f];
 }
 
-// min Jacobian and max skewness over all cells (cell-centred differences).
-__global__ void __launch_bounds__(1024) quality_kernel(const double *xi, const double *eta, int n, double *out) {
-    const int N1 = n + 1;
+// min Jacobian and max skewness over all cells (cell-centred differences),
+// in three launches on the caller's stream: out's two words set to the
+// order keys of +inf and 0, every block's extremes folded in with 64-bit
+// integer atomics on the keys, the keys turned back into doubles.  The key
+// of a double orders like the double (non-NaN); min and max are exact, so
+// the result does not depend on the order of the blocks.
+__device__ __forceinline__ unsigned long long order_key(double d) {
+    const unsigned long long b = (unsigned long long)__double_as_longlong(d);
+    return (b >> 63) ? ~b : (b | 0x8000000000000000ull);
+}
+
+__device__ __forceinline__ double key_value(unsigned long long k) {
+    return __longlong_as_double((long long)((k >> 63) ? (k & 0x7fffffffffffffffull) : ~k));
+}
+
+__global__ void quality_init_kernel(unsigned long long *keys) {
+    if (threadIdx.x == 0) {
+        keys[0] = order_key(INFINITY);
+        keys[1] = order_key(0.0);
+    }
+}
+
+constexpr int kQualityBlock = 256;
+
+__global__ void __launch_bounds__(kQualityBlock) quality_kernel(const double *xi, const double *eta, int n,
+                                                                unsigned long long *keys) {
+    const int64_t N1 = n + 1;
     const double inv2h = 0.5 * n;
+    // fmin / fmax pass over NaN values (a degenerate cell's skewness 0/0),
+    // so a block's extremes, and their keys, are never NaN
     double jmin = INFINITY, smax = 0.0;
     const int64_t cells = (int64_t)n * n;
-    for (int64_t c = threadIdx.x; c < cells; c += blockDim.x) {
-        const int i = (int)(c % n), j = (int)(c / n);
-        const int64_t g = (int64_t)j * N1 + i;
+    for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t j = c / n, i = c - j * n;
+        const int64_t g = j * N1 + i;
         const double a0 = xi[g], a1 = xi[g + 1], a2 = xi[g + N1], a3 = xi[g + N1 + 1];
         const double b0 = eta[g], b1 = eta[g + 1], b2 = eta[g + N1], b3 = eta[g + N1 + 1];
         const double xx = ((a1 - a0) + (a3 - a2)) * inv2h, xy = ((a2 - a0) + (a3 - a1)) * inv2h;
@@ -1269,17 +1295,26 @@ __global__ void __launch_bounds__(1024) quality_kernel(const double *xi, const d
         jmin = fmin(jmin, __shfl_xor(jmin, off, 64));
         smax = fmax(smax, __shfl_xor(smax, off, 64));
     }
-    __shared__ double pj[16], ps[16];
+    __shared__ double pj[kQualityBlock / 64], ps[kQualityBlock / 64];
     if ((threadIdx.x & 63) == 0) {
         pj[threadIdx.x >> 6] = jmin;
         ps[threadIdx.x >> 6] = smax;
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        for (int w = 1; w < (int)(blockDim.x >> 6); ++w) {
+        for (int w = 1; w < kQualityBlock / 64; ++w) {
             jmin = fmin(jmin, pj[w]);
             smax = fmax(smax, ps[w]);
         }
+        atomicMin(&keys[0], order_key(jmin));
+        atomicMax(&keys[1], order_key(smax));
+    }
+}
+
+__global__ void quality_final_kernel(unsigned long long *keys) {
+    if (threadIdx.x == 0) {
+        const double jmin = key_value(keys[0]), smax = key_value(keys[1]);
+        double *out = reinterpret_cast<double *>(keys);
         out[0] = jmin;
         out[1] = smax;
     }
@@ -1640,7 +1675,13 @@ int fk_density_grid_drift(const double *grid_w, int32_t n, float *grid_b, hipStr
 int fk_mesh_quality(const double *xi, const double *eta, int32_t n, double *out, hipStream_t stream) {
     g_last_error.clear();
     if (n < 1 || !xi || !eta || !out) return fail(FK_E_INVAL, "need n >= 1 and non-NULL arrays");
-    hipLaunchKernelGGL(quality_kernel, dim3(1), dim3(1024), 0, stream, xi, eta, n, out);
+    if (((uintptr_t)out & 7u) != 0) return fail(FK_E_INVAL, "out must be 8-byte aligned");
+    unsigned long long *keys = reinterpret_cast<unsigned long long *>(out);
+    const int64_t cells = (int64_t)n * n;
+    const int blocks = (int)std::min<int64_t>((cells + kQualityBlock - 1) / kQualityBlock, 2048);
+    hipLaunchKernelGGL(quality_init_kernel, dim3(1), dim3(64), 0, stream, keys);
+    hipLaunchKernelGGL(quality_kernel, dim3(blocks), dim3(kQualityBlock), 0, stream, xi, eta, n, keys);
+    hipLaunchKernelGGL(quality_final_kernel, dim3(1), dim3(64), 0, stream, keys);
     hipError_t e = hipGetLastError();
     return e == hipSuccess ? FK_OK : hip_fail(e, "quality kernel launch");
 }

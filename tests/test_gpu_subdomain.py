@@ -162,3 +162,11 @@ def test_mesh_quality_against_oracle(fk, n):
     X, Y = grid(n)
     q = fk.fk_mesh_quality(cuda(X), cuda(Y)).cpu().numpy()
     assert abs(q[0] - 1) < 1e-12 and q[1] < 1e-12
+    # a folded map (eta reversed): every Jacobian is -1, and a second call
+    # into the same output starts afresh
+    out = torch.zeros(2, dtype=torch.float64, device="cuda")
+    fk.fk_mesh_quality(cuda(X), cuda(Y), out=out)
+    fk.fk_mesh_quality(cuda(X), cuda(1.0 - Y), out=out)
+    q = out.cpu().numpy()
+    ref = S.mesh_quality(X, 1.0 - Y)
+    assert abs(q[0] + 1) < 1e-12 and abs(q[0] - ref[0]) < 1e-12 and q[1] < 1e-12
