@@ -84,30 +84,56 @@ __device__ __forceinline__ int cost_bucket(const TableArgs &t, double x, double 
     return min(kCostBuckets - 1, max(0, (int)((1.0 - f) * kCostBuckets)));
 }
 
+// Adds, for every lane with `take`, one to hist[b] -- one atomic per
+// distinct b in the wavefront (a mesh step's nodes mostly share a bucket,
+// and one atomic per node on one address serialises) -- and returns the
+// lane's slot: the old count plus its rank among the wavefront's lanes with
+// the same b.  Every lane of the wavefront calls it.
+__device__ __forceinline__ uint32_t wave_bucket_add(uint32_t *hist, bool take, int b) {
+    const int lane = (int)(threadIdx.x & 63u);
+    uint64_t left = __ballot(take);
+    uint32_t slot = 0;
+    while (left != 0ull) {
+        const int leader = __builtin_ctzll(left);
+        const int lb = __shfl(b, leader, 64);
+        const bool mine = take && b == lb;
+        const uint64_t grp = __ballot(mine);
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&hist[lb], (uint32_t)__popcll(grp));
+        base = (uint32_t)__shfl((int)base, leader, 64);
+        if (mine) slot = base + __builtin_amdgcn_mbcnt_hi((uint32_t)(grp >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)grp, 0u));
+        left &= ~grp;
+    }
+    return slot;
+}
+
 __global__ void table_count_kernel(const TableArgs t) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i == 0) *t.levels_out = t.level;
-    if (i >= t.n) return;
-    double x, y;
-    bool ok;
-    const bool want = node_wanted(t, i, x, y, ok);
-    OutDev o{};
-    o.shift_x = t.shift ? (double)(float)x : 0.0;
-    o.shift_y = t.shift ? (double)(float)y : 0.0;
-    o.K = t.level.K;
-    t.outs_out[i] = o;
-    if (t.outs_zero_out) {
-        o.shift_x = o.shift_y = 0.0;
-        t.outs_zero_out[i] = o;
+    bool take = false;
+    int bucket = 0;
+    if (i < t.n) {
+        double x, y;
+        bool ok;
+        const bool want = node_wanted(t, i, x, y, ok);
+        OutDev o{};
+        o.shift_x = t.shift ? (double)(float)x : 0.0;
+        o.shift_y = t.shift ? (double)(float)y : 0.0;
+        o.K = t.level.K;
+        t.outs_out[i] = o;
+        if (t.outs_zero_out) {
+            o.shift_x = o.shift_y = 0.0;
+            t.outs_zero_out[i] = o;
+        }
+        if (want && !ok) {
+            // not a node of the square: no paths, NaN results
+            t.acc[i].bad = 1u;
+            if (t.acc2) t.acc2[i].bad = 1u;
+        }
+        take = want && ok;
+        if (take) bucket = cost_bucket(t, x, y);
     }
-    if (!want) return;
-    if (!ok) {
-        // not a node of the square: no paths, NaN results
-        t.acc[i].bad = 1u;
-        if (t.acc2) t.acc2[i].bad = 1u;
-        return;
-    }
-    atomicAdd(&t.counters[kCtrHist + cost_bucket(t, x, y)], 1u);
+    wave_bucket_add(t.counters + kCtrHist, take, bucket);
 }
 
 __global__ void table_scan_kernel(uint32_t *c, uint32_t cpn) {
@@ -124,11 +150,15 @@ __global__ void table_scan_kernel(uint32_t *c, uint32_t cpn) {
 
 __global__ void table_scatter_kernel(const TableArgs t) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= t.n) return;
-    double x, y;
-    bool ok;
-    if (!node_wanted(t, i, x, y, ok) || !ok) return;
-    const uint32_t slot = atomicAdd(&t.counters[kCtrHist + cost_bucket(t, x, y)], 1u);
+    double x = 0.0, y = 0.0;
+    bool ok = false, take = false;
+    int bucket = 0;
+    if (i < t.n) {
+        take = node_wanted(t, i, x, y, ok) && ok;
+        if (take) bucket = cost_bucket(t, x, y);
+    }
+    const uint32_t slot = wave_bucket_add(t.counters + kCtrHist, take, bucket);
+    if (!take) return;
     NodeDev nd{};
     // the start point as an FP32 (hi, lo) pair holding the FP64 node to ~2^-48
     nd.x = (float)x;
