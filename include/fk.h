@@ -338,7 +338,9 @@ size_t fk_batch_workspace_bytes(fk_batch_t b);
 int fk_batch_set_plan(fk_batch_t b, const fk_plan *plan);
 int fk_batch_get_plan(fk_batch_t b, fk_plan *plan);
 /* Times the launch with probe_paths paths per node for each candidate shape
- * (as fk_plan_autotune: block x chunk x occupancy x node tile), keeps the
+ * (as fk_plan_autotune: block x chunk x occupancy x node tile; chunk 32 only
+ * when the batch's n_paths is below 16 x probe_paths, since a short probe
+ * does not show the queue traffic of small grabs at full size), keeps the
  * fastest as the batch's plan and returns it in *chosen (may be NULL).
  * Results are cached like fk_plan_autotune's (device signature + shape hash;
  * FK_TUNE_CACHE).  Synchronous; allocates and frees a small probe output

@@ -198,6 +198,11 @@ int fk_batch_autotune(fk_batch_t b, int64_t probe_paths, void *workspace, size_t
     const int occ = path_kernel_max_blocks_per_cu(b->T.kind, b->T.time_mode, b->T.uniform,
                                                   b->data.score_mode == FK_SCORE_BRIDGE, false, 256);
     fk_plan best = b->plan;
+    // Each grab costs one atomic on the queue counter.  A probe much shorter
+    // than the full launch does not show that cost, which grows with the
+    // path count: grabs below 128 paths are only tried when the full launch
+    // has less than 16 times the probe's paths.
+    const int min_chunk = b->n_paths >= 16 * probe_paths ? 128 : 1;
     const int rc = tune_sweep(
         occ,
         [&](const fk_plan &pl) {
@@ -205,7 +210,8 @@ int fk_batch_autotune(fk_batch_t b, int64_t probe_paths, void *workspace, size_t
                                 out + 3 * b->n_total, nullptr, nullptr, nullptr, workspace, workspace_bytes, stream,
                                 false);
         },
-        [&](const fk_plan &pl) { return check_chunks(b->n_total, probe_paths, pl) == FK_OK; }, stream, &best);
+        [&](const fk_plan &pl) { return check_chunks(b->n_total, probe_paths, pl) == FK_OK; }, stream, &best,
+        min_chunk);
     hipFree(out);
     if (rc != FK_OK) return rc;
     b->plan = best;

@@ -185,13 +185,14 @@ int few_paths_chunk(int64_t n_nodes, int64_t n_paths, int n_cu);
 // that persists it), and the sweep over candidate plans: `launch` enqueues
 // one run with a plan, `admissible` filters the candidates, occ_full is the
 // kernel's occupancy at 256 threads; best_out holds the starting plan and
-// receives the fastest.
+// receives the fastest; grab sizes below min_chunk are not tried.
 uint64_t fnv1a(const void *data, size_t n, uint64_t h);
 std::string device_signature(int dev);
 bool tune_cache_get(const std::string &key, fk_plan *out);
 void tune_cache_put(const std::string &key, const fk_plan &p);
 int tune_sweep(int occ_full, const std::function<int(const fk_plan &)> &launch,
-               const std::function<bool(const fk_plan &)> &admissible, hipStream_t stream, fk_plan *best_out);
+               const std::function<bool(const fk_plan &)> &admissible, hipStream_t stream, fk_plan *best_out,
+               int min_chunk = 1);
 // A persistent grid of `grid` blocks cut to no more wavefronts than there
 // are work chunks (small solves: a wavefront with no chunk only costs its
 // launch).

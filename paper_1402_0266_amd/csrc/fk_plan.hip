@@ -93,7 +93,8 @@ void tune_cache_put(const std::string &key, const fk_plan &p) {
 }
 
 int tune_sweep(int occ_full, const std::function<int(const fk_plan &)> &launch,
-               const std::function<bool(const fk_plan &)> &admissible, hipStream_t stream, fk_plan *best_out) {
+               const std::function<bool(const fk_plan &)> &admissible, hipStream_t stream, fk_plan *best_out,
+               int min_chunk) {
     static const int blocks[] = {64, 128, 256};
     static const int chunks[] = {32, 128, 512};
     static const int divs[] = {1, 2};
@@ -111,6 +112,7 @@ int tune_sweep(int occ_full, const std::function<int(const fk_plan &)> &launch,
     int rc = launch(best);
     for (int bl : blocks) {
         for (int ch : chunks) {
+            if (ch < min_chunk) continue;
             for (int dv : divs) {
                 for (int nt : tiles) {
                     if (rc != FK_OK) break;
