@@ -94,8 +94,8 @@ CV_PROFILE_PATHS = 2952
 # (scaled by a plain 1 GiB copy: fetch x2.0, write x1.0) on the moving-bump
 # solve at N* = 73858 (1521 x 578 chunks of 128 paths), per path, valid only
 # for the kernel sources it was measured on (hash below); otherwise null.
-TRAFFIC_BYTES_PER_PATH = (2.0 * 244.5 + 1.0 * 498778.78125) * 1024 / (1521 * 73858)
-TRAFFIC_SOURCE_HASH = "4fd64951c83c0cd6"
+TRAFFIC_BYTES_PER_PATH = (2.0 * 244.5 + 1.0 * 497344.03125) * 1024 / (1521 * 73858)
+TRAFFIC_SOURCE_HASH = "6b8ec78f4882275f"
 KERNEL_SOURCES = ["paper_1402_0266_amd/csrc/fk_paths.hip", "paper_1402_0266_amd/csrc/fk_device.hpp",
                   "paper_1402_0266_amd/csrc/fk_internal.hpp", "paper_1402_0266_amd/csrc/fk_pathstep.hpp",
                   "paper_1402_0266_amd/csrc/fk_accum.hpp"]
