@@ -1954,6 +1954,9 @@ int fk_interface_solve_cv(const fk_density *w, const fk_data *d, const double *p
     // by default (the network-control mesh step went from 29.9 to 22.6 ms on
     // the 768-cell run against 128); the grid control keeps 128.  Larger
     // grabs, which the plain kernel prefers there, cost these kernels 5%.
+    // Longer horizons: 32 to 128 by the path count, so that a solve with a
+    // few hundred paths per node still spreads over every wavefront (the
+    // Dynkin solve at 163 paths per node: 9.7 ms with 32, 11.7 with 128).
     if ((!plan || plan->chunk == 0) && !grid_ctl && level.K <= 64) pl.chunk = 256;
     else if ((!plan || plan->chunk == 0) && level.K > 64) pl.chunk = few_paths_chunk(n_nodes, n_paths, n_cu);
     const int64_t cpn = (n_paths + pl.chunk - 1) / pl.chunk;
