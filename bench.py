@@ -87,9 +87,8 @@ NET_GRAD_FLOP = 3 * 2 * 2 * 64 * 64
 # through the same two products.
 NET_DYNKIN_FLOP = 5 * 2 * 2 * 64 * 64
 BF16_PEAK_TFLOPS = 2500.0
-# Paths per node of the control-variate kernels' profile at a full grid
-# (the martingale form's N* at stride 100 with a 2000-step fit); the Dynkin
-# kernel is also profiled at the timed solve's N*.
+# Paths per node of the control-variate kernels' profile with the grid
+# full; the Dynkin kernel is also profiled at the timed solve's N*.
 CV_PROFILE_PATHS = 2952
 
 # HBM traffic of the path kernel from rocprofv3 --pmc FETCH_SIZE / WRITE_SIZE
