@@ -65,6 +65,25 @@ def test_plans_and_autotune_do_not_change_results(fk):
     b.close()
 
 
+def test_autotune_skips_small_grabs_for_long_launches(fk):
+    """A launch with 16 or more times the probe's paths per node is not
+    tuned to grabs below 128 paths (each grab is one atomic on the queue
+    counter, a cost a short probe does not show); the tuned plan changes no
+    result."""
+    import torch
+    levels = small_levels(3)
+    b = fk.FkBatch(levels, W.Data(), 1e-4, 1024, seed=2)
+    ref = to_np(b.run(exit_step=True))
+    chosen = b.autotune(64)
+    print(f"autotuned plan {chosen}", flush=True)
+    assert chosen["chunk"] >= 128
+    out = to_np(b.run(exit_step=True))
+    torch.cuda.synchronize()
+    for k in ("xi", "eta", "se_xi", "se_eta", "exit_step"):
+        assert np.array_equal(out[k], ref[k]), k
+    b.close()
+
+
 def test_graph_capture_and_replay(fk):
     import torch
     levels = small_levels(3)
