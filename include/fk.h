@@ -652,7 +652,7 @@ int fk_timing_last(double *path_kernel_ms, double *reduce_kernel_ms);
  *   word); out (device, [n][4] uint32).
  * fk_normals: for word pairs (ra[i], rb[i]) (device uint32 [n]) the FP32
  *   Brownian increments sqrt(2 D) (z0, z1) of the Box-Muller transform of
- *   u1 = ((ra >> 8) + 1) 2^-24 and u2 = (rb >> 8) 2^-24 (Sect. 4: increments
+ *   u1 = 1 - (ra mod 2^23) 2^-23 and u2 = (rb mod 2^23) 2^-23 (Sect. 4: increments
  *   are sqrt(step) times standard normals; sqrt(2) from the diffusion);
  *   out (device, [n][2] FP32).
  */

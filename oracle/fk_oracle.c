@@ -41,8 +41,8 @@
  *  - the normal generator: Philox4x32-10 (Salmon, Moraes, Dror & Shaw,
  *    SC'11), key = (seed low word, seed high word), counter = (k/2, path,
  *    node, (level << 4) | stream); one call serves two steps (words 0,1 for
- *    even steps, 2,3 for odd); Box-Muller on 24-bit uniforms
- *    u1 = ((r >> 8) + 1) 2^-24 in (0,1], u2 = (r >> 8) 2^-24 in [0,1).
+ *    even steps, 2,3 for odd); Box-Muller on the words' low 23 bits
+ *    m: u1 = 1 - m 2^-23 in (0,1], u2 = m 2^-23 in [0,1).
  *  - step sizes: K = ceil(t/dt), every step dt except the last, which is
  *    t - (K-1) dt.
  *  - exponential time-stepping (score mode 4; Sect. 4 names it as the
@@ -98,11 +98,12 @@ void or_philox_batch(const uint32_t *ctr, const uint32_t *key, int64_t n, uint32
         or_philox4x32_10(ctr + 4 * i, key + 2 * i, out + 4 * i);
 }
 
-/* Box-Muller on the two 24-bit uniforms taken from a pair of Philox words. */
+/* Box-Muller on the two 23-bit uniforms taken from a pair of Philox words
+ * (their low 23 bits). */
 static void box_muller(uint32_t ra, uint32_t rb, double *z0, double *z1)
 {
-    double u1 = ((double)(ra >> 8) + 1.0) * (1.0 / 16777216.0);   /* (0, 1] */
-    double u2 = (double)(rb >> 8) * (1.0 / 16777216.0);           /* [0, 1) */
+    double u1 = 1.0 - (double)(ra & 0x7fffffu) * 0x1p-23;   /* (0, 1] */
+    double u2 = (double)(rb & 0x7fffffu) * 0x1p-23;         /* [0, 1) */
     double r = sqrt(-2.0 * log(u1));
     *z0 = r * cos(2.0 * OR_PI * u2);
     *z1 = r * sin(2.0 * OR_PI * u2);

@@ -57,17 +57,21 @@ __device__ __forceinline__ float hw_rcp(float x) { return __builtin_amdgcn_rcpf(
 __device__ __forceinline__ float hw_sin_rev(float x) { return __builtin_amdgcn_sinf(x); }
 __device__ __forceinline__ float hw_cos_rev(float x) { return __builtin_amdgcn_cosf(x); }
 
-// Box-Muller increments: with u1 = ((ra >> 8) + 1) 2^-24 in (0,1] and
-// u2 = (rb >> 8) 2^-24 in [0,1), returns sqrt(2 D) (z0, z1) where
+// Box-Muller increments on the low 23 bits of each word: with
+// ma = ra mod 2^23 and mb = rb mod 2^23, u1 = 1 - ma 2^-23 in (0,1] and
+// u2 = mb 2^-23 in [0,1), returns sqrt(2 D) (z0, z1) where
 // z0 = sqrt(-2 ln u1) cos(2 pi u2), z1 = sqrt(-2 ln u1) sin(2 pi u2).
-// cbm = -4 ln2 D folds sqrt(2 D) and the change of logarithm base.
+// cbm = -4 ln2 D folds sqrt(2 D) and the change of logarithm base.  The
+// bits m under the exponent of 1.0 make the float 1 + m 2^-23 in one
+// instruction: u1 is 2 minus that (exact), and the angle is that float
+// itself, as sin and cos in revolutions have period 1.
 __device__ __forceinline__ void brownian_increment(uint32_t ra, uint32_t rb, float cbm,
                                                    float &dwx, float &dwy) {
-    const float u1 = fmaf((float)(ra >> 8), 0x1p-24f, 0x1p-24f);  // exact: ((ra >> 8) + 1) 2^-24
-    const float u2 = (float)(rb >> 8) * 0x1p-24f;
+    const float u1 = 2.f - __uint_as_float((ra & 0x7fffffu) | 0x3f800000u);
+    const float a2 = __uint_as_float((rb & 0x7fffffu) | 0x3f800000u);   // 1 + u2
     const float rad = hw_sqrt(cbm * hw_log2(u1));
-    dwx = rad * hw_cos_rev(u2);
-    dwy = rad * hw_sin_rev(u2);
+    dwx = rad * hw_cos_rev(a2);
+    dwy = rad * hw_sin_rev(a2);
 }
 
 // ---------------------------------------------------------------------------

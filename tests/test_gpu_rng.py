@@ -27,8 +27,9 @@ def test_normals_match_oracle(fk, oracle_mod):
     n = 1 << 20
     ra = rng.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)
     rb = rng.integers(0, 2 ** 32, size=n, dtype=np.uint64).astype(np.uint32)
-    ra[:4] = [0, 0xFFFFFFFF, 0x100, 0xFFFFFF00]
-    rb[:4] = [0, 1 << 30, 1 << 31, 0xFFFFFFFF]
+    # the extremes of the 23-bit uniforms: m = 0 and m = 2^23 - 1 in each word
+    ra[:4] = [0, 0x7FFFFF, 0xFF800000, 0xFFFFFFFF]
+    rb[:4] = [0, 1 << 21, 0x7FFFFF, 0xFF800000]
     for D in (1e-5, 1e-4, 2.5e-5):
         print(f"[gpu] normals n={n} D={D}", flush=True)
         got = fk.fk_normals(torch.from_numpy(ra.view(np.int32)).cuda(), torch.from_numpy(rb.view(np.int32)).cuda(),

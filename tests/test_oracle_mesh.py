@@ -113,16 +113,18 @@ def test_dd_step_heat_equation_matches_global_step(oracle_mod):
 def test_two_bump_interface_values_follow_the_frozen_flow(oracle_mod):
     """From the identity mesh the frozen two-bump flow has a stiff initial
     layer, so one backward-Euler step of dt_mesh differs from the exact flow
-    by several standard errors; ten sub-steps bring the global solve to the
-    flow the Monte-Carlo estimates, within their error."""
+    by several standard errors; forty sub-steps bring the global solve to
+    the flow the Monte-Carlo estimates, within their error (ten leave a
+    time-discretisation error of about one standard error at the worst
+    nodes: max |z| 4.6 there against 3.4 with forty, on the same paths)."""
     px, m, D = 4, 8, 5e-4
     N = px * m
     xi0, eta0 = nodal(N)
     dens = W.two_bumps(W.TIME_FROZEN, 0.0)
     mc = MS.interface_solve(dens, 0.0, D, 20, px, m, xi0, eta0, 40000, threads=THREADS)
     a, b = xi0, eta0
-    for _ in range(10):
-        a, b = S.global_be_step(dens, 0.0, D / 10, N, a, b)
+    for _ in range(40):
+        a, b = S.global_be_step(dens, 0.0, D / 40, N, a, b)
     ij = S.interface_index(px, m)
     z = (mc["mean"] - np.stack([a[ij[:, 1], ij[:, 0]], b[ij[:, 1], ij[:, 0]]], 1)) / mc["se"]
     assert np.abs(z).max() < 4.5 and 0.8 < z.std() < 1.25, (np.abs(z).max(), z.std())

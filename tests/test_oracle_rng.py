@@ -2,7 +2,7 @@
 
 * Philox4x32-10 words against rocRAND's independent implementation (its
   header-only engine compiled for the host and run on the CPU).
-* Box-Muller: exact special cases of the 24-bit uniform mapping, and the
+* Box-Muller: exact special cases of the 23-bit uniform mapping, and the
   distribution of 10^6 normals (moments, KS test against N(0,1)).
 """
 import os
@@ -53,19 +53,24 @@ def test_philox_word_uniformity(oracle_mod):
     ctr[:, 0] = np.arange(n)
     out = oracle_mod.philox(ctr, np.zeros((n, 2), dtype=np.uint32))
     u = (out >> 8).astype(np.float64) / 2 ** 24
+    ul = (out & 0x7FFFFF).astype(np.float64) / 2 ** 23     # the bits Box-Muller takes
     for c in range(4):
         assert stats.kstest(u[:, c], "uniform").pvalue > 1e-3
+        assert stats.kstest(ul[:, c], "uniform").pvalue > 1e-3
     # bits are balanced
     bits = np.unpackbits(out.view(np.uint8)).mean()
     assert abs(bits - 0.5) < 1e-3
 
 
 def test_box_muller_special_cases(oracle_mod):
-    # ra = 0xffffffff -> u1 = 1 -> radius 0; ra = 0 -> u1 = 2^-24 -> radius sqrt(48 ln 2)
-    # rb = 0 -> angle 0; rb = 2^30 (u2 = 1/4) -> angle pi/2
-    z = oracle_mod.normals([0xFFFFFFFF, 0, 0, 0], [123, 0, 1 << 30, 1 << 31])
+    # the low 23 bits m of each word: ra with m = 0 -> u1 = 1 -> radius 0
+    # (the high bits are ignored); m = 2^23 - 1 -> u1 = 2^-23 -> radius
+    # sqrt(46 ln 2); rb with m = 0 -> angle 0, m = 2^21 (u2 = 1/4) -> pi/2,
+    # m = 2^22 -> pi
+    z = oracle_mod.normals([0xFF800000, 0x7FFFFF, 0xFFFFFFFF, 0x007FFFFF],
+                           [123, 0xFF800000, 1 << 21, (1 << 22) | (1 << 31)])
     assert np.all(z[0] == 0.0)
-    r = np.sqrt(48 * np.log(2.0))
+    r = np.sqrt(46 * np.log(2.0))
     assert np.allclose(z[1], [r, 0.0], atol=1e-15)
     assert np.allclose(z[2], [0.0, r], atol=1e-14)
     assert np.allclose(z[3], [-r, 0.0], atol=1e-14)
