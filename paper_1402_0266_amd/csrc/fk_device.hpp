@@ -48,6 +48,58 @@ __device__ __forceinline__ PhiloxOut philox4x32_10(uint32_t c0, uint32_t c1, uin
     return PhiloxOut{c0, c1, c2, c3};
 }
 
+// A path's counter words 1 and 2 (path, node) stay fixed over its calls, so
+// round 1's second product (M1 times the node word) and round 2's first
+// product (M0 times round 1's first output, which combines that product with
+// the path word and key word 0) are the same in every call: formed once per
+// path, they save two of the twenty products of each call.
+struct PhiloxPath {
+    uint32_t b;        // round 1's second output: low half of M1 * node
+    uint32_t h0, l0;   // round 2's product M0 * (round 1's first output)
+};
+
+__device__ __forceinline__ PhiloxPath philox_path(uint32_t c1, uint32_t c2, uint32_t k0) {
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    const uint32_t a = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    const uint64_t q0 = (uint64_t)0xD2511F53u * a;
+    return PhiloxPath{(uint32_t)p1, (uint32_t)(q0 >> 32), (uint32_t)q0};
+}
+
+// philox4x32_10(c0, c1, c2, c3, k0, k1) with P = philox_path(c1, c2, k0):
+// bitwise the same four words.
+__device__ __forceinline__ PhiloxOut philox4x32_10_path(uint32_t c0, uint32_t c3, const PhiloxPath &P, uint32_t k0,
+                                                        uint32_t k1) {
+    asm volatile("" : "+s"(k0), "+s"(k1));
+    // round 1: words 0 and 1 of the result are fixed (their product is in P)
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint32_t x2 = xor3_uniform((uint32_t)(p0 >> 32), c3, k1);
+    const uint32_t x3 = (uint32_t)p0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+    // round 2: M0 times the fixed word 0 is P.h0, P.l0
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * x2;
+    c0 = xor3_uniform((uint32_t)(p1 >> 32), P.b, k0);
+    uint32_t c1 = (uint32_t)p1;
+    uint32_t c2 = xor3_uniform(P.h0, x3, k1);
+    c3 = P.l0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+#pragma unroll
+    for (int r = 2; r < 10; ++r) {
+        const uint64_t q0 = (uint64_t)0xD2511F53u * c0;
+        const uint64_t q1 = (uint64_t)0xCD9E8D57u * c2;
+        const uint32_t n0 = xor3_uniform((uint32_t)(q1 >> 32), c1, k0);
+        const uint32_t n2 = xor3_uniform((uint32_t)(q0 >> 32), c3, k1);
+        c1 = (uint32_t)q1;
+        c3 = (uint32_t)q0;
+        c0 = n0;
+        c2 = n2;
+        k0 += 0x9E3779B9u;
+        k1 += 0xBB67AE85u;
+    }
+    return PhiloxOut{c0, c1, c2, c3};
+}
+
 // Hardware transcendentals.  v_sin/v_cos take their argument in revolutions
 // (sin(2 pi x)), v_log is log2 and v_exp is exp2.
 __device__ __forceinline__ float hw_log2(float x) { return __builtin_amdgcn_logf(x); }

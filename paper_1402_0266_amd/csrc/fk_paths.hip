@@ -211,6 +211,7 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
     const uint32_t key0 = a.key0, key1 = a.key1;
 
     Lane L;
+    PhiloxPath pp{};          // the lane's path's fixed Philox products
     bool active = false;
     uint32_t my_tag = 0;      // accumulation tag of the lane's path's chunk
     uint32_t my_steps = 0;
@@ -253,6 +254,7 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)need, 0u));
             if (!active && rank < avail) {
                 lane_start<KIND, TMODE>(L, a.nodes[q_slot], a.levels, q_next + rank);
+                pp = philox_path(L.path, L.nid, key0);
                 my_tag = q_tag;
                 active = true;
             }
@@ -266,7 +268,7 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
         if (active) {
             bool out = false;
             if (L.k < L.K) {
-                const PhiloxOut r = philox4x32_10((uint32_t)L.k >> 1, L.path, L.nid, L.ctr3, key0, key1);
+                const PhiloxOut r = philox4x32_10_path((uint32_t)L.k >> 1, L.ctr3, pp, key0, key1);
                 float ox = L.ox, oy = L.oy, cr = 0.f, sr = 0.f;
                 if constexpr (kMovingBackward) {
                     // Orbit angle at PDE time t_init + t - k dt, in revolutions.
