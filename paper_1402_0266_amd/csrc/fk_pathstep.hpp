@@ -60,11 +60,11 @@ __device__ __forceinline__ bool em_step_w(Lane &L, uint32_t ra, uint32_t rb, flo
     comp_add(L.xh, L.xl, fmaf(bx, D, dwx));
     comp_add(L.yh, L.yl, fmaf(by, D, dwy));
     L.k += 1;
-    // Outside the closed square.  hi is the rounded position; (hi - 1) is
+    // Outside the closed square: -x > 0, -y > 0, x - 1 > 0 or y - 1 > 0, as
+    // one maximum and one compare.  hi is the rounded position; (hi - 1) is
     // exact near 1, so the tests against 1 see the lo part too.
-    const float lo = fminf(L.xh, L.yh);
-    const float hi = fmaxf((L.xh - 1.f) + L.xl, (L.yh - 1.f) + L.yl);
-    return (lo < 0.f) | (hi > 0.f);
+    const float m = fmaxf(fmaxf(-L.xh, -L.yh), fmaxf((L.xh - 1.f) + L.xl, (L.yh - 1.f) + L.yl));
+    return m > 0.f;
 }
 
 template <int KIND, bool UNIFORM>
