@@ -286,7 +286,6 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
                 if constexpr (BRIDGE) {
                     if (!out) out = bridge_exit<UNIFORM>(L, x0h, x0l, y0h, y0l, key0, key1);
                 }
-                my_steps += 1;
                 if (!out && L.k < L.K) {
                     if constexpr (kMovingBackward) {
                         // One step later the angle is smaller by omega dt:
@@ -303,7 +302,6 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
                     if constexpr (BRIDGE) {
                         if (!out) out = bridge_exit<UNIFORM>(L, x0h, x0l, y0h, y0l, key0, key1);
                     }
-                    my_steps += 1;
                 }
             }
             if (out || L.k >= L.K) {
@@ -311,6 +309,7 @@ __global__ void __launch_bounds__(256) fk_path_kernel(const PathArgs a) {
                 float v[2];
                 score_path(a, L, out, v[0], v[1]);
                 closed = acc_path<2>(slots, accs, my_tag, L.out, v, (uint32_t)L.k);
+                my_steps += (uint32_t)L.k;      // the path's steps, counted once at its end
                 if (a.scores) a.scores[path_rec(L, a.n_paths)] = make_float2(v[0], v[1]);
                 if (a.exit_step) a.exit_step[path_rec(L, a.n_paths)] = out ? L.k : -1;
                 active = false;
