@@ -95,8 +95,8 @@ CV_PROFILE_PATHS = 2952
 # (scaled by a plain 1 GiB copy: fetch x2.0, write x1.0) on the moving-bump
 # solve at N* = 73920 (1521 x 578 chunks of 128 paths), per path, valid only
 # for the kernel sources it was measured on (hash below); otherwise null.
-TRAFFIC_BYTES_PER_PATH = (2.0 * 244.5 + 1.0 * 505221.75) * 1024 / (1521 * 73920)
-TRAFFIC_SOURCE_HASH = "68c92eed24cbc2de"
+TRAFFIC_BYTES_PER_PATH = (2.0 * 244.75 + 1.0 * 505266.5625) * 1024 / (1521 * 73920)
+TRAFFIC_SOURCE_HASH = "ba5ecf16793f7980"
 KERNEL_SOURCES = ["paper_1402_0266_amd/csrc/fk_paths.hip", "paper_1402_0266_amd/csrc/fk_device.hpp",
                   "paper_1402_0266_amd/csrc/fk_internal.hpp", "paper_1402_0266_amd/csrc/fk_pathstep.hpp",
                   "paper_1402_0266_amd/csrc/fk_accum.hpp"]
